@@ -1,0 +1,125 @@
+/*
+ * vif.h -- C ABI of the MI355X (gfx950) implementation of Vecchia-inducing-
+ * points full-scale (VIF) Gaussian-process approximations (arXiv 2507.05064).
+ *
+ * Model (Sec. 2 and Sec. 3 of the paper). Points s_1..s_n in the given
+ * (Vecchia) order, m inducing points Z, conditioning sets N(i) of at most m_v
+ * earlier points. With Sigma_m = K(Z,Z) + tau_m I = L_m L_m^T and the whitened
+ * inducing features V = L_m^{-1} K(Z,X) (so that V_i . V_j = Sigma_mi^T
+ * Sigma_m^{-1} Sigma_mj, eq. def_b_low), the residual Vecchia factor of
+ * eq. D_A_Vecchia is, per point,
+ *     R_i = K(N,N) + s2 I - V_N^T V_N,   r_i = K(N,i) - V_N^T V_i,
+ *     A_i = R_i^{-1} r_i,                D_i = sigma1^2 + s2 - V_i.V_i - r_i.A_i,
+ * B unit lower triangular with B_{i,N(i)} = -A_i, and
+ *     Sigma~_dagger = V^T V + B^{-1} D B^{-T}              (Sec. 2.1).
+ * s2 is the Gaussian nugget sigma^2, or for latent models the jitter tau.
+ *
+ * Conventions shared by every entry point:
+ *  - Array arguments are DEVICE pointers (e.g. torch tensors' data_ptr()),
+ *    contiguous, row-major, in Vecchia order: X is n x d, Z is m x d (double),
+ *    y is n (double), neighbour lists are n x m_v int32 with -1 padding for
+ *    the first points (which have fewer than m_v earlier points).
+ *  - theta is a HOST double array (sigma1^2, lambda_1..lambda_L, s2) with
+ *    L = 1 for the isotropic Matern kernels (lambda = range rho) and L = d
+ *    for the ARD Gaussian kernel.
+ *  - Scalar outputs (NLL, gradient, statistics) are HOST pointers; such a
+ *    call synchronises the context's stream before returning.
+ *  - The caller owns every input and output buffer. The context owns its
+ *    workspace (sized once in vif_create) and the factor of the last
+ *    vif_build_factor call, valid until the next build or vif_destroy.
+ *  - All work is issued on the HIP stream given at creation (NULL = default).
+ *  - Errors: a status code, never an exception; vif_last_error() then holds a
+ *    message naming the failing point / iteration. One context per host
+ *    thread; calls on one context must not overlap.
+ */
+#ifndef VIF_H_
+#define VIF_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VIF_OK = 0,
+  VIF_E_ARG = 1,       /* bad size / pointer / enum value / neighbour index */
+  VIF_E_NAN = 2,       /* non-finite input or intermediate */
+  VIF_E_NOT_PD = 3,    /* a Cholesky factorisation failed (index in message) */
+  VIF_E_CG_MAXIT = 4,  /* conjugate gradients hit the iteration limit */
+  VIF_E_NEWTON = 5,    /* Newton mode finding did not converge */
+  VIF_E_HIP = 6,       /* HIP runtime error */
+  VIF_E_OOM = 7,       /* device allocation failed in vif_create */
+  VIF_E_STATE = 8      /* call order violated (e.g. nll before build) */
+} vif_status;
+
+typedef enum { VIF_MATERN12 = 0, VIF_MATERN32 = 1, VIF_GAUSSIAN_ARD = 2 } vif_kernel;
+typedef enum { VIF_LIK_GAUSSIAN = 0, VIF_LIK_BERNOULLI_LOGIT = 1, VIF_LIK_POISSON_LOG = 2 } vif_likelihood;
+/* Arithmetic of the per-point factor, V / U storage and the low-rank
+ * products. The m x m Cholesky factorisations, log-determinants and final
+ * reductions are FP64 in every form. */
+typedef enum { VIF_FP64 = 0, VIF_FP32 = 1, VIF_BF16_IN = 2 } vif_precision;
+
+typedef struct {
+  int64_t n;          /* number of points */
+  int32_t d;          /* input dimension (1..8) */
+  int32_t m;          /* inducing points (0..1024) */
+  int32_t m_v;        /* max neighbours per point (0..32) */
+  int32_t kernel;     /* vif_kernel */
+  int32_t likelihood; /* vif_likelihood */
+  int32_t precision;  /* vif_precision */
+  double tau_m;       /* fixed jitter added to the diagonal of Sigma_m */
+  /* Laplace / CG controls (Sec. 3-4) */
+  double cg_tol;      /* ||r_k|| <= cg_tol ||rhs|| */
+  int32_t cg_maxit;
+  int32_t newton_maxit;
+  double newton_tol;  /* stop when |Psi_{t+1} - Psi_t| <= newton_tol (1 + |Psi_{t+1}|) */
+} vif_config;
+
+typedef struct vif_ctx vif_ctx;
+
+/* Allocates the context and all device workspace for the sizes in cfg on the
+ * current HIP device; no later call allocates. */
+vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out);
+void vif_destroy(vif_ctx* ctx);
+const char* vif_last_error(const vif_ctx* ctx);
+
+/* Correlation-based conditioning sets (Sec. 6, correlation distance d_c with
+ * the residual covariance c_r). For i <= m_v (0-based) N(i) = {0..i-1};
+ * otherwise the m_v earlier points with the smallest key 1 - |rho_ij|,
+ * rho_ij = c_r(i,j) / sqrt(c_r(i,i) c_r(j,j)), c_r(i,j) = c(s_i,s_j) +
+ * s2 [i==j] - V_i.V_j, ties broken by the smaller index, |rho| < 1e-10 taken
+ * as 0. Exact FP64 brute force over all earlier points (the set the paper's
+ * cover tree of Alg. 3-4 also returns). nbr_out: device n x m_v int32, sorted
+ * by (key, index), -1 padded. */
+vif_status vif_select_neighbors(vif_ctx* ctx, const double* X, const double* Z,
+                                const double* theta, int32_t* nbr_out);
+
+/* Builds Sigma_m, L_m, V and the residual factor (A_i, D_i) of
+ * eq. D_A_Vecchia for every point, plus U = D^{-1/2} B V^T and the Woodbury
+ * matrix M' = I + U^T U, whose congruence L_m M' L_m^T is M of eq. def_M.
+ * nbr is device n x m_v int32 (entries must satisfy -1 or 0 <= j < i, -1 only
+ * in a trailing run). Returns VIF_E_NOT_PD naming the first failing point. */
+vif_status vif_build_factor(vif_ctx* ctx, const double* X, const double* Z,
+                            const int32_t* nbr, const double* theta);
+
+/* Gaussian NLL of Sec. 2.1 via SMW / Sylvester (Sec. 2.2), using the factor
+ * of the last vif_build_factor:
+ *   n/2 log 2pi + 1/2 (log det M' + sum_i log D_i) + 1/2 (yt.yt - s.s),
+ *   yt = D^{-1/2} B y, s = L_{M'}^{-1} U^T yt.  nll_out: host double. */
+vif_status vif_nll(vif_ctx* ctx, const double* y, double* nll_out);
+
+/* NLL and its gradient w.r.t. theta (Sec. 2.2, App. A) by a hand-written
+ * reverse-mode adjoint of the factor build; the per-point factors are
+ * recomputed, not stored. Requires the likelihood to be Gaussian.
+ * grad_out: host double[1 + L + 1] in the layout of theta. */
+vif_status vif_nll_grad(vif_ctx* ctx, const double* y, double* nll_out, double* grad_out);
+
+/* Copies the factor of the last build to device buffers A_out (n x m_v, the
+ * coefficients A_i over N(i), zero padded) and D_out (n), both double. */
+vif_status vif_export_factor(vif_ctx* ctx, double* A_out, double* D_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VIF_H_ */

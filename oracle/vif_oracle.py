@@ -446,3 +446,30 @@ def nll_gaussian_grad(model: Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarra
             dquad += float(-2.0 * du @ Minv_u + Minv_u @ dM @ Minv_u)
         grads[p] = 0.5 * dlogdet + 0.5 * dquad
     return base.nll, grads
+
+
+def vecchia_factor_points(model: Model, X: np.ndarray, ind: Inducing, nbr_rows: np.ndarray,
+                          points: np.ndarray):
+    """A_i, D_i (eq. D_A_Vecchia) for selected points only; nbr_rows[r] is
+    N(points[r]) (-1 padded). Returns (A rows, D) in the order given."""
+    points = np.asarray(points)
+    mv = nbr_rows.shape[1]
+    A = np.zeros((points.size, mv))
+    D = np.zeros(points.size)
+    for r, i in enumerate(points):
+        NB = nbr_rows[r][nbr_rows[r] >= 0]
+        k = NB.size
+        qii = float(ind.Smn[:, i] @ ind.W[:, i]) if ind.m else 0.0
+        c = model.sigma1_sq + model.s2 - qii
+        if k == 0:
+            D[r] = c
+            continue
+        R = cov(model, X[NB], X[NB]) + model.s2 * np.eye(k)
+        rr = cov(model, X[NB], X[i:i + 1])[:, 0]
+        if ind.m:
+            R = R - ind.Smn[:, NB].T @ ind.W[:, NB]
+            rr = rr - ind.Smn[:, NB].T @ ind.W[:, i]
+        a = np.linalg.solve(R, rr)
+        A[r, :k] = a
+        D[r] = c - a @ rr
+    return A, D

@@ -1,0 +1,323 @@
+// C ABI of the VIF library: context, workspace, argument checks and the
+// launch sequence of each entry point on the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/vif.h"
+#include "common.h"
+#include "kernels.h"
+
+struct vif_ctx {
+  vif_config cfg;
+  hipStream_t st = nullptr;
+  int device = 0;
+  int mp = 0;
+  std::string err;
+  CovParams cp{};
+  int chunk = 2048, nchunk = 1;
+  // device workspace
+  double *Sm = nullptr, *Linv = nullptr, *Mp = nullptr, *LMinv = nullptr;
+  double* Vd = nullptr;  // n x mp, FP64 (factor storage in the FP64 form, and the neighbour search)
+  float* Vf = nullptr;   // n x mp, FP32 storage (FP32 form)
+  void* A = nullptr;     // n x m_v (double or float)
+  void* U = nullptr;     // n x mp (double or float)
+  double *D = nullptr, *yt = nullptr, *vnorm = nullptr;
+  double *partial = nullptr, *vecpart = nullptr, *vec = nullptr;
+  double* scal = nullptr;  // [0] logdet Sigma_m, [1] logdet M', [4..7] NLL outputs
+  int* status = nullptr;   // [0] code, [1] stage, [2] index
+  double* hscal = nullptr;  // pinned host mirror of scal
+  int* hstatus = nullptr;
+  bool built = false;
+  // the context's own copy of the neighbour list of the last build (the
+  // caller's buffer may be freed after vif_build_factor returns)
+  int32_t* nbr = nullptr;
+  bool nbr_valid = false;
+  bool rev_valid = false;  // reverse (transposed) neighbour lists built for c->nbr
+};
+
+static vif_status fail(vif_ctx* c, vif_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return s;
+}
+
+#define HIPCHK(c, x)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess) return fail((c), VIF_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+static bool fp32_form(const vif_ctx* c) { return c->cfg.precision == VIF_FP32; }
+
+static size_t tsize(const vif_ctx* c) { return fp32_form(c) ? sizeof(float) : sizeof(double); }
+
+static vif_status set_params(vif_ctx* c, const double* theta) {
+  if (!theta) return fail(c, VIF_E_ARG, "theta is NULL");
+  const vif_config& g = c->cfg;
+  const int L = (g.kernel == VIF_GAUSSIAN_ARD) ? g.d : 1;
+  for (int k = 0; k < L + 2; ++k)
+    if (!isfinite(theta[k])) return fail(c, VIF_E_NAN, "theta[%d] is not finite", k);
+  if (!(theta[0] > 0)) return fail(c, VIF_E_ARG, "sigma1^2 must be > 0 (got %g)", theta[0]);
+  for (int k = 0; k < L; ++k)
+    if (!(theta[1 + k] > 0)) return fail(c, VIF_E_ARG, "length scale %d must be > 0 (got %g)", k, theta[1 + k]);
+  if (!(theta[L + 1] >= 0)) return fail(c, VIF_E_ARG, "s2 must be >= 0 (got %g)", theta[L + 1]);
+  CovParams p{};
+  p.kernel = g.kernel;
+  p.d = g.d;
+  p.sigma1_sq = theta[0];
+  p.s2 = theta[L + 1];
+  for (int k = 0; k < VIF_MAX_D; ++k) p.inv_ls[k] = (k < g.d) ? 1.0 / theta[1 + (L == 1 ? 0 : k)] : 0.0;
+  c->cp = p;
+  return VIF_OK;
+}
+
+// Entry checks of a neighbour list: -1 or 0 <= j < i, -1 only in a trailing
+// run, no duplicates. Flags the smallest offending point; status[4] is set
+// when the list differs from the context's copy `own`.
+__global__ void k_check_nbr(const int32_t* nbr, const int32_t* own, int64_t n, int mv, int* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool bad = false, seen_pad = false, diff = false;
+  for (int a = 0; a < mv; ++a) {
+    const int j = nbr[i * mv + a];
+    if (j != own[i * mv + a]) diff = true;
+    if (j < 0) {
+      if (j != -1) bad = true;
+      seen_pad = true;
+      continue;
+    }
+    if (seen_pad || j >= i) bad = true;
+    for (int b = 0; b < a; ++b)
+      if (nbr[i * mv + b] == j) bad = true;
+  }
+  if (bad) {
+    status[3] = 1;
+    atomicMin(&status[2], (int)i);
+  }
+  if (diff) status[4] = 1;
+}
+
+static vif_status reset_status(vif_ctx* c) {
+  const int init[8] = {0, 0, 0x7fffffff, 0, 0, 0, 0, 0};
+  HIPCHK(c, hipMemcpyAsync(c->status, init, sizeof init, hipMemcpyHostToDevice, c->st));
+  return VIF_OK;
+}
+
+static vif_status read_status(vif_ctx* c, const char* stage) {
+  HIPCHK(c, hipMemcpyAsync(c->hstatus, c->status, 8 * sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  const int* s = c->hstatus;
+  if (s[3]) return fail(c, VIF_E_ARG, "%s: invalid neighbour list at point %d", stage, s[2]);
+  if (s[0] == VIF_DEV_NOT_PD) {
+    if (s[1] == 1) return fail(c, VIF_E_NOT_PD, "%s: Sigma_m not positive definite at column %d", stage, s[2]);
+    if (s[1] == 2) return fail(c, VIF_E_NOT_PD, "%s: M' not positive definite at column %d", stage, s[2]);
+    return fail(c, VIF_E_NOT_PD, "%s: residual system not positive definite at point %d", stage, s[2]);
+  }
+  if (s[0] == VIF_DEV_NAN) return fail(c, VIF_E_NAN, "%s: non-finite value at %d", stage, s[2]);
+  return VIF_OK;
+}
+
+extern "C" {
+
+vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
+  if (!cfg || !out) return VIF_E_ARG;
+  *out = nullptr;
+  const vif_config& g = *cfg;
+  if (g.n < 1 || g.n > (int64_t)0x7ffffff0) return VIF_E_ARG;
+  if (g.d < 1 || g.d > VIF_MAX_D) return VIF_E_ARG;
+  if (g.m < 0 || g.m > 1024 || g.m > g.n) return VIF_E_ARG;
+  if (g.m_v < 0 || g.m_v > VIF_MAX_MV) return VIF_E_ARG;
+  if (g.kernel < 0 || g.kernel > 2 || g.likelihood < 0 || g.likelihood > 2) return VIF_E_ARG;
+  if (g.precision != VIF_FP64 && g.precision != VIF_FP32) return VIF_E_ARG;
+  if (g.kernel != VIF_GAUSSIAN_ARD && g.d > VIF_MAX_D) return VIF_E_ARG;
+  vif_ctx* c = new vif_ctx();
+  c->cfg = g;
+  c->st = (hipStream_t)hip_stream;
+  hipGetDevice(&c->device);
+  c->mp = round_up16(g.m);
+  const int64_t n = g.n;
+  const int mp = c->mp, mpa = mp > 0 ? mp : 1;
+  c->chunk = 2048;
+  while (ceil_div(n, c->chunk) > 256) c->chunk *= 2;
+  c->nchunk = (int)ceil_div(n, c->chunk);
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes > 0 ? bytes : 16);
+  };
+  alloc((void**)&c->Sm, sizeof(double) * mpa * mpa);
+  alloc((void**)&c->Linv, sizeof(double) * mpa * mpa);
+  alloc((void**)&c->Mp, sizeof(double) * mpa * mpa);
+  alloc((void**)&c->LMinv, sizeof(double) * mpa * mpa);
+  alloc((void**)&c->Vd, sizeof(double) * n * mpa);
+  if (fp32_form(c)) alloc((void**)&c->Vf, sizeof(float) * n * mpa);
+  alloc(&c->A, tsize(c) * n * (g.m_v > 0 ? g.m_v : 1));
+  alloc(&c->U, tsize(c) * n * mpa);
+  alloc((void**)&c->D, sizeof(double) * n);
+  alloc((void**)&c->yt, sizeof(double) * n);
+  alloc((void**)&c->vnorm, sizeof(double) * n);
+  alloc((void**)&c->partial, sizeof(double) * (size_t)c->nchunk * mpa * mpa);
+  alloc((void**)&c->vecpart, sizeof(double) * (size_t)c->nchunk * (mpa + 2));
+  alloc((void**)&c->vec, sizeof(double) * (mpa + 2));
+  alloc((void**)&c->scal, sizeof(double) * 16);
+  alloc((void**)&c->status, sizeof(int) * 8);
+  alloc((void**)&c->nbr, sizeof(int32_t) * n * (g.m_v > 0 ? g.m_v : 1));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->hscal, sizeof(double) * 16, 0);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->hstatus, sizeof(int) * 8, 0);
+  if (e != hipSuccess) {
+    vif_destroy(c);
+    return (e == hipErrorOutOfMemory) ? VIF_E_OOM : VIF_E_HIP;
+  }
+  *out = c;
+  return VIF_OK;
+}
+
+void vif_destroy(vif_ctx* c) {
+  if (!c) return;
+  if (c->st) hipStreamSynchronize(c->st); else hipDeviceSynchronize();
+  void* bufs[] = {c->Sm, c->Linv, c->Mp, c->LMinv, c->Vd, c->Vf, c->A, c->U, c->D, c->yt, c->vnorm,
+                  c->partial, c->vecpart, c->vec, c->scal, c->status, c->nbr};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  if (c->hscal) hipHostFree(c->hscal);
+  if (c->hstatus) hipHostFree(c->hstatus);
+  delete c;
+}
+
+const char* vif_last_error(const vif_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+// Sigma_m, its Cholesky factor and inverse, and V (FP64) -- shared by the
+// neighbour search and the factor build.
+static vif_status build_inducing(vif_ctx* c, const double* X, const double* Z, bool fp64_V) {
+  const vif_config& g = c->cfg;
+  if (g.m == 0) return VIF_OK;
+  if (!Z) return fail(c, VIF_E_ARG, "Z is NULL with m > 0");
+  launch_cov_zz(c->st, Z, g.m, c->mp, c->cp, g.tau_m, c->Sm);
+  launch_chol_inv(c->st, c->Sm, c->Linv, g.m, c->mp, c->scal + 0, c->status, 1);
+  if (fp64_V)
+    launch_whiten<double>(c->st, X, Z, c->Linv, g.m, c->mp, g.n, c->cp, false, c->Vd);
+  else
+    launch_whiten<float>(c->st, X, Z, c->Linv, g.m, c->mp, g.n, c->cp, false, c->Vf);
+  HIPCHK(c, hipGetLastError());
+  return VIF_OK;
+}
+
+vif_status vif_select_neighbors(vif_ctx* c, const double* X, const double* Z, const double* theta, int32_t* nbr_out) {
+  if (!c) return VIF_E_ARG;
+  if (!X || !nbr_out) return fail(c, VIF_E_ARG, "NULL X or nbr_out");
+  vif_status s = set_params(c, theta);
+  if (s) return s;
+  const vif_config& g = c->cfg;
+  if (g.m_v == 0) return VIF_OK;
+  if ((s = reset_status(c))) return s;
+  if (g.m > 0) {
+    if ((s = build_inducing(c, X, Z, true))) return s;
+    launch_rownorm<double>(c->st, c->Vd, g.n, c->mp, c->vnorm);
+  } else {
+    HIPCHK(c, hipMemsetAsync(c->vnorm, 0, sizeof(double) * g.n, c->st));
+  }
+  launch_knn(c->st, X, c->Vd, c->vnorm, g.n, c->mp, g.m_v, c->cp, nbr_out);
+  HIPCHK(c, hipGetLastError());
+  return read_status(c, "vif_select_neighbors");
+}
+
+vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const int32_t* nbr, const double* theta) {
+  if (!c) return VIF_E_ARG;
+  c->built = false;
+  if (!X) return fail(c, VIF_E_ARG, "X is NULL");
+  if (c->cfg.m_v > 0 && !nbr) return fail(c, VIF_E_ARG, "nbr is NULL with m_v > 0");
+  vif_status s = set_params(c, theta);
+  if (s) return s;
+  const vif_config& g = c->cfg;
+  if ((s = reset_status(c))) return s;
+  if (g.m_v > 0)
+    hipLaunchKernelGGL(k_check_nbr, dim3((unsigned)ceil_div(g.n, 256)), dim3(256), 0, c->st, nbr, c->nbr, g.n,
+                       g.m_v, c->status);
+  const bool f32 = fp32_form(c);
+  if ((s = build_inducing(c, X, Z, !f32))) return s;
+  if (f32)
+    launch_factor<float>(c->st, X, c->Vf, nbr, g.n, c->mp, g.m_v, c->cp, (float*)c->A, c->D, (float*)c->U, c->status);
+  else
+    launch_factor<double>(c->st, X, c->Vd, nbr, g.n, c->mp, g.m_v, c->cp, (double*)c->A, c->D, (double*)c->U,
+                          c->status);
+  if (g.m > 0) {
+    int nchunk = 0;
+    if (f32)
+      launch_gram_partial<float>(c->st, (const float*)c->U, g.n, c->mp, c->chunk, c->partial, &nchunk);
+    else
+      launch_gram_partial<double>(c->st, (const double*)c->U, g.n, c->mp, c->chunk, c->partial, &nchunk);
+    launch_reduce_gram(c->st, c->partial, nchunk, c->mp, c->Mp);
+    launch_chol_inv(c->st, c->Mp, c->LMinv, g.m, c->mp, c->scal + 1, c->status, 2);
+  }
+  HIPCHK(c, hipGetLastError());
+  s = read_status(c, "vif_build_factor");
+  if (s) return s;
+  if (g.m_v > 0 && (c->hstatus[4] || !c->nbr_valid)) {
+    HIPCHK(c, hipMemcpyAsync(c->nbr, nbr, sizeof(int32_t) * g.n * g.m_v, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->nbr_valid = true;
+    c->rev_valid = false;
+  }
+  c->built = true;
+  return VIF_OK;
+}
+
+vif_status vif_nll(vif_ctx* c, const double* y, double* nll_out) {
+  if (!c) return VIF_E_ARG;
+  if (!c->built) return fail(c, VIF_E_STATE, "vif_nll before a successful vif_build_factor");
+  if (!y || !nll_out) return fail(c, VIF_E_ARG, "NULL y or nll_out");
+  const vif_config& g = c->cfg;
+  if (g.likelihood != VIF_LIK_GAUSSIAN) return fail(c, VIF_E_ARG, "vif_nll needs the Gaussian likelihood");
+  const bool f32 = fp32_form(c);
+  if (f32)
+    launch_ytilde<float>(c->st, (const float*)c->A, c->D, c->nbr, y, g.n, g.m_v, c->yt);
+  else
+    launch_ytilde<double>(c->st, (const double*)c->A, c->D, c->nbr, y, g.n, g.m_v, c->yt);
+  const int len = c->mp + 2;
+  if (f32)
+    launch_uty_partial<float>(c->st, (const float*)c->U, c->yt, c->D, g.n, c->mp, c->chunk, c->vecpart);
+  else
+    launch_uty_partial<double>(c->st, (const double*)c->U, c->yt, c->D, g.n, c->mp, c->chunk, c->vecpart);
+  launch_vec_reduce(c->st, c->vecpart, c->nchunk, len, c->vec);
+  launch_nll_final(c->st, c->LMinv, c->vec, c->vec + c->mp, g.m, c->mp, c->scal + 1, g.n, c->scal + 4);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * 8, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  *nll_out = c->hscal[4];
+  if (!isfinite(*nll_out)) return fail(c, VIF_E_NAN, "NLL is not finite");
+  return VIF_OK;
+}
+
+vif_status vif_nll_grad(vif_ctx* c, const double* y, double* nll_out, double* grad_out) {
+  (void)y; (void)nll_out; (void)grad_out;
+  return fail(c, VIF_E_STATE, "vif_nll_grad is not available in this build");
+}
+
+__global__ void k_export_A(const void* A, bool f32, int64_t count, double* out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  out[q] = f32 ? (double)((const float*)A)[q] : ((const double*)A)[q];
+}
+
+vif_status vif_export_factor(vif_ctx* c, double* A_out, double* D_out) {
+  if (!c) return VIF_E_ARG;
+  if (!c->built) return fail(c, VIF_E_STATE, "vif_export_factor before a successful vif_build_factor");
+  const vif_config& g = c->cfg;
+  const int64_t cnt = g.n * g.m_v;
+  if (A_out && cnt > 0)
+    hipLaunchKernelGGL(k_export_A, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, c->st, c->A, fp32_form(c), cnt,
+                       A_out);
+  if (D_out) HIPCHK(c, hipMemcpyAsync(D_out, c->D, sizeof(double) * g.n, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return VIF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Shared device helpers of the VIF library: covariance functions, MFMA
+// wrappers with their lane layouts, wave reductions, launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define VIF_MAX_D 8
+#define VIF_MAX_MV 31  // the per-point system (m_v neighbours + the point) fits 32 MFMA rows
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// Covariance c(x, x') = sigma1^2 r(t), t = ||(x - x') / lambda|| (Sec. 2,
+// Assumption 2; ARD transform of Sec. 6). Matern-1/2: e^{-t};
+// Matern-3/2: (1 + sqrt3 t) e^{-sqrt3 t}; Gaussian: e^{-t^2/2}.
+struct CovParams {
+  int kernel;  // 0 Matern-1/2, 1 Matern-3/2, 2 Gaussian
+  int d;
+  double sigma1_sq;
+  double s2;                // nugget (Gaussian) or latent jitter tau
+  double inv_ls[VIF_MAX_D];  // 1 / lambda_k (isotropic: all equal)
+};
+
+template <typename T>
+__device__ __forceinline__ T cov_profile(int kernel, T t2) {
+  // r(t) from t^2 (t >= 0)
+  if (kernel == 2) return exp(T(-0.5) * t2);
+  T t = sqrt(t2);
+  if (kernel == 0) return exp(-t);
+  const T s3 = T(1.7320508075688772);
+  return (T(1) + s3 * t) * exp(-s3 * t);
+}
+
+// d r / d lambda for the isotropic kernels, given t and lambda: r'(t) * (-t / lambda)
+template <typename T>
+__device__ __forceinline__ T cov_profile_dls(int kernel, T t2, T inv_ls) {
+  T t = sqrt(t2);
+  if (kernel == 2) return t2 * exp(T(-0.5) * t2) * inv_ls;        // t^2 e^{-t^2/2} / lambda
+  if (kernel == 0) return t * exp(-t) * inv_ls;                     // t e^{-t} / lambda
+  const T s3 = T(1.7320508075688772);
+  return T(3) * t2 * exp(-s3 * t) * inv_ls;                         // 3 t^2 e^{-sqrt3 t} / lambda
+}
+
+template <typename T>
+__device__ __forceinline__ T scaled_sqdist(const CovParams& p, const double* a, const double* b) {
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < VIF_MAX_D; ++k) {
+    if (k < p.d) {
+      T z = T((a[k] - b[k]) * p.inv_ls[k]);
+      s += z * z;
+    }
+  }
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T cov_eval(const CovParams& p, const double* a, const double* b) {
+  return T(p.sigma1_sq) * cov_profile<T>(p.kernel, scaled_sqdist<T>(p, a, b));
+}
+
+// ---------------------------------------------------------------------------
+// MFMA wrappers. Lane layouts (verified on gfx950 with an in-bounds probe):
+//  f32 16x16x4 : A lane l holds A[l%16][l/16], B holds B[l/16][l%16],
+//                D element v of lane l is D[4*(l/16)+v][l%16].
+//  f64 16x16x4 : A, B as f32;  D element v of lane l is D[l/16 + 4*v][l%16].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> struct Acc4;
+template <> struct Acc4<double> { typedef d4 type; };
+template <> struct Acc4<float> { typedef f4 type; };
+
+// Row index (within a 16x16 tile) of accumulator element v held by lane.
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int v);
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int v) { return (lane >> 4) + 4 * v; }
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int v) { return 4 * (lane >> 4) + v; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__host__ __device__ static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline int round_up16(int m) { return (m + 15) / 16 * 16; }
+
+// Status words written by kernels (device int[4]): [0] error code, [1] index
+#define VIF_DEV_OK 0
+#define VIF_DEV_NOT_PD 3
+#define VIF_DEV_NAN 2

@@ -1,0 +1,124 @@
+// Reductions over points for the Woodbury / Sylvester step (Sec. 2.2):
+// M' = I + U^T U (the whitened eq. def_M), U^T yt, sum_i log D_i, yt^T yt.
+// Split over point chunks; each chunk writes an FP64 partial, a second pass
+// adds the partials in a fixed order (run-to-run reproducible, no atomics).
+#include "common.h"
+#include "kernels.h"
+
+// Partial U^T U of one point chunk for one 64 x 64 block of the lower
+// triangle. Each wave: a 32 x 32 sub-block (2 x 2 MFMA tiles), K = points.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_partial(const T* __restrict__ U, int64_t n, int mp, int chunk,
+                                                      double* __restrict__ partial) {
+  typedef typename Acc4<T>::type A4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  // block index -> (bi, bj), bi >= bj
+  int blk = blockIdx.y, bi = 0;
+  while (blk > bi) { blk -= bi + 1; ++bi; }
+  const int bj = blk;
+  const int L0 = bi * 64 + 32 * (w >> 1), C0 = bj * 64 + 32 * (w & 1);
+  if (L0 >= mp || C0 >= mp || C0 > L0 + 31) return;
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk;
+  const int64_t pend = min(n, pbeg + chunk);
+  bool rok[2], cok[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    rok[t] = L0 + 16 * t < mp;
+    cok[t] = C0 + 16 * t < mp;
+  }
+  A4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = A4{0, 0, 0, 0};
+  for (int64_t p0 = pbeg; p0 < pend; p0 += 4) {
+    const int64_t pp = p0 + g;
+    const bool pv = pp < pend;
+    const T* row = U + (size_t)(pv ? pp : pbeg) * mp;
+    T a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      a[t] = (pv && rok[t]) ? row[L0 + 16 * t + r] : T(0);
+      b[t] = (pv && cok[t]) ? row[C0 + 16 * t + r] : T(0);
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[x][y] = mfma16(a[x], b[y], acc[x][y]);
+  }
+  double* out = partial + (size_t)blockIdx.x * mp * mp;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+      if (rok[x] && cok[y])
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          out[(size_t)(L0 + 16 * x + acc_row<T>(lane, v)) * mp + C0 + 16 * y + r] = (double)acc[x][y][v];
+}
+
+// Per chunk: U^T yt (mp values), sum log D, sum yt^2 -> partial[chunk][mp + 2]
+template <typename T>
+__global__ __launch_bounds__(256) void k_uty_partial(const T* __restrict__ U, const double* __restrict__ yt,
+                                                     const double* __restrict__ D, int64_t n, int mp, int chunk,
+                                                     double* __restrict__ partial) {
+  __shared__ double red[2][4];
+  const int tid = threadIdx.x;
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk;
+  const int64_t pend = min(n, pbeg + chunk);
+  double* out = partial + (size_t)blockIdx.x * (mp + 2);
+  for (int l = tid; l < mp; l += 256) {
+    double s = 0.0;
+    for (int64_t p = pbeg; p < pend; ++p) s += (double)U[(size_t)p * mp + l] * yt[p];
+    out[l] = s;
+  }
+  double sl = 0.0, sy = 0.0;
+  for (int64_t p = pbeg + tid; p < pend; p += 256) {
+    sl += log(D[p]);
+    sy += yt[p] * yt[p];
+  }
+  sl = wave_sum(sl);
+  sy = wave_sum(sy);
+  if ((tid & 63) == 0) { red[0][tid >> 6] = sl; red[1][tid >> 6] = sy; }
+  __syncthreads();
+  if (tid == 0) {
+    out[mp] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    out[mp + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+__global__ void k_vec_reduce(const double* __restrict__ partial, int nchunk, int len, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= len) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += partial[(size_t)c * len + j];
+  out[j] = s;
+}
+
+template <typename T>
+void launch_gram_partial(hipStream_t st, const T* U, int64_t n, int mp, int chunk, double* partial, int* nchunk_out) {
+  const int nchunk = (int)ceil_div(n, chunk);
+  const int nb = (mp + 63) / 64;
+  dim3 grid(nchunk, nb * (nb + 1) / 2);
+  hipLaunchKernelGGL((k_gram_partial<T>), grid, dim3(256), 0, st, U, n, mp, chunk, partial);
+  *nchunk_out = nchunk;
+}
+
+template <typename T>
+void launch_uty_partial(hipStream_t st, const T* U, const double* yt, const double* D, int64_t n, int mp, int chunk,
+                        double* partial) {
+  const int nchunk = (int)ceil_div(n, chunk);
+  hipLaunchKernelGGL((k_uty_partial<T>), dim3(nchunk), dim3(256), 0, st, U, yt, D, n, mp, chunk, partial);
+}
+
+void launch_vec_reduce(hipStream_t st, const double* partial, int nchunk, int len, double* out) {
+  hipLaunchKernelGGL(k_vec_reduce, dim3((unsigned)ceil_div(len, 256)), dim3(256), 0, st, partial, nchunk, len, out);
+}
+
+template void launch_gram_partial<double>(hipStream_t, const double*, int64_t, int, int, double*, int*);
+template void launch_gram_partial<float>(hipStream_t, const float*, int64_t, int, int, double*, int*);
+template void launch_uty_partial<double>(hipStream_t, const double*, const double*, const double*, int64_t, int, int,
+                                         double*);
+template void launch_uty_partial<float>(hipStream_t, const float*, const double*, const double*, int64_t, int, int,
+                                        double*);

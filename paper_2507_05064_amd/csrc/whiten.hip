@@ -1,0 +1,91 @@
+// Whitened inducing features V = L_m^{-1} K(Z, X) (Sec. 2.1, eq. def_b_low:
+// V_i . V_j = Sigma_mi^T Sigma_m^{-1} Sigma_mj), stored point-major (n x mp)
+// so that a neighbour gather reads one contiguous row per point.
+//
+// One workgroup = 64 points x 128 rows of V; each wave owns 16 points and
+// the 8 row blocks. K(z_j, x_p) is evaluated on the fly as the B operand of
+// FP64 MFMA 16x16x4 and reused across the 8 row blocks; L_m^{-1} (lower
+// triangular, zero padded to mp) is the A operand and its zero upper part is
+// skipped. Always FP64 arithmetic; the store casts to the storage type.
+#include "common.h"
+#include "kernels.h"
+
+template <typename T, bool DERIV>
+__global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ X, const double* __restrict__ Z,
+                                                const double* __restrict__ Linv, int m, int mp, int64_t n,
+                                                CovParams p, T* __restrict__ V) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int64_t pt = (int64_t)blockIdx.x * 64 + 16 * w + c;
+  const bool pvalid = pt < n;
+  const int l0 = blockIdx.y * 128;
+  const int nrb = min(8, (mp - l0) / 16);
+  double xp[VIF_MAX_D];
+#pragma unroll
+  for (int k = 0; k < VIF_MAX_D; ++k) xp[k] = (pvalid && k < p.d) ? X[pt * p.d + k] : 0.0;
+  d4 acc[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) acc[r] = d4{0.0, 0.0, 0.0, 0.0};
+  const int jmax = min(m, l0 + nrb * 16);
+  for (int j0 = 0; j0 < jmax; j0 += 4) {
+    const int j = j0 + g;
+    double b = 0.0;
+    if (j < m && pvalid) {
+      const double t2 = scaled_sqdist<double>(p, Z + (size_t)j * p.d, xp);
+      b = DERIV ? p.sigma1_sq * cov_profile_dls<double>(p.kernel, t2, p.inv_ls[0])
+                : p.sigma1_sq * cov_profile<double>(p.kernel, t2);
+    }
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+      if (rb < nrb && j0 <= l0 + rb * 16 + 15) {
+        const double a = Linv[(size_t)(l0 + rb * 16 + c) * mp + j];
+        acc[rb] = mfma16(a, b, acc[rb]);
+      }
+    }
+  }
+  if (!pvalid) return;
+  T* vrow = V + (size_t)pt * mp + l0;
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb) {
+    if (rb < nrb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) vrow[rb * 16 + acc_row<double>(lane, v)] = (T)acc[rb][v];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_rownorm(const T* __restrict__ V, int64_t n, int mp, double* out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  double s = 0.0;
+  for (int l = lane; l < mp; l += 64) {
+    const double v = (double)V[(size_t)i * mp + l];
+    s += v * v;
+  }
+  s = wave_sum(s);
+  if (lane == 0) out[i] = s;
+}
+
+template <typename T>
+void launch_whiten(hipStream_t st, const double* X, const double* Z, const double* Linv, int m, int mp, int64_t n,
+                   const CovParams& p, bool deriv, T* V) {
+  dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(mp, 128));
+  if (deriv)
+    hipLaunchKernelGGL((k_whiten<T, true>), grid, dim3(256), 0, st, X, Z, Linv, m, mp, n, p, V);
+  else
+    hipLaunchKernelGGL((k_whiten<T, false>), grid, dim3(256), 0, st, X, Z, Linv, m, mp, n, p, V);
+}
+
+template <typename T>
+void launch_rownorm(hipStream_t st, const T* V, int64_t n, int mp, double* out) {
+  hipLaunchKernelGGL((k_rownorm<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, V, n, mp, out);
+}
+
+template void launch_whiten<double>(hipStream_t, const double*, const double*, const double*, int, int, int64_t,
+                                    const CovParams&, bool, double*);
+template void launch_whiten<float>(hipStream_t, const double*, const double*, const double*, int, int, int64_t,
+                                   const CovParams&, bool, float*);
+template void launch_rownorm<double>(hipStream_t, const double*, int64_t, int, double*);
+template void launch_rownorm<float>(hipStream_t, const float*, int64_t, int, double*);

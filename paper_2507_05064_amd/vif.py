@@ -1,0 +1,155 @@
+"""Python binding of libvif.so (ctypes): argument marshalling only.
+
+Every computation runs in the HIP library. Arrays are torch tensors on the
+GPU (their data_ptr() is passed as a device pointer); the library's stream is
+torch's current stream at context creation. There is no CPU fallback: if the
+library is not built, or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvif.so")
+_lib = None
+
+MATERN12, MATERN32, GAUSSIAN_ARD = 0, 1, 2
+LIK_GAUSSIAN, LIK_BERNOULLI_LOGIT, LIK_POISSON_LOG = 0, 1, 2
+FP64, FP32, BF16_IN = 0, 1, 2
+KERNELS = {"matern12": MATERN12, "matern32": MATERN32, "gaussian_ard": GAUSSIAN_ARD}
+LIKELIHOODS = {"gaussian": LIK_GAUSSIAN, "bernoulli_logit": LIK_BERNOULLI_LOGIT, "poisson_log": LIK_POISSON_LOG}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16_in": BF16_IN}
+
+STATUS = {0: "VIF_OK", 1: "VIF_E_ARG", 2: "VIF_E_NAN", 3: "VIF_E_NOT_PD", 4: "VIF_E_CG_MAXIT",
+          5: "VIF_E_NEWTON", 6: "VIF_E_HIP", 7: "VIF_E_OOM", 8: "VIF_E_STATE"}
+
+
+class VifError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class vif_config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("m", ctypes.c_int32), ("m_v", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("likelihood", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("tau_m", ctypes.c_double), ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
+                ("newton_maxit", ctypes.c_int32), ("newton_tol", ctypes.c_double)]
+
+
+EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors", "vif_build_factor", "vif_nll",
+           "vif_nll_grad", "vif_export_factor"]
+
+
+def load_library(path: Optional[str] = None):
+    """Loads libvif.so; raises if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or _LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libvif.so not built ({p}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    vp, i32p, dp = ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    lib.vif_create.argtypes = [ctypes.POINTER(vif_config), vp, ctypes.POINTER(vp)]
+    lib.vif_create.restype = ctypes.c_int
+    lib.vif_destroy.argtypes = [vp]
+    lib.vif_destroy.restype = None
+    lib.vif_last_error.argtypes = [vp]
+    lib.vif_last_error.restype = ctypes.c_char_p
+    lib.vif_select_neighbors.argtypes = [vp, vp, vp, dp, i32p]
+    lib.vif_select_neighbors.restype = ctypes.c_int
+    lib.vif_build_factor.argtypes = [vp, vp, vp, i32p, dp]
+    lib.vif_build_factor.restype = ctypes.c_int
+    lib.vif_nll.argtypes = [vp, vp, dp]
+    lib.vif_nll.restype = ctypes.c_int
+    lib.vif_nll_grad.argtypes = [vp, vp, dp, dp]
+    lib.vif_nll_grad.restype = ctypes.c_int
+    lib.vif_export_factor.argtypes = [vp, vp, vp]
+    lib.vif_export_factor.restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dbl_array(x: Sequence[float]):
+    arr = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    return arr, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class VifContext:
+    """One vif_ctx (workspace sized for n, d, m, m_v) on torch's current stream."""
+
+    def __init__(self, n: int, d: int, m: int, m_v: int, kernel: str = "matern32",
+                 likelihood: str = "gaussian", precision: str = "fp64", tau_m: float = 0.0,
+                 cg_tol: float = 1e-6, cg_maxit: int = 1000, newton_maxit: int = 100, newton_tol: float = 1e-9):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the VIF library has no CPU path")
+        self.lib = load_library()
+        self.cfg = vif_config(n, d, m, m_v, KERNELS[kernel], LIKELIHOODS[likelihood], PRECISIONS[precision],
+                              tau_m, cg_tol, cg_maxit, newton_maxit, newton_tol)
+        self.stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = self.lib.vif_create(ctypes.byref(self.cfg), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise VifError(rc, "vif_create failed")
+        self.h = h
+        self.n, self.d, self.m, self.m_v = n, d, m, m_v
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.vif_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != 0:
+            raise VifError(rc, self.lib.vif_last_error(self.h).decode())
+
+    def select_neighbors(self, X: torch.Tensor, Z: torch.Tensor, theta) -> torch.Tensor:
+        nbr = torch.empty((self.n, self.m_v), dtype=torch.int32, device=X.device)
+        th, thp = _dbl_array(theta)
+        self._check(self.lib.vif_select_neighbors(self.h, _ptr(X), _ptr(Z) if self.m else None, thp, _ptr(nbr)))
+        return nbr
+
+    def build_factor(self, X: torch.Tensor, Z: torch.Tensor, nbr: torch.Tensor, theta):
+        th, thp = _dbl_array(theta)
+        self._check(self.lib.vif_build_factor(self.h, _ptr(X), _ptr(Z) if self.m else None,
+                                              _ptr(nbr) if self.m_v else None, thp))
+
+    def nll(self, y: torch.Tensor) -> float:
+        out = ctypes.c_double()
+        self._check(self.lib.vif_nll(self.h, _ptr(y), ctypes.byref(out)))
+        return out.value
+
+    def nll_grad(self, y: torch.Tensor, n_theta: int):
+        out = ctypes.c_double()
+        g = np.zeros(n_theta)
+        self._check(self.lib.vif_nll_grad(self.h, _ptr(y), ctypes.byref(out),
+                                          g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.value, g
+
+    def export_factor(self):
+        A = torch.empty((self.n, max(self.m_v, 0)), dtype=torch.float64, device="cuda")
+        D = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        self._check(self.lib.vif_export_factor(self.h, _ptr(A) if self.m_v else None, _ptr(D)))
+        return A, D

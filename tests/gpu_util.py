@@ -1,0 +1,50 @@
+"""Helpers shared by the GPU tests: seeded problems and comparisons."""
+import numpy as np
+import torch
+
+import vif_inputs as vi
+from oracle import vif_oracle as vo
+
+
+def problem(w: vi.Workload):
+    X = vi.coords(w)
+    Z = vi.inducing_points(w, X)
+    model = vo.Model(w.kernel, w.sigma1_sq, np.asarray(w.lengthscales, float), w.s2, w.tau_m)
+    return X, Z, model
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def nbr_to_dev(nbr: np.ndarray):
+    return to_dev(nbr.astype(np.int32), torch.int32)
+
+
+def compare_neighbour_sets(model, X, ind, nbr_o, nbr_g, queries=None, tie_tol=1e-12):
+    """Neighbour sets must match; a difference is accepted only as a near-tie:
+    every swapped candidate's oracle key lies within tie_tol of the oracle's
+    m_v-th key. Returns (number of exact matches, number of near-ties)."""
+    qs = np.arange(nbr_o.shape[0]) if queries is None else np.asarray(queries)
+    exact = ties = 0
+    for r, i in enumerate(qs):
+        so = set(nbr_o[r][nbr_o[r] >= 0].tolist())
+        sg = set(nbr_g[r][nbr_g[r] >= 0].tolist())
+        assert len(sg) == len(nbr_g[r][nbr_g[r] >= 0]), f"duplicate neighbour at {i}"
+        assert all(j < i for j in sg), f"neighbour not earlier at {i}"
+        if so == sg:
+            exact += 1
+            continue
+        assert len(so) == len(sg), f"neighbour count differs at {i}"
+        diff = np.array(sorted(so ^ sg))
+        keys = vo.neighbour_keys(model, X, ind, int(i), diff)
+        kth = vo.neighbour_keys(model, X, ind, int(i), np.array(sorted(so))).max()
+        assert np.all(np.abs(keys - kth) <= tie_tol), (i, keys, kth)
+        ties += 1
+    return exact, ties
+
+
+def factor_rel_err(A_g, D_g, A_o, D_o):
+    ea = np.max(np.abs(A_g - A_o)) / max(np.max(np.abs(A_o)), 1e-300) if A_o.size else 0.0
+    ed = np.max(np.abs(D_g - D_o) / np.abs(D_o))
+    return ea, ed

@@ -1,0 +1,147 @@
+"""GPU parity of the factor build, neighbour selection and Gaussian NLL
+against the FP64 oracle (same seeded inputs on both sides).
+
+Tolerances (FP64 form): neighbour sets identical except near-ties whose
+oracle keys differ by <= 1e-12; A_i within 1e-10 of max|A| and D_i within
+1e-10 relative; NLL within 1e-10 relative. FP32 form: NLL within 2e-5
+relative -- the per-point systems are formed and factored in FP32 (unit
+roundoff 6e-8) with condition numbers up to ~1/s2 = 100 (C1), so A, D carry
+~1e-5 relative error, and the NLL is a sum of n such terms whose errors
+partly cancel.
+"""
+import numpy as np
+import pytest
+import torch
+
+import vif_inputs as vi
+from oracle import vif_oracle as vo
+from tests import dense_ref as dr
+from tests.gpu_util import compare_neighbour_sets, factor_rel_err, nbr_to_dev, problem, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(w, n=None, m=None, mv=None, precision="fp64"):
+    from paper_2507_05064_amd.vif import VifContext
+    return VifContext(n or w.n, w.d, w.m if m is None else m, w.m_v if mv is None else mv, kernel=w.kernel,
+                      likelihood=w.likelihood, precision=precision, tau_m=w.tau_m)
+
+
+def _y_exact(model, X, seed):
+    C = dr.exact_cov(model, X)
+    return np.linalg.cholesky(C) @ np.random.default_rng(seed).standard_normal(X.shape[0])
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = vi.config1()
+    X, Z, model = problem(w)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, w.m_v)
+    y = _y_exact(model, X, 11)
+    return w, X, Z, model, ind, nbr, y
+
+
+def test_c1_neighbours(c1):
+    w, X, Z, model, ind, nbr_o, y = c1
+    print(f"[gpu] C1 neighbours n={w.n} m={w.m} m_v={w.m_v}", flush=True)
+    ctx = _ctx(w)
+    nbr_g = ctx.select_neighbors(to_dev(X), to_dev(Z), w.theta).cpu().numpy()
+    exact, ties = compare_neighbour_sets(model, X, ind, nbr_o, nbr_g)
+    assert exact + ties == w.n
+    assert ties <= 2
+
+
+def test_c1_factor_and_nll_fp64(c1):
+    w, X, Z, model, ind, nbr, y = c1
+    print(f"[gpu] C1 factor/NLL fp64", flush=True)
+    fac = vo.vecchia_factor(model, X, ind, nbr)
+    nll_o = vo.nll_gaussian(model, X, Z, nbr, y).nll
+    ctx = _ctx(w)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    A_g, D_g = (t.cpu().numpy() for t in ctx.export_factor())
+    ea, ed = factor_rel_err(A_g, D_g, fac.A, fac.D)
+    assert ea <= 1e-10 and ed <= 1e-10, (ea, ed)
+    nll_g = ctx.nll(to_dev(y))
+    assert abs(nll_g - nll_o) <= 1e-10 * abs(nll_o), (nll_g, nll_o)
+
+
+def test_c1_nll_fp32(c1):
+    w, X, Z, model, ind, nbr, y = c1
+    print(f"[gpu] C1 NLL fp32", flush=True)
+    nll_o = vo.nll_gaussian(model, X, Z, nbr, y).nll
+    ctx = _ctx(w, precision="fp32")
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    nll_g = ctx.nll(to_dev(y))
+    assert abs(nll_g - nll_o) <= 2e-5 * abs(nll_o), (nll_g, nll_o)
+
+
+@pytest.mark.parametrize("n,m,mv", [(1, 0, 5), (2, 1, 3), (7, 3, 10), (33, 5, 15), (300, 0, 12),
+                                    (300, 17, 0), (517, 33, 31), (2500, 200, 20)])
+def test_shapes_and_edges_fp64(n, m, mv):
+    """Ragged heads, n < m_v, no inducing points (classical Vecchia), no
+    neighbours (FITC), m not a multiple of 16, 31 neighbours (two MFMA row
+    blocks), several point tiles."""
+    w = vi.scaled(vi.config2(), n, m=m, m_v=mv)
+    print(f"[gpu] shapes n={n} m={m} m_v={mv}", flush=True)
+    X, Z, model = problem(w)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, mv)
+    y = np.random.default_rng(n).standard_normal(n)
+    ctx = _ctx(w)
+    Xd, Zd = to_dev(X), to_dev(Z) if m else None
+    if mv:
+        nbr_g = ctx.select_neighbors(Xd, Zd, w.theta).cpu().numpy()
+        exact, ties = compare_neighbour_sets(model, X, ind, nbr, nbr_g)
+        assert exact + ties == n
+    ctx.build_factor(Xd, Zd, nbr_to_dev(nbr) if mv else None, w.theta)
+    A_g, D_g = (t.cpu().numpy() for t in ctx.export_factor())
+    fac = vo.vecchia_factor(model, X, ind, nbr)
+    ea, ed = factor_rel_err(A_g, D_g, fac.A, fac.D)
+    assert ea <= 1e-10 and ed <= 1e-10, (ea, ed)
+    nll_o = vo.nll_gaussian(model, X, Z, nbr, y).nll
+    nll_g = ctx.nll(to_dev(y))
+    assert abs(nll_g - nll_o) <= 1e-10 * abs(nll_o), (nll_g, nll_o)
+
+
+def test_full_conditioning_equals_exact_gp_on_gpu():
+    """m_v = n - 1 (n = 32): the GPU NLL equals the dense exact GP NLL."""
+    n = 32
+    w = vi.scaled(vi.config1(), n, m=6, m_v=n - 1)
+    X, Z, model = problem(w)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, n - 1)
+    y = _y_exact(model, X, 5)
+    ctx = _ctx(w)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    ref = dr.gaussian_nll_dense(dr.exact_cov(model, X), y)
+    assert abs(ctx.nll(to_dev(y)) - ref) <= 1e-10 * abs(ref)
+
+
+def test_invalid_neighbour_list_is_rejected():
+    from paper_2507_05064_amd.vif import VifError
+    w = vi.scaled(vi.config1(), 50, m=5, m_v=4)
+    X, Z, model = problem(w)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, 4)
+    nbr[30, 1] = 30  # not an earlier point
+    ctx = _ctx(w)
+    with pytest.raises(VifError) as e:
+        ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    assert e.value.code == 1 and "point 30" in str(e.value)
+
+
+def test_not_pd_is_reported():
+    from paper_2507_05064_amd.vif import VifError
+    w = vi.scaled(vi.config1(), 60, m=0, m_v=5)
+    X, Z, model = problem(w)
+    X[40] = X[7]
+    model0 = vo.Model(model.kernel, model.sigma1_sq, model.ls, 0.0)
+    ind = vo.inducing(model0, X, Z)
+    nbr = vo.neighbours(model0, X, ind, 5)
+    ctx = _ctx(w)
+    theta = w.theta.copy()
+    theta[-1] = 0.0
+    with pytest.raises(VifError) as e:
+        ctx.build_factor(to_dev(X), None, nbr_to_dev(nbr), theta)
+    assert e.value.code == 3 and "point 40" in str(e.value)
