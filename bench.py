@@ -1,0 +1,175 @@
+#!/usr/bin/env python
+"""Benchmark of the VIF hot path on one MI355X.
+
+Step = one evaluation of the Gaussian VIF negative log-likelihood and its
+gradient w.r.t. (variance, range, nugget) at n = 100,000 (d = 2, Matern-3/2
+variance 1 range 0.05, nugget 0.05, m = 200 inducing points, m_v = 20
+correlation neighbours): Sigma_m Cholesky, whitening, per-point factor,
+Woodbury/Sylvester reduction, adjoint gradient. Inputs are resident in HBM
+before the timed region; the neighbour search runs once before it (as in the
+paper, neighbour selection is not part of a likelihood evaluation).
+
+Prints one JSON line. ``value`` is FP32-form evaluations per second; the
+FP64 form is reported beside it under "fp64".
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "VIF NLL+grad evals/sec at n=100k (FP32 vs FP64); Laplace mode time, PCG iters"
+HBM_PEAK_GBS = 8000.0
+
+
+def factor_bytes_per_point(m: int, mv: int, d: int, tsize: int) -> int:
+    """Algorithmic HBM bytes of the per-point factor kernel for one point with
+    m_v neighbours: gather (m_v + 1) rows of V, the neighbour indices and the
+    m_v + 1 coordinates; write the U row, A_i and D_i."""
+    return (mv + 1) * m * tsize + mv * 4 + (mv + 1) * d * 8 + m * tsize + mv * tsize + 8
+
+
+def run_form(w, Xd, Zd, nbr, yd, precision, steps, warmup, grad):
+    import torch
+    from paper_2507_05064_amd.vif import VifContext
+    ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=w.likelihood, precision=precision,
+                     tau_m=w.tau_m)
+    theta = w.theta
+    nth = theta.size
+
+    def step():
+        ctx.build_factor(Xd, Zd, nbr, theta)
+        if grad:
+            return ctx.nll_grad(yd, nth)
+        return ctx.nll(yd), None
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    stages = ctx.timing()
+    ctx.set_timing(False)
+    ctx.close()
+    return dict(ms_per_step=1000.0 * wall / steps, gpu_ms_per_step=gpu_ms / steps, nll=out[0],
+                grad=None if out[1] is None else [float(v) for v in out[1]],
+                stages={k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1] > 0})
+
+
+def cpu_baseline(w, budget_points=6000):
+    """Oracle (FP64 numpy) NLL + forward-mode gradient on the first
+    `budget_points` points of the same workload (the prefix is itself a VIF
+    problem: its conditioning sets only reach earlier points), scaled by
+    n / budget_points to evaluations per second at full n."""
+    from oracle import vif_oracle as vo
+    import vif_inputs as vi
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    X = vi.coords(w)[:budget_points]
+    Z = vi.inducing_points(w, vi.coords(w))
+    model = vo.Model(w.kernel, w.sigma1_sq, np.asarray(w.lengthscales, float), w.s2, w.tau_m)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, w.m_v)
+    y = vi.normals(w, budget_points, stream=vi.STREAM_NOISE) * math.sqrt(w.sigma1_sq + w.s2)
+    t0 = time.perf_counter()
+    vo.nll_gaussian_grad(model, X, Z, nbr, y)
+    sec = time.perf_counter() - t0
+    sec_full = sec * w.n / budget_points
+    return {"value": 1.0 / sec_full, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"NLL + forward-mode gradient on the first {budget_points} of {w.n} points "
+                      f"({sec:.1f} s), scaled linearly to n={w.n}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--nll-only", action="store_true", help="time the NLL without the gradient")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import vif_inputs as vi
+    from paper_2507_05064_amd.vif import VifContext
+
+    w = vi.config2()
+    X = vi.coords(w)
+    Z = vi.inducing_points(w, X)
+    Xd = torch.as_tensor(X, device="cuda")
+    Zd = torch.as_tensor(Z, device="cuda")
+    sel = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, precision="fp64", tau_m=w.tau_m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nbr = sel.select_neighbors(Xd, Zd, w.theta)
+    torch.cuda.synchronize()
+    knn_s = time.perf_counter() - t0
+    sel.close()
+    # response: iid N(0, sigma1^2 + nugget) draws (the cost of an evaluation
+    # does not depend on the values of y)
+    y = vi.normals(w, w.n) * math.sqrt(w.sigma1_sq + w.s2)
+    yd = torch.as_tensor(y, device="cuda")
+    grad = not args.nll_only
+
+    r32 = run_form(w, Xd, Zd, nbr, yd, "fp32", args.steps, args.warmup, grad)
+    r64 = run_form(w, Xd, Zd, nbr, yd, "fp64", args.steps, args.warmup, grad)
+
+    fac_ms = r32["stages"].get("factor", float("nan"))
+    nbytes = w.n * factor_bytes_per_point(w.m, w.m_v, w.d, 4)
+    achieved = nbytes / (fac_ms * 1e-3) / 1e9
+    res = {
+        "metric": METRIC,
+        "value": 1000.0 / r32["ms_per_step"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"Gaussian VIF NLL{'+grad' if grad else ''}: n={w.n} d={w.d} Matern-3/2 "
+                               f"(var 1, range 0.05), nugget 0.05, m={w.m} random-subset inducing points, "
+                               f"m_v={w.m_v} correlation neighbours, random ordering",
+                   "objective": "nll+grad" if grad else "nll", "n": w.n, "m": w.m, "m_v": w.m_v},
+        "fp64": {"value": 1000.0 / r64["ms_per_step"], "unit": "evals/s", "ms_per_step": r64["ms_per_step"],
+                 "nll": r64["nll"], "grad": r64["grad"]},
+        "fp32_nll": r32["nll"],
+        "fp32_grad": r32["grad"],
+        "fp32_rel_err_vs_fp64_gpu": abs(r32["nll"] - r64["nll"]) / abs(r64["nll"]),
+        "stage_ms": {"fp32": r32["stages"], "fp64": r64["stages"]},
+        "neighbour_search_s": knn_s,
+        "roofline": {"bound": "hbm", "kernel": "k_factor<float>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": nbytes, "avg_launch_ms": fac_ms},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

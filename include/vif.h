@@ -119,6 +119,18 @@ vif_status vif_nll_grad(vif_ctx* ctx, const double* y, double* nll_out, double* 
  * coefficients A_i over N(i), zero padded) and D_out (n), both double. */
 vif_status vif_export_factor(vif_ctx* ctx, double* A_out, double* D_out);
 
+/* Per-stage device time, for profiling. When enabled, every entry point
+ * records a pair of HIP events around each of its stages on the context's
+ * stream; the elapsed times are added up at the call's own synchronisation
+ * point. vif_set_timing also clears the totals. Stage names (see
+ * vif_timing_stage_name): inducing_chol, whiten, factor, woodbury_gram,
+ * woodbury_chol, nll_tail, knn, and the gradient stages. ms_out / count_out
+ * are host arrays of nstage entries. */
+vif_status vif_set_timing(vif_ctx* ctx, int enable);
+int vif_timing_stages(void);
+const char* vif_timing_stage_name(int stage);
+vif_status vif_get_timing(vif_ctx* ctx, double* ms_out, int64_t* count_out, int nstage);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,8 +11,23 @@
 #include "common.h"
 #include "kernels.h"
 
+enum Stage { ST_INDUCING = 0, ST_WHITEN, ST_FACTOR, ST_GRAM, ST_MCHOL, ST_NLL, ST_KNN, ST_GPREP, ST_UBAR,
+             ST_FBWD, ST_VBAR, ST_SGRAD, ST_WDERIV, ST_REV, ST_COUNT };
+static const char* kStageNames[ST_COUNT] = {
+    "inducing_chol", "whiten", "factor", "woodbury_gram", "woodbury_chol", "nll_tail", "knn", "grad_prep",
+    "grad_ubar_gemm", "grad_factor_bwd", "grad_vbar", "grad_sigma_m", "grad_whiten_deriv", "reverse_lists"};
+
+struct StageTimer {
+  hipEvent_t b = nullptr, e = nullptr;
+  bool pending = false;
+  double ms = 0.0;
+  int64_t count = 0;
+};
+
 struct vif_ctx {
   vif_config cfg;
+  bool timing = false;
+  StageTimer timers[ST_COUNT];
   hipStream_t st = nullptr;
   int device = 0;
   int mp = 0;
@@ -20,7 +35,7 @@ struct vif_ctx {
   CovParams cp{};
   int chunk = 2048, nchunk = 1;
   // device workspace
-  double *Sm = nullptr, *Linv = nullptr, *Mp = nullptr, *LMinv = nullptr;
+  double *Sm = nullptr, *Linv = nullptr, *Mp = nullptr, *LMinv = nullptr, *Mwork = nullptr;
   double* Vd = nullptr;  // n x mp, FP64 (factor storage in the FP64 form, and the neighbour search)
   float* Vf = nullptr;   // n x mp, FP32 storage (FP32 form)
   void* A = nullptr;     // n x m_v (double or float)
@@ -37,6 +52,12 @@ struct vif_ctx {
   int32_t* nbr = nullptr;
   bool nbr_valid = false;
   bool rev_valid = false;  // reverse (transposed) neighbour lists built for c->nbr
+  double *Xc = nullptr, *Zc = nullptr;  // the context's copies of X and Z of the last build
+  // gradient workspace
+  double *Minv = nullptr, *wvec = nullptr, *e = nullptr, *Smat = nullptr, *Tm = nullptr, *tmpm = nullptr;
+  void *MinvT = nullptr, *Ubar = nullptr, *rho = nullptr, *G = nullptr, *S = nullptr, *Vr = nullptr;
+  double *tpart = nullptr, *vpart = nullptr, *rowpart = nullptr, *gred = nullptr;
+  int *rev_cnt = nullptr, *rev_ptr = nullptr, *rev_cur = nullptr, *rev_idx = nullptr;
 };
 
 static vif_status fail(vif_ctx* c, vif_status s, const char* fmt, ...) {
@@ -54,6 +75,30 @@ static vif_status fail(vif_ctx* c, vif_status s, const char* fmt, ...) {
     hipError_t e_ = (x);                                                                  \
     if (e_ != hipSuccess) return fail((c), VIF_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
   } while (0)
+
+static void stage_begin(vif_ctx* c, int s) {
+  if (c->timing) hipEventRecord(c->timers[s].b, c->st);
+}
+static void stage_end(vif_ctx* c, int s) {
+  if (c->timing) {
+    hipEventRecord(c->timers[s].e, c->st);
+    c->timers[s].pending = true;
+  }
+}
+// After a stream synchronisation: add the elapsed time of every recorded stage.
+static void harvest(vif_ctx* c) {
+  if (!c->timing) return;
+  for (int s = 0; s < ST_COUNT; ++s) {
+    StageTimer& t = c->timers[s];
+    if (!t.pending) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.b, t.e) == hipSuccess) {
+      t.ms += ms;
+      t.count += 1;
+    }
+    t.pending = false;
+  }
+}
 
 static bool fp32_form(const vif_ctx* c) { return c->cfg.precision == VIF_FP32; }
 
@@ -114,6 +159,7 @@ static vif_status reset_status(vif_ctx* c) {
 static vif_status read_status(vif_ctx* c, const char* stage) {
   HIPCHK(c, hipMemcpyAsync(c->hstatus, c->status, 8 * sizeof(int), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  harvest(c);
   const int* s = c->hstatus;
   if (s[3]) return fail(c, VIF_E_ARG, "%s: invalid neighbour list at point %d", stage, s[2]);
   if (s[0] == VIF_DEV_NOT_PD) {
@@ -145,8 +191,9 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   c->mp = round_up16(g.m);
   const int64_t n = g.n;
   const int mp = c->mp, mpa = mp > 0 ? mp : 1;
-  c->chunk = 2048;
-  while (ceil_div(n, c->chunk) > 256) c->chunk *= 2;
+  // point chunks of the split reductions: about 512 chunks (256 points at least)
+  c->chunk = 256;
+  while (ceil_div(n, c->chunk) > 512) c->chunk *= 2;
   c->nchunk = (int)ceil_div(n, c->chunk);
   hipError_t e = hipSuccess;
   auto alloc = [&](void** p, size_t bytes) {
@@ -156,6 +203,7 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   alloc((void**)&c->Linv, sizeof(double) * mpa * mpa);
   alloc((void**)&c->Mp, sizeof(double) * mpa * mpa);
   alloc((void**)&c->LMinv, sizeof(double) * mpa * mpa);
+  alloc((void**)&c->Mwork, sizeof(double) * mpa * mpa);
   alloc((void**)&c->Vd, sizeof(double) * n * mpa);
   if (fp32_form(c)) alloc((void**)&c->Vf, sizeof(float) * n * mpa);
   alloc(&c->A, tsize(c) * n * (g.m_v > 0 ? g.m_v : 1));
@@ -169,6 +217,35 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   alloc((void**)&c->scal, sizeof(double) * 16);
   alloc((void**)&c->status, sizeof(int) * 8);
   alloc((void**)&c->nbr, sizeof(int32_t) * n * (g.m_v > 0 ? g.m_v : 1));
+  alloc((void**)&c->Xc, sizeof(double) * n * g.d);
+  alloc((void**)&c->Zc, sizeof(double) * (g.m > 0 ? g.m : 1) * g.d);
+  if (g.likelihood == VIF_LIK_GAUSSIAN) {
+    const size_t mvn = (size_t)n * (g.m_v > 0 ? g.m_v : 1);
+    alloc((void**)&c->Minv, sizeof(double) * mpa * mpa);
+    alloc((void**)&c->Smat, sizeof(double) * mpa * mpa);
+    alloc((void**)&c->Tm, sizeof(double) * mpa * mpa);
+    alloc((void**)&c->tmpm, sizeof(double) * mpa * mpa);
+    alloc((void**)&c->wvec, sizeof(double) * mpa);
+    alloc((void**)&c->e, sizeof(double) * n);
+    alloc(&c->MinvT, tsize(c) * mpa * mpa);
+    alloc(&c->Ubar, tsize(c) * n * mpa);
+    alloc(&c->rho, tsize(c) * mvn);
+    alloc(&c->G, tsize(c) * n * mpa);
+    alloc(&c->S, tsize(c) * n * mpa);
+    alloc(&c->Vr, tsize(c) * n * mpa);
+    alloc((void**)&c->tpart, sizeof(double) * n * 3);
+    alloc((void**)&c->vpart, sizeof(double) * n * 2);
+    alloc((void**)&c->rowpart, sizeof(double) * mpa * 2);
+    alloc((void**)&c->gred, sizeof(double) * (ceil_div(n, 4096) * 5 + ceil_div(mpa, 4096) * 2 + 16));
+    alloc((void**)&c->rev_cnt, sizeof(int) * n);
+    alloc((void**)&c->rev_ptr, sizeof(int) * (n + 1));
+    alloc((void**)&c->rev_cur, sizeof(int) * n);
+    alloc((void**)&c->rev_idx, sizeof(int) * mvn);
+  }
+  for (int t = 0; t < ST_COUNT && e == hipSuccess; ++t) {
+    e = hipEventCreate(&c->timers[t].b);
+    if (e == hipSuccess) e = hipEventCreate(&c->timers[t].e);
+  }
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->hscal, sizeof(double) * 16, 0);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->hstatus, sizeof(int) * 8, 0);
   if (e != hipSuccess) {
@@ -182,10 +259,16 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
 void vif_destroy(vif_ctx* c) {
   if (!c) return;
   if (c->st) hipStreamSynchronize(c->st); else hipDeviceSynchronize();
-  void* bufs[] = {c->Sm, c->Linv, c->Mp, c->LMinv, c->Vd, c->Vf, c->A, c->U, c->D, c->yt, c->vnorm,
-                  c->partial, c->vecpart, c->vec, c->scal, c->status, c->nbr};
+  void* bufs[] = {c->Sm, c->Linv, c->Mp, c->LMinv, c->Mwork, c->Vd, c->Vf, c->A, c->U, c->D, c->yt, c->vnorm,
+                  c->partial, c->vecpart, c->vec, c->scal, c->status, c->nbr, c->Xc, c->Zc, c->Minv, c->wvec,
+                  c->e, c->Smat, c->Tm, c->tmpm, c->MinvT, c->Ubar, c->rho, c->G, c->S, c->Vr, c->tpart,
+                  c->vpart, c->rowpart, c->gred, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx};
   for (void* b : bufs)
     if (b) hipFree(b);
+  for (int t = 0; t < ST_COUNT; ++t) {
+    if (c->timers[t].b) hipEventDestroy(c->timers[t].b);
+    if (c->timers[t].e) hipEventDestroy(c->timers[t].e);
+  }
   if (c->hscal) hipHostFree(c->hscal);
   if (c->hstatus) hipHostFree(c->hstatus);
   delete c;
@@ -193,18 +276,48 @@ void vif_destroy(vif_ctx* c) {
 
 const char* vif_last_error(const vif_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+vif_status vif_set_timing(vif_ctx* c, int enable) {
+  if (!c) return VIF_E_ARG;
+  c->timing = enable != 0;
+  for (int t = 0; t < ST_COUNT; ++t) {
+    c->timers[t].ms = 0.0;
+    c->timers[t].count = 0;
+    c->timers[t].pending = false;
+  }
+  return VIF_OK;
+}
+
+int vif_timing_stages(void) { return ST_COUNT; }
+
+const char* vif_timing_stage_name(int stage) {
+  return (stage >= 0 && stage < ST_COUNT) ? kStageNames[stage] : "";
+}
+
+vif_status vif_get_timing(vif_ctx* c, double* ms_out, int64_t* count_out, int nstage) {
+  if (!c || !ms_out || nstage < 0) return VIF_E_ARG;
+  for (int t = 0; t < nstage && t < ST_COUNT; ++t) {
+    ms_out[t] = c->timers[t].ms;
+    if (count_out) count_out[t] = c->timers[t].count;
+  }
+  return VIF_OK;
+}
+
 // Sigma_m, its Cholesky factor and inverse, and V (FP64) -- shared by the
 // neighbour search and the factor build.
 static vif_status build_inducing(vif_ctx* c, const double* X, const double* Z, bool fp64_V) {
   const vif_config& g = c->cfg;
   if (g.m == 0) return VIF_OK;
   if (!Z) return fail(c, VIF_E_ARG, "Z is NULL with m > 0");
+  stage_begin(c, ST_INDUCING);
   launch_cov_zz(c->st, Z, g.m, c->mp, c->cp, g.tau_m, c->Sm);
-  launch_chol_inv(c->st, c->Sm, c->Linv, g.m, c->mp, c->scal + 0, c->status, 1);
+  launch_chol_inv(c->st, c->Sm, c->Linv, c->Mwork, g.m, c->mp, c->scal + 0, c->status, 1);
+  stage_end(c, ST_INDUCING);
+  stage_begin(c, ST_WHITEN);
   if (fp64_V)
     launch_whiten<double>(c->st, X, Z, c->Linv, g.m, c->mp, g.n, c->cp, false, c->Vd);
   else
     launch_whiten<float>(c->st, X, Z, c->Linv, g.m, c->mp, g.n, c->cp, false, c->Vf);
+  stage_end(c, ST_WHITEN);
   HIPCHK(c, hipGetLastError());
   return VIF_OK;
 }
@@ -223,7 +336,9 @@ vif_status vif_select_neighbors(vif_ctx* c, const double* X, const double* Z, co
   } else {
     HIPCHK(c, hipMemsetAsync(c->vnorm, 0, sizeof(double) * g.n, c->st));
   }
+  stage_begin(c, ST_KNN);
   launch_knn(c->st, X, c->Vd, c->vnorm, g.n, c->mp, g.m_v, c->cp, nbr_out);
+  stage_end(c, ST_KNN);
   HIPCHK(c, hipGetLastError());
   return read_status(c, "vif_select_neighbors");
 }
@@ -241,20 +356,33 @@ vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const 
     hipLaunchKernelGGL(k_check_nbr, dim3((unsigned)ceil_div(g.n, 256)), dim3(256), 0, c->st, nbr, c->nbr, g.n,
                        g.m_v, c->status);
   const bool f32 = fp32_form(c);
+  HIPCHK(c, hipMemcpyAsync(c->Xc, X, sizeof(double) * g.n * g.d, hipMemcpyDeviceToDevice, c->st));
+  if (g.m > 0) {
+    if (!Z) return fail(c, VIF_E_ARG, "Z is NULL with m > 0");
+    HIPCHK(c, hipMemcpyAsync(c->Zc, Z, sizeof(double) * g.m * g.d, hipMemcpyDeviceToDevice, c->st));
+  }
+  X = c->Xc;
+  Z = c->Zc;
   if ((s = build_inducing(c, X, Z, !f32))) return s;
+  stage_begin(c, ST_FACTOR);
   if (f32)
     launch_factor<float>(c->st, X, c->Vf, nbr, g.n, c->mp, g.m_v, c->cp, (float*)c->A, c->D, (float*)c->U, c->status);
   else
     launch_factor<double>(c->st, X, c->Vd, nbr, g.n, c->mp, g.m_v, c->cp, (double*)c->A, c->D, (double*)c->U,
                           c->status);
+  stage_end(c, ST_FACTOR);
   if (g.m > 0) {
     int nchunk = 0;
+    stage_begin(c, ST_GRAM);
     if (f32)
       launch_gram_partial<float>(c->st, (const float*)c->U, g.n, c->mp, c->chunk, c->partial, &nchunk);
     else
       launch_gram_partial<double>(c->st, (const double*)c->U, g.n, c->mp, c->chunk, c->partial, &nchunk);
     launch_reduce_gram(c->st, c->partial, nchunk, c->mp, c->Mp);
-    launch_chol_inv(c->st, c->Mp, c->LMinv, g.m, c->mp, c->scal + 1, c->status, 2);
+    stage_end(c, ST_GRAM);
+    stage_begin(c, ST_MCHOL);
+    launch_chol_inv(c->st, c->Mp, c->LMinv, c->Mwork, g.m, c->mp, c->scal + 1, c->status, 2);
+    stage_end(c, ST_MCHOL);
   }
   HIPCHK(c, hipGetLastError());
   s = read_status(c, "vif_build_factor");
@@ -276,6 +404,7 @@ vif_status vif_nll(vif_ctx* c, const double* y, double* nll_out) {
   const vif_config& g = c->cfg;
   if (g.likelihood != VIF_LIK_GAUSSIAN) return fail(c, VIF_E_ARG, "vif_nll needs the Gaussian likelihood");
   const bool f32 = fp32_form(c);
+  stage_begin(c, ST_NLL);
   if (f32)
     launch_ytilde<float>(c->st, (const float*)c->A, c->D, c->nbr, y, g.n, g.m_v, c->yt);
   else
@@ -287,17 +416,133 @@ vif_status vif_nll(vif_ctx* c, const double* y, double* nll_out) {
     launch_uty_partial<double>(c->st, (const double*)c->U, c->yt, c->D, g.n, c->mp, c->chunk, c->vecpart);
   launch_vec_reduce(c->st, c->vecpart, c->nchunk, len, c->vec);
   launch_nll_final(c->st, c->LMinv, c->vec, c->vec + c->mp, g.m, c->mp, c->scal + 1, g.n, c->scal + 4);
+  stage_end(c, ST_NLL);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * 8, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  harvest(c);
   *nll_out = c->hscal[4];
   if (!isfinite(*nll_out)) return fail(c, VIF_E_NAN, "NLL is not finite");
   return VIF_OK;
 }
 
+}  // extern "C"
+
+// Tail of the NLL on the device (no synchronisation): yt, U^T yt, sums, NLL.
+static void nll_tail(vif_ctx* c, const double* y) {
+  const vif_config& g = c->cfg;
+  const bool f32 = fp32_form(c);
+  if (f32)
+    launch_ytilde<float>(c->st, (const float*)c->A, c->D, c->nbr, y, g.n, g.m_v, c->yt);
+  else
+    launch_ytilde<double>(c->st, (const double*)c->A, c->D, c->nbr, y, g.n, g.m_v, c->yt);
+  const int len = c->mp + 2;
+  if (f32)
+    launch_uty_partial<float>(c->st, (const float*)c->U, c->yt, c->D, g.n, c->mp, c->chunk, c->vecpart);
+  else
+    launch_uty_partial<double>(c->st, (const double*)c->U, c->yt, c->D, g.n, c->mp, c->chunk, c->vecpart);
+  launch_vec_reduce(c->st, c->vecpart, c->nchunk, len, c->vec);
+  launch_nll_final(c->st, c->LMinv, c->vec, c->vec + c->mp, g.m, c->mp, c->scal + 1, g.n, c->scal + 4);
+}
+
+// grad = sum of the per-point, V-bar and Sigma_m parts (single thread).
+__global__ void k_grad_final(const double* tp, int nt, const double* vp, int nv, const double* rp, int nr,
+                             double inv_s1, double* out) {
+  double g0 = 0, g1 = 0, g2 = 0;
+  for (int b = 0; b < nt; ++b) { g0 += tp[b * 3]; g1 += tp[b * 3 + 1]; g2 += tp[b * 3 + 2]; }
+  for (int b = 0; b < nv; ++b) { g0 += vp[b * 2] * inv_s1; g1 += vp[b * 2 + 1]; }
+  for (int b = 0; b < nr; ++b) { g0 += rp[b * 2]; g1 += rp[b * 2 + 1]; }
+  out[0] = g0;
+  out[1] = g1;
+  out[2] = g2;
+}
+
+template <typename T>
+static vif_status nll_grad_impl(vif_ctx* c, const double* y) {
+  const vif_config& g = c->cfg;
+  const int mp = c->mp;
+  const T* V = (const T*)(fp32_form(c) ? (const void*)c->Vf : (const void*)c->Vd);
+  const T* U = (const T*)c->U;
+  if (g.m_v > 0 && !c->rev_valid) {
+    stage_begin(c, ST_REV);
+    launch_reverse_lists(c->st, c->nbr, g.n, g.m_v, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx);
+    stage_end(c, ST_REV);
+    c->rev_valid = true;
+  } else if (g.m_v == 0 && !c->rev_valid) {
+    HIPCHK(c, hipMemsetAsync(c->rev_ptr, 0, sizeof(int) * (g.n + 1), c->st));
+    c->rev_valid = true;
+  }
+  stage_begin(c, ST_NLL);
+  nll_tail(c, y);
+  stage_end(c, ST_NLL);
+  stage_begin(c, ST_GPREP);
+  if (g.m > 0) {
+    launch_gemm_sq(c->st, c->LMinv, c->LMinv, c->Minv, mp, true, false);
+    launch_prep_w<T>(c->st, c->Minv, c->vec, mp, c->wvec, (T*)c->MinvT);
+  }
+  launch_resid<T>(c->st, U, c->wvec, c->yt, g.n, mp, c->e);
+  stage_end(c, ST_GPREP);
+  stage_begin(c, ST_UBAR);
+  if (g.m > 0) launch_ubar<T>(c->st, U, (const T*)c->MinvT, c->e, c->wvec, g.n, mp, (T*)c->Ubar);
+  stage_end(c, ST_UBAR);
+  stage_begin(c, ST_FBWD);
+  launch_factor_bwd<T>(c->st, c->Xc, V, c->nbr, y, U, (const T*)c->Ubar, c->e, c->yt, g.n, mp, g.m_v, c->cp,
+                       (T*)c->rho, (T*)c->G, (T*)c->S, c->tpart, c->status);
+  stage_end(c, ST_FBWD);
+  int nv = 0, nr = 0;
+  double* tp = c->gred;
+  const int nt = launch_colsum(c->st, c->tpart, g.n, 3, tp);
+  double* vp = tp + (size_t)nt * 3;
+  double* rp = vp + (size_t)ceil_div(g.n, 4096) * 2;
+  if (g.m > 0) {
+    stage_begin(c, ST_WDERIV);
+    launch_whiten<T>(c->st, c->Xc, c->Zc, c->Linv, g.m, mp, g.n, c->cp, true, (T*)c->Vr);
+    stage_end(c, ST_WDERIV);
+    stage_begin(c, ST_VBAR);
+    T* Vbar = (T*)c->Ubar;  // Ubar is consumed by the per-point adjoint
+    launch_vbar<T>(c->st, (const T*)c->S, (const T*)c->G, U, c->D, (const T*)c->A, (const T*)c->rho, c->rev_ptr,
+                   c->rev_idx, V, (const T*)c->Vr, g.n, mp, g.m_v, Vbar, c->vpart);
+    stage_end(c, ST_VBAR);
+    stage_begin(c, ST_SGRAD);
+    int nchunk = 0;
+    launch_cross_partial<T>(c->st, V, Vbar, g.n, mp, c->chunk, c->partial, &nchunk);
+    launch_reduce_full(c->st, c->partial, nchunk, mp, c->Smat);
+    launch_gemm_sq(c->st, c->Smat, c->Linv, c->tmpm, mp, false, false);
+    launch_gemm_sq(c->st, c->Linv, c->tmpm, c->Tm, mp, true, false);
+    launch_sigma_m_grad(c->st, c->Tm, c->Zc, g.m, mp, c->cp, c->rowpart);
+    nv = launch_colsum(c->st, c->vpart, g.n, 2, vp);
+    nr = launch_colsum(c->st, c->rowpart, g.m, 2, rp);
+    stage_end(c, ST_SGRAD);
+  }
+  hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(1), 0, c->st, tp, nt, vp, nv, rp, nr, 1.0 / c->cp.sigma1_sq,
+                     c->scal + 8);
+  HIPCHK(c, hipGetLastError());
+  return VIF_OK;
+}
+
+extern "C" {
+
 vif_status vif_nll_grad(vif_ctx* c, const double* y, double* nll_out, double* grad_out) {
-  (void)y; (void)nll_out; (void)grad_out;
-  return fail(c, VIF_E_STATE, "vif_nll_grad is not available in this build");
+  if (!c) return VIF_E_ARG;
+  if (!c->built) return fail(c, VIF_E_STATE, "vif_nll_grad before a successful vif_build_factor");
+  if (!y || !nll_out || !grad_out) return fail(c, VIF_E_ARG, "NULL y, nll_out or grad_out");
+  const vif_config& g = c->cfg;
+  if (g.likelihood != VIF_LIK_GAUSSIAN) return fail(c, VIF_E_ARG, "vif_nll_grad needs the Gaussian likelihood");
+  if (g.kernel == VIF_GAUSSIAN_ARD)
+    return fail(c, VIF_E_ARG, "vif_nll_grad supports the isotropic kernels (one length scale)");
+  vif_status s = reset_status(c);
+  if (s) return s;
+  s = fp32_form(c) ? nll_grad_impl<float>(c, y) : nll_grad_impl<double>(c, y);
+  if (s) return s;
+  HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * 16, hipMemcpyDeviceToHost, c->st));
+  s = read_status(c, "vif_nll_grad");
+  if (s) return s;
+  *nll_out = c->hscal[4];
+  for (int k = 0; k < 3; ++k) grad_out[k] = c->hscal[8 + k];
+  if (!isfinite(*nll_out)) return fail(c, VIF_E_NAN, "NLL is not finite");
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(grad_out[k])) return fail(c, VIF_E_NAN, "gradient entry %d is not finite", k);
+  return VIF_OK;
 }
 
 __global__ void k_export_A(const void* A, bool f32, int64_t count, double* out) {

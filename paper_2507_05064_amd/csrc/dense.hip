@@ -14,126 +14,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// In-place Cholesky of the leading m x m block of A (row-major, leading
-// dimension ld); only the lower triangle is read and written. Left-looking,
-// 16-column blocks: block-column update (GEMM-like), diagonal block factored
-// by one wave in LDS, panel solved row-parallel. *s_fail = first failing
-// column + 1, or 0.
-__device__ void wg_chol(double* A, int m, int ld, int* s_fail) {
-  __shared__ double Lb[NB][NB + 1];
-  const int tid = threadIdx.x;
-  if (tid == 0) *s_fail = 0;
-  __syncthreads();
-  for (int kb = 0; kb < m; kb += NB) {
-    const int nb = min(NB, m - kb);
-    const int rows = m - kb;
-    // 1. A[i][kb+t] -= sum_{c<kb} L[i][c] L[kb+t][c]   (i >= kb + t)
-    for (int q = tid; q < rows * nb; q += WG) {
-      const int i = kb + q / nb, t = q % nb;
-      if (i < kb + t) continue;
-      const double* ai = A + (size_t)i * ld;
-      const double* aj = A + (size_t)(kb + t) * ld;
-      double s0 = 0, s1 = 0;
-      int c = 0;
-      for (; c + 1 < kb; c += 2) {
-        s0 += ai[c] * aj[c];
-        s1 += ai[c + 1] * aj[c + 1];
-      }
-      if (c < kb) s0 += ai[c] * aj[c];
-      A[(size_t)i * ld + kb + t] -= (s0 + s1);
-    }
-    __syncthreads();
-    // 2. diagonal block, one wave
-    if (tid < 64) {
-      for (int q = tid; q < nb * nb; q += 64) {
-        const int r = q / nb, c = q % nb;
-        Lb[r][c] = (c <= r) ? A[(size_t)(kb + r) * ld + kb + c] : 0.0;
-      }
-      wave_sync();
-      int fail = 0;
-      for (int j = 0; j < nb; ++j) {
-        const double piv = Lb[j][j];
-        if (!(piv > 0.0) || !isfinite(piv)) { fail = kb + j + 1; break; }
-        const double l = sqrt(piv);
-        wave_sync();
-        if (tid == j) Lb[j][j] = l;
-        if (tid > j && tid < nb) Lb[tid][j] /= l;
-        wave_sync();
-        if (tid > j && tid < nb) {
-          const double lr = Lb[tid][j];
-          for (int c = j + 1; c <= tid; ++c) Lb[tid][c] -= lr * Lb[c][j];
-        }
-        wave_sync();
-      }
-      if (tid == 0 && fail) *s_fail = fail;
-      if (!fail)
-        for (int q = tid; q < nb * nb; q += 64) {
-          const int r = q / nb, c = q % nb;
-          if (c <= r) A[(size_t)(kb + r) * ld + kb + c] = Lb[r][c];
-        }
-    }
-    __syncthreads();
-    if (*s_fail) return;
-    // 3. panel rows below: L[i][kb+t] = (A[i][kb+t] - sum_{u<t} L[i][kb+u] L_bb[t][u]) / L_bb[t][t]
-    for (int i = kb + nb + tid; i < m; i += WG) {
-      double* ai = A + (size_t)i * ld + kb;
-      double x[NB];
-#pragma unroll
-      for (int t = 0; t < NB; ++t) x[t] = (t < nb) ? ai[t] : 0.0;
-#pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        if (t < nb) {
-          double s = x[t];
-#pragma unroll
-          for (int u = 0; u < t; ++u) s -= x[u] * Lb[t][u];
-          x[t] = s / Lb[t][t];
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < NB; ++t) if (t < nb) ai[t] = x[t];
-    }
-    __syncthreads();
-  }
-}
-
-// X = L^{-1} for a lower-triangular L (leading m x m block, leading dimension
-// ld); X gets zeros above the diagonal and in the padding up to mp.
-__device__ void wg_trinv(const double* L, double* X, int m, int mp, int ld) {
-  const int tid = threadIdx.x;
-  for (int q = tid; q < mp * mp; q += WG) X[(size_t)(q / mp) * ld + (q % mp)] = 0.0;
-  __syncthreads();
-  for (int kb = 0; kb < m; kb += NB) {
-    const int nb = min(NB, m - kb);
-    const int ncol = kb + nb;
-    // S[t][c] = I[kb+t][c] - sum_{q<kb} L[kb+t][q] X[q][c]
-    for (int p = tid; p < nb * ncol; p += WG) {
-      const int t = p / ncol, c = p % ncol;
-      const double* lr = L + (size_t)(kb + t) * ld;
-      double s = (kb + t == c) ? 1.0 : 0.0;
-      for (int q = c; q < kb; ++q) s -= lr[q] * X[(size_t)q * ld + c];
-      X[(size_t)(kb + t) * ld + c] = s;
-    }
-    __syncthreads();
-    // forward substitution inside the block, one thread per column
-    for (int c = tid; c < ncol; c += WG) {
-      double x[NB];
-#pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        if (t < nb) {
-          const double* lr = L + (size_t)(kb + t) * ld + kb;
-          double s = X[(size_t)(kb + t) * ld + c];
-#pragma unroll
-          for (int u = 0; u < t; ++u) s -= lr[u] * x[u];
-          x[t] = (kb + t >= c) ? s / lr[t] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < NB; ++t) if (t < nb) X[(size_t)(kb + t) * ld + c] = x[t];
-    }
-    __syncthreads();
-  }
-}
-
 __device__ double wg_sum(double v) {
   __shared__ double red[WG / 64];
   v = wave_sum(v);
@@ -158,20 +38,190 @@ __global__ void k_cov_zz(const double* Z, int m, int mp, CovParams p, double tau
   }
 }
 
-// Cholesky of S (in place, lower), Linv = L^{-1}, out[0] = log det S.
-__global__ __launch_bounds__(WG) void k_chol_inv(double* S, double* Linv, int m, int mp, double* out,
-                                                 int* status, int code_base) {
+// Cholesky of S (in place, lower), Linv = L^{-1} and out[0] = log det S, in
+// one workgroup of 16 waves (m <= 1024; the matrices stay in L2).
+// Cholesky: right-looking over 32-column blocks; each diagonal block is
+// factored and inverted by one wave in LDS, the panel below it is
+// A_ib L_bb^{-T} and the trailing lower triangle is updated by 16x16 tiles,
+// both on FP64 MFMA. Inverse: X_jj = L_jj^{-1};
+// X_ij = -L_ii^{-1} sum_{k=j}^{i-1} L_ik X_kj, all block columns j advancing
+// one block row per step, the inner sums staged in `work` (mp x mp).
+#define CB 32
+__global__ __launch_bounds__(1024) void k_chol_inv(double* __restrict__ S, double* __restrict__ Linv,
+                                                   double* __restrict__ work, int m, int mp, double* out,
+                                                   int* status, int code_base) {
+  __shared__ double Db[CB][CB + 1];
+  __shared__ double Di[CB][CB + 1];
   __shared__ int s_fail;
-  wg_chol(S, m, mp, &s_fail);
-  if (s_fail) {
-    if (threadIdx.x == 0) { status[0] = VIF_DEV_NOT_PD; status[1] = code_base; status[2] = s_fail - 1; }
-    return;
+  __shared__ double red[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int nbk = (m + CB - 1) / CB;
+  for (int q = tid; q < mp * mp; q += 1024) Linv[q] = 0.0;
+  if (tid == 0) s_fail = 0;
+  __syncthreads();
+
+  for (int b = 0; b < nbk; ++b) {
+    const int kb = b * CB, nb = min(CB, m - kb);
+    // A. factor + invert the diagonal block (wave 0)
+    if (wv == 0) {
+      for (int q = lane; q < CB * CB; q += 64) {
+        const int rr = q / CB, cc = q % CB;
+        double v = (rr == cc) ? 1.0 : 0.0;
+        if (rr < nb && cc < nb && cc <= rr) v = S[(size_t)(kb + rr) * mp + kb + cc];
+        Db[rr][cc] = (cc <= rr) ? v : 0.0;
+      }
+      wave_sync();
+      int fail = 0;
+      for (int j = 0; j < CB; ++j) {
+        const double piv = Db[j][j];
+        if (!(piv > 0.0) || !isfinite(piv)) { fail = kb + j + 1; break; }
+        const double l = sqrt(piv);
+        wave_sync();
+        if (lane == j) Db[j][j] = l;
+        if (lane > j && lane < CB) Db[lane][j] /= l;
+        wave_sync();
+        if (lane > j && lane < CB) {
+          const double lr = Db[lane][j];
+          for (int c = j + 1; c <= lane; ++c) Db[lane][c] -= lr * Db[c][j];
+        }
+        wave_sync();
+      }
+      if (fail) {
+        if (lane == 0) s_fail = fail;
+      } else {
+        if (lane < CB) {  // column `lane` of the inverse, by forward substitution
+          for (int t = 0; t < CB; ++t) {
+            double sacc = (t == lane) ? 1.0 : 0.0;
+            for (int u = lane; u < t; ++u) sacc -= Db[t][u] * Di[u][lane];
+            Di[t][lane] = (t >= lane) ? sacc / Db[t][t] : 0.0;
+          }
+        }
+        wave_sync();
+        for (int q = lane; q < nb * nb; q += 64) {
+          const int rr = q / nb, cc = q % nb;
+          if (cc <= rr) {
+            S[(size_t)(kb + rr) * mp + kb + cc] = Db[rr][cc];
+            Linv[(size_t)(kb + rr) * mp + kb + cc] = Di[rr][cc];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (s_fail) {
+      if (tid == 0) { status[0] = VIF_DEV_NOT_PD; status[1] = code_base; status[2] = s_fail - 1; }
+      return;
+    }
+    const int T0 = kb + nb;
+    const int nt = (m - T0 + 15) / 16;
+    // B. panel L_ib = A_ib L_bb^{-T}
+    for (int t = wv; t < nt; t += 16) {
+      const int r0 = T0 + 16 * t;
+      d4 acc[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
+      const int row = r0 + r;
+#pragma unroll
+      for (int k0 = 0; k0 < CB; k0 += 4) {
+        const int kk = k0 + g;
+        const double a = (row < m && kk < nb) ? S[(size_t)row * mp + kb + kk] : 0.0;
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) acc[ct] = mfma16(a, Di[ct * 16 + r][kk], acc[ct]);
+      }
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = r0 + acc_row<double>(lane, v), cc = ct * 16 + r;
+          if (rr < m && cc < nb) S[(size_t)rr * mp + kb + cc] = acc[ct][v];
+        }
+    }
+    __syncthreads();
+    // C. trailing update of the lower 16x16 tiles: A_ij -= L_ib L_jb^T
+    const int ntile = nt * (nt + 1) / 2;
+    for (int q = wv; q < ntile; q += 16) {
+      int ti = 0, rem = q;
+      while (rem > ti) { rem -= ti + 1; ++ti; }
+      const int tj = rem;
+      const int R0 = T0 + 16 * ti, C0 = T0 + 16 * tj;
+      d4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = R0 + acc_row<double>(lane, v), cc = C0 + r;
+        acc[v] = (rr < m && cc < m) ? S[(size_t)rr * mp + cc] : 0.0;
+      }
+      const int ra = R0 + r, cb = C0 + r;
+#pragma unroll
+      for (int k0 = 0; k0 < CB; k0 += 4) {
+        const int kk = k0 + g;
+        const double a = (ra < m && kk < nb) ? -S[(size_t)ra * mp + kb + kk] : 0.0;
+        const double bb = (cb < m && kk < nb) ? S[(size_t)cb * mp + kb + kk] : 0.0;
+        acc = mfma16(a, bb, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = R0 + acc_row<double>(lane, v), cc = C0 + r;
+        if (rr < m && cc < m) S[(size_t)rr * mp + cc] = acc[v];
+      }
+    }
+    __syncthreads();
   }
-  wg_trinv(S, Linv, m, mp, mp);
-  double v = 0.0;
-  for (int i = threadIdx.x; i < m; i += WG) v += log(S[(size_t)i * mp + i]);
-  v = wg_sum(v);
-  if (threadIdx.x == 0) out[0] = 2.0 * v;
+
+  // log det = 2 sum log L_ii
+  {
+    double v = 0.0;
+    for (int i = tid; i < m; i += 1024) v += log(S[(size_t)i * mp + i]);
+    v = wave_sum(v);
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double sacc = 0.0;
+      for (int w = 0; w < 16; ++w) sacc += red[w];
+      out[0] = 2.0 * sacc;
+    }
+  }
+
+  // D. off-diagonal blocks of the inverse, one block row further per step
+  for (int s = 1; s < nbk; ++s) {
+    const int nitem = (nbk - s) * 4;
+    // D1. work_ij = sum_{k=j}^{i-1} L_ik X_kj  (i = j + s), 16x16 quadrant per item
+    for (int it = wv; it < nitem; it += 16) {
+      const int j = it >> 2, quad = it & 3, i = j + s;
+      const int R0 = i * CB + 16 * (quad >> 1), C0 = j * CB + 16 * (quad & 1);
+      d4 acc = {0, 0, 0, 0};
+      const int ra = R0 + r, cb = C0 + r;
+      for (int k0 = j * CB; k0 < i * CB; k0 += 4) {
+        const int kk = k0 + g;
+        const double a = (ra < m && kk < m) ? S[(size_t)ra * mp + kk] : 0.0;
+        const double bb = (kk < m && cb < m) ? Linv[(size_t)kk * mp + cb] : 0.0;
+        acc = mfma16(a, bb, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = R0 + acc_row<double>(lane, v), cc = C0 + r;
+        if (rr < mp && cc < mp) work[(size_t)rr * mp + cc] = acc[v];
+      }
+    }
+    __syncthreads();
+    // D2. X_ij = -L_ii^{-1} work_ij
+    for (int it = wv; it < nitem; it += 16) {
+      const int j = it >> 2, quad = it & 3, i = j + s;
+      const int R0 = i * CB + 16 * (quad >> 1), C0 = j * CB + 16 * (quad & 1);
+      d4 acc = {0, 0, 0, 0};
+      const int ra = R0 + r, cb = C0 + r;
+#pragma unroll
+      for (int k0 = 0; k0 < CB; k0 += 4) {
+        const int kk = i * CB + k0 + g;
+        const double a = (ra < m && kk < m) ? -Linv[(size_t)ra * mp + kk] : 0.0;
+        const double bb = (kk < m && cb < m) ? work[(size_t)kk * mp + cb] : 0.0;
+        acc = mfma16(a, bb, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = R0 + acc_row<double>(lane, v), cc = C0 + r;
+        if (rr < m && cc < m) Linv[(size_t)rr * mp + cc] = acc[v];
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // M' = I + sum_chunks partial over the lower triangle (every entry c <= l is
@@ -212,8 +262,9 @@ __global__ __launch_bounds__(WG) void k_nll_final(const double* LMinv, const dou
 void launch_cov_zz(hipStream_t st, const double* Z, int m, int mp, const CovParams& p, double tau_m, double* S) {
   hipLaunchKernelGGL(k_cov_zz, dim3(1, mp), dim3(256), 0, st, Z, m, mp, p, tau_m, S);
 }
-void launch_chol_inv(hipStream_t st, double* S, double* Linv, int m, int mp, double* out, int* status, int code) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(WG), 0, st, S, Linv, m, mp, out, status, code);
+void launch_chol_inv(hipStream_t st, double* S, double* Linv, double* work, int m, int mp, double* out, int* status,
+                     int code) {
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, st, S, Linv, work, m, mp, out, status, code);
 }
 void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp) {
   const int64_t total = (int64_t)mp * mp;

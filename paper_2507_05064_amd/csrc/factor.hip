@@ -30,29 +30,36 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+template <typename T>
+struct PointShared {
+  // Gram of the gathered rows; after the rows of C are in registers, the
+  // rows of the Cholesky factor L (row k = the point itself)
+  T GL[32][33];
+  double xs[32][VIF_MAX_D];  // coordinates of the rows
+  T As[32];                  // A_i
+  int nbs[32];               // row -> point index (N(i) then i)
+};
+
+// Steps 1-3 for point i, shared by the forward and the adjoint kernels.
+// On return (true): k = |N(i)|, D = D_i, Lrow = row `lane` of L (lanes
+// 0..k), sh.GL = L, sh.As = A_i, sh.nbs / sh.xs = row points / coordinates.
+// Returns false (after flagging status) when the system is not PD.
 template <typename T, int NBLK>
-__global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, const T* __restrict__ V,
-                                               const int32_t* __restrict__ nbr, int64_t n, int mp, int mv,
-                                               CovParams p, T* __restrict__ Aout, double* __restrict__ Dout,
-                                               T* __restrict__ U, int* status) {
+__device__ __forceinline__ bool factor_point(const double* __restrict__ X, const T* __restrict__ V,
+                                             const int32_t* __restrict__ nbr, int64_t i, int mp, int mv,
+                                             const CovParams& p, PointShared<T>& sh, T (&Lrow)[32], int& k_out,
+                                             T& D_out, int* status) {
   typedef typename Vec4<T>::type T4;
   typedef typename Acc4<T>::type A4;
-  // Gram of the gathered rows, then (after the rows of C are in registers)
-  // the rows of the Cholesky factor L
-  __shared__ T GL[32][33];
-  __shared__ double xs[32][VIF_MAX_D];
-  __shared__ T As[32];
-  __shared__ int nbs[32];
-
   const int lane = threadIdx.x;
-  const int64_t i = blockIdx.x;
   int nbv = (lane < mv) ? nbr[i * mv + lane] : -1;
   if (nbv >= i) nbv = -1;  // invalid entry (reported by the list check): never gather out of range
   const int k = __popcll(__ballot(nbv >= 0));
   const int rowpt = (lane < k) ? nbv : (lane == k ? (int)i : -1);
   if (lane < 32) {
-    nbs[lane] = rowpt;
-    for (int dd = 0; dd < VIF_MAX_D; ++dd) xs[lane][dd] = (rowpt >= 0 && dd < p.d) ? X[(int64_t)rowpt * p.d + dd] : 0.0;
+    sh.nbs[lane] = rowpt;
+    for (int dd = 0; dd < VIF_MAX_D; ++dd)
+      sh.xs[lane][dd] = (rowpt >= 0 && dd < p.d) ? X[(int64_t)rowpt * p.d + dd] : 0.0;
   }
 
   // 1. Gram of the gathered rows
@@ -79,10 +86,10 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int row = acc_row<T>(lane, v);
-    GL[row][r] = acc00[v];
+    sh.GL[row][r] = acc00[v];
     if (NBLK == 2) {
-      GL[16 + row][r] = acc10[v];
-      GL[16 + row][16 + r] = acc11[v];
+      sh.GL[16 + row][r] = acc10[v];
+      sh.GL[16 + row][16 + r] = acc11[v];
     }
   }
   __syncthreads();
@@ -90,19 +97,18 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
   // 2. row `lane` of C (lower part), in registers
   const bool active = lane <= k;
   const int myrow = lane & 31;
-  T Lrow[32];
 #pragma unroll
   for (int b = 0; b < 32; ++b) {
     T v = 0;
     if (active && b <= lane) {
       const T kv = (b == lane) ? T(p.sigma1_sq + p.s2)
-                               : T(p.sigma1_sq) * cov_profile<T>(p.kernel, scaled_sqdist<T>(p, xs[myrow], xs[b]));
-      v = kv - GL[myrow][b];
+                               : T(p.sigma1_sq) * cov_profile<T>(p.kernel, scaled_sqdist<T>(p, sh.xs[myrow], sh.xs[b]));
+      v = kv - sh.GL[myrow][b];
     }
     Lrow[b] = v;
   }
   __syncthreads();
-  T (*Ls)[33] = GL;
+  T (*Ls)[33] = sh.GL;
 
   // 3. Cholesky, row-oriented: step b finalises row b (its diagonal), then
   //    every later row computes its entry in column b from row b.
@@ -136,14 +142,11 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
     if (lane == 0) {
       status[0] = VIF_DEV_NOT_PD;
       atomicMin(&status[2], (int)i);
-      Dout[i] = __builtin_nan("");
     }
-    return;
+    return false;
   }
   wave_sync();
   const T lkk = Ls[k][k];
-  const T D = lkk * lkk;
-
   // A = L_R^{-T} l, l = row k of L without its diagonal
   T accv = (lane < k) ? Ls[k][myrow] : T(0);
   const T ldiag = Ls[myrow][myrow];
@@ -153,17 +156,169 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
     if (lane == a) Ab = Aa;
     if (lane < a) accv -= Ls[a][myrow] * Aa;
   }
-  if (lane < 32) As[lane] = Ab;
-  if (lane < mv) Aout[i * mv + lane] = (lane < k) ? Ab : T(0);
-  if (lane == 0) Dout[i] = (double)D;
+  if (lane < 32) sh.As[lane] = Ab;
   __syncthreads();
+  k_out = k;
+  D_out = lkk * lkk;
+  return true;
+}
 
+template <typename T, int NBLK>
+__global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, const T* __restrict__ V,
+                                               const int32_t* __restrict__ nbr, int64_t n, int mp, int mv,
+                                               CovParams p, T* __restrict__ Aout, double* __restrict__ Dout,
+                                               T* __restrict__ U, int* status) {
+  __shared__ PointShared<T> sh;
+  T Lrow[32];
+  int k;
+  T D;
+  const int lane = threadIdx.x;
+  const int64_t i = blockIdx.x;
+  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, Lrow, k, D, status)) {
+    if (lane == 0) Dout[i] = __builtin_nan("");
+    return;
+  }
+  if (lane < mv) Aout[i * mv + lane] = (lane < k) ? sh.As[lane] : T(0);
+  if (lane == 0) Dout[i] = (double)D;
   // 4. U_i
   const T rsd = T(1) / sqrt(D);
   for (int l = lane; l < mp; l += 64) {
     T u = V[(size_t)i * mp + l];
-    for (int a = 0; a < k; ++a) u -= As[a] * V[(size_t)nbs[a] * mp + l];
+    for (int a = 0; a < k; ++a) u -= sh.As[a] * V[(size_t)sh.nbs[a] * mp + l];
     U[(size_t)i * mp + l] = u * rsd;
+  }
+}
+
+// Adjoint of the per-point factor (reverse mode of steps 1-4, recomputed
+// from V rather than stored). Inputs: the cotangent of U,
+// Ubar = U M'^{-1} - e w^T, and of yt, e = yt - U w (w = M'^{-1} U^T yt),
+// from the Woodbury step. With ub = Ubar_i / sqrt(D_i):
+//   Dbar = 1/(2D) - (Ubar_i.U_i + e_i yt_i) / (2D)
+//   Abar_j = -ub.V_{N_j} - (e_i / sqrt(D)) y_{N_j}
+//   rho = R^{-1} Abar - Dbar A,  rbar = rho - Dbar A,  Rbar = -rho A^T
+// (D_i = c - |V_i|^2 - r^T R^{-1} r; A = R^{-1} r). Outputs per point: rho
+// (n x m_v), the kernel-entry part of the gradient (sigma1^2, range, s2), and
+// two m-vectors: G_i = sum_l rho_l V_{N_l} - ub + Dbar V_i (the cotangent
+// that neighbour N_j receives is A_j G_i + rho_j (-sqrt(D) U_i)), and the
+// point's own cotangent S_i = ub - 2 Dbar V_i - sum_l rho_l V_{N_l}
+// + Dbar (V_i - sqrt(D) U_i).
+template <typename T, int NBLK>
+__global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X, const T* __restrict__ V,
+                                                   const int32_t* __restrict__ nbr, const double* __restrict__ y,
+                                                   const T* __restrict__ U, const T* __restrict__ Ubar,
+                                                   const double* __restrict__ e, const double* __restrict__ yt,
+                                                   int64_t n, int mp, int mv, CovParams p, T* __restrict__ rho_out,
+                                                   T* __restrict__ G, T* __restrict__ S, double* __restrict__ tpart,
+                                                   int* status) {
+  __shared__ PointShared<T> sh;
+  __shared__ T rho_s[32];
+  T Lrow[32];
+  int k;
+  T D;
+  const int lane = threadIdx.x;
+  const int myrow = lane & 31;
+  const int64_t i = blockIdx.x;
+  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, Lrow, k, D, status)) {
+    if (lane == 0) tpart[i * 3] = tpart[i * 3 + 1] = tpart[i * 3 + 2] = __builtin_nan("");
+    return;
+  }
+  T (*Ls)[33] = sh.GL;
+  const T rsd = T(1) / sqrt(D), sd = sqrt(D);
+  const int nch = (mp + 63) >> 6;
+  constexpr int MAXCH = 16;
+  T ub[MAXCH];
+  T dotUU = 0;
+#pragma unroll
+  for (int c = 0; c < MAXCH; ++c) {
+    ub[c] = 0;
+    const int l = lane + 64 * c;
+    if (c < nch && l < mp) {
+      ub[c] = Ubar[(size_t)i * mp + l];
+      dotUU += ub[c] * U[(size_t)i * mp + l];
+    }
+  }
+  dotUU = wave_sum(dotUU);
+  const T ei = T(e[i]), yti = T(yt[i]);
+  const T Dbar = T(0.5) / D - T(0.5) * (dotUU + ei * yti) / D;
+  const T tbar = ei * rsd;
+  // Abar_j
+  T Abar = 0;
+  for (int j = 0; j < k; ++j) {
+    const T* vr = V + (size_t)sh.nbs[j] * mp;
+    T s = 0;
+#pragma unroll
+    for (int c = 0; c < MAXCH; ++c) {
+      const int l = lane + 64 * c;
+      if (c < nch && l < mp) s += ub[c] * vr[l];
+    }
+    s = wave_sum(s);
+    if (lane == j) Abar = -rsd * s - tbar * T(y[sh.nbs[j]]);
+  }
+  // z = L_R^{-1} Abar (lane a holds row a of L in Lrow)
+  T accz = (lane < k) ? Abar : T(0);
+  T z = 0;
+#pragma unroll
+  for (int q = 0; q < 32; ++q) {
+    if (q < k) {
+      const T zq = __shfl(accz / Lrow[q], q, 64);
+      if (lane == q) z = zq;
+      if (lane > q && lane < k) accz -= Lrow[q] * zq;
+    }
+  }
+  // a' = L_R^{-T} z
+  T acc = (lane < k) ? z : T(0);
+  T ap = 0;
+  const T ldiag = Ls[myrow][myrow];
+  for (int a = k - 1; a >= 0; --a) {
+    const T xa = __shfl(acc / ldiag, a, 64);
+    if (lane == a) ap = xa;
+    if (lane < a) acc -= Ls[a][myrow] * xa;
+  }
+  const T Aj = (lane < k) ? sh.As[myrow] : T(0);
+  const T rho = (lane < k) ? ap - Dbar * Aj : T(0);
+  const T rbar = rho - Dbar * Aj;
+  if (lane < 32) rho_s[lane] = rho;
+  if (lane < mv) rho_out[i * mv + lane] = rho;
+  __syncthreads();
+  // gradient terms from the covariance entries of R_i, r_i, c_ii
+  T ts = 0, tr = 0, tn = 0;
+  if (lane < k) {
+    T sA = 0, sAr = 0;
+    for (int l = 0; l < k; ++l) {
+      if (l == lane) {
+        sA += sh.As[l];
+      } else {
+        const T t2 = scaled_sqdist<T>(p, sh.xs[lane], sh.xs[l]);
+        sA += sh.As[l] * cov_profile<T>(p.kernel, t2);
+        sAr += sh.As[l] * T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2, T(p.inv_ls[0]));
+      }
+    }
+    const T t2i = scaled_sqdist<T>(p, sh.xs[lane], sh.xs[k]);
+    ts = -rho * sA + rbar * cov_profile<T>(p.kernel, t2i);
+    tr = -rho * sAr + rbar * T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2i, T(p.inv_ls[0]));
+    tn = -rho * Aj;
+  }
+  ts = wave_sum(ts);
+  tr = wave_sum(tr);
+  tn = wave_sum(tn);
+  if (lane == 0) {
+    tpart[i * 3 + 0] = (double)(ts + Dbar);
+    tpart[i * 3 + 1] = (double)tr;
+    tpart[i * 3 + 2] = (double)(tn + Dbar);
+  }
+  // vector cotangents
+#pragma unroll
+  for (int c = 0; c < MAXCH; ++c) {
+    const int l = lane + 64 * c;
+    if (c < nch && l < mp) {
+      const T Vi = V[(size_t)i * mp + l];
+      const T Ui = U[(size_t)i * mp + l];
+      const T u = ub[c] * rsd;
+      T beta = 0;
+      for (int j = 0; j < k; ++j) beta += rho_s[j] * V[(size_t)sh.nbs[j] * mp + l];
+      G[(size_t)i * mp + l] = beta - u + Dbar * Vi;
+      S[(size_t)i * mp + l] = u - T(2) * Dbar * Vi - beta + Dbar * (Vi - sd * Ui);
+    }
   }
 }
 
@@ -204,3 +359,21 @@ template void launch_ytilde<double>(hipStream_t, const double*, const double*, c
                                     int, double*);
 template void launch_ytilde<float>(hipStream_t, const float*, const double*, const int32_t*, const double*, int64_t,
                                    int, double*);
+
+template <typename T>
+void launch_factor_bwd(hipStream_t st, const double* X, const T* V, const int32_t* nbr, const double* y, const T* U,
+                       const T* Ubar, const double* e, const double* yt, int64_t n, int mp, int mv,
+                       const CovParams& p, T* rho, T* G, T* S, double* tpart, int* status) {
+  if (mv + 1 <= 16)
+    hipLaunchKernelGGL((k_factor_bwd<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, nbr, y, U, Ubar, e, yt, n, mp,
+                       mv, p, rho, G, S, tpart, status);
+  else
+    hipLaunchKernelGGL((k_factor_bwd<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, nbr, y, U, Ubar, e, yt, n, mp,
+                       mv, p, rho, G, S, tpart, status);
+}
+template void launch_factor_bwd<double>(hipStream_t, const double*, const double*, const int32_t*, const double*,
+                                        const double*, const double*, const double*, const double*, int64_t, int, int,
+                                        const CovParams&, double*, double*, double*, double*, int*);
+template void launch_factor_bwd<float>(hipStream_t, const double*, const float*, const int32_t*, const double*,
+                                       const float*, const float*, const double*, const double*, int64_t, int, int,
+                                       const CovParams&, float*, float*, float*, double*, int*);

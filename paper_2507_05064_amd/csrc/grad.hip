@@ -1,0 +1,364 @@
+// Reverse-mode gradient of the Gaussian VIF NLL (Sec. 2.2 and App. A) in the
+// whitened parametrisation, except for the per-point adjoint (factor.hip).
+//
+// NLL = 1/2 log det M' + 1/2 sum log D + 1/2 yt.yt - 1/2 b^T M'^{-1} b,
+// M' = I + U^T U, b = U^T yt. With w = M'^{-1} b and e = yt - U w:
+//   Ubar = U M'^{-1} - e w^T,  ytbar = e.
+// The per-point adjoint turns these into V-bar (through reverse neighbour
+// lists, no atomics) and the kernel-entry part of the gradient. V depends on
+// theta through K(Z,X) and L_m: with Sm_bar = V Vbar^T (symmetric, because the
+// NLL is invariant to V -> Q V for orthogonal Q),
+//   d/dtheta += sum_i Vbar_i . (L_m^{-1} dK(Z,x_i)/dtheta)
+//             - 1/2 tr(L_m^{-T} Sm_bar L_m^{-1} dSigma_m/dtheta).
+#include "common.h"
+#include "kernels.h"
+
+// C = op(A) op(B) for mp x mp FP64 matrices (op = transpose if flag set).
+__global__ __launch_bounds__(256) void k_gemm_sq(const double* __restrict__ A, const double* __restrict__ B,
+                                                 double* __restrict__ C, int mp, int ta, int tb) {
+  __shared__ double As[16][17], Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int row = blockIdx.y * 16 + ty, col = blockIdx.x * 16 + tx;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < mp; k0 += 16) {
+    const int ka = k0 + tx, kb = k0 + ty;
+    As[ty][tx] = (row < mp && ka < mp) ? (ta ? A[(size_t)ka * mp + row] : A[(size_t)row * mp + ka]) : 0.0;
+    Bs[ty][tx] = (kb < mp && col < mp) ? (tb ? B[(size_t)col * mp + kb] : B[(size_t)kb * mp + col]) : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc += As[ty][t] * Bs[t][tx];
+    __syncthreads();
+  }
+  if (row < mp && col < mp) C[(size_t)row * mp + col] = acc;
+}
+
+// w = Minv b (single workgroup), Minv in FP64; also a T copy of Minv.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prep_w(const double* __restrict__ Minv, const double* __restrict__ b, int mp,
+                                                double* __restrict__ w, T* __restrict__ MinvT) {
+  for (int l = threadIdx.x; l < mp; l += 256) {
+    const double* row = Minv + (size_t)l * mp;
+    double s = 0.0;
+    for (int c = 0; c < mp; ++c) s += row[c] * b[c];
+    w[l] = s;
+  }
+  for (int q = threadIdx.x; q < mp * mp; q += 256) MinvT[q] = (T)Minv[q];
+}
+
+// e_i = yt_i - U_i . w  (one wave per point)
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid(const T* __restrict__ U, const double* __restrict__ w,
+                                               const double* __restrict__ yt, int64_t n, int mp,
+                                               double* __restrict__ e) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  double s = 0.0;
+  for (int l = lane; l < mp; l += 64) s += (double)U[(size_t)i * mp + l] * w[l];
+  s = wave_sum(s);
+  if (lane == 0) e[i] = yt[i] - s;
+}
+
+// Ubar = U Minv - e w^T: a 64-point x 64-column tile per workgroup, one wave
+// per 16 points, MFMA 16x16x4 over the mp-long inner dimension.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ubar(const T* __restrict__ U, const T* __restrict__ Minv,
+                                              const double* __restrict__ e, const double* __restrict__ w, int64_t n,
+                                              int mp, T* __restrict__ Ubar) {
+  typedef typename Acc4<T>::type A4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t p0 = (int64_t)blockIdx.x * 64 + 16 * wv;
+  const int c0 = blockIdx.y * 64;
+  const int ntile = min(4, (mp - c0) / 16);
+  const int64_t pa = p0 + r;
+  const T* urow = U + (size_t)min(pa, n - 1) * mp;
+  A4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = A4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < mp; k0 += 4) {
+    const T a = (pa < n) ? urow[k0 + g] : T(0);
+    const T* mrow = Minv + (size_t)(k0 + g) * mp + c0 + r;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < ntile) acc[t] = mfma16(a, mrow[16 * t], acc[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t >= ntile) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t pt = p0 + acc_row<T>(lane, v);
+      const int col = c0 + 16 * t + r;
+      if (pt < n) Ubar[(size_t)pt * mp + col] = (T)((double)acc[t][v] - e[pt] * w[col]);
+    }
+  }
+}
+
+// Vbar_a = S_a + sum over (p, j) with N(p)_j = a of A_pj G_p - rho_pj sqrt(D_p) U_p,
+// fused with the two K(Z,X)-path gradient dots Vbar_a.V_a and Vbar_a.Vr_a.
+template <typename T>
+__global__ __launch_bounds__(256) void k_vbar(const T* __restrict__ S, const T* __restrict__ G,
+                                              const T* __restrict__ U, const double* __restrict__ D,
+                                              const T* __restrict__ A, const T* __restrict__ rho,
+                                              const int* __restrict__ rev_ptr, const int* __restrict__ rev_idx,
+                                              const T* __restrict__ V, const T* __restrict__ Vr, int64_t n, int mp,
+                                              int mv, T* __restrict__ Vbar, double* __restrict__ vpart) {
+  const int lane = threadIdx.x & 63;
+  const int64_t a = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (a >= n) return;
+  const int beg = rev_ptr[a], end = rev_ptr[a + 1];
+  double ds = 0.0, dr = 0.0;
+  for (int l = lane; l < mp; l += 64) {
+    T acc = S[(size_t)a * mp + l];
+    for (int q = beg; q < end; ++q) {
+      const int idx = rev_idx[q];
+      const int64_t p = idx / mv;
+      acc += A[idx] * G[(size_t)p * mp + l] - rho[idx] * T(sqrt(D[p])) * U[(size_t)p * mp + l];
+    }
+    Vbar[(size_t)a * mp + l] = acc;
+    ds += (double)acc * (double)V[(size_t)a * mp + l];
+    dr += (double)acc * (double)Vr[(size_t)a * mp + l];
+  }
+  ds = wave_sum(ds);
+  dr = wave_sum(dr);
+  if (lane == 0) {
+    vpart[a * 2 + 0] = ds;
+    vpart[a * 2 + 1] = dr;
+  }
+}
+
+// Partial sum_p P_p Q_p^T over a point chunk for one 64 x 64 block (all blocks).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cross_partial(const T* __restrict__ P, const T* __restrict__ Q, int64_t n,
+                                                       int mp, int chunk, double* __restrict__ partial) {
+  typedef typename Acc4<T>::type A4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int nb = (mp + 63) / 64;
+  const int bi = blockIdx.y / nb, bj = blockIdx.y % nb;
+  const int L0 = bi * 64 + 32 * (w >> 1), C0 = bj * 64 + 32 * (w & 1);
+  if (L0 >= mp || C0 >= mp) return;
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk;
+  const int64_t pend = min(n, pbeg + chunk);
+  bool rok[2], cok[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    rok[t] = L0 + 16 * t < mp;
+    cok[t] = C0 + 16 * t < mp;
+  }
+  A4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = A4{0, 0, 0, 0};
+  for (int64_t p0 = pbeg; p0 < pend; p0 += 4) {
+    const int64_t pp = p0 + g;
+    const bool pv = pp < pend;
+    const size_t off = (size_t)(pv ? pp : pbeg) * mp;
+    T a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      a[t] = (pv && rok[t]) ? P[off + L0 + 16 * t + r] : T(0);
+      b[t] = (pv && cok[t]) ? Q[off + C0 + 16 * t + r] : T(0);
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[x][y] = mfma16(a[x], b[y], acc[x][y]);
+  }
+  double* out = partial + (size_t)blockIdx.x * mp * mp;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+      if (rok[x] && cok[y])
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          out[(size_t)(L0 + 16 * x + acc_row<T>(lane, v)) * mp + C0 + 16 * y + r] = (double)acc[x][y][v];
+}
+
+__global__ void k_reduce_full(const double* __restrict__ partial, int nchunk, int mp, double* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)mp * mp) return;
+  double s = 0.0;
+  for (int k = 0; k < nchunk; ++k) s += partial[(size_t)k * mp * mp + q];
+  out[q] = s;
+}
+
+// -1/2 sum_ab Tm_ab dSigma_m[a][b]/dtheta for (sigma1^2, range): one block per row.
+__global__ __launch_bounds__(256) void k_sigma_m_grad(const double* __restrict__ Tm, const double* __restrict__ Z,
+                                                      int m, int mp, CovParams p, double* __restrict__ rowpart) {
+  __shared__ double red[2][4];
+  const int a = blockIdx.x;
+  double gs = 0.0, gr = 0.0;
+  for (int b = threadIdx.x; b < m; b += 256) {
+    const double t2 = scaled_sqdist<double>(p, Z + (size_t)a * p.d, Z + (size_t)b * p.d);
+    const double tv = Tm[(size_t)a * mp + b];
+    gs += tv * cov_profile<double>(p.kernel, t2);
+    if (a != b) gr += tv * p.sigma1_sq * cov_profile_dls<double>(p.kernel, t2, p.inv_ls[0]);
+  }
+  gs = wave_sum(gs);
+  gr = wave_sum(gr);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = gs; red[1][threadIdx.x >> 6] = gr; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    rowpart[a * 2 + 0] = -0.5 * (red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+    rowpart[a * 2 + 1] = -0.5 * (red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+  }
+}
+
+// Column sums of a rows x cols (cols <= 4) array: per-block partials.
+__global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ in, int64_t rows, int cols, int64_t per,
+                                                double* __restrict__ out) {
+  __shared__ double red[4][4];
+  const int64_t beg = (int64_t)blockIdx.x * per, end = min(rows, beg + per);
+  double s[4] = {0, 0, 0, 0};
+  for (int64_t r = beg + threadIdx.x; r < end; r += 256)
+    for (int c = 0; c < cols; ++c) s[c] += in[r * cols + c];
+  for (int c = 0; c < cols; ++c) {
+    const double v = wave_sum(s[c]);
+    if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < cols) {
+    const int c = threadIdx.x;
+    out[blockIdx.x * cols + c] = red[c][0] + red[c][1] + red[c][2] + red[c][3];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse (transposed) neighbour lists: for each point a, the flattened
+// positions p * m_v + j with N(p)_j = a, in increasing order.
+__global__ void k_rev_count(const int32_t* __restrict__ nbr, int64_t n, int mv, int* __restrict__ cnt) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n * mv) return;
+  const int a = nbr[q];
+  if (a >= 0) atomicAdd(&cnt[a], 1);
+}
+
+// Exclusive scan of cnt[0..n) into ptr[0..n]; one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ cnt, int64_t n, int* __restrict__ ptr) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t beg = t * per, end = min(n, beg + per);
+  int s = 0;
+  for (int64_t i = beg; i < end; ++i) s += cnt[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;  // exclusive prefix of this thread's segment
+  for (int64_t i = beg; i < end; ++i) {
+    ptr[i] = run;
+    run += cnt[i];
+  }
+  if (t == 1023) ptr[n] = part[1023];
+}
+
+__global__ void k_rev_fill(const int32_t* __restrict__ nbr, int64_t n, int mv, const int* __restrict__ ptr,
+                           int* __restrict__ cursor, int* __restrict__ idx) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n * mv) return;
+  const int a = nbr[q];
+  if (a >= 0) idx[ptr[a] + atomicAdd(&cursor[a], 1)] = (int)q;
+}
+
+// sort each segment (insertion sort; segments hold about m_v entries)
+__global__ void k_rev_sort(const int* __restrict__ ptr, int64_t n, int* __restrict__ idx) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const int beg = ptr[a], end = ptr[a + 1];
+  for (int q = beg + 1; q < end; ++q) {
+    const int v = idx[q];
+    int r = q - 1;
+    while (r >= beg && idx[r] > v) {
+      idx[r + 1] = idx[r];
+      --r;
+    }
+    idx[r + 1] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+void launch_gemm_sq(hipStream_t st, const double* A, const double* B, double* C, int mp, bool ta, bool tb) {
+  dim3 grid((mp + 15) / 16, (mp + 15) / 16);
+  hipLaunchKernelGGL(k_gemm_sq, grid, dim3(256), 0, st, A, B, C, mp, (int)ta, (int)tb);
+}
+template <typename T>
+void launch_prep_w(hipStream_t st, const double* Minv, const double* b, int mp, double* w, T* MinvT) {
+  hipLaunchKernelGGL((k_prep_w<T>), dim3(1), dim3(256), 0, st, Minv, b, mp, w, MinvT);
+}
+template <typename T>
+void launch_resid(hipStream_t st, const T* U, const double* w, const double* yt, int64_t n, int mp, double* e) {
+  hipLaunchKernelGGL((k_resid<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, U, w, yt, n, mp, e);
+}
+template <typename T>
+void launch_ubar(hipStream_t st, const T* U, const T* Minv, const double* e, const double* w, int64_t n, int mp,
+                 T* Ubar) {
+  dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(mp, 64));
+  hipLaunchKernelGGL((k_ubar<T>), grid, dim3(256), 0, st, U, Minv, e, w, n, mp, Ubar);
+}
+template <typename T>
+void launch_vbar(hipStream_t st, const T* S, const T* G, const T* U, const double* D, const T* A, const T* rho,
+                 const int* rev_ptr, const int* rev_idx, const T* V, const T* Vr, int64_t n, int mp, int mv, T* Vbar,
+                 double* vpart) {
+  hipLaunchKernelGGL((k_vbar<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, S, G, U, D, A, rho, rev_ptr,
+                     rev_idx, V, Vr, n, mp, mv, Vbar, vpart);
+}
+template <typename T>
+void launch_cross_partial(hipStream_t st, const T* P, const T* Q, int64_t n, int mp, int chunk, double* partial,
+                          int* nchunk_out) {
+  const int nchunk = (int)ceil_div(n, chunk);
+  const int nb = (mp + 63) / 64;
+  hipLaunchKernelGGL((k_cross_partial<T>), dim3(nchunk, nb * nb), dim3(256), 0, st, P, Q, n, mp, chunk, partial);
+  *nchunk_out = nchunk;
+}
+void launch_reduce_full(hipStream_t st, const double* partial, int nchunk, int mp, double* out) {
+  const int64_t total = (int64_t)mp * mp;
+  hipLaunchKernelGGL(k_reduce_full, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, partial, nchunk, mp, out);
+}
+void launch_sigma_m_grad(hipStream_t st, const double* Tm, const double* Z, int m, int mp, const CovParams& p,
+                         double* rowpart) {
+  hipLaunchKernelGGL(k_sigma_m_grad, dim3(m), dim3(256), 0, st, Tm, Z, m, mp, p, rowpart);
+}
+int launch_colsum(hipStream_t st, const double* in, int64_t rows, int cols, double* out) {
+  const int64_t per = 4096;
+  const int nblk = (int)ceil_div(rows, per);
+  if (nblk > 0) hipLaunchKernelGGL(k_colsum, dim3(nblk), dim3(256), 0, st, in, rows, cols, per, out);
+  return nblk;
+}
+void launch_reverse_lists(hipStream_t st, const int32_t* nbr, int64_t n, int mv, int* cnt, int* ptr, int* cursor,
+                          int* idx) {
+  hipMemsetAsync(cnt, 0, sizeof(int) * n, st);
+  hipMemsetAsync(cursor, 0, sizeof(int) * n, st);
+  const int64_t tot = n * mv;
+  if (tot > 0) hipLaunchKernelGGL(k_rev_count, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, nbr, n, mv, cnt);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, n, ptr);
+  if (tot > 0)
+    hipLaunchKernelGGL(k_rev_fill, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, nbr, n, mv, ptr, cursor, idx);
+  hipLaunchKernelGGL(k_rev_sort, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, ptr, n, idx);
+}
+
+template void launch_prep_w<double>(hipStream_t, const double*, const double*, int, double*, double*);
+template void launch_prep_w<float>(hipStream_t, const double*, const double*, int, double*, float*);
+template void launch_resid<double>(hipStream_t, const double*, const double*, const double*, int64_t, int, double*);
+template void launch_resid<float>(hipStream_t, const float*, const double*, const double*, int64_t, int, double*);
+template void launch_ubar<double>(hipStream_t, const double*, const double*, const double*, const double*, int64_t,
+                                  int, double*);
+template void launch_ubar<float>(hipStream_t, const float*, const float*, const double*, const double*, int64_t, int,
+                                 float*);
+template void launch_vbar<double>(hipStream_t, const double*, const double*, const double*, const double*,
+                                  const double*, const double*, const int*, const int*, const double*, const double*,
+                                  int64_t, int, int, double*, double*);
+template void launch_vbar<float>(hipStream_t, const float*, const float*, const float*, const double*, const float*,
+                                 const float*, const int*, const int*, const float*, const float*, int64_t, int, int,
+                                 float*, double*);
+template void launch_cross_partial<double>(hipStream_t, const double*, const double*, int64_t, int, int, double*,
+                                           int*);
+template void launch_cross_partial<float>(hipStream_t, const float*, const float*, int64_t, int, int, double*, int*);

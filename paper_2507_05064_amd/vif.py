@@ -42,7 +42,8 @@ class vif_config(ctypes.Structure):
 
 
 EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors", "vif_build_factor", "vif_nll",
-           "vif_nll_grad", "vif_export_factor"]
+           "vif_nll_grad", "vif_export_factor", "vif_set_timing", "vif_timing_stages", "vif_timing_stage_name",
+           "vif_get_timing"]
 
 
 def load_library(path: Optional[str] = None):
@@ -71,6 +72,14 @@ def load_library(path: Optional[str] = None):
     lib.vif_nll_grad.restype = ctypes.c_int
     lib.vif_export_factor.argtypes = [vp, vp, vp]
     lib.vif_export_factor.restype = ctypes.c_int
+    lib.vif_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.vif_set_timing.restype = ctypes.c_int
+    lib.vif_timing_stages.argtypes = []
+    lib.vif_timing_stages.restype = ctypes.c_int
+    lib.vif_timing_stage_name.argtypes = [ctypes.c_int]
+    lib.vif_timing_stage_name.restype = ctypes.c_char_p
+    lib.vif_get_timing.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.vif_get_timing.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -153,3 +162,15 @@ class VifContext:
         D = torch.empty(self.n, dtype=torch.float64, device="cuda")
         self._check(self.lib.vif_export_factor(self.h, _ptr(A) if self.m_v else None, _ptr(D)))
         return A, D
+
+    def set_timing(self, enable: bool = True):
+        self._check(self.lib.vif_set_timing(self.h, int(enable)))
+
+    def timing(self):
+        """{stage name: (total ms, launches)} since the last set_timing."""
+        k = self.lib.vif_timing_stages()
+        ms = np.zeros(k)
+        cnt = np.zeros(k, dtype=np.int64)
+        self._check(self.lib.vif_get_timing(self.h, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k))
+        return {self.lib.vif_timing_stage_name(s).decode(): (float(ms[s]), int(cnt[s])) for s in range(k)}

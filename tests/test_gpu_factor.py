@@ -4,10 +4,10 @@ against the FP64 oracle (same seeded inputs on both sides).
 Tolerances (FP64 form): neighbour sets identical except near-ties whose
 oracle keys differ by <= 1e-12; A_i within 1e-10 of max|A| and D_i within
 1e-10 relative; NLL within 1e-10 relative. FP32 form: NLL within 2e-5
-relative -- the per-point systems are formed and factored in FP32 (unit
-roundoff 6e-8) with condition numbers up to ~1/s2 = 100 (C1), so A, D carry
-~1e-5 relative error, and the NLL is a sum of n such terms whose errors
-partly cancel.
+relative, or 1e-5 per point when the NLL is small (it is a sum of n terms
+and can be near zero) -- the per-point systems are formed and factored in
+FP32 (unit roundoff 6e-8) with condition numbers up to ~1/s2 = 100 (C1), so
+each term carries up to ~1e-5 relative error.
 """
 import numpy as np
 import pytest
@@ -145,3 +145,33 @@ def test_not_pd_is_reported():
     with pytest.raises(VifError) as e:
         ctx.build_factor(to_dev(X), None, nbr_to_dev(nbr), theta)
     assert e.value.code == 3 and "point 40" in str(e.value)
+
+
+@pytest.mark.parametrize("n,m,mv,prec", [(400, 20, 8, "fp64"), (1500, 50, 10, "fp64"), (517, 33, 31, "fp64"),
+                                         (300, 0, 6, "fp64"), (300, 17, 0, "fp64"), (1500, 50, 10, "fp32")])
+def test_gradient_matches_oracle(n, m, mv, prec):
+    """Adjoint gradient (GPU) vs the oracle's forward-mode gradient at a
+    perturbed theta (1.3 sigma1^2, 0.8 range, 1.5 nugget) where the gradient
+    is far from zero. FP64: relative 1e-8 of max|g|; FP32: 1e-3 of max|g|."""
+    w = vi.scaled(vi.config1(), n, m=m, m_v=mv)
+    X, Z, model = problem(w)
+    theta = w.theta * np.array([1.3, 0.8, 1.5])
+    model = vo.Model.from_theta(w.kernel, theta, w.tau_m)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, mv)
+    y = _y_exact(vo.Model.from_theta(w.kernel, w.theta), X, 21)
+    print(f"[gpu] gradient n={n} m={m} m_v={mv} {prec}", flush=True)
+    nll_o, g_o = vo.nll_gaussian_grad(model, X, Z, nbr, y)
+    ctx = _ctx(w, precision=prec)
+    ctx.build_factor(to_dev(X), to_dev(Z) if m else None, nbr_to_dev(nbr) if mv else None, theta)
+    nll_g, g_g = ctx.nll_grad(to_dev(y), 3)
+    tol = 1e-8 if prec == "fp64" else 1e-3
+    nerr = abs(nll_g - nll_o)
+    if prec == "fp64":
+        assert nerr <= 1e-10 * abs(nll_o), (nll_g, nll_o)
+    else:
+        assert nerr <= 1e-5 * max(abs(nll_o), n), (nll_g, nll_o)
+    assert np.max(np.abs(g_g - g_o)) <= tol * np.max(np.abs(g_o)), (g_g, g_o)
+    # a second call on the same factor is bit-identical (no atomics in the sums)
+    nll_2, g_2 = ctx.nll_grad(to_dev(y), 3)
+    assert nll_2 == nll_g and np.array_equal(g_2, g_g)
