@@ -74,7 +74,19 @@ typedef struct {
   int32_t cg_maxit;
   int32_t newton_maxit;
   double newton_tol;  /* stop when |Psi_{t+1} - Psi_t| <= newton_tol (1 + |Psi_{t+1}|) */
+  double lik_param;   /* Gaussian likelihood in vif_laplace_mode: the noise variance */
 } vif_config;
+
+/* Statistics of one Laplace mode search (vif_laplace_mode). */
+typedef struct {
+  int32_t newton_iters;     /* Newton steps taken */
+  int32_t pcg_iters_total;  /* conjugate-gradient iterations over all steps */
+  int32_t pcg_iters[64];    /* per Newton step (first 64 steps) */
+  int32_t halvings;         /* step halvings over all steps */
+  int32_t converged;        /* 1 when the Newton stopping rule was met */
+  double psi;               /* final objective log p(y|b) - b^T Sigma_dagger^{-1} b / 2 */
+  double pcg_rel_residual;  /* relative residual of the last CG solve */
+} vif_laplace_stats;
 
 typedef struct vif_ctx vif_ctx;
 
@@ -114,6 +126,22 @@ vif_status vif_nll(vif_ctx* ctx, const double* y, double* nll_out);
  * recomputed, not stored. Requires the likelihood to be Gaussian.
  * grad_out: host double[1 + L + 1] in the layout of theta. */
 vif_status vif_nll_grad(vif_ctx* ctx, const double* y, double* nll_out, double* grad_out);
+
+/* Mode of p(y|b) p(b|theta) for the latent VIF prior b ~ N(0, Sigma_dagger)
+ * (Sec. 3, eq. LA; the factor of the last vif_build_factor, built with s2 =
+ * the latent jitter tau) and the likelihood of the configuration (Bernoulli-
+ * logit, Poisson-log; Gaussian with noise variance cfg.lik_param). Newton
+ * steps b <- b + eta (W + Sigma_dagger^{-1})^{-1} (g(b) - Sigma_dagger^{-1} b), which is
+ * eq. one_it_newton_mode for eta = 1; eta is halved (at most 10 times) while
+ * the objective would decrease; stop when |Psi_{t+1} - Psi_t| <=
+ * cfg.newton_tol (1 + |Psi_{t+1}|). Each linear system is solved by
+ * conjugate gradients on eq. pcls1 with the VIFDU preconditioner (Sec. 4.3.1,
+ * App. E.1), from x_0 = 0, to ||r|| <= cfg.cg_tol ||rhs||. y, b0 (start;
+ * NULL = 0) and mode_out are device arrays of n doubles; st is a host
+ * pointer (may be NULL). On VIF_E_NEWTON / VIF_E_CG_MAXIT, mode_out still
+ * holds the last iterate and st the history. */
+vif_status vif_laplace_mode(vif_ctx* ctx, const double* y, const double* b0, double* mode_out,
+                            vif_laplace_stats* st);
 
 /* Copies the factor of the last build to device buffers A_out (n x m_v, the
  * coefficients A_i over N(i), zero padded) and D_out (n), both double. */

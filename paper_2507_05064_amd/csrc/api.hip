@@ -6,16 +6,18 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/vif.h"
 #include "common.h"
 #include "kernels.h"
 
 enum Stage { ST_INDUCING = 0, ST_WHITEN, ST_FACTOR, ST_GRAM, ST_MCHOL, ST_NLL, ST_KNN, ST_GPREP, ST_UBAR,
-             ST_FBWD, ST_VBAR, ST_SGRAD, ST_WDERIV, ST_REV, ST_COUNT };
+             ST_FBWD, ST_VBAR, ST_SGRAD, ST_WDERIV, ST_REV, ST_LAPLACE, ST_COUNT };
 static const char* kStageNames[ST_COUNT] = {
     "inducing_chol", "whiten", "factor", "woodbury_gram", "woodbury_chol", "nll_tail", "knn", "grad_prep",
-    "grad_ubar_gemm", "grad_factor_bwd", "grad_vbar", "grad_sigma_m", "grad_whiten_deriv", "reverse_lists"};
+    "grad_ubar_gemm", "grad_factor_bwd", "grad_vbar", "grad_sigma_m", "grad_whiten_deriv", "reverse_lists",
+    "laplace_mode"};
 
 struct StageTimer {
   hipEvent_t b = nullptr, e = nullptr;
@@ -55,9 +57,17 @@ struct vif_ctx {
   double *Xc = nullptr, *Zc = nullptr;  // the context's copies of X and Z of the last build
   // gradient workspace
   double *Minv = nullptr, *wvec = nullptr, *e = nullptr, *Smat = nullptr, *Tm = nullptr, *tmpm = nullptr;
-  void *MinvT = nullptr, *Ubar = nullptr, *rho = nullptr, *G = nullptr, *S = nullptr, *Vr = nullptr;
-  double *tpart = nullptr, *vpart = nullptr, *rowpart = nullptr, *gred = nullptr;
+  void *MinvT = nullptr, *Ubar = nullptr, *Q1 = nullptr, *Gs = nullptr, *Bs = nullptr, *Vr = nullptr;
+  double *tpart = nullptr, *rowpart = nullptr, *gred = nullptr;
   int *rev_cnt = nullptr, *rev_ptr = nullptr, *rev_cur = nullptr, *rev_idx = nullptr;
+  // level schedules of the sparse triangular solves with B and B^T
+  int *fwd_order = nullptr, *fwd_lvl = nullptr, *bwd_order = nullptr, *bwd_lvl = nullptr;
+  int nlev_f = 0, nlev_b = 0;
+  bool lev_valid = false;
+  // Laplace workspace: n-vectors, m-vectors, m x m
+  double* lv = nullptr;  // 20 n-vectors
+  double *lm = nullptr, *M3inv = nullptr, *L3inv = nullptr, *M3 = nullptr, *lsc = nullptr, *lpart = nullptr;
+  double* hlsc = nullptr;
 };
 
 static vif_status fail(vif_ctx* c, vif_status s, const char* fmt, ...) {
@@ -165,6 +175,7 @@ static vif_status read_status(vif_ctx* c, const char* stage) {
   if (s[0] == VIF_DEV_NOT_PD) {
     if (s[1] == 1) return fail(c, VIF_E_NOT_PD, "%s: Sigma_m not positive definite at column %d", stage, s[2]);
     if (s[1] == 2) return fail(c, VIF_E_NOT_PD, "%s: M' not positive definite at column %d", stage, s[2]);
+    if (s[1] == 3) return fail(c, VIF_E_NOT_PD, "%s: M3' not positive definite at column %d", stage, s[2]);
     return fail(c, VIF_E_NOT_PD, "%s: residual system not positive definite at point %d", stage, s[2]);
   }
   if (s[0] == VIF_DEV_NAN) return fail(c, VIF_E_NAN, "%s: non-finite value at %d", stage, s[2]);
@@ -204,6 +215,7 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   alloc((void**)&c->Mp, sizeof(double) * mpa * mpa);
   alloc((void**)&c->LMinv, sizeof(double) * mpa * mpa);
   alloc((void**)&c->Mwork, sizeof(double) * mpa * mpa);
+  alloc((void**)&c->Minv, sizeof(double) * mpa * mpa);
   alloc((void**)&c->Vd, sizeof(double) * n * mpa);
   if (fp32_form(c)) alloc((void**)&c->Vf, sizeof(float) * n * mpa);
   alloc(&c->A, tsize(c) * n * (g.m_v > 0 ? g.m_v : 1));
@@ -221,7 +233,6 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   alloc((void**)&c->Zc, sizeof(double) * (g.m > 0 ? g.m : 1) * g.d);
   if (g.likelihood == VIF_LIK_GAUSSIAN) {
     const size_t mvn = (size_t)n * (g.m_v > 0 ? g.m_v : 1);
-    alloc((void**)&c->Minv, sizeof(double) * mpa * mpa);
     alloc((void**)&c->Smat, sizeof(double) * mpa * mpa);
     alloc((void**)&c->Tm, sizeof(double) * mpa * mpa);
     alloc((void**)&c->tmpm, sizeof(double) * mpa * mpa);
@@ -229,18 +240,32 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
     alloc((void**)&c->e, sizeof(double) * n);
     alloc(&c->MinvT, tsize(c) * mpa * mpa);
     alloc(&c->Ubar, tsize(c) * n * mpa);
-    alloc(&c->rho, tsize(c) * mvn);
-    alloc(&c->G, tsize(c) * n * mpa);
-    alloc(&c->S, tsize(c) * n * mpa);
+    alloc(&c->Q1, tsize(c) * n * mpa);
+    alloc(&c->Gs, tsize(c) * n * mpa);
+    alloc(&c->Bs, tsize(c) * n * mpa);
     alloc(&c->Vr, tsize(c) * n * mpa);
     alloc((void**)&c->tpart, sizeof(double) * n * 3);
-    alloc((void**)&c->vpart, sizeof(double) * n * 2);
     alloc((void**)&c->rowpart, sizeof(double) * mpa * 2);
-    alloc((void**)&c->gred, sizeof(double) * (ceil_div(n, 4096) * 5 + ceil_div(mpa, 4096) * 2 + 16));
+    alloc((void**)&c->gred, sizeof(double) * (ceil_div(n, 4096) * 3 + ceil_div(mpa, 4096) * 2 + 16));
+  }
+  {
+    const size_t mvn = (size_t)n * (g.m_v > 0 ? g.m_v : 1);
     alloc((void**)&c->rev_cnt, sizeof(int) * n);
     alloc((void**)&c->rev_ptr, sizeof(int) * (n + 1));
     alloc((void**)&c->rev_cur, sizeof(int) * n);
     alloc((void**)&c->rev_idx, sizeof(int) * mvn);
+    alloc((void**)&c->fwd_order, sizeof(int) * n);
+    alloc((void**)&c->fwd_lvl, sizeof(int) * (n + 1));
+    alloc((void**)&c->bwd_order, sizeof(int) * n);
+    alloc((void**)&c->bwd_lvl, sizeof(int) * (n + 1));
+    alloc((void**)&c->lv, sizeof(double) * n * 20);
+    alloc((void**)&c->lm, sizeof(double) * mpa * 4);
+    alloc((void**)&c->M3, sizeof(double) * mpa * mpa);
+    alloc((void**)&c->M3inv, sizeof(double) * mpa * mpa);
+    alloc((void**)&c->L3inv, sizeof(double) * mpa * mpa);
+    alloc((void**)&c->lsc, sizeof(double) * 64);
+    alloc((void**)&c->lpart, sizeof(double) * (ceil_div(n, 256) + ceil_div(n, 2048) * 2 + (size_t)c->nchunk * mpa + 64));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->hlsc, sizeof(double) * 64, 0);
   }
   for (int t = 0; t < ST_COUNT && e == hipSuccess; ++t) {
     e = hipEventCreate(&c->timers[t].b);
@@ -261,8 +286,10 @@ void vif_destroy(vif_ctx* c) {
   if (c->st) hipStreamSynchronize(c->st); else hipDeviceSynchronize();
   void* bufs[] = {c->Sm, c->Linv, c->Mp, c->LMinv, c->Mwork, c->Vd, c->Vf, c->A, c->U, c->D, c->yt, c->vnorm,
                   c->partial, c->vecpart, c->vec, c->scal, c->status, c->nbr, c->Xc, c->Zc, c->Minv, c->wvec,
-                  c->e, c->Smat, c->Tm, c->tmpm, c->MinvT, c->Ubar, c->rho, c->G, c->S, c->Vr, c->tpart,
-                  c->vpart, c->rowpart, c->gred, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx};
+                  c->e, c->Smat, c->Tm, c->tmpm, c->MinvT, c->Ubar, c->Q1, c->Gs, c->Bs, c->Vr, c->tpart,
+                  c->rowpart, c->gred, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx,
+                  c->fwd_order, c->fwd_lvl, c->bwd_order, c->bwd_lvl, c->lv, c->lm, c->M3, c->M3inv, c->L3inv,
+                  c->lsc, c->lpart};
   for (void* b : bufs)
     if (b) hipFree(b);
   for (int t = 0; t < ST_COUNT; ++t) {
@@ -270,6 +297,7 @@ void vif_destroy(vif_ctx* c) {
     if (c->timers[t].e) hipEventDestroy(c->timers[t].e);
   }
   if (c->hscal) hipHostFree(c->hscal);
+  if (c->hlsc) hipHostFree(c->hlsc);
   if (c->hstatus) hipHostFree(c->hstatus);
   delete c;
 }
@@ -392,6 +420,7 @@ vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const 
     HIPCHK(c, hipStreamSynchronize(c->st));
     c->nbr_valid = true;
     c->rev_valid = false;
+    c->lev_valid = false;
   }
   c->built = true;
   return VIF_OK;
@@ -445,12 +474,10 @@ static void nll_tail(vif_ctx* c, const double* y) {
   launch_nll_final(c->st, c->LMinv, c->vec, c->vec + c->mp, g.m, c->mp, c->scal + 1, g.n, c->scal + 4);
 }
 
-// grad = sum of the per-point, V-bar and Sigma_m parts (single thread).
-__global__ void k_grad_final(const double* tp, int nt, const double* vp, int nv, const double* rp, int nr,
-                             double inv_s1, double* out) {
+// grad = sum of the per-point and Sigma_m parts (single thread, fixed order).
+__global__ void k_grad_final(const double* tp, int nt, const double* rp, int nr, double* out) {
   double g0 = 0, g1 = 0, g2 = 0;
   for (int b = 0; b < nt; ++b) { g0 += tp[b * 3]; g1 += tp[b * 3 + 1]; g2 += tp[b * 3 + 2]; }
-  for (int b = 0; b < nv; ++b) { g0 += vp[b * 2] * inv_s1; g1 += vp[b * 2 + 1]; }
   for (int b = 0; b < nr; ++b) { g0 += rp[b * 2]; g1 += rp[b * 2 + 1]; }
   out[0] = g0;
   out[1] = g1;
@@ -463,15 +490,6 @@ static vif_status nll_grad_impl(vif_ctx* c, const double* y) {
   const int mp = c->mp;
   const T* V = (const T*)(fp32_form(c) ? (const void*)c->Vf : (const void*)c->Vd);
   const T* U = (const T*)c->U;
-  if (g.m_v > 0 && !c->rev_valid) {
-    stage_begin(c, ST_REV);
-    launch_reverse_lists(c->st, c->nbr, g.n, g.m_v, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx);
-    stage_end(c, ST_REV);
-    c->rev_valid = true;
-  } else if (g.m_v == 0 && !c->rev_valid) {
-    HIPCHK(c, hipMemsetAsync(c->rev_ptr, 0, sizeof(int) * (g.n + 1), c->st));
-    c->rev_valid = true;
-  }
   stage_begin(c, ST_NLL);
   nll_tail(c, y);
   stage_end(c, ST_NLL);
@@ -482,40 +500,35 @@ static vif_status nll_grad_impl(vif_ctx* c, const double* y) {
   }
   launch_resid<T>(c->st, U, c->wvec, c->yt, g.n, mp, c->e);
   stage_end(c, ST_GPREP);
-  stage_begin(c, ST_UBAR);
-  if (g.m > 0) launch_ubar<T>(c->st, U, (const T*)c->MinvT, c->e, c->wvec, g.n, mp, (T*)c->Ubar);
-  stage_end(c, ST_UBAR);
-  stage_begin(c, ST_FBWD);
-  launch_factor_bwd<T>(c->st, c->Xc, V, c->nbr, y, U, (const T*)c->Ubar, c->e, c->yt, g.n, mp, g.m_v, c->cp,
-                       (T*)c->rho, (T*)c->G, (T*)c->S, c->tpart, c->status);
-  stage_end(c, ST_FBWD);
-  int nv = 0, nr = 0;
-  double* tp = c->gred;
-  const int nt = launch_colsum(c->st, c->tpart, g.n, 3, tp);
-  double* vp = tp + (size_t)nt * 3;
-  double* rp = vp + (size_t)ceil_div(g.n, 4096) * 2;
   if (g.m > 0) {
+    stage_begin(c, ST_UBAR);
+    launch_ubar<T>(c->st, U, (const T*)c->MinvT, c->e, c->wvec, g.n, mp, (T*)c->Ubar);
+    stage_end(c, ST_UBAR);
     stage_begin(c, ST_WDERIV);
     launch_whiten<T>(c->st, c->Xc, c->Zc, c->Linv, g.m, mp, g.n, c->cp, true, (T*)c->Vr);
     stage_end(c, ST_WDERIV);
-    stage_begin(c, ST_VBAR);
-    T* Vbar = (T*)c->Ubar;  // Ubar is consumed by the per-point adjoint
-    launch_vbar<T>(c->st, (const T*)c->S, (const T*)c->G, U, c->D, (const T*)c->A, (const T*)c->rho, c->rev_ptr,
-                   c->rev_idx, V, (const T*)c->Vr, g.n, mp, g.m_v, Vbar, c->vpart);
-    stage_end(c, ST_VBAR);
+  }
+  stage_begin(c, ST_FBWD);
+  launch_factor_bwd<T>(c->st, c->Xc, V, (const T*)c->Vr, c->nbr, y, U, (const T*)c->Ubar, c->e, c->yt, c->D, g.n, mp,
+                       g.m_v, c->cp, (T*)c->Q1, (T*)c->Gs, (T*)c->Bs, c->tpart, c->status);
+  stage_end(c, ST_FBWD);
+  double* tp = c->gred;
+  const int nt = launch_colsum(c->st, c->tpart, g.n, 3, tp);
+  double* rp = tp + (size_t)nt * 3;
+  int nr = 0;
+  if (g.m > 0) {
     stage_begin(c, ST_SGRAD);
     int nchunk = 0;
-    launch_cross_partial<T>(c->st, V, Vbar, g.n, mp, c->chunk, c->partial, &nchunk);
-    launch_reduce_full(c->st, c->partial, nchunk, mp, c->Smat);
+    launch_cross3_partial<T>(c->st, V, (const T*)c->Q1, U, (const T*)c->Gs, (const T*)c->Bs, g.n, mp, c->chunk,
+                             c->partial, &nchunk);
+    launch_reduce_sym(c->st, c->partial, nchunk, mp, c->Smat);
     launch_gemm_sq(c->st, c->Smat, c->Linv, c->tmpm, mp, false, false);
     launch_gemm_sq(c->st, c->Linv, c->tmpm, c->Tm, mp, true, false);
     launch_sigma_m_grad(c->st, c->Tm, c->Zc, g.m, mp, c->cp, c->rowpart);
-    nv = launch_colsum(c->st, c->vpart, g.n, 2, vp);
     nr = launch_colsum(c->st, c->rowpart, g.m, 2, rp);
     stage_end(c, ST_SGRAD);
   }
-  hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(1), 0, c->st, tp, nt, vp, nv, rp, nr, 1.0 / c->cp.sigma1_sq,
-                     c->scal + 8);
+  hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(1), 0, c->st, tp, nt, rp, nr, c->scal + 8);
   HIPCHK(c, hipGetLastError());
   return VIF_OK;
 }
@@ -530,6 +543,7 @@ vif_status vif_nll_grad(vif_ctx* c, const double* y, double* nll_out, double* gr
   if (g.likelihood != VIF_LIK_GAUSSIAN) return fail(c, VIF_E_ARG, "vif_nll_grad needs the Gaussian likelihood");
   if (g.kernel == VIF_GAUSSIAN_ARD)
     return fail(c, VIF_E_ARG, "vif_nll_grad supports the isotropic kernels (one length scale)");
+  if (g.m_v > VIF_MAX_MV - 1) return fail(c, VIF_E_ARG, "vif_nll_grad supports m_v <= %d", VIF_MAX_MV - 1);
   vif_status s = reset_status(c);
   if (s) return s;
   s = fp32_form(c) ? nll_grad_impl<float>(c, y) : nll_grad_impl<double>(c, y);
@@ -543,6 +557,295 @@ vif_status vif_nll_grad(vif_ctx* c, const double* y, double* nll_out, double* gr
   for (int k = 0; k < 3; ++k)
     if (!isfinite(grad_out[k])) return fail(c, VIF_E_NAN, "gradient entry %d is not finite", k);
   return VIF_OK;
+}
+
+}  // extern "C"
+
+// Reverse neighbour lists and the level schedules of the triangular solves,
+// rebuilt when the neighbour list changes. Levels: lev(i) = 1 + max lev(N(i))
+// (a point only depends on earlier levels in B z = x); for B^T z = x the
+// reverse levels rlev(j) = 1 + max{rlev(q) : j in N(q)}. Computed on the host
+// (once per neighbour list, like the neighbour search itself).
+static vif_status ensure_schedules(vif_ctx* c) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  const int mv = g.m_v;
+  if (!c->rev_valid) {
+    if (mv > 0) {
+      stage_begin(c, ST_REV);
+      launch_reverse_lists(c->st, c->nbr, n, mv, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx);
+      stage_end(c, ST_REV);
+    } else {
+      HIPCHK(c, hipMemsetAsync(c->rev_ptr, 0, sizeof(int) * (n + 1), c->st));
+    }
+    c->rev_valid = true;
+  }
+  if (c->lev_valid) return VIF_OK;
+  std::vector<int32_t> nb((size_t)n * (mv > 0 ? mv : 1), -1);
+  if (mv > 0) HIPCHK(c, hipMemcpyAsync(nb.data(), c->nbr, sizeof(int32_t) * n * mv, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  std::vector<int> lev(n, 0), rlev(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    int l = 0;
+    for (int a = 0; a < mv; ++a) {
+      const int j = nb[(size_t)i * mv + a];
+      if (j >= 0 && lev[j] + 1 > l) l = lev[j] + 1;
+    }
+    lev[i] = l;
+  }
+  for (int64_t q = n - 1; q >= 0; --q)
+    for (int a = 0; a < mv; ++a) {
+      const int j = nb[(size_t)q * mv + a];
+      if (j >= 0 && rlev[q] + 1 > rlev[j]) rlev[j] = rlev[q] + 1;
+    }
+  auto schedule = [&](const std::vector<int>& L, std::vector<int>& order, std::vector<int>& ptr) {
+    int nl = 0;
+    for (int64_t i = 0; i < n; ++i) nl = std::max(nl, L[i] + 1);
+    ptr.assign(nl + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ptr[L[i] + 1]++;
+    for (int l = 0; l < nl; ++l) ptr[l + 1] += ptr[l];
+    std::vector<int> cur(ptr.begin(), ptr.end() - 1);
+    order.assign(n, 0);
+    for (int64_t i = 0; i < n; ++i) order[cur[L[i]]++] = (int)i;
+    return nl;
+  };
+  std::vector<int> fo, fp, bo, bp;
+  c->nlev_f = schedule(lev, fo, fp);
+  c->nlev_b = schedule(rlev, bo, bp);
+  HIPCHK(c, hipMemcpyAsync(c->fwd_order, fo.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->fwd_lvl, fp.data(), sizeof(int) * fp.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->bwd_order, bo.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->bwd_lvl, bp.data(), sizeof(int) * bp.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->lev_valid = true;
+  return VIF_OK;
+}
+
+// Laplace workspace views
+struct LapBufs {
+  double *b, *g, *W, *sb, *rhs, *x, *r, *z, *p, *Ap, *t, *s, *v, *q, *qd, *q2, *E, *sw, *sd, *tmp;
+  double *cbuf, *cp, *ctmp;
+  double* sc;    // device scalars: [0] rz [1] pAp [2] - [3] rz_new [4] rr [5] - [6] eta [7..8] dots [9] ll
+  double* part;  // partial sums
+  double* upart;
+};
+
+static LapBufs lap_bufs(vif_ctx* c) {
+  LapBufs B;
+  double* v = c->lv;
+  const int64_t n = c->cfg.n;
+  double** f[] = {&B.b, &B.g, &B.W, &B.sb, &B.rhs, &B.x, &B.r, &B.z, &B.p, &B.Ap,
+                  &B.t, &B.s, &B.v, &B.q, &B.qd, &B.q2, &B.E, &B.sw, &B.sd, &B.tmp};
+  for (int k = 0; k < 20; ++k) *f[k] = v + (size_t)k * n;
+  const int mpa = c->mp > 0 ? c->mp : 1;
+  B.cbuf = c->lm;
+  B.cp = c->lm + mpa;
+  B.ctmp = c->lm + 2 * mpa;
+  B.sc = c->lsc;
+  B.part = c->lpart;
+  B.upart = c->lpart + ceil_div(n, 256) + ceil_div(n, 2048) * 2 + 16;
+  return B;
+}
+
+// out = Sigma_dagger^{-1} w (+ W .* w when W is given)
+template <typename T>
+static void prec_matvec(vif_ctx* c, LapBufs& B, const double* w, const double* W, double* out) {
+  const vif_config& g = c->cfg;
+  const T* U = (const T*)c->U;
+  launch_bw<T>(c->st, (const T*)c->A, c->D, c->nbr, w, g.n, g.m_v, B.t);
+  if (g.m > 0) {
+    launch_utv<T>(c->st, U, B.t, nullptr, g.n, c->mp, c->chunk, B.upart);
+    launch_reduce_apply(c->st, B.upart, c->nchunk, c->mp, c->Minv, B.cbuf, B.cp);
+  }
+  launch_t_minus_uc<T>(c->st, U, B.cp, B.t, c->D, g.n, c->mp, B.s);
+  launch_btw<T>(c->st, (const T*)c->A, c->rev_ptr, c->rev_idx, B.s, W, w, g.n, g.m_v, out);
+}
+
+// z = P^{-1} r  (VIFDU; E and M3inv of the current W)
+template <typename T>
+static void vifdu_apply(vif_ctx* c, LapBufs& B, const double* r, double* z) {
+  const vif_config& g = c->cfg;
+  const T* U = (const T*)c->U;
+  launch_trsv_bwd<T>(c->st, c->bwd_order, c->bwd_lvl, c->nlev_b, c->rev_ptr, c->rev_idx, (const T*)c->A, r, g.m_v,
+                     B.v);
+  launch_scale_e(c->st, B.v, B.E, c->D, g.n, B.q, B.qd);
+  if (g.m > 0) {
+    launch_utv<T>(c->st, U, B.qd, nullptr, g.n, c->mp, c->chunk, B.upart);
+    launch_reduce_apply(c->st, B.upart, c->nchunk, c->mp, c->M3inv, B.cbuf, B.cp);
+  }
+  launch_q_plus_euc<T>(c->st, U, B.cp, B.q, B.E, c->D, g.n, c->mp, B.q2);
+  launch_trsv_fwd<T>(c->st, c->fwd_order, c->fwd_lvl, c->nlev_f, c->nbr, (const T*)c->A, B.q2, g.m_v, z);
+}
+
+__global__ void k_copy_scalar(double* dst, const double* src) { dst[0] = src[0]; }
+__global__ void k_sub(double* out, const double* a, const double* b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+
+static vif_status read_scalars(vif_ctx* c, int count) {
+  HIPCHK(c, hipMemcpyAsync(c->hlsc, c->lsc, sizeof(double) * count, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return VIF_OK;
+}
+
+// sum of the k_lik partials (one per 256 points) into sc[slot]
+__global__ void k_sum_part(const double* part, int nb, double* out) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b];
+    out[0] = s;
+  }
+}
+
+// Preconditioned CG for (W + Sigma_dagger^{-1}) x = rhs, x0 = 0.
+template <typename T>
+static vif_status pcg(vif_ctx* c, LapBufs& B, int* iters, double* relres) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  double* dpart = B.part + ceil_div(n, 256);
+  HIPCHK(c, hipMemsetAsync(B.x, 0, sizeof(double) * n, c->st));
+  HIPCHK(c, hipMemcpyAsync(B.r, B.rhs, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  vifdu_apply<T>(c, B, B.r, B.z);
+  HIPCHK(c, hipMemcpyAsync(B.p, B.z, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  launch_dot2(c->st, B.r, B.z, B.r, B.r, n, dpart, B.sc + 3);
+  hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, c->st, B.sc, B.sc + 3);
+  vif_status s = read_scalars(c, 5);
+  if (s) return s;
+  const double rr0 = c->hlsc[4];
+  const double thr = g.cg_tol * g.cg_tol * rr0;
+  *iters = 0;
+  *relres = 0.0;
+  if (!(rr0 > 0.0)) return VIF_OK;
+  const int check = 4;
+  for (int it = 1; it <= g.cg_maxit; ++it) {
+    prec_matvec<T>(c, B, B.p, B.W, B.Ap);
+    launch_dot2(c->st, B.p, B.Ap, nullptr, nullptr, n, dpart, B.sc + 1);
+    launch_cg_update(c->st, B.x, B.r, B.p, B.Ap, B.sc, n);
+    vifdu_apply<T>(c, B, B.r, B.z);
+    launch_dot2(c->st, B.r, B.z, B.r, B.r, n, dpart, B.sc + 3);
+    launch_cg_dir(c->st, B.p, B.z, B.sc + 3, B.sc, n);
+    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, c->st, B.sc, B.sc + 3);
+    if (it % check == 0 || it == g.cg_maxit) {
+      s = read_scalars(c, 5);
+      if (s) return s;
+      const double rr = c->hlsc[4];
+      if (!isfinite(rr)) return fail(c, VIF_E_NAN, "conjugate gradients: non-finite residual at iteration %d", it);
+      *iters = it;
+      *relres = sqrt(rr / rr0);
+      if (rr <= thr) return VIF_OK;
+    }
+  }
+  return fail(c, VIF_E_CG_MAXIT, "conjugate gradients did not reach %g in %d iterations (relative residual %g)",
+              g.cg_tol, g.cg_maxit, *relres);
+}
+
+template <typename T>
+static vif_status laplace_impl(vif_ctx* c, const double* y, const double* b0, double* mode_out,
+                               vif_laplace_stats* st) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  const int mp = c->mp;
+  LapBufs B = lap_bufs(c);
+  vif_status s = ensure_schedules(c);
+  if (s) return s;
+  vif_laplace_stats S{};
+  if (g.m > 0) launch_gemm_sq(c->st, c->LMinv, c->LMinv, c->Minv, mp, true, false);
+  if (b0) HIPCHK(c, hipMemcpyAsync(B.b, b0, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  else HIPCHK(c, hipMemsetAsync(B.b, 0, sizeof(double) * n, c->st));
+  const int nlb = (int)ceil_div(n, 256);
+  double* dpart = B.part + nlb;
+  // Psi at the start
+  prec_matvec<T>(c, B, B.b, nullptr, B.sb);
+  launch_lik(c->st, g.likelihood, g.lik_param, y, B.b, n, B.g, B.W, B.part);
+  hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, B.part, nlb, B.sc + 9);
+  launch_dot2(c->st, B.b, B.sb, nullptr, nullptr, n, dpart, B.sc + 7);
+  if ((s = read_scalars(c, 10))) return s;
+  double psi_cur = c->hlsc[9] - 0.5 * c->hlsc[7];
+  double bsb = c->hlsc[7];
+  if (!isfinite(psi_cur)) return fail(c, VIF_E_NAN, "Laplace objective not finite at the start");
+  bool converged = false;
+  for (int t = 1; t <= g.newton_maxit; ++t) {
+    // rhs = g - Sigma^{-1} b ; VIFDU data for the current W
+    hipLaunchKernelGGL(k_sub, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->st, B.rhs, B.g, B.sb, n);
+    launch_vifdu_diag(c->st, c->D, B.W, n, B.E, B.sw);
+    if (g.m > 0) {
+      int nchunk = 0;
+      if (fp32_form(c))
+        launch_wgram_partial<float>(c->st, (const float*)c->U, B.sw, n, mp, c->chunk, c->partial, &nchunk);
+      else
+        launch_wgram_partial<double>(c->st, (const double*)c->U, B.sw, n, mp, c->chunk, c->partial, &nchunk);
+      launch_reduce_gram(c->st, c->partial, nchunk, mp, c->M3);
+      launch_chol_inv(c->st, c->M3, c->L3inv, c->Mwork, g.m, mp, B.sc + 12, c->status, 3);
+      launch_gemm_sq(c->st, c->L3inv, c->L3inv, c->M3inv, mp, true, false);
+    }
+    int its = 0;
+    double rel = 0.0;
+    s = pcg<T>(c, B, &its, &rel);
+    if (t <= 64) S.pcg_iters[t - 1] = its;
+    S.pcg_iters_total += its;
+    S.pcg_rel_residual = rel;
+    S.newton_iters = t;
+    if (s) {
+      HIPCHK(c, hipMemcpyAsync(mode_out, B.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+      if (st) *st = S;
+      return s;
+    }
+    // Sigma^{-1} delta, then the objective along b + eta delta (quadratic prior term)
+    prec_matvec<T>(c, B, B.x, nullptr, B.sd);
+    launch_dot2(c->st, B.x, B.sb, B.x, B.sd, n, dpart, B.sc + 7);
+    double eta = 1.0, psi_new = 0.0;
+    int h = 0;
+    for (;; ++h) {
+      c->hlsc[6] = eta;
+      HIPCHK(c, hipMemcpyAsync(B.sc + 6, c->hlsc + 6, sizeof(double), hipMemcpyHostToDevice, c->st));
+      launch_lik_at(c->st, g.likelihood, g.lik_param, y, B.b, B.x, B.sc + 6, n, B.part);
+      hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, B.part, nlb, B.sc + 9);
+      if ((s = read_scalars(c, 10))) return s;
+      const double quad = bsb + 2.0 * eta * c->hlsc[7] + eta * eta * c->hlsc[8];
+      psi_new = c->hlsc[9] - 0.5 * quad;
+      if ((isfinite(psi_new) && psi_new >= psi_cur) || h == 10) {
+        bsb = quad;
+        break;
+      }
+      eta *= 0.5;
+    }
+    S.halvings += h;
+    launch_axpy(c->st, B.b, B.x, B.sc + 6, n);
+    launch_axpy(c->st, B.sb, B.sd, B.sc + 6, n);
+    launch_lik(c->st, g.likelihood, g.lik_param, y, B.b, n, B.g, B.W, B.part);
+    const bool done = fabs(psi_new - psi_cur) <= g.newton_tol * (1.0 + fabs(psi_new));
+    psi_cur = psi_new;
+    if (done) {
+      converged = true;
+      break;
+    }
+  }
+  S.psi = psi_cur;
+  S.converged = converged ? 1 : 0;
+  HIPCHK(c, hipMemcpyAsync(mode_out, B.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipGetLastError());
+  if ((s = read_status(c, "vif_laplace_mode"))) return s;
+  if (st) *st = S;
+  if (!converged) return fail(c, VIF_E_NEWTON, "Newton did not converge in %d iterations", g.newton_maxit);
+  return VIF_OK;
+}
+
+extern "C" {
+
+vif_status vif_laplace_mode(vif_ctx* c, const double* y, const double* b0, double* mode_out, vif_laplace_stats* st) {
+  if (!c) return VIF_E_ARG;
+  if (!c->built) return fail(c, VIF_E_STATE, "vif_laplace_mode before a successful vif_build_factor");
+  if (!y || !mode_out) return fail(c, VIF_E_ARG, "NULL y or mode_out");
+  if (c->cfg.likelihood == VIF_LIK_GAUSSIAN && !(c->cfg.lik_param > 0))
+    return fail(c, VIF_E_ARG, "Gaussian likelihood needs lik_param (noise variance) > 0");
+  vif_status s = reset_status(c);
+  if (s) return s;
+  stage_begin(c, ST_LAPLACE);
+  s = fp32_form(c) ? laplace_impl<float>(c, y, b0, mode_out, st) : laplace_impl<double>(c, y, b0, mode_out, st);
+  stage_end(c, ST_LAPLACE);
+  harvest(c);
+  return s;
 }
 
 __global__ void k_export_A(const void* A, bool f32, int64_t count, double* out) {

@@ -39,7 +39,7 @@ __global__ void k_cov_zz(const double* Z, int m, int mp, CovParams p, double tau
 }
 
 // Cholesky of S (in place, lower), Linv = L^{-1} and out[0] = log det S, in
-// one workgroup of 16 waves (m <= 1024; the matrices stay in L2).
+// one workgroup of 8 waves (m <= 1024; the matrices stay in L2).
 // Cholesky: right-looking over 32-column blocks; each diagonal block is
 // factored and inverted by one wave in LDS, the panel below it is
 // A_ib L_bb^{-T} and the trailing lower triangle is updated by 16x16 tiles,
@@ -47,55 +47,86 @@ __global__ void k_cov_zz(const double* Z, int m, int mp, CovParams p, double tau
 // X_ij = -L_ii^{-1} sum_{k=j}^{i-1} L_ik X_kj, all block columns j advancing
 // one block row per step, the inner sums staged in `work` (mp x mp).
 #define CB 32
-__global__ __launch_bounds__(1024) void k_chol_inv(double* __restrict__ S, double* __restrict__ Linv,
+#define CWG 512
+#define CNW (CWG / 64)
+__global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double* __restrict__ Linv,
                                                    double* __restrict__ work, int m, int mp, double* out,
                                                    int* status, int code_base) {
   __shared__ double Db[CB][CB + 1];
   __shared__ double Di[CB][CB + 1];
   __shared__ int s_fail;
-  __shared__ double red[16];
+  __shared__ double red[CNW];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = lane & 15, g = lane >> 4;
   const int nbk = (m + CB - 1) / CB;
-  for (int q = tid; q < mp * mp; q += 1024) Linv[q] = 0.0;
+  for (int q = tid; q < mp * mp; q += CWG) Linv[q] = 0.0;
   if (tid == 0) s_fail = 0;
   __syncthreads();
 
   for (int b = 0; b < nbk; ++b) {
     const int kb = b * CB, nb = min(CB, m - kb);
-    // A. factor + invert the diagonal block (wave 0)
+    // A. factor + invert the diagonal block (wave 0, lanes 0..31 own one
+    //    row each in registers; rows are broadcast through LDS)
     if (wv == 0) {
-      for (int q = lane; q < CB * CB; q += 64) {
-        const int rr = q / CB, cc = q % CB;
-        double v = (rr == cc) ? 1.0 : 0.0;
-        if (rr < nb && cc < nb && cc <= rr) v = S[(size_t)(kb + rr) * mp + kb + cc];
-        Db[rr][cc] = (cc <= rr) ? v : 0.0;
+      double Lrow[CB];
+      const int myr = lane & (CB - 1);
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        double v = (myr == c) ? 1.0 : 0.0;
+        if (myr < nb && c < nb && c <= myr) v = S[(size_t)(kb + myr) * mp + kb + c];
+        Lrow[c] = (c <= myr) ? v : 0.0;
       }
-      wave_sync();
       int fail = 0;
-      for (int j = 0; j < CB; ++j) {
-        const double piv = Db[j][j];
-        if (!(piv > 0.0) || !isfinite(piv)) { fail = kb + j + 1; break; }
-        const double l = sqrt(piv);
-        wave_sync();
-        if (lane == j) Db[j][j] = l;
-        if (lane > j && lane < CB) Db[lane][j] /= l;
-        wave_sync();
-        if (lane > j && lane < CB) {
-          const double lr = Db[lane][j];
-          for (int c = j + 1; c <= lane; ++c) Db[lane][c] -= lr * Db[c][j];
+#pragma unroll
+      for (int bb = 0; bb < CB; ++bb) {
+        if (lane == bb) {
+          double sd = Lrow[bb];
+#pragma unroll
+          for (int q = 0; q < bb; ++q) sd -= Lrow[q] * Lrow[q];
+          Lrow[bb] = (sd > 0.0 && isfinite(sd)) ? sqrt(sd) : 0.0;
+#pragma unroll
+          for (int q = 0; q <= bb; ++q) Db[bb][q] = Lrow[q];
         }
         wave_sync();
+        const double lbb = Db[bb][bb];
+        if (!(lbb > 0.0) && !fail) fail = kb + bb + 1;
+        if (!fail && lane > bb && lane < CB) {
+          double sd = Lrow[bb];
+#pragma unroll
+          for (int q = 0; q < bb; ++q) sd -= Lrow[q] * Db[bb][q];
+          Lrow[bb] = sd / lbb;
+        }
       }
       if (fail) {
         if (lane == 0) s_fail = fail;
       } else {
-        if (lane < CB) {  // column `lane` of the inverse, by forward substitution
-          for (int t = 0; t < CB; ++t) {
-            double sacc = (t == lane) ? 1.0 : 0.0;
-            for (int u = lane; u < t; ++u) sacc -= Db[t][u] * Di[u][lane];
-            Di[t][lane] = (t >= lane) ? sacc / Db[t][t] : 0.0;
+        wave_sync();
+        // L_bb^{-1}, row `lane` in registers, 16 columns at a time: sweep
+        // u = 0..31; row u is final at step u (divided by L_uu) and is
+        // subtracted from the later rows.
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          double xr[16];
+#pragma unroll
+          for (int c = 0; c < 16; ++c) xr[c] = (16 * h + c == myr) ? 1.0 : 0.0;
+#pragma unroll
+          for (int u = 0; u < CB; ++u) {
+            if (lane == u) {
+              const double inv = 1.0 / Lrow[u];
+#pragma unroll
+              for (int c = 0; c < 16; ++c) {
+                xr[c] *= inv;
+                Di[u][16 * h + c] = xr[c];
+              }
+            }
+            wave_sync();
+            if (lane > u && lane < CB) {
+              const double ltu = Lrow[u];
+#pragma unroll
+              for (int c = 0; c < 16; ++c) xr[c] -= ltu * Di[u][16 * h + c];
+            }
           }
+          wave_sync();
         }
         wave_sync();
         for (int q = lane; q < nb * nb; q += 64) {
@@ -115,7 +146,7 @@ __global__ __launch_bounds__(1024) void k_chol_inv(double* __restrict__ S, doubl
     const int T0 = kb + nb;
     const int nt = (m - T0 + 15) / 16;
     // B. panel L_ib = A_ib L_bb^{-T}
-    for (int t = wv; t < nt; t += 16) {
+    for (int t = wv; t < nt; t += CNW) {
       const int r0 = T0 + 16 * t;
       d4 acc[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
       const int row = r0 + r;
@@ -137,7 +168,7 @@ __global__ __launch_bounds__(1024) void k_chol_inv(double* __restrict__ S, doubl
     __syncthreads();
     // C. trailing update of the lower 16x16 tiles: A_ij -= L_ib L_jb^T
     const int ntile = nt * (nt + 1) / 2;
-    for (int q = wv; q < ntile; q += 16) {
+    for (int q = wv; q < ntile; q += CNW) {
       int ti = 0, rem = q;
       while (rem > ti) { rem -= ti + 1; ++ti; }
       const int tj = rem;
@@ -168,13 +199,13 @@ __global__ __launch_bounds__(1024) void k_chol_inv(double* __restrict__ S, doubl
   // log det = 2 sum log L_ii
   {
     double v = 0.0;
-    for (int i = tid; i < m; i += 1024) v += log(S[(size_t)i * mp + i]);
+    for (int i = tid; i < m; i += CWG) v += log(S[(size_t)i * mp + i]);
     v = wave_sum(v);
     if (lane == 0) red[wv] = v;
     __syncthreads();
     if (tid == 0) {
       double sacc = 0.0;
-      for (int w = 0; w < 16; ++w) sacc += red[w];
+      for (int w = 0; w < CNW; ++w) sacc += red[w];
       out[0] = 2.0 * sacc;
     }
   }
@@ -183,11 +214,12 @@ __global__ __launch_bounds__(1024) void k_chol_inv(double* __restrict__ S, doubl
   for (int s = 1; s < nbk; ++s) {
     const int nitem = (nbk - s) * 4;
     // D1. work_ij = sum_{k=j}^{i-1} L_ik X_kj  (i = j + s), 16x16 quadrant per item
-    for (int it = wv; it < nitem; it += 16) {
+    for (int it = wv; it < nitem; it += CNW) {
       const int j = it >> 2, quad = it & 3, i = j + s;
       const int R0 = i * CB + 16 * (quad >> 1), C0 = j * CB + 16 * (quad & 1);
       d4 acc = {0, 0, 0, 0};
       const int ra = R0 + r, cb = C0 + r;
+#pragma unroll 8
       for (int k0 = j * CB; k0 < i * CB; k0 += 4) {
         const int kk = k0 + g;
         const double a = (ra < m && kk < m) ? S[(size_t)ra * mp + kk] : 0.0;
@@ -202,7 +234,7 @@ __global__ __launch_bounds__(1024) void k_chol_inv(double* __restrict__ S, doubl
     }
     __syncthreads();
     // D2. X_ij = -L_ii^{-1} work_ij
-    for (int it = wv; it < nitem; it += 16) {
+    for (int it = wv; it < nitem; it += CNW) {
       const int j = it >> 2, quad = it & 3, i = j + s;
       const int R0 = i * CB + 16 * (quad >> 1), C0 = j * CB + 16 * (quad & 1);
       d4 acc = {0, 0, 0, 0};
@@ -264,7 +296,7 @@ void launch_cov_zz(hipStream_t st, const double* Z, int m, int mp, const CovPara
 }
 void launch_chol_inv(hipStream_t st, double* S, double* Linv, double* work, int m, int mp, double* out, int* status,
                      int code) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, st, S, Linv, work, m, mp, out, status, code);
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(CWG), 0, st, S, Linv, work, m, mp, out, status, code);
 }
 void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp) {
   const int64_t total = (int64_t)mp * mp;

@@ -43,12 +43,16 @@ struct PointShared {
 // Steps 1-3 for point i, shared by the forward and the adjoint kernels.
 // On return (true): k = |N(i)|, D = D_i, Lrow = row `lane` of L (lanes
 // 0..k), sh.GL = L, sh.As = A_i, sh.nbs / sh.xs = row points / coordinates.
+// With `extra` set, the m-vector extra * extra_scale joins the Gram as row
+// k + 1 (needs k + 2 <= 32): sh.GL[k + 1][j] then holds its dot products
+// with the rows j <= k (row k + 1 is not touched by the Cholesky).
 // Returns false (after flagging status) when the system is not PD.
 template <typename T, int NBLK>
 __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const T* __restrict__ V,
                                              const int32_t* __restrict__ nbr, int64_t i, int mp, int mv,
                                              const CovParams& p, PointShared<T>& sh, T (&Lrow)[32], int& k_out,
-                                             T& D_out, int* status) {
+                                             T& D_out, int* status, const T* extra = nullptr,
+                                             T extra_scale = T(1)) {
   typedef typename Vec4<T>::type T4;
   typedef typename Acc4<T>::type A4;
   const int lane = threadIdx.x;
@@ -64,16 +68,24 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
 
   // 1. Gram of the gathered rows
   const int r = lane & 15, g = lane >> 4;
-  const int pt0 = __shfl(rowpt, r, 64);
-  const int pt1 = __shfl(rowpt, 16 + r, 64);
+  const T* src = nullptr;
+  T scl = T(1);
+  if (rowpt >= 0) {
+    src = V + (size_t)rowpt * mp;
+  } else if (extra != nullptr && lane == k + 1) {
+    src = extra;
+    scl = extra_scale;
+  }
+  const unsigned long long srcbits = (unsigned long long)(uintptr_t)src;
+  const T* s0 = (const T*)(uintptr_t)__shfl(srcbits, r, 64);
+  const T* s1 = (const T*)(uintptr_t)__shfl(srcbits, 16 + r, 64);
+  const T sc0 = __shfl(scl, r, 64), sc1 = __shfl(scl, 16 + r, 64);
   A4 acc00 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
-  const T* v0 = V + (size_t)(pt0 >= 0 ? pt0 : 0) * mp + 4 * g;
-  const T* v1 = V + (size_t)(pt1 >= 0 ? pt1 : 0) * mp + 4 * g;
   const T4 zero4 = {0, 0, 0, 0};
   for (int kk = 0; kk < mp; kk += 16) {
-    const T4 a0 = (pt0 >= 0) ? *reinterpret_cast<const T4*>(v0 + kk) : zero4;
+    const T4 a0 = (s0 != nullptr) ? *reinterpret_cast<const T4*>(s0 + 4 * g + kk) * sc0 : zero4;
     T4 a1 = zero4;
-    if (NBLK == 2) a1 = (pt1 >= 0) ? *reinterpret_cast<const T4*>(v1 + kk) : zero4;
+    if (NBLK == 2) a1 = (s1 != nullptr) ? *reinterpret_cast<const T4*>(s1 + 4 * g + kk) * sc1 : zero4;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       acc00 = mfma16(a0[t], a0[t], acc00);
@@ -192,23 +204,32 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
 // Adjoint of the per-point factor (reverse mode of steps 1-4, recomputed
 // from V rather than stored). Inputs: the cotangent of U,
 // Ubar = U M'^{-1} - e w^T, and of yt, e = yt - U w (w = M'^{-1} U^T yt),
-// from the Woodbury step. With ub = Ubar_i / sqrt(D_i):
+// from the Woodbury step, and Vr = L_m^{-1} dK(Z,X)/drange. With
+// ub = Ubar_i / sqrt(D_i) (joined to the Gram as an extra row, so its dot
+// products with V_{N_j} and V_i come out of the same MFMA pass):
 //   Dbar = 1/(2D) - (Ubar_i.U_i + e_i yt_i) / (2D)
 //   Abar_j = -ub.V_{N_j} - (e_i / sqrt(D)) y_{N_j}
 //   rho = R^{-1} Abar - Dbar A,  rbar = rho - Dbar A,  Rbar = -rho A^T
-// (D_i = c - |V_i|^2 - r^T R^{-1} r; A = R^{-1} r). Outputs per point: rho
-// (n x m_v), the kernel-entry part of the gradient (sigma1^2, range, s2), and
-// two m-vectors: G_i = sum_l rho_l V_{N_l} - ub + Dbar V_i (the cotangent
-// that neighbour N_j receives is A_j G_i + rho_j (-sqrt(D) U_i)), and the
-// point's own cotangent S_i = ub - 2 Dbar V_i - sum_l rho_l V_{N_l}
-// + Dbar (V_i - sqrt(D) U_i).
+// (D_i = c - |V_i|^2 - r^T R^{-1} r; A = R^{-1} r). The cotangent of V is
+// Vbar = sum_i [S_i at i, A_ij G_i + rho_j H_i at N(i)_j] with
+//   G_i = beta_i - ub + Dbar V_i,  H_i = -sqrt(D) U_i,
+//   S_i = ub - 2 Dbar V_i - beta_i + Dbar alpha_i,
+//   alpha_i = sum_j A_j V_{N_j},  beta_i = sum_j rho_j V_{N_j}.
+// Instead of scattering Vbar, each point returns the dot products it adds to
+// sum_a Vbar_a.V_a and sum_a Vbar_a.Vr_a (the K(Z,X) part of the gradient)
+// and the three rows whose outer products with V, U make
+// sum_a V_a Vbar_a^T = sum_i [V_i (S_i + G_i)^T - U_i (sqrt(D) G_i)^T
+//                             - (sqrt(D) beta_i) U_i^T].
+// tpart[i] = (d/dsigma1^2, d/drange, d/ds2) of the covariance entries of
+// R_i, r_i, c_ii plus the K(Z,X) dots.
 template <typename T, int NBLK>
 __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X, const T* __restrict__ V,
-                                                   const int32_t* __restrict__ nbr, const double* __restrict__ y,
-                                                   const T* __restrict__ U, const T* __restrict__ Ubar,
-                                                   const double* __restrict__ e, const double* __restrict__ yt,
-                                                   int64_t n, int mp, int mv, CovParams p, T* __restrict__ rho_out,
-                                                   T* __restrict__ G, T* __restrict__ S, double* __restrict__ tpart,
+                                                   const T* __restrict__ Vr, const int32_t* __restrict__ nbr,
+                                                   const double* __restrict__ y, const T* __restrict__ U,
+                                                   const T* __restrict__ Ubar, const double* __restrict__ e,
+                                                   const double* __restrict__ yt, const double* __restrict__ Dfwd,
+                                                   int64_t n, int mp, int mv, CovParams p, T* __restrict__ Q1,
+                                                   T* __restrict__ Gs, T* __restrict__ Bs, double* __restrict__ tpart,
                                                    int* status) {
   __shared__ PointShared<T> sh;
   __shared__ T rho_s[32];
@@ -218,44 +239,23 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   const int lane = threadIdx.x;
   const int myrow = lane & 31;
   const int64_t i = blockIdx.x;
-  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, Lrow, k, D, status)) {
+  const T rsd = T(1) / sqrt(T(Dfwd[i]));
+  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, Lrow, k, D, status, Ubar + (size_t)i * mp, rsd)) {
     if (lane == 0) tpart[i * 3] = tpart[i * 3 + 1] = tpart[i * 3 + 2] = __builtin_nan("");
     return;
   }
   T (*Ls)[33] = sh.GL;
-  const T rsd = T(1) / sqrt(D), sd = sqrt(D);
-  const int nch = (mp + 63) >> 6;
-  constexpr int MAXCH = 16;
-  T ub[MAXCH];
-  T dotUU = 0;
-#pragma unroll
-  for (int c = 0; c < MAXCH; ++c) {
-    ub[c] = 0;
-    const int l = lane + 64 * c;
-    if (c < nch && l < mp) {
-      ub[c] = Ubar[(size_t)i * mp + l];
-      dotUU += ub[c] * U[(size_t)i * mp + l];
-    }
-  }
-  dotUU = wave_sum(dotUU);
+  const T sd = sqrt(D);
+  // ub.V_{N_j} = GL[k+1][j], ub.V_i = GL[k+1][k];  Ubar_i.U_i = ub.V_i - sum_j A_j ub.V_{N_j}
+  const T ubv = (lane < k) ? sh.GL[k + 1][myrow] : T(0);
+  T ubU = (lane < k) ? -sh.As[myrow] * ubv : T(0);
+  ubU = wave_sum(ubU) + sh.GL[k + 1][k];
   const T ei = T(e[i]), yti = T(yt[i]);
-  const T Dbar = T(0.5) / D - T(0.5) * (dotUU + ei * yti) / D;
+  const T Dbar = T(0.5) / D - T(0.5) * (ubU + ei * yti) / D;
   const T tbar = ei * rsd;
-  // Abar_j
-  T Abar = 0;
-  for (int j = 0; j < k; ++j) {
-    const T* vr = V + (size_t)sh.nbs[j] * mp;
-    T s = 0;
-#pragma unroll
-    for (int c = 0; c < MAXCH; ++c) {
-      const int l = lane + 64 * c;
-      if (c < nch && l < mp) s += ub[c] * vr[l];
-    }
-    s = wave_sum(s);
-    if (lane == j) Abar = -rsd * s - tbar * T(y[sh.nbs[j]]);
-  }
+  const T Abar = (lane < k) ? -ubv - tbar * T(y[sh.nbs[myrow]]) : T(0);
   // z = L_R^{-1} Abar (lane a holds row a of L in Lrow)
-  T accz = (lane < k) ? Abar : T(0);
+  T accz = Abar;
   T z = 0;
 #pragma unroll
   for (int q = 0; q < 32; ++q) {
@@ -278,7 +278,6 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   const T rho = (lane < k) ? ap - Dbar * Aj : T(0);
   const T rbar = rho - Dbar * Aj;
   if (lane < 32) rho_s[lane] = rho;
-  if (lane < mv) rho_out[i * mv + lane] = rho;
   __syncthreads();
   // gradient terms from the covariance entries of R_i, r_i, c_ii
   T ts = 0, tr = 0, tn = 0;
@@ -298,27 +297,39 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
     tr = -rho * sAr + rbar * T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2i, T(p.inv_ls[0]));
     tn = -rho * Aj;
   }
+  // vector part: G, S, H per column; dots with V_i, Vr_i and the gathered sums
+  T tsv = 0, trv = 0;
+  for (int l = lane; l < mp; l += 64) {
+    const size_t o = (size_t)i * mp + l;
+    const T Vi = V[o], Ui = U[o], Vri = Vr[o];
+    const T u = Ubar[o] * rsd;
+    T al = 0, be = 0, alr = 0, ber = 0;
+    for (int j = 0; j < k; ++j) {
+      const size_t oj = (size_t)sh.nbs[j] * mp + l;
+      const T v = V[oj], vr = Vr[oj];
+      al += sh.As[j] * v;
+      be += rho_s[j] * v;
+      alr += sh.As[j] * vr;
+      ber += rho_s[j] * vr;
+    }
+    const T Gl = be - u + Dbar * Vi;
+    const T Sl = u - T(2) * Dbar * Vi - be + Dbar * al;
+    const T Hl = -sd * Ui;
+    tsv += Sl * Vi + Gl * al + Hl * be;
+    trv += Sl * Vri + Gl * alr + Hl * ber;
+    Q1[o] = Sl + Gl;
+    Gs[o] = sd * Gl;
+    Bs[o] = sd * be;
+  }
   ts = wave_sum(ts);
   tr = wave_sum(tr);
   tn = wave_sum(tn);
+  tsv = wave_sum(tsv);
+  trv = wave_sum(trv);
   if (lane == 0) {
-    tpart[i * 3 + 0] = (double)(ts + Dbar);
-    tpart[i * 3 + 1] = (double)tr;
+    tpart[i * 3 + 0] = (double)(ts + Dbar) + (double)tsv / p.sigma1_sq;
+    tpart[i * 3 + 1] = (double)tr + (double)trv;
     tpart[i * 3 + 2] = (double)(tn + Dbar);
-  }
-  // vector cotangents
-#pragma unroll
-  for (int c = 0; c < MAXCH; ++c) {
-    const int l = lane + 64 * c;
-    if (c < nch && l < mp) {
-      const T Vi = V[(size_t)i * mp + l];
-      const T Ui = U[(size_t)i * mp + l];
-      const T u = ub[c] * rsd;
-      T beta = 0;
-      for (int j = 0; j < k; ++j) beta += rho_s[j] * V[(size_t)sh.nbs[j] * mp + l];
-      G[(size_t)i * mp + l] = beta - u + Dbar * Vi;
-      S[(size_t)i * mp + l] = u - T(2) * Dbar * Vi - beta + Dbar * (Vi - sd * Ui);
-    }
   }
 }
 
@@ -361,19 +372,21 @@ template void launch_ytilde<float>(hipStream_t, const float*, const double*, con
                                    int, double*);
 
 template <typename T>
-void launch_factor_bwd(hipStream_t st, const double* X, const T* V, const int32_t* nbr, const double* y, const T* U,
-                       const T* Ubar, const double* e, const double* yt, int64_t n, int mp, int mv,
-                       const CovParams& p, T* rho, T* G, T* S, double* tpart, int* status) {
-  if (mv + 1 <= 16)
-    hipLaunchKernelGGL((k_factor_bwd<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, nbr, y, U, Ubar, e, yt, n, mp,
-                       mv, p, rho, G, S, tpart, status);
+void launch_factor_bwd(hipStream_t st, const double* X, const T* V, const T* Vr, const int32_t* nbr, const double* y,
+                       const T* U, const T* Ubar, const double* e, const double* yt, const double* D, int64_t n,
+                       int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status) {
+  if (mv + 2 <= 16)
+    hipLaunchKernelGGL((k_factor_bwd<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
+                       n, mp, mv, p, Q1, Gs, Bs, tpart, status);
   else
-    hipLaunchKernelGGL((k_factor_bwd<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, nbr, y, U, Ubar, e, yt, n, mp,
-                       mv, p, rho, G, S, tpart, status);
+    hipLaunchKernelGGL((k_factor_bwd<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
+                       n, mp, mv, p, Q1, Gs, Bs, tpart, status);
 }
-template void launch_factor_bwd<double>(hipStream_t, const double*, const double*, const int32_t*, const double*,
-                                        const double*, const double*, const double*, const double*, int64_t, int, int,
-                                        const CovParams&, double*, double*, double*, double*, int*);
-template void launch_factor_bwd<float>(hipStream_t, const double*, const float*, const int32_t*, const double*,
-                                       const float*, const float*, const double*, const double*, int64_t, int, int,
-                                       const CovParams&, float*, float*, float*, double*, int*);
+template void launch_factor_bwd<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
+                                        const double*, const double*, const double*, const double*, const double*,
+                                        const double*, int64_t, int, int, const CovParams&, double*, double*, double*,
+                                        double*, int*);
+template void launch_factor_bwd<float>(hipStream_t, const double*, const float*, const float*, const int32_t*,
+                                       const double*, const float*, const float*, const double*, const double*,
+                                       const double*, int64_t, int, int, const CovParams&, float*, float*, float*,
+                                       double*, int*);

@@ -95,51 +95,29 @@ __global__ __launch_bounds__(256) void k_ubar(const T* __restrict__ U, const T* 
   }
 }
 
-// Vbar_a = S_a + sum over (p, j) with N(p)_j = a of A_pj G_p - rho_pj sqrt(D_p) U_p,
-// fused with the two K(Z,X)-path gradient dots Vbar_a.V_a and Vbar_a.Vr_a.
+// Partial of sum_p [V_p Q1_p^T - U_p Gs_p^T - Bs_p U_p^T] over one point chunk
+// for one 64 x 64 block of the lower triangle (the full sum is symmetric).
+// Workgroups are numbered so that the blocks of one chunk run on one XCD
+// (consecutive workgroup ids go to different XCDs), sharing its L2.
 template <typename T>
-__global__ __launch_bounds__(256) void k_vbar(const T* __restrict__ S, const T* __restrict__ G,
-                                              const T* __restrict__ U, const double* __restrict__ D,
-                                              const T* __restrict__ A, const T* __restrict__ rho,
-                                              const int* __restrict__ rev_ptr, const int* __restrict__ rev_idx,
-                                              const T* __restrict__ V, const T* __restrict__ Vr, int64_t n, int mp,
-                                              int mv, T* __restrict__ Vbar, double* __restrict__ vpart) {
-  const int lane = threadIdx.x & 63;
-  const int64_t a = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (a >= n) return;
-  const int beg = rev_ptr[a], end = rev_ptr[a + 1];
-  double ds = 0.0, dr = 0.0;
-  for (int l = lane; l < mp; l += 64) {
-    T acc = S[(size_t)a * mp + l];
-    for (int q = beg; q < end; ++q) {
-      const int idx = rev_idx[q];
-      const int64_t p = idx / mv;
-      acc += A[idx] * G[(size_t)p * mp + l] - rho[idx] * T(sqrt(D[p])) * U[(size_t)p * mp + l];
-    }
-    Vbar[(size_t)a * mp + l] = acc;
-    ds += (double)acc * (double)V[(size_t)a * mp + l];
-    dr += (double)acc * (double)Vr[(size_t)a * mp + l];
-  }
-  ds = wave_sum(ds);
-  dr = wave_sum(dr);
-  if (lane == 0) {
-    vpart[a * 2 + 0] = ds;
-    vpart[a * 2 + 1] = dr;
-  }
-}
-
-// Partial sum_p P_p Q_p^T over a point chunk for one 64 x 64 block (all blocks).
-template <typename T>
-__global__ __launch_bounds__(256) void k_cross_partial(const T* __restrict__ P, const T* __restrict__ Q, int64_t n,
-                                                       int mp, int chunk, double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_cross3_partial(const T* __restrict__ V, const T* __restrict__ Q1,
+                                                        const T* __restrict__ U, const T* __restrict__ Gs,
+                                                        const T* __restrict__ Bs, int64_t n, int mp, int chunk,
+                                                        int nchunk, int nblk, double* __restrict__ partial) {
   typedef typename Acc4<T>::type A4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = lane & 15, g = lane >> 4;
-  const int nb = (mp + 63) / 64;
-  const int bi = blockIdx.y / nb, bj = blockIdx.y % nb;
+  const int wg = blockIdx.x;
+  const int xcd = wg & 7, slot = wg >> 3;
+  const int blk = slot % nblk;
+  const int cidx = (slot / nblk) * 8 + xcd;
+  if (cidx >= nchunk) return;
+  int bl = blk, bi = 0;
+  while (bl > bi) { bl -= bi + 1; ++bi; }
+  const int bj = bl;
   const int L0 = bi * 64 + 32 * (w >> 1), C0 = bj * 64 + 32 * (w & 1);
-  if (L0 >= mp || C0 >= mp) return;
-  const int64_t pbeg = (int64_t)blockIdx.x * chunk;
+  if (L0 >= mp || C0 >= mp || C0 > L0 + 31) return;
+  const int64_t pbeg = (int64_t)cidx * chunk;
   const int64_t pend = min(n, pbeg + chunk);
   bool rok[2], cok[2];
 #pragma unroll
@@ -151,38 +129,51 @@ __global__ __launch_bounds__(256) void k_cross_partial(const T* __restrict__ P, 
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = A4{0, 0, 0, 0};
+    for (int yy = 0; yy < 2; ++yy) acc[x][yy] = A4{0, 0, 0, 0};
   for (int64_t p0 = pbeg; p0 < pend; p0 += 4) {
     const int64_t pp = p0 + g;
     const bool pv = pp < pend;
     const size_t off = (size_t)(pv ? pp : pbeg) * mp;
-    T a[2], b[2];
+    T a1[2], b1[2], a2[2], b2[2], a3[2], b3[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      a[t] = (pv && rok[t]) ? P[off + L0 + 16 * t + r] : T(0);
-      b[t] = (pv && cok[t]) ? Q[off + C0 + 16 * t + r] : T(0);
+      const bool ra = pv && rok[t], cb = pv && cok[t];
+      const size_t oa = off + L0 + 16 * t + r, ob = off + C0 + 16 * t + r;
+      a1[t] = ra ? V[oa] : T(0);
+      b1[t] = cb ? Q1[ob] : T(0);
+      a2[t] = ra ? -U[oa] : T(0);
+      b2[t] = cb ? Gs[ob] : T(0);
+      a3[t] = ra ? -Bs[oa] : T(0);
+      b3[t] = cb ? U[ob] : T(0);
     }
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y) acc[x][y] = mfma16(a[x], b[y], acc[x][y]);
+      for (int yy = 0; yy < 2; ++yy) {
+        acc[x][yy] = mfma16(a1[x], b1[yy], acc[x][yy]);
+        acc[x][yy] = mfma16(a2[x], b2[yy], acc[x][yy]);
+        acc[x][yy] = mfma16(a3[x], b3[yy], acc[x][yy]);
+      }
   }
-  double* out = partial + (size_t)blockIdx.x * mp * mp;
+  double* out = partial + (size_t)cidx * mp * mp;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
-      if (rok[x] && cok[y])
+    for (int yy = 0; yy < 2; ++yy)
+      if (rok[x] && cok[yy])
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          out[(size_t)(L0 + 16 * x + acc_row<T>(lane, v)) * mp + C0 + 16 * y + r] = (double)acc[x][y][v];
+          out[(size_t)(L0 + 16 * x + acc_row<T>(lane, v)) * mp + C0 + 16 * yy + r] = (double)acc[x][yy][v];
 }
 
-__global__ void k_reduce_full(const double* __restrict__ partial, int nchunk, int mp, double* __restrict__ out) {
+// out = sum of the partials' lower triangles, mirrored to a full symmetric matrix
+__global__ void k_reduce_sym(const double* __restrict__ partial, int nchunk, int mp, double* __restrict__ out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)mp * mp) return;
+  const int l = (int)(q / mp), c = (int)(q % mp);
+  const size_t src = (c <= l) ? (size_t)q : (size_t)c * mp + l;
   double s = 0.0;
-  for (int k = 0; k < nchunk; ++k) s += partial[(size_t)k * mp * mp + q];
+  for (int k = 0; k < nchunk; ++k) s += partial[(size_t)k * mp * mp + src];
   out[q] = s;
 }
 
@@ -305,23 +296,19 @@ void launch_ubar(hipStream_t st, const T* U, const T* Minv, const double* e, con
   hipLaunchKernelGGL((k_ubar<T>), grid, dim3(256), 0, st, U, Minv, e, w, n, mp, Ubar);
 }
 template <typename T>
-void launch_vbar(hipStream_t st, const T* S, const T* G, const T* U, const double* D, const T* A, const T* rho,
-                 const int* rev_ptr, const int* rev_idx, const T* V, const T* Vr, int64_t n, int mp, int mv, T* Vbar,
-                 double* vpart) {
-  hipLaunchKernelGGL((k_vbar<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, S, G, U, D, A, rho, rev_ptr,
-                     rev_idx, V, Vr, n, mp, mv, Vbar, vpart);
-}
-template <typename T>
-void launch_cross_partial(hipStream_t st, const T* P, const T* Q, int64_t n, int mp, int chunk, double* partial,
-                          int* nchunk_out) {
+void launch_cross3_partial(hipStream_t st, const T* V, const T* Q1, const T* U, const T* Gs, const T* Bs, int64_t n,
+                           int mp, int chunk, double* partial, int* nchunk_out) {
   const int nchunk = (int)ceil_div(n, chunk);
   const int nb = (mp + 63) / 64;
-  hipLaunchKernelGGL((k_cross_partial<T>), dim3(nchunk, nb * nb), dim3(256), 0, st, P, Q, n, mp, chunk, partial);
+  const int nblk = nb * (nb + 1) / 2;
+  const int nwg = (int)(ceil_div(nchunk, 8) * 8 * nblk);
+  hipLaunchKernelGGL((k_cross3_partial<T>), dim3(nwg), dim3(256), 0, st, V, Q1, U, Gs, Bs, n, mp, chunk, nchunk, nblk,
+                     partial);
   *nchunk_out = nchunk;
 }
-void launch_reduce_full(hipStream_t st, const double* partial, int nchunk, int mp, double* out) {
+void launch_reduce_sym(hipStream_t st, const double* partial, int nchunk, int mp, double* out) {
   const int64_t total = (int64_t)mp * mp;
-  hipLaunchKernelGGL(k_reduce_full, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, partial, nchunk, mp, out);
+  hipLaunchKernelGGL(k_reduce_sym, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, partial, nchunk, mp, out);
 }
 void launch_sigma_m_grad(hipStream_t st, const double* Tm, const double* Z, int m, int mp, const CovParams& p,
                          double* rowpart) {
@@ -353,12 +340,7 @@ template void launch_ubar<double>(hipStream_t, const double*, const double*, con
                                   int, double*);
 template void launch_ubar<float>(hipStream_t, const float*, const float*, const double*, const double*, int64_t, int,
                                  float*);
-template void launch_vbar<double>(hipStream_t, const double*, const double*, const double*, const double*,
-                                  const double*, const double*, const int*, const int*, const double*, const double*,
-                                  int64_t, int, int, double*, double*);
-template void launch_vbar<float>(hipStream_t, const float*, const float*, const float*, const double*, const float*,
-                                 const float*, const int*, const int*, const float*, const float*, int64_t, int, int,
-                                 float*, double*);
-template void launch_cross_partial<double>(hipStream_t, const double*, const double*, int64_t, int, int, double*,
-                                           int*);
-template void launch_cross_partial<float>(hipStream_t, const float*, const float*, int64_t, int, int, double*, int*);
+template void launch_cross3_partial<double>(hipStream_t, const double*, const double*, const double*, const double*,
+                                            const double*, int64_t, int, int, double*, int*);
+template void launch_cross3_partial<float>(hipStream_t, const float*, const float*, const float*, const float*,
+                                           const float*, int64_t, int, int, double*, int*);

@@ -40,9 +40,9 @@ void launch_vec_reduce(hipStream_t st, const double* partial, int nchunk, int le
 
 // factor.hip (adjoint)
 template <typename T>
-void launch_factor_bwd(hipStream_t st, const double* X, const T* V, const int32_t* nbr, const double* y, const T* U,
-                       const T* Ubar, const double* e, const double* yt, int64_t n, int mp, int mv,
-                       const CovParams& p, T* rho, T* G, T* S, double* tpart, int* status);
+void launch_factor_bwd(hipStream_t st, const double* X, const T* V, const T* Vr, const int32_t* nbr, const double* y,
+                       const T* U, const T* Ubar, const double* e, const double* yt, const double* D, int64_t n,
+                       int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status);
 
 // grad.hip
 void launch_gemm_sq(hipStream_t st, const double* A, const double* B, double* C, int mp, bool ta, bool tb);
@@ -54,15 +54,54 @@ template <typename T>
 void launch_ubar(hipStream_t st, const T* U, const T* Minv, const double* e, const double* w, int64_t n, int mp,
                  T* Ubar);
 template <typename T>
-void launch_vbar(hipStream_t st, const T* S, const T* G, const T* U, const double* D, const T* A, const T* rho,
-                 const int* rev_ptr, const int* rev_idx, const T* V, const T* Vr, int64_t n, int mp, int mv, T* Vbar,
-                 double* vpart);
-template <typename T>
-void launch_cross_partial(hipStream_t st, const T* P, const T* Q, int64_t n, int mp, int chunk, double* partial,
-                          int* nchunk_out);
-void launch_reduce_full(hipStream_t st, const double* partial, int nchunk, int mp, double* out);
+void launch_cross3_partial(hipStream_t st, const T* V, const T* Q1, const T* U, const T* Gs, const T* Bs, int64_t n,
+                           int mp, int chunk, double* partial, int* nchunk_out);
+void launch_reduce_sym(hipStream_t st, const double* partial, int nchunk, int mp, double* out);
 void launch_sigma_m_grad(hipStream_t st, const double* Tm, const double* Z, int m, int mp, const CovParams& p,
                          double* rowpart);
 int launch_colsum(hipStream_t st, const double* in, int64_t rows, int cols, double* out);
 void launch_reverse_lists(hipStream_t st, const int32_t* nbr, int64_t n, int mv, int* cnt, int* ptr, int* cursor,
                           int* idx);
+
+// laplace.hip
+void launch_lik(hipStream_t st, int lik, double lpar, const double* y, const double* b, int64_t n, double* g,
+                double* W, double* part);
+void launch_lik_at(hipStream_t st, int lik, double lpar, const double* y, const double* b, const double* d,
+                   const double* eta, int64_t n, double* part);
+template <typename T>
+void launch_bw(hipStream_t st, const T* A, const double* D, const int32_t* nbr, const double* w, int64_t n, int mv,
+               double* t);
+template <typename T>
+void launch_utv(hipStream_t st, const T* U, const double* v, const double* scale, int64_t n, int mp, int chunk,
+                double* partial);
+void launch_reduce_apply(hipStream_t st, const double* partial, int nchunk, int mp, const double* Minv, double* cbuf,
+                         double* out);
+template <typename T>
+void launch_t_minus_uc(hipStream_t st, const T* U, const double* c, const double* t, const double* D, int64_t n,
+                       int mp, double* out);
+template <typename T>
+void launch_btw(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s, const double* W,
+                const double* p, int64_t n, int mv, double* out);
+int launch_dot2(hipStream_t st, const double* a, const double* b, const double* c, const double* d, int64_t n,
+                double* part, double* out);
+void launch_cg_update(hipStream_t st, double* x, double* r, const double* p, const double* Ap, const double* sc,
+                      int64_t n);
+void launch_cg_dir(hipStream_t st, double* p, const double* z, const double* rz_new, const double* rz_old,
+                   int64_t n);
+void launch_vifdu_diag(hipStream_t st, const double* D, const double* W, int64_t n, double* E, double* sw);
+void launch_scale_e(hipStream_t st, const double* v, const double* E, const double* D, int64_t n, double* q,
+                    double* qd);
+template <typename T>
+void launch_q_plus_euc(hipStream_t st, const T* U, const double* c, const double* q, const double* E,
+                       const double* D, int64_t n, int mp, double* out);
+template <typename T>
+void launch_wgram_partial(hipStream_t st, const T* U, const double* sw, int64_t n, int mp, int chunk, double* partial,
+                          int* nchunk_out);
+template <typename T>
+void launch_trsv_fwd(hipStream_t st, const int* order, const int* lvl, int nlev, const int32_t* nbr, const T* A,
+                     const double* x, int mv, double* z);
+template <typename T>
+void launch_trsv_bwd(hipStream_t st, const int* order, const int* lvl, int nlev, const int* rev_ptr,
+                     const int* rev_idx, const T* A, const double* x, int mv, double* z);
+void launch_chol_apply(hipStream_t st, const double* Linv, const double* c, int mp, double* tmp, double* out);
+void launch_axpy(hipStream_t st, double* y, const double* x, const double* eta, int64_t n);

@@ -1,0 +1,459 @@
+// Laplace mode finding for latent VIF models (Sec. 3 and Sec. 4): likelihood
+// terms, the matrix-vector product with A = W + Sigma_dagger^{-1}
+// (eq. pcls1), the VIFDU preconditioner (Sec. 4.3.1, App. E.1) and the
+// vector kernels of the preconditioned CG iteration.
+//
+// Whitened forms (U = D^{-1/2} B V^T, M' = I + U^T U; L_m M' L_m^T = M):
+//   Sigma_dagger^{-1} w = B^T D^{-1/2} (t - U M'^{-1} U^T t),  t = D^{-1/2} B w
+//   P^{-1} w = B^{-1} [E + E D^{-1/2} U M3'^{-1} U^T D^{-1/2} E] B^{-T} w,
+//   E = diag(D_i / (1 + D_i W_i)),  M3' = I + U^T diag(D_i W_i / (1 + D_i W_i)) U,
+// the congruences (by L_m) of the paper's M and M_3 forms.
+#include "common.h"
+#include "kernels.h"
+
+// --- likelihoods: Bernoulli-logit, Poisson-log, Gaussian with noise variance lp ---
+__device__ __forceinline__ void lik_terms(int lik, double lpar, double y, double b, double& logp, double& g,
+                                          double& W) {
+  if (lik == 1) {  // Bernoulli, logit link
+    const double pi = 1.0 / (1.0 + exp(-b));
+    logp = y * b - (b > 0 ? b + log1p(exp(-b)) : log1p(exp(b)));
+    g = y - pi;
+    W = pi * (1.0 - pi);
+  } else if (lik == 2) {  // Poisson, log link
+    const double mu = exp(b);
+    logp = y * b - mu - lgamma(y + 1.0);
+    g = y - mu;
+    W = mu;
+  } else {  // Gaussian with noise variance lpar
+    logp = -0.9189385332046727 - 0.5 * log(lpar) - 0.5 * (y - b) * (y - b) / lpar;
+    g = (y - b) / lpar;
+    W = 1.0 / lpar;
+  }
+}
+
+// g, W at b and per-chunk partial sums of log p(y|b)
+__global__ __launch_bounds__(256) void k_lik(int lik, double lpar, const double* __restrict__ y, const double* __restrict__ b,
+                                             int64_t n, double* __restrict__ g, double* __restrict__ W,
+                                             double* __restrict__ part) {
+  __shared__ double red[4];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double lp = 0.0;
+  if (i < n) {
+    double gg, ww;
+    lik_terms(lik, lpar, y[i], b[i], lp, gg, ww);
+    g[i] = gg;
+    W[i] = ww;
+  }
+  lp = wave_sum(lp);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lp;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// per-chunk partial sums of log p(y | b + eta d)
+__global__ __launch_bounds__(256) void k_lik_at(int lik, double lpar, const double* __restrict__ y, const double* __restrict__ b,
+                                                const double* __restrict__ d, const double* __restrict__ eta,
+                                                int64_t n, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double lp = 0.0;
+  if (i < n) {
+    double gg, ww;
+    lik_terms(lik, lpar, y[i], b[i] + eta[0] * d[i], lp, gg, ww);
+  }
+  lp = wave_sum(lp);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lp;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// t = D^{-1/2} B w :  t_i = (w_i - sum_j A_ij w_{N(i)_j}) / sqrt(D_i)
+template <typename T>
+__global__ void k_bw(const T* __restrict__ A, const double* __restrict__ D, const int32_t* __restrict__ nbr,
+                     const double* __restrict__ w, int64_t n, int mv, double* __restrict__ t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = w[i];
+  for (int a = 0; a < mv; ++a) {
+    const int j = nbr[i * mv + a];
+    if (j >= 0) s -= (double)A[i * mv + a] * w[j];
+  }
+  t[i] = s / sqrt(D[i]);
+}
+
+// per-chunk partials of U^T (scale .* v): partial[chunk][mp]; scale may be null
+template <typename T>
+__global__ __launch_bounds__(256) void k_utv(const T* __restrict__ U, const double* __restrict__ v,
+                                             const double* __restrict__ scale, int64_t n, int mp, int chunk,
+                                             double* __restrict__ partial) {
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk;
+  const int64_t pend = min(n, pbeg + chunk);
+  for (int l = threadIdx.x; l < mp; l += 256) {
+    double s = 0.0;
+    for (int64_t p = pbeg; p < pend; ++p) {
+      const double vv = scale ? v[p] * scale[p] : v[p];
+      s += (double)U[(size_t)p * mp + l] * vv;
+    }
+    partial[(size_t)blockIdx.x * mp + l] = s;
+  }
+}
+
+// c = sum_chunks partial; out = Minv c  (Minv full symmetric mp x mp), one workgroup
+__global__ __launch_bounds__(256) void k_reduce_apply(const double* __restrict__ partial, int nchunk, int mp,
+                                                      const double* __restrict__ Minv, double* __restrict__ cbuf,
+                                                      double* __restrict__ out) {
+  for (int l = threadIdx.x; l < mp; l += 256) {
+    double s = 0.0;
+    for (int c = 0; c < nchunk; ++c) s += partial[(size_t)c * mp + l];
+    cbuf[l] = s;
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < mp; l += 256) {
+    const double* row = Minv + (size_t)l * mp;
+    double s = 0.0;
+    for (int c = 0; c < mp; ++c) s += row[c] * cbuf[c];
+    out[l] = s;
+  }
+}
+
+// out_i = (t_i - U_i . c) * f_i   (one wave per point), f = D^{-1/2}
+template <typename T>
+__global__ __launch_bounds__(256) void k_t_minus_uc(const T* __restrict__ U, const double* __restrict__ c,
+                                                    const double* __restrict__ t, const double* __restrict__ D,
+                                                    int64_t n, int mp, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  double s = 0.0;
+  for (int l = lane; l < mp; l += 64) s += (double)U[(size_t)i * mp + l] * c[l];
+  s = wave_sum(s);
+  if (lane == 0) out[i] = (t[i] - s) / sqrt(D[i]);
+}
+
+// out_j = W_j p_j + s_j - sum_{(q,slot): N(q)_slot = j} A_{q,slot} s_q   (W may be null)
+template <typename T>
+__global__ void k_btw(const T* __restrict__ A, const int* __restrict__ rev_ptr, const int* __restrict__ rev_idx,
+                      const double* __restrict__ s, const double* __restrict__ W, const double* __restrict__ p,
+                      int64_t n, int mv, double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double v = s[j];
+  const int beg = rev_ptr[j], end = rev_ptr[j + 1];
+  for (int q = beg; q < end; ++q) {
+    const int idx = rev_idx[q];
+    v -= (double)A[idx] * s[idx / mv];
+  }
+  if (W) v += W[j] * p[j];
+  out[j] = v;
+}
+
+// per-block partials of up to two dot products a.b, c.d
+__global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ a, const double* __restrict__ b,
+                                              const double* __restrict__ c, const double* __restrict__ d, int64_t n,
+                                              double* __restrict__ part) {
+  __shared__ double red[2][4];
+  const int64_t i0 = (int64_t)blockIdx.x * 2048;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < min(n, i0 + 2048); i += 256) {
+    s0 += a[i] * b[i];
+    if (c) s1 += c[i] * d[i];
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = s0; red[1][threadIdx.x >> 6] = s1; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 2] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    part[blockIdx.x * 2 + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+// sum the partials in a fixed order: out[0] = sum part[2b], out[1] = sum part[2b+1]
+__global__ void k_sum2(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = 0; b < nb; ++b) { s0 += part[2 * b]; s1 += part[2 * b + 1]; }
+    out[0] = s0;
+    out[1] = s1;
+  }
+}
+
+// y = x + alpha * (coef) * z ...: axpy forms used by CG
+// x += a p ; r -= a Ap   with a = sc[0] / sc[1]
+__global__ void k_cg_update(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                            const double* __restrict__ Ap, const double* __restrict__ sc, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = sc[0] / sc[1];
+  x[i] += a * p[i];
+  r[i] -= a * Ap[i];
+}
+
+// p = z + beta p with beta = sc_new / sc_old
+__global__ void k_cg_dir(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ rz_new,
+                         const double* __restrict__ rz_old, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p[i] = z[i] + (rz_new[0] / rz_old[0]) * p[i];
+}
+
+// E_i = D_i / (1 + D_i W_i); weights for M3': sqrt(D_i W_i / (1 + D_i W_i))
+__global__ void k_vifdu_diag(const double* __restrict__ D, const double* __restrict__ W, int64_t n,
+                             double* __restrict__ E, double* __restrict__ sw) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double dw = D[i] * W[i];
+  E[i] = D[i] / (1.0 + dw);
+  sw[i] = sqrt(dw / (1.0 + dw));
+}
+
+// q_i = E_i v_i ; out_i = q_i / sqrt(D_i)
+__global__ void k_scale_e(const double* __restrict__ v, const double* __restrict__ E, const double* __restrict__ D,
+                          int64_t n, double* __restrict__ q, double* __restrict__ qd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double qq = E[i] * v[i];
+  q[i] = qq;
+  qd[i] = qq / sqrt(D[i]);
+}
+
+// out_i = q_i + E_i D_i^{-1/2} U_i . c   (one wave per point)
+template <typename T>
+__global__ __launch_bounds__(256) void k_q_plus_euc(const T* __restrict__ U, const double* __restrict__ c,
+                                                    const double* __restrict__ q, const double* __restrict__ E,
+                                                    const double* __restrict__ D, int64_t n, int mp,
+                                                    double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  double s = 0.0;
+  for (int l = lane; l < mp; l += 64) s += (double)U[(size_t)i * mp + l] * c[l];
+  s = wave_sum(s);
+  if (lane == 0) out[i] = q[i] + E[i] * s / sqrt(D[i]);
+}
+
+// Weighted Gram partial: sum_p (sw_p U_p)(sw_p U_p)^T over a chunk, lower 64x64 blocks
+template <typename T>
+__global__ __launch_bounds__(256) void k_wgram_partial(const T* __restrict__ U, const double* __restrict__ sw,
+                                                       int64_t n, int mp, int chunk, double* __restrict__ partial) {
+  typedef typename Acc4<T>::type A4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  int blk = blockIdx.y, bi = 0;
+  while (blk > bi) { blk -= bi + 1; ++bi; }
+  const int bj = blk;
+  const int L0 = bi * 64 + 32 * (w >> 1), C0 = bj * 64 + 32 * (w & 1);
+  if (L0 >= mp || C0 >= mp || C0 > L0 + 31) return;
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk;
+  const int64_t pend = min(n, pbeg + chunk);
+  bool rok[2], cok[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    rok[t] = L0 + 16 * t < mp;
+    cok[t] = C0 + 16 * t < mp;
+  }
+  A4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = A4{0, 0, 0, 0};
+  for (int64_t p0 = pbeg; p0 < pend; p0 += 4) {
+    const int64_t pp = p0 + g;
+    const bool pv = pp < pend;
+    const T* row = U + (size_t)(pv ? pp : pbeg) * mp;
+    const T s = pv ? (T)sw[pp] : T(0);
+    T a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      a[t] = (pv && rok[t]) ? row[L0 + 16 * t + r] * s : T(0);
+      b[t] = (pv && cok[t]) ? row[C0 + 16 * t + r] * s : T(0);
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int yy = 0; yy < 2; ++yy) acc[x][yy] = mfma16(a[x], b[yy], acc[x][yy]);
+  }
+  double* out = partial + (size_t)blockIdx.x * mp * mp;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy)
+      if (rok[x] && cok[yy])
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          out[(size_t)(L0 + 16 * x + acc_row<T>(lane, v)) * mp + C0 + 16 * yy + r] = (double)acc[x][yy][v];
+}
+
+// Level-scheduled sparse unit-triangular solves, one workgroup of 1024
+// threads sweeping the levels in order (a level only reads earlier levels).
+// Forward, B z = x:   z_i = x_i + sum_j A_ij z_{N(i)_j}
+template <typename T>
+__global__ __launch_bounds__(1024) void k_trsv_fwd(const int* __restrict__ order, const int* __restrict__ lvl,
+                                                   int nlev, const int32_t* __restrict__ nbr,
+                                                   const T* __restrict__ A, const double* __restrict__ x, int mv,
+                                                   double* __restrict__ z) {
+  for (int L = 0; L < nlev; ++L) {
+    const int beg = lvl[L], end = lvl[L + 1];
+    for (int q = beg + threadIdx.x; q < end; q += 1024) {
+      const int i = order[q];
+      double s = x[i];
+      for (int a = 0; a < mv; ++a) {
+        const int j = nbr[(size_t)i * mv + a];
+        if (j >= 0) s += (double)A[(size_t)i * mv + a] * z[j];
+      }
+      z[i] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// Transposed, B^T z = x:  z_j = x_j + sum_{(q,slot): N(q)_slot = j} A_{q,slot} z_q
+template <typename T>
+__global__ __launch_bounds__(1024) void k_trsv_bwd(const int* __restrict__ order, const int* __restrict__ lvl,
+                                                   int nlev, const int* __restrict__ rev_ptr,
+                                                   const int* __restrict__ rev_idx, const T* __restrict__ A,
+                                                   const double* __restrict__ x, int mv, double* __restrict__ z) {
+  for (int L = 0; L < nlev; ++L) {
+    const int beg = lvl[L], end = lvl[L + 1];
+    for (int q = beg + threadIdx.x; q < end; q += 1024) {
+      const int j = order[q];
+      double s = x[j];
+      for (int e = rev_ptr[j]; e < rev_ptr[j + 1]; ++e) {
+        const int idx = rev_idx[e];
+        s += (double)A[idx] * z[idx / mv];
+      }
+      z[j] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// out = L^{-T} (L^{-1} c)  for L^{-1} given (lower, mp x mp): one workgroup
+__global__ __launch_bounds__(256) void k_chol_apply(const double* __restrict__ Linv, const double* __restrict__ c,
+                                                    int mp, double* __restrict__ tmp, double* __restrict__ out) {
+  for (int l = threadIdx.x; l < mp; l += 256) {
+    const double* row = Linv + (size_t)l * mp;
+    double s = 0.0;
+    for (int q = 0; q <= l; ++q) s += row[q] * c[q];
+    tmp[l] = s;
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < mp; l += 256) {
+    double s = 0.0;
+    for (int q = l; q < mp; ++q) s += Linv[(size_t)q * mp + l] * tmp[q];
+    out[l] = s;
+  }
+}
+
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, const double* __restrict__ eta,
+                       int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += eta[0] * x[i];
+}
+
+// ---------------------------------------------------------------------------
+static inline dim3 g1(int64_t n, int bs = 256) { return dim3((unsigned)ceil_div(n, bs)); }
+
+void launch_lik(hipStream_t st, int lik, double lpar, const double* y, const double* b, int64_t n, double* g,
+                double* W, double* part) {
+  hipLaunchKernelGGL(k_lik, g1(n), dim3(256), 0, st, lik, lpar, y, b, n, g, W, part);
+}
+void launch_lik_at(hipStream_t st, int lik, double lpar, const double* y, const double* b, const double* d,
+                   const double* eta, int64_t n, double* part) {
+  hipLaunchKernelGGL(k_lik_at, g1(n), dim3(256), 0, st, lik, lpar, y, b, d, eta, n, part);
+}
+template <typename T>
+void launch_bw(hipStream_t st, const T* A, const double* D, const int32_t* nbr, const double* w, int64_t n, int mv,
+               double* t) {
+  hipLaunchKernelGGL((k_bw<T>), g1(n), dim3(256), 0, st, A, D, nbr, w, n, mv, t);
+}
+template <typename T>
+void launch_utv(hipStream_t st, const T* U, const double* v, const double* scale, int64_t n, int mp, int chunk,
+                double* partial) {
+  hipLaunchKernelGGL((k_utv<T>), dim3((unsigned)ceil_div(n, chunk)), dim3(256), 0, st, U, v, scale, n, mp, chunk,
+                     partial);
+}
+void launch_reduce_apply(hipStream_t st, const double* partial, int nchunk, int mp, const double* Minv, double* cbuf,
+                         double* out) {
+  hipLaunchKernelGGL(k_reduce_apply, dim3(1), dim3(256), 0, st, partial, nchunk, mp, Minv, cbuf, out);
+}
+template <typename T>
+void launch_t_minus_uc(hipStream_t st, const T* U, const double* c, const double* t, const double* D, int64_t n,
+                       int mp, double* out) {
+  hipLaunchKernelGGL((k_t_minus_uc<T>), g1(n, 4), dim3(256), 0, st, U, c, t, D, n, mp, out);
+}
+template <typename T>
+void launch_btw(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s, const double* W,
+                const double* p, int64_t n, int mv, double* out) {
+  hipLaunchKernelGGL((k_btw<T>), g1(n), dim3(256), 0, st, A, rev_ptr, rev_idx, s, W, p, n, mv, out);
+}
+int launch_dot2(hipStream_t st, const double* a, const double* b, const double* c, const double* d, int64_t n,
+                double* part, double* out) {
+  const int nb = (int)ceil_div(n, 2048);
+  hipLaunchKernelGGL(k_dot2, dim3(nb), dim3(256), 0, st, a, b, c, d, n, part);
+  hipLaunchKernelGGL(k_sum2, dim3(1), dim3(64), 0, st, part, nb, out);
+  return nb;
+}
+void launch_cg_update(hipStream_t st, double* x, double* r, const double* p, const double* Ap, const double* sc,
+                      int64_t n) {
+  hipLaunchKernelGGL(k_cg_update, g1(n), dim3(256), 0, st, x, r, p, Ap, sc, n);
+}
+void launch_cg_dir(hipStream_t st, double* p, const double* z, const double* rz_new, const double* rz_old,
+                   int64_t n) {
+  hipLaunchKernelGGL(k_cg_dir, g1(n), dim3(256), 0, st, p, z, rz_new, rz_old, n);
+}
+void launch_vifdu_diag(hipStream_t st, const double* D, const double* W, int64_t n, double* E, double* sw) {
+  hipLaunchKernelGGL(k_vifdu_diag, g1(n), dim3(256), 0, st, D, W, n, E, sw);
+}
+void launch_scale_e(hipStream_t st, const double* v, const double* E, const double* D, int64_t n, double* q,
+                    double* qd) {
+  hipLaunchKernelGGL(k_scale_e, g1(n), dim3(256), 0, st, v, E, D, n, q, qd);
+}
+template <typename T>
+void launch_q_plus_euc(hipStream_t st, const T* U, const double* c, const double* q, const double* E,
+                       const double* D, int64_t n, int mp, double* out) {
+  hipLaunchKernelGGL((k_q_plus_euc<T>), g1(n, 4), dim3(256), 0, st, U, c, q, E, D, n, mp, out);
+}
+template <typename T>
+void launch_wgram_partial(hipStream_t st, const T* U, const double* sw, int64_t n, int mp, int chunk, double* partial,
+                          int* nchunk_out) {
+  const int nchunk = (int)ceil_div(n, chunk);
+  const int nb = (mp + 63) / 64;
+  hipLaunchKernelGGL((k_wgram_partial<T>), dim3(nchunk, nb * (nb + 1) / 2), dim3(256), 0, st, U, sw, n, mp, chunk,
+                     partial);
+  *nchunk_out = nchunk;
+}
+template <typename T>
+void launch_trsv_fwd(hipStream_t st, const int* order, const int* lvl, int nlev, const int32_t* nbr, const T* A,
+                     const double* x, int mv, double* z) {
+  hipLaunchKernelGGL((k_trsv_fwd<T>), dim3(1), dim3(1024), 0, st, order, lvl, nlev, nbr, A, x, mv, z);
+}
+template <typename T>
+void launch_trsv_bwd(hipStream_t st, const int* order, const int* lvl, int nlev, const int* rev_ptr,
+                     const int* rev_idx, const T* A, const double* x, int mv, double* z) {
+  hipLaunchKernelGGL((k_trsv_bwd<T>), dim3(1), dim3(1024), 0, st, order, lvl, nlev, rev_ptr, rev_idx, A, x, mv, z);
+}
+void launch_chol_apply(hipStream_t st, const double* Linv, const double* c, int mp, double* tmp, double* out) {
+  hipLaunchKernelGGL(k_chol_apply, dim3(1), dim3(256), 0, st, Linv, c, mp, tmp, out);
+}
+void launch_axpy(hipStream_t st, double* y, const double* x, const double* eta, int64_t n) {
+  hipLaunchKernelGGL(k_axpy, g1(n), dim3(256), 0, st, y, x, eta, n);
+}
+
+#define INST(T)                                                                                                    \
+  template void launch_bw<T>(hipStream_t, const T*, const double*, const int32_t*, const double*, int64_t, int,    \
+                             double*);                                                                            \
+  template void launch_utv<T>(hipStream_t, const T*, const double*, const double*, int64_t, int, int, double*);   \
+  template void launch_t_minus_uc<T>(hipStream_t, const T*, const double*, const double*, const double*, int64_t, \
+                                     int, double*);                                                               \
+  template void launch_btw<T>(hipStream_t, const T*, const int*, const int*, const double*, const double*,        \
+                              const double*, int64_t, int, double*);                                              \
+  template void launch_q_plus_euc<T>(hipStream_t, const T*, const double*, const double*, const double*,          \
+                                     const double*, int64_t, int, double*);                                       \
+  template void launch_wgram_partial<T>(hipStream_t, const T*, const double*, int64_t, int, int, double*, int*);  \
+  template void launch_trsv_fwd<T>(hipStream_t, const int*, const int*, int, const int32_t*, const T*,            \
+                                   const double*, int, double*);                                                  \
+  template void launch_trsv_bwd<T>(hipStream_t, const int*, const int*, int, const int*, const int*, const T*,    \
+                                   const double*, int, double*);
+INST(double)
+INST(float)

@@ -147,7 +147,7 @@ def test_not_pd_is_reported():
     assert e.value.code == 3 and "point 40" in str(e.value)
 
 
-@pytest.mark.parametrize("n,m,mv,prec", [(400, 20, 8, "fp64"), (1500, 50, 10, "fp64"), (517, 33, 31, "fp64"),
+@pytest.mark.parametrize("n,m,mv,prec", [(400, 20, 8, "fp64"), (1500, 50, 10, "fp64"), (517, 33, 30, "fp64"),
                                          (300, 0, 6, "fp64"), (300, 17, 0, "fp64"), (1500, 50, 10, "fp32")])
 def test_gradient_matches_oracle(n, m, mv, prec):
     """Adjoint gradient (GPU) vs the oracle's forward-mode gradient at a
@@ -175,3 +175,17 @@ def test_gradient_matches_oracle(n, m, mv, prec):
     # a second call on the same factor is bit-identical (no atomics in the sums)
     nll_2, g_2 = ctx.nll_grad(to_dev(y), 3)
     assert nll_2 == nll_g and np.array_equal(g_2, g_g)
+
+
+def test_gradient_rejects_31_neighbours():
+    """The adjoint joins one extra row to the 32-row per-point Gram: m_v <= 30."""
+    from paper_2507_05064_amd.vif import VifError
+    w = vi.scaled(vi.config1(), 100, m=8, m_v=31)
+    X, Z, model = problem(w)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, 31)
+    ctx = _ctx(w)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    with pytest.raises(VifError) as e:
+        ctx.nll_grad(to_dev(np.zeros(100)), 3)
+    assert e.value.code == 1
