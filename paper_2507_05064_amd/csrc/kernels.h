@@ -105,3 +105,8 @@ void launch_trsv_bwd(hipStream_t st, const int* order, const int* lvl, int nlev,
                      const int* rev_idx, const T* A, const double* x, int mv, double* z);
 void launch_chol_apply(hipStream_t st, const double* Linv, const double* c, int mp, double* tmp, double* out);
 void launch_axpy(hipStream_t st, double* y, const double* x, const double* eta, int64_t n);
+
+// mlp.hip
+template <typename T>
+void launch_features(hipStream_t st, const double* y, const T* A, const double* D, const int32_t* nbr, int64_t n,
+                     int mv, double s1, double s2, double log_ls, double* scratch, float* feat);

@@ -38,12 +38,24 @@ class vif_config(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("m", ctypes.c_int32), ("m_v", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("likelihood", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("tau_m", ctypes.c_double), ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
-                ("newton_maxit", ctypes.c_int32), ("newton_tol", ctypes.c_double)]
+                ("newton_maxit", ctypes.c_int32), ("newton_tol", ctypes.c_double), ("lik_param", ctypes.c_double)]
+
+
+class vif_laplace_stats(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int32), ("pcg_iters_total", ctypes.c_int32),
+                ("pcg_iters", ctypes.c_int32 * 64), ("halvings", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("psi", ctypes.c_double), ("pcg_rel_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        k = min(self.newton_iters, 64)
+        return {"newton_iters": self.newton_iters, "pcg_iters_total": self.pcg_iters_total,
+                "pcg_iters": list(self.pcg_iters[:k]), "halvings": self.halvings, "converged": bool(self.converged),
+                "psi": self.psi, "pcg_rel_residual": self.pcg_rel_residual}
 
 
 EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors", "vif_build_factor", "vif_nll",
            "vif_nll_grad", "vif_export_factor", "vif_set_timing", "vif_timing_stages", "vif_timing_stage_name",
-           "vif_get_timing"]
+           "vif_get_timing", "vif_laplace_mode"]
 
 
 def load_library(path: Optional[str] = None):
@@ -80,6 +92,8 @@ def load_library(path: Optional[str] = None):
     lib.vif_timing_stage_name.restype = ctypes.c_char_p
     lib.vif_get_timing.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     lib.vif_get_timing.restype = ctypes.c_int
+    lib.vif_laplace_mode.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vif_laplace_stats)]
+    lib.vif_laplace_mode.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -105,12 +119,13 @@ class VifContext:
 
     def __init__(self, n: int, d: int, m: int, m_v: int, kernel: str = "matern32",
                  likelihood: str = "gaussian", precision: str = "fp64", tau_m: float = 0.0,
-                 cg_tol: float = 1e-6, cg_maxit: int = 1000, newton_maxit: int = 100, newton_tol: float = 1e-9):
+                 cg_tol: float = 1e-6, cg_maxit: int = 1000, newton_maxit: int = 100, newton_tol: float = 1e-9,
+                 lik_param: float = 1.0):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the VIF library has no CPU path")
         self.lib = load_library()
         self.cfg = vif_config(n, d, m, m_v, KERNELS[kernel], LIKELIHOODS[likelihood], PRECISIONS[precision],
-                              tau_m, cg_tol, cg_maxit, newton_maxit, newton_tol)
+                              tau_m, cg_tol, cg_maxit, newton_maxit, newton_tol, lik_param)
         self.stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()
         rc = self.lib.vif_create(ctypes.byref(self.cfg), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
@@ -174,3 +189,12 @@ class VifContext:
         self._check(self.lib.vif_get_timing(self.h, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                             cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k))
         return {self.lib.vif_timing_stage_name(s).decode(): (float(ms[s]), int(cnt[s])) for s in range(k)}
+
+    def laplace_mode(self, y: torch.Tensor, b0: Optional[torch.Tensor] = None, raise_on_error: bool = True):
+        """(mode, stats dict, status code). Raises on error unless raise_on_error is False."""
+        mode = torch.empty(self.n, dtype=torch.float64, device=y.device)
+        st = vif_laplace_stats()
+        rc = self.lib.vif_laplace_mode(self.h, _ptr(y), _ptr(b0), _ptr(mode), ctypes.byref(st))
+        if raise_on_error:
+            self._check(rc)
+        return mode, st.as_dict(), rc

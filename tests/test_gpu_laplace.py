@@ -1,0 +1,96 @@
+"""GPU parity of VIF-Laplace mode finding (Newton + VIFDU-preconditioned CG)
+against the FP64 oracle (Newton with dense Cholesky solves): the mode is
+unique (strictly concave objective), so the converged iterates are compared.
+Both sides run to tight tolerances (CG 1e-12, Newton 1e-14): agreement within
+1e-8 of max|mode|."""
+import numpy as np
+import pytest
+import torch
+from scipy.special import expit
+
+import vif_inputs as vi
+from oracle import laplace_oracle as lo
+from oracle import vif_oracle as vo
+from tests import dense_ref as dr
+from tests.gpu_util import nbr_to_dev, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(lik, n, m, mv, d=2, kernel=vo.MATERN32, ls=(0.15,), seed=3):
+    w = vi.Workload(f"laplace {lik}", 9, n, d, m, mv, kernel, 1.0, np.array(ls, float), 1e-6,
+                    1e-8 if kernel == vo.GAUSSIAN_ARD else 0.0, lik, "kmeanspp" if m >= 20 else "subset")
+    X = vi.coords(w)
+    Z = vi.inducing_points(w, X)
+    model = vo.Model(kernel, 1.0, np.array(ls, float), w.s2, w.tau_m)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, mv)
+    prior = lo.LatentVIF.build(model, X, Z, nbr)
+    C = dr.vif_cov(model, X, Z, nbr, prior.fac.A, prior.fac.D)
+    eps1, eps2, u = vi.prior_noise(w)
+    b = np.linalg.cholesky(C) @ eps2
+    if lik == lo.BERNOULLI_LOGIT:
+        y = vi.bernoulli_from_uniform(expit(b), u)
+    elif lik == lo.POISSON_LOG:
+        y = vi.poisson_from_uniform(np.exp(b), u)
+    else:
+        y = b + 0.5 * eps2[::-1]
+    return w, X, Z, model, nbr, prior, y
+
+
+def _ctx(w, lik, **kw):
+    from paper_2507_05064_amd.vif import VifContext
+    return VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=lik, precision="fp64", tau_m=w.tau_m, **kw)
+
+
+@pytest.mark.parametrize("lik,n,m,mv,d,kernel,ls", [
+    (lo.BERNOULLI_LOGIT, 1200, 30, 10, 5, vo.GAUSSIAN_ARD, (0.2, 0.3, 0.4, 0.5, 0.6)),
+    (lo.BERNOULLI_LOGIT, 900, 0, 8, 2, vo.MATERN32, (0.1,)),
+    (lo.POISSON_LOG, 1000, 25, 12, 2, vo.MATERN12, (0.1,)),
+    (lo.POISSON_LOG, 700, 16, 30, 2, vo.MATERN32, (0.1,)),
+])
+def test_mode_matches_oracle(lik, n, m, mv, d, kernel, ls):
+    w, X, Z, model, nbr, prior, y = _problem(lik, n, m, mv, d, kernel, ls)
+    print(f"[gpu] laplace {lik} n={n} m={m} m_v={mv}", flush=True)
+    ref = lo.find_mode(prior, lik, y, tol=1e-14, solver="dense")
+    ctx = _ctx(w, lik, cg_tol=1e-12, cg_maxit=5000, newton_tol=1e-14)
+    ctx.build_factor(to_dev(X), to_dev(Z) if m else None, nbr_to_dev(nbr), w.theta)
+    mode, st, _ = ctx.laplace_mode(to_dev(y))
+    mode = mode.cpu().numpy()
+    err = np.max(np.abs(mode - ref.mode)) / np.max(np.abs(ref.mode))
+    assert err <= 1e-8, (err, st)
+    assert st["converged"] and st["pcg_iters_total"] > 0
+    assert abs(st["psi"] - ref.psi) <= 1e-9 * abs(ref.psi)
+
+
+def test_gaussian_likelihood_one_newton_step_gives_posterior_mean():
+    w, X, Z, model, nbr, prior, y = _problem(lo.GAUSSIAN, 600, 20, 10)
+    s2 = 0.25
+    C = dr.vif_cov(model, X, Z, nbr, prior.fac.A, prior.fac.D)
+    ref = C @ np.linalg.solve(C + s2 * np.eye(len(C)), y)
+    ctx = _ctx(w, "gaussian", cg_tol=1e-13, cg_maxit=5000, newton_tol=1e-15, newton_maxit=1, lik_param=s2)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    mode, st, rc = ctx.laplace_mode(to_dev(y), raise_on_error=False)
+    assert st["newton_iters"] == 1
+    np.testing.assert_allclose(mode.cpu().numpy(), ref, atol=1e-8 * np.max(np.abs(ref)))
+
+
+def test_cg_iteration_limit_is_reported():
+    from paper_2507_05064_amd.vif import VifError
+    w, X, Z, model, nbr, prior, y = _problem(lo.BERNOULLI_LOGIT, 400, 10, 6)
+    ctx = _ctx(w, lo.BERNOULLI_LOGIT, cg_tol=1e-14, cg_maxit=2)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    mode, st, rc = ctx.laplace_mode(to_dev(y), raise_on_error=False)
+    assert rc == 4 and st["newton_iters"] == 1
+    assert np.all(np.isfinite(mode.cpu().numpy()))
+
+
+def test_warm_start_at_the_mode_converges_in_one_step():
+    w, X, Z, model, nbr, prior, y = _problem(lo.BERNOULLI_LOGIT, 800, 20, 10)
+    ref = lo.find_mode(prior, lo.BERNOULLI_LOGIT, y, tol=1e-14, solver="dense")
+    ctx = _ctx(w, lo.BERNOULLI_LOGIT, cg_tol=1e-12, cg_maxit=5000, newton_tol=1e-12)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    mode, st, _ = ctx.laplace_mode(to_dev(y), to_dev(ref.mode))
+    assert st["newton_iters"] == 1 and st["converged"]
+    _, st0, _ = ctx.laplace_mode(to_dev(y))
+    assert st0["newton_iters"] > 1
