@@ -11,6 +11,14 @@ paper, neighbour selection is not part of a likelihood evaluation).
 
 Prints one JSON line. ``value`` is FP32-form evaluations per second; the
 FP64 form is reported beside it under "fp64".
+
+Second leg ("laplace"): Laplace mode finding for a Bernoulli-logit latent VIF
+model at n = 200,000 in [0,1]^5 (ARD Gaussian kernel, length scales
+0.2..0.6, m = 500 kMeans++ inducing points, m_v = 30), Newton with
+VIFDU-preconditioned CG to relative residual 1e-6, from the zero start and
+from the learned warm start (feature and network time included). The network
+is trained before the timed region on modes the method computes for three
+other problems of the same shape.
 """
 import argparse
 import json
@@ -71,6 +79,73 @@ def run_form(w, Xd, Zd, nbr, yd, precision, steps, warmup, grad):
                 stages={k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1] > 0})
 
 
+def _pct(v, q):
+    return float(np.percentile(np.asarray(v), q))
+
+
+def laplace_leg(reps, warmup, log):
+    """Mode time and iterations, zero start vs learned warm start (FP64)."""
+    import torch
+    import vif_inputs as vi
+    from paper_2507_05064_amd import warmstart as ws
+    w = vi.config3()
+    t0 = time.perf_counter()
+    train = [ws.make_problem(w, p, theta_scale=sc) for p, sc in ((11, (0.8, 1.1)), (12, (1.25, 0.9)), (13, (1.0, 1.0)))]
+    feat, target = ws.training_pairs(train, cg_tol=1e-8)
+    del train
+    log(f"laplace: {feat.shape[0]} training pairs in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    mlp = ws.train(feat, target, epochs=20)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del feat, target
+    prob = ws.make_problem(w, 0)
+    ctx = ws.context_for(prob, cg_tol=1e-6)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    build_ms = []
+    for r in range(warmup + reps):
+        ev[0].record()
+        ctx.build_factor(prob.X, prob.Z, prob.nbr, prob.theta)
+        ev[1].record()
+        torch.cuda.synchronize()
+        if r >= warmup:
+            build_ms.append(ev[0].elapsed_time(ev[1]))
+    out = {}
+    modes = {}
+    for form in ("zero", "warm"):
+        ms, st = [], None
+        for r in range(warmup + reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if form == "zero":
+                mode, st, _ = ctx.laplace_mode(prob.y)
+            else:
+                b0 = mlp.forward(ctx.mlp_features(prob.y), double=True)
+                mode, st, _ = ctx.laplace_mode(prob.y, b0)
+            torch.cuda.synchronize()
+            if r >= warmup:
+                ms.append(1000.0 * (time.perf_counter() - t0))
+        modes[form] = mode
+        out[form] = {"mode_ms_median": _pct(ms, 50), "mode_ms_p10": _pct(ms, 10), "mode_ms_p90": _pct(ms, 90),
+                     "newton_iters": st["newton_iters"], "pcg_iters_total": st["pcg_iters_total"],
+                     "pcg_iters": st["pcg_iters"], "halvings": st["halvings"], "start_used": st["start_used"],
+                     "psi": st["psi"]}
+        log(f"laplace {form}: {out[form]}")
+    b0 = mlp.forward(ctx.mlp_features(prob.y), double=True)
+    ref = modes["zero"]
+    out["net_rel_err"] = float(torch.linalg.norm(b0 - ref) / torch.linalg.norm(ref))
+    out["mode_rel_diff"] = float(torch.linalg.norm(modes["warm"] - ref) / torch.linalg.norm(ref))
+    out["speedup_warm_vs_zero"] = out["zero"]["mode_ms_median"] / out["warm"]["mode_ms_median"]
+    out["factor_build_ms_median"] = _pct(build_ms, 50)
+    out["mlp_train_s"] = train_s
+    out["reps"] = reps
+    out["workload"] = (f"Bernoulli-logit latent VIF: n={w.n} d={w.d} ARD Gaussian (var 1, length scales "
+                       f"0.2..0.6), m={w.m} kMeans++ inducing points, m_v={w.m_v}, b from the VIF prior, "
+                       f"Newton + VIFDU-PCG (tol 1e-6), FP64")
+    ctx.close()
+    return out
+
+
 def cpu_baseline(w, budget_points=6000):
     """Oracle (FP64 numpy) NLL + forward-mode gradient on the first
     `budget_points` points of the same workload (the prefix is itself a VIF
@@ -105,6 +180,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nll-only", action="store_true", help="time the NLL without the gradient")
+    ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace mode leg")
+    ap.add_argument("--laplace-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -126,10 +203,13 @@ def main():
     torch.cuda.synchronize()
     knn_s = time.perf_counter() - t0
     sel.close()
-    # response: iid N(0, sigma1^2 + nugget) draws (the cost of an evaluation
-    # does not depend on the values of y)
-    y = vi.normals(w, w.n) * math.sqrt(w.sigma1_sq + w.s2)
-    yd = torch.as_tensor(y, device="cuda")
+    # response: a draw from the VIF prior at the true parameters,
+    # y = V^T eps1 + B^{-1} D^{1/2} eps2 with the nugget inside D
+    samp = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, precision="fp64", tau_m=w.tau_m)
+    samp.build_factor(Xd, Zd, nbr, w.theta)
+    eps1, eps2, _ = vi.prior_noise(w)
+    yd = samp.sample_prior(torch.as_tensor(eps1, device="cuda"), torch.as_tensor(eps2, device="cuda"))
+    samp.close()
     grad = not args.nll_only
 
     r32 = run_form(w, Xd, Zd, nbr, yd, "fp32", args.steps, args.warmup, grad)
@@ -166,6 +246,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": nbytes, "avg_launch_ms": fac_ms},
     }
+    if not args.no_laplace:
+        res["laplace"] = laplace_leg(args.laplace_reps, 1, lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res))

@@ -86,6 +86,8 @@ typedef struct {
   int32_t converged;        /* 1 when the Newton stopping rule was met */
   double psi;               /* final objective log p(y|b) - b^T Sigma_dagger^{-1} b / 2 */
   double pcg_rel_residual;  /* relative residual of the last CG solve */
+  int32_t start_used;       /* 1: the given start b0 was kept; 0: the zero start */
+  double psi_start;         /* objective at the start used */
 } vif_laplace_stats;
 
 typedef struct vif_ctx vif_ctx;
@@ -136,12 +138,52 @@ vif_status vif_nll_grad(vif_ctx* ctx, const double* y, double* nll_out, double* 
  * the objective would decrease; stop when |Psi_{t+1} - Psi_t| <=
  * cfg.newton_tol (1 + |Psi_{t+1}|). Each linear system is solved by
  * conjugate gradients on eq. pcls1 with the VIFDU preconditioner (Sec. 4.3.1,
- * App. E.1), from x_0 = 0, to ||r|| <= cfg.cg_tol ||rhs||. y, b0 (start;
- * NULL = 0) and mode_out are device arrays of n doubles; st is a host
- * pointer (may be NULL). On VIF_E_NEWTON / VIF_E_CG_MAXIT, mode_out still
+ * App. E.1). CG works on the direct form (unknown b_{t+1}, right-hand side
+ * W b_t + g(b_t)), starts from whichever of b_t and 0 has the smaller
+ * residual, and stops at ||r|| <= cfg.cg_tol ||W b_t + g(b_t)||. y, b0
+ * (start; NULL = 0) and mode_out are device arrays of n doubles; st is a
+ * host pointer (may be NULL). A given start b0 is kept when the first
+ * Newton step from it ends with a higher objective than Psi(0); otherwise
+ * the search restarts from zero (the fallback). The converged mode does not
+ * depend on the start. On VIF_E_NEWTON / VIF_E_CG_MAXIT, mode_out still
  * holds the last iterate and st the history. */
 vif_status vif_laplace_mode(vif_ctx* ctx, const double* y, const double* b0, double* mode_out,
                             vif_laplace_stats* st);
+
+/* A draw from the VIF prior N(0, Sigma_dagger) of the last build:
+ * b = V^T eps1 + B^{-1} D^{1/2} eps2 (the predictive-process part through the
+ * whitened features, V^T eps1 = Sigma_mn^T Sigma_m^{-1} L_m eps1, plus the
+ * residual Vecchia part; Sec. 2.1 and the sampling remark of Sec. 4.3.1).
+ * eps1 (m), eps2 (n) and b_out (n) are device arrays of doubles. */
+vif_status vif_sample_prior(vif_ctx* ctx, const double* eps1, const double* eps2, double* b_out);
+
+/* Warm-start network (not in the paper; its output only seeds the Newton
+ * iterations of vif_laplace_mode, whose converged mode it cannot change).
+ * A fully connected network F -> H -> H -> H -> 1 with ReLU hidden layers,
+ * FP32, parameters in one flat device array: W1 (F x H), b1 (H), W2 (H x H),
+ * b2, W3 (H x H), b3, w4 (H), b4 (1), row-major (input index first).
+ * 16 <= H <= 512, 1 <= F <= 64. Device pointers throughout; `stream` is a
+ * HIP stream (NULL = default). ws: device workspace of
+ * vif_mlp_workspace_floats(n, F, H) floats. */
+int64_t vif_mlp_num_params(int32_t F, int32_t H);
+int64_t vif_mlp_workspace_floats(int64_t n, int32_t F, int32_t H);
+/* out (float, n) and/or out64 (double, n; either may be NULL) = network(X),
+ * X is n x F row-major. */
+vif_status vif_mlp_forward(const float* params, const float* X, int64_t n, int32_t F, int32_t H, float* ws,
+                           float* out, double* out64, void* stream);
+/* grad (P floats) = d/dparams of mean_i (network(X)_i - target_i)^2;
+ * loss_out (host, may be NULL) = that mean (synchronises the stream). */
+vif_status vif_mlp_backward(const float* params, const float* X, const float* target, int64_t n, int32_t F,
+                            int32_t H, float* ws, float* grad, double* loss_out, void* stream);
+/* One Adam step (bias-corrected, step >= 1) on params with moments m, v. */
+vif_status vif_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t P, float lr, float beta1,
+                        float beta2, float eps, int32_t step, void* stream);
+/* Per-point network inputs (F = 16, n x 16 floats) from y and the factor of
+ * the last build: y_i, the mean of y over N(i), sum_j A_ij y_j, sum_j A_ij,
+ * log D_i, D_i / (sigma1^2 + s2), |N(i)| / m_v, log sigma1^2, log of the
+ * mean length scale, the mean of y, the mean over N(i) of the second
+ * feature, y_i minus the second feature, then zeros. */
+vif_status vif_mlp_features(vif_ctx* ctx, const double* y, float* feat_out);
 
 /* Copies the factor of the last build to device buffers A_out (n x m_v, the
  * coefficients A_i over N(i), zero padded) and D_out (n), both double. */

@@ -264,7 +264,7 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
     alloc((void**)&c->M3inv, sizeof(double) * mpa * mpa);
     alloc((void**)&c->L3inv, sizeof(double) * mpa * mpa);
     alloc((void**)&c->lsc, sizeof(double) * 64);
-    alloc((void**)&c->lpart, sizeof(double) * (ceil_div(n, 256) + ceil_div(n, 2048) * 2 + (size_t)c->nchunk * mpa + 64));
+    alloc((void**)&c->lpart, sizeof(double) * (3 * ceil_div(n, 256) + ceil_div(n, 2048) * 2 + (size_t)c->nchunk * mpa + 64));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->hlsc, sizeof(double) * 64, 0);
   }
   for (int t = 0; t < ST_COUNT && e == hipSuccess; ++t) {
@@ -643,7 +643,7 @@ static LapBufs lap_bufs(vif_ctx* c) {
   B.ctmp = c->lm + 2 * mpa;
   B.sc = c->lsc;
   B.part = c->lpart;
-  B.upart = c->lpart + ceil_div(n, 256) + ceil_div(n, 2048) * 2 + 16;
+  B.upart = c->lpart + 3 * ceil_div(n, 256) + ceil_div(n, 2048) * 2 + 16;
   return B;
 }
 
@@ -678,6 +678,10 @@ static void vifdu_apply(vif_ctx* c, LapBufs& B, const double* r, double* z) {
 }
 
 __global__ void k_copy_scalar(double* dst, const double* src) { dst[0] = src[0]; }
+__global__ void k_neg(double* out, const double* a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = -a[i];
+}
 __global__ void k_sub(double* out, const double* a, const double* b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a[i] - b[i];
@@ -698,25 +702,41 @@ __global__ void k_sum_part(const double* part, int nb, double* out) {
   }
 }
 
-// Preconditioned CG for (W + Sigma_dagger^{-1}) x = rhs, x0 = 0.
+// Preconditioned CG for the Newton increment (W + Sigma_dagger^{-1}) x = g - Sigma_dagger^{-1} b
+// (B.rhs). In the direct form of eq. one_it_newton_mode the unknown is b + x
+// with right-hand side W b + g; CG starts from whichever of b (x = 0) and 0
+// (x = -b) leaves the smaller residual, and stops at
+// ||r|| <= cg_tol ||W b + g||, so late Newton steps, whose increments are
+// small, cost few iterations. The zero guess wins when b is far from smooth
+// (a learned start), the guess b once b is an earlier Newton iterate.
 template <typename T>
 static vif_status pcg(vif_ctx* c, LapBufs& B, int* iters, double* relres) {
   const vif_config& g = c->cfg;
   const int64_t n = g.n;
   double* dpart = B.part + ceil_div(n, 256);
-  HIPCHK(c, hipMemsetAsync(B.x, 0, sizeof(double) * n, c->st));
-  HIPCHK(c, hipMemcpyAsync(B.r, B.rhs, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  launch_direct_rhs(c->st, B.W, B.b, B.g, n, B.tmp);
+  launch_dot2(c->st, B.rhs, B.rhs, B.tmp, B.tmp, n, dpart, B.sc + 10);
+  vif_status s = read_scalars(c, 12);
+  if (s) return s;
+  const double inc2 = c->hlsc[10], dir2 = c->hlsc[11];
+  if (inc2 <= dir2) {
+    HIPCHK(c, hipMemsetAsync(B.x, 0, sizeof(double) * n, c->st));
+    HIPCHK(c, hipMemcpyAsync(B.r, B.rhs, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  } else {
+    hipLaunchKernelGGL(k_neg, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->st, B.x, B.b, n);
+    HIPCHK(c, hipMemcpyAsync(B.r, B.tmp, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  }
   vifdu_apply<T>(c, B, B.r, B.z);
   HIPCHK(c, hipMemcpyAsync(B.p, B.z, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
   launch_dot2(c->st, B.r, B.z, B.r, B.r, n, dpart, B.sc + 3);
   hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, c->st, B.sc, B.sc + 3);
-  vif_status s = read_scalars(c, 5);
-  if (s) return s;
+  if ((s = read_scalars(c, 5))) return s;
   const double rr0 = c->hlsc[4];
-  const double thr = g.cg_tol * g.cg_tol * rr0;
+  const double ref2 = dir2 > 0.0 ? dir2 : rr0;
+  const double thr = g.cg_tol * g.cg_tol * ref2;
   *iters = 0;
-  *relres = 0.0;
-  if (!(rr0 > 0.0)) return VIF_OK;
+  *relres = ref2 > 0.0 ? sqrt(rr0 / ref2) : 0.0;
+  if (!(rr0 > thr)) return VIF_OK;
   const int check = 4;
   for (int it = 1; it <= g.cg_maxit; ++it) {
     prec_matvec<T>(c, B, B.p, B.W, B.Ap);
@@ -732,7 +752,7 @@ static vif_status pcg(vif_ctx* c, LapBufs& B, int* iters, double* relres) {
       const double rr = c->hlsc[4];
       if (!isfinite(rr)) return fail(c, VIF_E_NAN, "conjugate gradients: non-finite residual at iteration %d", it);
       *iters = it;
-      *relres = sqrt(rr / rr0);
+      *relres = sqrt(rr / ref2);
       if (rr <= thr) return VIF_OK;
     }
   }
@@ -751,18 +771,39 @@ static vif_status laplace_impl(vif_ctx* c, const double* y, const double* b0, do
   if (s) return s;
   vif_laplace_stats S{};
   if (g.m > 0) launch_gemm_sq(c->st, c->LMinv, c->LMinv, c->Minv, mp, true, false);
-  if (b0) HIPCHK(c, hipMemcpyAsync(B.b, b0, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
-  else HIPCHK(c, hipMemsetAsync(B.b, 0, sizeof(double) * n, c->st));
   const int nlb = (int)ceil_div(n, 256);
   double* dpart = B.part + nlb;
-  // Psi at the start
-  prec_matvec<T>(c, B, B.b, nullptr, B.sb);
+  // Psi at the zero start (prior term 0)
+  HIPCHK(c, hipMemsetAsync(B.b, 0, sizeof(double) * n, c->st));
+  HIPCHK(c, hipMemsetAsync(B.sb, 0, sizeof(double) * n, c->st));
   launch_lik(c->st, g.likelihood, g.lik_param, y, B.b, n, B.g, B.W, B.part);
   hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, B.part, nlb, B.sc + 9);
-  launch_dot2(c->st, B.b, B.sb, nullptr, nullptr, n, dpart, B.sc + 7);
   if ((s = read_scalars(c, 10))) return s;
-  double psi_cur = c->hlsc[9] - 0.5 * c->hlsc[7];
-  double bsb = c->hlsc[7];
+  const double psi_zero = c->hlsc[9];
+  double psi_cur = psi_zero;
+  double bsb = 0.0;
+  S.start_used = 0;
+  if (b0) {
+    // a given start: Psi(b0) = log p(y | b0) - b0^T Sigma^{-1} b0 / 2. It is kept
+    // if one Newton step from it ends above Psi(0) (checked after that step).
+    prec_matvec<T>(c, B, b0, nullptr, B.sd);
+    launch_dot2(c->st, b0, B.sd, nullptr, nullptr, n, dpart, B.sc + 7);
+    launch_lik(c->st, g.likelihood, g.lik_param, y, b0, n, B.g, B.W, B.part);
+    hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, B.part, nlb, B.sc + 9);
+    if ((s = read_scalars(c, 10))) return s;
+    const double q = c->hlsc[7], psi_b0 = c->hlsc[9] - 0.5 * q;
+    S.psi_start = psi_b0;
+    if (isfinite(psi_b0)) {
+      S.start_used = 1;
+      psi_cur = psi_b0;
+      bsb = q;
+      HIPCHK(c, hipMemcpyAsync(B.b, b0, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+      HIPCHK(c, hipMemcpyAsync(B.sb, B.sd, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+    } else {
+      launch_lik(c->st, g.likelihood, g.lik_param, y, B.b, n, B.g, B.W, B.part);
+    }
+  }
+  if (!S.start_used) S.psi_start = psi_zero;
   if (!isfinite(psi_cur)) return fail(c, VIF_E_NAN, "Laplace objective not finite at the start");
   bool converged = false;
   for (int t = 1; t <= g.newton_maxit; ++t) {
@@ -811,6 +852,17 @@ static vif_status laplace_impl(vif_ctx* c, const double* y, const double* b0, do
       eta *= 0.5;
     }
     S.halvings += h;
+    if (t == 1 && S.start_used && !(psi_new > psi_zero)) {
+      // the given start did worse than zero after one step: restart from zero
+      S.start_used = 0;
+      S.psi_start = psi_zero;
+      psi_cur = psi_zero;
+      bsb = 0.0;
+      HIPCHK(c, hipMemsetAsync(B.b, 0, sizeof(double) * n, c->st));
+      HIPCHK(c, hipMemsetAsync(B.sb, 0, sizeof(double) * n, c->st));
+      launch_lik(c->st, g.likelihood, g.lik_param, y, B.b, n, B.g, B.W, B.part);
+      continue;
+    }
     launch_axpy(c->st, B.b, B.x, B.sc + 6, n);
     launch_axpy(c->st, B.sb, B.sd, B.sc + 6, n);
     launch_lik(c->st, g.likelihood, g.lik_param, y, B.b, n, B.g, B.W, B.part);
@@ -832,6 +884,79 @@ static vif_status laplace_impl(vif_ctx* c, const double* y, const double* b0, do
 }
 
 extern "C" {
+
+vif_status vif_sample_prior(vif_ctx* c, const double* eps1, const double* eps2, double* b_out) {
+  if (!c) return VIF_E_ARG;
+  if (!c->built) return fail(c, VIF_E_STATE, "vif_sample_prior before a successful vif_build_factor");
+  const vif_config& g = c->cfg;
+  if (!eps2 || !b_out || (g.m > 0 && !eps1)) return fail(c, VIF_E_ARG, "NULL eps1, eps2 or b_out");
+  vif_status s = ensure_schedules(c);
+  if (s) return s;
+  LapBufs B = lap_bufs(c);
+  launch_sqrtd_scale(c->st, c->D, eps2, g.n, B.t);
+  if (fp32_form(c)) {
+    launch_trsv_fwd<float>(c->st, c->fwd_order, c->fwd_lvl, c->nlev_f, c->nbr, (const float*)c->A, B.t, g.m_v, B.s);
+    launch_add_ve<float>(c->st, c->Vf, eps1, B.s, g.n, g.m > 0 ? c->mp : 0, b_out);
+  } else {
+    launch_trsv_fwd<double>(c->st, c->fwd_order, c->fwd_lvl, c->nlev_f, c->nbr, (const double*)c->A, B.t, g.m_v,
+                            B.s);
+    launch_add_ve<double>(c->st, c->Vd, eps1, B.s, g.n, g.m > 0 ? c->mp : 0, b_out);
+  }
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return VIF_OK;
+}
+
+vif_status vif_mlp_features(vif_ctx* c, const double* y, float* feat_out) {
+  if (!c) return VIF_E_ARG;
+  if (!c->built) return fail(c, VIF_E_STATE, "vif_mlp_features before a successful vif_build_factor");
+  if (!y || !feat_out) return fail(c, VIF_E_ARG, "NULL y or feat_out");
+  const vif_config& g = c->cfg;
+  double lls = 0.0;
+  const int L = (g.kernel == VIF_GAUSSIAN_ARD) ? g.d : 1;
+  for (int k = 0; k < L; ++k) lls += 1.0 / c->cp.inv_ls[k];
+  lls = log(lls / L);
+  // low-rank smoother: s = V^T (I + W0 V V^T)^{-1} V (y - p0), the posterior
+  // mean of b_l ~ N(0, V^T V) under the likelihood's Gaussian approximation
+  // at b = 0 (gradient y - p0, curvature W0)
+  const double p0 = (g.likelihood == VIF_LIK_BERNOULLI_LOGIT) ? 0.5 : (g.likelihood == VIF_LIK_POISSON_LOG ? 1.0 : 0.0);
+  const double W0 = (g.likelihood == VIF_LIK_BERNOULLI_LOGIT) ? 0.25
+                    : (g.likelihood == VIF_LIK_POISSON_LOG ? 1.0 : 1.0 / g.lik_param);
+  LapBufs B = lap_bufs(c);
+  const double* smooth = nullptr;
+  const bool f32 = fp32_form(c);
+  if (g.m > 0) {
+    const int mp = c->mp;
+    int nchunk = 0;
+    if (f32)
+      launch_gram_partial<float>(c->st, c->Vf, g.n, mp, c->chunk, c->partial, &nchunk);
+    else
+      launch_gram_partial<double>(c->st, c->Vd, g.n, mp, c->chunk, c->partial, &nchunk);
+    launch_reduce_gram(c->st, c->partial, nchunk, mp, c->M3, W0);
+    launch_chol_inv(c->st, c->M3, c->L3inv, c->Mwork, g.m, mp, B.sc + 12, c->status, 3);
+    launch_gemm_sq(c->st, c->L3inv, c->L3inv, c->M3inv, mp, true, false);
+    launch_shift(c->st, y, p0, g.n, B.tmp);
+    if (f32)
+      launch_utv<float>(c->st, c->Vf, B.tmp, nullptr, g.n, mp, c->chunk, B.upart);
+    else
+      launch_utv<double>(c->st, c->Vd, B.tmp, nullptr, g.n, mp, c->chunk, B.upart);
+    launch_reduce_apply(c->st, B.upart, c->nchunk, mp, c->M3inv, B.cbuf, B.cp);
+    HIPCHK(c, hipMemsetAsync(B.q, 0, sizeof(double) * g.n, c->st));
+    if (f32)
+      launch_add_ve<float>(c->st, c->Vf, B.cp, B.q, g.n, mp, B.q2);
+    else
+      launch_add_ve<double>(c->st, c->Vd, B.cp, B.q, g.n, mp, B.q2);
+    smooth = B.q2;
+  }
+  if (f32)
+    launch_features<float>(c->st, y, (const float*)c->A, c->D, c->nbr, smooth, g.n, g.m_v, c->cp.sigma1_sq, c->cp.s2,
+                           lls, c->lpart, feat_out);
+  else
+    launch_features<double>(c->st, y, (const double*)c->A, c->D, c->nbr, smooth, g.n, g.m_v, c->cp.sigma1_sq,
+                            c->cp.s2, lls, c->lpart, feat_out);
+  HIPCHK(c, hipGetLastError());
+  return VIF_OK;
+}
 
 vif_status vif_laplace_mode(vif_ctx* c, const double* y, const double* b0, double* mode_out, vif_laplace_stats* st) {
   if (!c) return VIF_E_ARG;

@@ -256,17 +256,17 @@ __global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double
   }
 }
 
-// M' = I + sum_chunks partial over the lower triangle (every entry c <= l is
+// M' = I + scale * sum_chunks partial over the lower triangle (every entry c <= l is
 // written by k_gram_partial) -- one thread per element.
-__global__ void k_reduce_gram(const double* partial, int nchunk, int mp, double* Mp) {
+__global__ void k_reduce_gram(const double* partial, int nchunk, int mp, double scale, double* Mp) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)mp * mp) return;
   const int l = (int)(q / mp), c = (int)(q % mp);
-  double s = (l == c) ? 1.0 : 0.0;
+  double s = 0.0;
   if (c <= l) {
     for (int k = 0; k < nchunk; ++k) s += partial[(size_t)k * mp * mp + q];
   }
-  Mp[q] = s;
+  Mp[q] = ((l == c) ? 1.0 : 0.0) + scale * s;
 }
 
 // Final Gaussian NLL. vec[0..mp) holds U^T yt, scal[0] = sum log D,
@@ -298,9 +298,10 @@ void launch_chol_inv(hipStream_t st, double* S, double* Linv, double* work, int 
                      int code) {
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(CWG), 0, st, S, Linv, work, m, mp, out, status, code);
 }
-void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp) {
+void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp, double scale) {
   const int64_t total = (int64_t)mp * mp;
-  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, partial, nchunk, mp, Mp);
+  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, partial, nchunk, mp, scale,
+                     Mp);
 }
 void launch_nll_final(hipStream_t st, const double* LMinv, const double* vec, const double* scal, int m, int mp,
                       const double* logdet_mprime, int64_t n, double* out) {

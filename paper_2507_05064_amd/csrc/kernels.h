@@ -6,7 +6,7 @@
 void launch_cov_zz(hipStream_t st, const double* Z, int m, int mp, const CovParams& p, double tau_m, double* S);
 void launch_chol_inv(hipStream_t st, double* S, double* Linv, double* work, int m, int mp, double* out, int* status,
                      int code);
-void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp);
+void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp, double scale = 1.0);
 void launch_nll_final(hipStream_t st, const double* LMinv, const double* vec, const double* scal, int m, int mp,
                       const double* logdet_mprime, int64_t n, double* out);
 
@@ -108,5 +108,12 @@ void launch_axpy(hipStream_t st, double* y, const double* x, const double* eta, 
 
 // mlp.hip
 template <typename T>
-void launch_features(hipStream_t st, const double* y, const T* A, const double* D, const int32_t* nbr, int64_t n,
-                     int mv, double s1, double s2, double log_ls, double* scratch, float* feat);
+void launch_features(hipStream_t st, const double* y, const T* A, const double* D, const int32_t* nbr,
+                     const double* smooth, int64_t n, int mv, double s1, double s2, double log_ls, double* scratch,
+                     float* feat);
+void launch_shift(hipStream_t st, const double* y, double p0, int64_t n, double* out);
+void launch_sqrtd_scale(hipStream_t st, const double* D, const double* e, int64_t n, double* t);
+template <typename T>
+void launch_add_ve(hipStream_t st, const T* V, const double* e1, const double* r, int64_t n, int mp, double* b);
+void launch_direct_rhs(hipStream_t st, const double* W, const double* b, const double* g, int64_t n,
+                       double* out);

@@ -67,6 +67,13 @@ __global__ __launch_bounds__(256) void k_lik_at(int lik, double lpar, const doub
   if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// Right-hand side of the Newton system in direct form: W b + d log p / d b
+__global__ void k_direct_rhs(const double* __restrict__ W, const double* __restrict__ b,
+                             const double* __restrict__ g, int64_t n, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = W[i] * b[i] + g[i];
+}
+
 // t = D^{-1/2} B w :  t_i = (w_i - sum_j A_ij w_{N(i)_j}) / sqrt(D_i)
 template <typename T>
 __global__ void k_bw(const T* __restrict__ A, const double* __restrict__ D, const int32_t* __restrict__ nbr,
@@ -351,6 +358,27 @@ __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, con
   if (i < n) y[i] += eta[0] * x[i];
 }
 
+// t_i = sqrt(D_i) e_i
+__global__ void k_sqrtd_scale(const double* __restrict__ D, const double* __restrict__ e, int64_t n,
+                              double* __restrict__ t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = sqrt(D[i]) * e[i];
+}
+
+// b_i = r_i + V_i . e1  (one wave per point)
+template <typename T>
+__global__ __launch_bounds__(256) void k_add_ve(const T* __restrict__ V, const double* __restrict__ e1,
+                                                const double* __restrict__ r, int64_t n, int mp,
+                                                double* __restrict__ b) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  double s = 0.0;
+  for (int l = lane; l < mp; l += 64) s += (double)V[(size_t)i * mp + l] * e1[l];
+  s = wave_sum(s);
+  if (lane == 0) b[i] = r[i] + s;
+}
+
 // ---------------------------------------------------------------------------
 static inline dim3 g1(int64_t n, int bs = 256) { return dim3((unsigned)ceil_div(n, bs)); }
 
@@ -439,6 +467,21 @@ void launch_chol_apply(hipStream_t st, const double* Linv, const double* c, int 
 void launch_axpy(hipStream_t st, double* y, const double* x, const double* eta, int64_t n) {
   hipLaunchKernelGGL(k_axpy, g1(n), dim3(256), 0, st, y, x, eta, n);
 }
+
+void launch_direct_rhs(hipStream_t st, const double* W, const double* b, const double* g, int64_t n,
+                       double* out) {
+  hipLaunchKernelGGL(k_direct_rhs, g1(n), dim3(256), 0, st, W, b, g, n, out);
+}
+
+void launch_sqrtd_scale(hipStream_t st, const double* D, const double* e, int64_t n, double* t) {
+  hipLaunchKernelGGL(k_sqrtd_scale, g1(n), dim3(256), 0, st, D, e, n, t);
+}
+template <typename T>
+void launch_add_ve(hipStream_t st, const T* V, const double* e1, const double* r, int64_t n, int mp, double* b) {
+  hipLaunchKernelGGL((k_add_ve<T>), g1(n, 4), dim3(256), 0, st, V, e1, r, n, mp, b);
+}
+template void launch_add_ve<double>(hipStream_t, const double*, const double*, const double*, int64_t, int, double*);
+template void launch_add_ve<float>(hipStream_t, const float*, const double*, const double*, int64_t, int, double*);
 
 #define INST(T)                                                                                                    \
   template void launch_bw<T>(hipStream_t, const T*, const double*, const int32_t*, const double*, int64_t, int,    \

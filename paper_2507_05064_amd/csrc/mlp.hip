@@ -173,11 +173,15 @@ __global__ void k_sum_d(const double* part, int nb, double* out) {
 //  0 y_i, 1 mean of y over N(i), 2 sum_j A_ij y_j, 3 sum_j A_ij, 4 log D_i,
 //  5 D_i / (sigma1^2 + s2), 6 |N(i)| / m_v, 7 log sigma1^2, 8 log of the mean
 //  length scale, 9 mean of y over all points, 10 (second pass) mean over N(i)
-//  of feature 1, 11 y_i - feature 1, 12..15 zero.
+//  of feature 1, 11 y_i - feature 1, 12 a low-rank smoother of y (the
+//  posterior mean of the inducing-point part of the prior under the
+//  likelihood's Gaussian approximation at b = 0), 13 (second pass)
+//  sum_j A_ij times feature 12 of N(i)_j, 14..15 zero.
 template <typename T>
 __global__ void k_features1(const double* __restrict__ y, const T* __restrict__ A, const double* __restrict__ D,
-                            const int32_t* __restrict__ nbr, const double* __restrict__ ymean, int64_t n, int mv,
-                            double s1, double s2, double log_ls, float* __restrict__ feat) {
+                            const int32_t* __restrict__ nbr, const double* __restrict__ ymean,
+                            const double* __restrict__ smooth, int64_t n, int mv, double s1, double s2, double log_ls,
+                            float* __restrict__ feat) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double sy = 0.0, sa = 0.0, say = 0.0;
@@ -204,21 +208,26 @@ __global__ void k_features1(const double* __restrict__ y, const T* __restrict__ 
   f[8] = (float)log_ls;
   f[9] = (float)ymean[0];
   f[11] = (float)(y[i] - ym);
-  f[12] = f[13] = f[14] = f[15] = 0.f;
+  f[12] = smooth ? (float)smooth[i] : 0.f;
+  f[13] = f[14] = f[15] = 0.f;
 }
 
-__global__ void k_features2(const int32_t* __restrict__ nbr, int64_t n, int mv, float* __restrict__ feat) {
+template <typename T>
+__global__ void k_features2(const int32_t* __restrict__ nbr, const T* __restrict__ A, int64_t n, int mv,
+                            float* __restrict__ feat) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float s = 0.f;
+  float s = 0.f, sa = 0.f;
   int k = 0;
   for (int a = 0; a < mv; ++a) {
     const int j = nbr[i * mv + a];
     if (j < 0) continue;
     s += feat[(int64_t)j * 16 + 1];
+    sa += (float)A[i * mv + a] * feat[(int64_t)j * 16 + 12];
     ++k;
   }
   feat[i * 16 + 10] = k ? s / k : 0.f;
+  feat[i * 16 + 13] = sa;
 }
 
 __global__ __launch_bounds__(256) void k_mean_partial(const double* __restrict__ y, int64_t n, double* part) {
@@ -241,19 +250,29 @@ __global__ void k_mean_final(const double* part, int nb, int64_t n, double* out)
 }
 
 template <typename T>
-void launch_features(hipStream_t st, const double* y, const T* A, const double* D, const int32_t* nbr, int64_t n,
-                     int mv, double s1, double s2, double log_ls, double* scratch, float* feat) {
+void launch_features(hipStream_t st, const double* y, const T* A, const double* D, const int32_t* nbr,
+                     const double* smooth, int64_t n, int mv, double s1, double s2, double log_ls, double* scratch,
+                     float* feat) {
   const int nb = (int)ceil_div(n, 4096);
   hipLaunchKernelGGL(k_mean_partial, dim3(nb), dim3(256), 0, st, y, n, scratch + 1);
   hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(64), 0, st, scratch + 1, nb, n, scratch);
-  hipLaunchKernelGGL((k_features1<T>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, y, A, D, nbr, scratch, n,
-                     mv, s1, s2, log_ls, feat);
-  hipLaunchKernelGGL(k_features2, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, nbr, n, mv, feat);
+  hipLaunchKernelGGL((k_features1<T>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, y, A, D, nbr, scratch,
+                     smooth, n, mv, s1, s2, log_ls, feat);
+  hipLaunchKernelGGL((k_features2<T>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, nbr, A, n, mv, feat);
 }
 template void launch_features<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
-                                      int64_t, int, double, double, double, double*, float*);
-template void launch_features<float>(hipStream_t, const double*, const float*, const double*, const int32_t*, int64_t,
-                                     int, double, double, double, double*, float*);
+                                      const double*, int64_t, int, double, double, double, double*, float*);
+template void launch_features<float>(hipStream_t, const double*, const float*, const double*, const int32_t*,
+                                     const double*, int64_t, int, double, double, double, double*, float*);
+
+// g0_i = y_i - p0 (the likelihood gradient at b = 0)
+__global__ void k_shift(const double* __restrict__ y, double p0, int64_t n, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = y[i] - p0;
+}
+void launch_shift(hipStream_t st, const double* y, double p0, int64_t n, double* out) {
+  hipLaunchKernelGGL(k_shift, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, y, p0, n, out);
+}
 
 // ---------------------------------------------------------------------------
 struct MlpLayout {

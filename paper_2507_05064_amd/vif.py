@@ -44,18 +44,21 @@ class vif_config(ctypes.Structure):
 class vif_laplace_stats(ctypes.Structure):
     _fields_ = [("newton_iters", ctypes.c_int32), ("pcg_iters_total", ctypes.c_int32),
                 ("pcg_iters", ctypes.c_int32 * 64), ("halvings", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("psi", ctypes.c_double), ("pcg_rel_residual", ctypes.c_double)]
+                ("psi", ctypes.c_double), ("pcg_rel_residual", ctypes.c_double), ("start_used", ctypes.c_int32),
+                ("psi_start", ctypes.c_double)]
 
     def as_dict(self):
         k = min(self.newton_iters, 64)
         return {"newton_iters": self.newton_iters, "pcg_iters_total": self.pcg_iters_total,
                 "pcg_iters": list(self.pcg_iters[:k]), "halvings": self.halvings, "converged": bool(self.converged),
-                "psi": self.psi, "pcg_rel_residual": self.pcg_rel_residual}
+                "psi": self.psi, "pcg_rel_residual": self.pcg_rel_residual, "start_used": bool(self.start_used),
+                "psi_start": self.psi_start}
 
 
 EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors", "vif_build_factor", "vif_nll",
            "vif_nll_grad", "vif_export_factor", "vif_set_timing", "vif_timing_stages", "vif_timing_stage_name",
-           "vif_get_timing", "vif_laplace_mode"]
+           "vif_get_timing", "vif_laplace_mode", "vif_mlp_num_params", "vif_mlp_workspace_floats",
+           "vif_mlp_forward", "vif_mlp_backward", "vif_mlp_adam", "vif_mlp_features", "vif_sample_prior"]
 
 
 def load_library(path: Optional[str] = None):
@@ -94,6 +97,21 @@ def load_library(path: Optional[str] = None):
     lib.vif_get_timing.restype = ctypes.c_int
     lib.vif_laplace_mode.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vif_laplace_stats)]
     lib.vif_laplace_mode.restype = ctypes.c_int
+    lib.vif_mlp_num_params.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.vif_mlp_num_params.restype = ctypes.c_int64
+    lib.vif_mlp_workspace_floats.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+    lib.vif_mlp_workspace_floats.restype = ctypes.c_int64
+    lib.vif_mlp_forward.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
+    lib.vif_mlp_forward.restype = ctypes.c_int
+    lib.vif_mlp_backward.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp, vp, dp, vp]
+    lib.vif_mlp_backward.restype = ctypes.c_int
+    lib.vif_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_int32, vp]
+    lib.vif_mlp_adam.restype = ctypes.c_int
+    lib.vif_mlp_features.argtypes = [vp, vp, vp]
+    lib.vif_mlp_features.restype = ctypes.c_int
+    lib.vif_sample_prior.argtypes = [vp, vp, vp, vp]
+    lib.vif_sample_prior.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -198,3 +216,81 @@ class VifContext:
         if raise_on_error:
             self._check(rc)
         return mode, st.as_dict(), rc
+
+    def sample_prior(self, eps1: Optional[torch.Tensor], eps2: torch.Tensor) -> torch.Tensor:
+        b = torch.empty(self.n, dtype=torch.float64, device=eps2.device)
+        self._check(self.lib.vif_sample_prior(self.h, _ptr(eps1) if self.m else None, _ptr(eps2), _ptr(b)))
+        return b
+
+    def mlp_features(self, y: torch.Tensor) -> torch.Tensor:
+        feat = torch.empty((self.n, MLP_FEATURES), dtype=torch.float32, device=y.device)
+        self._check(self.lib.vif_mlp_features(self.h, _ptr(y), _ptr(feat)))
+        return feat
+
+
+MLP_FEATURES = 16
+
+
+def _mlp_call(rc: int, what: str):
+    if rc != 0:
+        raise VifError(rc, what)
+
+
+class WarmStartMLP:
+    """The warm-start network's parameters (one flat FP32 device tensor) and
+    its Adam state; every computation runs in the library's kernels."""
+
+    def __init__(self, H: int = 128, F: int = MLP_FEATURES, params: Optional[torch.Tensor] = None, seed: int = 0):
+        self.lib = load_library()
+        self.F, self.H = F, H
+        self.P = int(self.lib.vif_mlp_num_params(F, H))
+        if params is None:
+            g = np.random.default_rng(seed)
+            parts = []
+            for name, shape in (("W1", (F, H)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (H, H)),
+                                ("b3", (H,)), ("w4", (H,)), ("b4", (1,))):
+                if name[0] == "W":
+                    parts.append(g.standard_normal(shape).ravel() * np.sqrt(2.0 / shape[0]))
+                elif name == "w4":
+                    parts.append(g.standard_normal(shape) * np.sqrt(1.0 / shape[0]))
+                else:
+                    parts.append(np.zeros(int(np.prod(shape))))
+            params = torch.as_tensor(np.concatenate(parts).astype(np.float32), device="cuda")
+        assert params.numel() == self.P
+        self.params = params.contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self._ws = None
+
+    def _workspace(self, n: int) -> torch.Tensor:
+        need = int(self.lib.vif_mlp_workspace_floats(n, self.F, self.H))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.float32, device="cuda")
+        return self._ws
+
+    def forward(self, X: torch.Tensor, double: bool = False) -> torch.Tensor:
+        n = X.shape[0]
+        out = torch.empty(n, dtype=torch.float64 if double else torch.float32, device=X.device)
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        _mlp_call(self.lib.vif_mlp_forward(_ptr(self.params), _ptr(X), n, self.F, self.H, _ptr(self._workspace(n)),
+                                           None if double else _ptr(out), _ptr(out) if double else None, st),
+                  "vif_mlp_forward")
+        return out
+
+    def loss_grad(self, X: torch.Tensor, target: torch.Tensor):
+        n = X.shape[0]
+        grad = torch.empty_like(self.params)
+        loss = ctypes.c_double()
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        _mlp_call(self.lib.vif_mlp_backward(_ptr(self.params), _ptr(X), _ptr(target), n, self.F, self.H,
+                                            _ptr(self._workspace(n)), _ptr(grad), ctypes.byref(loss), st),
+                  "vif_mlp_backward")
+        return loss.value, grad
+
+    def adam(self, grad: torch.Tensor, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8):
+        self.step += 1
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        _mlp_call(self.lib.vif_mlp_adam(_ptr(self.params), _ptr(grad), _ptr(self.m), _ptr(self.v), self.P, lr, beta1,
+                                        beta2, eps, self.step, st), "vif_mlp_adam")

@@ -1,0 +1,126 @@
+"""Learned warm start for Laplace mode finding (not part of the paper).
+
+Training pairs (per-point features of (y, theta) -> Laplace mode) are made by
+the method itself: synthetic latent-VIF problems are drawn with
+vif_sample_prior, their modes found by vif_laplace_mode from the zero start,
+their features computed by vif_mlp_features. The network is trained by the
+library's forward / backward / Adam kernels (vif_mlp_*). At use, its output
+seeds vif_laplace_mode, which falls back to the zero start when the seed has
+a lower objective; the converged mode does not depend on the seed.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+import vif_inputs as vi
+from paper_2507_05064_amd.vif import MLP_FEATURES, VifContext, WarmStartMLP
+
+
+@dataclasses.dataclass
+class Problem:
+    w: vi.Workload
+    X: torch.Tensor
+    Z: Optional[torch.Tensor]
+    nbr: torch.Tensor
+    theta: np.ndarray
+    y: torch.Tensor
+    b_true: torch.Tensor
+
+
+def make_problem(w: vi.Workload, problem: int, theta_scale=(1.0, 1.0), cg_tol: float = 1e-6) -> Problem:
+    """A latent VIF problem of the workload's shape: inputs from the seeded
+    generator, b ~ N(0, Sigma_dagger) drawn on the GPU, y from the likelihood."""
+    X = vi.coords(w, problem)
+    Z = vi.inducing_points(w, X, problem)
+    theta = w.theta.copy()
+    theta[0] *= theta_scale[0]
+    theta[1:-1] *= theta_scale[1]
+    Xd = torch.as_tensor(X, device="cuda")
+    Zd = torch.as_tensor(Z, device="cuda") if w.m else None
+    ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=w.likelihood, precision="fp64", tau_m=w.tau_m,
+                     cg_tol=cg_tol)
+    nbr = ctx.select_neighbors(Xd, Zd, theta)
+    ctx.build_factor(Xd, Zd, nbr, theta)
+    eps1, eps2, u = vi.prior_noise(w, problem)
+    b = ctx.sample_prior(torch.as_tensor(eps1, device="cuda") if w.m else None, torch.as_tensor(eps2, device="cuda"))
+    bn = b.cpu().numpy()
+    if w.likelihood == vi.BERNOULLI_LOGIT:
+        y = vi.bernoulli_from_uniform(1.0 / (1.0 + np.exp(-bn)), u)
+    elif w.likelihood == vi.POISSON_LOG:
+        y = vi.poisson_from_uniform(np.exp(bn), u)
+    else:
+        raise ValueError("warm start is for non-Gaussian likelihoods")
+    ctx.close()
+    return Problem(w, Xd, Zd, nbr, theta, torch.as_tensor(y, device="cuda"), b)
+
+
+def context_for(p: Problem, cg_tol: float = 1e-6, cg_maxit: int = 1000, newton_tol: float = 1e-9) -> VifContext:
+    w = p.w
+    ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=w.likelihood, precision="fp64", tau_m=w.tau_m,
+                     cg_tol=cg_tol, cg_maxit=cg_maxit, newton_tol=newton_tol)
+    ctx.build_factor(p.X, p.Z, p.nbr, p.theta)
+    return ctx
+
+
+def training_pairs(problems: List[Problem], cg_tol: float = 1e-8):
+    """(features, mode) of every point of every problem, modes by the method."""
+    feats, modes = [], []
+    for p in problems:
+        ctx = context_for(p, cg_tol=cg_tol, newton_tol=1e-12)
+        mode, st, _ = ctx.laplace_mode(p.y)
+        feats.append(ctx.mlp_features(p.y))
+        modes.append(mode.float())
+        ctx.close()
+    return torch.cat(feats), torch.cat(modes)
+
+
+def train(feat: torch.Tensor, target: torch.Tensor, H: int = 128, epochs: int = 30, batch: int = 8192,
+          lr: float = 2e-3, seed: int = 0, log=None) -> WarmStartMLP:
+    """Adam on mean squared error with the library's kernels; minibatches in
+    a seeded random order."""
+    mlp = WarmStartMLP(H=H, seed=seed)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    n = feat.shape[0]
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(feat.device)
+        tot, cnt = 0.0, 0
+        for s in range(0, n, batch):
+            idx = perm[s:s + batch]
+            X = feat[idx].contiguous()
+            t = target[idx].contiguous()
+            loss, grad = mlp.loss_grad(X, t)
+            mlp.adam(grad, lr=lr * (0.5 ** (ep // 10)))
+            tot += loss * idx.numel()
+            cnt += idx.numel()
+        if log:
+            log(f"epoch {ep} mse {tot / cnt:.5f}")
+    return mlp
+
+
+def evaluate(mlp: WarmStartMLP, p: Problem, cg_tol: float = 1e-6, newton_tol: float = 1e-9):
+    """Mode time / iterations from the zero start and from the network's
+    output (network time included), and the network's relative error
+    ||b0 - mode|| / ||mode||."""
+    out = {}
+    ctx = context_for(p, cg_tol=cg_tol, newton_tol=newton_tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mode0, st0, _ = ctx.laplace_mode(p.y)
+    torch.cuda.synchronize()
+    out["zero"] = dict(seconds=time.perf_counter() - t0, **st0)
+    t0 = time.perf_counter()
+    feat = ctx.mlp_features(p.y)
+    b0 = mlp.forward(feat, double=True)
+    mode1, st1, _ = ctx.laplace_mode(p.y, b0)
+    torch.cuda.synchronize()
+    out["warm"] = dict(seconds=time.perf_counter() - t0, **st1)
+    out["net_rel_err"] = float(torch.linalg.norm(b0 - mode0) / torch.linalg.norm(mode0))
+    out["mode_rel_diff"] = float(torch.linalg.norm(mode1 - mode0) / torch.linalg.norm(mode0))
+    ctx.close()
+    return out
