@@ -231,6 +231,32 @@ class VifContext:
 MLP_FEATURES = 16
 
 
+class VifNLLFunction(torch.autograd.Function):
+    """Gaussian VIF negative log-likelihood as a differentiable function of
+    theta (a host FP64 tensor: sigma1^2, range or ARD length scales, nugget).
+    The forward builds the factor and runs vif_nll_grad, whose adjoint
+    (Sec. 2.3, App. A) gives dNLL/dtheta; the backward scales it."""
+
+    @staticmethod
+    def forward(fctx, theta, vctx, X, Z, nbr, y):
+        th = theta.detach().cpu().double().numpy()
+        vctx.build_factor(X, Z, nbr, th)
+        nll, g = vctx.nll_grad(y, th.size)
+        fctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype))
+        return theta.new_tensor(nll)
+
+    @staticmethod
+    def backward(fctx, gout):
+        (g,) = fctx.saved_tensors
+        return gout * g.to(gout.device), None, None, None, None, None
+
+
+def vif_nll(theta: torch.Tensor, vctx: "VifContext", X: torch.Tensor, Z: Optional[torch.Tensor],
+            nbr: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """NLL(theta) with autograd support through the library's adjoint."""
+    return VifNLLFunction.apply(theta, vctx, X, Z, nbr, y)
+
+
 def _mlp_call(rc: int, what: str):
     if rc != 0:
         raise VifError(rc, what)

@@ -189,3 +189,33 @@ def test_gradient_rejects_31_neighbours():
     with pytest.raises(VifError) as e:
         ctx.nll_grad(to_dev(np.zeros(100)), 3)
     assert e.value.code == 1
+
+
+def test_autograd_function_matches_oracle_and_finite_differences():
+    """torch.autograd through VifNLLFunction: the gradient equals the oracle's
+    forward-mode gradient, and central differences of the GPU NLL agree with
+    it (step 1e-5 relative, FP64)."""
+    import torch
+    from paper_2507_05064_amd.vif import vif_nll
+    w = vi.scaled(vi.config1(), 400, m=20, m_v=10)
+    X, Z, model = problem(w)
+    theta0 = w.theta * np.array([1.3, 0.8, 1.5])
+    model = vo.Model.from_theta(w.kernel, theta0, w.tau_m)
+    nbr = vo.neighbours(model, X, vo.inducing(model, X, Z), 10)
+    y = _y_exact(vo.Model.from_theta(w.kernel, w.theta), X, 5)
+    _, g_o = vo.nll_gaussian_grad(model, X, Z, nbr, y)
+    ctx = _ctx(w)
+    Xd, Zd, nd, yd = to_dev(X), to_dev(Z), nbr_to_dev(nbr), to_dev(y)
+    theta = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+    out = vif_nll(theta, ctx, Xd, Zd, nd, yd)
+    (2.0 * out).backward()
+    g = theta.grad.numpy() / 2.0
+    assert np.max(np.abs(g - g_o)) <= 1e-8 * np.max(np.abs(g_o)), (g, g_o)
+    for k in range(3):
+        h = 1e-5 * theta0[k]
+        tp, tm = theta0.copy(), theta0.copy()
+        tp[k] += h
+        tm[k] -= h
+        fp = vif_nll(torch.tensor(tp), ctx, Xd, Zd, nd, yd).item()
+        fm = vif_nll(torch.tensor(tm), ctx, Xd, Zd, nd, yd).item()
+        assert abs((fp - fm) / (2 * h) - g[k]) <= 1e-5 * max(abs(g[k]), 1.0), (k, (fp - fm) / (2 * h), g[k])
