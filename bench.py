@@ -146,6 +146,58 @@ def laplace_leg(reps, warmup, log):
     return out
 
 
+def batch_leg(steps, warmup, log):
+    """64 independent Gaussian problems (n uniform in [5000, 50000], d = 2,
+    Matern-3/2 with per-problem range in [0.02, 0.2], nugget 0.05, m = 100
+    random-subset inducing points, m_v = 15), y from each problem's VIF prior:
+    one vif_batch_nll_grad call = all 64 factor builds, NLLs and gradients.
+    Neighbours are selected per problem before the timed region."""
+    import torch
+    import vif_inputs as vi
+    from paper_2507_05064_amd.vif import VifBatch, VifContext
+    ws = vi.config4_problems(64)
+    Xs, Zs, nbrs, ys, thetas = [], [], [], [], []
+    t0 = time.perf_counter()
+    for p, w in enumerate(ws):
+        X = vi.coords(w, p)
+        Z = vi.inducing_points(w, X, p)
+        Xd, Zd = torch.as_tensor(X, device="cuda"), torch.as_tensor(Z, device="cuda")
+        ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, precision="fp64", tau_m=w.tau_m)
+        nbr = ctx.select_neighbors(Xd, Zd, w.theta)
+        ctx.build_factor(Xd, Zd, nbr, w.theta)
+        eps1, eps2, _ = vi.prior_noise(w, p)
+        y = ctx.sample_prior(torch.as_tensor(eps1, device="cuda"), torch.as_tensor(eps2, device="cuda"))
+        ctx.close()
+        Xs.append(Xd)
+        Zs.append(Zd)
+        nbrs.append(nbr)
+        ys.append(y)
+        thetas.append(w.theta)
+    Xc, Zc, nc, yc = torch.cat(Xs), torch.cat(Zs), torch.cat(nbrs), torch.cat(ys)
+    theta = np.stack(thetas)
+    sizes = [w.n for w in ws]
+    log(f"batch: 64 problems, {sum(sizes)} points, inputs in {time.perf_counter() - t0:.1f} s")
+    out = {"workload": "64 Gaussian VIF problems, n uniform in [5000, 50000] (total %d), d=2, Matern-3/2 "
+                       "(var 1, range uniform in [0.02, 0.2]), nugget 0.05, m=100 random-subset inducing points, "
+                       "m_v=15, y from the VIF prior; NLL + gradient of all 64 per call" % sum(sizes),
+           "problems": 64, "points": int(sum(sizes))}
+    for prec in ("fp32", "fp64"):
+        bt = VifBatch(sizes, 2, 100, 15, precision=prec)
+        for _ in range(warmup):
+            bt.nll_grad(Xc, Zc, nc, theta, yc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            nll, g = bt.nll_grad(Xc, Zc, nc, theta, yc)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / steps
+        bt.close()
+        out[prec] = {"ms_per_call": ms, "problems_per_s": 64 * 1000.0 / ms,
+                     "points_per_s": sum(sizes) * 1000.0 / ms, "nll_sum": float(np.sum(nll))}
+        log(f"batch {prec}: {out[prec]}")
+    return out
+
+
 def cpu_baseline(w, budget_points=6000):
     """Oracle (FP64 numpy) NLL + forward-mode gradient on the first
     `budget_points` points of the same workload (the prefix is itself a VIF
@@ -182,6 +234,7 @@ def main():
     ap.add_argument("--nll-only", action="store_true", help="time the NLL without the gradient")
     ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace mode leg")
     ap.add_argument("--laplace-reps", type=int, default=5)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -246,6 +299,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": nbytes, "avg_launch_ms": fac_ms},
     }
+    if not args.no_batch:
+        res["batch"] = batch_leg(args.steps, args.warmup, lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_laplace:
         res["laplace"] = laplace_leg(args.laplace_reps, 1, lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:

@@ -185,6 +185,15 @@ vif_status vif_mlp_adam(float* params, const float* grad, float* m, float* v, in
  * feature, y_i minus the second feature, then zeros. */
 vif_status vif_mlp_features(vif_ctx* ctx, const double* y, float* feat_out);
 
+/* Applies the VIFDU preconditioner of Sec. 4.3.1 / App. E.1 for a given
+ * diagonal W: z = P^{-1} r with P = B^T W B + Sigma_dagger^{-1}, in the
+ * whitened form z = B^{-1} [E + E D^{-1/2} U M3'^{-1} U^T D^{-1/2} E] B^{-T} r,
+ * E = diag(D / (1 + D W)), M3' = I + U^T diag(D W / (1 + D W)) U. This is
+ * the preconditioner vif_laplace_mode uses at each Newton step. W, r and z
+ * are device arrays of n doubles; z must not overlap r. Needs a built
+ * factor; VIF_E_NOT_PD if M3' is not positive definite. */
+vif_status vif_precond_solve(vif_ctx* ctx, const double* W, const double* r, double* z);
+
 /* Copies the factor of the last build to device buffers A_out (n x m_v, the
  * coefficients A_i over N(i), zero padded) and D_out (n), both double. */
 vif_status vif_export_factor(vif_ctx* ctx, double* A_out, double* D_out);
@@ -200,6 +209,43 @@ vif_status vif_set_timing(vif_ctx* ctx, int enable);
 int vif_timing_stages(void);
 const char* vif_timing_stage_name(int stage);
 vif_status vif_get_timing(vif_ctx* ctx, double* ms_out, int64_t* count_out, int nstage);
+
+/* ---- Many independent Gaussian problems in one pass ----
+ * nprob problems, each the Gaussian VIF model of Sec. 2 with its own points,
+ * inducing points, neighbour sets and parameters, share d, m, m_v, the
+ * kernel and the precision form. One call of vif_batch_nll_grad builds every
+ * factor (eq. D_A_Vecchia) and returns every NLL (Sec. 2.2) and gradient
+ * (Sec. 2.3, App. A), each stage one launch over all problems. */
+typedef struct {
+  int32_t nprob;      /* number of problems, >= 1 */
+  int32_t d;          /* input dimension, 1..8 */
+  int32_t m;          /* inducing points per problem, 1..1024 */
+  int32_t m_v;        /* neighbours per point, 0..30 */
+  int32_t kernel;     /* VIF_MATERN12 or VIF_MATERN32 (one range per problem) */
+  int32_t precision;  /* VIF_FP64 or VIF_FP32 */
+  double tau_m;       /* jitter added to every Sigma_m */
+} vif_batch_config;
+
+typedef struct vif_batch vif_batch;
+
+/* n: host array of nprob point counts (each >= m). Allocates all device
+ * workspace for the sizes given (each problem is padded to a multiple of
+ * 256 points inside); later calls allocate nothing. Work is queued on
+ * hip_stream (NULL = default stream). VIF_E_ARG for invalid sizes,
+ * VIF_E_OOM if device memory runs out. */
+vif_status vif_batch_create(const vif_batch_config* cfg, const int64_t* n, void* hip_stream, vif_batch** out);
+void vif_batch_destroy(vif_batch* b);
+const char* vif_batch_last_error(const vif_batch* b);
+
+/* Device arrays, problems back to back in order: X (sum n x d), y (sum n),
+ * nbr (sum n x m_v, indices local to the problem: -1 or 0 <= j < i); Z
+ * (nprob x m x d). Host arrays: theta (nprob x 3: sigma1^2, range, nugget),
+ * nll_out (nprob), grad_out (nprob x 3, or NULL for the NLL alone). The
+ * caller's arrays are read during the call only. Errors: VIF_E_ARG (a
+ * neighbour index out of range; the message names the padded point),
+ * VIF_E_NOT_PD (with the problem index), VIF_E_NAN. */
+vif_status vif_batch_nll_grad(vif_batch* b, const double* X, const double* Z, const int32_t* nbr,
+                              const double* theta, const double* y, double* nll_out, double* grad_out);
 
 #ifdef __cplusplus
 }

@@ -63,6 +63,7 @@ struct vif_ctx {
   // level schedules of the sparse triangular solves with B and B^T
   int *fwd_order = nullptr, *fwd_lvl = nullptr, *bwd_order = nullptr, *bwd_lvl = nullptr;
   int nlev_f = 0, nlev_b = 0;
+  std::vector<int> hfwd_lvl, hbwd_lvl;  // host copies of the level offsets
   bool lev_valid = false;
   // Laplace workspace: n-vectors, m-vectors, m x m
   double* lv = nullptr;  // 20 n-vectors
@@ -612,6 +613,8 @@ static vif_status ensure_schedules(vif_ctx* c) {
   std::vector<int> fo, fp, bo, bp;
   c->nlev_f = schedule(lev, fo, fp);
   c->nlev_b = schedule(rlev, bo, bp);
+  c->hfwd_lvl = fp;
+  c->hbwd_lvl = bp;
   HIPCHK(c, hipMemcpyAsync(c->fwd_order, fo.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->fwd_lvl, fp.data(), sizeof(int) * fp.size(), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->bwd_order, bo.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
@@ -666,7 +669,7 @@ template <typename T>
 static void vifdu_apply(vif_ctx* c, LapBufs& B, const double* r, double* z) {
   const vif_config& g = c->cfg;
   const T* U = (const T*)c->U;
-  launch_trsv_bwd<T>(c->st, c->bwd_order, c->bwd_lvl, c->nlev_b, c->rev_ptr, c->rev_idx, (const T*)c->A, r, g.m_v,
+  launch_trsv_bwd<T>(c->st, c->bwd_order, c->bwd_lvl, c->hbwd_lvl.data(), c->nlev_b, c->rev_ptr, c->rev_idx, (const T*)c->A, r, g.m_v,
                      B.v);
   launch_scale_e(c->st, B.v, B.E, c->D, g.n, B.q, B.qd);
   if (g.m > 0) {
@@ -674,7 +677,7 @@ static void vifdu_apply(vif_ctx* c, LapBufs& B, const double* r, double* z) {
     launch_reduce_apply(c->st, B.upart, c->nchunk, c->mp, c->M3inv, B.cbuf, B.cp);
   }
   launch_q_plus_euc<T>(c->st, U, B.cp, B.q, B.E, c->D, g.n, c->mp, B.q2);
-  launch_trsv_fwd<T>(c->st, c->fwd_order, c->fwd_lvl, c->nlev_f, c->nbr, (const T*)c->A, B.q2, g.m_v, z);
+  launch_trsv_fwd<T>(c->st, c->fwd_order, c->fwd_lvl, c->hfwd_lvl.data(), c->nlev_f, c->nbr, (const T*)c->A, B.q2, g.m_v, z);
 }
 
 __global__ void k_copy_scalar(double* dst, const double* src) { dst[0] = src[0]; }
@@ -699,6 +702,25 @@ __global__ void k_sum_part(const double* part, int nb, double* out) {
     double s = 0.0;
     for (int b = 0; b < nb; ++b) s += part[b];
     out[0] = s;
+  }
+}
+
+// VIFDU data for the diagonal B.W: E = D / (1 + D W), sw = D W / (1 + D W),
+// M3' = I + U^T diag(sw) U, its Cholesky factor, inverse and log-det (sc[12])
+static void build_vifdu(vif_ctx* c, LapBufs& B) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  const int mp = c->mp;
+  launch_vifdu_diag(c->st, c->D, B.W, n, B.E, B.sw);
+  if (g.m > 0) {
+    int nchunk = 0;
+    if (fp32_form(c))
+      launch_wgram_partial<float>(c->st, (const float*)c->U, B.sw, n, mp, c->chunk, c->partial, &nchunk);
+    else
+      launch_wgram_partial<double>(c->st, (const double*)c->U, B.sw, n, mp, c->chunk, c->partial, &nchunk);
+    launch_reduce_gram(c->st, c->partial, nchunk, mp, c->M3);
+    launch_chol_inv(c->st, c->M3, c->L3inv, c->Mwork, g.m, mp, B.sc + 12, c->status, 3);
+    launch_gemm_sq(c->st, c->L3inv, c->L3inv, c->M3inv, mp, true, false);
   }
 }
 
@@ -809,17 +831,7 @@ static vif_status laplace_impl(vif_ctx* c, const double* y, const double* b0, do
   for (int t = 1; t <= g.newton_maxit; ++t) {
     // rhs = g - Sigma^{-1} b ; VIFDU data for the current W
     hipLaunchKernelGGL(k_sub, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->st, B.rhs, B.g, B.sb, n);
-    launch_vifdu_diag(c->st, c->D, B.W, n, B.E, B.sw);
-    if (g.m > 0) {
-      int nchunk = 0;
-      if (fp32_form(c))
-        launch_wgram_partial<float>(c->st, (const float*)c->U, B.sw, n, mp, c->chunk, c->partial, &nchunk);
-      else
-        launch_wgram_partial<double>(c->st, (const double*)c->U, B.sw, n, mp, c->chunk, c->partial, &nchunk);
-      launch_reduce_gram(c->st, c->partial, nchunk, mp, c->M3);
-      launch_chol_inv(c->st, c->M3, c->L3inv, c->Mwork, g.m, mp, B.sc + 12, c->status, 3);
-      launch_gemm_sq(c->st, c->L3inv, c->L3inv, c->M3inv, mp, true, false);
-    }
+    build_vifdu(c, B);
     int its = 0;
     double rel = 0.0;
     s = pcg<T>(c, B, &its, &rel);
@@ -895,10 +907,10 @@ vif_status vif_sample_prior(vif_ctx* c, const double* eps1, const double* eps2, 
   LapBufs B = lap_bufs(c);
   launch_sqrtd_scale(c->st, c->D, eps2, g.n, B.t);
   if (fp32_form(c)) {
-    launch_trsv_fwd<float>(c->st, c->fwd_order, c->fwd_lvl, c->nlev_f, c->nbr, (const float*)c->A, B.t, g.m_v, B.s);
+    launch_trsv_fwd<float>(c->st, c->fwd_order, c->fwd_lvl, c->hfwd_lvl.data(), c->nlev_f, c->nbr, (const float*)c->A, B.t, g.m_v, B.s);
     launch_add_ve<float>(c->st, c->Vf, eps1, B.s, g.n, g.m > 0 ? c->mp : 0, b_out);
   } else {
-    launch_trsv_fwd<double>(c->st, c->fwd_order, c->fwd_lvl, c->nlev_f, c->nbr, (const double*)c->A, B.t, g.m_v,
+    launch_trsv_fwd<double>(c->st, c->fwd_order, c->fwd_lvl, c->hfwd_lvl.data(), c->nlev_f, c->nbr, (const double*)c->A, B.t, g.m_v,
                             B.s);
     launch_add_ve<double>(c->st, c->Vd, eps1, B.s, g.n, g.m > 0 ? c->mp : 0, b_out);
   }
@@ -977,6 +989,24 @@ __global__ void k_export_A(const void* A, bool f32, int64_t count, double* out) 
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= count) return;
   out[q] = f32 ? (double)((const float*)A)[q] : ((const double*)A)[q];
+}
+
+vif_status vif_precond_solve(vif_ctx* c, const double* W, const double* r, double* z) {
+  if (!c) return VIF_E_ARG;
+  if (!c->built) return fail(c, VIF_E_STATE, "vif_precond_solve before a successful vif_build_factor");
+  if (!W || !r || !z) return fail(c, VIF_E_ARG, "NULL W, r or z");
+  vif_status s = reset_status(c);
+  if (s) return s;
+  if ((s = ensure_schedules(c))) return s;
+  LapBufs B = lap_bufs(c);
+  HIPCHK(c, hipMemcpyAsync(B.W, W, sizeof(double) * c->cfg.n, hipMemcpyDeviceToDevice, c->st));
+  build_vifdu(c, B);
+  if (fp32_form(c))
+    vifdu_apply<float>(c, B, r, z);
+  else
+    vifdu_apply<double>(c, B, r, z);
+  HIPCHK(c, hipGetLastError());
+  return read_status(c, "vif_precond_solve");
 }
 
 vif_status vif_export_factor(vif_ctx* c, double* A_out, double* D_out) {

@@ -101,3 +101,23 @@ static inline int round_up16(int m) { return (m + 15) / 16 * 16; }
 #define VIF_DEV_OK 0
 #define VIF_DEV_NOT_PD 3
 #define VIF_DEV_NAN 2
+
+// Several independent problems in one launch. Each problem's points sit in
+// a contiguous range of the concatenated arrays, padded to a multiple of
+// kBatchBlock; padding points are inert (no neighbours, A = 0, D = 1,
+// U = 0, y = 0), so point-chunk partial sums need no problem boundaries.
+// Kernels take a Batch by value; bp == nullptr means one problem (the
+// single-problem arguments apply, blockIdx selects nothing).
+constexpr int kBatchBlock = 256;
+struct BatchProb {
+  int64_t uoff;    // first point in the caller's (unpadded) arrays
+  int64_t poff;    // first point (multiple of kBatchBlock)
+  int64_t n;       // points of the problem
+  int32_t cbeg;    // first kBatchBlock chunk
+  int32_t nchunk;  // chunks of the problem
+  CovParams cp;
+};
+struct Batch {
+  const BatchProb* bp;      // per problem; nullptr: one problem
+  const int32_t* blk2prob;  // problem of each kBatchBlock-point block
+};

@@ -26,7 +26,13 @@ __device__ double wg_sum(double v) {
 }
 
 // Sigma_m = K(Z,Z) + tau_m I into an mp x mp buffer (zero padded).
-__global__ void k_cov_zz(const double* Z, int m, int mp, CovParams p, double tau_m, double* S) {
+__global__ void k_cov_zz(const double* Z, int m, int mp, CovParams p_in, double tau_m, double* S, Batch bt) {
+  CovParams p = p_in;
+  if (bt.bp) {  // problem blockIdx.z
+    p = bt.bp[blockIdx.z].cp;
+    Z += (size_t)blockIdx.z * m * p.d;
+    S += (size_t)blockIdx.z * mp * mp;
+  }
   const int a = blockIdx.y;
   for (int b = threadIdx.x; b < mp; b += blockDim.x) {
     double v = 0.0;
@@ -51,7 +57,15 @@ __global__ void k_cov_zz(const double* Z, int m, int mp, CovParams p, double tau
 #define CNW (CWG / 64)
 __global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double* __restrict__ Linv,
                                                    double* __restrict__ work, int m, int mp, double* out,
-                                                   int* status, int code_base) {
+                                                   int* status, int code_base, int ostride) {
+  // one matrix per workgroup: blockIdx.x selects it (stride mp x mp; out stride ostride)
+  {
+    const size_t mo = (size_t)blockIdx.x * mp * mp;
+    S += mo;
+    Linv += mo;
+    work += mo;
+    out += (size_t)blockIdx.x * ostride;
+  }
   __shared__ double Db[CB][CB + 1];
   __shared__ double Di[CB][CB + 1];
   __shared__ int s_fail;
@@ -140,7 +154,12 @@ __global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double
     }
     __syncthreads();
     if (s_fail) {
-      if (tid == 0) { status[0] = VIF_DEV_NOT_PD; status[1] = code_base; status[2] = s_fail - 1; }
+      if (tid == 0) {
+        status[0] = VIF_DEV_NOT_PD;
+        status[1] = code_base;
+        status[2] = s_fail - 1;
+        status[5] = blockIdx.x;
+      }
       return;
     }
     const int T0 = kb + nb;
@@ -258,7 +277,13 @@ __global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double
 
 // M' = I + scale * sum_chunks partial over the lower triangle (every entry c <= l is
 // written by k_gram_partial) -- one thread per element.
-__global__ void k_reduce_gram(const double* partial, int nchunk, int mp, double scale, double* Mp) {
+__global__ void k_reduce_gram(const double* partial, int nchunk, int mp, double scale, double* Mp, Batch bt) {
+  if (bt.bp) {  // problem blockIdx.y: its chunk range
+    const BatchProb& pb = bt.bp[blockIdx.y];
+    partial += (size_t)pb.cbeg * mp * mp;
+    nchunk = pb.nchunk;
+    Mp += (size_t)blockIdx.y * mp * mp;
+  }
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)mp * mp) return;
   const int l = (int)(q / mp), c = (int)(q % mp);
@@ -272,7 +297,17 @@ __global__ void k_reduce_gram(const double* partial, int nchunk, int mp, double 
 // Final Gaussian NLL. vec[0..mp) holds U^T yt, scal[0] = sum log D,
 // scal[1] = sum yt^2 (already reduced). LMinv = L_{M'}^{-1}.
 __global__ __launch_bounds__(WG) void k_nll_final(const double* LMinv, const double* vec, const double* scal,
-                                                  int m, int mp, const double* logdet_mprime, int64_t n, double* out) {
+                                                  int m, int mp, const double* logdet_mprime, int64_t n, double* out,
+                                                  Batch bt, int ostride) {
+  if (bt.bp) {  // problem blockIdx.x: vec/scal stride mp + 2, outputs stride ostride
+    const int b = blockIdx.x;
+    LMinv += (size_t)b * mp * mp;
+    vec += (size_t)b * (mp + 2);
+    scal += (size_t)b * (mp + 2);
+    logdet_mprime += (size_t)b * ostride;
+    out += (size_t)b * ostride;
+    n = bt.bp[b].n;
+  }
   double ss = 0.0;
   for (int l = threadIdx.x; l < m; l += WG) {
     const double* row = LMinv + (size_t)l * mp;
@@ -291,19 +326,22 @@ __global__ __launch_bounds__(WG) void k_nll_final(const double* LMinv, const dou
 }
 
 // ---------------------------------------------------------------------------
-void launch_cov_zz(hipStream_t st, const double* Z, int m, int mp, const CovParams& p, double tau_m, double* S) {
-  hipLaunchKernelGGL(k_cov_zz, dim3(1, mp), dim3(256), 0, st, Z, m, mp, p, tau_m, S);
+void launch_cov_zz(hipStream_t st, const double* Z, int m, int mp, const CovParams& p, double tau_m, double* S,
+                   Batch bt, int nprob) {
+  hipLaunchKernelGGL(k_cov_zz, dim3(1, mp, nprob), dim3(256), 0, st, Z, m, mp, p, tau_m, S, bt);
 }
 void launch_chol_inv(hipStream_t st, double* S, double* Linv, double* work, int m, int mp, double* out, int* status,
-                     int code) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(CWG), 0, st, S, Linv, work, m, mp, out, status, code);
+                     int code, int nmat, int ostride) {
+  hipLaunchKernelGGL(k_chol_inv, dim3(nmat), dim3(CWG), 0, st, S, Linv, work, m, mp, out, status, code, ostride);
 }
-void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp, double scale) {
+void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp, double scale, Batch bt,
+                        int nprob) {
   const int64_t total = (int64_t)mp * mp;
-  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, partial, nchunk, mp, scale,
-                     Mp);
+  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)ceil_div(total, 256), nprob), dim3(256), 0, st, partial, nchunk,
+                     mp, scale, Mp, bt);
 }
 void launch_nll_final(hipStream_t st, const double* LMinv, const double* vec, const double* scal, int m, int mp,
-                      const double* logdet_mprime, int64_t n, double* out) {
-  hipLaunchKernelGGL(k_nll_final, dim3(1), dim3(WG), 0, st, LMinv, vec, scal, m, mp, logdet_mprime, n, out);
+                      const double* logdet_mprime, int64_t n, double* out, Batch bt, int nprob, int ostride) {
+  hipLaunchKernelGGL(k_nll_final, dim3(nprob), dim3(WG), 0, st, LMinv, vec, scal, m, mp, logdet_mprime, n, out, bt,
+                     ostride);
 }

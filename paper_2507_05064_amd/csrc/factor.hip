@@ -178,14 +178,25 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
 template <typename T, int NBLK>
 __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, const T* __restrict__ V,
                                                const int32_t* __restrict__ nbr, int64_t n, int mp, int mv,
-                                               CovParams p, T* __restrict__ Aout, double* __restrict__ Dout,
-                                               T* __restrict__ U, int* status) {
+                                               CovParams p_in, T* __restrict__ Aout, double* __restrict__ Dout,
+                                               T* __restrict__ U, int* status, Batch bt) {
   __shared__ PointShared<T> sh;
   T Lrow[32];
   int k;
   T D;
   const int lane = threadIdx.x;
   const int64_t i = blockIdx.x;
+  CovParams p = p_in;
+  if (bt.bp) {
+    const BatchProb& q = bt.bp[bt.blk2prob[i / kBatchBlock]];
+    if (i - q.poff >= q.n) {  // padding point: inert row
+      if (lane < mv) Aout[i * mv + lane] = T(0);
+      if (lane == 0) Dout[i] = 1.0;
+      for (int l = lane; l < mp; l += 64) U[(size_t)i * mp + l] = T(0);
+      return;
+    }
+    p = q.cp;
+  }
   if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, Lrow, k, D, status)) {
     if (lane == 0) Dout[i] = __builtin_nan("");
     return;
@@ -228,9 +239,9 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
                                                    const double* __restrict__ y, const T* __restrict__ U,
                                                    const T* __restrict__ Ubar, const double* __restrict__ e,
                                                    const double* __restrict__ yt, const double* __restrict__ Dfwd,
-                                                   int64_t n, int mp, int mv, CovParams p, T* __restrict__ Q1,
+                                                   int64_t n, int mp, int mv, CovParams p_in, T* __restrict__ Q1,
                                                    T* __restrict__ Gs, T* __restrict__ Bs, double* __restrict__ tpart,
-                                                   int* status) {
+                                                   int* status, Batch bt) {
   __shared__ PointShared<T> sh;
   __shared__ T rho_s[32];
   T Lrow[32];
@@ -239,6 +250,21 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   const int lane = threadIdx.x;
   const int myrow = lane & 31;
   const int64_t i = blockIdx.x;
+  CovParams p = p_in;
+  if (bt.bp) {
+    const BatchProb& q = bt.bp[bt.blk2prob[i / kBatchBlock]];
+    if (i - q.poff >= q.n) {  // padding point: no contribution
+      for (int l = lane; l < mp; l += 64) {
+        const size_t o = (size_t)i * mp + l;
+        Q1[o] = T(0);
+        Gs[o] = T(0);
+        Bs[o] = T(0);
+      }
+      if (lane < 3) tpart[i * 3 + lane] = 0.0;
+      return;
+    }
+    p = q.cp;
+  }
   const T rsd = T(1) / sqrt(T(Dfwd[i]));
   if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, Lrow, k, D, status, Ubar + (size_t)i * mp, rsd)) {
     if (lane == 0) tpart[i * 3] = tpart[i * 3 + 1] = tpart[i * 3 + 2] = __builtin_nan("");
@@ -349,11 +375,13 @@ __global__ void k_ytilde(const T* __restrict__ A, const double* __restrict__ D, 
 
 template <typename T>
 void launch_factor(hipStream_t st, const double* X, const T* V, const int32_t* nbr, int64_t n, int mp, int mv,
-                   const CovParams& p, T* A, double* D, T* U, int* status) {
+                   const CovParams& p, T* A, double* D, T* U, int* status, Batch bt) {
   if (mv + 1 <= 16)
-    hipLaunchKernelGGL((k_factor<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, nbr, n, mp, mv, p, A, D, U, status);
+    hipLaunchKernelGGL((k_factor<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, nbr, n, mp, mv, p, A, D, U, status,
+                       bt);
   else
-    hipLaunchKernelGGL((k_factor<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, nbr, n, mp, mv, p, A, D, U, status);
+    hipLaunchKernelGGL((k_factor<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, nbr, n, mp, mv, p, A, D, U, status,
+                       bt);
 }
 
 template <typename T>
@@ -363,9 +391,9 @@ void launch_ytilde(hipStream_t st, const T* A, const double* D, const int32_t* n
 }
 
 template void launch_factor<double>(hipStream_t, const double*, const double*, const int32_t*, int64_t, int, int,
-                                    const CovParams&, double*, double*, double*, int*);
+                                    const CovParams&, double*, double*, double*, int*, Batch);
 template void launch_factor<float>(hipStream_t, const double*, const float*, const int32_t*, int64_t, int, int,
-                                   const CovParams&, float*, double*, float*, int*);
+                                   const CovParams&, float*, double*, float*, int*, Batch);
 template void launch_ytilde<double>(hipStream_t, const double*, const double*, const int32_t*, const double*, int64_t,
                                     int, double*);
 template void launch_ytilde<float>(hipStream_t, const float*, const double*, const int32_t*, const double*, int64_t,
@@ -374,19 +402,20 @@ template void launch_ytilde<float>(hipStream_t, const float*, const double*, con
 template <typename T>
 void launch_factor_bwd(hipStream_t st, const double* X, const T* V, const T* Vr, const int32_t* nbr, const double* y,
                        const T* U, const T* Ubar, const double* e, const double* yt, const double* D, int64_t n,
-                       int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status) {
+                       int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status,
+                       Batch bt) {
   if (mv + 2 <= 16)
     hipLaunchKernelGGL((k_factor_bwd<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
-                       n, mp, mv, p, Q1, Gs, Bs, tpart, status);
+                       n, mp, mv, p, Q1, Gs, Bs, tpart, status, bt);
   else
     hipLaunchKernelGGL((k_factor_bwd<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
-                       n, mp, mv, p, Q1, Gs, Bs, tpart, status);
+                       n, mp, mv, p, Q1, Gs, Bs, tpart, status, bt);
 }
 template void launch_factor_bwd<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
                                         const double*, const double*, const double*, const double*, const double*,
                                         const double*, int64_t, int, int, const CovParams&, double*, double*, double*,
-                                        double*, int*);
+                                        double*, int*, Batch);
 template void launch_factor_bwd<float>(hipStream_t, const double*, const float*, const float*, const int32_t*,
                                        const double*, const float*, const float*, const double*, const double*,
                                        const double*, int64_t, int, int, const CovParams&, float*, float*, float*,
-                                       double*, int*);
+                                       double*, int*, Batch);

@@ -17,6 +17,12 @@
 __global__ __launch_bounds__(256) void k_gemm_sq(const double* __restrict__ A, const double* __restrict__ B,
                                                  double* __restrict__ C, int mp, int ta, int tb) {
   __shared__ double As[16][17], Bs[16][17];
+  {  // blockIdx.z: matrix of a batch (mp x mp apart)
+    const size_t mo = (size_t)blockIdx.z * mp * mp;
+    A += mo;
+    B += mo;
+    C += mo;
+  }
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int row = blockIdx.y * 16 + ty, col = blockIdx.x * 16 + tx;
   double acc = 0.0;
@@ -35,7 +41,14 @@ __global__ __launch_bounds__(256) void k_gemm_sq(const double* __restrict__ A, c
 // w = Minv b (single workgroup), Minv in FP64; also a T copy of Minv.
 template <typename T>
 __global__ __launch_bounds__(256) void k_prep_w(const double* __restrict__ Minv, const double* __restrict__ b, int mp,
-                                                double* __restrict__ w, T* __restrict__ MinvT) {
+                                                double* __restrict__ w, T* __restrict__ MinvT, int bstride) {
+  {  // blockIdx.x: problem of a batch
+    const size_t z = blockIdx.x;
+    Minv += z * mp * mp;
+    MinvT += z * mp * mp;
+    b += z * bstride;
+    w += z * mp;
+  }
   for (int l = threadIdx.x; l < mp; l += 256) {
     const double* row = Minv + (size_t)l * mp;
     double s = 0.0;
@@ -49,10 +62,11 @@ __global__ __launch_bounds__(256) void k_prep_w(const double* __restrict__ Minv,
 template <typename T>
 __global__ __launch_bounds__(256) void k_resid(const T* __restrict__ U, const double* __restrict__ w,
                                                const double* __restrict__ yt, int64_t n, int mp,
-                                               double* __restrict__ e) {
+                                               double* __restrict__ e, Batch bt) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n) return;
+  if (bt.bp) w += (size_t)bt.blk2prob[i / kBatchBlock] * mp;
   double s = 0.0;
   for (int l = lane; l < mp; l += 64) s += (double)U[(size_t)i * mp + l] * w[l];
   s = wave_sum(s);
@@ -64,8 +78,13 @@ __global__ __launch_bounds__(256) void k_resid(const T* __restrict__ U, const do
 template <typename T>
 __global__ __launch_bounds__(256) void k_ubar(const T* __restrict__ U, const T* __restrict__ Minv,
                                               const double* __restrict__ e, const double* __restrict__ w, int64_t n,
-                                              int mp, T* __restrict__ Ubar) {
+                                              int mp, T* __restrict__ Ubar, Batch bt) {
   typedef typename Acc4<T>::type A4;
+  if (bt.bp) {  // the 64-point tile lies in one problem
+    const int b = bt.blk2prob[((int64_t)blockIdx.x * 64) / kBatchBlock];
+    Minv += (size_t)b * mp * mp;
+    w += (size_t)b * mp;
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r = lane & 15, g = lane >> 4;
   const int64_t p0 = (int64_t)blockIdx.x * 64 + 16 * wv;
@@ -167,7 +186,14 @@ __global__ __launch_bounds__(256) void k_cross3_partial(const T* __restrict__ V,
 }
 
 // out = sum of the partials' lower triangles, mirrored to a full symmetric matrix
-__global__ void k_reduce_sym(const double* __restrict__ partial, int nchunk, int mp, double* __restrict__ out) {
+__global__ void k_reduce_sym(const double* __restrict__ partial, int nchunk, int mp, double* __restrict__ out,
+                             Batch bt) {
+  if (bt.bp) {  // problem blockIdx.y: its chunk range
+    const BatchProb& pb = bt.bp[blockIdx.y];
+    partial += (size_t)pb.cbeg * mp * mp;
+    nchunk = pb.nchunk;
+    out += (size_t)blockIdx.y * mp * mp;
+  }
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)mp * mp) return;
   const int l = (int)(q / mp), c = (int)(q % mp);
@@ -179,8 +205,17 @@ __global__ void k_reduce_sym(const double* __restrict__ partial, int nchunk, int
 
 // -1/2 sum_ab Tm_ab dSigma_m[a][b]/dtheta for (sigma1^2, range): one block per row.
 __global__ __launch_bounds__(256) void k_sigma_m_grad(const double* __restrict__ Tm, const double* __restrict__ Z,
-                                                      int m, int mp, CovParams p, double* __restrict__ rowpart) {
+                                                      int m, int mp, CovParams p_in, double* __restrict__ rowpart,
+                                                      Batch bt) {
   __shared__ double red[2][4];
+  CovParams p = p_in;
+  if (bt.bp) {  // problem blockIdx.y
+    const int b = blockIdx.y;
+    p = bt.bp[b].cp;
+    Tm += (size_t)b * mp * mp;
+    Z += (size_t)b * m * p.d;
+    rowpart += (size_t)b * m * 2;
+  }
   const int a = blockIdx.x;
   double gs = 0.0, gr = 0.0;
   for (int b = threadIdx.x; b < m; b += 256) {
@@ -216,6 +251,32 @@ __global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ in, i
     const int c = threadIdx.x;
     out[blockIdx.x * cols + c] = red[c][0] + red[c][1] + red[c][2] + red[c][3];
   }
+}
+
+// Batched final gradient: one workgroup per problem adds its points' parts
+// (tpart, 3 per point over the padded range) and its Sigma_m rows (rowpart,
+// 2 per row) in a fixed order.
+__global__ __launch_bounds__(256) void k_batch_grad_final(const double* __restrict__ tpart,
+                                                          const double* __restrict__ rowpart, int m, Batch bt,
+                                                          double* __restrict__ out, int ostride) {
+  __shared__ double red[3][4];
+  const int b = blockIdx.x;
+  const BatchProb& pb = bt.bp[b];
+  const int64_t beg = pb.poff, end = pb.poff + (int64_t)pb.nchunk * kBatchBlock;
+  double s[3] = {0, 0, 0};
+  for (int64_t r = beg + threadIdx.x; r < end; r += 256)
+    for (int c = 0; c < 3; ++c) s[c] += tpart[r * 3 + c];
+  for (int r = threadIdx.x; r < m; r += 256) {
+    s[0] += rowpart[((size_t)b * m + r) * 2];
+    s[1] += rowpart[((size_t)b * m + r) * 2 + 1];
+  }
+  for (int c = 0; c < 3; ++c) {
+    const double v = wave_sum(s[c]);
+    if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) out[(size_t)b * ostride + threadIdx.x] =
+      red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
 }
 
 // ---------------------------------------------------------------------------
@@ -277,23 +338,25 @@ __global__ void k_rev_sort(const int* __restrict__ ptr, int64_t n, int* __restri
 }
 
 // ---------------------------------------------------------------------------
-void launch_gemm_sq(hipStream_t st, const double* A, const double* B, double* C, int mp, bool ta, bool tb) {
-  dim3 grid((mp + 15) / 16, (mp + 15) / 16);
+void launch_gemm_sq(hipStream_t st, const double* A, const double* B, double* C, int mp, bool ta, bool tb, int nmat) {
+  dim3 grid((mp + 15) / 16, (mp + 15) / 16, nmat);
   hipLaunchKernelGGL(k_gemm_sq, grid, dim3(256), 0, st, A, B, C, mp, (int)ta, (int)tb);
 }
 template <typename T>
-void launch_prep_w(hipStream_t st, const double* Minv, const double* b, int mp, double* w, T* MinvT) {
-  hipLaunchKernelGGL((k_prep_w<T>), dim3(1), dim3(256), 0, st, Minv, b, mp, w, MinvT);
+void launch_prep_w(hipStream_t st, const double* Minv, const double* b, int mp, double* w, T* MinvT, int nprob,
+                   int bstride) {
+  hipLaunchKernelGGL((k_prep_w<T>), dim3(nprob), dim3(256), 0, st, Minv, b, mp, w, MinvT, bstride);
 }
 template <typename T>
-void launch_resid(hipStream_t st, const T* U, const double* w, const double* yt, int64_t n, int mp, double* e) {
-  hipLaunchKernelGGL((k_resid<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, U, w, yt, n, mp, e);
+void launch_resid(hipStream_t st, const T* U, const double* w, const double* yt, int64_t n, int mp, double* e,
+                  Batch bt) {
+  hipLaunchKernelGGL((k_resid<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, U, w, yt, n, mp, e, bt);
 }
 template <typename T>
 void launch_ubar(hipStream_t st, const T* U, const T* Minv, const double* e, const double* w, int64_t n, int mp,
-                 T* Ubar) {
+                 T* Ubar, Batch bt) {
   dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(mp, 64));
-  hipLaunchKernelGGL((k_ubar<T>), grid, dim3(256), 0, st, U, Minv, e, w, n, mp, Ubar);
+  hipLaunchKernelGGL((k_ubar<T>), grid, dim3(256), 0, st, U, Minv, e, w, n, mp, Ubar, bt);
 }
 template <typename T>
 void launch_cross3_partial(hipStream_t st, const T* V, const T* Q1, const T* U, const T* Gs, const T* Bs, int64_t n,
@@ -306,13 +369,18 @@ void launch_cross3_partial(hipStream_t st, const T* V, const T* Q1, const T* U, 
                      partial);
   *nchunk_out = nchunk;
 }
-void launch_reduce_sym(hipStream_t st, const double* partial, int nchunk, int mp, double* out) {
+void launch_reduce_sym(hipStream_t st, const double* partial, int nchunk, int mp, double* out, Batch bt, int nprob) {
   const int64_t total = (int64_t)mp * mp;
-  hipLaunchKernelGGL(k_reduce_sym, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, partial, nchunk, mp, out);
+  hipLaunchKernelGGL(k_reduce_sym, dim3((unsigned)ceil_div(total, 256), nprob), dim3(256), 0, st, partial, nchunk, mp,
+                     out, bt);
 }
 void launch_sigma_m_grad(hipStream_t st, const double* Tm, const double* Z, int m, int mp, const CovParams& p,
-                         double* rowpart) {
-  hipLaunchKernelGGL(k_sigma_m_grad, dim3(m), dim3(256), 0, st, Tm, Z, m, mp, p, rowpart);
+                         double* rowpart, Batch bt, int nprob) {
+  hipLaunchKernelGGL(k_sigma_m_grad, dim3(m, nprob), dim3(256), 0, st, Tm, Z, m, mp, p, rowpart, bt);
+}
+void launch_batch_grad_final(hipStream_t st, const double* tpart, const double* rowpart, int m, Batch bt, int nprob,
+                             double* out, int ostride) {
+  hipLaunchKernelGGL(k_batch_grad_final, dim3(nprob), dim3(256), 0, st, tpart, rowpart, m, bt, out, ostride);
 }
 int launch_colsum(hipStream_t st, const double* in, int64_t rows, int cols, double* out) {
   const int64_t per = 4096;
@@ -332,14 +400,16 @@ void launch_reverse_lists(hipStream_t st, const int32_t* nbr, int64_t n, int mv,
   hipLaunchKernelGGL(k_rev_sort, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, ptr, n, idx);
 }
 
-template void launch_prep_w<double>(hipStream_t, const double*, const double*, int, double*, double*);
-template void launch_prep_w<float>(hipStream_t, const double*, const double*, int, double*, float*);
-template void launch_resid<double>(hipStream_t, const double*, const double*, const double*, int64_t, int, double*);
-template void launch_resid<float>(hipStream_t, const float*, const double*, const double*, int64_t, int, double*);
+template void launch_prep_w<double>(hipStream_t, const double*, const double*, int, double*, double*, int, int);
+template void launch_prep_w<float>(hipStream_t, const double*, const double*, int, double*, float*, int, int);
+template void launch_resid<double>(hipStream_t, const double*, const double*, const double*, int64_t, int, double*,
+                                   Batch);
+template void launch_resid<float>(hipStream_t, const float*, const double*, const double*, int64_t, int, double*,
+                                  Batch);
 template void launch_ubar<double>(hipStream_t, const double*, const double*, const double*, const double*, int64_t,
-                                  int, double*);
+                                  int, double*, Batch);
 template void launch_ubar<float>(hipStream_t, const float*, const float*, const double*, const double*, int64_t, int,
-                                 float*);
+                                 float*, Batch);
 template void launch_cross3_partial<double>(hipStream_t, const double*, const double*, const double*, const double*,
                                             const double*, int64_t, int, int, double*, int*);
 template void launch_cross3_partial<float>(hipStream_t, const float*, const float*, const float*, const float*,

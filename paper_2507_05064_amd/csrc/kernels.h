@@ -3,17 +3,22 @@
 #include "common.h"
 
 // dense.hip
-void launch_cov_zz(hipStream_t st, const double* Z, int m, int mp, const CovParams& p, double tau_m, double* S);
+// Batched forms: with bt.bp set, nprob problems (matrices mp x mp apart,
+// per-problem outputs ostride apart); the defaults are one problem.
+void launch_cov_zz(hipStream_t st, const double* Z, int m, int mp, const CovParams& p, double tau_m, double* S,
+                   Batch bt = Batch{nullptr, nullptr}, int nprob = 1);
 void launch_chol_inv(hipStream_t st, double* S, double* Linv, double* work, int m, int mp, double* out, int* status,
-                     int code);
-void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp, double scale = 1.0);
+                     int code, int nmat = 1, int ostride = 0);
+void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp, double scale = 1.0,
+                        Batch bt = Batch{nullptr, nullptr}, int nprob = 1);
 void launch_nll_final(hipStream_t st, const double* LMinv, const double* vec, const double* scal, int m, int mp,
-                      const double* logdet_mprime, int64_t n, double* out);
+                      const double* logdet_mprime, int64_t n, double* out, Batch bt = Batch{nullptr, nullptr},
+                      int nprob = 1, int ostride = 0);
 
 // whiten.hip: V = L_m^{-1} K(Z, X) (or L_m^{-1} dK/drho(Z, X)), stored n x mp
 template <typename T>
 void launch_whiten(hipStream_t st, const double* X, const double* Z, const double* Linv, int m, int mp, int64_t n,
-                   const CovParams& p, bool deriv, T* V);
+                   const CovParams& p, bool deriv, T* V, Batch bt = Batch{nullptr, nullptr});
 // per-point |V_i|^2 in FP64 (for the neighbour-selection variances)
 template <typename T>
 void launch_rownorm(hipStream_t st, const T* V, int64_t n, int mp, double* out);
@@ -25,7 +30,7 @@ void launch_knn(hipStream_t st, const double* X, const double* V, const double* 
 // factor.hip
 template <typename T>
 void launch_factor(hipStream_t st, const double* X, const T* V, const int32_t* nbr, int64_t n, int mp, int mv,
-                   const CovParams& p, T* A, double* D, T* U, int* status);
+                   const CovParams& p, T* A, double* D, T* U, int* status, Batch bt = Batch{nullptr, nullptr});
 template <typename T>
 void launch_ytilde(hipStream_t st, const T* A, const double* D, const int32_t* nbr, const double* y, int64_t n,
                    int mv, double* yt);
@@ -36,29 +41,37 @@ void launch_gram_partial(hipStream_t st, const T* U, int64_t n, int mp, int chun
 template <typename T>
 void launch_uty_partial(hipStream_t st, const T* U, const double* yt, const double* D, int64_t n, int mp, int chunk,
                         double* partial);
-void launch_vec_reduce(hipStream_t st, const double* partial, int nchunk, int len, double* out);
+void launch_vec_reduce(hipStream_t st, const double* partial, int nchunk, int len, double* out,
+                       Batch bt = Batch{nullptr, nullptr}, int nprob = 1);
 
 // factor.hip (adjoint)
 template <typename T>
 void launch_factor_bwd(hipStream_t st, const double* X, const T* V, const T* Vr, const int32_t* nbr, const double* y,
                        const T* U, const T* Ubar, const double* e, const double* yt, const double* D, int64_t n,
-                       int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status);
+                       int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status,
+                       Batch bt = Batch{nullptr, nullptr});
 
 // grad.hip
-void launch_gemm_sq(hipStream_t st, const double* A, const double* B, double* C, int mp, bool ta, bool tb);
+void launch_gemm_sq(hipStream_t st, const double* A, const double* B, double* C, int mp, bool ta, bool tb,
+                    int nmat = 1);
 template <typename T>
-void launch_prep_w(hipStream_t st, const double* Minv, const double* b, int mp, double* w, T* MinvT);
+void launch_prep_w(hipStream_t st, const double* Minv, const double* b, int mp, double* w, T* MinvT, int nprob = 1,
+                   int bstride = 0);
 template <typename T>
-void launch_resid(hipStream_t st, const T* U, const double* w, const double* yt, int64_t n, int mp, double* e);
+void launch_resid(hipStream_t st, const T* U, const double* w, const double* yt, int64_t n, int mp, double* e,
+                  Batch bt = Batch{nullptr, nullptr});
 template <typename T>
 void launch_ubar(hipStream_t st, const T* U, const T* Minv, const double* e, const double* w, int64_t n, int mp,
-                 T* Ubar);
+                 T* Ubar, Batch bt = Batch{nullptr, nullptr});
 template <typename T>
 void launch_cross3_partial(hipStream_t st, const T* V, const T* Q1, const T* U, const T* Gs, const T* Bs, int64_t n,
                            int mp, int chunk, double* partial, int* nchunk_out);
-void launch_reduce_sym(hipStream_t st, const double* partial, int nchunk, int mp, double* out);
+void launch_reduce_sym(hipStream_t st, const double* partial, int nchunk, int mp, double* out,
+                       Batch bt = Batch{nullptr, nullptr}, int nprob = 1);
 void launch_sigma_m_grad(hipStream_t st, const double* Tm, const double* Z, int m, int mp, const CovParams& p,
-                         double* rowpart);
+                         double* rowpart, Batch bt = Batch{nullptr, nullptr}, int nprob = 1);
+void launch_batch_grad_final(hipStream_t st, const double* tpart, const double* rowpart, int m, Batch bt, int nprob,
+                             double* out, int ostride);
 int launch_colsum(hipStream_t st, const double* in, int64_t rows, int cols, double* out);
 void launch_reverse_lists(hipStream_t st, const int32_t* nbr, int64_t n, int mv, int* cnt, int* ptr, int* cursor,
                           int* idx);
@@ -98,10 +111,10 @@ template <typename T>
 void launch_wgram_partial(hipStream_t st, const T* U, const double* sw, int64_t n, int mp, int chunk, double* partial,
                           int* nchunk_out);
 template <typename T>
-void launch_trsv_fwd(hipStream_t st, const int* order, const int* lvl, int nlev, const int32_t* nbr, const T* A,
-                     const double* x, int mv, double* z);
+void launch_trsv_fwd(hipStream_t st, const int* order, const int* lvl, const int* hlvl, int nlev, const int32_t* nbr,
+                     const T* A, const double* x, int mv, double* z);
 template <typename T>
-void launch_trsv_bwd(hipStream_t st, const int* order, const int* lvl, int nlev, const int* rev_ptr,
+void launch_trsv_bwd(hipStream_t st, const int* order, const int* lvl, const int* hlvl, int nlev, const int* rev_ptr,
                      const int* rev_idx, const T* A, const double* x, int mv, double* z);
 void launch_chol_apply(hipStream_t st, const double* Linv, const double* c, int mp, double* tmp, double* out);
 void launch_axpy(hipStream_t st, double* y, const double* x, const double* eta, int64_t n);

@@ -89,38 +89,68 @@ __global__ void k_bw(const T* __restrict__ A, const double* __restrict__ D, cons
 }
 
 // per-chunk partials of U^T (scale .* v): partial[chunk][mp]; scale may be null
+// partial[chunk] = sum_{p in chunk} U_p (v_p scale_p)   (m_p-vector per chunk)
+// 8 waves per chunk take every 8th point; lane l owns columns l, l + 64, ...
+// (coalesced row reads); the waves' sums are added in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_utv(const T* __restrict__ U, const double* __restrict__ v,
+__global__ __launch_bounds__(512) void k_utv(const T* __restrict__ U, const double* __restrict__ v,
                                              const double* __restrict__ scale, int64_t n, int mp, int chunk,
                                              double* __restrict__ partial) {
+  __shared__ double red[8][1024];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t pbeg = (int64_t)blockIdx.x * chunk;
   const int64_t pend = min(n, pbeg + chunk);
-  for (int l = threadIdx.x; l < mp; l += 256) {
-    double s = 0.0;
-    for (int64_t p = pbeg; p < pend; ++p) {
-      const double vv = scale ? v[p] * scale[p] : v[p];
-      s += (double)U[(size_t)p * mp + l] * vv;
+  double acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+  for (int64_t p = pbeg + w; p < pend; p += 8) {
+    const double vv = scale ? v[p] * scale[p] : v[p];
+    const T* row = U + (size_t)p * mp;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int l = lane + 64 * c;
+      if (l < mp) acc[c] += (double)row[l] * vv;
     }
+  }
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int l = lane + 64 * c;
+    if (l < mp) red[w][l] = acc[c];
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < mp; l += 512) {
+    double s = 0.0;
+    for (int k = 0; k < 8; ++k) s += red[k][l];
     partial[(size_t)blockIdx.x * mp + l] = s;
   }
 }
 
-// c = sum_chunks partial; out = Minv c  (Minv full symmetric mp x mp), one workgroup
-__global__ __launch_bounds__(256) void k_reduce_apply(const double* __restrict__ partial, int nchunk, int mp,
-                                                      const double* __restrict__ Minv, double* __restrict__ cbuf,
-                                                      double* __restrict__ out) {
-  for (int l = threadIdx.x; l < mp; l += 256) {
-    double s = 0.0;
-    for (int c = 0; c < nchunk; ++c) s += partial[(size_t)c * mp + l];
-    cbuf[l] = s;
-  }
+// cbuf[l] = sum_chunks partial[chunk][l]: 64 columns per workgroup, the 4
+// waves take every 4th chunk, fixed-order combination
+__global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ partial, int nchunk, int mp,
+                                                   double* __restrict__ cbuf) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = blockIdx.x * 64 + lane;
+  double s = 0.0;
+  if (l < mp)
+    for (int c = w; c < nchunk; c += 4) s += partial[(size_t)c * mp + l];
+  red[w][lane] = s;
   __syncthreads();
-  for (int l = threadIdx.x; l < mp; l += 256) {
-    const double* row = Minv + (size_t)l * mp;
-    double s = 0.0;
-    for (int c = 0; c < mp; ++c) s += row[c] * cbuf[c];
-    out[l] = s;
-  }
+  if (w == 0 && l < mp) cbuf[l] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+}
+
+// out = Minv cbuf (Minv full mp x mp): one wave per row
+__global__ __launch_bounds__(256) void k_symv(const double* __restrict__ Minv, const double* __restrict__ cbuf, int mp,
+                                              double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (l >= mp) return;
+  const double* row = Minv + (size_t)l * mp;
+  double s = 0.0;
+  for (int c = lane; c < mp; c += 64) s += row[c] * cbuf[c];
+  s = wave_sum(s);
+  if (lane == 0) out[l] = s;
 }
 
 // out_i = (t_i - U_i . c) * f_i   (one wave per point), f = D^{-1/2}
@@ -293,20 +323,42 @@ __global__ __launch_bounds__(256) void k_wgram_partial(const T* __restrict__ U, 
 
 // Level-scheduled sparse unit-triangular solves, one workgroup of 1024
 // threads sweeping the levels in order (a level only reads earlier levels).
-// Forward, B z = x:   z_i = x_i + sum_j A_ij z_{N(i)_j}
+// Level-scheduled unit-triangular solves with B (points of one level are
+// independent). Runs of small levels go to one workgroup that walks them
+// with a barrier between levels, one thread per point, each thread issuing
+// all the loads of its point before using any; z written by one wave is read
+// by others only after the level's barrier. A level with at least
+// kWideLevel points gets a launch of its own over the whole GPU with 32
+// lanes per point (coalesced row loads, parallel gathers); kernel order on
+// the stream separates the levels.
+constexpr int kWideLevel = 1024;
+
+// Forward, B z = x:   z_i = x_i + sum_j A_ij z_{N(i)_j}   (levels L0 .. L1-1)
 template <typename T>
 __global__ __launch_bounds__(1024) void k_trsv_fwd(const int* __restrict__ order, const int* __restrict__ lvl,
-                                                   int nlev, const int32_t* __restrict__ nbr,
+                                                   int L0, int L1, const int32_t* __restrict__ nbr,
                                                    const T* __restrict__ A, const double* __restrict__ x, int mv,
-                                                   double* __restrict__ z) {
-  for (int L = 0; L < nlev; ++L) {
+                                                   double* z) {
+  for (int L = L0; L < L1; ++L) {
     const int beg = lvl[L], end = lvl[L + 1];
     for (int q = beg + threadIdx.x; q < end; q += 1024) {
       const int i = order[q];
+      const int32_t* nr = nbr + (size_t)i * mv;
+      const T* ar = A + (size_t)i * mv;
       double s = x[i];
-      for (int a = 0; a < mv; ++a) {
-        const int j = nbr[(size_t)i * mv + a];
-        if (j >= 0) s += (double)A[(size_t)i * mv + a] * z[j];
+      for (int a0 = 0; a0 < mv; a0 += 16) {
+        int j[16];
+        double av[16], zv[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const bool ok = a0 + k < mv;
+          j[k] = ok ? nr[a0 + k] : -1;
+          av[k] = ok ? (double)ar[a0 + k] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) zv[k] = j[k] >= 0 ? z[j[k]] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += av[k] * zv[k];
       }
       z[i] = s;
     }
@@ -314,25 +366,75 @@ __global__ __launch_bounds__(1024) void k_trsv_fwd(const int* __restrict__ order
   }
 }
 
-// Transposed, B^T z = x:  z_j = x_j + sum_{(q,slot): N(q)_slot = j} A_{q,slot} z_q
+// one wide level of the forward solve: 32 lanes per point (m_v <= 31)
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_fwd_wide(const int* __restrict__ order, int beg, int end,
+                                                        const int32_t* __restrict__ nbr, const T* __restrict__ A,
+                                                        const double* __restrict__ x, int mv, double* z) {
+  const int lane = threadIdx.x & 31;
+  const int q = beg + blockIdx.x * 8 + (threadIdx.x >> 5);
+  if (q >= end) return;
+  const int i = order[q];
+  double s = 0.0;
+  if (lane < mv) {
+    const int j = nbr[(size_t)i * mv + lane];
+    if (j >= 0) s = (double)A[(size_t)i * mv + lane] * z[j];
+  }
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
+  if (lane == 0) z[i] = x[i] + s;
+}
+
+// Transposed, B^T z = x:  z_j = x_j + sum_{(q,slot): N(q)_slot = j} A_{q,slot} z_q   (levels L0 .. L1-1)
 template <typename T>
 __global__ __launch_bounds__(1024) void k_trsv_bwd(const int* __restrict__ order, const int* __restrict__ lvl,
-                                                   int nlev, const int* __restrict__ rev_ptr,
+                                                   int L0, int L1, const int* __restrict__ rev_ptr,
                                                    const int* __restrict__ rev_idx, const T* __restrict__ A,
-                                                   const double* __restrict__ x, int mv, double* __restrict__ z) {
-  for (int L = 0; L < nlev; ++L) {
+                                                   const double* __restrict__ x, int mv, double* z) {
+  for (int L = L0; L < L1; ++L) {
     const int beg = lvl[L], end = lvl[L + 1];
     for (int q = beg + threadIdx.x; q < end; q += 1024) {
       const int j = order[q];
       double s = x[j];
-      for (int e = rev_ptr[j]; e < rev_ptr[j + 1]; ++e) {
-        const int idx = rev_idx[e];
-        s += (double)A[idx] * z[idx / mv];
+      const int e0 = rev_ptr[j], e1 = rev_ptr[j + 1];
+      for (int e = e0; e < e1; e += 16) {
+        int idx[16];
+        double av[16], zv[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) idx[k] = e + k < e1 ? rev_idx[e + k] : -1;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          av[k] = idx[k] >= 0 ? (double)A[idx[k]] : 0.0;
+          zv[k] = idx[k] >= 0 ? z[idx[k] / mv] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += av[k] * zv[k];
       }
       z[j] = s;
     }
     __syncthreads();
   }
+}
+
+// one wide level of the transposed solve: 32 lanes per point
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_bwd_wide(const int* __restrict__ order, int beg, int end,
+                                                        const int* __restrict__ rev_ptr,
+                                                        const int* __restrict__ rev_idx, const T* __restrict__ A,
+                                                        const double* __restrict__ x, int mv, double* z) {
+  const int lane = threadIdx.x & 31;
+  const int q = beg + blockIdx.x * 8 + (threadIdx.x >> 5);
+  if (q >= end) return;
+  const int j = order[q];
+  double s = 0.0;
+  const int e1 = rev_ptr[j + 1];
+  for (int e = rev_ptr[j] + lane; e < e1; e += 32) {
+    const int idx = rev_idx[e];
+    s += (double)A[idx] * z[idx / mv];
+  }
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
+  if (lane == 0) z[j] = x[j] + s;
 }
 
 // out = L^{-T} (L^{-1} c)  for L^{-1} given (lower, mp x mp): one workgroup
@@ -398,12 +500,13 @@ void launch_bw(hipStream_t st, const T* A, const double* D, const int32_t* nbr, 
 template <typename T>
 void launch_utv(hipStream_t st, const T* U, const double* v, const double* scale, int64_t n, int mp, int chunk,
                 double* partial) {
-  hipLaunchKernelGGL((k_utv<T>), dim3((unsigned)ceil_div(n, chunk)), dim3(256), 0, st, U, v, scale, n, mp, chunk,
+  hipLaunchKernelGGL((k_utv<T>), dim3((unsigned)ceil_div(n, chunk)), dim3(512), 0, st, U, v, scale, n, mp, chunk,
                      partial);
 }
 void launch_reduce_apply(hipStream_t st, const double* partial, int nchunk, int mp, const double* Minv, double* cbuf,
                          double* out) {
-  hipLaunchKernelGGL(k_reduce_apply, dim3(1), dim3(256), 0, st, partial, nchunk, mp, Minv, cbuf, out);
+  hipLaunchKernelGGL(k_colreduce, dim3((unsigned)ceil_div(mp, 64)), dim3(256), 0, st, partial, nchunk, mp, cbuf);
+  hipLaunchKernelGGL(k_symv, dim3((unsigned)ceil_div(mp, 4)), dim3(256), 0, st, Minv, cbuf, mp, out);
 }
 template <typename T>
 void launch_t_minus_uc(hipStream_t st, const T* U, const double* c, const double* t, const double* D, int64_t n,
@@ -451,15 +554,44 @@ void launch_wgram_partial(hipStream_t st, const T* U, const double* sw, int64_t 
                      partial);
   *nchunk_out = nchunk;
 }
+// Host-side walk over the levels (hlvl: host copy of the level offsets):
+// consecutive levels below kWideLevel points form one single-workgroup
+// launch, every wider level one launch of its own.
 template <typename T>
-void launch_trsv_fwd(hipStream_t st, const int* order, const int* lvl, int nlev, const int32_t* nbr, const T* A,
-                     const double* x, int mv, double* z) {
-  hipLaunchKernelGGL((k_trsv_fwd<T>), dim3(1), dim3(1024), 0, st, order, lvl, nlev, nbr, A, x, mv, z);
+void launch_trsv_fwd(hipStream_t st, const int* order, const int* lvl, const int* hlvl, int nlev, const int32_t* nbr,
+                     const T* A, const double* x, int mv, double* z) {
+  int L = 0;
+  while (L < nlev) {
+    const int cnt = hlvl[L + 1] - hlvl[L];
+    if (cnt >= kWideLevel) {
+      hipLaunchKernelGGL((k_trsv_fwd_wide<T>), dim3((unsigned)ceil_div(cnt, 8)), dim3(256), 0, st, order, hlvl[L],
+                         hlvl[L + 1], nbr, A, x, mv, z);
+      ++L;
+      continue;
+    }
+    int L1 = L + 1;
+    while (L1 < nlev && hlvl[L1 + 1] - hlvl[L1] < kWideLevel) ++L1;
+    hipLaunchKernelGGL((k_trsv_fwd<T>), dim3(1), dim3(1024), 0, st, order, lvl, L, L1, nbr, A, x, mv, z);
+    L = L1;
+  }
 }
 template <typename T>
-void launch_trsv_bwd(hipStream_t st, const int* order, const int* lvl, int nlev, const int* rev_ptr,
+void launch_trsv_bwd(hipStream_t st, const int* order, const int* lvl, const int* hlvl, int nlev, const int* rev_ptr,
                      const int* rev_idx, const T* A, const double* x, int mv, double* z) {
-  hipLaunchKernelGGL((k_trsv_bwd<T>), dim3(1), dim3(1024), 0, st, order, lvl, nlev, rev_ptr, rev_idx, A, x, mv, z);
+  int L = 0;
+  while (L < nlev) {
+    const int cnt = hlvl[L + 1] - hlvl[L];
+    if (cnt >= kWideLevel) {
+      hipLaunchKernelGGL((k_trsv_bwd_wide<T>), dim3((unsigned)ceil_div(cnt, 8)), dim3(256), 0, st, order, hlvl[L],
+                         hlvl[L + 1], rev_ptr, rev_idx, A, x, mv, z);
+      ++L;
+      continue;
+    }
+    int L1 = L + 1;
+    while (L1 < nlev && hlvl[L1 + 1] - hlvl[L1] < kWideLevel) ++L1;
+    hipLaunchKernelGGL((k_trsv_bwd<T>), dim3(1), dim3(1024), 0, st, order, lvl, L, L1, rev_ptr, rev_idx, A, x, mv, z);
+    L = L1;
+  }
 }
 void launch_chol_apply(hipStream_t st, const double* Linv, const double* c, int mp, double* tmp, double* out) {
   hipLaunchKernelGGL(k_chol_apply, dim3(1), dim3(256), 0, st, Linv, c, mp, tmp, out);
@@ -494,9 +626,9 @@ template void launch_add_ve<float>(hipStream_t, const float*, const double*, con
   template void launch_q_plus_euc<T>(hipStream_t, const T*, const double*, const double*, const double*,          \
                                      const double*, int64_t, int, double*);                                       \
   template void launch_wgram_partial<T>(hipStream_t, const T*, const double*, int64_t, int, int, double*, int*);  \
-  template void launch_trsv_fwd<T>(hipStream_t, const int*, const int*, int, const int32_t*, const T*,            \
-                                   const double*, int, double*);                                                  \
-  template void launch_trsv_bwd<T>(hipStream_t, const int*, const int*, int, const int*, const int*, const T*,    \
-                                   const double*, int, double*);
+  template void launch_trsv_fwd<T>(hipStream_t, const int*, const int*, const int*, int, const int32_t*,       \
+                                   const T*, const double*, int, double*);                                        \
+  template void launch_trsv_bwd<T>(hipStream_t, const int*, const int*, const int*, int, const int*, const int*,  \
+                                   const T*, const double*, int, double*);
 INST(double)
 INST(float)

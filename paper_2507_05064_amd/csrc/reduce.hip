@@ -88,7 +88,14 @@ __global__ __launch_bounds__(256) void k_uty_partial(const T* __restrict__ U, co
   }
 }
 
-__global__ void k_vec_reduce(const double* __restrict__ partial, int nchunk, int len, double* __restrict__ out) {
+__global__ void k_vec_reduce(const double* __restrict__ partial, int nchunk, int len, double* __restrict__ out,
+                             Batch bt) {
+  if (bt.bp) {  // problem blockIdx.y: its chunk range; outputs len apart
+    const BatchProb& pb = bt.bp[blockIdx.y];
+    partial += (size_t)pb.cbeg * len;
+    nchunk = pb.nchunk;
+    out += (size_t)blockIdx.y * len;
+  }
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= len) return;
   double s = 0.0;
@@ -112,8 +119,9 @@ void launch_uty_partial(hipStream_t st, const T* U, const double* yt, const doub
   hipLaunchKernelGGL((k_uty_partial<T>), dim3(nchunk), dim3(256), 0, st, U, yt, D, n, mp, chunk, partial);
 }
 
-void launch_vec_reduce(hipStream_t st, const double* partial, int nchunk, int len, double* out) {
-  hipLaunchKernelGGL(k_vec_reduce, dim3((unsigned)ceil_div(len, 256)), dim3(256), 0, st, partial, nchunk, len, out);
+void launch_vec_reduce(hipStream_t st, const double* partial, int nchunk, int len, double* out, Batch bt, int nprob) {
+  hipLaunchKernelGGL(k_vec_reduce, dim3((unsigned)ceil_div(len, 256), nprob), dim3(256), 0, st, partial, nchunk, len,
+                     out, bt);
 }
 
 template void launch_gram_partial<double>(hipStream_t, const double*, int64_t, int, int, double*, int*);

@@ -13,7 +13,14 @@
 template <typename T, bool DERIV>
 __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ X, const double* __restrict__ Z,
                                                 const double* __restrict__ Linv, int m, int mp, int64_t n,
-                                                CovParams p, T* __restrict__ V) {
+                                                CovParams p_in, T* __restrict__ V, Batch bt) {
+  CovParams p = p_in;
+  if (bt.bp) {  // the 64-point tile lies in one problem: its Z, L_m^{-1} and parameters
+    const int b = bt.blk2prob[((int64_t)blockIdx.x * 64) / kBatchBlock];
+    p = bt.bp[b].cp;
+    Z += (size_t)b * m * p.d;
+    Linv += (size_t)b * mp * mp;
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c = lane & 15, g = lane >> 4;
   const int64_t pt = (int64_t)blockIdx.x * 64 + 16 * w + c;
@@ -70,12 +77,12 @@ __global__ __launch_bounds__(256) void k_rownorm(const T* __restrict__ V, int64_
 
 template <typename T>
 void launch_whiten(hipStream_t st, const double* X, const double* Z, const double* Linv, int m, int mp, int64_t n,
-                   const CovParams& p, bool deriv, T* V) {
+                   const CovParams& p, bool deriv, T* V, Batch bt) {
   dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(mp, 128));
   if (deriv)
-    hipLaunchKernelGGL((k_whiten<T, true>), grid, dim3(256), 0, st, X, Z, Linv, m, mp, n, p, V);
+    hipLaunchKernelGGL((k_whiten<T, true>), grid, dim3(256), 0, st, X, Z, Linv, m, mp, n, p, V, bt);
   else
-    hipLaunchKernelGGL((k_whiten<T, false>), grid, dim3(256), 0, st, X, Z, Linv, m, mp, n, p, V);
+    hipLaunchKernelGGL((k_whiten<T, false>), grid, dim3(256), 0, st, X, Z, Linv, m, mp, n, p, V, bt);
 }
 
 template <typename T>
@@ -84,8 +91,8 @@ void launch_rownorm(hipStream_t st, const T* V, int64_t n, int mp, double* out) 
 }
 
 template void launch_whiten<double>(hipStream_t, const double*, const double*, const double*, int, int, int64_t,
-                                    const CovParams&, bool, double*);
+                                    const CovParams&, bool, double*, Batch);
 template void launch_whiten<float>(hipStream_t, const double*, const double*, const double*, int, int, int64_t,
-                                   const CovParams&, bool, float*);
+                                   const CovParams&, bool, float*, Batch);
 template void launch_rownorm<double>(hipStream_t, const double*, int64_t, int, double*);
 template void launch_rownorm<float>(hipStream_t, const float*, int64_t, int, double*);

@@ -41,6 +41,11 @@ class vif_config(ctypes.Structure):
                 ("newton_maxit", ctypes.c_int32), ("newton_tol", ctypes.c_double), ("lik_param", ctypes.c_double)]
 
 
+class vif_batch_config(ctypes.Structure):
+    _fields_ = [("nprob", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32), ("m_v", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("precision", ctypes.c_int32), ("tau_m", ctypes.c_double)]
+
+
 class vif_laplace_stats(ctypes.Structure):
     _fields_ = [("newton_iters", ctypes.c_int32), ("pcg_iters_total", ctypes.c_int32),
                 ("pcg_iters", ctypes.c_int32 * 64), ("halvings", ctypes.c_int32), ("converged", ctypes.c_int32),
@@ -58,7 +63,9 @@ class vif_laplace_stats(ctypes.Structure):
 EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors", "vif_build_factor", "vif_nll",
            "vif_nll_grad", "vif_export_factor", "vif_set_timing", "vif_timing_stages", "vif_timing_stage_name",
            "vif_get_timing", "vif_laplace_mode", "vif_mlp_num_params", "vif_mlp_workspace_floats",
-           "vif_mlp_forward", "vif_mlp_backward", "vif_mlp_adam", "vif_mlp_features", "vif_sample_prior"]
+           "vif_mlp_forward", "vif_mlp_backward", "vif_mlp_adam", "vif_mlp_features", "vif_sample_prior",
+           "vif_precond_solve", "vif_batch_create", "vif_batch_destroy", "vif_batch_last_error",
+           "vif_batch_nll_grad"]
 
 
 def load_library(path: Optional[str] = None):
@@ -97,6 +104,17 @@ def load_library(path: Optional[str] = None):
     lib.vif_get_timing.restype = ctypes.c_int
     lib.vif_laplace_mode.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vif_laplace_stats)]
     lib.vif_laplace_mode.restype = ctypes.c_int
+    lib.vif_precond_solve.argtypes = [vp, vp, vp, vp]
+    lib.vif_precond_solve.restype = ctypes.c_int
+    lib.vif_batch_create.argtypes = [ctypes.POINTER(vif_batch_config), ctypes.POINTER(ctypes.c_int64), vp,
+                                     ctypes.POINTER(vp)]
+    lib.vif_batch_create.restype = ctypes.c_int
+    lib.vif_batch_destroy.argtypes = [vp]
+    lib.vif_batch_destroy.restype = None
+    lib.vif_batch_last_error.argtypes = [vp]
+    lib.vif_batch_last_error.restype = ctypes.c_char_p
+    lib.vif_batch_nll_grad.argtypes = [vp, vp, vp, vp, dp, vp, dp, dp]
+    lib.vif_batch_nll_grad.restype = ctypes.c_int
     lib.vif_mlp_num_params.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.vif_mlp_num_params.restype = ctypes.c_int64
     lib.vif_mlp_workspace_floats.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
@@ -222,6 +240,11 @@ class VifContext:
         self._check(self.lib.vif_sample_prior(self.h, _ptr(eps1) if self.m else None, _ptr(eps2), _ptr(b)))
         return b
 
+    def precond_solve(self, W: torch.Tensor, r: torch.Tensor) -> torch.Tensor:
+        z = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        self._check(self.lib.vif_precond_solve(self.h, _ptr(W), _ptr(r), _ptr(z)))
+        return z
+
     def mlp_features(self, y: torch.Tensor) -> torch.Tensor:
         feat = torch.empty((self.n, MLP_FEATURES), dtype=torch.float32, device=y.device)
         self._check(self.lib.vif_mlp_features(self.h, _ptr(y), _ptr(feat)))
@@ -229,6 +252,53 @@ class VifContext:
 
 
 MLP_FEATURES = 16
+
+
+class VifBatch:
+    """One vif_batch: many independent Gaussian problems (sizes n_list) that
+    share d, m, m_v, the kernel and the precision form."""
+
+    def __init__(self, n_list: Sequence[int], d: int, m: int, m_v: int, kernel: str = "matern32",
+                 precision: str = "fp32", tau_m: float = 0.0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the VIF library has no CPU path")
+        self.lib = load_library()
+        self.n_list = [int(v) for v in n_list]
+        self.nprob = len(self.n_list)
+        self.cfg = vif_batch_config(self.nprob, d, m, m_v, KERNELS[kernel], PRECISIONS[precision], tau_m)
+        nn = (ctypes.c_int64 * self.nprob)(*self.n_list)
+        self.stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = self.lib.vif_batch_create(ctypes.byref(self.cfg), nn, ctypes.c_void_p(self.stream.cuda_stream),
+                                       ctypes.byref(h))
+        if rc != 0:
+            raise VifError(rc, "vif_batch_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.vif_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nll_grad(self, X: torch.Tensor, Z: torch.Tensor, nbr: torch.Tensor, theta, y: torch.Tensor,
+                 grad: bool = True):
+        """theta: nprob x 3 (sigma1^2, range, nugget). Returns (nll[nprob],
+        grad[nprob, 3] or None) as numpy arrays."""
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(self.nprob, 3))
+        nll = np.zeros(self.nprob)
+        g = np.zeros((self.nprob, 3)) if grad else None
+        dptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        rc = self.lib.vif_batch_nll_grad(self.h, _ptr(X), _ptr(Z), _ptr(nbr), dptr(th), _ptr(y), dptr(nll),
+                                         dptr(g) if grad else None)
+        if rc != 0:
+            raise VifError(rc, self.lib.vif_batch_last_error(self.h).decode())
+        return nll, g
 
 
 class VifNLLFunction(torch.autograd.Function):
