@@ -129,7 +129,8 @@ def laplace_leg(reps, warmup, log):
         out[form] = {"mode_ms_median": _pct(ms, 50), "mode_ms_p10": _pct(ms, 10), "mode_ms_p90": _pct(ms, 90),
                      "newton_iters": st["newton_iters"], "pcg_iters_total": st["pcg_iters_total"],
                      "pcg_iters": st["pcg_iters"], "halvings": st["halvings"], "start_used": st["start_used"],
-                     "psi": st["psi"]}
+                     "psi": st["psi"], "levels_fwd": st["levels_fwd"], "levels_bwd": st["levels_bwd"],
+                     "wide_fwd": st["wide_fwd"], "wide_bwd": st["wide_bwd"]}
         log(f"laplace {form}: {out[form]}")
     b0 = mlp.forward(ctx.mlp_features(prob.y), double=True)
     ref = modes["zero"]

@@ -88,6 +88,10 @@ typedef struct {
   double pcg_rel_residual;  /* relative residual of the last CG solve */
   int32_t start_used;       /* 1: the given start b0 was kept; 0: the zero start */
   double psi_start;         /* objective at the start used */
+  int32_t levels_fwd;       /* levels of the B^{-1} solve (dependency depth) */
+  int32_t levels_bwd;       /* levels of the B^{-T} solve */
+  int32_t wide_fwd;         /* of which with >= 1024 points (whole-GPU launches) */
+  int32_t wide_bwd;
 } vif_laplace_stats;
 
 typedef struct vif_ctx vif_ctx;
@@ -184,6 +188,30 @@ vif_status vif_mlp_adam(float* params, const float* grad, float* m, float* v, in
  * mean length scale, the mean of y, the mean over N(i) of the second
  * feature, y_i minus the second feature, then zeros. */
 vif_status vif_mlp_features(vif_ctx* ctx, const double* y, float* feat_out);
+
+/* Laplace negative log-marginal likelihood (eq. log_det_VIFLA) at a given
+ * mode b (device, n doubles; normally the output of vif_laplace_mode):
+ *   -log p(y|b) + b^T Sigma_dagger^{-1} b / 2 + log det(Sigma_dagger W + I) / 2,
+ * W = W(b) (eq. W_diag). The log-determinant is
+ *   log det Sigma_dagger + log det P + log det(P^{-1/2} A P^{-1/2}),
+ * A = W + Sigma_dagger^{-1}, P the VIFDU preconditioner (App. E.1); the
+ * first two terms in closed form (sum_i log(1 + D_i W_i) + log det M3', M3'
+ * as for vif_precond_solve), the last by stochastic Lanczos quadrature
+ * (Sec. 4.2, eq. slq_v1): for each of ell probes z_k ~ N(0, P),
+ * preconditioned CG from 0 on A x = z_k (to cfg.cg_tol) gives the Lanczos
+ * matrix T_k from its coefficients (T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+ * T_{j,j+1} = sqrt(beta_j)/alpha_j), and the term is the mean of
+ * (z_k^T P^{-1} z_k) e_1^T log(T_k) e_1 (exact normalisation).
+ * The probes come from caller-supplied standard normals (device):
+ * eps_n ((2 ell) x n: rows e1_0, e2_0, e1_1, e2_1, ...) and eps_m (ell x m):
+ *   z_k = B^T W^{1/2} e1_k + Sigma_dagger^{-1} (V^T e3_k + B^{-1} D^{1/2} e2_k),
+ * V^T e3 = Sigma_mn^T L_m^{-T} e3. nll_out (host) gets the NLL, logdet_out
+ * (host, may be NULL) the estimate of log det(Sigma_dagger W + I). The solves
+ * A^{-1} z_k and P^{-1} z_k are kept in the context for a following gradient
+ * call. The first call with a given ell allocates its workspace. Errors:
+ * VIF_E_CG_MAXIT, VIF_E_NOT_PD (M3'), VIF_E_NAN. */
+vif_status vif_laplace_nll(vif_ctx* ctx, const double* y, const double* mode, int32_t ell, const double* eps_n,
+                           const double* eps_m, double* nll_out, double* logdet_out);
 
 /* Applies the VIFDU preconditioner of Sec. 4.3.1 / App. E.1 for a given
  * diagonal W: z = P^{-1} r with P = B^T W B + Sigma_dagger^{-1}, in the

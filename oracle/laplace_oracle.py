@@ -255,3 +255,238 @@ def vifdu_logdet(prior: LatentVIF, W: np.ndarray) -> float:
         M3 = M - H.T @ (C[:, None] * H)
         v += -np.linalg.slogdet(M)[1] + np.linalg.slogdet(M3)[1]
     return v
+
+
+# ----------------------------------------------------------------------------
+# Laplace NLL and its gradient by stochastic Lanczos quadrature and stochastic
+# trace estimation (Sec. 4.2 eq. slq_v1 with the VIFDU preconditioner of
+# Sec. 4.3.1; gradient of App. B with the estimators of App. D)
+# ----------------------------------------------------------------------------
+
+def dense_B(prior: LatentVIF) -> np.ndarray:
+    return prior.Bsp.toarray()
+
+
+def dense_cov(prior: LatentVIF) -> np.ndarray:
+    """Sigma_dagger = B^{-1} D B^{-T} + Sigma_mn^T Sigma_m^{-1} Sigma_mn (Sec. 3)."""
+    Binv = np.linalg.inv(dense_B(prior))
+    S = Binv @ (prior.fac.D[:, None] * Binv.T)
+    if prior.ind.m:
+        S = S + prior.ind.Smn.T @ prior.ind.W
+    return S
+
+
+def dB_dense(prior: LatentVIF, dA: np.ndarray) -> np.ndarray:
+    """dB: B_{i,N(i)} = -A_i, so dB_{i,N(i)} = -dA_i."""
+    n = prior.n
+    out = np.zeros((n, n))
+    for s_ in range(prior.nbr.shape[1]):
+        v = prior.nbr[:, s_] >= 0
+        out[np.nonzero(v)[0], prior.nbr[v, s_]] = -dA[v, s_]
+    return out
+
+
+def cov_tangent_dense(prior: LatentVIF, tg: vo.FactorTangent) -> np.ndarray:
+    """d Sigma_dagger / d theta_p by the product rule on B^{-1} D B^{-T} and
+    Sigma_mn^T Sigma_m^{-1} Sigma_mn (d B^{-1} = -B^{-1} dB B^{-1})."""
+    Binv = np.linalg.inv(dense_B(prior))
+    dBinv = -Binv @ dB_dense(prior, tg.dA) @ Binv
+    D = prior.fac.D
+    dS = dBinv @ (D[:, None] * Binv.T) + Binv @ (tg.dD[:, None] * Binv.T) + Binv @ (D[:, None] * dBinv.T)
+    if prior.ind.m:
+        Wm = prior.ind.W  # Sigma_m^{-1} Sigma_mn
+        dS = dS + tg.dSmn.T @ Wm + Wm.T @ tg.dSmn - Wm.T @ tg.dSm @ Wm
+    return dS
+
+
+def prec_tangent_dense(prior: LatentVIF, tg: vo.FactorTangent, S=None) -> np.ndarray:
+    """d Sigma_dagger^{-1} / d theta_p = -Sigma^{-1} dSigma Sigma^{-1}."""
+    Si = np.linalg.inv(dense_cov(prior) if S is None else S)
+    return -Si @ cov_tangent_dense(prior, tg) @ Si
+
+
+def vifdu_tangent_dense(prior: LatentVIF, tg: vo.FactorTangent, W: np.ndarray, dPrec: np.ndarray) -> np.ndarray:
+    """d P / d theta_p for P = B^T W B + Sigma_dagger^{-1} (App. E.1), W fixed."""
+    B = dense_B(prior)
+    dB = dB_dense(prior, tg.dA)
+    return dB.T @ (W[:, None] * B) + B.T @ (W[:, None] * dB) + dPrec
+
+
+def vifdu_probes(prior: LatentVIF, W: np.ndarray, e1: np.ndarray, e2: np.ndarray, e3: np.ndarray) -> np.ndarray:
+    """Probe vectors z ~ N(0, P), P = B^T W B + Sigma_dagger^{-1}, from
+    standard normals e1, e2 (n x l) and e3 (m x l):
+      z = B^T W^{1/2} e1 + Sigma_dagger^{-1} x,  x = B^{-1} D^{1/2} e2 + Sigma_mn^T L_m^{-T} e3,
+    where x ~ N(0, Sigma_dagger) is a prior draw, so Cov(z) = B^T W B + Sigma_dagger^{-1}."""
+    from scipy.sparse.linalg import spsolve_triangular
+    sw = np.sqrt(W)
+    Z = np.zeros_like(e1)
+    Lm = np.tril(prior.ind.cf[0]) if prior.ind.m else None
+    for k in range(e1.shape[1]):
+        x = spsolve_triangular(prior.Bsp.tocsr(), np.sqrt(prior.fac.D) * e2[:, k], lower=True)
+        if prior.ind.m:
+            x = x + prior.ind.Smn.T @ np.linalg.solve(Lm.T, e3[:, k])
+        Z[:, k] = prior.Bsp.T @ (sw * e1[:, k]) + prior.prec_matvec(x)
+    return Z
+
+
+@dataclasses.dataclass
+class PCGRun:
+    x: np.ndarray        # A^{-1} b
+    pz0: np.ndarray      # P^{-1} b (the first preconditioned residual)
+    alphas: np.ndarray
+    betas: np.ndarray
+    bPb: float           # b^T P^{-1} b = ||P^{-1/2} b||^2
+    iters: int
+
+
+def pcg_run(matvec, psolve, b: np.ndarray, tol: float = 1e-10, maxit: int = 10000) -> PCGRun:
+    """Preconditioned CG from x_0 = 0 to ||r|| <= tol ||b||, keeping its
+    step lengths alpha_j and direction coefficients beta_j."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = psolve(r)
+    pz0 = z.copy()
+    p = z.copy()
+    rz = r @ z
+    bPb = float(rz)
+    alphas, betas = [], []
+    nb = np.linalg.norm(b)
+    it = 0
+    while it < maxit and np.linalg.norm(r) > tol * nb:
+        Ap = matvec(p)
+        a = rz / (p @ Ap)
+        x += a * p
+        r -= a * Ap
+        z = psolve(r)
+        rz_new = r @ z
+        bta = rz_new / rz
+        alphas.append(a)
+        betas.append(bta)
+        p = z + bta * p
+        rz = rz_new
+        it += 1
+    return PCGRun(x, pz0, np.array(alphas), np.array(betas), bPb, it)
+
+
+def lanczos_from_cg(alphas: np.ndarray, betas: np.ndarray) -> np.ndarray:
+    """Tridiagonal Lanczos matrix of the preconditioned operator from the CG
+    coefficients (the relation Sec. 4.2 cites, Saad 2003):
+      T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},  T_{j,j+1} = sqrt(beta_j)/alpha_j."""
+    k = len(alphas)
+    T = np.zeros((k, k))
+    for j in range(k):
+        T[j, j] = 1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0)
+        if j + 1 < k:
+            T[j, j + 1] = T[j + 1, j] = math.sqrt(betas[j]) / alphas[j]
+    return T
+
+
+def e1_log_e1(T: np.ndarray) -> float:
+    """e_1^T log(T) e_1 by the eigendecomposition of the tridiagonal T."""
+    lam, Q = np.linalg.eigh(T)
+    return float(np.sum(Q[0, :] ** 2 * np.log(lam)))
+
+
+@dataclasses.dataclass
+class LaplaceSLQ:
+    nll: float
+    logdet: float            # estimate of log det(Sigma_dagger W + I)
+    slq_terms: np.ndarray    # per probe: ||P^{-1/2} z||^2 e_1^T log(T) e_1
+    runs: list               # PCGRun per probe
+
+
+def laplace_nll_slq(prior: LatentVIF, lik: str, y: np.ndarray, mode: np.ndarray, Z: np.ndarray,
+                    noise_var: float = 1.0, tol: float = 1e-10, psolve=None, logdet_P=None) -> LaplaceSLQ:
+    """eq. log_det_VIFLA with log det(Sigma_dagger W + I) = log det Sigma_dagger
+    + log det P + log det(P^{-1/2} A P^{-1/2}), A = W + Sigma_dagger^{-1}, the
+    last term by SLQ (eq. slq_v1) over the probes Z (columns, z ~ N(0, P)),
+    normalised by ||P^{-1/2} z||^2 = z^T P^{-1} z (the exact norm).
+    Default P: VIFDU at W(mode); psolve / logdet_P override it."""
+    _, W, _ = grad_hess(lik, y, mode, noise_var)
+    if psolve is None:
+        psolve = lambda v: vifdu_solve(prior, W, v)
+        logdet_P = vifdu_logdet(prior, W)
+    matvec = lambda v: W * v + prior.prec_matvec(v)
+    runs, terms = [], []
+    for k in range(Z.shape[1]):
+        run = pcg_run(matvec, psolve, Z[:, k], tol)
+        runs.append(run)
+        terms.append(run.bPb * e1_log_e1(lanczos_from_cg(run.alphas, run.betas)) if run.iters else 0.0)
+    terms = np.array(terms)
+    logdet = prior.logdet() + logdet_P + float(np.mean(terms))
+    nll = float(-np.sum(loglik(lik, y, mode, noise_var)) + 0.5 * mode @ prior.prec_matvec(mode) + 0.5 * logdet)
+    return LaplaceSLQ(nll, logdet, terms, runs)
+
+
+def laplace_grad_dense(prior: LatentVIF, tangents, lik: str, y: np.ndarray, mode: np.ndarray,
+                       noise_var: float = 1.0) -> np.ndarray:
+    """Exact gradient of eq. log_det_VIFLA at small n (App. B): for each theta_p
+      1/2 b^T dPrec b + 1/2 [tr(Sigma^{-1} dSigma) + tr(A^{-1} dPrec)] - v^T dPrec b,
+    v = A^{-1} dL/db, dL/db_i = 1/2 (A^{-1})_ii dW_ii/db_i (the implicit
+    term through the mode), A = W + Sigma_dagger^{-1}, dPrec = dSigma^{-1}/dtheta_p."""
+    _, W, dW = grad_hess(lik, y, mode, noise_var)
+    S = dense_cov(prior)
+    Si = np.linalg.inv(S)
+    Ainv = np.linalg.inv(np.diag(W) + Si)
+    v = Ainv @ (0.5 * np.diag(Ainv) * dW)
+    out = []
+    for tg in tangents:
+        dS = cov_tangent_dense(prior, tg)
+        dPrec = -Si @ dS @ Si
+        val = 0.5 * mode @ dPrec @ mode + 0.5 * (np.trace(Si @ dS) + np.trace(Ainv @ dPrec)) - v @ dPrec @ mode
+        out.append(val)
+    return np.array(out)
+
+
+def laplace_grad_ste(prior: LatentVIF, tangents, lik: str, y: np.ndarray, mode: np.ndarray, slq: LaplaceSLQ,
+                     noise_var: float = 1.0, tol: float = 1e-10, control_variate: bool = True) -> np.ndarray:
+    """The same gradient with stochastic trace estimates (App. D) over the
+    probes of `slq` (z_i ~ N(0, P), u_i = A^{-1} z_i, q_i = P^{-1} z_i):
+      tr(A^{-1} dPrec) ~ mean_i [u_i^T dPrec q_i - c (q_i^T dP q_i)] + c tr(P^{-1} dP),
+      c = sum_i (f_i - mean f)(g_i - tr(P^{-1} dP)) / sum_i (g_i - tr(P^{-1} dP))^2
+    (f_i = u_i^T dPrec q_i, g_i = q_i^T dP q_i; c = 0 without the control
+    variate); the diagonal (A^{-1})_ii dW_i ~ mean_i [u_i dW q_i - c_b dW (B q_i)^2]
+    + c_b dW diag(B P^{-1} B^T), with one pooled coefficient c_b for all i.
+    Every dense trace here is of P, whose closed forms the GPU uses."""
+    _, W, dW = grad_hess(lik, y, mode, noise_var)
+    S = dense_cov(prior)
+    Si = np.linalg.inv(S)
+    B = dense_B(prior)
+    P = vifdu_dense(prior, W)
+    Pi = np.linalg.inv(P)
+    U = np.column_stack([r.x for r in slq.runs])
+    Q = np.column_stack([r.pz0 for r in slq.runs])
+    ell = U.shape[1]
+    # diagonal of A^{-1}, times dW
+    h = U * Q * dW[:, None]
+    BQ = B @ Q
+    gq = dW[:, None] * BQ * BQ
+    trq = dW * np.diag(B @ Pi @ B.T)
+    cb = 0.0
+    if control_variate:
+        dg = gq - trq[:, None]
+        den = float(np.sum(dg * dg))
+        if den > 0:
+            cb = float(np.sum((h - h.mean(1, keepdims=True)) * dg)) / den
+    dhat = np.mean(h - cb * gq, axis=1) + cb * trq
+    dLdb = 0.5 * dhat
+    matvec = lambda v: W * v + prior.prec_matvec(v)
+    psolve = lambda v: vifdu_solve(prior, W, v)
+    v = pcg_run(matvec, psolve, dLdb, tol).x
+    out = []
+    for tg in tangents:
+        dS = cov_tangent_dense(prior, tg)
+        dPrec = -Si @ dS @ Si
+        dP = vifdu_tangent_dense(prior, tg, W, dPrec)
+        f = np.einsum("ik,ik->k", U, dPrec @ Q)
+        g = np.einsum("ik,ik->k", Q, dP @ Q)
+        trP = float(np.trace(Pi @ dP))
+        c = 0.0
+        if control_variate:
+            den = float(np.sum((g - trP) ** 2))
+            if den > 0:
+                c = float(np.sum((f - f.mean()) * (g - trP))) / den
+        that = float(np.mean(f - c * g)) + c * trP
+        val = 0.5 * mode @ dPrec @ mode + 0.5 * (np.trace(Si @ dS) + that) - v @ dPrec @ mode
+        out.append(val)
+    return np.array(out)

@@ -349,39 +349,33 @@ def nll_gaussian(model: Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray,
     return GaussianNLL(nll, logdet, quad, fac, ind)
 
 
-def nll_gaussian_grad(model: Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray,
-                      y: np.ndarray, chunk: int = 2048):
-    """NLL and its gradient w.r.t. theta = (sigma1^2, lambda..., s2).
+@dataclasses.dataclass
+class FactorTangent:
+    """Derivatives of the factor with respect to one parameter theta_p."""
+    dA: np.ndarray     # n x m_v
+    dD: np.ndarray     # n
+    dSm: np.ndarray    # m x m
+    dSmn: np.ndarray   # m x n
 
-    Forward mode: every quantity of nll_gaussian gets a tangent per
-    parameter (Sec. 2.2 gradient; App. A derivatives of B and D taken from
-    eq. D_A_Vecchia itself):
+
+def factor_tangents(model: Model, X: np.ndarray, Z: np.ndarray, ind: Inducing, nbr: np.ndarray, fac: Factor,
+                    chunk: int = 2048) -> List[FactorTangent]:
+    """Forward-mode derivatives of A, D (eq. D_A_Vecchia, differentiated
+    directly; App. A) and of Sigma_m, Sigma_mn for every parameter of
+    theta = (sigma1^2, lambda..., s2):
       W = Sigma_m^{-1} Sigma_mn, W' = Sigma_m^{-1}(Sigma_mn' - Sigma_m' W)
       q'(a, b) = Sigma_ma'^T W_b + Sigma_ma^T W_b'
-      A_i' = R_i^{-1}(r_i' - R_i' A_i),  D_i' = c_ii' + s2' - q'(i,i) - r_i'.A_i - r_i.A_i'
-      G = B Sigma_mn^T, t = B y, M = Sigma_m + G^T D^{-1} G and their tangents,
-      logdet' = tr(M^{-1} M') - tr(Sigma_m^{-1} Sigma_m') + sum D'/D,
-      quad' by the product rule on t^T D^{-1} t - u^T M^{-1} u, u = G^T D^{-1} t."""
+      A_i' = R_i^{-1}(r_i' - R_i' A_i),  D_i' = c_ii' + s2' - q'(i,i) - r_i'.A_i - r_i.A_i'"""
     n = X.shape[0]
-    base = nll_gaussian(model, X, Z, nbr, y)
-    ind, fac = base.ind, base.factor
-    A, D = fac.A, fac.D
+    A = fac.A
     m = ind.m
     mv = nbr.shape[1]
     cnt = neighbour_counts(nbr)
-    t = apply_B(nbr, A, y)
     npar = 1 + model.ls.size + 1
-    grads = np.zeros(npar)
-
     if m:
-        G = B_times_rows(nbr, A, ind.Smn.T)
-        M = ind.Sm + G.T @ (G / D[:, None])
-        cM = cho_factor(M, lower=True)
-        u = G.T @ (t / D)
-        Minv_u = cho_solve(cM, u)
         dSm_all = cov_grads(model, Z, Z)
         dSmn_all = cov_grads(model, Z, X)
-
+    out = []
     for p in range(npar):
         is_s2 = p == npar - 1
         ds2 = 1.0 if is_s2 else 0.0
@@ -395,6 +389,7 @@ def nll_gaussian_grad(model: Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarra
             dW = cho_solve(ind.cf, dSmn - dSm @ ind.W)
             dqdiag = np.einsum("ki,ki->i", dSmn, ind.W) + np.einsum("ki,ki->i", ind.Smn, dW)
         else:
+            dSm, dSmn = np.zeros((0, 0)), np.zeros((0, n))
             dqdiag = np.zeros(n)
         dA = np.zeros((n, mv))
         dD = dc_ii + ds2 - dqdiag
@@ -426,6 +421,39 @@ def nll_gaussian_grad(model: Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarra
                 dAi = np.linalg.solve(R, rhs[:, :, None])[:, :, 0]
                 dA[P, :k] = dAi
                 dD[P] = dD[P] - np.sum(dr * Ai, axis=1) - np.sum(r * dAi, axis=1)
+        out.append(FactorTangent(dA, dD, dSm, dSmn))
+    return out
+
+
+def nll_gaussian_grad(model: Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray,
+                      y: np.ndarray, chunk: int = 2048):
+    """NLL and its gradient w.r.t. theta = (sigma1^2, lambda..., s2).
+
+    Forward mode: every quantity of nll_gaussian gets a tangent per
+    parameter (Sec. 2.2 gradient; App. A derivatives of B and D from
+    factor_tangents):
+      G = B Sigma_mn^T, t = B y, M = Sigma_m + G^T D^{-1} G and their tangents,
+      logdet' = tr(M^{-1} M') - tr(Sigma_m^{-1} Sigma_m') + sum D'/D,
+      quad' by the product rule on t^T D^{-1} t - u^T M^{-1} u, u = G^T D^{-1} t."""
+    n = X.shape[0]
+    base = nll_gaussian(model, X, Z, nbr, y)
+    ind, fac = base.ind, base.factor
+    A, D = fac.A, fac.D
+    m = ind.m
+    mv = nbr.shape[1]
+    t = apply_B(nbr, A, y)
+    tangents = factor_tangents(model, X, Z, ind, nbr, fac, chunk)
+    grads = np.zeros(len(tangents))
+
+    if m:
+        G = B_times_rows(nbr, A, ind.Smn.T)
+        M = ind.Sm + G.T @ (G / D[:, None])
+        cM = cho_factor(M, lower=True)
+        u = G.T @ (t / D)
+        Minv_u = cho_solve(cM, u)
+
+    for p, tg in enumerate(tangents):
+        dA, dD, dSm, dSmn = tg.dA, tg.dD, tg.dSm, tg.dSmn
         # tangent of t = B y
         dt = np.zeros(n)
         valid = nbr >= 0

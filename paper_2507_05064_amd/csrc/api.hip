@@ -65,10 +65,23 @@ struct vif_ctx {
   int nlev_f = 0, nlev_b = 0;
   std::vector<int> hfwd_lvl, hbwd_lvl;  // host copies of the level offsets
   bool lev_valid = false;
+  // level-ordered rows of B and B^T (see trsv.hip) and their coefficients,
+  // copied from A after each build
+  int *fcol = nullptr, *bptr = nullptr, *bcol = nullptr, *bsrc = nullptr;
+  void *fcoef = nullptr, *bcoef = nullptr;
+  bool coef_valid = false;
+  TriSchedule sf{}, sb{};
   // Laplace workspace: n-vectors, m-vectors, m x m
   double* lv = nullptr;  // 20 n-vectors
   double *lm = nullptr, *M3inv = nullptr, *L3inv = nullptr, *M3 = nullptr, *lsc = nullptr, *lpart = nullptr;
   double* hlsc = nullptr;
+  // SLQ workspace (allocated by the first Laplace-likelihood call, grown on
+  // demand): per probe the logged CG coefficients, the solves u = A^{-1} z
+  // and q = P^{-1} z (n each)
+  int slq_ell = 0, slq_ld = 0;
+  double *slq_a = nullptr, *slq_b = nullptr, *slq_rz = nullptr, *slq_terms = nullptr, *slq_work = nullptr;
+  double *slq_u = nullptr, *slq_q = nullptr;
+  int* slq_iters = nullptr;
 };
 
 static vif_status fail(vif_ctx* c, vif_status s, const char* fmt, ...) {
@@ -259,7 +272,13 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
     alloc((void**)&c->fwd_lvl, sizeof(int) * (n + 1));
     alloc((void**)&c->bwd_order, sizeof(int) * n);
     alloc((void**)&c->bwd_lvl, sizeof(int) * (n + 1));
-    alloc((void**)&c->lv, sizeof(double) * n * 20);
+    alloc((void**)&c->lv, sizeof(double) * n * 22);
+    alloc((void**)&c->fcol, sizeof(int) * mvn);
+    alloc((void**)&c->bptr, sizeof(int) * (n + 1));
+    alloc((void**)&c->bcol, sizeof(int) * mvn);
+    alloc((void**)&c->bsrc, sizeof(int) * mvn);
+    alloc(&c->fcoef, tsize(c) * mvn);
+    alloc(&c->bcoef, tsize(c) * mvn);
     alloc((void**)&c->lm, sizeof(double) * mpa * 4);
     alloc((void**)&c->M3, sizeof(double) * mpa * mpa);
     alloc((void**)&c->M3inv, sizeof(double) * mpa * mpa);
@@ -290,7 +309,8 @@ void vif_destroy(vif_ctx* c) {
                   c->e, c->Smat, c->Tm, c->tmpm, c->MinvT, c->Ubar, c->Q1, c->Gs, c->Bs, c->Vr, c->tpart,
                   c->rowpart, c->gred, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx,
                   c->fwd_order, c->fwd_lvl, c->bwd_order, c->bwd_lvl, c->lv, c->lm, c->M3, c->M3inv, c->L3inv,
-                  c->lsc, c->lpart};
+                  c->lsc, c->lpart, c->fcol, c->bptr, c->bcol, c->bsrc, c->fcoef, c->bcoef, c->slq_a, c->slq_b, c->slq_rz, c->slq_terms, c->slq_work, c->slq_u,
+                  c->slq_q, c->slq_iters};
   for (void* b : bufs)
     if (b) hipFree(b);
   for (int t = 0; t < ST_COUNT; ++t) {
@@ -424,6 +444,7 @@ vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const 
     c->lev_valid = false;
   }
   c->built = true;
+  c->coef_valid = false;
   return VIF_OK;
 }
 
@@ -567,6 +588,24 @@ vif_status vif_nll_grad(vif_ctx* c, const double* y, double* nll_out, double* gr
 // (a point only depends on earlier levels in B z = x); for B^T z = x the
 // reverse levels rlev(j) = 1 + max{rlev(q) : j in N(q)}. Computed on the host
 // (once per neighbour list, like the neighbour search itself).
+// coefficients of the level-ordered rows, copied from A after a build
+static vif_status refresh_coef(vif_ctx* c) {
+  if (c->coef_valid || c->cfg.m_v == 0) {
+    c->coef_valid = true;
+    return VIF_OK;
+  }
+  if (fp32_form(c)) {
+    launch_coef_fwd<float>(c->st, c->sf, (const float*)c->A, (float*)c->fcoef);
+    launch_coef_bwd<float>(c->st, c->sb, (const float*)c->A, (float*)c->bcoef);
+  } else {
+    launch_coef_fwd<double>(c->st, c->sf, (const double*)c->A, (double*)c->fcoef);
+    launch_coef_bwd<double>(c->st, c->sb, (const double*)c->A, (double*)c->bcoef);
+  }
+  HIPCHK(c, hipGetLastError());
+  c->coef_valid = true;
+  return VIF_OK;
+}
+
 static vif_status ensure_schedules(vif_ctx* c) {
   const vif_config& g = c->cfg;
   const int64_t n = g.n;
@@ -581,7 +620,7 @@ static vif_status ensure_schedules(vif_ctx* c) {
     }
     c->rev_valid = true;
   }
-  if (c->lev_valid) return VIF_OK;
+  if (c->lev_valid) return refresh_coef(c);
   std::vector<int32_t> nb((size_t)n * (mv > 0 ? mv : 1), -1);
   if (mv > 0) HIPCHK(c, hipMemcpyAsync(nb.data(), c->nbr, sizeof(int32_t) * n * mv, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
@@ -615,18 +654,58 @@ static vif_status ensure_schedules(vif_ctx* c) {
   c->nlev_b = schedule(rlev, bo, bp);
   c->hfwd_lvl = fp;
   c->hbwd_lvl = bp;
+  // level-ordered rows: B (fixed width m_v) and B^T (CSR over the points that
+  // have the row's point as a neighbour, in increasing (point, slot) order)
+  {
+    const int mva = mv > 0 ? mv : 1;
+    std::vector<int> fpos(n), bpos(n);
+    for (int64_t q = 0; q < n; ++q) fpos[fo[q]] = (int)q;
+    for (int64_t q = 0; q < n; ++q) bpos[bo[q]] = (int)q;
+    std::vector<int> fcol((size_t)n * mva, -1);
+    for (int64_t q = 0; q < n; ++q)
+      for (int a = 0; a < mv; ++a) {
+        const int j = nb[(size_t)fo[q] * mv + a];
+        fcol[(size_t)q * mv + a] = j >= 0 ? fpos[j] : -1;
+      }
+    std::vector<int> cnt(n, 0);
+    for (size_t e = 0; e < (size_t)n * mv; ++e)
+      if (nb[e] >= 0) cnt[nb[e]]++;
+    std::vector<int> bptr(n + 1, 0);
+    for (int64_t q = 0; q < n; ++q) bptr[q + 1] = bptr[q] + cnt[bo[q]];
+    std::vector<int> start(n);
+    for (int64_t q = 0; q < n; ++q) start[bo[q]] = bptr[q];
+    const int64_t ne = bptr[n];
+    std::vector<int> bcol(ne > 0 ? ne : 1), bsrc(ne > 0 ? ne : 1);
+    for (int64_t i = 0; i < n; ++i)  // increasing i, then slot: a fixed order per row
+      for (int a = 0; a < mv; ++a) {
+        const int j = nb[(size_t)i * mv + a];
+        if (j < 0) continue;
+        const int e = start[j]++;
+        bcol[e] = bpos[i];
+        bsrc[e] = (int)(i * mv + a);
+      }
+    HIPCHK(c, hipMemcpyAsync(c->fcol, fcol.data(), sizeof(int) * fcol.size(), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bptr, bptr.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bcol, bcol.data(), sizeof(int) * bcol.size(), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bsrc, bsrc.data(), sizeof(int) * bsrc.size(), hipMemcpyHostToDevice, c->st));
+    c->sf = TriSchedule{(int)n, mv, c->nlev_f, 0, c->fwd_order, c->fwd_lvl, nullptr, nullptr, c->fcol, nullptr};
+    c->sb = TriSchedule{(int)n, mv, c->nlev_b, ne, c->bwd_order, c->bwd_lvl, nullptr, c->bptr, c->bcol, c->bsrc};
+  }
   HIPCHK(c, hipMemcpyAsync(c->fwd_order, fo.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->fwd_lvl, fp.data(), sizeof(int) * fp.size(), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->bwd_order, bo.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->bwd_lvl, bp.data(), sizeof(int) * bp.size(), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  c->sf.hlvl = c->hfwd_lvl.data();
+  c->sb.hlvl = c->hbwd_lvl.data();
   c->lev_valid = true;
-  return VIF_OK;
+  c->coef_valid = false;
+  return refresh_coef(c);
 }
 
 // Laplace workspace views
 struct LapBufs {
-  double *b, *g, *W, *sb, *rhs, *x, *r, *z, *p, *Ap, *t, *s, *v, *q, *qd, *q2, *E, *sw, *sd, *tmp;
+  double *b, *g, *W, *sb, *rhs, *x, *r, *z, *p, *Ap, *t, *s, *v, *q, *qd, *q2, *E, *sw, *sd, *tmp, *xq, *zq;
   double *cbuf, *cp, *ctmp;
   double* sc;    // device scalars: [0] rz [1] pAp [2] - [3] rz_new [4] rr [5] - [6] eta [7..8] dots [9] ll
   double* part;  // partial sums
@@ -638,8 +717,8 @@ static LapBufs lap_bufs(vif_ctx* c) {
   double* v = c->lv;
   const int64_t n = c->cfg.n;
   double** f[] = {&B.b, &B.g, &B.W, &B.sb, &B.rhs, &B.x, &B.r, &B.z, &B.p, &B.Ap,
-                  &B.t, &B.s, &B.v, &B.q, &B.qd, &B.q2, &B.E, &B.sw, &B.sd, &B.tmp};
-  for (int k = 0; k < 20; ++k) *f[k] = v + (size_t)k * n;
+                  &B.t, &B.s, &B.v, &B.q, &B.qd, &B.q2, &B.E, &B.sw, &B.sd, &B.tmp, &B.xq, &B.zq};
+  for (int k = 0; k < 22; ++k) *f[k] = v + (size_t)k * n;
   const int mpa = c->mp > 0 ? c->mp : 1;
   B.cbuf = c->lm;
   B.cp = c->lm + mpa;
@@ -669,15 +748,14 @@ template <typename T>
 static void vifdu_apply(vif_ctx* c, LapBufs& B, const double* r, double* z) {
   const vif_config& g = c->cfg;
   const T* U = (const T*)c->U;
-  launch_trsv_bwd<T>(c->st, c->bwd_order, c->bwd_lvl, c->hbwd_lvl.data(), c->nlev_b, c->rev_ptr, c->rev_idx, (const T*)c->A, r, g.m_v,
-                     B.v);
+  launch_trsv_bwd<T>(c->st, c->sb, (const T*)c->bcoef, r, B.xq, B.zq, B.v);
   launch_scale_e(c->st, B.v, B.E, c->D, g.n, B.q, B.qd);
   if (g.m > 0) {
     launch_utv<T>(c->st, U, B.qd, nullptr, g.n, c->mp, c->chunk, B.upart);
     launch_reduce_apply(c->st, B.upart, c->nchunk, c->mp, c->M3inv, B.cbuf, B.cp);
   }
   launch_q_plus_euc<T>(c->st, U, B.cp, B.q, B.E, c->D, g.n, c->mp, B.q2);
-  launch_trsv_fwd<T>(c->st, c->fwd_order, c->fwd_lvl, c->hfwd_lvl.data(), c->nlev_f, c->nbr, (const T*)c->A, B.q2, g.m_v, z);
+  launch_trsv_fwd<T>(c->st, c->sf, (const T*)c->fcoef, B.q2, B.xq, B.zq, z);
 }
 
 __global__ void k_copy_scalar(double* dst, const double* src) { dst[0] = src[0]; }
@@ -887,6 +965,10 @@ static vif_status laplace_impl(vif_ctx* c, const double* y, const double* b0, do
   }
   S.psi = psi_cur;
   S.converged = converged ? 1 : 0;
+  S.levels_fwd = c->nlev_f;
+  S.levels_bwd = c->nlev_b;
+  for (int L = 0; L < c->nlev_f; ++L) S.wide_fwd += (c->hfwd_lvl[L + 1] - c->hfwd_lvl[L] >= 1024);
+  for (int L = 0; L < c->nlev_b; ++L) S.wide_bwd += (c->hbwd_lvl[L + 1] - c->hbwd_lvl[L] >= 1024);
   HIPCHK(c, hipMemcpyAsync(mode_out, B.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
   HIPCHK(c, hipGetLastError());
   if ((s = read_status(c, "vif_laplace_mode"))) return s;
@@ -907,12 +989,11 @@ vif_status vif_sample_prior(vif_ctx* c, const double* eps1, const double* eps2, 
   LapBufs B = lap_bufs(c);
   launch_sqrtd_scale(c->st, c->D, eps2, g.n, B.t);
   if (fp32_form(c)) {
-    launch_trsv_fwd<float>(c->st, c->fwd_order, c->fwd_lvl, c->hfwd_lvl.data(), c->nlev_f, c->nbr, (const float*)c->A, B.t, g.m_v, B.s);
-    launch_add_ve<float>(c->st, c->Vf, eps1, B.s, g.n, g.m > 0 ? c->mp : 0, b_out);
+    launch_trsv_fwd<float>(c->st, c->sf, (const float*)c->fcoef, B.t, B.xq, B.zq, B.s);
+    launch_add_ve<float>(c->st, c->Vf, eps1, B.s, g.n, c->mp, g.m, b_out);
   } else {
-    launch_trsv_fwd<double>(c->st, c->fwd_order, c->fwd_lvl, c->hfwd_lvl.data(), c->nlev_f, c->nbr, (const double*)c->A, B.t, g.m_v,
-                            B.s);
-    launch_add_ve<double>(c->st, c->Vd, eps1, B.s, g.n, g.m > 0 ? c->mp : 0, b_out);
+    launch_trsv_fwd<double>(c->st, c->sf, (const double*)c->fcoef, B.t, B.xq, B.zq, B.s);
+    launch_add_ve<double>(c->st, c->Vd, eps1, B.s, g.n, c->mp, g.m, b_out);
   }
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->st));
@@ -955,9 +1036,9 @@ vif_status vif_mlp_features(vif_ctx* c, const double* y, float* feat_out) {
     launch_reduce_apply(c->st, B.upart, c->nchunk, mp, c->M3inv, B.cbuf, B.cp);
     HIPCHK(c, hipMemsetAsync(B.q, 0, sizeof(double) * g.n, c->st));
     if (f32)
-      launch_add_ve<float>(c->st, c->Vf, B.cp, B.q, g.n, mp, B.q2);
+      launch_add_ve<float>(c->st, c->Vf, B.cp, B.q, g.n, mp, g.m, B.q2);
     else
-      launch_add_ve<double>(c->st, c->Vd, B.cp, B.q, g.n, mp, B.q2);
+      launch_add_ve<double>(c->st, c->Vd, B.cp, B.q, g.n, mp, g.m, B.q2);
     smooth = B.q2;
   }
   if (f32)
@@ -989,6 +1070,183 @@ __global__ void k_export_A(const void* A, bool f32, int64_t count, double* out) 
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= count) return;
   out[q] = f32 ? (double)((const float*)A)[q] : ((const double*)A)[q];
+}
+
+}  // extern "C"
+
+// Plain preconditioned CG (VIFDU of the current B.W / E / M3') for
+// A x = rhs, A = W + Sigma_dagger^{-1}, from x_0 = 0 to ||r|| <= cg_tol ||rhs||.
+// Logs alpha_j and beta_j (when alog is set), returns the iterations, the
+// initial rhs^T P^{-1} rhs and (when q0 is set) P^{-1} rhs.
+template <typename T>
+static vif_status pcg_plain(vif_ctx* c, LapBufs& B, const double* rhs, double* x, double* alog, double* blog,
+                            double* q0, int* iters, double* rz0) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  double* dpart = B.part + ceil_div(n, 256);
+  HIPCHK(c, hipMemsetAsync(x, 0, sizeof(double) * n, c->st));
+  HIPCHK(c, hipMemcpyAsync(B.r, rhs, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  vifdu_apply<T>(c, B, B.r, B.z);
+  if (q0) HIPCHK(c, hipMemcpyAsync(q0, B.z, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(B.p, B.z, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  launch_dot2(c->st, B.r, B.z, B.r, B.r, n, dpart, B.sc + 3);
+  hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, c->st, B.sc, B.sc + 3);
+  vif_status s = read_scalars(c, 5);
+  if (s) return s;
+  *rz0 = c->hlsc[3];
+  const double rr0 = c->hlsc[4];
+  const double thr = g.cg_tol * g.cg_tol * rr0;
+  *iters = 0;
+  if (!(rr0 > 0.0)) return VIF_OK;
+  const int check = 4;
+  for (int it = 1; it <= g.cg_maxit; ++it) {
+    prec_matvec<T>(c, B, B.p, B.W, B.Ap);
+    launch_dot2(c->st, B.p, B.Ap, nullptr, nullptr, n, dpart, B.sc + 1);
+    launch_cg_update(c->st, x, B.r, B.p, B.Ap, B.sc, n);
+    vifdu_apply<T>(c, B, B.r, B.z);
+    launch_dot2(c->st, B.r, B.z, B.r, B.r, n, dpart, B.sc + 3);
+    if (alog) launch_log_ab(c->st, B.sc, alog + it - 1, blog + it - 1);
+    launch_cg_dir(c->st, B.p, B.z, B.sc + 3, B.sc, n);
+    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, c->st, B.sc, B.sc + 3);
+    if (it % check == 0 || it == g.cg_maxit) {
+      if ((s = read_scalars(c, 5))) return s;
+      const double rr = c->hlsc[4];
+      if (!isfinite(rr)) return fail(c, VIF_E_NAN, "conjugate gradients: non-finite residual at iteration %d", it);
+      *iters = it;
+      if (rr <= thr) return VIF_OK;
+    }
+  }
+  return fail(c, VIF_E_CG_MAXIT, "conjugate gradients did not reach %g in %d iterations", g.cg_tol, g.cg_maxit);
+}
+
+static vif_status ensure_slq(vif_ctx* c, int ell) {
+  const int ld = c->cfg.cg_maxit + 4;
+  if (ell <= c->slq_ell && ld <= c->slq_ld) return VIF_OK;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  void* old[] = {c->slq_a, c->slq_b, c->slq_rz, c->slq_terms, c->slq_work, c->slq_u, c->slq_q, c->slq_iters};
+  for (void* p : old)
+    if (p) hipFree(p);
+  c->slq_ell = c->slq_ld = 0;
+  const size_t n = c->cfg.n;
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+    else *p = nullptr;
+  };
+  alloc((void**)&c->slq_a, sizeof(double) * ell * ld);
+  alloc((void**)&c->slq_b, sizeof(double) * ell * ld);
+  alloc((void**)&c->slq_rz, sizeof(double) * ell);
+  alloc((void**)&c->slq_terms, sizeof(double) * ell);
+  alloc((void**)&c->slq_work, sizeof(double) * ell * 3 * ld);
+  alloc((void**)&c->slq_u, sizeof(double) * ell * n);
+  alloc((void**)&c->slq_q, sizeof(double) * ell * n);
+  alloc((void**)&c->slq_iters, sizeof(int) * ell);
+  if (e != hipSuccess) return fail(c, e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP, "SLQ workspace: %s",
+                                   hipGetErrorString(e));
+  c->slq_ell = ell;
+  c->slq_ld = ld;
+  return VIF_OK;
+}
+
+// x ~ N(0, Sigma_dagger): x = V^T eps_m + B^{-1} D^{1/2} eps_n  (whitened V rows)
+template <typename T>
+static void prior_draw(vif_ctx* c, LapBufs& B, const double* eps_m, const double* eps_n, double* out) {
+  const vif_config& g = c->cfg;
+  launch_sqrtd_scale(c->st, c->D, eps_n, g.n, B.t);
+  launch_trsv_fwd<T>(c->st, c->sf, (const T*)c->fcoef, B.t, B.xq, B.zq, B.s);
+  const T* V = (const T*)(fp32_form(c) ? (const void*)c->Vf : (const void*)c->Vd);
+  launch_add_ve<T>(c->st, V, eps_m, B.s, g.n, c->mp, g.m, out);
+}
+
+// Laplace NLL (eq. log_det_VIFLA) at a given mode with the SLQ log-determinant:
+//   -log p(y|b) + b^T Sigma^{-1} b / 2
+//   + [sum log(1 + D W) + log det M3' + mean_k ||P^{-1/2} z_k||^2 e_1^T log(T_k) e_1] / 2,
+// the first two log-det terms being log det Sigma_dagger + log det P (VIFDU,
+// App. E.1) in whitened form. Probes z_k = B^T (W^{1/2} e1_k + D^{-1/2}(t - U M'^{-1} U^T t)),
+// t = D^{-1/2} B x_k, x_k = V^T e3_k + B^{-1} D^{1/2} e2_k (a prior draw), so
+// z_k = B^T W^{1/2} e1_k + Sigma_dagger^{-1} x_k ~ N(0, P).
+template <typename T>
+static vif_status laplace_nll_impl(vif_ctx* c, const double* y, const double* mode, int ell, const double* eps_n,
+                                   const double* eps_m, double* out3) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  const int mp = c->mp;
+  LapBufs B = lap_bufs(c);
+  vif_status s = ensure_schedules(c);
+  if (s) return s;
+  if ((s = ensure_slq(c, ell))) return s;
+  const int nlb = (int)ceil_div(n, 256);
+  double* dpart = B.part + nlb;
+  if (g.m > 0) launch_gemm_sq(c->st, c->LMinv, c->LMinv, c->Minv, mp, true, false);
+  // likelihood terms at the mode, VIFDU for W(mode)
+  launch_lik(c->st, g.likelihood, g.lik_param, y, mode, n, B.g, B.W, B.part);
+  hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, B.part, nlb, B.sc + 9);
+  build_vifdu(c, B);
+  prec_matvec<T>(c, B, mode, nullptr, B.sd);
+  launch_dot2(c->st, mode, B.sd, nullptr, nullptr, n, dpart, B.sc + 7);
+  const int nb = launch_sum_log1p_dw(c->st, c->D, B.W, n, B.part);
+  hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, B.part, nb, B.sc + 10);
+  if ((s = read_scalars(c, 13))) return s;
+  const double loglik = c->hlsc[9], bsb = c->hlsc[7], l1p = c->hlsc[10];
+  const double ldM3 = g.m > 0 ? c->hlsc[12] : 0.0;
+  std::vector<int> its(ell);
+  std::vector<double> rz(ell);
+  const T* U = (const T*)c->U;
+  for (int k = 0; k < ell; ++k) {
+    const double* e1 = eps_n + (size_t)(2 * k) * n;
+    const double* e2 = eps_n + (size_t)(2 * k + 1) * n;
+    prior_draw<T>(c, B, g.m > 0 ? eps_m + (size_t)k * g.m : nullptr, e2, B.tmp);
+    launch_bw<T>(c->st, (const T*)c->A, c->D, c->nbr, B.tmp, n, g.m_v, B.t);
+    if (g.m > 0) {
+      launch_utv<T>(c->st, U, B.t, nullptr, n, mp, c->chunk, B.upart);
+      launch_reduce_apply(c->st, B.upart, c->nchunk, mp, c->Minv, B.cbuf, B.cp);
+    }
+    launch_t_minus_uc<T>(c->st, U, B.cp, B.t, c->D, n, mp, B.s);
+    launch_add_sqrtw(c->st, B.s, B.W, e1, n);
+    launch_btw<T>(c->st, (const T*)c->A, c->rev_ptr, c->rev_idx, B.s, nullptr, nullptr, n, g.m_v, B.rhs);
+    s = pcg_plain<T>(c, B, B.rhs, c->slq_u + (size_t)k * n, c->slq_a + (size_t)k * c->slq_ld,
+                     c->slq_b + (size_t)k * c->slq_ld, c->slq_q + (size_t)k * n, &its[k], &rz[k]);
+    if (s) return s;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->slq_iters, its.data(), sizeof(int) * ell, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->slq_rz, rz.data(), sizeof(double) * ell, hipMemcpyHostToDevice, c->st));
+  launch_slq_terms(c->st, c->slq_a, c->slq_b, c->slq_iters, c->slq_rz, ell, c->slq_ld, c->slq_work, c->slq_terms);
+  std::vector<double> terms(ell);
+  HIPCHK(c, hipMemcpyAsync(terms.data(), c->slq_terms, sizeof(double) * ell, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  double mean = 0.0;
+  for (int k = 0; k < ell; ++k) {
+    if (!isfinite(terms[k])) return fail(c, VIF_E_NAN, "SLQ: Lanczos quadrature failed for probe %d", k);
+    mean += terms[k];
+  }
+  mean /= ell;
+  const double logdet = l1p + ldM3 + mean;
+  out3[0] = -loglik + 0.5 * bsb + 0.5 * logdet;
+  out3[1] = logdet;
+  out3[2] = mean;
+  return VIF_OK;
+}
+
+extern "C" {
+
+vif_status vif_laplace_nll(vif_ctx* c, const double* y, const double* mode, int32_t ell, const double* eps_n,
+                           const double* eps_m, double* nll_out, double* logdet_out) {
+  if (!c) return VIF_E_ARG;
+  if (!c->built) return fail(c, VIF_E_STATE, "vif_laplace_nll before a successful vif_build_factor");
+  const vif_config& g = c->cfg;
+  if (!y || !mode || !eps_n || !nll_out || (g.m > 0 && !eps_m)) return fail(c, VIF_E_ARG, "NULL argument");
+  if (ell < 1) return fail(c, VIF_E_ARG, "need at least one probe (got %d)", ell);
+  vif_status s = reset_status(c);
+  if (s) return s;
+  double out3[3];
+  s = fp32_form(c) ? laplace_nll_impl<float>(c, y, mode, ell, eps_n, eps_m, out3)
+                   : laplace_nll_impl<double>(c, y, mode, ell, eps_n, eps_m, out3);
+  if (s) return s;
+  if ((s = read_status(c, "vif_laplace_nll"))) return s;
+  *nll_out = out3[0];
+  if (logdet_out) logdet_out[0] = out3[1];
+  if (!isfinite(out3[0])) return fail(c, VIF_E_NAN, "Laplace NLL is not finite");
+  return VIF_OK;
 }
 
 vif_status vif_precond_solve(vif_ctx* c, const double* W, const double* r, double* z) {

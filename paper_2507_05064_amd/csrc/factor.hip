@@ -359,6 +359,175 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   }
 }
 
+// Forward-mode derivative of the per-point factor with respect to one
+// parameter theta_p (eq. D_A_Vecchia differentiated; App. A). With
+// C = [[R, r], [r^T, c]] the residual covariance over N(i) + {i} and
+// dC_ab = dK_ab + ds2 delta_ab - (dV_a . V_b + V_a . dV_b):
+//   dA = R^{-1} (dr - dR A),  dD = dc - 2 dr . A + A^T dR A,
+//   dU_i = (dV_i - sum_j (dA_j V_{N_j} + A_j dV_{N_j})) / sqrt(D) - U_i dD / (2 D).
+// which: 0 = sigma1^2, 1 = range (isotropic), 2 = s2 (then dV = 0, pass NULL).
+// The cross Gram dV_a . V_b comes from MFMA like the forward Gram.
+template <typename T, int NBLK>
+__global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X, const T* __restrict__ V,
+                                                   const T* __restrict__ dV, const int32_t* __restrict__ nbr,
+                                                   const T* __restrict__ U, int64_t n, int mp, int mv, CovParams p,
+                                                   int which, T* __restrict__ dA, double* __restrict__ dD,
+                                                   T* __restrict__ dU, int* status) {
+  typedef typename Vec4<T>::type T4;
+  typedef typename Acc4<T>::type A4;
+  __shared__ PointShared<T> sh;
+  __shared__ T Xc[32][33];  // cross Gram dV_a . V_b
+  __shared__ T dAs[32];
+  T Lrow[32];
+  int k;
+  T D;
+  const int lane = threadIdx.x;
+  const int myrow = lane & 31;
+  const int64_t i = blockIdx.x;
+  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, Lrow, k, D, status)) {
+    if (lane == 0) dD[i] = __builtin_nan("");
+    return;
+  }
+  T (*Ls)[33] = sh.GL;
+  // cross Gram (rows = sh.nbs, 0..k)
+  if (dV != nullptr) {
+    const int r = lane & 15, g = lane >> 4;
+    const int p0 = sh.nbs[r], p1 = sh.nbs[16 + r];
+    const T* v0 = p0 >= 0 ? V + (size_t)p0 * mp : nullptr;
+    const T* v1 = p1 >= 0 ? V + (size_t)p1 * mp : nullptr;
+    const T* w0 = p0 >= 0 ? dV + (size_t)p0 * mp : nullptr;
+    const T* w1 = p1 >= 0 ? dV + (size_t)p1 * mp : nullptr;
+    A4 a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a10 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
+    const T4 zero4 = {0, 0, 0, 0};
+    for (int kk = 0; kk < mp; kk += 16) {
+      const T4 x0 = w0 ? *reinterpret_cast<const T4*>(w0 + 4 * g + kk) : zero4;
+      const T4 y0 = v0 ? *reinterpret_cast<const T4*>(v0 + 4 * g + kk) : zero4;
+      T4 x1 = zero4, y1 = zero4;
+      if (NBLK == 2) {
+        x1 = w1 ? *reinterpret_cast<const T4*>(w1 + 4 * g + kk) : zero4;
+        y1 = v1 ? *reinterpret_cast<const T4*>(v1 + 4 * g + kk) : zero4;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a00 = mfma16(x0[t], y0[t], a00);
+        if (NBLK == 2) {
+          a01 = mfma16(x0[t], y1[t], a01);
+          a10 = mfma16(x1[t], y0[t], a10);
+          a11 = mfma16(x1[t], y1[t], a11);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = acc_row<T>(lane, v);
+      Xc[row][r] = a00[v];
+      if (NBLK == 2) {
+        Xc[row][16 + r] = a01[v];
+        Xc[16 + row][r] = a10[v];
+        Xc[16 + row][16 + r] = a11[v];
+      }
+    }
+  }
+  __syncthreads();
+  // dC row `lane` (lanes 0..k), full row
+  T dCrow[32];
+  const bool active = lane <= k;
+#pragma unroll
+  for (int b = 0; b < 32; ++b) {
+    T v = 0;
+    if (active && b <= k) {
+      T dk;
+      if (which == 2) {
+        dk = (b == lane) ? T(1) : T(0);
+      } else if (b == lane) {
+        dk = (which == 0) ? T(1) : T(0);
+      } else {
+        const T t2 = scaled_sqdist<T>(p, sh.xs[myrow], sh.xs[b]);
+        dk = (which == 0) ? cov_profile<T>(p.kernel, t2)
+                          : T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2, T(p.inv_ls[0]));
+      }
+      if (dV != nullptr) dk -= Xc[myrow][b] + Xc[b][myrow];
+      v = dk;
+    }
+    dCrow[b] = v;
+  }
+  // rhs_a = dr_a - sum_b dR_ab A_b  (lanes a < k);  dD pieces
+  T rhs = 0, drA = 0, AdRA = 0;
+  if (lane < k) {
+    T sdr = 0;
+#pragma unroll
+    for (int b = 0; b < 32; ++b)
+      if (b < k) sdr += dCrow[b] * sh.As[b];
+    rhs = dCrow[k] - sdr;
+    drA = dCrow[k] * sh.As[lane];
+    AdRA = sh.As[lane] * sdr;
+  }
+  T dc = __shfl(dCrow[0], 0, 64);
+  {
+    // dC[k][k] sits in lane k, entry k
+    T mine = 0;
+#pragma unroll
+    for (int b = 0; b < 32; ++b)
+      if (b == k) mine = dCrow[b];
+    dc = __shfl(mine, k, 64);
+  }
+  drA = wave_sum(drA);
+  AdRA = wave_sum(AdRA);
+  const T dDi = dc - T(2) * drA + AdRA;
+  // dA = L_R^{-T} L_R^{-1} rhs  (lane a holds row a of L in Lrow)
+  T accz = rhs, z = 0;
+#pragma unroll
+  for (int q = 0; q < 32; ++q) {
+    if (q < k) {
+      const T zq = __shfl(accz / Lrow[q], q, 64);
+      if (lane == q) z = zq;
+      if (lane > q && lane < k) accz -= Lrow[q] * zq;
+    }
+  }
+  T acc = (lane < k) ? z : T(0), x = 0;
+  const T ldiag = Ls[myrow][myrow];
+  for (int a = k - 1; a >= 0; --a) {
+    const T xa = __shfl(acc / ldiag, a, 64);
+    if (lane == a) x = xa;
+    if (lane < a) acc -= Ls[a][myrow] * xa;
+  }
+  if (lane < 32) dAs[lane] = (lane < k) ? x : T(0);
+  __syncthreads();
+  if (lane < mv) dA[i * mv + lane] = (lane < k) ? dAs[lane] : T(0);
+  if (lane == 0) dD[i] = (double)dDi;
+  // dU_i
+  const T rsd = T(1) / sqrt(D);
+  const T hdd = T(0.5) * dDi / D;
+  for (int l = lane; l < mp; l += 64) {
+    const size_t o = (size_t)i * mp + l;
+    T u = dV ? dV[o] : T(0);
+    for (int a = 0; a < k; ++a) {
+      const size_t oa = (size_t)sh.nbs[a] * mp + l;
+      u -= dAs[a] * V[oa];
+      if (dV) u -= sh.As[a] * dV[oa];
+    }
+    dU[o] = u * rsd - U[o] * hdd;
+  }
+}
+
+template <typename T>
+void launch_factor_jvp(hipStream_t st, const double* X, const T* V, const T* dV, const int32_t* nbr, const T* U,
+                       int64_t n, int mp, int mv, const CovParams& p, int which, T* dA, double* dD, T* dU,
+                       int* status) {
+  if (mv + 1 <= 16)
+    hipLaunchKernelGGL((k_factor_jvp<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, dV, nbr, U, n, mp, mv, p,
+                       which, dA, dD, dU, status);
+  else
+    hipLaunchKernelGGL((k_factor_jvp<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, dV, nbr, U, n, mp, mv, p,
+                       which, dA, dD, dU, status);
+}
+template void launch_factor_jvp<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
+                                        const double*, int64_t, int, int, const CovParams&, int, double*, double*,
+                                        double*, int*);
+template void launch_factor_jvp<float>(hipStream_t, const double*, const float*, const float*, const int32_t*,
+                                       const float*, int64_t, int, int, const CovParams&, int, float*, double*,
+                                       float*, int*);
+
 // yt_i = (y_i - sum_j A_ij y_{N(i)_j}) / sqrt(D_i)  (a row of D^{-1/2} B y)
 template <typename T>
 __global__ void k_ytilde(const T* __restrict__ A, const double* __restrict__ D, const int32_t* __restrict__ nbr,

@@ -110,12 +110,28 @@ void launch_q_plus_euc(hipStream_t st, const T* U, const double* c, const double
 template <typename T>
 void launch_wgram_partial(hipStream_t st, const T* U, const double* sw, int64_t n, int mp, int chunk, double* partial,
                           int* nchunk_out);
+// Level-scheduled solves with B (trsv.hip). Positions q list the points
+// level by level; rows hold the positions they read.
+struct TriSchedule {
+  int n, mv, nlev;
+  int64_t ne;        // entries of the B^T rows
+  const int* order;  // position -> point
+  const int* lvl;    // level offsets (device, nlev + 1)
+  const int* hlvl;   // the same on the host
+  const int* ptr;    // B^T: row offsets by position (n + 1)
+  const int* col;    // B: n x m_v positions (-1 = none); B^T: positions of the entries
+  const int* src;    // B^T: index into A (n x m_v) of each entry
+};
 template <typename T>
-void launch_trsv_fwd(hipStream_t st, const int* order, const int* lvl, const int* hlvl, int nlev, const int32_t* nbr,
-                     const T* A, const double* x, int mv, double* z);
+void launch_trsv_fwd(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, double* xq, double* zq,
+                     double* z);
 template <typename T>
-void launch_trsv_bwd(hipStream_t st, const int* order, const int* lvl, const int* hlvl, int nlev, const int* rev_ptr,
-                     const int* rev_idx, const T* A, const double* x, int mv, double* z);
+void launch_trsv_bwd(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, double* xq, double* zq,
+                     double* z);
+template <typename T>
+void launch_coef_fwd(hipStream_t st, const TriSchedule& s, const T* A, T* coef);
+template <typename T>
+void launch_coef_bwd(hipStream_t st, const TriSchedule& s, const T* A, T* coef);
 void launch_chol_apply(hipStream_t st, const double* Linv, const double* c, int mp, double* tmp, double* out);
 void launch_axpy(hipStream_t st, double* y, const double* x, const double* eta, int64_t n);
 
@@ -127,6 +143,47 @@ void launch_features(hipStream_t st, const double* y, const T* A, const double* 
 void launch_shift(hipStream_t st, const double* y, double p0, int64_t n, double* out);
 void launch_sqrtd_scale(hipStream_t st, const double* D, const double* e, int64_t n, double* t);
 template <typename T>
-void launch_add_ve(hipStream_t st, const T* V, const double* e1, const double* r, int64_t n, int mp, double* b);
+void launch_add_ve(hipStream_t st, const T* V, const double* e1, const double* r, int64_t n, int mp, int m,
+                   double* b);
 void launch_direct_rhs(hipStream_t st, const double* W, const double* b, const double* g, int64_t n,
                        double* out);
+
+template <typename T>
+void launch_factor_jvp(hipStream_t st, const double* X, const T* V, const T* dV, const int32_t* nbr, const T* U,
+                       int64_t n, int mp, int mv, const CovParams& p, int which, T* dA, double* dD, T* dU,
+                       int* status);
+
+// SLQ / Laplace likelihood (slq.hip)
+void launch_log_ab(hipStream_t st, const double* sc, double* alog, double* blog);
+void launch_slq_terms(hipStream_t st, const double* alog, const double* blog, const int* iters, const double* rz0,
+                      int nprobe, int ld, double* work, double* terms);
+int launch_sum_log1p_dw(hipStream_t st, const double* D, const double* W, int64_t n, double* part);
+void launch_add_sqrtw(hipStream_t st, double* s, const double* W, const double* e, int64_t n);
+
+// Laplace NLL gradient (lapgrad.hip)
+void launch_lik_dW(hipStream_t st, int lik, double lpar, const double* b, int64_t n, double* dW);
+template <typename T>
+void launch_rowmm(hipStream_t st, const T* A, const T* M, const T* Cadd, double alpha, double beta, int64_t n, int mp,
+                  T* out);
+template <typename T>
+void launch_phi_t(hipStream_t st, const double* P, int m, int mp, T* out);
+void launch_cov_zz_d(hipStream_t st, const double* Z, int m, int mp, const CovParams& p, int which, double* S);
+template <typename T>
+void launch_rowvec(hipStream_t st, const T* A, const double* c, int64_t n, int mp, double* out);
+template <typename T>
+void launch_rowdot(hipStream_t st, const T* A, const T* B, int64_t n, int mp, double* out);
+template <typename T>
+void launch_dbx(hipStream_t st, const T* dA, const int32_t* nbr, const double* x, int64_t n, int mv, double* out);
+int launch_bilin(hipStream_t st, const double* tu, const double* su, const double* bu, const double* au,
+                 const double* tw, const double* sw, const double* bw, const double* aw, const double* D,
+                 const double* dD, const double* W, int64_t n, double* part);
+template <typename T>
+int launch_trace_terms(hipStream_t st, const T* Ut, const T* Ut3, const T* U, const T* dU, const double* D,
+                       const double* dD, const double* W, int64_t n, int mp, double* part);
+template <typename T>
+int launch_diag_ste(hipStream_t st, const double* us, const double* qs, int ell, const T* A, const int32_t* nbr,
+                    const double* D, const double* E, const double* dW, const double* u3u, int64_t n, int mv,
+                    double* Sh, double* Sg, double* tr, double* part);
+void launch_diag_final(hipStream_t st, const double* Sh, const double* Sg, const double* tr, double c, int ell,
+                       int64_t n, double* out);
+void launch_sum_cols(hipStream_t st, const double* part, int nb, int cols, double* out);

@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_t_minus_uc(const T* __restrict__ U, con
   double s = 0.0;
   for (int l = lane; l < mp; l += 64) s += (double)U[(size_t)i * mp + l] * c[l];
   s = wave_sum(s);
-  if (lane == 0) out[i] = (t[i] - s) / sqrt(D[i]);
+  if (lane == 0) out[i] = D ? (t[i] - s) / sqrt(D[i]) : t[i] - s;  // D = NULL: no scaling
 }
 
 // out_j = W_j p_j + s_j - sum_{(q,slot): N(q)_slot = j} A_{q,slot} s_q   (W may be null)
@@ -323,120 +323,6 @@ __global__ __launch_bounds__(256) void k_wgram_partial(const T* __restrict__ U, 
 
 // Level-scheduled sparse unit-triangular solves, one workgroup of 1024
 // threads sweeping the levels in order (a level only reads earlier levels).
-// Level-scheduled unit-triangular solves with B (points of one level are
-// independent). Runs of small levels go to one workgroup that walks them
-// with a barrier between levels, one thread per point, each thread issuing
-// all the loads of its point before using any; z written by one wave is read
-// by others only after the level's barrier. A level with at least
-// kWideLevel points gets a launch of its own over the whole GPU with 32
-// lanes per point (coalesced row loads, parallel gathers); kernel order on
-// the stream separates the levels.
-constexpr int kWideLevel = 1024;
-
-// Forward, B z = x:   z_i = x_i + sum_j A_ij z_{N(i)_j}   (levels L0 .. L1-1)
-template <typename T>
-__global__ __launch_bounds__(1024) void k_trsv_fwd(const int* __restrict__ order, const int* __restrict__ lvl,
-                                                   int L0, int L1, const int32_t* __restrict__ nbr,
-                                                   const T* __restrict__ A, const double* __restrict__ x, int mv,
-                                                   double* z) {
-  for (int L = L0; L < L1; ++L) {
-    const int beg = lvl[L], end = lvl[L + 1];
-    for (int q = beg + threadIdx.x; q < end; q += 1024) {
-      const int i = order[q];
-      const int32_t* nr = nbr + (size_t)i * mv;
-      const T* ar = A + (size_t)i * mv;
-      double s = x[i];
-      for (int a0 = 0; a0 < mv; a0 += 16) {
-        int j[16];
-        double av[16], zv[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const bool ok = a0 + k < mv;
-          j[k] = ok ? nr[a0 + k] : -1;
-          av[k] = ok ? (double)ar[a0 + k] : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) zv[k] = j[k] >= 0 ? z[j[k]] : 0.0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) s += av[k] * zv[k];
-      }
-      z[i] = s;
-    }
-    __syncthreads();
-  }
-}
-
-// one wide level of the forward solve: 32 lanes per point (m_v <= 31)
-template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_fwd_wide(const int* __restrict__ order, int beg, int end,
-                                                        const int32_t* __restrict__ nbr, const T* __restrict__ A,
-                                                        const double* __restrict__ x, int mv, double* z) {
-  const int lane = threadIdx.x & 31;
-  const int q = beg + blockIdx.x * 8 + (threadIdx.x >> 5);
-  if (q >= end) return;
-  const int i = order[q];
-  double s = 0.0;
-  if (lane < mv) {
-    const int j = nbr[(size_t)i * mv + lane];
-    if (j >= 0) s = (double)A[(size_t)i * mv + lane] * z[j];
-  }
-#pragma unroll
-  for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
-  if (lane == 0) z[i] = x[i] + s;
-}
-
-// Transposed, B^T z = x:  z_j = x_j + sum_{(q,slot): N(q)_slot = j} A_{q,slot} z_q   (levels L0 .. L1-1)
-template <typename T>
-__global__ __launch_bounds__(1024) void k_trsv_bwd(const int* __restrict__ order, const int* __restrict__ lvl,
-                                                   int L0, int L1, const int* __restrict__ rev_ptr,
-                                                   const int* __restrict__ rev_idx, const T* __restrict__ A,
-                                                   const double* __restrict__ x, int mv, double* z) {
-  for (int L = L0; L < L1; ++L) {
-    const int beg = lvl[L], end = lvl[L + 1];
-    for (int q = beg + threadIdx.x; q < end; q += 1024) {
-      const int j = order[q];
-      double s = x[j];
-      const int e0 = rev_ptr[j], e1 = rev_ptr[j + 1];
-      for (int e = e0; e < e1; e += 16) {
-        int idx[16];
-        double av[16], zv[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) idx[k] = e + k < e1 ? rev_idx[e + k] : -1;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          av[k] = idx[k] >= 0 ? (double)A[idx[k]] : 0.0;
-          zv[k] = idx[k] >= 0 ? z[idx[k] / mv] : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) s += av[k] * zv[k];
-      }
-      z[j] = s;
-    }
-    __syncthreads();
-  }
-}
-
-// one wide level of the transposed solve: 32 lanes per point
-template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_bwd_wide(const int* __restrict__ order, int beg, int end,
-                                                        const int* __restrict__ rev_ptr,
-                                                        const int* __restrict__ rev_idx, const T* __restrict__ A,
-                                                        const double* __restrict__ x, int mv, double* z) {
-  const int lane = threadIdx.x & 31;
-  const int q = beg + blockIdx.x * 8 + (threadIdx.x >> 5);
-  if (q >= end) return;
-  const int j = order[q];
-  double s = 0.0;
-  const int e1 = rev_ptr[j + 1];
-  for (int e = rev_ptr[j] + lane; e < e1; e += 32) {
-    const int idx = rev_idx[e];
-    s += (double)A[idx] * z[idx / mv];
-  }
-#pragma unroll
-  for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
-  if (lane == 0) z[j] = x[j] + s;
-}
-
 // out = L^{-T} (L^{-1} c)  for L^{-1} given (lower, mp x mp): one workgroup
 __global__ __launch_bounds__(256) void k_chol_apply(const double* __restrict__ Linv, const double* __restrict__ c,
                                                     int mp, double* __restrict__ tmp, double* __restrict__ out) {
@@ -470,13 +356,13 @@ __global__ void k_sqrtd_scale(const double* __restrict__ D, const double* __rest
 // b_i = r_i + V_i . e1  (one wave per point)
 template <typename T>
 __global__ __launch_bounds__(256) void k_add_ve(const T* __restrict__ V, const double* __restrict__ e1,
-                                                const double* __restrict__ r, int64_t n, int mp,
+                                                const double* __restrict__ r, int64_t n, int mp, int m,
                                                 double* __restrict__ b) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n) return;
   double s = 0.0;
-  for (int l = lane; l < mp; l += 64) s += (double)V[(size_t)i * mp + l] * e1[l];
+  for (int l = lane; l < m; l += 64) s += (double)V[(size_t)i * mp + l] * e1[l];  // e1 has m entries
   s = wave_sum(s);
   if (lane == 0) b[i] = r[i] + s;
 }
@@ -554,45 +440,6 @@ void launch_wgram_partial(hipStream_t st, const T* U, const double* sw, int64_t 
                      partial);
   *nchunk_out = nchunk;
 }
-// Host-side walk over the levels (hlvl: host copy of the level offsets):
-// consecutive levels below kWideLevel points form one single-workgroup
-// launch, every wider level one launch of its own.
-template <typename T>
-void launch_trsv_fwd(hipStream_t st, const int* order, const int* lvl, const int* hlvl, int nlev, const int32_t* nbr,
-                     const T* A, const double* x, int mv, double* z) {
-  int L = 0;
-  while (L < nlev) {
-    const int cnt = hlvl[L + 1] - hlvl[L];
-    if (cnt >= kWideLevel) {
-      hipLaunchKernelGGL((k_trsv_fwd_wide<T>), dim3((unsigned)ceil_div(cnt, 8)), dim3(256), 0, st, order, hlvl[L],
-                         hlvl[L + 1], nbr, A, x, mv, z);
-      ++L;
-      continue;
-    }
-    int L1 = L + 1;
-    while (L1 < nlev && hlvl[L1 + 1] - hlvl[L1] < kWideLevel) ++L1;
-    hipLaunchKernelGGL((k_trsv_fwd<T>), dim3(1), dim3(1024), 0, st, order, lvl, L, L1, nbr, A, x, mv, z);
-    L = L1;
-  }
-}
-template <typename T>
-void launch_trsv_bwd(hipStream_t st, const int* order, const int* lvl, const int* hlvl, int nlev, const int* rev_ptr,
-                     const int* rev_idx, const T* A, const double* x, int mv, double* z) {
-  int L = 0;
-  while (L < nlev) {
-    const int cnt = hlvl[L + 1] - hlvl[L];
-    if (cnt >= kWideLevel) {
-      hipLaunchKernelGGL((k_trsv_bwd_wide<T>), dim3((unsigned)ceil_div(cnt, 8)), dim3(256), 0, st, order, hlvl[L],
-                         hlvl[L + 1], rev_ptr, rev_idx, A, x, mv, z);
-      ++L;
-      continue;
-    }
-    int L1 = L + 1;
-    while (L1 < nlev && hlvl[L1 + 1] - hlvl[L1] < kWideLevel) ++L1;
-    hipLaunchKernelGGL((k_trsv_bwd<T>), dim3(1), dim3(1024), 0, st, order, lvl, L, L1, rev_ptr, rev_idx, A, x, mv, z);
-    L = L1;
-  }
-}
 void launch_chol_apply(hipStream_t st, const double* Linv, const double* c, int mp, double* tmp, double* out) {
   hipLaunchKernelGGL(k_chol_apply, dim3(1), dim3(256), 0, st, Linv, c, mp, tmp, out);
 }
@@ -609,11 +456,14 @@ void launch_sqrtd_scale(hipStream_t st, const double* D, const double* e, int64_
   hipLaunchKernelGGL(k_sqrtd_scale, g1(n), dim3(256), 0, st, D, e, n, t);
 }
 template <typename T>
-void launch_add_ve(hipStream_t st, const T* V, const double* e1, const double* r, int64_t n, int mp, double* b) {
-  hipLaunchKernelGGL((k_add_ve<T>), g1(n, 4), dim3(256), 0, st, V, e1, r, n, mp, b);
+void launch_add_ve(hipStream_t st, const T* V, const double* e1, const double* r, int64_t n, int mp, int m,
+                   double* b) {
+  hipLaunchKernelGGL((k_add_ve<T>), g1(n, 4), dim3(256), 0, st, V, e1, r, n, mp, m, b);
 }
-template void launch_add_ve<double>(hipStream_t, const double*, const double*, const double*, int64_t, int, double*);
-template void launch_add_ve<float>(hipStream_t, const float*, const double*, const double*, int64_t, int, double*);
+template void launch_add_ve<double>(hipStream_t, const double*, const double*, const double*, int64_t, int, int,
+                                    double*);
+template void launch_add_ve<float>(hipStream_t, const float*, const double*, const double*, int64_t, int, int,
+                                   double*);
 
 #define INST(T)                                                                                                    \
   template void launch_bw<T>(hipStream_t, const T*, const double*, const int32_t*, const double*, int64_t, int,    \
@@ -625,10 +475,7 @@ template void launch_add_ve<float>(hipStream_t, const float*, const double*, con
                               const double*, int64_t, int, double*);                                              \
   template void launch_q_plus_euc<T>(hipStream_t, const T*, const double*, const double*, const double*,          \
                                      const double*, int64_t, int, double*);                                       \
-  template void launch_wgram_partial<T>(hipStream_t, const T*, const double*, int64_t, int, int, double*, int*);  \
-  template void launch_trsv_fwd<T>(hipStream_t, const int*, const int*, const int*, int, const int32_t*,       \
-                                   const T*, const double*, int, double*);                                        \
-  template void launch_trsv_bwd<T>(hipStream_t, const int*, const int*, const int*, int, const int*, const int*,  \
-                                   const T*, const double*, int, double*);
+  template void launch_wgram_partial<T>(hipStream_t, const T*, const double*, int64_t, int, int, double*, int*);
+
 INST(double)
 INST(float)

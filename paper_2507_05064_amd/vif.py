@@ -50,14 +50,16 @@ class vif_laplace_stats(ctypes.Structure):
     _fields_ = [("newton_iters", ctypes.c_int32), ("pcg_iters_total", ctypes.c_int32),
                 ("pcg_iters", ctypes.c_int32 * 64), ("halvings", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("psi", ctypes.c_double), ("pcg_rel_residual", ctypes.c_double), ("start_used", ctypes.c_int32),
-                ("psi_start", ctypes.c_double)]
+                ("psi_start", ctypes.c_double), ("levels_fwd", ctypes.c_int32), ("levels_bwd", ctypes.c_int32),
+                ("wide_fwd", ctypes.c_int32), ("wide_bwd", ctypes.c_int32)]
 
     def as_dict(self):
         k = min(self.newton_iters, 64)
         return {"newton_iters": self.newton_iters, "pcg_iters_total": self.pcg_iters_total,
                 "pcg_iters": list(self.pcg_iters[:k]), "halvings": self.halvings, "converged": bool(self.converged),
                 "psi": self.psi, "pcg_rel_residual": self.pcg_rel_residual, "start_used": bool(self.start_used),
-                "psi_start": self.psi_start}
+                "psi_start": self.psi_start, "levels_fwd": self.levels_fwd, "levels_bwd": self.levels_bwd,
+                "wide_fwd": self.wide_fwd, "wide_bwd": self.wide_bwd}
 
 
 EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors", "vif_build_factor", "vif_nll",
@@ -65,7 +67,7 @@ EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors"
            "vif_get_timing", "vif_laplace_mode", "vif_mlp_num_params", "vif_mlp_workspace_floats",
            "vif_mlp_forward", "vif_mlp_backward", "vif_mlp_adam", "vif_mlp_features", "vif_sample_prior",
            "vif_precond_solve", "vif_batch_create", "vif_batch_destroy", "vif_batch_last_error",
-           "vif_batch_nll_grad"]
+           "vif_batch_nll_grad", "vif_laplace_nll"]
 
 
 def load_library(path: Optional[str] = None):
@@ -106,6 +108,8 @@ def load_library(path: Optional[str] = None):
     lib.vif_laplace_mode.restype = ctypes.c_int
     lib.vif_precond_solve.argtypes = [vp, vp, vp, vp]
     lib.vif_precond_solve.restype = ctypes.c_int
+    lib.vif_laplace_nll.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, dp, dp]
+    lib.vif_laplace_nll.restype = ctypes.c_int
     lib.vif_batch_create.argtypes = [ctypes.POINTER(vif_batch_config), ctypes.POINTER(ctypes.c_int64), vp,
                                      ctypes.POINTER(vp)]
     lib.vif_batch_create.restype = ctypes.c_int
@@ -239,6 +243,14 @@ class VifContext:
         b = torch.empty(self.n, dtype=torch.float64, device=eps2.device)
         self._check(self.lib.vif_sample_prior(self.h, _ptr(eps1) if self.m else None, _ptr(eps2), _ptr(b)))
         return b
+
+    def laplace_nll(self, y: torch.Tensor, mode: torch.Tensor, eps_n: torch.Tensor, eps_m: Optional[torch.Tensor]):
+        """(NLL, log det estimate) with ell = eps_n.shape[0] // 2 SLQ probes."""
+        ell = eps_n.shape[0] // 2
+        nll, ld = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.vif_laplace_nll(self.h, _ptr(y), _ptr(mode), ell, _ptr(eps_n),
+                                             _ptr(eps_m) if self.m else None, ctypes.byref(nll), ctypes.byref(ld)))
+        return nll.value, ld.value
 
     def precond_solve(self, W: torch.Tensor, r: torch.Tensor) -> torch.Tensor:
         z = torch.empty(self.n, dtype=torch.float64, device="cuda")
