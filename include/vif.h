@@ -213,6 +213,23 @@ vif_status vif_mlp_features(vif_ctx* ctx, const double* y, float* feat_out);
 vif_status vif_laplace_nll(vif_ctx* ctx, const double* y, const double* mode, int32_t ell, const double* eps_n,
                            const double* eps_m, double* nll_out, double* logdet_out);
 
+/* The Laplace NLL as vif_laplace_nll plus its gradient (App. B) with
+ * respect to theta = (sigma1^2, range, s2) (isotropic kernels; s2 = the
+ * latent jitter):
+ *   dL/dtheta_p = 1/2 b^T dSigma^{-1} b + 1/2 [d log det Sigma_dagger + tr(A^{-1} dSigma^{-1})]
+ *                 - v^T dSigma^{-1} b,   v = A^{-1} dL/db,
+ *   dL/db_i = 1/2 (A^{-1})_ii dW_ii/db_i (the dependence of the mode on theta).
+ * The traces are stochastic estimates over the same probes (App. D):
+ *   tr(A^{-1} dSigma^{-1}) ~ mean_k [u_k^T dSigma^{-1} q_k - c_p q_k^T dP q_k] + c_p tr(P^{-1} dP),
+ * u_k = A^{-1} z_k, q_k = P^{-1} z_k, c_p the variance-minimising
+ * control-variate coefficient and tr(P^{-1} dP) exact (VIFDU log-det
+ * identity); the diagonal (A^{-1})_ii dW_i likewise with one pooled
+ * coefficient. Derivatives of the factor are taken in forward mode (eq.
+ * D_A_Vecchia differentiated) for each parameter. grad_out: host, 3
+ * doubles. ell >= 2. */
+vif_status vif_laplace_nll_grad(vif_ctx* ctx, const double* y, const double* mode, int32_t ell, const double* eps_n,
+                                const double* eps_m, double* nll_out, double* grad_out);
+
 /* Applies the VIFDU preconditioner of Sec. 4.3.1 / App. E.1 for a given
  * diagonal W: z = P^{-1} r with P = B^T W B + Sigma_dagger^{-1}, in the
  * whitened form z = B^{-1} [E + E D^{-1/2} U M3'^{-1} U^T D^{-1/2} E] B^{-T} r,

@@ -82,6 +82,14 @@ struct vif_ctx {
   double *slq_a = nullptr, *slq_b = nullptr, *slq_rz = nullptr, *slq_terms = nullptr, *slq_work = nullptr;
   double *slq_u = nullptr, *slq_q = nullptr;
   int* slq_iters = nullptr;
+  // Laplace-gradient workspace (first gradient call): tangents per parameter
+  // and per-point work vectors
+  bool lg_ready = false;
+  void *lg_Ut = nullptr, *lg_Ut3 = nullptr, *lg_dV = nullptr, *lg_dU[3] = {nullptr, nullptr, nullptr};
+  void *lg_dA[3] = {nullptr, nullptr, nullptr}, *lg_MT = nullptr, *lg_M3T = nullptr, *lg_PhiT = nullptr;
+  double *lg_dD[3] = {nullptr, nullptr, nullptr}, *lg_mm = nullptr, *lg_vec = nullptr, *lg_part = nullptr;
+  double* lg_slots = nullptr;
+  int lg_slot_cap = 0;
 };
 
 static vif_status fail(vif_ctx* c, vif_status s, const char* fmt, ...) {
@@ -310,7 +318,9 @@ void vif_destroy(vif_ctx* c) {
                   c->rowpart, c->gred, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx,
                   c->fwd_order, c->fwd_lvl, c->bwd_order, c->bwd_lvl, c->lv, c->lm, c->M3, c->M3inv, c->L3inv,
                   c->lsc, c->lpart, c->fcol, c->bptr, c->bcol, c->bsrc, c->fcoef, c->bcoef, c->slq_a, c->slq_b, c->slq_rz, c->slq_terms, c->slq_work, c->slq_u,
-                  c->slq_q, c->slq_iters};
+                  c->slq_q, c->slq_iters, c->lg_Ut, c->lg_Ut3, c->lg_dV, c->lg_dU[0], c->lg_dU[1], c->lg_dU[2],
+                  c->lg_dA[0], c->lg_dA[1], c->lg_dA[2], c->lg_MT, c->lg_M3T, c->lg_PhiT, c->lg_dD[0],
+                  c->lg_dD[1], c->lg_dD[2], c->lg_mm, c->lg_vec, c->lg_part, c->lg_slots};
   for (void* b : bufs)
     if (b) hipFree(b);
   for (int t = 0; t < ST_COUNT; ++t) {
@@ -1227,6 +1237,207 @@ static vif_status laplace_nll_impl(vif_ctx* c, const double* y, const double* mo
   return VIF_OK;
 }
 
+static vif_status ensure_lapgrad(vif_ctx* c, int nslot) {
+  const size_t n = c->cfg.n, mpa = c->mp > 0 ? c->mp : 1, mva = c->cfg.m_v > 0 ? c->cfg.m_v : 1;
+  const size_t ts = tsize(c);
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+  };
+  if (!c->lg_ready) {
+    alloc(&c->lg_Ut, ts * n * mpa);
+    alloc(&c->lg_Ut3, ts * n * mpa);
+    alloc(&c->lg_dV, ts * n * mpa);
+    for (int k = 0; k < 3; ++k) {
+      alloc(&c->lg_dU[k], ts * n * mpa);
+      alloc(&c->lg_dA[k], ts * n * mva);
+      alloc((void**)&c->lg_dD[k], sizeof(double) * n);
+    }
+    alloc(&c->lg_MT, ts * mpa * mpa);
+    alloc(&c->lg_M3T, ts * mpa * mpa);
+    alloc(&c->lg_PhiT, ts * mpa * mpa);
+    alloc((void**)&c->lg_mm, sizeof(double) * mpa * mpa * 2);
+    alloc((void**)&c->lg_vec, sizeof(double) * n * 22 + sizeof(double) * mpa * 4);
+    alloc((void**)&c->lg_part, sizeof(double) * (ceil_div(n, 4) * 4 + 64));
+    if (e != hipSuccess) return fail(c, e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP, "gradient workspace");
+    c->lg_ready = true;
+  }
+  if (nslot > c->lg_slot_cap) {
+    if (c->lg_slots) hipFree(c->lg_slots);
+    c->lg_slots = nullptr;
+    alloc((void**)&c->lg_slots, sizeof(double) * nslot);
+    if (e != hipSuccess) return fail(c, VIF_E_OOM, "gradient slots");
+    c->lg_slot_cap = nslot;
+  }
+  return VIF_OK;
+}
+
+__global__ void k_cast_d2f(const double* in, int64_t len, float* out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < len) out[q] = (float)in[q];
+}
+template <typename T>
+static void to_form(vif_ctx* c, const double* in, int64_t len, void* out) {
+  if (sizeof(T) == sizeof(double))
+    hipMemcpyAsync(out, in, sizeof(double) * len, hipMemcpyDeviceToDevice, c->st);
+  else
+    hipLaunchKernelGGL(k_cast_d2f, dim3((unsigned)ceil_div(len, 256)), dim3(256), 0, c->st, in, len, (float*)out);
+}
+
+// t = D^{-1/2} B x, a = M'^{-1} U^T t, s = t - U a  (for the bilinear forms)
+struct VecPrep {
+  double *t, *s, *a;
+};
+template <typename T>
+static void vec_prep(vif_ctx* c, LapBufs& B, const double* x, VecPrep v) {
+  const vif_config& g = c->cfg;
+  const T* U = (const T*)c->U;
+  launch_bw<T>(c->st, (const T*)c->A, c->D, c->nbr, x, g.n, g.m_v, v.t);
+  if (g.m > 0) {
+    launch_utv<T>(c->st, U, v.t, nullptr, g.n, c->mp, c->chunk, B.upart);
+    launch_reduce_apply(c->st, B.upart, c->nchunk, c->mp, c->Minv, B.cbuf, v.a);
+  }
+  launch_t_minus_uc<T>(c->st, U, v.a, v.t, nullptr, g.n, c->mp, v.s);
+}
+
+// Gradient of the Laplace NLL (App. B) with the traces by STE and control
+// variates (App. D), after laplace_nll_impl has run on the same probes (its
+// solves u_k = A^{-1} z_k, q_k = P^{-1} z_k, W(mode), VIFDU state and M'^{-1}
+// are reused). Parameters: sigma1^2, range, s2 (isotropic kernels).
+template <typename T>
+static vif_status laplace_grad_impl(vif_ctx* c, const double* y, const double* mode, int ell, double* grad) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  const int mp = c->mp, mv = g.m_v, m = g.m;
+  const int nslot = 3 * (2 + 2 * ell) + 16;
+  vif_status s = ensure_lapgrad(c, nslot);
+  if (s) return s;
+  LapBufs B = lap_bufs(c);
+  const T* U = (const T*)c->U;
+  const T* V = (const T*)(fp32_form(c) ? (const void*)c->Vf : (const void*)c->Vd);
+  double* w = c->lg_vec;
+  double *dW = w, *Sh = w + n, *Sg = w + 2 * n, *trq = w + 3 * n, *dLdb = w + 4 * n, *vsol = w + 5 * n,
+         *u3u = w + 6 * n;
+  VecPrep Pb{w + 7 * n, w + 8 * n, nullptr}, Pv{w + 9 * n, w + 10 * n, nullptr};
+  VecPrep Pu{w + 11 * n, w + 12 * n, nullptr}, Pq{w + 13 * n, w + 14 * n, nullptr};
+  double *dBb = w + 15 * n, *aUb = w + 16 * n, *dBv = w + 17 * n, *aUv = w + 18 * n, *dBx = w + 19 * n,
+         *aUx = w + 20 * n, *dBq = w + 21 * n;
+  double* mvec = w + 22 * n;
+  const int mpa = mp > 0 ? mp : 1;
+  Pb.a = mvec;
+  Pv.a = mvec + mpa;
+  Pu.a = mvec + 2 * mpa;
+  Pq.a = mvec + 3 * mpa;
+  if (m == 0)
+    for (double* a : {Pb.a, Pv.a, Pu.a, Pq.a}) HIPCHK(c, hipMemsetAsync(a, 0, sizeof(double) * mpa, c->st));
+  double* part = c->lg_part;
+  double* slots = c->lg_slots;
+  // slot layout: [p * (2 + 2 ell) + 0] f(b, b), [+1] f(v, b), [+2 + k] f(u_k, q_k), [+2 + ell + k] g(q_k)
+  double* tslots = slots + 3 * (2 + 2 * ell);  // traces: 4 per parameter
+  launch_lik_dW(c->st, g.likelihood, g.lik_param, mode, n, dW);
+  // Ut = U M'^{-1}, Ut3 = U M3'^{-1}, u3u_i = Ut3_i . U_i
+  if (m > 0) {
+    to_form<T>(c, c->Minv, (int64_t)mp * mp, c->lg_MT);
+    to_form<T>(c, c->M3inv, (int64_t)mp * mp, c->lg_M3T);
+    launch_rowmm<T>(c->st, U, (const T*)c->lg_MT, nullptr, 1.0, 0.0, n, mp, (T*)c->lg_Ut);
+    launch_rowmm<T>(c->st, U, (const T*)c->lg_M3T, nullptr, 1.0, 0.0, n, mp, (T*)c->lg_Ut3);
+    launch_rowdot<T>(c->st, (const T*)c->lg_Ut3, U, n, mp, u3u);
+  } else {
+    HIPCHK(c, hipMemsetAsync(u3u, 0, sizeof(double) * n, c->st));
+  }
+  // diagonal of A^{-1} (times dW) by STE with a pooled control variate, then v = A^{-1} dL/db
+  int nb = launch_diag_ste<T>(c->st, c->slq_u, c->slq_q, ell, (const T*)c->A, c->nbr, c->D, B.E, dW, u3u, n, mv, Sh,
+                              Sg, trq, part);
+  launch_sum_cols(c->st, part, nb, 2, B.sc + 13);
+  if ((s = read_scalars(c, 15))) return s;
+  const double cb = (c->hlsc[14] > 0.0) ? c->hlsc[13] / c->hlsc[14] : 0.0;
+  launch_diag_final(c->st, Sh, Sg, trq, cb, ell, n, dLdb);
+  int vits = 0;
+  double vrz = 0.0;
+  if ((s = pcg_plain<T>(c, B, dLdb, vsol, nullptr, nullptr, nullptr, &vits, &vrz))) return s;
+  vec_prep<T>(c, B, mode, Pb);
+  vec_prep<T>(c, B, vsol, Pv);
+  // tangents of the factor for sigma1^2, range, s2
+  for (int p = 0; p < 3; ++p) {
+    T* dU = (T*)c->lg_dU[p];
+    T* dA = (T*)c->lg_dA[p];
+    const T* dVp = nullptr;
+    if (p < 2 && m > 0) {
+      double* dSm = c->lg_mm;
+      double* Pm = c->lg_mm + (size_t)mp * mp;
+      launch_cov_zz_d(c->st, c->Zc, m, mp, c->cp, p, dSm);
+      launch_gemm_sq(c->st, dSm, c->Linv, c->Mwork, mp, false, true);
+      launch_gemm_sq(c->st, c->Linv, c->Mwork, Pm, mp, false, false);
+      launch_phi_t<T>(c->st, Pm, m, mp, (T*)c->lg_PhiT);
+      T* dV = (T*)c->lg_dV;
+      if (p == 0) {
+        launch_rowmm<T>(c->st, V, (const T*)c->lg_PhiT, V, -1.0, 1.0 / c->cp.sigma1_sq, n, mp, dV);
+      } else {
+        launch_whiten<T>(c->st, c->Xc, c->Zc, c->Linv, m, mp, n, c->cp, true, dV);
+        launch_rowmm<T>(c->st, V, (const T*)c->lg_PhiT, dV, -1.0, 1.0, n, mp, dV);
+      }
+      dVp = dV;
+    }
+    launch_factor_jvp<T>(c->st, c->Xc, V, dVp, c->nbr, U, n, mp, mv, c->cp, p, dA, c->lg_dD[p], dU, c->status);
+    nb = launch_trace_terms<T>(c->st, (const T*)c->lg_Ut, (const T*)c->lg_Ut3, U, dU, c->D, c->lg_dD[p], B.W, n, mp,
+                               part);
+    launch_sum_cols(c->st, part, nb, 4, tslots + 4 * p);
+    double* fs = slots + (size_t)p * (2 + 2 * ell);
+    // f(b, b), f(v, b)
+    launch_dbx<T>(c->st, dA, c->nbr, mode, n, mv, dBb);
+    launch_rowvec<T>(c->st, dU, Pb.a, n, mp, aUb);
+    launch_dbx<T>(c->st, dA, c->nbr, vsol, n, mv, dBv);
+    launch_rowvec<T>(c->st, dU, Pv.a, n, mp, aUv);
+    nb = launch_bilin(c->st, Pb.t, Pb.s, dBb, aUb, Pb.t, Pb.s, dBb, aUb, c->D, c->lg_dD[p], nullptr, n, part);
+    hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, part, nb, fs + 0);
+    nb = launch_bilin(c->st, Pv.t, Pv.s, dBv, aUv, Pb.t, Pb.s, dBb, aUb, c->D, c->lg_dD[p], nullptr, n, part);
+    hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, part, nb, fs + 1);
+  }
+  // per probe: f(u_k, q_k) and g(q_k) for each parameter
+  for (int k = 0; k < ell; ++k) {
+    const double* uk = c->slq_u + (size_t)k * n;
+    const double* qk = c->slq_q + (size_t)k * n;
+    vec_prep<T>(c, B, uk, Pu);
+    vec_prep<T>(c, B, qk, Pq);
+    for (int p = 0; p < 3; ++p) {
+      const T* dU = (const T*)c->lg_dU[p];
+      const T* dA = (const T*)c->lg_dA[p];
+      double* fs = slots + (size_t)p * (2 + 2 * ell);
+      launch_dbx<T>(c->st, dA, c->nbr, uk, n, mv, dBx);
+      launch_rowvec<T>(c->st, dU, Pu.a, n, mp, aUx);
+      launch_dbx<T>(c->st, dA, c->nbr, qk, n, mv, dBq);
+      launch_rowvec<T>(c->st, dU, Pq.a, n, mp, aUb);  // aUb reused for dU a_q
+      nb = launch_bilin(c->st, Pu.t, Pu.s, dBx, aUx, Pq.t, Pq.s, dBq, aUb, c->D, c->lg_dD[p], nullptr, n, part);
+      hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, part, nb, fs + 2 + k);
+      nb = launch_bilin(c->st, Pq.t, Pq.s, dBq, aUb, Pq.t, Pq.s, dBq, aUb, c->D, c->lg_dD[p], B.W, n, part);
+      hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, part, nb, fs + 2 + ell + k);
+    }
+  }
+  std::vector<double> hs(nslot);
+  HIPCHK(c, hipMemcpyAsync(hs.data(), slots, sizeof(double) * nslot, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  for (int p = 0; p < 3; ++p) {
+    const double* fs = hs.data() + (size_t)p * (2 + 2 * ell);
+    const double* ts = hs.data() + 3 * (2 + 2 * ell) + 4 * p;
+    const double dlogdetS = ts[0] + ts[1];          // sum dD/D + tr(M'^{-1} dM')
+    const double trP = ts[3] - ts[0] + ts[2] - ts[1];  // d log det P (W fixed)
+    double fm = 0.0;
+    for (int k = 0; k < ell; ++k) fm += fs[2 + k];
+    fm /= ell;
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < ell; ++k) {
+      num += (fs[2 + k] - fm) * (fs[2 + ell + k] - trP);
+      den += (fs[2 + ell + k] - trP) * (fs[2 + ell + k] - trP);
+    }
+    const double cp = den > 0.0 ? num / den : 0.0;
+    double that = 0.0;
+    for (int k = 0; k < ell; ++k) that += fs[2 + k] - cp * fs[2 + ell + k];
+    that = that / ell + cp * trP;
+    grad[p] = 0.5 * fs[0] + 0.5 * (dlogdetS + that) - fs[1];
+  }
+  return VIF_OK;
+}
+
 extern "C" {
 
 vif_status vif_laplace_nll(vif_ctx* c, const double* y, const double* mode, int32_t ell, const double* eps_n,
@@ -1246,6 +1457,34 @@ vif_status vif_laplace_nll(vif_ctx* c, const double* y, const double* mode, int3
   *nll_out = out3[0];
   if (logdet_out) logdet_out[0] = out3[1];
   if (!isfinite(out3[0])) return fail(c, VIF_E_NAN, "Laplace NLL is not finite");
+  return VIF_OK;
+}
+
+vif_status vif_laplace_nll_grad(vif_ctx* c, const double* y, const double* mode, int32_t ell, const double* eps_n,
+                                const double* eps_m, double* nll_out, double* grad_out) {
+  if (!c) return VIF_E_ARG;
+  if (!c->built) return fail(c, VIF_E_STATE, "vif_laplace_nll_grad before a successful vif_build_factor");
+  const vif_config& g = c->cfg;
+  if (!y || !mode || !eps_n || !nll_out || !grad_out || (g.m > 0 && !eps_m))
+    return fail(c, VIF_E_ARG, "NULL argument");
+  if (ell < 2) return fail(c, VIF_E_ARG, "the control variates need at least two probes (got %d)", ell);
+  if (g.kernel == VIF_GAUSSIAN_ARD)
+    return fail(c, VIF_E_ARG, "vif_laplace_nll_grad supports the isotropic kernels (one length scale)");
+  vif_status s = reset_status(c);
+  if (s) return s;
+  double out3[3];
+  if (fp32_form(c)) {
+    s = laplace_nll_impl<float>(c, y, mode, ell, eps_n, eps_m, out3);
+    if (!s) s = laplace_grad_impl<float>(c, y, mode, ell, grad_out);
+  } else {
+    s = laplace_nll_impl<double>(c, y, mode, ell, eps_n, eps_m, out3);
+    if (!s) s = laplace_grad_impl<double>(c, y, mode, ell, grad_out);
+  }
+  if (s) return s;
+  if ((s = read_status(c, "vif_laplace_nll_grad"))) return s;
+  *nll_out = out3[0];
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(grad_out[k])) return fail(c, VIF_E_NAN, "gradient entry %d is not finite", k);
   return VIF_OK;
 }
 

@@ -67,7 +67,7 @@ EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors"
            "vif_get_timing", "vif_laplace_mode", "vif_mlp_num_params", "vif_mlp_workspace_floats",
            "vif_mlp_forward", "vif_mlp_backward", "vif_mlp_adam", "vif_mlp_features", "vif_sample_prior",
            "vif_precond_solve", "vif_batch_create", "vif_batch_destroy", "vif_batch_last_error",
-           "vif_batch_nll_grad", "vif_laplace_nll"]
+           "vif_batch_nll_grad", "vif_laplace_nll", "vif_laplace_nll_grad"]
 
 
 def load_library(path: Optional[str] = None):
@@ -110,6 +110,8 @@ def load_library(path: Optional[str] = None):
     lib.vif_precond_solve.restype = ctypes.c_int
     lib.vif_laplace_nll.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, dp, dp]
     lib.vif_laplace_nll.restype = ctypes.c_int
+    lib.vif_laplace_nll_grad.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, dp, dp]
+    lib.vif_laplace_nll_grad.restype = ctypes.c_int
     lib.vif_batch_create.argtypes = [ctypes.POINTER(vif_batch_config), ctypes.POINTER(ctypes.c_int64), vp,
                                      ctypes.POINTER(vp)]
     lib.vif_batch_create.restype = ctypes.c_int
@@ -251,6 +253,17 @@ class VifContext:
         self._check(self.lib.vif_laplace_nll(self.h, _ptr(y), _ptr(mode), ell, _ptr(eps_n),
                                              _ptr(eps_m) if self.m else None, ctypes.byref(nll), ctypes.byref(ld)))
         return nll.value, ld.value
+
+    def laplace_nll_grad(self, y: torch.Tensor, mode: torch.Tensor, eps_n: torch.Tensor,
+                         eps_m: Optional[torch.Tensor]):
+        """(NLL, gradient w.r.t. (sigma1^2, range, s2)) with ell = eps_n.shape[0] // 2 probes."""
+        ell = eps_n.shape[0] // 2
+        nll = ctypes.c_double()
+        g = np.zeros(3)
+        self._check(self.lib.vif_laplace_nll_grad(self.h, _ptr(y), _ptr(mode), ell, _ptr(eps_n),
+                                                  _ptr(eps_m) if self.m else None, ctypes.byref(nll),
+                                                  g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return nll.value, g
 
     def precond_solve(self, W: torch.Tensor, r: torch.Tensor) -> torch.Tensor:
         z = torch.empty(self.n, dtype=torch.float64, device="cuda")
