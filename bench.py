@@ -199,6 +199,66 @@ def batch_leg(steps, warmup, log):
     return out
 
 
+def c5_leg(reps, log, ell=50):
+    """Poisson-log latent VIF at n = 1,000,000 in [0,1]^2 (Matern-1/2, variance
+    1, range 0.05, m = 500 k-means++ inducing points, m_v = 20), FP32 factor
+    with FP64 L_m and log-determinants: factor build, mode from the zero start,
+    then the Laplace NLL and its gradient with ell = 50 SLQ/STE probes (one
+    evaluation = build + mode + NLL + gradient)."""
+    import torch
+    import vif_inputs as vi
+    from paper_2507_05064_amd.vif import VifContext
+    w = vi.config5()
+    t0 = time.perf_counter()
+    X = vi.coords(w)
+    Z = vi.inducing_points(w, X)
+    Xd, Zd = torch.as_tensor(X, device="cuda"), torch.as_tensor(Z, device="cuda")
+    ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=w.likelihood, precision="fp32",
+                     tau_m=w.tau_m, cg_tol=1e-6, cg_maxit=2000)
+    nbr = ctx.select_neighbors(Xd, Zd, w.theta)
+    ctx.build_factor(Xd, Zd, nbr, w.theta)
+    eps1, eps2, u = vi.prior_noise(w)
+    b = ctx.sample_prior(torch.as_tensor(eps1, device="cuda"), torch.as_tensor(eps2, device="cuda")).cpu().numpy()
+    yd = torch.as_tensor(vi.poisson_from_uniform(np.exp(b), u), device="cuda")
+    e3, e1, e2 = vi.probe_normals(w, ell)
+    eps_n = np.empty((2 * ell, w.n))
+    eps_n[0::2], eps_n[1::2] = e1.T, e2.T
+    eps_nd, eps_md = torch.as_tensor(eps_n, device="cuda"), torch.as_tensor(np.ascontiguousarray(e3.T), device="cuda")
+    del eps_n
+    log(f"c5: inputs in {time.perf_counter() - t0:.1f} s")
+    times = {"build": [], "mode": [], "nll_grad": []}
+    out = None
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.build_factor(Xd, Zd, nbr, w.theta)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mode, st, _ = ctx.laplace_mode(yd)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        nll, grad = ctx.laplace_nll_grad(yd, mode, eps_nd, eps_md)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if r > 0:  # the first pass warms up
+            times["build"].append(1000 * (t1 - t0))
+            times["mode"].append(1000 * (t2 - t1))
+            times["nll_grad"].append(1000 * (t3 - t2))
+        out = dict(nll=nll, grad=[float(v) for v in grad], newton_iters=st["newton_iters"],
+                   pcg_iters_total=st["pcg_iters_total"], levels_fwd=st["levels_fwd"])
+        log(f"c5 rep {r}: build {1000 * (t1 - t0):.1f} ms, mode {1000 * (t2 - t1):.1f} ms, "
+            f"nll+grad {1000 * (t3 - t2):.1f} ms, {out}")
+    ctx.close()
+    res = {k + "_ms_median": _pct(v, 50) for k, v in times.items()}
+    res["eval_ms_median"] = sum(res.values())
+    res.update(out)
+    res["probes"] = ell
+    res["workload"] = ("Poisson-log latent VIF: n=1000000 d=2 Matern-1/2 (var 1, range 0.05), m=500 k-means++ "
+                       "inducing points, m_v=20, b from the VIF prior; FP32 factor; mode by Newton + VIFDU-PCG "
+                       "(tol 1e-6) from zero, Laplace NLL + gradient with 50 SLQ/STE probes")
+    return res
+
+
 def cpu_baseline(w, budget_points=6000):
     """Oracle (FP64 numpy) NLL + forward-mode gradient on the first
     `budget_points` points of the same workload (the prefix is itself a VIF
@@ -226,6 +286,29 @@ def cpu_baseline(w, budget_points=6000):
                       f"({sec:.1f} s), scaled linearly to n={w.n}"}
 
 
+def counters_mode(w):
+    """Workload for `rocprofv3 --pmc`: the factor kernel at C2 (FP32) and a
+    plain device copy of 1 GiB, whose FETCH_SIZE / WRITE_SIZE readings give
+    the counters' scale against known bytes."""
+    import torch
+    import vif_inputs as vi
+    from paper_2507_05064_amd.vif import VifContext
+    X = vi.coords(w)
+    Z = vi.inducing_points(w, X)
+    Xd, Zd = torch.as_tensor(X, device="cuda"), torch.as_tensor(Z, device="cuda")
+    ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, precision="fp32", tau_m=w.tau_m)
+    nbr = ctx.select_neighbors(Xd, Zd, w.theta)
+    for _ in range(5):
+        ctx.build_factor(Xd, Zd, nbr, w.theta)
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)  # 1 GiB
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"factor_bytes_per_launch": w.n * factor_bytes_per_point(w.m, w.m_v, w.d, 4),
+                      "copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +319,11 @@ def main():
     ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace mode leg")
     ap.add_argument("--laplace-reps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched leg")
+    ap.add_argument("--counters", action="store_true",
+                    help="hardware-counter mode: 5 FP32 factor builds of the C2 workload and 5 copies of a 1 GiB "
+                         "buffer (the counters' scale reference), nothing timed")
+    ap.add_argument("--c5", action="store_true",
+                    help="also run the n = 1M Poisson leg (Laplace NLL + gradient; a few minutes of set-up)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -246,6 +334,9 @@ def main():
     from paper_2507_05064_amd.vif import VifContext
 
     w = vi.config2()
+    if args.counters:
+        counters_mode(w)
+        return
     X = vi.coords(w)
     Z = vi.inducing_points(w, X)
     Xd = torch.as_tensor(X, device="cuda")
@@ -304,6 +395,8 @@ def main():
         res["batch"] = batch_leg(args.steps, args.warmup, lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_laplace:
         res["laplace"] = laplace_leg(args.laplace_reps, 1, lambda msg: print(msg, file=sys.stderr, flush=True))
+    if args.c5:
+        res["laplace_nll_grad_c5"] = c5_leg(2, lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res))

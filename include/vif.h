@@ -230,6 +230,26 @@ vif_status vif_laplace_nll(vif_ctx* ctx, const double* y, const double* mode, in
 vif_status vif_laplace_nll_grad(vif_ctx* ctx, const double* y, const double* mode, int32_t ell, const double* eps_n,
                                 const double* eps_m, double* nll_out, double* grad_out);
 
+/* Conditioning sets of n_p prediction points Xp (device, n_p x d): the m_v
+ * training points of the last build with the smallest 1 - |rho| (residual
+ * correlation, as for vif_select_neighbors; ties to the smaller index).
+ * Prediction points condition on training points only (so B_p = I in
+ * Prop. 2.1). nbrp_out: device, n_p x m_v int32, training indices. */
+vif_status vif_select_neighbors_pred(vif_ctx* ctx, const double* Xp, int64_t n_p, int32_t* nbrp_out);
+
+/* Posterior predictive mean at n_p points (Prop. 2.1 with B_p = I):
+ *   mu_p = Sigma_mnp^T Sigma_m^{-1} Sigma_mn Sigma_dagger^{-1} y
+ *          - B_po (y - Sigma_mn^T M^{-1} Sigma_mn B^T D^{-1} B y),
+ * B_po holding -A^p over the training neighbours nbrp (from
+ * vif_select_neighbors_pred or the caller), A^p by eq. D_A_Vecchia for the
+ * prediction point. For a Gaussian context y is the response; for a latent
+ * context pass the mode: the result is then the predictive mean of the
+ * latent process, Cov(b_p, b) Sigma_dagger^{-1} b~. Device arrays: y (n), Xp
+ * (n_p x d), nbrp (n_p x m_v), mean_out (n_p). var_out must be NULL
+ * (predictive variances are not provided). */
+vif_status vif_predict(vif_ctx* ctx, const double* y, const double* Xp, const int32_t* nbrp, int64_t n_p,
+                       double* mean_out, double* var_out);
+
 /* Applies the VIFDU preconditioner of Sec. 4.3.1 / App. E.1 for a given
  * diagonal W: z = P^{-1} r with P = B^T W B + Sigma_dagger^{-1}, in the
  * whitened form z = B^{-1} [E + E D^{-1/2} U M3'^{-1} U^T D^{-1/2} E] B^{-T} r,

@@ -1,0 +1,73 @@
+"""FP64 CPU oracle of VIF prediction -- TEST INFRASTRUCTURE ONLY.
+
+The posterior predictive mean of Prop. 2.1 (Sec. 2.4), in the paper's own
+unwhitened form, for a Gaussian likelihood, or for the latent process given
+a vector in place of y (then the residual factor carries the latent jitter
+instead of the nugget):
+  mu_p = Sigma_mnp^T Sigma_m^{-1} Sigma_mn Sigma_dagger^{-1} y
+         - B_p^{-1} B_po (y - Sigma_mn^T M^{-1} Sigma_mn B^T D^{-1} B y),
+Sigma_dagger^{-1} y = Q y - Q Sigma_mn^T M^{-1} Sigma_mn Q y, Q = B^T D^{-1} B.
+Reading (Q12, the paper is silent): a prediction point conditions only on
+training points -- its m_v nearest training points by the residual
+correlation of Sec. 6 -- so B_p = I and row p of B_po holds -A^p over N(p),
+with A^p from eq. D_A_Vecchia applied to the prediction point.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+from scipy.linalg import cho_factor, cho_solve
+
+from oracle import vif_oracle as vo
+
+
+def prediction_neighbours(model: vo.Model, X: np.ndarray, Z: np.ndarray, Xp: np.ndarray, m_v: int) -> np.ndarray:
+    """N(p): the m_v training points with the smallest key 1 - |rho| (ties to
+    the smaller index) for every prediction point, by brute force."""
+    n = X.shape[0]
+    XA = np.vstack([X, Xp])
+    ind = vo.inducing(model, XA, Z)
+    out = -np.ones((Xp.shape[0], m_v), dtype=np.int64)
+    cand = np.arange(n)
+    for j in range(Xp.shape[0]):
+        key = vo.neighbour_keys(model, XA, ind, n + j, cand)
+        order = np.lexsort((cand, key))[:m_v]
+        out[j, :order.size] = cand[order]
+    return out
+
+
+def predictive_mean(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray, y: np.ndarray,
+                    Xp: np.ndarray, nbr_p: np.ndarray) -> np.ndarray:
+    n, npred = X.shape[0], Xp.shape[0]
+    ind = vo.inducing(model, X, Z)
+    fac = vo.vecchia_factor(model, X, ind, nbr)
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [np.ones(n)]
+    for s_ in range(nbr.shape[1]):
+        v = nbr[:, s_] >= 0
+        rows.append(np.nonzero(v)[0])
+        cols.append(nbr[v, s_])
+        vals.append(-fac.A[v, s_])
+    B = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    Dinv = 1.0 / fac.D
+    Qy = B.T @ (Dinv * (B @ y))
+    # prediction factor: eq. D_A_Vecchia for the prediction points over training neighbours
+    XA = np.vstack([X, Xp])
+    indA = vo.inducing(model, XA, Z)
+    Ap, _ = vo.vecchia_factor_points(model, XA, indA, nbr_p, n + np.arange(npred))
+    Bpo = np.zeros((npred, n))
+    for s_ in range(nbr_p.shape[1]):
+        v = nbr_p[:, s_] >= 0
+        Bpo[np.nonzero(v)[0], nbr_p[v, s_]] = -Ap[v, s_]
+    if ind.m:
+        G = B @ ind.Smn.T                      # B Sigma_mn^T
+        M = ind.Sm + G.T @ (Dinv[:, None] * G)
+        cM = cho_factor(M, lower=True)
+        QSt = B.T @ (Dinv[:, None] * G)        # Q Sigma_mn^T
+        Sinv_y = Qy - QSt @ cho_solve(cM, ind.Smn @ Qy)
+        Smnp = vo.cov(model, Z, Xp)
+        low = Smnp.T @ cho_solve(ind.cf, ind.Smn @ Sinv_y)
+        inner = y - ind.Smn.T @ cho_solve(cM, ind.Smn @ Qy)
+    else:
+        low = np.zeros(npred)
+        inner = y
+    return low - Bpo @ inner

@@ -90,6 +90,10 @@ struct vif_ctx {
   double *lg_dD[3] = {nullptr, nullptr, nullptr}, *lg_mm = nullptr, *lg_vec = nullptr, *lg_part = nullptr;
   double* lg_slots = nullptr;
   int lg_slot_cap = 0;
+  // prediction workspace (grown on demand)
+  int64_t pred_cap = 0;
+  void *pred_Vp = nullptr, *pred_Ap = nullptr;
+  double *pred_Vpd = nullptr, *pred_vn = nullptr, *pred_Dp = nullptr;
 };
 
 static vif_status fail(vif_ctx* c, vif_status s, const char* fmt, ...) {
@@ -320,7 +324,8 @@ void vif_destroy(vif_ctx* c) {
                   c->lsc, c->lpart, c->fcol, c->bptr, c->bcol, c->bsrc, c->fcoef, c->bcoef, c->slq_a, c->slq_b, c->slq_rz, c->slq_terms, c->slq_work, c->slq_u,
                   c->slq_q, c->slq_iters, c->lg_Ut, c->lg_Ut3, c->lg_dV, c->lg_dU[0], c->lg_dU[1], c->lg_dU[2],
                   c->lg_dA[0], c->lg_dA[1], c->lg_dA[2], c->lg_MT, c->lg_M3T, c->lg_PhiT, c->lg_dD[0],
-                  c->lg_dD[1], c->lg_dD[2], c->lg_mm, c->lg_vec, c->lg_part, c->lg_slots};
+                  c->lg_dD[1], c->lg_dD[2], c->lg_mm, c->lg_vec, c->lg_part, c->lg_slots, c->pred_Vp,
+                  c->pred_Ap, c->pred_Vpd, c->pred_vn, c->pred_Dp};
   for (void* b : bufs)
     if (b) hipFree(b);
   for (int t = 0; t < ST_COUNT; ++t) {
@@ -1486,6 +1491,110 @@ vif_status vif_laplace_nll_grad(vif_ctx* c, const double* y, const double* mode,
   for (int k = 0; k < 3; ++k)
     if (!isfinite(grad_out[k])) return fail(c, VIF_E_NAN, "gradient entry %d is not finite", k);
   return VIF_OK;
+}
+
+}  // extern "C"
+
+static vif_status ensure_pred(vif_ctx* c, int64_t np_) {
+  if (np_ <= c->pred_cap) return VIF_OK;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  void* old[] = {c->pred_Vp, c->pred_Ap, c->pred_Vpd, c->pred_vn, c->pred_Dp};
+  for (void* q : old)
+    if (q) hipFree(q);
+  c->pred_Vp = c->pred_Ap = nullptr;
+  c->pred_Vpd = c->pred_vn = c->pred_Dp = nullptr;
+  c->pred_cap = 0;
+  const size_t mpa = c->mp > 0 ? c->mp : 1, mva = c->cfg.m_v > 0 ? c->cfg.m_v : 1;
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** q, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(q, bytes);
+  };
+  alloc(&c->pred_Vp, tsize(c) * np_ * mpa);
+  alloc(&c->pred_Ap, tsize(c) * np_ * mva);
+  alloc((void**)&c->pred_Vpd, sizeof(double) * np_ * mpa);
+  alloc((void**)&c->pred_vn, sizeof(double) * np_);
+  alloc((void**)&c->pred_Dp, sizeof(double) * np_);
+  if (e != hipSuccess) return fail(c, e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP, "prediction workspace");
+  c->pred_cap = np_;
+  return VIF_OK;
+}
+
+// mu_p = Vp . (U^T e) + sum_a A^p_a (y - V w)_{N(p)_a}, e = yt - U w,
+// w = M'^{-1} U^T yt, yt = D^{-1/2} B y: Prop. 2.1 with B_p = I, whitened
+// (Sigma_mnp^T Sigma_m^{-1} Sigma_mn Sigma_dagger^{-1} y = Vp . U^T e and
+// Sigma_mn^T M^{-1} Sigma_mn B^T D^{-1} B y = V w).
+template <typename T>
+static vif_status predict_impl(vif_ctx* c, const double* y, const double* Xp, const int32_t* nbrp, int64_t np_,
+                               double* mean) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  const int mp = c->mp, mv = g.m_v;
+  LapBufs B = lap_bufs(c);
+  const T* V = (const T*)(fp32_form(c) ? (const void*)c->Vf : (const void*)c->Vd);
+  const T* U = (const T*)c->U;
+  T* Vp = (T*)c->pred_Vp;
+  if (g.m > 0) launch_whiten<T>(c->st, Xp, c->Zc, c->Linv, g.m, mp, np_, c->cp, false, Vp);
+  launch_pred_factor<T>(c->st, c->Xc, V, Xp, Vp, nbrp, n, np_, mp, mv, c->cp, (T*)c->pred_Ap, c->pred_Dp,
+                        c->status);
+  double *yt = B.t, *e = B.s, *r = B.tmp, *w = B.cp, *c1 = B.ctmp;
+  launch_ytilde<T>(c->st, (const T*)c->A, c->D, c->nbr, y, n, mv, yt);
+  if (g.m > 0) {
+    launch_gemm_sq(c->st, c->LMinv, c->LMinv, c->Minv, mp, true, false);
+    launch_utv<T>(c->st, U, yt, nullptr, n, mp, c->chunk, B.upart);
+    launch_reduce_apply(c->st, B.upart, c->nchunk, mp, c->Minv, B.cbuf, w);
+    launch_t_minus_uc<T>(c->st, U, w, yt, nullptr, n, mp, e);
+    launch_utv<T>(c->st, U, e, nullptr, n, mp, c->chunk, B.upart);
+    launch_colreduce(c->st, B.upart, c->nchunk, mp, c1);
+    launch_rowvec<T>(c->st, V, w, n, mp, r);
+    hipLaunchKernelGGL(k_sub, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->st, r, y, r, n);
+  } else {
+    HIPCHK(c, hipMemcpyAsync(r, y, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  }
+  launch_pred_mean<T>(c->st, Vp, c1, (const T*)c->pred_Ap, nbrp, r, np_, mp, mv, mean);
+  HIPCHK(c, hipGetLastError());
+  return VIF_OK;
+}
+
+extern "C" {
+
+vif_status vif_select_neighbors_pred(vif_ctx* c, const double* Xp, int64_t np_, int32_t* nbrp_out) {
+  if (!c) return VIF_E_ARG;
+  if (!c->built) return fail(c, VIF_E_STATE, "vif_select_neighbors_pred before a successful vif_build_factor");
+  if (!Xp || !nbrp_out || np_ < 1) return fail(c, VIF_E_ARG, "NULL Xp / nbrp_out or no prediction points");
+  const vif_config& g = c->cfg;
+  if (g.m_v == 0) return VIF_OK;
+  vif_status s = reset_status(c);
+  if (s) return s;
+  if ((s = ensure_pred(c, np_))) return s;
+  if (g.m > 0) {
+    if ((s = build_inducing(c, c->Xc, c->Zc, true))) return s;  // FP64 V of the training points
+    launch_rownorm<double>(c->st, c->Vd, g.n, c->mp, c->vnorm);
+    launch_whiten<double>(c->st, Xp, c->Zc, c->Linv, g.m, c->mp, np_, c->cp, false, c->pred_Vpd);
+    launch_rownorm<double>(c->st, c->pred_Vpd, np_, c->mp, c->pred_vn);
+  } else {
+    HIPCHK(c, hipMemsetAsync(c->vnorm, 0, sizeof(double) * g.n, c->st));
+    HIPCHK(c, hipMemsetAsync(c->pred_vn, 0, sizeof(double) * np_, c->st));
+  }
+  launch_knn_pred(c->st, Xp, c->pred_Vpd, c->pred_vn, np_, c->Xc, c->Vd, c->vnorm, g.n, c->mp, g.m_v, c->cp,
+                  nbrp_out);
+  HIPCHK(c, hipGetLastError());
+  return read_status(c, "vif_select_neighbors_pred");
+}
+
+vif_status vif_predict(vif_ctx* c, const double* y, const double* Xp, const int32_t* nbrp, int64_t np_,
+                       double* mean_out, double* var_out) {
+  if (!c) return VIF_E_ARG;
+  if (!c->built) return fail(c, VIF_E_STATE, "vif_predict before a successful vif_build_factor");
+  const vif_config& g = c->cfg;
+  if (!y || !Xp || !mean_out || np_ < 1 || (g.m_v > 0 && !nbrp)) return fail(c, VIF_E_ARG, "NULL argument");
+  if (var_out) return fail(c, VIF_E_ARG, "predictive variances are not provided (pass var_out = NULL)");
+  vif_status s = reset_status(c);
+  if (s) return s;
+  if ((s = ensure_pred(c, np_))) return s;
+  s = fp32_form(c) ? predict_impl<float>(c, y, Xp, nbrp, np_, mean_out)
+                   : predict_impl<double>(c, y, Xp, nbrp, np_, mean_out);
+  if (s) return s;
+  return read_status(c, "vif_predict");
 }
 
 vif_status vif_precond_solve(vif_ctx* c, const double* W, const double* r, double* z) {

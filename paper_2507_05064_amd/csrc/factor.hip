@@ -52,25 +52,32 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
                                              const int32_t* __restrict__ nbr, int64_t i, int mp, int mv,
                                              const CovParams& p, PointShared<T>& sh, T (&Lrow)[32], int& k_out,
                                              T& D_out, int* status, const T* extra = nullptr,
-                                             T extra_scale = T(1)) {
+                                             T extra_scale = T(1), const T* own_v = nullptr,
+                                             const double* own_x = nullptr, const int32_t* own_nbr = nullptr) {
+  // own_v / own_x / own_nbr (prediction points): the point's own V row,
+  // coordinates and neighbour row come from these, its neighbours (all < i)
+  // from V, X
   typedef typename Vec4<T>::type T4;
   typedef typename Acc4<T>::type A4;
   const int lane = threadIdx.x;
-  int nbv = (lane < mv) ? nbr[i * mv + lane] : -1;
+  int nbv = (lane < mv) ? (own_nbr ? own_nbr[lane] : nbr[i * mv + lane]) : -1;
   if (nbv >= i) nbv = -1;  // invalid entry (reported by the list check): never gather out of range
   const int k = __popcll(__ballot(nbv >= 0));
   const int rowpt = (lane < k) ? nbv : (lane == k ? (int)i : -1);
+  const bool own = own_v != nullptr && lane == k;
   if (lane < 32) {
     sh.nbs[lane] = rowpt;
     for (int dd = 0; dd < VIF_MAX_D; ++dd)
-      sh.xs[lane][dd] = (rowpt >= 0 && dd < p.d) ? X[(int64_t)rowpt * p.d + dd] : 0.0;
+      sh.xs[lane][dd] = (rowpt >= 0 && dd < p.d) ? (own ? own_x[dd] : X[(int64_t)rowpt * p.d + dd]) : 0.0;
   }
 
   // 1. Gram of the gathered rows
   const int r = lane & 15, g = lane >> 4;
   const T* src = nullptr;
   T scl = T(1);
-  if (rowpt >= 0) {
+  if (own) {
+    src = own_v;
+  } else if (rowpt >= 0) {
     src = V + (size_t)rowpt * mp;
   } else if (extra != nullptr && lane == k + 1) {
     src = extra;
@@ -527,6 +534,77 @@ template void launch_factor_jvp<double>(hipStream_t, const double*, const double
 template void launch_factor_jvp<float>(hipStream_t, const double*, const float*, const float*, const int32_t*,
                                        const float*, int64_t, int, int, const CovParams&, int, float*, double*,
                                        float*, int*);
+
+// Factor rows of prediction points (Prop. 2.1, with B_p = I): eq. D_A_Vecchia
+// for prediction point j over its training neighbours nbrp[j] (all < n),
+// giving A^p_j and D^p_j. Vp, Xp: the prediction points' V rows and inputs.
+template <typename T, int NBLK>
+__global__ __launch_bounds__(64) void k_pred_factor(const double* __restrict__ X, const T* __restrict__ V,
+                                                    const double* __restrict__ Xp, const T* __restrict__ Vp,
+                                                    const int32_t* __restrict__ nbrp, int64_t n, int mp, int mv,
+                                                    CovParams p, T* __restrict__ Ap, double* __restrict__ Dp,
+                                                    int* status) {
+  __shared__ PointShared<T> sh;
+  T Lrow[32];
+  int k;
+  T D;
+  const int lane = threadIdx.x;
+  const int64_t j = blockIdx.x;
+  if (!factor_point<T, NBLK>(X, V, nullptr, n, mp, mv, p, sh, Lrow, k, D, status, nullptr, T(1),
+                             Vp + (size_t)j * mp, Xp + (size_t)j * p.d, nbrp + (size_t)j * mv)) {
+    if (lane == 0) Dp[j] = __builtin_nan("");
+    return;
+  }
+  if (lane < mv) Ap[j * mv + lane] = (lane < k) ? sh.As[lane] : T(0);
+  if (lane == 0) Dp[j] = (double)D;
+}
+
+// mu_j = Vp_j . c + sum_a A^p_ja r_{N(j)_a}  (one wave per prediction point)
+template <typename T>
+__global__ __launch_bounds__(256) void k_pred_mean(const T* __restrict__ Vp, const double* __restrict__ c,
+                                                   const T* __restrict__ Ap, const int32_t* __restrict__ nbrp,
+                                                   const double* __restrict__ r, int64_t np_, int mp, int mv,
+                                                   double* __restrict__ mu) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= np_) return;
+  double s = 0.0;
+  for (int l = lane; l < mp; l += 64) s += (double)Vp[(size_t)j * mp + l] * c[l];
+  if (lane < mv) {
+    const int q = nbrp[j * mv + lane];
+    if (q >= 0) s += (double)Ap[j * mv + lane] * r[q];
+  }
+  s = wave_sum(s);
+  if (lane == 0) mu[j] = s;
+}
+
+template <typename T>
+void launch_pred_factor(hipStream_t st, const double* X, const T* V, const double* Xp, const T* Vp,
+                        const int32_t* nbrp, int64_t n, int64_t np_, int mp, int mv, const CovParams& p, T* Ap,
+                        double* Dp, int* status) {
+  if (mv + 1 <= 16)
+    hipLaunchKernelGGL((k_pred_factor<T, 1>), dim3((unsigned)np_), dim3(64), 0, st, X, V, Xp, Vp, nbrp, n, mp, mv, p,
+                       Ap, Dp, status);
+  else
+    hipLaunchKernelGGL((k_pred_factor<T, 2>), dim3((unsigned)np_), dim3(64), 0, st, X, V, Xp, Vp, nbrp, n, mp, mv, p,
+                       Ap, Dp, status);
+}
+template <typename T>
+void launch_pred_mean(hipStream_t st, const T* Vp, const double* c, const T* Ap, const int32_t* nbrp,
+                      const double* r, int64_t np_, int mp, int mv, double* mu) {
+  hipLaunchKernelGGL((k_pred_mean<T>), dim3((unsigned)ceil_div(np_, 4)), dim3(256), 0, st, Vp, c, Ap, nbrp, r, np_,
+                     mp, mv, mu);
+}
+template void launch_pred_factor<double>(hipStream_t, const double*, const double*, const double*, const double*,
+                                         const int32_t*, int64_t, int64_t, int, int, const CovParams&, double*,
+                                         double*, int*);
+template void launch_pred_factor<float>(hipStream_t, const double*, const float*, const double*, const float*,
+                                        const int32_t*, int64_t, int64_t, int, int, const CovParams&, float*, double*,
+                                        int*);
+template void launch_pred_mean<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
+                                       const double*, int64_t, int, int, double*);
+template void launch_pred_mean<float>(hipStream_t, const float*, const double*, const float*, const int32_t*,
+                                      const double*, int64_t, int, int, double*);
 
 // yt_i = (y_i - sum_j A_ij y_{N(i)_j}) / sqrt(D_i)  (a row of D^{-1/2} B y)
 template <typename T>

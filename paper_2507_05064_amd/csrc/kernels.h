@@ -26,6 +26,9 @@ void launch_rownorm(hipStream_t st, const T* V, int64_t n, int mp, double* out);
 // knn.hip
 void launch_knn(hipStream_t st, const double* X, const double* V, const double* vnorm, int64_t n, int mp, int mv,
                 const CovParams& p, int32_t* nbr);
+void launch_knn_pred(hipStream_t st, const double* Xq, const double* Vq, const double* vnq, int64_t nq,
+                     const double* X, const double* V, const double* vnorm, int64_t n, int mp, int mv,
+                     const CovParams& p, int32_t* nbr);
 
 // factor.hip
 template <typename T>
@@ -87,6 +90,7 @@ void launch_bw(hipStream_t st, const T* A, const double* D, const int32_t* nbr, 
 template <typename T>
 void launch_utv(hipStream_t st, const T* U, const double* v, const double* scale, int64_t n, int mp, int chunk,
                 double* partial);
+void launch_colreduce(hipStream_t st, const double* partial, int nchunk, int mp, double* out);
 void launch_reduce_apply(hipStream_t st, const double* partial, int nchunk, int mp, const double* Minv, double* cbuf,
                          double* out);
 template <typename T>
@@ -152,6 +156,14 @@ template <typename T>
 void launch_factor_jvp(hipStream_t st, const double* X, const T* V, const T* dV, const int32_t* nbr, const T* U,
                        int64_t n, int mp, int mv, const CovParams& p, int which, T* dA, double* dD, T* dU,
                        int* status);
+
+template <typename T>
+void launch_pred_factor(hipStream_t st, const double* X, const T* V, const double* Xp, const T* Vp,
+                        const int32_t* nbrp, int64_t n, int64_t np_, int mp, int mv, const CovParams& p, T* Ap,
+                        double* Dp, int* status);
+template <typename T>
+void launch_pred_mean(hipStream_t st, const T* Vp, const double* c, const T* Ap, const int32_t* nbrp,
+                      const double* r, int64_t np_, int mp, int mv, double* mu);
 
 // SLQ / Laplace likelihood (slq.hip)
 void launch_log_ab(hipStream_t st, const double* sc, double* alog, double* blog);

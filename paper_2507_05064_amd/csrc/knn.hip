@@ -18,9 +18,15 @@
 
 #define QB 64
 
-__global__ __launch_bounds__(256) void k_knn(const double* __restrict__ X, const double* __restrict__ V,
+// Queries (Xq, Vq, vnq: nq points) against the candidates (X, V, vnorm: n
+// points): with pred = 0 the queries are the candidates themselves and only
+// earlier points count; with pred = 1 (prediction points) every candidate
+// counts.
+__global__ __launch_bounds__(256) void k_knn(const double* __restrict__ Xq, const double* __restrict__ Vq,
+                                             const double* __restrict__ vnq, int64_t nq,
+                                             const double* __restrict__ X, const double* __restrict__ V,
                                              const double* __restrict__ vnorm, int64_t n, int mp, int mv,
-                                             CovParams p, int32_t* __restrict__ nbr) {
+                                             CovParams p, int pred, int32_t* __restrict__ nbr) {
   __shared__ double keys[QB][QB + 1];
   __shared__ double tk[QB][33];
   __shared__ int ti[QB][33];
@@ -30,19 +36,19 @@ __global__ __launch_bounds__(256) void k_knn(const double* __restrict__ X, const
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
-  const int64_t nblk = ceil_div(n, QB);
-  const int64_t q0 = (nblk - 1 - (int64_t)blockIdx.x) * QB;  // heaviest blocks first
+  const int64_t nblk = ceil_div(nq, QB);
+  const int64_t q0 = pred ? (int64_t)blockIdx.x * QB : (nblk - 1 - (int64_t)blockIdx.x) * QB;  // heaviest first
   const double base_var = p.sigma1_sq + p.s2;
 
   if (tid < QB) {
     const int64_t q = q0 + tid;
-    for (int k = 0; k < VIF_MAX_D; ++k) xq[tid][k] = (q < n && k < p.d) ? X[q * p.d + k] : 0.0;
-    vq[tid] = (q < n) ? base_var - vnorm[q] : 0.0;
+    for (int k = 0; k < VIF_MAX_D; ++k) xq[tid][k] = (q < nq && k < p.d) ? Xq[q * p.d + k] : 0.0;
+    vq[tid] = (q < nq) ? base_var - vnq[q] : 0.0;
     tcnt[tid] = 0;
   }
   const int64_t qa = q0 + 16 * w + c;  // A-operand query row of this lane
-  const double* vqa = V + (size_t)min(qa, n - 1) * mp;
-  const int64_t jend = min(q0 + QB, n);
+  const double* vqa = Vq + (size_t)min(qa, nq - 1) * mp;
+  const int64_t jend = pred ? n : min(q0 + QB, n);
 
   for (int64_t j0 = 0; j0 < jend; j0 += QB) {
     __syncthreads();
@@ -71,7 +77,7 @@ __global__ __launch_bounds__(256) void k_knn(const double* __restrict__ X, const
         const int cl = 16 * t + c;
         const int64_t qi = q0 + ql, cj = j0 + cl;
         double key = 3.0;
-        if (qi < n && cj < qi) {
+        if (qi < nq && cj < n && (pred || cj < qi)) {
           const double t2 = scaled_sqdist<double>(p, xq[ql], xc[cl]);
           const double cr = p.sigma1_sq * cov_profile<double>(p.kernel, t2) - acc[t][v];
           const double vi = vq[ql], vj = vc[cl];
@@ -106,12 +112,19 @@ __global__ __launch_bounds__(256) void k_knn(const double* __restrict__ X, const
   __syncthreads();
   if (tid < QB) {
     const int64_t q = q0 + tid;
-    if (q < n)
+    if (q < nq)
       for (int s = 0; s < mv; ++s) nbr[q * mv + s] = (s < tcnt[tid]) ? ti[tid][s] : -1;
   }
 }
 
 void launch_knn(hipStream_t st, const double* X, const double* V, const double* vnorm, int64_t n, int mp, int mv,
                 const CovParams& p, int32_t* nbr) {
-  hipLaunchKernelGGL(k_knn, dim3((unsigned)ceil_div(n, QB)), dim3(256), 0, st, X, V, vnorm, n, mp, mv, p, nbr);
+  hipLaunchKernelGGL(k_knn, dim3((unsigned)ceil_div(n, QB)), dim3(256), 0, st, X, V, vnorm, n, X, V, vnorm, n, mp, mv,
+                     p, 0, nbr);
+}
+void launch_knn_pred(hipStream_t st, const double* Xq, const double* Vq, const double* vnq, int64_t nq,
+                     const double* X, const double* V, const double* vnorm, int64_t n, int mp, int mv,
+                     const CovParams& p, int32_t* nbr) {
+  hipLaunchKernelGGL(k_knn, dim3((unsigned)ceil_div(nq, QB)), dim3(256), 0, st, Xq, Vq, vnq, nq, X, V, vnorm, n, mp,
+                     mv, p, 1, nbr);
 }

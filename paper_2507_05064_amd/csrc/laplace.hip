@@ -389,6 +389,9 @@ void launch_utv(hipStream_t st, const T* U, const double* v, const double* scale
   hipLaunchKernelGGL((k_utv<T>), dim3((unsigned)ceil_div(n, chunk)), dim3(512), 0, st, U, v, scale, n, mp, chunk,
                      partial);
 }
+void launch_colreduce(hipStream_t st, const double* partial, int nchunk, int mp, double* out) {
+  hipLaunchKernelGGL(k_colreduce, dim3((unsigned)ceil_div(mp, 64)), dim3(256), 0, st, partial, nchunk, mp, out);
+}
 void launch_reduce_apply(hipStream_t st, const double* partial, int nchunk, int mp, const double* Minv, double* cbuf,
                          double* out) {
   hipLaunchKernelGGL(k_colreduce, dim3((unsigned)ceil_div(mp, 64)), dim3(256), 0, st, partial, nchunk, mp, cbuf);

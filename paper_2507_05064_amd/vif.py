@@ -67,7 +67,8 @@ EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors"
            "vif_get_timing", "vif_laplace_mode", "vif_mlp_num_params", "vif_mlp_workspace_floats",
            "vif_mlp_forward", "vif_mlp_backward", "vif_mlp_adam", "vif_mlp_features", "vif_sample_prior",
            "vif_precond_solve", "vif_batch_create", "vif_batch_destroy", "vif_batch_last_error",
-           "vif_batch_nll_grad", "vif_laplace_nll", "vif_laplace_nll_grad"]
+           "vif_batch_nll_grad", "vif_laplace_nll", "vif_laplace_nll_grad", "vif_select_neighbors_pred",
+           "vif_predict"]
 
 
 def load_library(path: Optional[str] = None):
@@ -112,6 +113,10 @@ def load_library(path: Optional[str] = None):
     lib.vif_laplace_nll.restype = ctypes.c_int
     lib.vif_laplace_nll_grad.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, dp, dp]
     lib.vif_laplace_nll_grad.restype = ctypes.c_int
+    lib.vif_select_neighbors_pred.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.vif_select_neighbors_pred.restype = ctypes.c_int
+    lib.vif_predict.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp]
+    lib.vif_predict.restype = ctypes.c_int
     lib.vif_batch_create.argtypes = [ctypes.POINTER(vif_batch_config), ctypes.POINTER(ctypes.c_int64), vp,
                                      ctypes.POINTER(vp)]
     lib.vif_batch_create.restype = ctypes.c_int
@@ -264,6 +269,18 @@ class VifContext:
                                                   _ptr(eps_m) if self.m else None, ctypes.byref(nll),
                                                   g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return nll.value, g
+
+    def select_neighbors_pred(self, Xp: torch.Tensor) -> torch.Tensor:
+        nbrp = torch.full((Xp.shape[0], max(self.m_v, 1)), -1, dtype=torch.int32, device="cuda")
+        self._check(self.lib.vif_select_neighbors_pred(self.h, _ptr(Xp), Xp.shape[0], _ptr(nbrp)))
+        return nbrp
+
+    def predict(self, y: torch.Tensor, Xp: torch.Tensor, nbrp: torch.Tensor) -> torch.Tensor:
+        """Posterior predictive mean at Xp (Prop. 2.1); y = response, or the mode for a latent model."""
+        mu = torch.empty(Xp.shape[0], dtype=torch.float64, device="cuda")
+        self._check(self.lib.vif_predict(self.h, _ptr(y), _ptr(Xp), _ptr(nbrp) if self.m_v else None, Xp.shape[0],
+                                         _ptr(mu), None))
+        return mu
 
     def precond_solve(self, W: torch.Tensor, r: torch.Tensor) -> torch.Tensor:
         z = torch.empty(self.n, dtype=torch.float64, device="cuda")

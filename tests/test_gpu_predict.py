@@ -1,0 +1,65 @@
+"""GPU parity of prediction (Prop. 2.1, B_p = I): prediction neighbours
+bit-exact as sets against the oracle's brute force (near-ties in key within
+1e-12 accepted), and the predictive mean against the oracle on the same
+neighbour sets: FP64 within 1e-10 of max|mu|, FP32 form within 1e-4."""
+import numpy as np
+import pytest
+import torch
+
+import vif_inputs as vi
+from oracle import predict_oracle as po
+from oracle import vif_oracle as vo
+from tests.gpu_util import nbr_to_dev, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n, npred, m, mv, seed):
+    w = vi.Workload("pred", 13, n + npred, 2, m, mv, vo.MATERN32, 1.0, np.array([0.1]), 0.05, 0.0, "gaussian",
+                    "subset")
+    XA = vi.coords(w, seed)
+    X, Xp = XA[:n], XA[n:]
+    Z = vi.inducing_points(vi.scaled(w, n), X, seed) if m else np.zeros((0, 2))
+    model = vo.Model(vo.MATERN32, 1.0, np.array([0.1]), 0.05)
+    nbr = vo.neighbours(model, X, vo.inducing(model, X, Z), mv)
+    y = np.linalg.cholesky(vo.cov(model, X, X) + 0.05 * np.eye(n)) @ np.random.default_rng(seed).standard_normal(n)
+    return w, model, X, Xp, Z, nbr, y
+
+
+@pytest.mark.parametrize("n,npred,m,mv,prec", [(1000, 300, 25, 10, "fp64"), (777, 129, 0, 7, "fp64"),
+                                               (1000, 300, 25, 10, "fp32"), (600, 70, 17, 20, "fp64")])
+def test_predict_matches_oracle(n, npred, m, mv, prec):
+    from paper_2507_05064_amd.vif import VifContext
+    w, model, X, Xp, Z, nbr, y = _setup(n, npred, m, mv, seed=n + npred)
+    nbr_p = po.prediction_neighbours(model, X, Z, Xp, mv)
+    ref = po.predictive_mean(model, X, Z, nbr, y, Xp, nbr_p)
+    print(f"[gpu] predict n={n} n_p={npred} m={m} m_v={mv} {prec}", flush=True)
+    ctx = VifContext(n, 2, m, mv, kernel=model.kernel, precision=prec)
+    ctx.build_factor(to_dev(X), to_dev(Z) if m else None, nbr_to_dev(nbr), model.theta)
+    g = ctx.select_neighbors_pred(to_dev(Xp)).cpu().numpy()
+    same = [set(g[j]) == set(nbr_p[j]) for j in range(npred)]
+    if not all(same):  # only near-ties may differ
+        XA = np.vstack([X, Xp])
+        indA = vo.inducing(model, XA, Z)
+        for j in np.nonzero(~np.array(same))[0]:
+            keys = vo.neighbour_keys(model, XA, indA, n + j, np.arange(n))
+            kg, ko = np.sort(keys[g[j]]), np.sort(keys[nbr_p[j]])
+            assert np.max(np.abs(kg - ko)) <= 1e-12, (j, kg, ko)
+    mu = ctx.predict(to_dev(y), to_dev(Xp), nbr_to_dev(nbr_p)).cpu().numpy()
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    assert np.max(np.abs(mu - ref)) <= tol * np.max(np.abs(ref)), np.max(np.abs(mu - ref))
+
+
+def test_predict_rejects_variances():
+    from paper_2507_05064_amd.vif import VifContext, VifError
+    import ctypes
+    w, model, X, Xp, Z, nbr, y = _setup(300, 10, 10, 5, seed=1)
+    ctx = VifContext(300, 2, 10, 5, kernel=model.kernel)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), model.theta)
+    var = torch.empty(10, dtype=torch.float64, device="cuda")
+    mu = torch.empty(10, dtype=torch.float64, device="cuda")
+    nbrp = ctx.select_neighbors_pred(to_dev(Xp))
+    rc = ctx.lib.vif_predict(ctx.h, ctypes.c_void_p(to_dev(y).data_ptr()), ctypes.c_void_p(to_dev(Xp).data_ptr()),
+                             ctypes.c_void_p(nbrp.data_ptr()), 10, ctypes.c_void_p(mu.data_ptr()),
+                             ctypes.c_void_p(var.data_ptr()))
+    assert rc == 1

@@ -1,0 +1,91 @@
+"""Pins of the predictive-mean oracle (Prop. 2.1) against closed forms:
+  * full conditioning (training m_v = n - 1, prediction points conditioning
+    on all n training points) makes the Vecchia part exact, so the mean is
+    the exact GP predictive mean K_pn (K + s2 I)^{-1} y for any m;
+  * m_v = 0 for training and prediction gives the FITC predictive mean
+    Q_pn (Q_nn + diag(K - Q_nn) + s2 I)^{-1} y, Q = K_.m K_m^{-1} K_m.;
+  * in general, the conditional mean of the joint covariance that
+    eq. vecchia_pred defines, built densely (B_p = I);
+  * the prediction neighbours are the brute-force smallest keys."""
+import numpy as np
+import pytest
+
+import vif_inputs as vi
+from oracle import predict_oracle as po
+from oracle import vif_oracle as vo
+
+
+def _setup(n=150, npred=20, m=12, s2=0.05, seed=0):
+    w = vi.Workload("pred", 13, n + npred, 2, m, 5, vo.MATERN32, 1.0, np.array([0.2]), s2, 0.0, "gaussian", "subset")
+    XA = vi.coords(w, seed)
+    X, Xp = XA[:n], XA[n:]
+    Z = vi.inducing_points(vi.scaled(w, n), X, seed) if m else np.zeros((0, 2))
+    model = vo.Model(vo.MATERN32, 1.0, np.array([0.2]), s2)
+    y = np.linalg.cholesky(vo.cov(model, X, X) + s2 * np.eye(n)) @ np.random.default_rng(seed).standard_normal(n)
+    return model, X, Xp, Z, y
+
+
+@pytest.mark.parametrize("m", [0, 12])
+def test_full_conditioning_gives_exact_gp_mean(m):
+    model, X, Xp, Z, y = _setup(m=m)
+    n = X.shape[0]
+    nbr = -np.ones((n, n - 1), dtype=np.int64)
+    for i in range(n):
+        nbr[i, :i] = np.arange(i)
+    nbr_p = np.tile(np.arange(n), (Xp.shape[0], 1))
+    mu = po.predictive_mean(model, X, Z, nbr, y, Xp, nbr_p)
+    ref = vo.cov(model, Xp, X) @ np.linalg.solve(vo.cov(model, X, X) + model.s2 * np.eye(n), y)
+    assert np.max(np.abs(mu - ref)) <= 1e-8 * np.max(np.abs(ref))
+
+
+def test_no_neighbours_gives_fitc_mean():
+    model, X, Xp, Z, y = _setup()
+    n = X.shape[0]
+    mu = po.predictive_mean(model, X, Z, np.zeros((n, 0), dtype=np.int64), y, Xp,
+                            np.zeros((Xp.shape[0], 0), dtype=np.int64))
+    Kmm = vo.cov(model, Z, Z)
+    Kmn, Kmp = vo.cov(model, Z, X), vo.cov(model, Z, Xp)
+    Q = Kmn.T @ np.linalg.solve(Kmm, Kmn)
+    S = Q + np.diag(np.diag(vo.cov(model, X, X) - Q)) + model.s2 * np.eye(n)
+    ref = Kmp.T @ np.linalg.solve(Kmm, Kmn) @ np.linalg.solve(S, y)
+    assert np.max(np.abs(mu - ref)) <= 1e-9 * np.max(np.abs(ref))
+
+
+def test_mean_is_the_conditional_of_the_joint_vecchia_covariance():
+    model, X, Xp, Z, y = _setup(n=120, npred=15)
+    n, npred, mv = X.shape[0], Xp.shape[0], 5
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, mv)
+    nbr_p = po.prediction_neighbours(model, X, Z, Xp, mv)
+    mu = po.predictive_mean(model, X, Z, nbr, y, Xp, nbr_p)
+    # joint residual precision of eq. vecchia_pred with B_p = I, densely
+    XA = np.vstack([X, Xp])
+    indA = vo.inducing(model, XA, Z)
+    fac = vo.vecchia_factor(model, X, ind, nbr)
+    Ap, Dp = vo.vecchia_factor_points(model, XA, indA, nbr_p, n + np.arange(npred))
+    N = n + npred
+    BJ = np.eye(N)
+    for i in range(n):
+        for s_ in range(mv):
+            if nbr[i, s_] >= 0:
+                BJ[i, nbr[i, s_]] = -fac.A[i, s_]
+    for j in range(npred):
+        for s_ in range(mv):
+            BJ[n + j, nbr_p[j, s_]] = -Ap[j, s_]
+    DJ = np.concatenate([fac.D, Dp])
+    res = np.linalg.inv(BJ.T @ np.diag(1.0 / DJ) @ BJ)
+    Kzm = vo.cov(model, Z, XA)
+    C = Kzm.T @ np.linalg.solve(vo.cov(model, Z, Z), Kzm) + res
+    ref = C[n:, :n] @ np.linalg.solve(C[:n, :n], y)
+    assert np.max(np.abs(mu - ref)) <= 1e-8 * np.max(np.abs(ref))
+
+
+def test_prediction_neighbours_are_smallest_keys():
+    model, X, Xp, Z, y = _setup(n=80, npred=6)
+    nbr_p = po.prediction_neighbours(model, X, Z, Xp, 7)
+    XA = np.vstack([X, Xp])
+    indA = vo.inducing(model, XA, Z)
+    for j in range(6):
+        keys = vo.neighbour_keys(model, XA, indA, 80 + j, np.arange(80))
+        ref = sorted(range(80), key=lambda c: (keys[c], c))[:7]
+        assert list(nbr_p[j]) == ref
