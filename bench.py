@@ -43,6 +43,26 @@ def factor_bytes_per_point(m: int, mv: int, d: int, tsize: int) -> int:
     return (mv + 1) * m * tsize + mv * 4 + (mv + 1) * d * 8 + m * tsize + mv * tsize + 8
 
 
+def measured_traffic():
+    """HBM bytes per launch of the factor kernel from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
+    import hashlib
+    try:
+        txt = open(os.path.join(ROOT, "profiles", "k_factor_fp32_c2_pmc.md")).read()
+        src = open(os.path.join(ROOT, "paper_2507_05064_amd", "csrc", "factor.hip"), "rb").read()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        line = line.strip().lstrip("- ")
+        for key in ("traffic_bytes_per_launch", "source_sha256"):
+            if line.startswith(key):
+                vals[key] = line.split(":", 1)[1].strip().split()[-1]
+    if vals.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return float(vals["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in vals else None
+
+
 def run_form(w, Xd, Zd, nbr, yd, precision, steps, warmup, grad):
     import torch
     from paper_2507_05064_amd.vif import VifContext
@@ -388,7 +408,7 @@ def main():
         "stage_ms": {"fp32": r32["stages"], "fp64": r64["stages"]},
         "neighbour_search_s": knn_s,
         "roofline": {"bound": "hbm", "kernel": "k_factor<float>", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "bytes_per_launch": nbytes, "avg_launch_ms": fac_ms},
     }
     if not args.no_batch:
