@@ -1,5 +1,7 @@
 // C ABI of the VIF library: context, workspace, argument checks and the
 // launch sequence of each entry point on the caller's stream.
+#include <algorithm>
+#include <cmath>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -54,6 +56,10 @@ struct vif_ctx {
   int32_t* nbr = nullptr;
   bool nbr_valid = false;
   bool rev_valid = false;  // reverse (transposed) neighbour lists built for c->nbr
+  // visiting order of the per-point factor kernels (a permutation of 0..n-1,
+  // recomputed from X whenever the neighbour list changes); null = natural
+  int* vorder = nullptr;
+  bool vorder_valid = false;
   double *Xc = nullptr, *Zc = nullptr;  // the context's copies of X and Z of the last build
   // gradient workspace
   double *Minv = nullptr, *wvec = nullptr, *e = nullptr, *Smat = nullptr, *Tm = nullptr, *tmpm = nullptr;
@@ -111,6 +117,8 @@ static vif_status fail(vif_ctx* c, vif_status s, const char* fmt, ...) {
     hipError_t e_ = (x);                                                                  \
     if (e_ != hipSuccess) return fail((c), VIF_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
   } while (0)
+
+static const int* vorder(const vif_ctx* c) { return c->vorder_valid ? c->vorder : nullptr; }
 
 static void stage_begin(vif_ctx* c, int s) {
   if (c->timing) hipEventRecord(c->timers[s].b, c->st);
@@ -255,6 +263,7 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   alloc((void**)&c->scal, sizeof(double) * 16);
   alloc((void**)&c->status, sizeof(int) * 8);
   alloc((void**)&c->nbr, sizeof(int32_t) * n * (g.m_v > 0 ? g.m_v : 1));
+  alloc((void**)&c->vorder, sizeof(int) * n);
   alloc((void**)&c->Xc, sizeof(double) * n * g.d);
   alloc((void**)&c->Zc, sizeof(double) * (g.m > 0 ? g.m : 1) * g.d);
   if (g.likelihood == VIF_LIK_GAUSSIAN) {
@@ -325,7 +334,7 @@ void vif_destroy(vif_ctx* c) {
                   c->slq_q, c->slq_iters, c->lg_Ut, c->lg_Ut3, c->lg_dV, c->lg_dU[0], c->lg_dU[1], c->lg_dU[2],
                   c->lg_dA[0], c->lg_dA[1], c->lg_dA[2], c->lg_MT, c->lg_M3T, c->lg_PhiT, c->lg_dD[0],
                   c->lg_dD[1], c->lg_dD[2], c->lg_mm, c->lg_vec, c->lg_part, c->lg_slots, c->pred_Vp,
-                  c->pred_Ap, c->pred_Vpd, c->pred_vn, c->pred_Dp};
+                  c->pred_Ap, c->pred_Vpd, c->pred_vn, c->pred_Dp, c->vorder};
   for (void* b : bufs)
     if (b) hipFree(b);
   for (int t = 0; t < ST_COUNT; ++t) {
@@ -407,6 +416,43 @@ vif_status vif_select_neighbors(vif_ctx* c, const double* X, const double* Z, co
   return read_status(c, "vif_select_neighbors");
 }
 
+// Visiting order of the per-point factor kernels. A point's gather touches its
+// neighbours' V rows, which are spatially close; sorting the points along a
+// Morton (Z-order) curve of X makes the workgroups that run together share
+// those rows in L2. Workgroups are dealt round-robin to the 8 XCDs, each with
+// its own L2, so XCD x is given one contiguous stretch of the curve: launch
+// slot b maps to curve position off(b % 8) + b / 8. Every point is visited
+// exactly once whatever the order, so the results do not depend on it.
+static void morton_order(const std::vector<double>& X, int64_t n, int d, std::vector<int>& out) {
+  const int bits = d > 0 ? std::min(21, 63 / d) : 1;
+  std::vector<double> lo(d, 1e300), hi(d, -1e300);
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < d; ++k) {
+      lo[k] = std::min(lo[k], X[i * d + k]);
+      hi[k] = std::max(hi[k], X[i * d + k]);
+    }
+  const double cells = (double)((1ull << bits) - 1);
+  std::vector<std::pair<uint64_t, int>> key((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t code = 0;
+    uint32_t q[VIF_MAX_D];
+    for (int k = 0; k < d; ++k) {
+      const double w = hi[k] > lo[k] ? (X[i * d + k] - lo[k]) / (hi[k] - lo[k]) : 0.0;
+      q[k] = (uint32_t)std::min(cells, std::max(0.0, std::floor(w * cells + 0.5)));
+    }
+    for (int b = bits - 1; b >= 0; --b)
+      for (int k = 0; k < d; ++k) code = (code << 1) | ((q[k] >> b) & 1u);
+    key[(size_t)i] = {code, (int)i};
+  }
+  std::sort(key.begin(), key.end());
+  const int64_t qn = n / 8, rn = n % 8;
+  out.resize((size_t)n);
+  for (int64_t b = 0; b < n; ++b) {
+    const int64_t x = b % 8, slot = b / 8;
+    out[(size_t)b] = key[(size_t)(x * qn + std::min<int64_t>(x, rn) + slot)].second;
+  }
+}
+
 vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const int32_t* nbr, const double* theta) {
   if (!c) return VIF_E_ARG;
   c->built = false;
@@ -430,10 +476,11 @@ vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const 
   if ((s = build_inducing(c, X, Z, !f32))) return s;
   stage_begin(c, ST_FACTOR);
   if (f32)
-    launch_factor<float>(c->st, X, c->Vf, nbr, g.n, c->mp, g.m_v, c->cp, (float*)c->A, c->D, (float*)c->U, c->status);
+    launch_factor<float>(c->st, X, c->Vf, nbr, g.n, c->mp, g.m_v, c->cp, (float*)c->A, c->D, (float*)c->U, c->status,
+                         Batch{nullptr, nullptr}, vorder(c));
   else
     launch_factor<double>(c->st, X, c->Vd, nbr, g.n, c->mp, g.m_v, c->cp, (double*)c->A, c->D, (double*)c->U,
-                          c->status);
+                          c->status, Batch{nullptr, nullptr}, vorder(c));
   stage_end(c, ST_FACTOR);
   if (g.m > 0) {
     int nchunk = 0;
@@ -457,6 +504,14 @@ vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const 
     c->nbr_valid = true;
     c->rev_valid = false;
     c->lev_valid = false;
+    std::vector<double> hx((size_t)g.n * g.d);
+    HIPCHK(c, hipMemcpyAsync(hx.data(), c->Xc, sizeof(double) * g.n * g.d, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    std::vector<int> ord;
+    morton_order(hx, g.n, g.d, ord);
+    HIPCHK(c, hipMemcpyAsync(c->vorder, ord.data(), sizeof(int) * g.n, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->vorder_valid = true;
   }
   c->built = true;
   c->coef_valid = false;
@@ -547,7 +602,8 @@ static vif_status nll_grad_impl(vif_ctx* c, const double* y) {
   }
   stage_begin(c, ST_FBWD);
   launch_factor_bwd<T>(c->st, c->Xc, V, (const T*)c->Vr, c->nbr, y, U, (const T*)c->Ubar, c->e, c->yt, c->D, g.n, mp,
-                       g.m_v, c->cp, (T*)c->Q1, (T*)c->Gs, (T*)c->Bs, c->tpart, c->status);
+                       g.m_v, c->cp, (T*)c->Q1, (T*)c->Gs, (T*)c->Bs, c->tpart, c->status, Batch{nullptr, nullptr},
+                       vorder(c));
   stage_end(c, ST_FBWD);
   double* tp = c->gred;
   const int nt = launch_colsum(c->st, c->tpart, g.n, 3, tp);
@@ -1383,7 +1439,8 @@ static vif_status laplace_grad_impl(vif_ctx* c, const double* y, const double* m
       }
       dVp = dV;
     }
-    launch_factor_jvp<T>(c->st, c->Xc, V, dVp, c->nbr, U, n, mp, mv, c->cp, p, dA, c->lg_dD[p], dU, c->status);
+    launch_factor_jvp<T>(c->st, c->Xc, V, dVp, c->nbr, U, n, mp, mv, c->cp, p, dA, c->lg_dD[p], dU, c->status,
+                         vorder(c));
     nb = launch_trace_terms<T>(c->st, (const T*)c->lg_Ut, (const T*)c->lg_Ut3, U, dU, c->D, c->lg_dD[p], B.W, n, mp,
                                part);
     launch_sum_cols(c->st, part, nb, 4, tslots + 4 * p);

@@ -186,13 +186,16 @@ template <typename T, int NBLK>
 __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, const T* __restrict__ V,
                                                const int32_t* __restrict__ nbr, int64_t n, int mp, int mv,
                                                CovParams p_in, T* __restrict__ Aout, double* __restrict__ Dout,
-                                               T* __restrict__ U, int* status, Batch bt) {
+                                               T* __restrict__ U, int* status, Batch bt,
+                                               const int* __restrict__ perm) {
   __shared__ PointShared<T> sh;
   T Lrow[32];
   int k;
   T D;
   const int lane = threadIdx.x;
-  const int64_t i = blockIdx.x;
+  // perm: a visiting order (workgroups that run together take nearby points,
+  // whose neighbour rows then meet in L2); results do not depend on it
+  const int64_t i = perm ? (int64_t)perm[blockIdx.x] : (int64_t)blockIdx.x;
   CovParams p = p_in;
   if (bt.bp) {
     const BatchProb& q = bt.bp[bt.blk2prob[i / kBatchBlock]];
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
                                                    const double* __restrict__ yt, const double* __restrict__ Dfwd,
                                                    int64_t n, int mp, int mv, CovParams p_in, T* __restrict__ Q1,
                                                    T* __restrict__ Gs, T* __restrict__ Bs, double* __restrict__ tpart,
-                                                   int* status, Batch bt) {
+                                                   int* status, Batch bt, const int* __restrict__ perm) {
   __shared__ PointShared<T> sh;
   __shared__ T rho_s[32];
   T Lrow[32];
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   T D;
   const int lane = threadIdx.x;
   const int myrow = lane & 31;
-  const int64_t i = blockIdx.x;
+  const int64_t i = perm ? (int64_t)perm[blockIdx.x] : (int64_t)blockIdx.x;
   CovParams p = p_in;
   if (bt.bp) {
     const BatchProb& q = bt.bp[bt.blk2prob[i / kBatchBlock]];
@@ -379,7 +382,7 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
                                                    const T* __restrict__ dV, const int32_t* __restrict__ nbr,
                                                    const T* __restrict__ U, int64_t n, int mp, int mv, CovParams p,
                                                    int which, T* __restrict__ dA, double* __restrict__ dD,
-                                                   T* __restrict__ dU, int* status) {
+                                                   T* __restrict__ dU, int* status, const int* __restrict__ perm) {
   typedef typename Vec4<T>::type T4;
   typedef typename Acc4<T>::type A4;
   __shared__ PointShared<T> sh;
@@ -390,7 +393,7 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
   T D;
   const int lane = threadIdx.x;
   const int myrow = lane & 31;
-  const int64_t i = blockIdx.x;
+  const int64_t i = perm ? (int64_t)perm[blockIdx.x] : (int64_t)blockIdx.x;
   if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, Lrow, k, D, status)) {
     if (lane == 0) dD[i] = __builtin_nan("");
     return;
@@ -520,20 +523,20 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
 template <typename T>
 void launch_factor_jvp(hipStream_t st, const double* X, const T* V, const T* dV, const int32_t* nbr, const T* U,
                        int64_t n, int mp, int mv, const CovParams& p, int which, T* dA, double* dD, T* dU,
-                       int* status) {
+                       int* status, const int* perm) {
   if (mv + 1 <= 16)
     hipLaunchKernelGGL((k_factor_jvp<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, dV, nbr, U, n, mp, mv, p,
-                       which, dA, dD, dU, status);
+                       which, dA, dD, dU, status, perm);
   else
     hipLaunchKernelGGL((k_factor_jvp<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, dV, nbr, U, n, mp, mv, p,
-                       which, dA, dD, dU, status);
+                       which, dA, dD, dU, status, perm);
 }
 template void launch_factor_jvp<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
                                         const double*, int64_t, int, int, const CovParams&, int, double*, double*,
-                                        double*, int*);
+                                        double*, int*, const int*);
 template void launch_factor_jvp<float>(hipStream_t, const double*, const float*, const float*, const int32_t*,
                                        const float*, int64_t, int, int, const CovParams&, int, float*, double*,
-                                       float*, int*);
+                                       float*, int*, const int*);
 
 // Factor rows of prediction points (Prop. 2.1, with B_p = I): eq. D_A_Vecchia
 // for prediction point j over its training neighbours nbrp[j] (all < n),
@@ -622,13 +625,13 @@ __global__ void k_ytilde(const T* __restrict__ A, const double* __restrict__ D, 
 
 template <typename T>
 void launch_factor(hipStream_t st, const double* X, const T* V, const int32_t* nbr, int64_t n, int mp, int mv,
-                   const CovParams& p, T* A, double* D, T* U, int* status, Batch bt) {
+                   const CovParams& p, T* A, double* D, T* U, int* status, Batch bt, const int* perm) {
   if (mv + 1 <= 16)
     hipLaunchKernelGGL((k_factor<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, nbr, n, mp, mv, p, A, D, U, status,
-                       bt);
+                       bt, perm);
   else
     hipLaunchKernelGGL((k_factor<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, nbr, n, mp, mv, p, A, D, U, status,
-                       bt);
+                       bt, perm);
 }
 
 template <typename T>
@@ -638,9 +641,9 @@ void launch_ytilde(hipStream_t st, const T* A, const double* D, const int32_t* n
 }
 
 template void launch_factor<double>(hipStream_t, const double*, const double*, const int32_t*, int64_t, int, int,
-                                    const CovParams&, double*, double*, double*, int*, Batch);
+                                    const CovParams&, double*, double*, double*, int*, Batch, const int*);
 template void launch_factor<float>(hipStream_t, const double*, const float*, const int32_t*, int64_t, int, int,
-                                   const CovParams&, float*, double*, float*, int*, Batch);
+                                   const CovParams&, float*, double*, float*, int*, Batch, const int*);
 template void launch_ytilde<double>(hipStream_t, const double*, const double*, const int32_t*, const double*, int64_t,
                                     int, double*);
 template void launch_ytilde<float>(hipStream_t, const float*, const double*, const int32_t*, const double*, int64_t,
@@ -650,19 +653,19 @@ template <typename T>
 void launch_factor_bwd(hipStream_t st, const double* X, const T* V, const T* Vr, const int32_t* nbr, const double* y,
                        const T* U, const T* Ubar, const double* e, const double* yt, const double* D, int64_t n,
                        int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status,
-                       Batch bt) {
+                       Batch bt, const int* perm) {
   if (mv + 2 <= 16)
     hipLaunchKernelGGL((k_factor_bwd<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
-                       n, mp, mv, p, Q1, Gs, Bs, tpart, status, bt);
+                       n, mp, mv, p, Q1, Gs, Bs, tpart, status, bt, perm);
   else
     hipLaunchKernelGGL((k_factor_bwd<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
-                       n, mp, mv, p, Q1, Gs, Bs, tpart, status, bt);
+                       n, mp, mv, p, Q1, Gs, Bs, tpart, status, bt, perm);
 }
 template void launch_factor_bwd<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
                                         const double*, const double*, const double*, const double*, const double*,
                                         const double*, int64_t, int, int, const CovParams&, double*, double*, double*,
-                                        double*, int*, Batch);
+                                        double*, int*, Batch, const int*);
 template void launch_factor_bwd<float>(hipStream_t, const double*, const float*, const float*, const int32_t*,
                                        const double*, const float*, const float*, const double*, const double*,
                                        const double*, int64_t, int, int, const CovParams&, float*, float*, float*,
-                                       double*, int*, Batch);
+                                       double*, int*, Batch, const int*);

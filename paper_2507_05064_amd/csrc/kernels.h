@@ -33,7 +33,8 @@ void launch_knn_pred(hipStream_t st, const double* Xq, const double* Vq, const d
 // factor.hip
 template <typename T>
 void launch_factor(hipStream_t st, const double* X, const T* V, const int32_t* nbr, int64_t n, int mp, int mv,
-                   const CovParams& p, T* A, double* D, T* U, int* status, Batch bt = Batch{nullptr, nullptr});
+                   const CovParams& p, T* A, double* D, T* U, int* status, Batch bt = Batch{nullptr, nullptr},
+                   const int* perm = nullptr);
 template <typename T>
 void launch_ytilde(hipStream_t st, const T* A, const double* D, const int32_t* nbr, const double* y, int64_t n,
                    int mv, double* yt);
@@ -52,7 +53,7 @@ template <typename T>
 void launch_factor_bwd(hipStream_t st, const double* X, const T* V, const T* Vr, const int32_t* nbr, const double* y,
                        const T* U, const T* Ubar, const double* e, const double* yt, const double* D, int64_t n,
                        int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status,
-                       Batch bt = Batch{nullptr, nullptr});
+                       Batch bt = Batch{nullptr, nullptr}, const int* perm = nullptr);
 
 // grad.hip
 void launch_gemm_sq(hipStream_t st, const double* A, const double* B, double* C, int mp, bool ta, bool tb,
@@ -155,7 +156,7 @@ void launch_direct_rhs(hipStream_t st, const double* W, const double* b, const d
 template <typename T>
 void launch_factor_jvp(hipStream_t st, const double* X, const T* V, const T* dV, const int32_t* nbr, const T* U,
                        int64_t n, int mp, int mv, const CovParams& p, int which, T* dA, double* dD, T* dU,
-                       int* status);
+                       int* status, const int* perm = nullptr);
 
 template <typename T>
 void launch_pred_factor(hipStream_t st, const double* X, const T* V, const double* Xp, const T* Vp,

@@ -76,16 +76,21 @@ __global__ void k_direct_rhs(const double* __restrict__ W, const double* __restr
 
 // t = D^{-1/2} B w :  t_i = (w_i - sum_j A_ij w_{N(i)_j}) / sqrt(D_i)
 template <typename T>
-__global__ void k_bw(const T* __restrict__ A, const double* __restrict__ D, const int32_t* __restrict__ nbr,
-                     const double* __restrict__ w, int64_t n, int mv, double* __restrict__ t) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = w[i];
-  for (int a = 0; a < mv; ++a) {
+// (8 lanes per point split the row; their sums are combined by shuffles)
+__global__ __launch_bounds__(256) void k_bw(const T* __restrict__ A, const double* __restrict__ D,
+                                            const int32_t* __restrict__ nbr, const double* __restrict__ w, int64_t n,
+                                            int mv, double* __restrict__ t) {
+  const int lig = threadIdx.x & 7;
+  const int64_t i = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
+  if (i >= n) return;  // whole 8-lane groups leave together
+  double s = 0.0;
+  for (int a = lig; a < mv; a += 8) {
     const int j = nbr[i * mv + a];
-    if (j >= 0) s -= (double)A[i * mv + a] * w[j];
+    if (j >= 0) s += (double)A[i * mv + a] * w[j];
   }
-  t[i] = s / sqrt(D[i]);
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) s += __shfl_xor(s, o, 8);
+  if (lig == 0) t[i] = (w[i] - s) / sqrt(D[i]);
 }
 
 // per-chunk partials of U^T (scale .* v): partial[chunk][mp]; scale may be null
@@ -169,19 +174,22 @@ __global__ __launch_bounds__(256) void k_t_minus_uc(const T* __restrict__ U, con
 
 // out_j = W_j p_j + s_j - sum_{(q,slot): N(q)_slot = j} A_{q,slot} s_q   (W may be null)
 template <typename T>
-__global__ void k_btw(const T* __restrict__ A, const int* __restrict__ rev_ptr, const int* __restrict__ rev_idx,
-                      const double* __restrict__ s, const double* __restrict__ W, const double* __restrict__ p,
-                      int64_t n, int mv, double* __restrict__ out) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  double v = s[j];
-  const int beg = rev_ptr[j], end = rev_ptr[j + 1];
-  for (int q = beg; q < end; ++q) {
+__global__ __launch_bounds__(256) void k_btw(const T* __restrict__ A, const int* __restrict__ rev_ptr,
+                                             const int* __restrict__ rev_idx, const double* __restrict__ s,
+                                             const double* __restrict__ W, const double* __restrict__ p, int64_t n,
+                                             int mv, double* __restrict__ out) {
+  const int lig = threadIdx.x & 7;
+  const int64_t j = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
+  if (j >= n) return;  // whole 8-lane groups leave together
+  double v = 0.0;
+  const int end = rev_ptr[j + 1];
+  for (int q = rev_ptr[j] + lig; q < end; q += 8) {
     const int idx = rev_idx[q];
-    v -= (double)A[idx] * s[idx / mv];
+    v += (double)A[idx] * s[idx / mv];
   }
-  if (W) v += W[j] * p[j];
-  out[j] = v;
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) v += __shfl_xor(v, o, 8);
+  if (lig == 0) out[j] = s[j] - v + (W ? W[j] * p[j] : 0.0);
 }
 
 // per-block partials of up to two dot products a.b, c.d
@@ -381,7 +389,7 @@ void launch_lik_at(hipStream_t st, int lik, double lpar, const double* y, const 
 template <typename T>
 void launch_bw(hipStream_t st, const T* A, const double* D, const int32_t* nbr, const double* w, int64_t n, int mv,
                double* t) {
-  hipLaunchKernelGGL((k_bw<T>), g1(n), dim3(256), 0, st, A, D, nbr, w, n, mv, t);
+  hipLaunchKernelGGL((k_bw<T>), g1(n, 32), dim3(256), 0, st, A, D, nbr, w, n, mv, t);
 }
 template <typename T>
 void launch_utv(hipStream_t st, const T* U, const double* v, const double* scale, int64_t n, int mp, int chunk,
@@ -405,7 +413,7 @@ void launch_t_minus_uc(hipStream_t st, const T* U, const double* c, const double
 template <typename T>
 void launch_btw(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s, const double* W,
                 const double* p, int64_t n, int mv, double* out) {
-  hipLaunchKernelGGL((k_btw<T>), g1(n), dim3(256), 0, st, A, rev_ptr, rev_idx, s, W, p, n, mv, out);
+  hipLaunchKernelGGL((k_btw<T>), g1(n, 32), dim3(256), 0, st, A, rev_ptr, rev_idx, s, W, p, n, mv, out);
 }
 int launch_dot2(hipStream_t st, const double* a, const double* b, const double* c, const double* d, int64_t n,
                 double* part, double* out) {

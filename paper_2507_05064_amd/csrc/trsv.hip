@@ -151,7 +151,21 @@ __global__ __launch_bounds__(1024) void k_trsv_bwd_run(const int* __restrict__ l
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < kPre; ++k) s += cur.w[k] * zv[k];
-    for (int a = cur.rem; a < cur.e1; a += G) s += (double)coef[a] * zq[col[a]];  // rows longer than 8G
+    // rows longer than 8 G entries: the rest, 8 per lane at a time (loads first)
+    for (int a0 = cur.rem; a0 < cur.e1; a0 += kPre * G) {
+      int cc[kPre];
+      double ww[kPre], zz[kPre];
+#pragma unroll
+      for (int k = 0; k < kPre; ++k) {
+        const int a = a0 + k * G;
+        cc[k] = a < cur.e1 ? col[a] : -1;
+        ww[k] = a < cur.e1 ? (double)coef[a] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kPre; ++k) zz[k] = cc[k] >= 0 ? zq[cc[k]] : 0.0;
+#pragma unroll
+      for (int k = 0; k < kPre; ++k) s += ww[k] * zz[k];
+    }
     for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if (cur.q >= 0 && lig == 0) zq[cur.q] = cur.x + s;
     __syncthreads();
