@@ -44,6 +44,110 @@ __global__ void k_cov_zz(const double* Z, int m, int mp, CovParams p_in, double 
   }
 }
 
+// Entry (i, j) of an mp x mp matrix if ok, else 0. The load is unconditional,
+// at a clamped in-range address, so that the loads of a tile issue together
+// instead of one guarded round trip each.
+__device__ __forceinline__ double ldm(const double* M, int i, int j, int mp, bool ok) {
+  const double v = M[(size_t)min(i, mp - 1) * mp + min(j, mp - 1)];
+  return ok ? v : 0.0;
+}
+
+#define CB 32
+#define CWG 512
+#define CNW (CWG / 64)
+
+// Cholesky and inverse of one SPD 16 x 16 tile on one wave. T (input, lower
+// part read), Lo and Xo are row-major with row stride CB + 1; Lo gets L and
+// Xo gets L^{-1} (upper parts zero). The 136 entries of the lower triangle
+// are dealt to the 64 lanes (entry e = lane + 64 s in packed row order) and
+// kept in registers. The factorisation runs as LDL^T (one reciprocal per
+// step, square roots applied at the end); the inverse goes row by row (row u
+// is final once scaled by 1/L_uu; every later row t subtracts L_tu times it).
+// Each step is one LDS broadcast and a branch-free update of the lane's
+// entries. buf: 32 doubles of LDS. Returns 0, or 1 + the column whose pivot
+// was not positive.
+__device__ int chol_inv16(const double* T, double* Lo, double* Xo, double* buf, int lane) {
+  constexpr int LD = CB + 1;
+  int ei[3], ej[3];
+  double a[3];
+#pragma unroll
+  for (int sl = 0; sl < 3; ++sl) {
+    const int e = lane + 64 * sl;
+    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    while (i * (i + 1) / 2 > e) --i;
+    const bool ok = e < 136;
+    ei[sl] = ok ? i : 16;  // 16 marks an unused slot
+    ej[sl] = ok ? e - i * (i + 1) / 2 : 16;
+    a[sl] = ok ? T[ei[sl] * LD + ej[sl]] : 0.0;
+  }
+  for (int k = 0; k < 16; ++k) {
+    double* col = buf + 16 * (k & 1);
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl)
+      if (ej[sl] == k) col[ei[sl]] = a[sl];
+    wave_sync();
+    const double akk = col[k];
+    double ci[3], cj[3];
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      ci[sl] = col[min(ei[sl], 15)];
+      cj[sl] = col[min(ej[sl], 15)];
+    }
+    if (!(akk > 0.0 && isfinite(akk))) return k + 1;
+    const double rk = 1.0 / akk;
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      const double upd = fma(-ci[sl] * rk, cj[sl], a[sl]);
+      a[sl] = (ej[sl] > k && ej[sl] < 16) ? upd : a[sl];
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int sl = 0; sl < 3; ++sl)
+    if (ei[sl] == ej[sl] && ei[sl] < 16) {
+      const double sq = sqrt(a[sl]);
+      buf[ei[sl]] = sq;
+      buf[16 + ei[sl]] = 1.0 / sq;
+    }
+  for (int q = lane; q < 256; q += 64) {
+    Lo[(q >> 4) * LD + (q & 15)] = 0.0;
+    Xo[(q >> 4) * LD + (q & 15)] = 0.0;
+  }
+  wave_sync();
+#pragma unroll
+  for (int sl = 0; sl < 3; ++sl) {
+    const int jj = min(ej[sl], 15);
+    a[sl] = (ei[sl] == ej[sl]) ? buf[jj] : a[sl] * buf[16 + jj];
+    if (ei[sl] < 16) Lo[ei[sl] * LD + ej[sl]] = a[sl];
+    a[sl] = (ei[sl] == ej[sl]) ? 1.0 : 0.0;
+  }
+  wave_sync();
+  for (int u = 0; u < 16; ++u) {
+    const double iu = buf[16 + u];
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl)
+      if (ei[sl] == u) {
+        a[sl] *= iu;
+        Xo[u * LD + ej[sl]] = a[sl];
+      }
+    wave_sync();
+    double lt[3], rv[3];
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      lt[sl] = Lo[min(ei[sl], 15) * LD + u];
+      rv[sl] = Xo[u * LD + min(ej[sl], 15)];
+    }
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      const double upd = fma(-lt[sl], rv[sl], a[sl]);
+      a[sl] = (ei[sl] > u && ei[sl] < 16 && ej[sl] <= u) ? upd : a[sl];
+    }
+  }
+  wave_sync();
+  return 0;
+}
+
 // Cholesky of S (in place, lower), Linv = L^{-1} and out[0] = log det S, in
 // one workgroup of 8 waves (m <= 1024; the matrices stay in L2).
 // Cholesky: right-looking over 32-column blocks; each diagonal block is
@@ -52,9 +156,6 @@ __global__ void k_cov_zz(const double* Z, int m, int mp, CovParams p_in, double 
 // both on FP64 MFMA. Inverse: X_jj = L_jj^{-1};
 // X_ij = -L_ii^{-1} sum_{k=j}^{i-1} L_ik X_kj, all block columns j advancing
 // one block row per step, the inner sums staged in `work` (mp x mp).
-#define CB 32
-#define CWG 512
-#define CNW (CWG / 64)
 __global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double* __restrict__ Linv,
                                                    double* __restrict__ work, int m, int mp, double* out,
                                                    int* status, int code_base, int ostride) {
@@ -68,6 +169,8 @@ __global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double
   }
   __shared__ double Db[CB][CB + 1];
   __shared__ double Di[CB][CB + 1];
+  __shared__ double Dt[16][CB + 1];
+  __shared__ double Dbuf[2 * CB];
   __shared__ int s_fail;
   __shared__ double red[CNW];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -79,70 +182,76 @@ __global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double
 
   for (int b = 0; b < nbk; ++b) {
     const int kb = b * CB, nb = min(CB, m - kb);
-    // A. factor + invert the diagonal block (wave 0, lanes 0..31 own one
-    //    row each in registers; rows are broadcast through LDS)
+    // A. factor + invert the 32 x 32 diagonal block on wave 0 as 2 x 2
+    //    blocks of 16: L11 and X11 = L11^{-1} (chol_inv16), the panel
+    //    L21 = A21 X11^T and A22 - L21 L21^T on MFMA, L22 and X22, then
+    //    X21 = -X22 (L21 X11) on MFMA. Rows >= nb are identity padding.
     if (wv == 0) {
-      double Lrow[CB];
-      const int myr = lane & (CB - 1);
-#pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        double v = (myr == c) ? 1.0 : 0.0;
-        if (myr < nb && c < nb && c <= myr) v = S[(size_t)(kb + myr) * mp + kb + c];
-        Lrow[c] = (c <= myr) ? v : 0.0;
+      for (int q = lane; q < CB * CB; q += 64) {
+        Db[q / CB][q % CB] = 0.0;
+        Di[q / CB][q % CB] = 0.0;
       }
-      int fail = 0;
+      double a11[4], a21[4], a22[4];  // this lane's entries of A11, A21, A22, loaded together
 #pragma unroll
-      for (int bb = 0; bb < CB; ++bb) {
-        if (lane == bb) {
-          double sd = Lrow[bb];
+      for (int t = 0; t < 4; ++t) {
+        const int q = lane + 64 * t, i = q >> 4, j = q & 15;
+        a11[t] = ldm(S, kb + i, kb + j, mp, i < nb && j < nb);
+        const int kk = 4 * t + g;
+        a21[t] = ldm(S, kb + 16 + r, kb + kk, mp, 16 + r < nb && kk < nb);
+        const int i2 = acc_row<double>(lane, t);
+        a22[t] = ldm(S, kb + 16 + i2, kb + 16 + r, mp, 16 + i2 < nb && 16 + r < nb);
+      }
 #pragma unroll
-          for (int q = 0; q < bb; ++q) sd -= Lrow[q] * Lrow[q];
-          Lrow[bb] = (sd > 0.0 && isfinite(sd)) ? sqrt(sd) : 0.0;
+      for (int t = 0; t < 4; ++t) {
+        const int q = lane + 64 * t, i = q >> 4, j = q & 15;
+        Dt[i][j] = (i < nb && j < nb) ? a11[t] : (i == j ? 1.0 : 0.0);
+      }
+      wave_sync();
+      int fail = chol_inv16(&Dt[0][0], &Db[0][0], &Di[0][0], Dbuf, lane);
+      if (!fail) {
+        d4 acc = {0, 0, 0, 0};
 #pragma unroll
-          for (int q = 0; q <= bb; ++q) Db[bb][q] = Lrow[q];
-        }
+        for (int k0 = 0; k0 < 16; k0 += 4)  // L21 = A21 X11^T
+          acc = mfma16(a21[k0 / 4], Di[r][k0 + g], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Db[16 + acc_row<double>(lane, v)][r] = acc[v];
         wave_sync();
-        const double lbb = Db[bb][bb];
-        if (!(lbb > 0.0) && !fail) fail = kb + bb + 1;
-        if (!fail && lane > bb && lane < CB) {
-          double sd = Lrow[bb];
 #pragma unroll
-          for (int q = 0; q < bb; ++q) sd -= Lrow[q] * Db[bb][q];
-          Lrow[bb] = sd / lbb;
+        for (int v = 0; v < 4; ++v) {  // A22 - L21 L21^T
+          const int i = acc_row<double>(lane, v);
+          acc[v] = (16 + i < nb && 16 + r < nb) ? a22[v] : (i == r ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int k0 = 0; k0 < 16; k0 += 4) {
+          const double l = Db[16 + r][k0 + g];
+          acc = mfma16(-l, l, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Dt[acc_row<double>(lane, v)][r] = acc[v];
+        wave_sync();
+        fail = chol_inv16(&Dt[0][0], &Db[16][16], &Di[16][16], Dbuf, lane);
+        if (fail) {
+          fail += 16;
+        } else {
+          acc = d4{0, 0, 0, 0};
+#pragma unroll
+          for (int k0 = 0; k0 < 16; k0 += 4)  // T = L21 X11
+            acc = mfma16(Db[16 + r][k0 + g], Di[k0 + g][r], acc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Dt[acc_row<double>(lane, v)][r] = acc[v];
+          wave_sync();
+          acc = d4{0, 0, 0, 0};
+#pragma unroll
+          for (int k0 = 0; k0 < 16; k0 += 4)  // X21 = -X22 T
+            acc = mfma16(-Di[16 + r][16 + k0 + g], Dt[k0 + g][r], acc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Di[16 + acc_row<double>(lane, v)][r] = acc[v];
+          wave_sync();
         }
       }
       if (fail) {
-        if (lane == 0) s_fail = fail;
+        if (lane == 0) s_fail = kb + fail;
       } else {
-        wave_sync();
-        // L_bb^{-1}, row `lane` in registers, 16 columns at a time: sweep
-        // u = 0..31; row u is final at step u (divided by L_uu) and is
-        // subtracted from the later rows.
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          double xr[16];
-#pragma unroll
-          for (int c = 0; c < 16; ++c) xr[c] = (16 * h + c == myr) ? 1.0 : 0.0;
-#pragma unroll
-          for (int u = 0; u < CB; ++u) {
-            if (lane == u) {
-              const double inv = 1.0 / Lrow[u];
-#pragma unroll
-              for (int c = 0; c < 16; ++c) {
-                xr[c] *= inv;
-                Di[u][16 * h + c] = xr[c];
-              }
-            }
-            wave_sync();
-            if (lane > u && lane < CB) {
-              const double ltu = Lrow[u];
-#pragma unroll
-              for (int c = 0; c < 16; ++c) xr[c] -= ltu * Di[u][16 * h + c];
-            }
-          }
-          wave_sync();
-        }
-        wave_sync();
         for (int q = lane; q < nb * nb; q += 64) {
           const int rr = q / nb, cc = q % nb;
           if (cc <= rr) {
@@ -169,12 +278,14 @@ __global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double
       const int r0 = T0 + 16 * t;
       d4 acc[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
       const int row = r0 + r;
+      double a[CB / 4];
+#pragma unroll
+      for (int k0 = 0; k0 < CB; k0 += 4) a[k0 / 4] = ldm(S, row, kb + k0 + g, mp, row < m && k0 + g < nb);
 #pragma unroll
       for (int k0 = 0; k0 < CB; k0 += 4) {
         const int kk = k0 + g;
-        const double a = (row < m && kk < nb) ? S[(size_t)row * mp + kb + kk] : 0.0;
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) acc[ct] = mfma16(a, Di[ct * 16 + r][kk], acc[ct]);
+        for (int ct = 0; ct < 2; ++ct) acc[ct] = mfma16(a[k0 / 4], Di[ct * 16 + r][kk], acc[ct]);
       }
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct)
@@ -196,14 +307,14 @@ __global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int rr = R0 + acc_row<double>(lane, v), cc = C0 + r;
-        acc[v] = (rr < m && cc < m) ? S[(size_t)rr * mp + cc] : 0.0;
+        acc[v] = ldm(S, rr, cc, mp, rr < m && cc < m);
       }
       const int ra = R0 + r, cb = C0 + r;
 #pragma unroll
       for (int k0 = 0; k0 < CB; k0 += 4) {
         const int kk = k0 + g;
-        const double a = (ra < m && kk < nb) ? -S[(size_t)ra * mp + kb + kk] : 0.0;
-        const double bb = (cb < m && kk < nb) ? S[(size_t)cb * mp + kb + kk] : 0.0;
+        const double a = -ldm(S, ra, kb + kk, mp, ra < m && kk < nb);
+        const double bb = ldm(S, cb, kb + kk, mp, cb < m && kk < nb);
         acc = mfma16(a, bb, acc);
       }
 #pragma unroll
@@ -241,8 +352,8 @@ __global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double
 #pragma unroll 8
       for (int k0 = j * CB; k0 < i * CB; k0 += 4) {
         const int kk = k0 + g;
-        const double a = (ra < m && kk < m) ? S[(size_t)ra * mp + kk] : 0.0;
-        const double bb = (kk < m && cb < m) ? Linv[(size_t)kk * mp + cb] : 0.0;
+        const double a = ldm(S, ra, kk, mp, ra < m && kk < m);
+        const double bb = ldm(Linv, kk, cb, mp, kk < m && cb < m);
         acc = mfma16(a, bb, acc);
       }
 #pragma unroll
@@ -261,8 +372,8 @@ __global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double
 #pragma unroll
       for (int k0 = 0; k0 < CB; k0 += 4) {
         const int kk = i * CB + k0 + g;
-        const double a = (ra < m && kk < m) ? -Linv[(size_t)ra * mp + kk] : 0.0;
-        const double bb = (kk < m && cb < m) ? work[(size_t)kk * mp + cb] : 0.0;
+        const double a = -ldm(Linv, ra, kk, mp, ra < m && kk < m);
+        const double bb = ldm(work, kk, cb, mp, kk < m && cb < m);
         acc = mfma16(a, bb, acc);
       }
 #pragma unroll
