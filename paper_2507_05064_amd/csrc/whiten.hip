@@ -2,18 +2,26 @@
 // V_i . V_j = Sigma_mi^T Sigma_m^{-1} Sigma_mj), stored point-major (n x mp)
 // so that a neighbour gather reads one contiguous row per point.
 //
-// One workgroup = 64 points x 128 rows of V; each wave owns 16 points and
-// the 8 row blocks. K(z_j, x_p) is evaluated on the fly as the B operand of
-// FP64 MFMA 16x16x4 and reused across the 8 row blocks; L_m^{-1} (lower
-// triangular, zero padded to mp) is the A operand and its zero upper part is
-// skipped. Always FP64 arithmetic; the store casts to the storage type.
+// One workgroup = 64 points x 128 rows of V (blockIdx.y picks the rows);
+// each wave owns 16 points and the 8 row blocks of 16. The columns j of
+// K(Z, x) are taken 16 at a time: the workgroup stages the matching 128 x 16
+// slice of L_m^{-1} (lower triangular, zero padded to mp) in LDS with
+// coalesced loads, transposed so that the MFMA A operand reads 16
+// consecutive rows; each lane evaluates the four K(z_j, x_p) it feeds as the
+// B operand of FP64 MFMA 16x16x4. Blocks above the diagonal are skipped.
+// Always FP64 arithmetic; the store casts to the storage type.
 #include "common.h"
 #include "kernels.h"
 
+#define WJC 16
+#define WROWS 128
 template <typename T, bool DERIV>
 __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ X, const double* __restrict__ Z,
                                                 const double* __restrict__ Linv, int m, int mp, int64_t n,
                                                 CovParams p_in, T* __restrict__ V, Batch bt) {
+  // Ls[jj][row - l0] = L_m^{-1}[row][jc + jj]; the row pitch (WROWS + 16 doubles) puts
+  // the four k-rows an MFMA operand read touches in distinct LDS banks
+  __shared__ double Ls[WJC][WROWS + 16];
   CovParams p = p_in;
   if (bt.bp) {  // the 64-point tile lies in one problem: its Z, L_m^{-1} and parameters
     const int b = bt.blk2prob[((int64_t)blockIdx.x * 64) / kBatchBlock];
@@ -21,12 +29,12 @@ __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ X, co
     Z += (size_t)b * m * p.d;
     Linv += (size_t)b * mp * mp;
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
   const int64_t pt = (int64_t)blockIdx.x * 64 + 16 * w + c;
   const bool pvalid = pt < n;
-  const int l0 = blockIdx.y * 128;
-  const int nrb = min(8, (mp - l0) / 16);
+  const int l0 = blockIdx.y * WROWS;
+  const int nrb = min(WROWS / 16, (mp - l0) / 16);
   double xp[VIF_MAX_D];
 #pragma unroll
   for (int k = 0; k < VIF_MAX_D; ++k) xp[k] = (pvalid && k < p.d) ? X[pt * p.d + k] : 0.0;
@@ -34,20 +42,37 @@ __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ X, co
 #pragma unroll
   for (int r = 0; r < 8; ++r) acc[r] = d4{0.0, 0.0, 0.0, 0.0};
   const int jmax = min(m, l0 + nrb * 16);
-  for (int j0 = 0; j0 < jmax; j0 += 4) {
-    const int j = j0 + g;
-    double b = 0.0;
-    if (j < m && pvalid) {
-      const double t2 = scaled_sqdist<double>(p, Z + (size_t)j * p.d, xp);
-      b = DERIV ? p.sigma1_sq * cov_profile_dls<double>(p.kernel, t2, p.inv_ls[0])
-                : p.sigma1_sq * cov_profile<double>(p.kernel, t2);
-    }
+  // staging: thread -> (row, 2 consecutive columns); 8 threads cover a row's 16 columns
+  const int srow = tid >> 3, scol = 2 * (tid & 7);
+  for (int jc = 0; jc < jmax; jc += WJC) {
+    __syncthreads();
 #pragma unroll
-    for (int rb = 0; rb < 8; ++rb) {
-      if (rb < nrb && j0 <= l0 + rb * 16 + 15) {
-        const double a = Linv[(size_t)(l0 + rb * 16 + c) * mp + j];
-        acc[rb] = mfma16(a, b, acc[rb]);
+    for (int pass = 0; pass < WROWS / 32; ++pass) {
+      const int rr = srow + 32 * pass;
+      double2 v = {0.0, 0.0};
+      if (rr < nrb * 16) v = *reinterpret_cast<const double2*>(Linv + (size_t)(l0 + rr) * mp + jc + scol);
+      Ls[scol][rr] = v.x;
+      Ls[scol + 1][rr] = v.y;
+    }
+    double bv[WJC / 4];
+#pragma unroll
+    for (int q = 0; q < WJC / 4; ++q) {
+      const int j = jc + 4 * q + g;
+      double b = 0.0;
+      if (j < m && pvalid) {
+        const double t2 = scaled_sqdist<double>(p, Z + (size_t)j * p.d, xp);
+        b = DERIV ? p.sigma1_sq * cov_profile_dls<double>(p.kernel, t2, p.inv_ls[0])
+                  : p.sigma1_sq * cov_profile<double>(p.kernel, t2);
       }
+      bv[q] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < WJC / 4; ++q) {
+      const int j0 = jc + 4 * q;
+#pragma unroll
+      for (int rb = 0; rb < 8; ++rb)
+        if (rb < nrb && j0 <= l0 + rb * 16 + 15) acc[rb] = mfma16(Ls[4 * q + g][rb * 16 + c], bv[q], acc[rb]);
     }
   }
   if (!pvalid) return;
@@ -78,7 +103,7 @@ __global__ __launch_bounds__(256) void k_rownorm(const T* __restrict__ V, int64_
 template <typename T>
 void launch_whiten(hipStream_t st, const double* X, const double* Z, const double* Linv, int m, int mp, int64_t n,
                    const CovParams& p, bool deriv, T* V, Batch bt) {
-  dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(mp, 128));
+  dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(mp, WROWS));
   if (deriv)
     hipLaunchKernelGGL((k_whiten<T, true>), grid, dim3(256), 0, st, X, Z, Linv, m, mp, n, p, V, bt);
   else
