@@ -23,6 +23,11 @@ template <> struct PivEps<float> { static constexpr float value = 1.1920929e-07f
 template <typename T> struct Vec4;
 template <> struct Vec4<double> { typedef d4 type; };
 template <> struct Vec4<float> { typedef f4 type; };
+// per-lane vector width of the adjoint's row loop
+template <typename T> struct VecW;
+typedef double d1 __attribute__((ext_vector_type(1)));
+template <> struct VecW<double> { typedef d1 type; static constexpr int width = 1; };
+template <> struct VecW<float> { typedef f4 type; static constexpr int width = 4; };
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -113,19 +118,24 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
   }
   __syncthreads();
 
-  // 2. row `lane` of C (lower part), in registers
+  // 2. C = K + s2 I - Gram over the lower triangle of rows 0..k, its
+  //    (k+1)(k+2)/2 entries dealt to the lanes (packed row order), in place
+  //    in GL; then row `lane` of C into registers
   const bool active = lane <= k;
   const int myrow = lane & 31;
-#pragma unroll
-  for (int b = 0; b < 32; ++b) {
-    T v = 0;
-    if (active && b <= lane) {
-      const T kv = (b == lane) ? T(p.sigma1_sq + p.s2)
-                               : T(p.sigma1_sq) * cov_profile<T>(p.kernel, scaled_sqdist<T>(p, sh.xs[myrow], sh.xs[b]));
-      v = kv - sh.GL[myrow][b];
-    }
-    Lrow[b] = v;
+  const int ne = (k + 1) * (k + 2) / 2;
+  for (int e = lane; e < ne; e += 64) {
+    int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    while ((a + 1) * (a + 2) / 2 <= e) ++a;
+    while (a * (a + 1) / 2 > e) --a;
+    const int b = e - a * (a + 1) / 2;
+    const T kv = (a == b) ? T(p.sigma1_sq + p.s2)
+                          : T(p.sigma1_sq) * cov_profile<T>(p.kernel, scaled_sqdist<T>(p, sh.xs[a], sh.xs[b]));
+    sh.GL[a][b] = kv - sh.GL[a][b];
   }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < 32; ++b) Lrow[b] = (active && b <= lane) ? sh.GL[myrow][b] : T(0);
   __syncthreads();
   T (*Ls)[33] = sh.GL;
 
@@ -213,12 +223,13 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
   }
   if (lane < mv) Aout[i * mv + lane] = (lane < k) ? sh.As[lane] : T(0);
   if (lane == 0) Dout[i] = (double)D;
-  // 4. U_i
+  // 4. U_i, four consecutive entries per lane
+  typedef typename Vec4<T>::type T4;
   const T rsd = T(1) / sqrt(D);
-  for (int l = lane; l < mp; l += 64) {
-    T u = V[(size_t)i * mp + l];
-    for (int a = 0; a < k; ++a) u -= sh.As[a] * V[(size_t)sh.nbs[a] * mp + l];
-    U[(size_t)i * mp + l] = u * rsd;
+  for (int l = 4 * lane; l < mp; l += 256) {
+    T4 u = *reinterpret_cast<const T4*>(V + (size_t)i * mp + l);
+    for (int a = 0; a < k; ++a) u -= sh.As[a] * *reinterpret_cast<const T4*>(V + (size_t)sh.nbs[a] * mp + l);
+    *reinterpret_cast<T4*>(U + (size_t)i * mp + l) = u * rsd;
   }
 }
 
@@ -312,50 +323,69 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   }
   const T Aj = (lane < k) ? sh.As[myrow] : T(0);
   const T rho = (lane < k) ? ap - Dbar * Aj : T(0);
-  const T rbar = rho - Dbar * Aj;
   if (lane < 32) rho_s[lane] = rho;
   __syncthreads();
-  // gradient terms from the covariance entries of R_i, r_i, c_ii
-  T ts = 0, tr = 0, tn = 0;
-  if (lane < k) {
-    T sA = 0, sAr = 0;
-    for (int l = 0; l < k; ++l) {
-      if (l == lane) {
-        sA += sh.As[l];
-      } else {
-        const T t2 = scaled_sqdist<T>(p, sh.xs[lane], sh.xs[l]);
-        sA += sh.As[l] * cov_profile<T>(p.kernel, t2);
-        sAr += sh.As[l] * T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2, T(p.inv_ls[0]));
+  // gradient terms from the covariance entries of R_i, r_i, c_ii:
+  //   ts = sum_a [-rho_a sum_l A_l P_al + rbar_a P_ak],  P = K / sigma1^2 (P_aa = 1)
+  //   tr = sum_a [-rho_a sum_{l != a} A_l dP_al + rbar_a dP_ak] (dP = dK/drange)
+  // summed over the lower triangle of rows 0..k (P symmetric), entries dealt
+  // to the lanes in packed row order
+  T ts = 0, tr = 0;
+  T tn = (lane < k) ? -rho * Aj : T(0);
+  {
+    const int ne = (k + 1) * (k + 2) / 2;
+    for (int e = lane; e < ne; e += 64) {
+      int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+      while ((a + 1) * (a + 2) / 2 <= e) ++a;
+      while (a * (a + 1) / 2 > e) --a;
+      const int b = e - a * (a + 1) / 2;
+      if (a == b) {
+        if (a < k) ts -= rho_s[a] * sh.As[a];
+        continue;
       }
+      const T t2 = scaled_sqdist<T>(p, sh.xs[a], sh.xs[b]);
+      const T pv = cov_profile<T>(p.kernel, t2);
+      const T dv = T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2, T(p.inv_ls[0]));
+      // a == k: the r_i entry of row b; else the pair (a, b) of R_i, both orders
+      const T wgt = (a == k) ? rho_s[b] - Dbar * sh.As[b] : -(rho_s[a] * sh.As[b] + rho_s[b] * sh.As[a]);
+      ts += wgt * pv;
+      tr += wgt * dv;
     }
-    const T t2i = scaled_sqdist<T>(p, sh.xs[lane], sh.xs[k]);
-    ts = -rho * sA + rbar * cov_profile<T>(p.kernel, t2i);
-    tr = -rho * sAr + rbar * T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2i, T(p.inv_ls[0]));
-    tn = -rho * Aj;
   }
-  // vector part: G, S, H per column; dots with V_i, Vr_i and the gathered sums
+  // vector part: G, S, H per column; dots with V_i, Vr_i and the gathered
+  // sums (VW consecutive entries per lane: four in FP32, one in FP64, where
+  // wider accumulators would cost occupancy)
+  typedef typename VecW<T>::type TW;
+  constexpr int VW = VecW<T>::width;
   T tsv = 0, trv = 0;
-  for (int l = lane; l < mp; l += 64) {
+  for (int l = VW * lane; l < mp; l += 64 * VW) {
     const size_t o = (size_t)i * mp + l;
-    const T Vi = V[o], Ui = U[o], Vri = Vr[o];
-    const T u = Ubar[o] * rsd;
-    T al = 0, be = 0, alr = 0, ber = 0;
+    const TW Vi = *reinterpret_cast<const TW*>(V + o), Ui = *reinterpret_cast<const TW*>(U + o);
+    const TW Vri = *reinterpret_cast<const TW*>(Vr + o);
+    const TW u = *reinterpret_cast<const TW*>(Ubar + o) * rsd;
+    TW al = TW(0), be = TW(0), alr = TW(0), ber = TW(0);
     for (int j = 0; j < k; ++j) {
       const size_t oj = (size_t)sh.nbs[j] * mp + l;
-      const T v = V[oj], vr = Vr[oj];
-      al += sh.As[j] * v;
-      be += rho_s[j] * v;
-      alr += sh.As[j] * vr;
-      ber += rho_s[j] * vr;
+      const TW v = *reinterpret_cast<const TW*>(V + oj), vr = *reinterpret_cast<const TW*>(Vr + oj);
+      const T aj = sh.As[j], rj = rho_s[j];
+      al += aj * v;
+      be += rj * v;
+      alr += aj * vr;
+      ber += rj * vr;
     }
-    const T Gl = be - u + Dbar * Vi;
-    const T Sl = u - T(2) * Dbar * Vi - be + Dbar * al;
-    const T Hl = -sd * Ui;
-    tsv += Sl * Vi + Gl * al + Hl * be;
-    trv += Sl * Vri + Gl * alr + Hl * ber;
-    Q1[o] = Sl + Gl;
-    Gs[o] = sd * Gl;
-    Bs[o] = sd * be;
+    const TW Gl = be - u + Dbar * Vi;
+    const TW Sl = u - T(2) * Dbar * Vi - be + Dbar * al;
+    const TW Hl = -sd * Ui;
+    const TW tv = Sl * Vi + Gl * al + Hl * be;
+    const TW rv = Sl * Vri + Gl * alr + Hl * ber;
+#pragma unroll
+    for (int q = 0; q < VW; ++q) {
+      tsv += tv[q];
+      trv += rv[q];
+    }
+    *reinterpret_cast<TW*>(Q1 + o) = Sl + Gl;
+    *reinterpret_cast<TW*>(Gs + o) = sd * Gl;
+    *reinterpret_cast<TW*>(Bs + o) = sd * be;
   }
   ts = wave_sum(ts);
   tr = wave_sum(tr);
@@ -439,28 +469,36 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
     }
   }
   __syncthreads();
-  // dC row `lane` (lanes 0..k), full row
-  T dCrow[32];
+  // dC over the lower triangle of rows 0..k, entries dealt to the lanes
+  // (packed row order), written in place over the cross Gram (entry (a, b)
+  // reads only Xc[a][b] and Xc[b][a]); then row `lane` (lanes 0..k), full
   const bool active = lane <= k;
-#pragma unroll
-  for (int b = 0; b < 32; ++b) {
-    T v = 0;
-    if (active && b <= k) {
+  {
+    const int ne = (k + 1) * (k + 2) / 2;
+    for (int e = lane; e < ne; e += 64) {
+      int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+      while ((a + 1) * (a + 2) / 2 <= e) ++a;
+      while (a * (a + 1) / 2 > e) --a;
+      const int b = e - a * (a + 1) / 2;
       T dk;
       if (which == 2) {
-        dk = (b == lane) ? T(1) : T(0);
-      } else if (b == lane) {
+        dk = (a == b) ? T(1) : T(0);
+      } else if (a == b) {
         dk = (which == 0) ? T(1) : T(0);
       } else {
-        const T t2 = scaled_sqdist<T>(p, sh.xs[myrow], sh.xs[b]);
+        const T t2 = scaled_sqdist<T>(p, sh.xs[a], sh.xs[b]);
         dk = (which == 0) ? cov_profile<T>(p.kernel, t2)
                           : T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2, T(p.inv_ls[0]));
       }
-      if (dV != nullptr) dk -= Xc[myrow][b] + Xc[b][myrow];
-      v = dk;
+      if (dV != nullptr) dk -= Xc[a][b] + Xc[b][a];
+      Xc[a][b] = dk;
     }
-    dCrow[b] = v;
   }
+  __syncthreads();
+  T dCrow[32];
+#pragma unroll
+  for (int b = 0; b < 32; ++b)
+    dCrow[b] = (active && b <= k) ? ((b <= lane) ? Xc[myrow][b] : Xc[b][myrow]) : T(0);
   // rhs_a = dr_a - sum_b dR_ab A_b  (lanes a < k);  dD pieces
   T rhs = 0, drA = 0, AdRA = 0;
   if (lane < k) {
@@ -508,15 +546,16 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
   // dU_i
   const T rsd = T(1) / sqrt(D);
   const T hdd = T(0.5) * dDi / D;
-  for (int l = lane; l < mp; l += 64) {
+  for (int l = 4 * lane; l < mp; l += 256) {  // four consecutive entries per lane
     const size_t o = (size_t)i * mp + l;
-    T u = dV ? dV[o] : T(0);
+    T4 u = {0, 0, 0, 0};
+    if (dV) u = *reinterpret_cast<const T4*>(dV + o);
     for (int a = 0; a < k; ++a) {
       const size_t oa = (size_t)sh.nbs[a] * mp + l;
-      u -= dAs[a] * V[oa];
-      if (dV) u -= sh.As[a] * dV[oa];
+      u -= dAs[a] * *reinterpret_cast<const T4*>(V + oa);
+      if (dV) u -= sh.As[a] * *reinterpret_cast<const T4*>(dV + oa);
     }
-    dU[o] = u * rsd - U[o] * hdd;
+    *reinterpret_cast<T4*>(dU + o) = u * rsd - *reinterpret_cast<const T4*>(U + o) * hdd;
   }
 }
 
