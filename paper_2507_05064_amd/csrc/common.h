@@ -83,6 +83,18 @@ template <typename T> __device__ __forceinline__ int acc_row(int lane, int v);
 template <> __device__ __forceinline__ int acc_row<double>(int lane, int v) { return (lane >> 4) + 4 * v; }
 template <> __device__ __forceinline__ int acc_row<float>(int lane, int v) { return 4 * (lane >> 4) + v; }
 
+// sum_{c < count} p[c * stride] with eight loads in flight (fixed order)
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int count, size_t stride) {
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int c = 0;
+  for (; c + 8 <= count; c += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s[q] += p[(size_t)(c + q) * stride];
+  }
+  for (; c < count; ++c) s[0] += p[(size_t)c * stride];
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

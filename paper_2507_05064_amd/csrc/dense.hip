@@ -398,10 +398,7 @@ __global__ void k_reduce_gram(const double* partial, int nchunk, int mp, double 
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)mp * mp) return;
   const int l = (int)(q / mp), c = (int)(q % mp);
-  double s = 0.0;
-  if (c <= l) {
-    for (int k = 0; k < nchunk; ++k) s += partial[(size_t)k * mp * mp + q];
-  }
+  const double s = (c <= l) ? strided_sum(partial + q, nchunk, (size_t)mp * mp) : 0.0;
   Mp[q] = ((l == c) ? 1.0 : 0.0) + scale * s;
 }
 

@@ -13,6 +13,7 @@
 #include "common.h"
 #include "kernels.h"
 
+
 // C = op(A) op(B) for mp x mp FP64 matrices (op = transpose if flag set).
 __global__ __launch_bounds__(256) void k_gemm_sq(const double* __restrict__ A, const double* __restrict__ B,
                                                  double* __restrict__ C, int mp, int ta, int tb) {
@@ -38,24 +39,30 @@ __global__ __launch_bounds__(256) void k_gemm_sq(const double* __restrict__ A, c
   if (row < mp && col < mp) C[(size_t)row * mp + col] = acc;
 }
 
-// w = Minv b (single workgroup), Minv in FP64; also a T copy of Minv.
+// w = Minv b, Minv in FP64, and a T copy of Minv: one wave per row (four
+// rows per workgroup); blockIdx.y = problem of a batch.
 template <typename T>
 __global__ __launch_bounds__(256) void k_prep_w(const double* __restrict__ Minv, const double* __restrict__ b, int mp,
                                                 double* __restrict__ w, T* __restrict__ MinvT, int bstride) {
-  {  // blockIdx.x: problem of a batch
-    const size_t z = blockIdx.x;
+  {
+    const size_t z = blockIdx.y;
     Minv += z * mp * mp;
     MinvT += z * mp * mp;
     b += z * bstride;
     w += z * mp;
   }
-  for (int l = threadIdx.x; l < mp; l += 256) {
-    const double* row = Minv + (size_t)l * mp;
-    double s = 0.0;
-    for (int c = 0; c < mp; ++c) s += row[c] * b[c];
-    w[l] = s;
+  const int lane = threadIdx.x & 63;
+  const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (l >= mp) return;
+  const double* row = Minv + (size_t)l * mp;
+  double s = 0.0;
+  for (int c = lane; c < mp; c += 64) {
+    const double v = row[c];
+    s += v * b[c];
+    MinvT[(size_t)l * mp + c] = (T)v;
   }
-  for (int q = threadIdx.x; q < mp * mp; q += 256) MinvT[q] = (T)Minv[q];
+  s = wave_sum(s);
+  if (lane == 0) w[l] = s;
 }
 
 // e_i = yt_i - U_i . w  (one wave per point)
@@ -91,12 +98,14 @@ __global__ __launch_bounds__(256) void k_ubar(const T* __restrict__ U, const T* 
   const int c0 = blockIdx.y * 64;
   const int ntile = min(4, (mp - c0) / 16);
   const int64_t pa = p0 + r;
+  const bool pok = pa < n;
   const T* urow = U + (size_t)min(pa, n - 1) * mp;
   A4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = A4{0, 0, 0, 0};
   for (int k0 = 0; k0 < mp; k0 += 4) {
-    const T a = (pa < n) ? urow[k0 + g] : T(0);
+    const T av = urow[k0 + g];  // unconditional (clamped row), so loads are not serialised
+    const T a = pok ? av : T(0);
     const T* mrow = Minv + (size_t)(k0 + g) * mp + c0 + r;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -156,14 +165,16 @@ __global__ __launch_bounds__(256) void k_cross3_partial(const T* __restrict__ V,
     T a1[2], b1[2], a2[2], b2[2], a3[2], b3[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
+      // unconditional in-range loads, so that they issue together
       const bool ra = pv && rok[t], cb = pv && cok[t];
-      const size_t oa = off + L0 + 16 * t + r, ob = off + C0 + 16 * t + r;
-      a1[t] = ra ? V[oa] : T(0);
-      b1[t] = cb ? Q1[ob] : T(0);
-      a2[t] = ra ? -U[oa] : T(0);
-      b2[t] = cb ? Gs[ob] : T(0);
-      a3[t] = ra ? -Bs[oa] : T(0);
-      b3[t] = cb ? U[ob] : T(0);
+      const size_t oa = off + min(L0 + 16 * t + r, mp - 1), ob = off + min(C0 + 16 * t + r, mp - 1);
+      const T v1 = V[oa], w1 = Q1[ob], v2 = U[oa], w2 = Gs[ob], v3 = Bs[oa], w3 = U[ob];
+      a1[t] = ra ? v1 : T(0);
+      b1[t] = cb ? w1 : T(0);
+      a2[t] = ra ? -v2 : T(0);
+      b2[t] = cb ? w2 : T(0);
+      a3[t] = ra ? -v3 : T(0);
+      b3[t] = cb ? w3 : T(0);
     }
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -198,9 +209,7 @@ __global__ void k_reduce_sym(const double* __restrict__ partial, int nchunk, int
   if (q >= (int64_t)mp * mp) return;
   const int l = (int)(q / mp), c = (int)(q % mp);
   const size_t src = (c <= l) ? (size_t)q : (size_t)c * mp + l;
-  double s = 0.0;
-  for (int k = 0; k < nchunk; ++k) s += partial[(size_t)k * mp * mp + src];
-  out[q] = s;
+  out[q] = strided_sum(partial + src, nchunk, (size_t)mp * mp);
 }
 
 // -1/2 sum_ab Tm_ab dSigma_m[a][b]/dtheta for (sigma1^2, range): one block per row.
@@ -345,7 +354,8 @@ void launch_gemm_sq(hipStream_t st, const double* A, const double* B, double* C,
 template <typename T>
 void launch_prep_w(hipStream_t st, const double* Minv, const double* b, int mp, double* w, T* MinvT, int nprob,
                    int bstride) {
-  hipLaunchKernelGGL((k_prep_w<T>), dim3(nprob), dim3(256), 0, st, Minv, b, mp, w, MinvT, bstride);
+  hipLaunchKernelGGL((k_prep_w<T>), dim3((unsigned)ceil_div(mp, 4), nprob), dim3(256), 0, st, Minv, b, mp, w, MinvT,
+                     bstride);
 }
 template <typename T>
 void launch_resid(hipStream_t st, const T* U, const double* w, const double* yt, int64_t n, int mp, double* e,

@@ -5,6 +5,10 @@
 #include "common.h"
 #include "kernels.h"
 
+template <typename T> struct Vec4T;
+template <> struct Vec4T<double> { typedef d4 type; };
+template <> struct Vec4T<float> { typedef f4 type; };
+
 // Partial U^T U of one point chunk for one 64 x 64 block of the lower
 // triangle. Each wave: a 32 x 32 sub-block (2 x 2 MFMA tiles), K = points.
 template <typename T>
@@ -38,9 +42,10 @@ __global__ __launch_bounds__(256) void k_gram_partial(const T* __restrict__ U, i
     const T* row = U + (size_t)(pv ? pp : pbeg) * mp;
     T a[2], b[2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      a[t] = (pv && rok[t]) ? row[L0 + 16 * t + r] : T(0);
-      b[t] = (pv && cok[t]) ? row[C0 + 16 * t + r] : T(0);
+    for (int t = 0; t < 2; ++t) {  // unconditional in-range loads, so they issue together
+      const T av = row[min(L0 + 16 * t + r, mp - 1)], bv = row[min(C0 + 16 * t + r, mp - 1)];
+      a[t] = (pv && rok[t]) ? av : T(0);
+      b[t] = (pv && cok[t]) ? bv : T(0);
     }
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -58,20 +63,42 @@ __global__ __launch_bounds__(256) void k_gram_partial(const T* __restrict__ U, i
           out[(size_t)(L0 + 16 * x + acc_row<T>(lane, v)) * mp + C0 + 16 * y + r] = (double)acc[x][y][v];
 }
 
-// Per chunk: U^T yt (mp values), sum log D, sum yt^2 -> partial[chunk][mp + 2]
+// Per chunk: U^T yt (mp values), sum log D, sum yt^2 -> partial[chunk][mp + 2].
+// Thread = (four consecutive columns, one of four point groups); the groups
+// stride through the chunk's points and meet in LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void k_uty_partial(const T* __restrict__ U, const double* __restrict__ yt,
                                                      const double* __restrict__ D, int64_t n, int mp, int chunk,
                                                      double* __restrict__ partial) {
+  typedef typename Vec4T<T>::type T4;
   __shared__ double red[2][4];
-  const int tid = threadIdx.x;
+  __shared__ double colred[4][257];
+  const int tid = threadIdx.x, lg = tid & 63, pg = tid >> 6;
   const int64_t pbeg = (int64_t)blockIdx.x * chunk;
   const int64_t pend = min(n, pbeg + chunk);
   double* out = partial + (size_t)blockIdx.x * (mp + 2);
-  for (int l = tid; l < mp; l += 256) {
-    double s = 0.0;
-    for (int64_t p = pbeg; p < pend; ++p) s += (double)U[(size_t)p * mp + l] * yt[p];
-    out[l] = s;
+  for (int cb = 0; cb < mp; cb += 256) {
+    const int l4 = cb + 4 * lg;
+    const bool lok = l4 < mp;
+    const int lc = lok ? l4 : mp - 4;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 4
+    for (int64_t p = pbeg + pg; p < pend; p += 4) {
+      const T4 u = *reinterpret_cast<const T4*>(U + (size_t)p * mp + lc);
+      const double y = yt[p];
+      s0 += (double)u[0] * y;
+      s1 += (double)u[1] * y;
+      s2 += (double)u[2] * y;
+      s3 += (double)u[3] * y;
+    }
+    __syncthreads();
+    colred[pg][4 * lg] = s0;
+    colred[pg][4 * lg + 1] = s1;
+    colred[pg][4 * lg + 2] = s2;
+    colred[pg][4 * lg + 3] = s3;
+    __syncthreads();
+    const int l = cb + tid;
+    if (l < mp) out[l] = (colred[0][tid] + colred[1][tid]) + (colred[2][tid] + colred[3][tid]);
   }
   double sl = 0.0, sy = 0.0;
   for (int64_t p = pbeg + tid; p < pend; p += 256) {
@@ -98,9 +125,7 @@ __global__ void k_vec_reduce(const double* __restrict__ partial, int nchunk, int
   }
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= len) return;
-  double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += partial[(size_t)c * len + j];
-  out[j] = s;
+  out[j] = strided_sum(partial + j, nchunk, (size_t)len);
 }
 
 template <typename T>
