@@ -29,6 +29,17 @@ typedef double d1 __attribute__((ext_vector_type(1)));
 template <> struct VecW<double> { typedef d1 type; static constexpr int width = 1; };
 template <> struct VecW<float> { typedef f4 type; static constexpr int width = 4; };
 
+// value of v in lane src (src uniform across the wave)
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, src);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -139,32 +150,27 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
   __syncthreads();
   T (*Ls)[33] = sh.GL;
 
-  // 3. Cholesky, row-oriented: step b finalises row b (its diagonal), then
-  //    every later row computes its entry in column b from row b.
+  // 3. Cholesky by columns: at step b every row i >= b forms
+  //    s_i = C_ib - sum_{q<b} L_iq L_bq (row b of L read from LDS, the same
+  //    address for all lanes), the pivot s_b is read from lane b, and
+  //    L_bb = sqrt(s_b), L_ib = s_i / L_bb; each row then publishes L_ib.
+  // (A failed pivot clears `ok` and skips the remaining steps; no early
+  // exit, so the unrolled loop keeps one path and Lrow stays in place.)
   bool ok = true;
 #pragma unroll
   for (int b = 0; b < 32; ++b) {
-    if (b <= k) {
-      if (lane == b) {
-        const T cbb = Lrow[b];
-        T s = cbb;
+    if (b <= k && ok) {
+      T s = Lrow[b];
 #pragma unroll
-        for (int q = 0; q < b; ++q) s -= Lrow[q] * Lrow[q];
-        // a pivot below 32 ulps of the diagonal it came from is numerically zero
-        const bool piv_ok = (s > cbb * T(32) * PivEps<T>::value) && isfinite(s);
-        Lrow[b] = piv_ok ? sqrt(s) : T(0);
-#pragma unroll
-        for (int q = 0; q <= b; ++q) Ls[b][q] = Lrow[q];
-      }
+      for (int q = 0; q < b; ++q) s -= Lrow[q] * Ls[b][q];
+      // a pivot below 32 ulps of the diagonal it came from is numerically zero
+      const bool piv_ok = (s > Lrow[b] * T(32) * PivEps<T>::value) && isfinite(s);
+      ok = __ballot(lane == b && piv_ok) != 0;
+      const T lbb = sqrt(lane_bcast(s, b));
+      const T il = T(1) / lbb;
+      if (ok && active && lane >= b) Lrow[b] = (lane == b) ? lbb : s * il;
+      if (active) Ls[myrow][b] = Lrow[b];
       wave_sync();
-      const T lbb = Ls[b][b];
-      if (!(lbb > T(0))) { ok = false; break; }
-      if (lane > b && active) {
-        T s = Lrow[b];
-#pragma unroll
-        for (int q = 0; q < b; ++q) s -= Lrow[q] * Ls[b][q];
-        Lrow[b] = s / lbb;
-      }
     }
   }
   if (!ok) {
@@ -178,10 +184,10 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
   const T lkk = Ls[k][k];
   // A = L_R^{-T} l, l = row k of L without its diagonal
   T accv = (lane < k) ? Ls[k][myrow] : T(0);
-  const T ldiag = Ls[myrow][myrow];
+  const T rdiag = T(1) / Ls[myrow][myrow];  // only lanes < k use theirs
   T Ab = 0;
   for (int a = k - 1; a >= 0; --a) {
-    const T Aa = __shfl(accv / ldiag, a, 64);
+    const T Aa = lane_bcast(accv * rdiag, a);
     if (lane == a) Ab = Aa;
     if (lane < a) accv -= Ls[a][myrow] * Aa;
   }
@@ -302,12 +308,13 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   const T tbar = ei * rsd;
   const T Abar = (lane < k) ? -ubv - tbar * T(y[sh.nbs[myrow]]) : T(0);
   // z = L_R^{-1} Abar (lane a holds row a of L in Lrow)
+  const T rdiag = T(1) / Ls[myrow][myrow];  // only lanes < k use theirs
   T accz = Abar;
   T z = 0;
 #pragma unroll
   for (int q = 0; q < 32; ++q) {
     if (q < k) {
-      const T zq = __shfl(accz / Lrow[q], q, 64);
+      const T zq = lane_bcast(accz * rdiag, q);
       if (lane == q) z = zq;
       if (lane > q && lane < k) accz -= Lrow[q] * zq;
     }
@@ -315,9 +322,8 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   // a' = L_R^{-T} z
   T acc = (lane < k) ? z : T(0);
   T ap = 0;
-  const T ldiag = Ls[myrow][myrow];
   for (int a = k - 1; a >= 0; --a) {
-    const T xa = __shfl(acc / ldiag, a, 64);
+    const T xa = lane_bcast(acc * rdiag, a);
     if (lane == a) ap = xa;
     if (lane < a) acc -= Ls[a][myrow] * xa;
   }
@@ -523,19 +529,19 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
   AdRA = wave_sum(AdRA);
   const T dDi = dc - T(2) * drA + AdRA;
   // dA = L_R^{-T} L_R^{-1} rhs  (lane a holds row a of L in Lrow)
+  const T rdiag = T(1) / Ls[myrow][myrow];  // only lanes < k use theirs
   T accz = rhs, z = 0;
 #pragma unroll
   for (int q = 0; q < 32; ++q) {
     if (q < k) {
-      const T zq = __shfl(accz / Lrow[q], q, 64);
+      const T zq = lane_bcast(accz * rdiag, q);
       if (lane == q) z = zq;
       if (lane > q && lane < k) accz -= Lrow[q] * zq;
     }
   }
   T acc = (lane < k) ? z : T(0), x = 0;
-  const T ldiag = Ls[myrow][myrow];
   for (int a = k - 1; a >= 0; --a) {
-    const T xa = __shfl(acc / ldiag, a, 64);
+    const T xa = lane_bcast(acc * rdiag, a);
     if (lane == a) x = xa;
     if (lane < a) acc -= Ls[a][myrow] * xa;
   }
