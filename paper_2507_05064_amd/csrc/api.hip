@@ -33,6 +33,14 @@ struct vif_ctx {
   bool timing = false;
   StageTimer timers[ST_COUNT];
   hipStream_t st = nullptr;
+  // second stream (Gaussian likelihood with inducing points): once a
+  // gradient has been asked for, each build starts Vr = L_m^{-1} dK(Z,X)/drange
+  // there as soon as L_m^{-1} is final, overlapping the rest of the build
+  // (the per-point factor, the one-workgroup Cholesky of M'); the gradient
+  // waits on ev_vr
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_lm = nullptr, ev_vr = nullptr;
+  bool vr_pending = false, grad_seen = false;
   int device = 0;
   int mp = 0;
   std::string err;
@@ -171,13 +179,20 @@ static vif_status set_params(vif_ctx* c, const double* theta) {
 // Entry checks of a neighbour list: -1 or 0 <= j < i, -1 only in a trailing
 // run, no duplicates. Flags the smallest offending point; status[4] is set
 // when the list differs from the context's copy `own`.
-__global__ void k_check_nbr(const int32_t* nbr, const int32_t* own, int64_t n, int mv, int* status) {
+// Compares each point's neighbour row with the context's copy (status[4] on
+// any difference) and validates the rows that differ, or all rows when
+// `all` is set (no validated copy yet): entries in [0, i) and distinct, -1
+// padding only at the end (status[3] and the first bad point in status[2]).
+__global__ void k_check_nbr(const int32_t* nbr, const int32_t* own, int64_t n, int mv, int all, int* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  bool bad = false, seen_pad = false, diff = false;
+  bool diff = false;
+  for (int a = 0; a < mv; ++a) diff |= nbr[i * mv + a] != own[i * mv + a];
+  if (diff) status[4] = 1;
+  if (!diff && !all) return;
+  bool bad = false, seen_pad = false;
   for (int a = 0; a < mv; ++a) {
     const int j = nbr[i * mv + a];
-    if (j != own[i * mv + a]) diff = true;
     if (j < 0) {
       if (j != -1) bad = true;
       seen_pad = true;
@@ -191,7 +206,6 @@ __global__ void k_check_nbr(const int32_t* nbr, const int32_t* own, int64_t n, i
     status[3] = 1;
     atomicMin(&status[2], (int)i);
   }
-  if (diff) status[4] = 1;
 }
 
 static vif_status reset_status(vif_ctx* c) {
@@ -312,6 +326,11 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
     e = hipEventCreate(&c->timers[t].b);
     if (e == hipSuccess) e = hipEventCreate(&c->timers[t].e);
   }
+  if (e == hipSuccess && g.likelihood == VIF_LIK_GAUSSIAN && g.m > 0 && g.kernel != VIF_GAUSSIAN_ARD) {
+    e = hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_lm, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_vr, hipEventDisableTiming);
+  }
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->hscal, sizeof(double) * 16, 0);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->hstatus, sizeof(int) * 8, 0);
   if (e != hipSuccess) {
@@ -325,6 +344,7 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
 void vif_destroy(vif_ctx* c) {
   if (!c) return;
   if (c->st) hipStreamSynchronize(c->st); else hipDeviceSynchronize();
+  if (c->st2) hipStreamSynchronize(c->st2);
   void* bufs[] = {c->Sm, c->Linv, c->Mp, c->LMinv, c->Mwork, c->Vd, c->Vf, c->A, c->U, c->D, c->yt, c->vnorm,
                   c->partial, c->vecpart, c->vec, c->scal, c->status, c->nbr, c->Xc, c->Zc, c->Minv, c->wvec,
                   c->e, c->Smat, c->Tm, c->tmpm, c->MinvT, c->Ubar, c->Q1, c->Gs, c->Bs, c->Vr, c->tpart,
@@ -341,6 +361,9 @@ void vif_destroy(vif_ctx* c) {
     if (c->timers[t].b) hipEventDestroy(c->timers[t].b);
     if (c->timers[t].e) hipEventDestroy(c->timers[t].e);
   }
+  if (c->ev_lm) hipEventDestroy(c->ev_lm);
+  if (c->ev_vr) hipEventDestroy(c->ev_vr);
+  if (c->st2) hipStreamDestroy(c->st2);
   if (c->hscal) hipHostFree(c->hscal);
   if (c->hlsc) hipHostFree(c->hlsc);
   if (c->hstatus) hipHostFree(c->hstatus);
@@ -456,6 +479,10 @@ static void morton_order(const std::vector<double>& X, int64_t n, int d, std::ve
 vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const int32_t* nbr, const double* theta) {
   if (!c) return VIF_E_ARG;
   c->built = false;
+  if (c->vr_pending) {  // the previous build's Vr still reads X, Z and L_m^{-1}
+    HIPCHK(c, hipStreamWaitEvent(c->st, c->ev_vr, 0));
+    c->vr_pending = false;
+  }
   if (!X) return fail(c, VIF_E_ARG, "X is NULL");
   if (c->cfg.m_v > 0 && !nbr) return fail(c, VIF_E_ARG, "nbr is NULL with m_v > 0");
   vif_status s = set_params(c, theta);
@@ -464,7 +491,7 @@ vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const 
   if ((s = reset_status(c))) return s;
   if (g.m_v > 0)
     hipLaunchKernelGGL(k_check_nbr, dim3((unsigned)ceil_div(g.n, 256)), dim3(256), 0, c->st, nbr, c->nbr, g.n,
-                       g.m_v, c->status);
+                       g.m_v, c->nbr_valid ? 0 : 1, c->status);
   const bool f32 = fp32_form(c);
   HIPCHK(c, hipMemcpyAsync(c->Xc, X, sizeof(double) * g.n * g.d, hipMemcpyDeviceToDevice, c->st));
   if (g.m > 0) {
@@ -474,6 +501,17 @@ vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const 
   X = c->Xc;
   Z = c->Zc;
   if ((s = build_inducing(c, X, Z, !f32))) return s;
+  if (c->grad_seen && c->st2) {  // Vr for the gradient, on the second stream
+    HIPCHK(c, hipEventRecord(c->ev_lm, c->st));
+    HIPCHK(c, hipStreamWaitEvent(c->st2, c->ev_lm, 0));
+    if (f32)
+      launch_whiten<float>(c->st2, X, Z, c->Linv, g.m, c->mp, g.n, c->cp, true, (float*)c->Vr);
+    else
+      launch_whiten<double>(c->st2, X, Z, c->Linv, g.m, c->mp, g.n, c->cp, true, (double*)c->Vr);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(c->ev_vr, c->st2));
+    c->vr_pending = true;
+  }
   stage_begin(c, ST_FACTOR);
   if (f32)
     launch_factor<float>(c->st, X, c->Vf, nbr, g.n, c->mp, g.m_v, c->cp, (float*)c->A, c->D, (float*)c->U, c->status,
@@ -597,7 +635,12 @@ static vif_status nll_grad_impl(vif_ctx* c, const double* y) {
     launch_ubar<T>(c->st, U, (const T*)c->MinvT, c->e, c->wvec, g.n, mp, (T*)c->Ubar);
     stage_end(c, ST_UBAR);
     stage_begin(c, ST_WDERIV);
-    launch_whiten<T>(c->st, c->Xc, c->Zc, c->Linv, g.m, mp, g.n, c->cp, true, (T*)c->Vr);
+    if (c->vr_pending) {  // started by the build on the second stream
+      HIPCHK(c, hipStreamWaitEvent(c->st, c->ev_vr, 0));
+      c->vr_pending = false;
+    } else {
+      launch_whiten<T>(c->st, c->Xc, c->Zc, c->Linv, g.m, mp, g.n, c->cp, true, (T*)c->Vr);
+    }
     stage_end(c, ST_WDERIV);
   }
   stage_begin(c, ST_FBWD);
@@ -639,6 +682,7 @@ vif_status vif_nll_grad(vif_ctx* c, const double* y, double* nll_out, double* gr
   if (g.m_v > VIF_MAX_MV - 1) return fail(c, VIF_E_ARG, "vif_nll_grad supports m_v <= %d", VIF_MAX_MV - 1);
   vif_status s = reset_status(c);
   if (s) return s;
+  c->grad_seen = true;
   s = fp32_form(c) ? nll_grad_impl<float>(c, y) : nll_grad_impl<double>(c, y);
   if (s) return s;
   HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * 16, hipMemcpyDeviceToHost, c->st));

@@ -177,6 +177,33 @@ def test_gradient_matches_oracle(n, m, mv, prec):
     assert nll_2 == nll_g and np.array_equal(g_2, g_g)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_repeated_gradient_evaluations_match_fresh_contexts(prec):
+    """After its first gradient a context starts the derivative whitening of
+    each later build on a second stream; a sequence of build + gradient (and
+    a build followed by NLL only) on one context gives the same values as a
+    fresh context per theta, bit for bit."""
+    w = vi.scaled(vi.config1(), 1200, m=40, m_v=12)
+    X, Z, model = problem(w)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, w.m_v)
+    y = _y_exact(model, X, 5)
+    thetas = [w.theta * np.array(f) for f in ([1.0, 1.0, 1.0], [1.3, 0.8, 1.5], [0.7, 1.2, 0.9], [1.1, 0.9, 1.2])]
+    print(f"[gpu] repeated gradients n={w.n} m={w.m} m_v={w.m_v} {prec}", flush=True)
+    shared = _ctx(w, precision=prec)
+    dX, dZ, dN, dy = to_dev(X), to_dev(Z), nbr_to_dev(nbr), to_dev(y)
+    for k, th in enumerate(thetas):
+        shared.build_factor(dX, dZ, dN, th)
+        if k == 2:  # NLL only: the started whitening is waited for by the next build
+            shared.nll(dy)
+            continue
+        got = shared.nll_grad(dy, 3)
+        fresh = _ctx(w, precision=prec)
+        fresh.build_factor(dX, dZ, dN, th)
+        ref = fresh.nll_grad(dy, 3)
+        assert got[0] == ref[0] and np.array_equal(got[1], ref[1]), (k, got, ref)
+
+
 def test_gradient_rejects_31_neighbours():
     """The adjoint joins one extra row to the 32-row per-point Gram: m_v <= 30."""
     from paper_2507_05064_amd.vif import VifError
