@@ -29,6 +29,20 @@ typedef double d1 __attribute__((ext_vector_type(1)));
 template <> struct VecW<double> { typedef d1 type; static constexpr int width = 1; };
 template <> struct VecW<float> { typedef f4 type; static constexpr int width = 4; };
 
+// sqrt(x) and 1/sqrt(x), 1/x: correctly rounded in FP64; in FP32 the
+// hardware reciprocal square root and reciprocal (1 ulp), far inside the
+// FP32 form's error budget and a fraction of the IEEE sequences' cost
+__device__ __forceinline__ void sqrt_and_rsqrt(double x, double& sq, double& rs) {
+  sq = sqrt(x);
+  rs = 1.0 / sq;
+}
+__device__ __forceinline__ void sqrt_and_rsqrt(float x, float& sq, float& rs) {
+  rs = __builtin_amdgcn_rsqf(x);
+  sq = x * rs;
+}
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // value of v in lane src (src uniform across the wave)
 __device__ __forceinline__ float lane_bcast(float v, int src) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
@@ -166,8 +180,8 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
       // a pivot below 32 ulps of the diagonal it came from is numerically zero
       const bool piv_ok = (s > Lrow[b] * T(32) * PivEps<T>::value) && isfinite(s);
       ok = __ballot(lane == b && piv_ok) != 0;
-      const T lbb = sqrt(lane_bcast(s, b));
-      const T il = T(1) / lbb;
+      T lbb, il;
+      sqrt_and_rsqrt(lane_bcast(s, b), lbb, il);
       if (ok && active && lane >= b) Lrow[b] = (lane == b) ? lbb : s * il;
       if (active) Ls[myrow][b] = Lrow[b];
       wave_sync();
@@ -184,7 +198,7 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
   const T lkk = Ls[k][k];
   // A = L_R^{-T} l, l = row k of L without its diagonal
   T accv = (lane < k) ? Ls[k][myrow] : T(0);
-  const T rdiag = T(1) / Ls[myrow][myrow];  // only lanes < k use theirs
+  const T rdiag = recip(Ls[myrow][myrow]);  // only lanes < k use theirs
   T Ab = 0;
   for (int a = k - 1; a >= 0; --a) {
     const T Aa = lane_bcast(accv * rdiag, a);
@@ -308,7 +322,7 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   const T tbar = ei * rsd;
   const T Abar = (lane < k) ? -ubv - tbar * T(y[sh.nbs[myrow]]) : T(0);
   // z = L_R^{-1} Abar (lane a holds row a of L in Lrow)
-  const T rdiag = T(1) / Ls[myrow][myrow];  // only lanes < k use theirs
+  const T rdiag = recip(Ls[myrow][myrow]);  // only lanes < k use theirs
   T accz = Abar;
   T z = 0;
 #pragma unroll
@@ -529,7 +543,7 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
   AdRA = wave_sum(AdRA);
   const T dDi = dc - T(2) * drA + AdRA;
   // dA = L_R^{-T} L_R^{-1} rhs  (lane a holds row a of L in Lrow)
-  const T rdiag = T(1) / Ls[myrow][myrow];  // only lanes < k use theirs
+  const T rdiag = recip(Ls[myrow][myrow]);  // only lanes < k use theirs
   T accz = rhs, z = 0;
 #pragma unroll
   for (int q = 0; q < 32; ++q) {
