@@ -27,7 +27,13 @@
  *  - The caller owns every input and output buffer. The context owns its
  *    workspace (sized once in vif_create) and the factor of the last
  *    vif_build_factor call, valid until the next build or vif_destroy.
- *  - All work is issued on the HIP stream given at creation (NULL = default).
+ *  - All work is issued on the HIP stream given at creation (NULL = default),
+ *    except one kernel of a Gaussian context with inducing points: after the
+ *    context's first vif_nll_grad, each vif_build_factor also starts the
+ *    derivative features L_m^{-1} dK(Z, X)/drange on a second, context-owned
+ *    stream, ordered after the build's L_m and before the next gradient or
+ *    build by events (a caller that synchronises the creation stream after
+ *    vif_nll_grad sees every result).
  *  - Errors: a status code, never an exception; vif_last_error() then holds a
  *    message naming the failing point / iteration. One context per host
  *    thread; calls on one context must not overlap.
