@@ -82,6 +82,8 @@ struct vif_ctx {
   // level-ordered rows of B and B^T (see trsv.hip) and their coefficients,
   // copied from A after each build
   int *fcol = nullptr, *bptr = nullptr, *bcol = nullptr, *bsrc = nullptr;
+  int *fsrc = nullptr, *fsplit = nullptr, *bsplit = nullptr;
+  std::vector<int> hfwd_run, hbwd_run;  // runs of small levels (level pairs)
   void *fcoef = nullptr, *bcoef = nullptr;
   bool coef_valid = false;
   TriSchedule sf{}, sb{};
@@ -312,6 +314,9 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
     alloc((void**)&c->bptr, sizeof(int) * (n + 1));
     alloc((void**)&c->bcol, sizeof(int) * mvn);
     alloc((void**)&c->bsrc, sizeof(int) * mvn);
+    alloc((void**)&c->fsrc, sizeof(int) * mvn);
+    alloc((void**)&c->fsplit, sizeof(int) * n);
+    alloc((void**)&c->bsplit, sizeof(int) * n);
     alloc(&c->fcoef, tsize(c) * mvn);
     alloc(&c->bcoef, tsize(c) * mvn);
     alloc((void**)&c->lm, sizeof(double) * mpa * 4);
@@ -350,7 +355,7 @@ void vif_destroy(vif_ctx* c) {
                   c->e, c->Smat, c->Tm, c->tmpm, c->MinvT, c->Ubar, c->Q1, c->Gs, c->Bs, c->Vr, c->tpart,
                   c->rowpart, c->gred, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx,
                   c->fwd_order, c->fwd_lvl, c->bwd_order, c->bwd_lvl, c->lv, c->lm, c->M3, c->M3inv, c->L3inv,
-                  c->lsc, c->lpart, c->fcol, c->bptr, c->bcol, c->bsrc, c->fcoef, c->bcoef, c->slq_a, c->slq_b, c->slq_rz, c->slq_terms, c->slq_work, c->slq_u,
+                  c->lsc, c->lpart, c->fcol, c->bptr, c->bcol, c->bsrc, c->fsrc, c->fsplit, c->bsplit, c->fcoef, c->bcoef, c->slq_a, c->slq_b, c->slq_rz, c->slq_terms, c->slq_work, c->slq_u,
                   c->slq_q, c->slq_iters, c->lg_Ut, c->lg_Ut3, c->lg_dV, c->lg_dU[0], c->lg_dU[1], c->lg_dU[2],
                   c->lg_dA[0], c->lg_dA[1], c->lg_dA[2], c->lg_MT, c->lg_M3T, c->lg_PhiT, c->lg_dD[0],
                   c->lg_dD[1], c->lg_dD[2], c->lg_mm, c->lg_vec, c->lg_part, c->lg_slots, c->pred_Vp,
@@ -769,19 +774,45 @@ static vif_status ensure_schedules(vif_ctx* c) {
   c->nlev_b = schedule(rlev, bo, bp);
   c->hfwd_lvl = fp;
   c->hbwd_lvl = bp;
+  // runs of small levels, and for each position in a run the run's first
+  // position P0 (entries at positions >= P0 are inside the run)
+  trsv_runs(fp.data(), c->nlev_f, c->hfwd_run);
+  trsv_runs(bp.data(), c->nlev_b, c->hbwd_run);
+  auto run_start = [&](const std::vector<int>& lp, const std::vector<int>& runs) {
+    std::vector<int> p0(n, -1);
+    for (size_t r = 0; r + 1 < runs.size(); r += 2)
+      for (int q = lp[runs[r]]; q < lp[runs[r + 1]]; ++q) p0[q] = lp[runs[r]];
+    return p0;
+  };
+  const std::vector<int> fp0 = run_start(fp, c->hfwd_run), bp0 = run_start(bp, c->hbwd_run);
   // level-ordered rows: B (fixed width m_v) and B^T (CSR over the points that
-  // have the row's point as a neighbour, in increasing (point, slot) order)
+  // have the row's point as a neighbour, in increasing (point, slot) order);
+  // in a run's rows the in-run entries are moved to the front (stable)
   {
     const int mva = mv > 0 ? mv : 1;
     std::vector<int> fpos(n), bpos(n);
     for (int64_t q = 0; q < n; ++q) fpos[fo[q]] = (int)q;
     for (int64_t q = 0; q < n; ++q) bpos[bo[q]] = (int)q;
-    std::vector<int> fcol((size_t)n * mva, -1);
-    for (int64_t q = 0; q < n; ++q)
+    std::vector<int> fcol((size_t)n * mva, -1), fsrc((size_t)n * mva, -1), fsplit(n, 0);
+    for (int64_t q = 0; q < n; ++q) {
+      int k = 0;
+      for (int pass = 0; pass < 2; ++pass)  // pass 0: in-run entries, pass 1: the rest
+        for (int a = 0; a < mv; ++a) {
+          const int j = nb[(size_t)fo[q] * mv + a];
+          if (j < 0) continue;
+          const bool inrun = fp0[q] >= 0 && fpos[j] >= fp0[q];
+          if (inrun != (pass == 0)) continue;
+          fcol[(size_t)q * mv + k] = fpos[j];
+          fsrc[(size_t)q * mv + k] = (int)(fo[q] * mv + a);
+          ++k;
+        }
+      int nin = 0;
       for (int a = 0; a < mv; ++a) {
-        const int j = nb[(size_t)fo[q] * mv + a];
-        fcol[(size_t)q * mv + a] = j >= 0 ? fpos[j] : -1;
+        const int cpos = fcol[(size_t)q * mv + a];
+        if (cpos >= 0 && fp0[q] >= 0 && cpos >= fp0[q]) ++nin;
       }
+      fsplit[q] = nin;
+    }
     std::vector<int> cnt(n, 0);
     for (size_t e = 0; e < (size_t)n * mv; ++e)
       if (nb[e] >= 0) cnt[nb[e]]++;
@@ -799,12 +830,44 @@ static vif_status ensure_schedules(vif_ctx* c) {
         bcol[e] = bpos[i];
         bsrc[e] = (int)(i * mv + a);
       }
+    std::vector<int> bsplit(n);
+    {
+      std::vector<int> tc, ts;
+      for (int64_t q = 0; q < n; ++q) {
+        const int e0 = bptr[q], e1 = bptr[q + 1];
+        if (bp0[q] < 0) {
+          bsplit[q] = e1;
+          continue;
+        }
+        tc.clear();
+        ts.clear();
+        for (int pass = 0; pass < 2; ++pass)
+          for (int e = e0; e < e1; ++e)
+            if ((bcol[e] >= bp0[q]) == (pass == 0)) {
+              tc.push_back(bcol[e]);
+              ts.push_back(bsrc[e]);
+            }
+        int nin = 0;
+        for (int e = e0; e < e1; ++e) nin += bcol[e] >= bp0[q];
+        for (int e = e0; e < e1; ++e) {
+          bcol[e] = tc[e - e0];
+          bsrc[e] = ts[e - e0];
+        }
+        bsplit[q] = e0 + nin;
+      }
+    }
     HIPCHK(c, hipMemcpyAsync(c->fcol, fcol.data(), sizeof(int) * fcol.size(), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->fsrc, fsrc.data(), sizeof(int) * fsrc.size(), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->fsplit, fsplit.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bptr, bptr.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bcol, bcol.data(), sizeof(int) * bcol.size(), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bsrc, bsrc.data(), sizeof(int) * bsrc.size(), hipMemcpyHostToDevice, c->st));
-    c->sf = TriSchedule{(int)n, mv, c->nlev_f, 0, c->fwd_order, c->fwd_lvl, nullptr, nullptr, c->fcol, nullptr};
-    c->sb = TriSchedule{(int)n, mv, c->nlev_b, ne, c->bwd_order, c->bwd_lvl, nullptr, c->bptr, c->bcol, c->bsrc};
+    HIPCHK(c, hipMemcpyAsync(c->bsplit, bsplit.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));  // the host vectors go out of scope
+    c->sf = TriSchedule{(int)n, mv, c->nlev_f, (int64_t)n * mv, c->fwd_order, c->fwd_lvl, nullptr, nullptr,
+                        c->fcol, c->fsrc, c->fsplit, c->hfwd_run.data(), (int)c->hfwd_run.size() / 2};
+    c->sb = TriSchedule{(int)n, mv, c->nlev_b, ne, c->bwd_order, c->bwd_lvl, nullptr, c->bptr, c->bcol, c->bsrc,
+                        c->bsplit, c->hbwd_run.data(), (int)c->hbwd_run.size() / 2};
   }
   HIPCHK(c, hipMemcpyAsync(c->fwd_order, fo.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->fwd_lvl, fp.data(), sizeof(int) * fp.size(), hipMemcpyHostToDevice, c->st));
@@ -1082,8 +1145,8 @@ static vif_status laplace_impl(vif_ctx* c, const double* y, const double* b0, do
   S.converged = converged ? 1 : 0;
   S.levels_fwd = c->nlev_f;
   S.levels_bwd = c->nlev_b;
-  for (int L = 0; L < c->nlev_f; ++L) S.wide_fwd += (c->hfwd_lvl[L + 1] - c->hfwd_lvl[L] >= 1024);
-  for (int L = 0; L < c->nlev_b; ++L) S.wide_bwd += (c->hbwd_lvl[L + 1] - c->hbwd_lvl[L] >= 1024);
+  for (int L = 0; L < c->nlev_f; ++L) S.wide_fwd += (c->hfwd_lvl[L + 1] - c->hfwd_lvl[L] > kTrsvSmallLevel);
+  for (int L = 0; L < c->nlev_b; ++L) S.wide_bwd += (c->hbwd_lvl[L + 1] - c->hbwd_lvl[L] > kTrsvSmallLevel);
   HIPCHK(c, hipMemcpyAsync(mode_out, B.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
   HIPCHK(c, hipGetLastError());
   if ((s = read_status(c, "vif_laplace_mode"))) return s;

@@ -1,5 +1,7 @@
 // Host-side launchers of the VIF kernels (one translation unit per family).
 #pragma once
+
+#include <vector>
 #include "common.h"
 
 // dense.hip
@@ -117,16 +119,30 @@ void launch_wgram_partial(hipStream_t st, const T* U, const double* sw, int64_t 
                           int* nchunk_out);
 // Level-scheduled solves with B (trsv.hip). Positions q list the points
 // level by level; rows hold the positions they read.
+// Level schedule of a sparse unit-triangular solve (trsv.hip). Runs of
+// consecutive small levels are walked by one workgroup; inside a run's rows
+// the entries that point into the run come first, the rest (final before the
+// run starts) are folded into x by a parallel pre-pass.
+constexpr int kTrsvSmallLevel = 256;   // levels with more points get a whole-GPU launch
+constexpr int kTrsvRunLevels = 2048;   // levels per run
+constexpr int kTrsvRunCap = 16384;     // positions per run (their z sit in LDS)
 struct TriSchedule {
   int n, mv, nlev;
-  int64_t ne;        // entries of the B^T rows
+  int64_t ne;        // entries of the rows (B: n * m_v slots; B^T: CSR entries)
   const int* order;  // position -> point
   const int* lvl;    // level offsets (device, nlev + 1)
   const int* hlvl;   // the same on the host
   const int* ptr;    // B^T: row offsets by position (n + 1)
   const int* col;    // B: n x m_v positions (-1 = none); B^T: positions of the entries
-  const int* src;    // B^T: index into A (n x m_v) of each entry
+  const int* src;    // index into A (n x m_v) of each entry (-1 = none)
+  const int* split;  // per position in a run: B: in-run entries of the row (they come first);
+                     // B^T: end of the in-run entries (row start + count)
+  const int* hrun;   // host: runs as level pairs [hrun[2r], hrun[2r + 1])
+  int nrun;
 };
+// runs of a level schedule (host): consecutive levels of <= kTrsvSmallLevel
+// points, at most kTrsvRunLevels levels and kTrsvRunCap positions each
+void trsv_runs(const int* hlvl, int nlev, std::vector<int>& runs);
 template <typename T>
 void launch_trsv_fwd(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, double* xq, double* zq,
                      double* z);

@@ -10,19 +10,30 @@
 // contiguous memory, and the next level's rows can be loaded before the
 // current level's results are known.
 //
-// Small levels (at most kSmallLevel points) are walked by one workgroup,
-// with a barrier between levels: each point gets G lanes (the largest power
-// of two with G * points <= 1024, at least 4), each lane up to 8 entries,
-// and while a level is being summed the rows of the next level are already
-// in registers, so a level costs one round of gathers of z. Larger levels
-// get a launch of their own over the whole GPU (32 lanes per point); kernel
-// order on the stream separates them.
+// Small levels (at most kTrsvSmallLevel points) are walked by one workgroup,
+// a run of consecutive small levels per launch: each point gets G lanes (the
+// largest power of two with G * points <= 1024, at least 4), each lane up to
+// 8 entries held in registers, loaded one level ahead. The run's positions
+// are contiguous and their z values live in LDS for the whole run, so a
+// level's dependence on earlier levels of the run is an LDS read and the
+// barrier between levels waits for LDS only. A row's entries that point
+// before the run are final when the run starts: a parallel pre-pass over the
+// run's rows adds them into x, and the walk reads only the in-run entries
+// (stored first in each row). The run's z is written back once at its end.
+// Larger levels get a launch of their own over the whole GPU (32 lanes per
+// point); kernel order on the stream separates them.
 #include "common.h"
 #include "kernels.h"
 
-constexpr int kSmallLevel = 256;
-constexpr int kRunLevels = 2048;
 constexpr int kPre = 8;  // entries per lane held in registers
+
+// barrier for LDS traffic only: outstanding global loads (the next level's
+// rows) stay in flight across it
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 __device__ __forceinline__ int lanes_for(int cnt, int cap) {
   int G = cap;
@@ -31,25 +42,55 @@ __device__ __forceinline__ int lanes_for(int cnt, int cap) {
 }
 
 struct RowRegs {
-  int c[kPre];
-  double w[kPre];
+  int c[kPre];     // LDS index (position - P0) of an in-run entry, or -1
+  double w[kPre];  // coefficient (0 where there is no entry)
   double x;
   int q;    // position, or -1
-  int rem;  // first entry not held (B^T rows), end in e1
+  int rem;  // first in-run entry not held (B^T rows), end in e1
   int e1;
 };
 
+__device__ __forceinline__ double row_sum(const RowRegs& r, const double* zs) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kPre; ++k) s += r.w[k] * (r.c[k] >= 0 ? zs[r.c[k]] : 0.0);
+  return s;
+}
+
 // ---------------------------------------------------------------- B^{-1}
+// pre-pass of a run: xq[q] += sum of the row's entries before the run (from
+// slot nin[q] on), 32 lanes per point
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_fwd_pre(int beg, int end, const int* __restrict__ col,
+                                                       const T* __restrict__ coef, const int* __restrict__ nin,
+                                                       int mv, const double* __restrict__ zq, double* xq) {
+  const int lane = threadIdx.x & 31;
+  const int q = beg + blockIdx.x * 8 + (threadIdx.x >> 5);
+  if (q >= end) return;
+  double s = 0.0;
+  if (lane < mv && lane >= nin[q]) {
+    const int j = col[(size_t)q * mv + lane];
+    if (j >= 0) s = (double)coef[(size_t)q * mv + lane] * zq[j];
+  }
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
+  if (lane == 0) xq[q] += s;
+}
+
 template <typename T>
 __device__ __forceinline__ void fwd_load(RowRegs& r, int q, bool active, int lig, int G, const int* col,
-                                         const T* coef, const double* xq, int mv) {
+                                         const T* coef, const int* nin, const double* xq, int mv, int P0) {
   r.q = active ? q : -1;
+  const int cnt = active ? nin[q] : 0;
 #pragma unroll
   for (int k = 0; k < kPre; ++k) {
     const int a = lig + k * G;
     const bool ok = active && a < mv;
-    r.c[k] = ok ? col[(size_t)q * mv + a] : -1;
-    r.w[k] = ok ? (double)coef[(size_t)q * mv + a] : 0.0;
+    const int pos = ok ? col[(size_t)q * mv + a] : -1;
+    const double w = ok ? (double)coef[(size_t)q * mv + a] : 0.0;
+    const bool in = a < cnt;
+    r.c[k] = in ? pos - P0 : -1;
+    r.w[k] = in ? w : 0.0;
   }
   r.x = active ? xq[q] : 0.0;
 }
@@ -57,15 +98,17 @@ __device__ __forceinline__ void fwd_load(RowRegs& r, int q, bool active, int lig
 template <typename T>
 __global__ __launch_bounds__(1024) void k_trsv_fwd_run(const int* __restrict__ lvl, int L0, int L1,
                                                        const int* __restrict__ col, const T* __restrict__ coef,
-                                                       const double* __restrict__ xq, int mv, double* zq) {
-  __shared__ int slv[kRunLevels + 1];
+                                                       const int* __restrict__ nin, const double* __restrict__ xq,
+                                                       int mv, double* zq) {
+  __shared__ int slv[kTrsvRunLevels + 1];
+  __shared__ double zs[kTrsvRunCap];
   for (int t = threadIdx.x; t <= L1 - L0; t += 1024) slv[t] = lvl[L0 + t];
   __syncthreads();
-  const int nL = L1 - L0;
+  const int nL = L1 - L0, P0 = slv[0];
   RowRegs cur, nxt;
   {
     const int cnt = slv[1] - slv[0], G = lanes_for(cnt, 32), grp = threadIdx.x / G;
-    fwd_load<T>(nxt, slv[0] + grp, grp < cnt, threadIdx.x - grp * G, G, col, coef, xq, mv);
+    fwd_load<T>(nxt, slv[0] + grp, grp < cnt, threadIdx.x - grp * G, G, col, coef, nin, xq, mv, P0);
   }
   for (int L = 0; L < nL; ++L) {
     const int cnt = slv[L + 1] - slv[L];
@@ -73,18 +116,14 @@ __global__ __launch_bounds__(1024) void k_trsv_fwd_run(const int* __restrict__ l
     cur = nxt;
     if (L + 1 < nL) {
       const int cn = slv[L + 2] - slv[L + 1], Gn = lanes_for(cn, 32), gn = threadIdx.x / Gn;
-      fwd_load<T>(nxt, slv[L + 1] + gn, gn < cn, threadIdx.x - gn * Gn, Gn, col, coef, xq, mv);
+      fwd_load<T>(nxt, slv[L + 1] + gn, gn < cn, threadIdx.x - gn * Gn, Gn, col, coef, nin, xq, mv, P0);
     }
-    double zv[kPre];
-#pragma unroll
-    for (int k = 0; k < kPre; ++k) zv[k] = cur.c[k] >= 0 ? zq[cur.c[k]] : 0.0;
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < kPre; ++k) s += cur.w[k] * zv[k];
+    double s = row_sum(cur, zs);
     for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (cur.q >= 0 && lig == 0) zq[cur.q] = cur.x + s;
-    __syncthreads();
+    if (cur.q >= 0 && lig == 0) zs[cur.q - P0] = cur.x + s;
+    lds_barrier();
   }
+  for (int t = threadIdx.x; t < slv[nL] - P0; t += 1024) zq[P0 + t] = zs[t];
 }
 
 // one large level of B^{-1}: 32 lanes per point (m_v <= 31)
@@ -106,16 +145,35 @@ __global__ __launch_bounds__(256) void k_trsv_fwd_wide(int beg, int end, const i
 }
 
 // ---------------------------------------------------------------- B^{-T}
+// pre-pass of a run: xq[q] += sum of the row's entries before the run
+// ([split[q], ptr[q + 1])), 32 lanes per point
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_bwd_pre(int beg, int end, const int* __restrict__ ptr,
+                                                       const int* __restrict__ split, const int* __restrict__ col,
+                                                       const T* __restrict__ coef, const double* __restrict__ zq,
+                                                       double* xq) {
+  const int lane = threadIdx.x & 31;
+  const int q = beg + blockIdx.x * 8 + (threadIdx.x >> 5);
+  if (q >= end) return;
+  double s = 0.0;
+  const int e1 = ptr[q + 1];
+  for (int a = split[q] + lane; a < e1; a += 32) s += (double)coef[a] * zq[col[a]];
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
+  if (lane == 0) xq[q] += s;
+}
+
 template <typename T>
 __device__ __forceinline__ void bwd_load(RowRegs& r, int q, bool active, int lig, int G, const int* ptr,
-                                         const int* col, const T* coef, const double* xq) {
+                                         const int* split, const int* col, const T* coef, const double* xq,
+                                         int P0) {
   r.q = active ? q : -1;
-  const int e0 = active ? ptr[q] : 0, e1 = active ? ptr[q + 1] : 0;
+  const int e0 = active ? ptr[q] : 0, e1 = active ? split[q] : 0;
 #pragma unroll
   for (int k = 0; k < kPre; ++k) {
     const int a = e0 + lig + k * G;
     const bool ok = a < e1;
-    r.c[k] = ok ? col[a] : -1;
+    r.c[k] = ok ? col[a] - P0 : -1;
     r.w[k] = ok ? (double)coef[a] : 0.0;
   }
   r.x = active ? xq[q] : 0.0;
@@ -125,17 +183,18 @@ __device__ __forceinline__ void bwd_load(RowRegs& r, int q, bool active, int lig
 
 template <typename T>
 __global__ __launch_bounds__(1024) void k_trsv_bwd_run(const int* __restrict__ lvl, int L0, int L1,
-                                                       const int* __restrict__ ptr, const int* __restrict__ col,
-                                                       const T* __restrict__ coef, const double* __restrict__ xq,
-                                                       double* zq) {
-  __shared__ int slv[kRunLevels + 1];
+                                                       const int* __restrict__ ptr, const int* __restrict__ split,
+                                                       const int* __restrict__ col, const T* __restrict__ coef,
+                                                       const double* __restrict__ xq, double* zq) {
+  __shared__ int slv[kTrsvRunLevels + 1];
+  __shared__ double zs[kTrsvRunCap];
   for (int t = threadIdx.x; t <= L1 - L0; t += 1024) slv[t] = lvl[L0 + t];
   __syncthreads();
-  const int nL = L1 - L0;
+  const int nL = L1 - L0, P0 = slv[0];
   RowRegs cur, nxt;
   {
     const int cnt = slv[1] - slv[0], G = lanes_for(cnt, 64), grp = threadIdx.x / G;
-    bwd_load<T>(nxt, slv[0] + grp, grp < cnt, threadIdx.x - grp * G, G, ptr, col, coef, xq);
+    bwd_load<T>(nxt, slv[0] + grp, grp < cnt, threadIdx.x - grp * G, G, ptr, split, col, coef, xq, P0);
   }
   for (int L = 0; L < nL; ++L) {
     const int cnt = slv[L + 1] - slv[L];
@@ -143,33 +202,27 @@ __global__ __launch_bounds__(1024) void k_trsv_bwd_run(const int* __restrict__ l
     cur = nxt;
     if (L + 1 < nL) {
       const int cn = slv[L + 2] - slv[L + 1], Gn = lanes_for(cn, 64), gn = threadIdx.x / Gn;
-      bwd_load<T>(nxt, slv[L + 1] + gn, gn < cn, threadIdx.x - gn * Gn, Gn, ptr, col, coef, xq);
+      bwd_load<T>(nxt, slv[L + 1] + gn, gn < cn, threadIdx.x - gn * Gn, Gn, ptr, split, col, coef, xq, P0);
     }
-    double zv[kPre];
+    double s = row_sum(cur, zs);
+    // in-run parts longer than 8 G entries: the rest, 4 per lane at a time
+    for (int a0 = cur.rem; a0 < cur.e1; a0 += 4 * G) {
+      int cc[4];
+      double ww[4];
 #pragma unroll
-    for (int k = 0; k < kPre; ++k) zv[k] = cur.c[k] >= 0 ? zq[cur.c[k]] : 0.0;
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < kPre; ++k) s += cur.w[k] * zv[k];
-    // rows longer than 8 G entries: the rest, 8 per lane at a time (loads first)
-    for (int a0 = cur.rem; a0 < cur.e1; a0 += kPre * G) {
-      int cc[kPre];
-      double ww[kPre], zz[kPre];
-#pragma unroll
-      for (int k = 0; k < kPre; ++k) {
+      for (int k = 0; k < 4; ++k) {
         const int a = a0 + k * G;
-        cc[k] = a < cur.e1 ? col[a] : -1;
+        cc[k] = a < cur.e1 ? col[a] - P0 : -1;
         ww[k] = a < cur.e1 ? (double)coef[a] : 0.0;
       }
 #pragma unroll
-      for (int k = 0; k < kPre; ++k) zz[k] = cc[k] >= 0 ? zq[cc[k]] : 0.0;
-#pragma unroll
-      for (int k = 0; k < kPre; ++k) s += ww[k] * zz[k];
+      for (int k = 0; k < 4; ++k) s += ww[k] * (cc[k] >= 0 ? zs[cc[k]] : 0.0);
     }
     for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (cur.q >= 0 && lig == 0) zq[cur.q] = cur.x + s;
-    __syncthreads();
+    if (cur.q >= 0 && lig == 0) zs[cur.q - P0] = cur.x + s;
+    lds_barrier();
   }
+  for (int t = threadIdx.x; t < slv[nL] - P0; t += 1024) zq[P0 + t] = zs[t];
 }
 
 // one large level of B^{-T}: 32 lanes per point
@@ -199,41 +252,53 @@ __global__ void k_perm_scatter(const int* __restrict__ order, const double* __re
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q < n) z[order[q]] = zq[q];
 }
-// coef[q * mv + a] = A[order[q] * mv + a]
+// coef[e] = A[src[e]] (0 where src[e] < 0)
 template <typename T>
-__global__ void k_coef_fwd(const int* __restrict__ order, const T* __restrict__ A, int64_t n, int mv,
-                           T* __restrict__ coef) {
+__global__ void k_coef_src(const int* __restrict__ src, const T* __restrict__ A, int64_t ne, T* __restrict__ coef) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * mv) return;
-  const int64_t q = e / mv;
-  coef[e] = A[(size_t)order[q] * mv + (e - q * mv)];
-}
-// coef[e] = A[src[e]]
-template <typename T>
-__global__ void k_coef_bwd(const int* __restrict__ src, const T* __restrict__ A, int64_t ne, T* __restrict__ coef) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < ne) coef[e] = A[src[e]];
+  if (e < ne) coef[e] = src[e] >= 0 ? A[src[e]] : T(0);
 }
 
 // ---------------------------------------------------------------- launchers
+void trsv_runs(const int* hlvl, int nlev, std::vector<int>& runs) {
+  runs.clear();
+  int L = 0;
+  while (L < nlev) {
+    if (hlvl[L + 1] - hlvl[L] > kTrsvSmallLevel) {
+      ++L;
+      continue;
+    }
+    int L1 = L + 1;
+    while (L1 < nlev && L1 - L < kTrsvRunLevels && hlvl[L1 + 1] - hlvl[L1] <= kTrsvSmallLevel &&
+           hlvl[L1 + 1] - hlvl[L] <= kTrsvRunCap)
+      ++L1;
+    runs.push_back(L);
+    runs.push_back(L1);
+    L = L1;
+  }
+}
+
 template <typename T>
 void launch_trsv_fwd(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, double* xq, double* zq,
                      double* z) {
   const int64_t n = s.n;
   hipLaunchKernelGGL(k_perm_gather, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, s.order, x, n, xq);
-  int L = 0;
+  int L = 0, r = 0;
   while (L < s.nlev) {
-    const int cnt = s.hlvl[L + 1] - s.hlvl[L];
-    if (cnt > kSmallLevel) {
-      hipLaunchKernelGGL((k_trsv_fwd_wide<T>), dim3((unsigned)ceil_div(cnt, 8)), dim3(256), 0, st, s.hlvl[L],
-                         s.hlvl[L + 1], s.col, coef, xq, s.mv, zq);
-      ++L;
+    if (r < s.nrun && s.hrun[2 * r] == L) {
+      const int L1 = s.hrun[2 * r + 1], P0 = s.hlvl[L], P1 = s.hlvl[L1];
+      hipLaunchKernelGGL((k_trsv_fwd_pre<T>), dim3((unsigned)ceil_div(P1 - P0, 8)), dim3(256), 0, st, P0, P1,
+                         s.col, coef, s.split, s.mv, zq, xq);
+      hipLaunchKernelGGL((k_trsv_fwd_run<T>), dim3(1), dim3(1024), 0, st, s.lvl, L, L1, s.col, coef, s.split, xq,
+                         s.mv, zq);
+      L = L1;
+      ++r;
       continue;
     }
-    int L1 = L + 1;
-    while (L1 < s.nlev && L1 - L < kRunLevels && s.hlvl[L1 + 1] - s.hlvl[L1] <= kSmallLevel) ++L1;
-    hipLaunchKernelGGL((k_trsv_fwd_run<T>), dim3(1), dim3(1024), 0, st, s.lvl, L, L1, s.col, coef, xq, s.mv, zq);
-    L = L1;
+    const int cnt = s.hlvl[L + 1] - s.hlvl[L];
+    hipLaunchKernelGGL((k_trsv_fwd_wide<T>), dim3((unsigned)ceil_div(cnt, 8)), dim3(256), 0, st, s.hlvl[L],
+                       s.hlvl[L + 1], s.col, coef, xq, s.mv, zq);
+    ++L;
   }
   hipLaunchKernelGGL(k_perm_scatter, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, s.order, zq, n, z);
 }
@@ -243,32 +308,34 @@ void launch_trsv_bwd(hipStream_t st, const TriSchedule& s, const T* coef, const 
                      double* z) {
   const int64_t n = s.n;
   hipLaunchKernelGGL(k_perm_gather, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, s.order, x, n, xq);
-  int L = 0;
+  int L = 0, r = 0;
   while (L < s.nlev) {
-    const int cnt = s.hlvl[L + 1] - s.hlvl[L];
-    if (cnt > kSmallLevel) {
-      hipLaunchKernelGGL((k_trsv_bwd_wide<T>), dim3((unsigned)ceil_div(cnt, 8)), dim3(256), 0, st, s.hlvl[L],
-                         s.hlvl[L + 1], s.ptr, s.col, coef, xq, zq);
-      ++L;
+    if (r < s.nrun && s.hrun[2 * r] == L) {
+      const int L1 = s.hrun[2 * r + 1], P0 = s.hlvl[L], P1 = s.hlvl[L1];
+      hipLaunchKernelGGL((k_trsv_bwd_pre<T>), dim3((unsigned)ceil_div(P1 - P0, 8)), dim3(256), 0, st, P0, P1,
+                         s.ptr, s.split, s.col, coef, zq, xq);
+      hipLaunchKernelGGL((k_trsv_bwd_run<T>), dim3(1), dim3(1024), 0, st, s.lvl, L, L1, s.ptr, s.split, s.col, coef,
+                         xq, zq);
+      L = L1;
+      ++r;
       continue;
     }
-    int L1 = L + 1;
-    while (L1 < s.nlev && L1 - L < kRunLevels && s.hlvl[L1 + 1] - s.hlvl[L1] <= kSmallLevel) ++L1;
-    hipLaunchKernelGGL((k_trsv_bwd_run<T>), dim3(1), dim3(1024), 0, st, s.lvl, L, L1, s.ptr, s.col, coef, xq, zq);
-    L = L1;
+    const int cnt = s.hlvl[L + 1] - s.hlvl[L];
+    hipLaunchKernelGGL((k_trsv_bwd_wide<T>), dim3((unsigned)ceil_div(cnt, 8)), dim3(256), 0, st, s.hlvl[L],
+                       s.hlvl[L + 1], s.ptr, s.col, coef, xq, zq);
+    ++L;
   }
   hipLaunchKernelGGL(k_perm_scatter, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, s.order, zq, n, z);
 }
 
 template <typename T>
 void launch_coef_fwd(hipStream_t st, const TriSchedule& s, const T* A, T* coef) {
-  const int64_t ne = (int64_t)s.n * s.mv;
-  if (ne > 0) hipLaunchKernelGGL((k_coef_fwd<T>), dim3((unsigned)ceil_div(ne, 256)), dim3(256), 0, st, s.order, A,
-                                 (int64_t)s.n, s.mv, coef);
+  if (s.ne > 0) hipLaunchKernelGGL((k_coef_src<T>), dim3((unsigned)ceil_div(s.ne, 256)), dim3(256), 0, st, s.src, A,
+                                   s.ne, coef);
 }
 template <typename T>
 void launch_coef_bwd(hipStream_t st, const TriSchedule& s, const T* A, T* coef) {
-  if (s.ne > 0) hipLaunchKernelGGL((k_coef_bwd<T>), dim3((unsigned)ceil_div(s.ne, 256)), dim3(256), 0, st, s.src, A,
+  if (s.ne > 0) hipLaunchKernelGGL((k_coef_src<T>), dim3((unsigned)ceil_div(s.ne, 256)), dim3(256), 0, st, s.src, A,
                                    s.ne, coef);
 }
 
