@@ -96,7 +96,7 @@ typedef struct {
   double psi_start;         /* objective at the start used */
   int32_t levels_fwd;       /* levels of the B^{-1} solve (dependency depth) */
   int32_t levels_bwd;       /* levels of the B^{-T} solve */
-  int32_t wide_fwd;         /* of which with >= 1024 points (whole-GPU launches) */
+  int32_t wide_fwd;         /* of which with > 256 points (whole-GPU launches) */
   int32_t wide_bwd;
 } vif_laplace_stats;
 

@@ -161,12 +161,12 @@ __global__ void k_mlp_adam(float* __restrict__ p, const float* __restrict__ g, f
   p[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
 }
 
+// out[0] = sum of nb partials (one wave, fixed order)
 __global__ void k_sum_d(const double* part, int nb, double* out) {
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[b];
-    out[0] = s;
-  }
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 64) s += part[b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[0] = s;
 }
 
 // Per-point input features of the warm-start network (F = 16 columns):

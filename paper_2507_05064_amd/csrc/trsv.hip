@@ -13,7 +13,7 @@
 // Small levels (at most kTrsvSmallLevel points) are walked by one workgroup,
 // a run of consecutive small levels per launch: each point gets G lanes (the
 // largest power of two with G * points <= 1024, at least 4), each lane up to
-// 8 entries held in registers, loaded one level ahead. The run's positions
+// 8 entries held in registers, loaded two levels ahead. The run's positions
 // are contiguous and their z values live in LDS for the whole run, so a
 // level's dependence on earlier levels of the run is an LDS read and the
 // barrier between levels waits for LDS only. A row's entries that point
@@ -41,19 +41,30 @@ __device__ __forceinline__ int lanes_for(int cnt, int cap) {
   return G;
 }
 
+// One level's rows as loaded: raw values only. Loads are predicated (lanes
+// and whole waves without work issue none) and nothing is derived from a
+// loaded value until the row is used, so the loads of the levels ahead stay
+// in flight (a value used at load time would make the compiler wait for
+// them). Registers of slots that were not loaded are masked at use.
 struct RowRegs {
-  int c[kPre];     // LDS index (position - P0) of an in-run entry, or -1
-  double w[kPre];  // coefficient (0 where there is no entry)
+  int c[kPre];     // loaded entry positions
+  double w[kPre];  // loaded coefficients
   double x;
-  int q;    // position, or -1
-  int rem;  // first in-run entry not held (B^T rows), end in e1
-  int e1;
+  int q;     // position, or -1 for an idle lane group
+  int cnt;   // B: in-run entries of the row (loaded); B^T: first entry (loaded)
+  int e1;    // B^T: end of the in-run entries (loaded)
 };
 
-__device__ __forceinline__ double row_sum(const RowRegs& r, const double* zs) {
+// sum of w * z over the held in-run entries: entry slot a = lig + k G is
+// valid when a < lim; its z is read from LDS at position - P0
+__device__ __forceinline__ double row_sum(const RowRegs& r, int lig, int G, int lim, int P0, const double* zs) {
   double s = 0.0;
 #pragma unroll
-  for (int k = 0; k < kPre; ++k) s += r.w[k] * (r.c[k] >= 0 ? zs[r.c[k]] : 0.0);
+  for (int k = 0; k < kPre; ++k) {
+    const bool ok = r.q >= 0 && lig + k * G < lim;
+    const double z = zs[ok ? r.c[k] - P0 : 0];
+    s += ok ? r.w[k] * z : 0.0;
+  }
   return s;
 }
 
@@ -81,18 +92,18 @@ template <typename T>
 __device__ __forceinline__ void fwd_load(RowRegs& r, int q, bool active, int lig, int G, const int* col,
                                          const T* coef, const int* nin, const double* xq, int mv, int P0) {
   r.q = active ? q : -1;
-  const int cnt = active ? nin[q] : 0;
+  if (active) {
+    r.cnt = nin[q];
+    r.x = xq[q];
+  }
 #pragma unroll
   for (int k = 0; k < kPre; ++k) {
     const int a = lig + k * G;
-    const bool ok = active && a < mv;
-    const int pos = ok ? col[(size_t)q * mv + a] : -1;
-    const double w = ok ? (double)coef[(size_t)q * mv + a] : 0.0;
-    const bool in = a < cnt;
-    r.c[k] = in ? pos - P0 : -1;
-    r.w[k] = in ? w : 0.0;
+    if (active && a < mv) {
+      r.c[k] = col[(size_t)q * mv + a];
+      r.w[k] = (double)coef[(size_t)q * mv + a];
+    }
   }
-  r.x = active ? xq[q] : 0.0;
 }
 
 template <typename T>
@@ -105,23 +116,34 @@ __global__ __launch_bounds__(1024) void k_trsv_fwd_run(const int* __restrict__ l
   for (int t = threadIdx.x; t <= L1 - L0; t += 1024) slv[t] = lvl[L0 + t];
   __syncthreads();
   const int nL = L1 - L0, P0 = slv[0];
-  RowRegs cur, nxt;
-  {
-    const int cnt = slv[1] - slv[0], G = lanes_for(cnt, 32), grp = threadIdx.x / G;
-    fwd_load<T>(nxt, slv[0] + grp, grp < cnt, threadIdx.x - grp * G, G, col, coef, nin, xq, mv, P0);
-  }
-  for (int L = 0; L < nL; ++L) {
+  // rows are loaded two levels ahead (their offsets, then the entries: two
+  // dependent loads)
+  auto load = [&](RowRegs& r, int L) {
+    const int cn = slv[L + 1] - slv[L], Gn = lanes_for(cn, 32), gn = threadIdx.x / Gn;
+    fwd_load<T>(r, slv[L] + gn, gn < cn, threadIdx.x - gn * Gn, Gn, col, coef, nin, xq, mv, P0);
+  };
+  auto step = [&](const RowRegs& cur, int L) {
     const int cnt = slv[L + 1] - slv[L];
     const int G = lanes_for(cnt, 32), grp = threadIdx.x / G, lig = threadIdx.x - grp * G;
-    cur = nxt;
-    if (L + 1 < nL) {
-      const int cn = slv[L + 2] - slv[L + 1], Gn = lanes_for(cn, 32), gn = threadIdx.x / Gn;
-      fwd_load<T>(nxt, slv[L + 1] + gn, gn < cn, threadIdx.x - gn * Gn, Gn, col, coef, nin, xq, mv, P0);
-    }
-    double s = row_sum(cur, zs);
+    double s = row_sum(cur, lig, G, cur.q >= 0 ? min(cur.cnt, mv) : 0, P0, zs);
     for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if (cur.q >= 0 && lig == 0) zs[cur.q - P0] = cur.x + s;
     lds_barrier();
+  };
+  // three register sets in rotation (no copies: a copy would wait for the
+  // loads still in flight)
+  RowRegs R0, R1, R2;
+  load(R0, 0);
+  if (nL > 1) load(R1, 1);
+  for (int L = 0; L < nL; L += 3) {
+    if (L + 2 < nL) load(R2, L + 2);
+    step(R0, L);
+    if (L + 1 >= nL) break;
+    if (L + 3 < nL) load(R0, L + 3);
+    step(R1, L + 1);
+    if (L + 2 >= nL) break;
+    if (L + 4 < nL) load(R1, L + 4);
+    step(R2, L + 2);
   }
   for (int t = threadIdx.x; t < slv[nL] - P0; t += 1024) zq[P0 + t] = zs[t];
 }
@@ -166,61 +188,75 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_pre(int beg, int end, const in
 template <typename T>
 __device__ __forceinline__ void bwd_load(RowRegs& r, int q, bool active, int lig, int G, const int* ptr,
                                          const int* split, const int* col, const T* coef, const double* xq,
-                                         int P0) {
+                                         int P0, int64_t ne) {
   r.q = active ? q : -1;
-  const int e0 = active ? ptr[q] : 0, e1 = active ? split[q] : 0;
+  if (!active) return;
+  const int e0 = ptr[q], e1 = split[q];  // the entry addresses need them: one dependent load
+  r.cnt = e0;
+  r.e1 = e1;
+  r.x = xq[q];
 #pragma unroll
   for (int k = 0; k < kPre; ++k) {
     const int a = e0 + lig + k * G;
-    const bool ok = a < e1;
-    r.c[k] = ok ? col[a] - P0 : -1;
-    r.w[k] = ok ? (double)coef[a] : 0.0;
+    if (a < e1) {
+      r.c[k] = col[a];
+      r.w[k] = (double)coef[a];
+    }
   }
-  r.x = active ? xq[q] : 0.0;
-  r.rem = e0 + lig + kPre * G;
-  r.e1 = e1;
 }
 
 template <typename T>
 __global__ __launch_bounds__(1024) void k_trsv_bwd_run(const int* __restrict__ lvl, int L0, int L1,
                                                        const int* __restrict__ ptr, const int* __restrict__ split,
                                                        const int* __restrict__ col, const T* __restrict__ coef,
-                                                       const double* __restrict__ xq, double* zq) {
+                                                       const double* __restrict__ xq, int64_t ne, double* zq) {
   __shared__ int slv[kTrsvRunLevels + 1];
   __shared__ double zs[kTrsvRunCap];
   for (int t = threadIdx.x; t <= L1 - L0; t += 1024) slv[t] = lvl[L0 + t];
   __syncthreads();
   const int nL = L1 - L0, P0 = slv[0];
-  RowRegs cur, nxt;
-  {
-    const int cnt = slv[1] - slv[0], G = lanes_for(cnt, 64), grp = threadIdx.x / G;
-    bwd_load<T>(nxt, slv[0] + grp, grp < cnt, threadIdx.x - grp * G, G, ptr, split, col, coef, xq, P0);
-  }
-  for (int L = 0; L < nL; ++L) {
+  // rows are loaded two levels ahead (their offsets, then the entries: two
+  // dependent loads)
+  auto load = [&](RowRegs& r, int L) {
+    const int cn = slv[L + 1] - slv[L], Gn = lanes_for(cn, 64), gn = threadIdx.x / Gn;
+    bwd_load<T>(r, slv[L] + gn, gn < cn, threadIdx.x - gn * Gn, Gn, ptr, split, col, coef, xq, P0, ne);
+  };
+  auto step = [&](const RowRegs& cur, int L) {
     const int cnt = slv[L + 1] - slv[L];
     const int G = lanes_for(cnt, 64), grp = threadIdx.x / G, lig = threadIdx.x - grp * G;
-    cur = nxt;
-    if (L + 1 < nL) {
-      const int cn = slv[L + 2] - slv[L + 1], Gn = lanes_for(cn, 64), gn = threadIdx.x / Gn;
-      bwd_load<T>(nxt, slv[L + 1] + gn, gn < cn, threadIdx.x - gn * Gn, Gn, ptr, split, col, coef, xq, P0);
-    }
-    double s = row_sum(cur, zs);
+    const int e0 = cur.q >= 0 ? cur.cnt : 0, e1 = cur.q >= 0 ? cur.e1 : 0;
+    double s = row_sum(cur, lig, G, e1 - e0, P0, zs);
     // in-run parts longer than 8 G entries: the rest, 4 per lane at a time
-    for (int a0 = cur.rem; a0 < cur.e1; a0 += 4 * G) {
+    for (int a0 = e0 + kPre * G + lig; a0 < e1; a0 += 4 * G) {
       int cc[4];
       double ww[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int a = a0 + k * G;
-        cc[k] = a < cur.e1 ? col[a] - P0 : -1;
-        ww[k] = a < cur.e1 ? (double)coef[a] : 0.0;
+        cc[k] = a < e1 ? col[a] : P0;
+        ww[k] = a < e1 ? (double)coef[a] : 0.0;
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) s += ww[k] * (cc[k] >= 0 ? zs[cc[k]] : 0.0);
+      for (int k = 0; k < 4; ++k) s += ww[k] * zs[cc[k] - P0];
     }
     for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if (cur.q >= 0 && lig == 0) zs[cur.q - P0] = cur.x + s;
     lds_barrier();
+  };
+  // three register sets in rotation (no copies: a copy would wait for the
+  // loads still in flight)
+  RowRegs R0, R1, R2;
+  load(R0, 0);
+  if (nL > 1) load(R1, 1);
+  for (int L = 0; L < nL; L += 3) {
+    if (L + 2 < nL) load(R2, L + 2);
+    step(R0, L);
+    if (L + 1 >= nL) break;
+    if (L + 3 < nL) load(R0, L + 3);
+    step(R1, L + 1);
+    if (L + 2 >= nL) break;
+    if (L + 4 < nL) load(R1, L + 4);
+    step(R2, L + 2);
   }
   for (int t = threadIdx.x; t < slv[nL] - P0; t += 1024) zq[P0 + t] = zs[t];
 }
@@ -315,7 +351,7 @@ void launch_trsv_bwd(hipStream_t st, const TriSchedule& s, const T* coef, const 
       hipLaunchKernelGGL((k_trsv_bwd_pre<T>), dim3((unsigned)ceil_div(P1 - P0, 8)), dim3(256), 0, st, P0, P1,
                          s.ptr, s.split, s.col, coef, zq, xq);
       hipLaunchKernelGGL((k_trsv_bwd_run<T>), dim3(1), dim3(1024), 0, st, s.lvl, L, L1, s.ptr, s.split, s.col, coef,
-                         xq, zq);
+                         xq, s.ne, zq);
       L = L1;
       ++r;
       continue;
