@@ -97,37 +97,53 @@ __global__ __launch_bounds__(256) void k_bw(const T* __restrict__ A, const doubl
 // partial[chunk] = sum_{p in chunk} U_p (v_p scale_p)   (m_p-vector per chunk)
 // 8 waves per chunk take every 8th point; lane l owns columns l, l + 64, ...
 // (coalesced row reads); the waves' sums are added in a fixed order.
+template <typename T> struct Vec2L;
+template <> struct Vec2L<double> { typedef d2 type; };
+template <> struct Vec2L<float> { typedef float __attribute__((ext_vector_type(2))) type; };
+
+// partial[chunk][l] = sum over the chunk's points p of U[p][l] v_p (scale_p):
+// 4 waves per workgroup stride through the chunk's points, two rows at a
+// time; lane = two consecutive columns (one 2-wide load), mp <= 1024
 template <typename T>
-__global__ __launch_bounds__(512) void k_utv(const T* __restrict__ U, const double* __restrict__ v,
+__global__ __launch_bounds__(256) void k_utv(const T* __restrict__ U, const double* __restrict__ v,
                                              const double* __restrict__ scale, int64_t n, int mp, int chunk,
                                              double* __restrict__ partial) {
-  __shared__ double red[8][1024];
+  typedef typename Vec2L<T>::type T2;
+  __shared__ double red[4][1024];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t pbeg = (int64_t)blockIdx.x * chunk;
   const int64_t pend = min(n, pbeg + chunk);
+  const int nc = (mp + 127) / 128;  // 128-column steps
   double acc[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) acc[c] = 0.0;
   for (int64_t p = pbeg + w; p < pend; p += 8) {
-    const double vv = scale ? v[p] * scale[p] : v[p];
-    const T* row = U + (size_t)p * mp;
+    const bool two = p + 4 < pend;
+    const double v0 = scale ? v[p] * scale[p] : v[p];
+    const double v1 = two ? (scale ? v[p + 4] * scale[p + 4] : v[p + 4]) : 0.0;
+    const T* r0 = U + (size_t)p * mp;
+    const T* r1 = U + (size_t)(two ? p + 4 : p) * mp;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const int l = lane + 64 * c;
-      if (l < mp) acc[c] += (double)row[l] * vv;
+    for (int c = 0; c < 8; ++c) {
+      const int l = 2 * lane + 128 * c;
+      if (c < nc && l < mp) {
+        const T2 a = *reinterpret_cast<const T2*>(r0 + l), b = *reinterpret_cast<const T2*>(r1 + l);
+        acc[2 * c] += (double)a[0] * v0 + (double)b[0] * v1;
+        acc[2 * c + 1] += (double)a[1] * v0 + (double)b[1] * v1;
+      }
     }
   }
 #pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const int l = lane + 64 * c;
-    if (l < mp) red[w][l] = acc[c];
+  for (int c = 0; c < 8; ++c) {
+    const int l = 2 * lane + 128 * c;
+    if (c < nc && l < mp) {
+      red[w][l] = acc[2 * c];
+      red[w][l + 1] = acc[2 * c + 1];
+    }
   }
   __syncthreads();
-  for (int l = threadIdx.x; l < mp; l += 512) {
-    double s = 0.0;
-    for (int k = 0; k < 8; ++k) s += red[k][l];
-    partial[(size_t)blockIdx.x * mp + l] = s;
-  }
+  for (int l = threadIdx.x; l < mp; l += 256)
+    partial[(size_t)blockIdx.x * mp + l] = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
 }
 
 // cbuf[l] = sum_chunks partial[chunk][l]: 64 columns per workgroup, the 4
@@ -159,17 +175,58 @@ __global__ __launch_bounds__(256) void k_symv(const double* __restrict__ Minv, c
 }
 
 // out_i = (t_i - U_i . c) * f_i   (one wave per point), f = D^{-1/2}
+// U_i . c for the four points i0..i0+3 of a wave (rows past n read row n-1
+// and are not used): lane = two consecutive columns per 128-column step,
+// c held in registers, the four wave sums interleaved
+template <typename T>
+__device__ __forceinline__ void dot4_rows(const T* __restrict__ U, const double* __restrict__ c, int64_t i0,
+                                          int64_t n, int mp, double (&s)[4]) {
+  typedef typename Vec2L<T>::type T2;
+  const int lane = threadIdx.x & 63, nc = (mp + 127) / 128;
+  double cr[16];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int l = 2 * lane + 128 * k;
+    const bool ok = k < nc && l < mp;
+    cr[2 * k] = ok ? c[l] : 0.0;
+    cr[2 * k + 1] = ok ? c[l + 1] : 0.0;
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const T* row = U + (size_t)min(i0 + p, n - 1) * mp;
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int l = 2 * lane + 128 * k;
+      if (k < nc && l < mp) {
+        const T2 u = *reinterpret_cast<const T2*>(row + l);
+        a += (double)u[0] * cr[2 * k] + (double)u[1] * cr[2 * k + 1];
+      }
+    }
+    s[p] = a;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) s[p] += __shfl_xor(s[p], o, 64);
+}
+
+// out_i = (t_i - U_i . c) * f_i, f = D^{-1/2} (D = NULL: no scaling); four
+// points per wave
 template <typename T>
 __global__ __launch_bounds__(256) void k_t_minus_uc(const T* __restrict__ U, const double* __restrict__ c,
                                                     const double* __restrict__ t, const double* __restrict__ D,
                                                     int64_t n, int mp, double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n) return;
-  double s = 0.0;
-  for (int l = lane; l < mp; l += 64) s += (double)U[(size_t)i * mp + l] * c[l];
-  s = wave_sum(s);
-  if (lane == 0) out[i] = D ? (t[i] - s) / sqrt(D[i]) : t[i] - s;  // D = NULL: no scaling
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
+  if (i0 >= n) return;
+  double s[4];
+  dot4_rows<T>(U, c, i0, n, mp, s);
+  if (lane < 4 && i0 + lane < n) {
+    const int64_t i = i0 + lane;
+    const double sv = lane == 0 ? s[0] : lane == 1 ? s[1] : lane == 2 ? s[2] : s[3];
+    out[i] = D ? (t[i] - sv) / sqrt(D[i]) : t[i] - sv;
+  }
 }
 
 // out_j = W_j p_j + s_j - sum_{(q,slot): N(q)_slot = j} A_{q,slot} s_q   (W may be null)
@@ -263,18 +320,22 @@ __global__ void k_scale_e(const double* __restrict__ v, const double* __restrict
 }
 
 // out_i = q_i + E_i D_i^{-1/2} U_i . c   (one wave per point)
+// out_i = q_i + E_i (U_i . c) / sqrt(D_i), four points per wave
 template <typename T>
 __global__ __launch_bounds__(256) void k_q_plus_euc(const T* __restrict__ U, const double* __restrict__ c,
                                                     const double* __restrict__ q, const double* __restrict__ E,
                                                     const double* __restrict__ D, int64_t n, int mp,
                                                     double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n) return;
-  double s = 0.0;
-  for (int l = lane; l < mp; l += 64) s += (double)U[(size_t)i * mp + l] * c[l];
-  s = wave_sum(s);
-  if (lane == 0) out[i] = q[i] + E[i] * s / sqrt(D[i]);
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
+  if (i0 >= n) return;
+  double s[4];
+  dot4_rows<T>(U, c, i0, n, mp, s);
+  if (lane < 4 && i0 + lane < n) {
+    const int64_t i = i0 + lane;
+    const double sv = lane == 0 ? s[0] : lane == 1 ? s[1] : lane == 2 ? s[2] : s[3];
+    out[i] = q[i] + E[i] * sv / sqrt(D[i]);
+  }
 }
 
 // Weighted Gram partial: sum_p (sw_p U_p)(sw_p U_p)^T over a chunk, lower 64x64 blocks
@@ -394,7 +455,7 @@ void launch_bw(hipStream_t st, const T* A, const double* D, const int32_t* nbr, 
 template <typename T>
 void launch_utv(hipStream_t st, const T* U, const double* v, const double* scale, int64_t n, int mp, int chunk,
                 double* partial) {
-  hipLaunchKernelGGL((k_utv<T>), dim3((unsigned)ceil_div(n, chunk)), dim3(512), 0, st, U, v, scale, n, mp, chunk,
+  hipLaunchKernelGGL((k_utv<T>), dim3((unsigned)ceil_div(n, chunk)), dim3(256), 0, st, U, v, scale, n, mp, chunk,
                      partial);
 }
 void launch_colreduce(hipStream_t st, const double* partial, int nchunk, int mp, double* out) {
@@ -408,7 +469,7 @@ void launch_reduce_apply(hipStream_t st, const double* partial, int nchunk, int 
 template <typename T>
 void launch_t_minus_uc(hipStream_t st, const T* U, const double* c, const double* t, const double* D, int64_t n,
                        int mp, double* out) {
-  hipLaunchKernelGGL((k_t_minus_uc<T>), g1(n, 4), dim3(256), 0, st, U, c, t, D, n, mp, out);
+  hipLaunchKernelGGL((k_t_minus_uc<T>), g1(n, 16), dim3(256), 0, st, U, c, t, D, n, mp, out);
 }
 template <typename T>
 void launch_btw(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s, const double* W,
@@ -440,7 +501,7 @@ void launch_scale_e(hipStream_t st, const double* v, const double* E, const doub
 template <typename T>
 void launch_q_plus_euc(hipStream_t st, const T* U, const double* c, const double* q, const double* E,
                        const double* D, int64_t n, int mp, double* out) {
-  hipLaunchKernelGGL((k_q_plus_euc<T>), g1(n, 4), dim3(256), 0, st, U, c, q, E, D, n, mp, out);
+  hipLaunchKernelGGL((k_q_plus_euc<T>), g1(n, 16), dim3(256), 0, st, U, c, q, E, D, n, mp, out);
 }
 template <typename T>
 void launch_wgram_partial(hipStream_t st, const T* U, const double* sw, int64_t n, int mp, int chunk, double* partial,
