@@ -661,7 +661,7 @@ static vif_status nll_grad_impl(vif_ctx* c, const double* y) {
     stage_begin(c, ST_SGRAD);
     int nchunk = 0;
     launch_cross3_partial<T>(c->st, V, (const T*)c->Q1, U, (const T*)c->Gs, (const T*)c->Bs, g.n, mp, c->chunk,
-                             c->partial, &nchunk);
+                             c->partial, &nchunk, true);
     launch_reduce_sym(c->st, c->partial, nchunk, mp, c->Smat);
     launch_gemm_sq(c->st, c->Smat, c->Linv, c->tmpm, mp, false, false);
     launch_gemm_sq(c->st, c->Linv, c->tmpm, c->Tm, mp, true, false);

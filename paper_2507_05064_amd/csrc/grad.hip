@@ -10,8 +10,14 @@
 // NLL is invariant to V -> Q V for orthogonal Q),
 //   d/dtheta += sum_i Vbar_i . (L_m^{-1} dK(Z,x_i)/dtheta)
 //             - 1/2 tr(L_m^{-T} Sm_bar L_m^{-1} dSigma_m/dtheta).
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
+
+template <typename T> struct Vec4G2;
+template <> struct Vec4G2<double> { typedef d2 type; };
+template <> struct Vec4G2<float> { typedef f4 type; };
 
 
 // C = op(A) op(B) for mp x mp FP64 matrices (op = transpose if flag set).
@@ -196,6 +202,106 @@ __global__ __launch_bounds__(256) void k_cross3_partial(const T* __restrict__ V,
           out[(size_t)(L0 + 16 * x + acc_row<T>(lane, v)) * mp + C0 + 16 * yy + r] = (double)acc[x][yy][v];
 }
 
+// The same partials with one workgroup per point chunk computing every lower
+// 16 x 16 tile (m_p <= 256): the chunk's rows of V, Q1, U, Gs, Bs pass
+// through LDS in slices of 8 points (coalesced 16-byte loads, the next slice
+// prefetched into registers while the MFMAs run on the current one), and the
+// 8 waves take the tiles in turn, each tile a 16 x 16 x 4 MFMA triple per 4
+// points. Each input row is read from memory once per chunk.
+constexpr int kC3Slice = 8, kC3Pitch = 256 + 16;
+// largest m_p per form: the FP64 accumulators (8 registers per tile) limit a
+// wave to 12 tiles, i.e. 91 tiles over the 8 waves
+template <typename T> struct C3Max;
+template <> struct C3Max<float> { static constexpr int value = 256; };
+template <> struct C3Max<double> { static constexpr int value = 208; };
+template <typename T>
+__global__ __launch_bounds__(512) void k_cross3_tiles(const T* __restrict__ V, const T* __restrict__ Q1,
+                                                      const T* __restrict__ U, const T* __restrict__ Gs,
+                                                      const T* __restrict__ Bs, int64_t n, int mp, int chunk,
+                                                      double* __restrict__ partial) {
+  typedef typename Acc4<T>::type A4;
+  typedef typename Vec4G2<T>::type TV;  // 16 bytes
+  constexpr int VW = 16 / sizeof(T);
+  constexpr int kMax = C3Max<T>::value;
+  constexpr int kMaxTiles = ((kMax / 16) * (kMax / 16 + 1) / 2 + 7) / 8;  // per wave
+  __shared__ __align__(16) T sl[5][kC3Slice][kC3Pitch];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: tile indices in scalar registers
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk, pend = min(n, pbeg + chunk);
+  const int nt = mp / 16, ntile = nt * (nt + 1) / 2;
+  const int rowv = mp / VW;                      // 16-byte vectors per row
+  const int nvec = 5 * kC3Slice * rowv;          // per slice
+  const T* src[5] = {V, Q1, U, Gs, Bs};
+  constexpr int kPerThread = (5 * kC3Slice * (kMax / VW) + 511) / 512;
+  TV pre[kPerThread];
+  auto fetch = [&](int64_t p0) {
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int e = tid + 512 * t;
+      TV v = {};
+      if (e < nvec) {
+        const int a = e / (kC3Slice * rowv), rem = e - a * kC3Slice * rowv;
+        const int pp = rem / rowv, c4 = rem - pp * rowv;
+        const int64_t p = p0 + pp;
+        if (p < pend) v = *reinterpret_cast<const TV*>(src[a] + (size_t)p * mp + c4 * VW);
+      }
+      pre[t] = v;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int e = tid + 512 * t;
+      if (e < nvec) {
+        const int a = e / (kC3Slice * rowv), rem = e - a * kC3Slice * rowv;
+        const int pp = rem / rowv, c4 = rem - pp * rowv;
+        *reinterpret_cast<TV*>(&sl[a][pp][c4 * VW]) = pre[t];
+      }
+    }
+  };
+  A4 acc[kMaxTiles];
+  int tr[kMaxTiles], tc[kMaxTiles];
+#pragma unroll
+  for (int k = 0; k < kMaxTiles; ++k) {
+    acc[k] = A4{0, 0, 0, 0};
+    const int t = w + 8 * k;
+    int ti = 0, rem = t < ntile ? t : 0;
+    while (rem > ti) { rem -= ti + 1; ++ti; }
+    tr[k] = ti * 16;
+    tc[k] = rem * 16;
+  }
+  fetch(pbeg);
+  for (int64_t p0 = pbeg; p0 < pend; p0 += kC3Slice) {
+    __syncthreads();  // the previous slice is no longer read
+    stash();
+    __syncthreads();
+    if (p0 + kC3Slice < pend) fetch(p0 + kC3Slice);
+#pragma unroll
+    for (int k0 = 0; k0 < kC3Slice; k0 += 4) {
+#pragma unroll
+      for (int k = 0; k < kMaxTiles; ++k) {
+        if (w + 8 * k < ntile) {
+          const int kk = k0 + g;
+          const T a1 = sl[0][kk][tr[k] + r], b1 = sl[1][kk][tc[k] + r];
+          const T a2 = -sl[2][kk][tr[k] + r], b2 = sl[3][kk][tc[k] + r];
+          const T a3 = -sl[4][kk][tr[k] + r], b3 = sl[2][kk][tc[k] + r];
+          acc[k] = mfma16(a1, b1, acc[k]);
+          acc[k] = mfma16(a2, b2, acc[k]);
+          acc[k] = mfma16(a3, b3, acc[k]);
+        }
+      }
+    }
+  }
+  double* out = partial + (size_t)blockIdx.x * mp * mp;
+#pragma unroll
+  for (int k = 0; k < kMaxTiles; ++k)
+    if (w + 8 * k < ntile)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        out[(size_t)(tr[k] + acc_row<T>(lane, v)) * mp + tc[k] + r] = (double)acc[k][v];
+}
+
 // out = sum of the partials' lower triangles, mirrored to a full symmetric matrix
 __global__ void k_reduce_sym(const double* __restrict__ partial, int nchunk, int mp, double* __restrict__ out,
                              Batch bt) {
@@ -370,7 +476,16 @@ void launch_ubar(hipStream_t st, const T* U, const T* Minv, const double* e, con
 }
 template <typename T>
 void launch_cross3_partial(hipStream_t st, const T* V, const T* Q1, const T* U, const T* Gs, const T* Bs, int64_t n,
-                           int mp, int chunk, double* partial, int* nchunk_out) {
+                           int mp, int chunk, double* partial, int* nchunk_out, bool tiles) {
+  if (tiles && mp <= C3Max<T>::value) {
+    // one workgroup per chunk, at most 256 chunks (one per CU), chunk a multiple of the slice and >= the given one
+    int64_t ch = std::max<int64_t>(chunk, ceil_div(n, 256));
+    ch = ceil_div(ch, kC3Slice) * kC3Slice;
+    const int nch = (int)ceil_div(n, ch);
+    hipLaunchKernelGGL((k_cross3_tiles<T>), dim3(nch), dim3(512), 0, st, V, Q1, U, Gs, Bs, n, mp, (int)ch, partial);
+    *nchunk_out = nch;
+    return;
+  }
   const int nchunk = (int)ceil_div(n, chunk);
   const int nb = (mp + 63) / 64;
   const int nblk = nb * (nb + 1) / 2;
@@ -421,6 +536,6 @@ template void launch_ubar<double>(hipStream_t, const double*, const double*, con
 template void launch_ubar<float>(hipStream_t, const float*, const float*, const double*, const double*, int64_t, int,
                                  float*, Batch);
 template void launch_cross3_partial<double>(hipStream_t, const double*, const double*, const double*, const double*,
-                                            const double*, int64_t, int, int, double*, int*);
+                                            const double*, int64_t, int, int, double*, int*, bool);
 template void launch_cross3_partial<float>(hipStream_t, const float*, const float*, const float*, const float*,
-                                           const float*, int64_t, int, int, double*, int*);
+                                           const float*, int64_t, int, int, double*, int*, bool);

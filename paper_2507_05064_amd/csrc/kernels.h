@@ -71,7 +71,7 @@ void launch_ubar(hipStream_t st, const T* U, const T* Minv, const double* e, con
                  T* Ubar, Batch bt = Batch{nullptr, nullptr});
 template <typename T>
 void launch_cross3_partial(hipStream_t st, const T* V, const T* Q1, const T* U, const T* Gs, const T* Bs, int64_t n,
-                           int mp, int chunk, double* partial, int* nchunk_out);
+                           int mp, int chunk, double* partial, int* nchunk_out, bool tiles = false);
 void launch_reduce_sym(hipStream_t st, const double* partial, int nchunk, int mp, double* out,
                        Batch bt = Batch{nullptr, nullptr}, int nprob = 1);
 void launch_sigma_m_grad(hipStream_t st, const double* Tm, const double* Z, int m, int mp, const CovParams& p,
