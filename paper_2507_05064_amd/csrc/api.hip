@@ -529,9 +529,9 @@ vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const 
     int nchunk = 0;
     stage_begin(c, ST_GRAM);
     if (f32)
-      launch_gram_partial<float>(c->st, (const float*)c->U, g.n, c->mp, c->chunk, c->partial, &nchunk);
+      launch_gram_partial<float>(c->st, (const float*)c->U, g.n, c->mp, c->chunk, c->partial, &nchunk, true);
     else
-      launch_gram_partial<double>(c->st, (const double*)c->U, g.n, c->mp, c->chunk, c->partial, &nchunk);
+      launch_gram_partial<double>(c->st, (const double*)c->U, g.n, c->mp, c->chunk, c->partial, &nchunk, true);
     launch_reduce_gram(c->st, c->partial, nchunk, c->mp, c->Mp);
     stage_end(c, ST_GRAM);
     stage_begin(c, ST_MCHOL);

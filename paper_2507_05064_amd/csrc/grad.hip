@@ -87,18 +87,21 @@ __global__ __launch_bounds__(256) void k_resid(const T* __restrict__ U, const do
 }
 
 // Ubar = U Minv - e w^T: a 64-point x 64-column tile per workgroup, one wave
-// per 16 points, MFMA 16x16x4 over the mp-long inner dimension.
+// per 16 points, MFMA 16x16x4 over the mp-long inner dimension. The
+// workgroup stages 64 x 64 blocks of Minv in LDS (read once per workgroup,
+// not once per wave); loads are unconditional at clamped addresses.
 template <typename T>
 __global__ __launch_bounds__(256) void k_ubar(const T* __restrict__ U, const T* __restrict__ Minv,
                                               const double* __restrict__ e, const double* __restrict__ w, int64_t n,
                                               int mp, T* __restrict__ Ubar, Batch bt) {
   typedef typename Acc4<T>::type A4;
+  __shared__ T Ms[64][80];  // Minv[kc + kk][c0 + cc]; pitch 80 spreads the MFMA reads over the banks
   if (bt.bp) {  // the 64-point tile lies in one problem
     const int b = bt.blk2prob[((int64_t)blockIdx.x * 64) / kBatchBlock];
     Minv += (size_t)b * mp * mp;
     w += (size_t)b * mp;
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = lane & 15, g = lane >> 4;
   const int64_t p0 = (int64_t)blockIdx.x * 64 + 16 * wv;
   const int c0 = blockIdx.y * 64;
@@ -109,13 +112,24 @@ __global__ __launch_bounds__(256) void k_ubar(const T* __restrict__ U, const T* 
   A4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = A4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < mp; k0 += 4) {
-    const T av = urow[k0 + g];  // unconditional (clamped row), so loads are not serialised
-    const T a = pok ? av : T(0);
-    const T* mrow = Minv + (size_t)(k0 + g) * mp + c0 + r;
+  for (int kc = 0; kc < mp; kc += 64) {
+    __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (t < ntile) acc[t] = mfma16(a, mrow[16 * t], acc[t]);
+    for (int q = 0; q < 16; ++q) {
+      const int el = tid + 256 * q, kk = el >> 6, cc = el & 63;
+      const bool ok = kc + kk < mp && c0 + cc < mp;
+      const T v = Minv[(size_t)min(kc + kk, mp - 1) * mp + min(c0 + cc, mp - 1)];
+      Ms[kk][cc] = ok ? v : T(0);
+    }
+    __syncthreads();
+    const int kend = min(64, mp - kc);
+    for (int k0 = 0; k0 < kend; k0 += 4) {
+      const T av = urow[kc + k0 + g];
+      const T a = pok ? av : T(0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < ntile) acc[t] = mfma16(a, Ms[k0 + g][16 * t + r], acc[t]);
+    }
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {

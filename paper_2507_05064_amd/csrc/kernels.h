@@ -43,7 +43,8 @@ void launch_ytilde(hipStream_t st, const T* A, const double* D, const int32_t* n
 
 // reduce.hip
 template <typename T>
-void launch_gram_partial(hipStream_t st, const T* U, int64_t n, int mp, int chunk, double* partial, int* nchunk_out);
+void launch_gram_partial(hipStream_t st, const T* U, int64_t n, int mp, int chunk, double* partial, int* nchunk_out,
+                         bool tiles = false);
 template <typename T>
 void launch_uty_partial(hipStream_t st, const T* U, const double* yt, const double* D, int64_t n, int mp, int chunk,
                         double* partial);

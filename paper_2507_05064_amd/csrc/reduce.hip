@@ -2,12 +2,17 @@
 // M' = I + U^T U (the whitened eq. def_M), U^T yt, sum_i log D_i, yt^T yt.
 // Split over point chunks; each chunk writes an FP64 partial, a second pass
 // adds the partials in a fixed order (run-to-run reproducible, no atomics).
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
 template <typename T> struct Vec4T;
 template <> struct Vec4T<double> { typedef d4 type; };
 template <> struct Vec4T<float> { typedef f4 type; };
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { typedef d2 type; };
+template <> struct Vec16<float> { typedef f4 type; };
 
 // Partial U^T U of one point chunk for one 64 x 64 block of the lower
 // triangle. Each wave: a 32 x 32 sub-block (2 x 2 MFMA tiles), K = points.
@@ -61,6 +66,80 @@ __global__ __launch_bounds__(256) void k_gram_partial(const T* __restrict__ U, i
 #pragma unroll
         for (int v = 0; v < 4; ++v)
           out[(size_t)(L0 + 16 * x + acc_row<T>(lane, v)) * mp + C0 + 16 * y + r] = (double)acc[x][y][v];
+}
+
+// The same partial with one workgroup per point chunk computing every lower
+// 16 x 16 tile (m_p <= 256): the chunk's U rows pass through LDS in slices
+// of 16 points (coalesced 16-byte loads, the next slice prefetched into
+// registers while the MFMAs run), the 8 waves take the tiles in turn. Each
+// row is read once per chunk.
+constexpr int kGSlice = 16, kGMax = 256, kGPitch = kGMax + 16;
+template <typename T>
+__global__ __launch_bounds__(512) void k_gram_tiles(const T* __restrict__ U, int64_t n, int mp, int chunk,
+                                                    double* __restrict__ partial) {
+  typedef typename Acc4<T>::type A4;
+  typedef typename Vec16<T>::type TV;
+  constexpr int VW = 16 / sizeof(T);
+  constexpr int kMaxTiles = ((kGMax / 16) * (kGMax / 16 + 1) / 2 + 7) / 8;  // per wave
+  constexpr int kPerThread = (kGSlice * (kGMax / VW) + 511) / 512;
+  __shared__ __align__(16) T sl[kGSlice][kGPitch];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk, pend = min(n, pbeg + chunk);
+  const int nt = mp / 16, ntile = nt * (nt + 1) / 2;
+  const int rowv = mp / VW, nvec = kGSlice * rowv;
+  TV pre[kPerThread];
+  auto fetch = [&](int64_t p0) {
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int e = tid + 512 * t;
+      TV v = {};
+      if (e < nvec) {
+        const int pp = e / rowv, c4 = e - pp * rowv;
+        if (p0 + pp < pend) v = *reinterpret_cast<const TV*>(U + (size_t)(p0 + pp) * mp + c4 * VW);
+      }
+      pre[t] = v;
+    }
+  };
+  A4 acc[kMaxTiles];
+  int tr[kMaxTiles], tc[kMaxTiles];
+#pragma unroll
+  for (int k = 0; k < kMaxTiles; ++k) {
+    acc[k] = A4{0, 0, 0, 0};
+    const int t = w + 8 * k;
+    int ti = 0, rem = t < ntile ? t : 0;
+    while (rem > ti) { rem -= ti + 1; ++ti; }
+    tr[k] = ti * 16;
+    tc[k] = rem * 16;
+  }
+  fetch(pbeg);
+  for (int64_t p0 = pbeg; p0 < pend; p0 += kGSlice) {
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int e = tid + 512 * t;
+      if (e < nvec) {
+        const int pp = e / rowv, c4 = e - pp * rowv;
+        *reinterpret_cast<TV*>(&sl[pp][c4 * VW]) = pre[t];
+      }
+    }
+    __syncthreads();
+    if (p0 + kGSlice < pend) fetch(p0 + kGSlice);
+#pragma unroll
+    for (int k0 = 0; k0 < kGSlice; k0 += 4) {
+#pragma unroll
+      for (int k = 0; k < kMaxTiles; ++k)
+        if (w + 8 * k < ntile) acc[k] = mfma16(sl[k0 + g][tr[k] + r], sl[k0 + g][tc[k] + r], acc[k]);
+    }
+  }
+  double* out = partial + (size_t)blockIdx.x * mp * mp;
+#pragma unroll
+  for (int k = 0; k < kMaxTiles; ++k)
+    if (w + 8 * k < ntile)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        out[(size_t)(tr[k] + acc_row<T>(lane, v)) * mp + tc[k] + r] = (double)acc[k][v];
 }
 
 // Per chunk: U^T yt (mp values), sum log D, sum yt^2 -> partial[chunk][mp + 2].
@@ -129,7 +208,19 @@ __global__ void k_vec_reduce(const double* __restrict__ partial, int nchunk, int
 }
 
 template <typename T>
-void launch_gram_partial(hipStream_t st, const T* U, int64_t n, int mp, int chunk, double* partial, int* nchunk_out) {
+void launch_gram_partial(hipStream_t st, const T* U, int64_t n, int mp, int chunk, double* partial, int* nchunk_out,
+                         bool tiles) {
+  // FP64 only: in the FP32 form the small-workgroup kernel below interleaves
+  // better with the derivative whitening that runs on the second stream
+  if (tiles && sizeof(T) == 8 && mp <= kGMax) {
+    // one workgroup per chunk, at most 256 chunks, chunk a multiple of the slice and >= the given one
+    int64_t ch = std::max<int64_t>(chunk, ceil_div(n, 256));
+    ch = ceil_div(ch, kGSlice) * kGSlice;
+    const int nch = (int)ceil_div(n, ch);
+    hipLaunchKernelGGL((k_gram_tiles<T>), dim3(nch), dim3(512), 0, st, U, n, mp, (int)ch, partial);
+    *nchunk_out = nch;
+    return;
+  }
   const int nchunk = (int)ceil_div(n, chunk);
   const int nb = (mp + 63) / 64;
   dim3 grid(nchunk, nb * (nb + 1) / 2);
@@ -149,8 +240,8 @@ void launch_vec_reduce(hipStream_t st, const double* partial, int nchunk, int le
                      out, bt);
 }
 
-template void launch_gram_partial<double>(hipStream_t, const double*, int64_t, int, int, double*, int*);
-template void launch_gram_partial<float>(hipStream_t, const float*, int64_t, int, int, double*, int*);
+template void launch_gram_partial<double>(hipStream_t, const double*, int64_t, int, int, double*, int*, bool);
+template void launch_gram_partial<float>(hipStream_t, const float*, int64_t, int, int, double*, int*, bool);
 template void launch_uty_partial<double>(hipStream_t, const double*, const double*, const double*, int64_t, int, int,
                                          double*);
 template void launch_uty_partial<float>(hipStream_t, const float*, const double*, const double*, int64_t, int, int,
