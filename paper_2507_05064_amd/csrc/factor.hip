@@ -65,14 +65,15 @@ struct PointShared {
   // Gram of the gathered rows; after the rows of C are in registers, the
   // rows of the Cholesky factor L (row k = the point itself)
   T GL[32][33];
-  double xs[32][VIF_MAX_D];  // coordinates of the rows
   T As[32];                  // A_i
   int nbs[32];               // row -> point index (N(i) then i)
 };
 
 // Steps 1-3 for point i, shared by the forward and the adjoint kernels.
 // On return (true): k = |N(i)|, D = D_i, Lrow = row `lane` of L (lanes
-// 0..k), sh.GL = L, sh.As = A_i, sh.nbs / sh.xs = row points / coordinates.
+// 0..k), sh.GL = L, sh.As = A_i, sh.nbs = row points and xs (LDS, 32 x d,
+// sized at launch so that a point's LDS block fits its dimension) = their
+// coordinates.
 // With `extra` set, the m-vector extra * extra_scale joins the Gram as row
 // k + 1 (needs k + 2 <= 32): sh.GL[k + 1][j] then holds its dot products
 // with the rows j <= k (row k + 1 is not touched by the Cholesky).
@@ -80,7 +81,7 @@ struct PointShared {
 template <typename T, int NBLK>
 __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const T* __restrict__ V,
                                              const int32_t* __restrict__ nbr, int64_t i, int mp, int mv,
-                                             const CovParams& p, PointShared<T>& sh, T (&Lrow)[32], int& k_out,
+                                             const CovParams& p, PointShared<T>& sh, double* xs, T (&Lrow)[32], int& k_out,
                                              T& D_out, int* status, const T* extra = nullptr,
                                              T extra_scale = T(1), const T* own_v = nullptr,
                                              const double* own_x = nullptr, const int32_t* own_nbr = nullptr) {
@@ -97,8 +98,8 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
   const bool own = own_v != nullptr && lane == k;
   if (lane < 32) {
     sh.nbs[lane] = rowpt;
-    for (int dd = 0; dd < VIF_MAX_D; ++dd)
-      sh.xs[lane][dd] = (rowpt >= 0 && dd < p.d) ? (own ? own_x[dd] : X[(int64_t)rowpt * p.d + dd]) : 0.0;
+    for (int dd = 0; dd < p.d; ++dd)
+      xs[lane * p.d + dd] = rowpt >= 0 ? (own ? own_x[dd] : X[(int64_t)rowpt * p.d + dd]) : 0.0;
   }
 
   // 1. Gram of the gathered rows
@@ -155,7 +156,7 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
     while (a * (a + 1) / 2 > e) --a;
     const int b = e - a * (a + 1) / 2;
     const T kv = (a == b) ? T(p.sigma1_sq + p.s2)
-                          : T(p.sigma1_sq) * cov_profile<T>(p.kernel, scaled_sqdist<T>(p, sh.xs[a], sh.xs[b]));
+                          : T(p.sigma1_sq) * cov_profile<T>(p.kernel, scaled_sqdist<T>(p, xs + a * p.d, xs + b * p.d));
     sh.GL[a][b] = kv - sh.GL[a][b];
   }
   __syncthreads();
@@ -219,6 +220,7 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
                                                T* __restrict__ U, int* status, Batch bt,
                                                const int* __restrict__ perm) {
   __shared__ PointShared<T> sh;
+  extern __shared__ double xs[];  // 32 x d coordinates (dynamic)
   T Lrow[32];
   int k;
   T D;
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
     }
     p = q.cp;
   }
-  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, Lrow, k, D, status)) {
+  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, xs, Lrow, k, D, status)) {
     if (lane == 0) Dout[i] = __builtin_nan("");
     return;
   }
@@ -284,6 +286,7 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
                                                    T* __restrict__ Gs, T* __restrict__ Bs, double* __restrict__ tpart,
                                                    int* status, Batch bt, const int* __restrict__ perm) {
   __shared__ PointShared<T> sh;
+  extern __shared__ double xs[];  // 32 x d coordinates (dynamic)
   __shared__ T rho_s[32];
   T Lrow[32];
   int k;
@@ -307,7 +310,7 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
     p = q.cp;
   }
   const T rsd = T(1) / sqrt(T(Dfwd[i]));
-  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, Lrow, k, D, status, Ubar + (size_t)i * mp, rsd)) {
+  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, xs, Lrow, k, D, status, Ubar + (size_t)i * mp, rsd)) {
     if (lane == 0) tpart[i * 3] = tpart[i * 3 + 1] = tpart[i * 3 + 2] = __builtin_nan("");
     return;
   }
@@ -363,7 +366,7 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
         if (a < k) ts -= rho_s[a] * sh.As[a];
         continue;
       }
-      const T t2 = scaled_sqdist<T>(p, sh.xs[a], sh.xs[b]);
+      const T t2 = scaled_sqdist<T>(p, xs + a * p.d, xs + b * p.d);
       const T pv = cov_profile<T>(p.kernel, t2);
       const T dv = T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2, T(p.inv_ls[0]));
       // a == k: the r_i entry of row b; else the pair (a, b) of R_i, both orders
@@ -436,6 +439,7 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
   typedef typename Vec4<T>::type T4;
   typedef typename Acc4<T>::type A4;
   __shared__ PointShared<T> sh;
+  extern __shared__ double xs[];  // 32 x d coordinates (dynamic)
   __shared__ T Xc[32][33];  // cross Gram dV_a . V_b
   __shared__ T dAs[32];
   T Lrow[32];
@@ -444,7 +448,7 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
   const int lane = threadIdx.x;
   const int myrow = lane & 31;
   const int64_t i = perm ? (int64_t)perm[blockIdx.x] : (int64_t)blockIdx.x;
-  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, Lrow, k, D, status)) {
+  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, xs, Lrow, k, D, status)) {
     if (lane == 0) dD[i] = __builtin_nan("");
     return;
   }
@@ -506,7 +510,7 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
       } else if (a == b) {
         dk = (which == 0) ? T(1) : T(0);
       } else {
-        const T t2 = scaled_sqdist<T>(p, sh.xs[a], sh.xs[b]);
+        const T t2 = scaled_sqdist<T>(p, xs + a * p.d, xs + b * p.d);
         dk = (which == 0) ? cov_profile<T>(p.kernel, t2)
                           : T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2, T(p.inv_ls[0]));
       }
@@ -584,10 +588,10 @@ void launch_factor_jvp(hipStream_t st, const double* X, const T* V, const T* dV,
                        int64_t n, int mp, int mv, const CovParams& p, int which, T* dA, double* dD, T* dU,
                        int* status, const int* perm) {
   if (mv + 1 <= 16)
-    hipLaunchKernelGGL((k_factor_jvp<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, dV, nbr, U, n, mp, mv, p,
+    hipLaunchKernelGGL((k_factor_jvp<T, 1>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, dV, nbr, U, n, mp, mv, p,
                        which, dA, dD, dU, status, perm);
   else
-    hipLaunchKernelGGL((k_factor_jvp<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, dV, nbr, U, n, mp, mv, p,
+    hipLaunchKernelGGL((k_factor_jvp<T, 2>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, dV, nbr, U, n, mp, mv, p,
                        which, dA, dD, dU, status, perm);
 }
 template void launch_factor_jvp<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
@@ -607,12 +611,13 @@ __global__ __launch_bounds__(64) void k_pred_factor(const double* __restrict__ X
                                                     CovParams p, T* __restrict__ Ap, double* __restrict__ Dp,
                                                     int* status) {
   __shared__ PointShared<T> sh;
+  extern __shared__ double xs[];  // 32 x d coordinates (dynamic)
   T Lrow[32];
   int k;
   T D;
   const int lane = threadIdx.x;
   const int64_t j = blockIdx.x;
-  if (!factor_point<T, NBLK>(X, V, nullptr, n, mp, mv, p, sh, Lrow, k, D, status, nullptr, T(1),
+  if (!factor_point<T, NBLK>(X, V, nullptr, n, mp, mv, p, sh, xs, Lrow, k, D, status, nullptr, T(1),
                              Vp + (size_t)j * mp, Xp + (size_t)j * p.d, nbrp + (size_t)j * mv)) {
     if (lane == 0) Dp[j] = __builtin_nan("");
     return;
@@ -645,10 +650,10 @@ void launch_pred_factor(hipStream_t st, const double* X, const T* V, const doubl
                         const int32_t* nbrp, int64_t n, int64_t np_, int mp, int mv, const CovParams& p, T* Ap,
                         double* Dp, int* status) {
   if (mv + 1 <= 16)
-    hipLaunchKernelGGL((k_pred_factor<T, 1>), dim3((unsigned)np_), dim3(64), 0, st, X, V, Xp, Vp, nbrp, n, mp, mv, p,
+    hipLaunchKernelGGL((k_pred_factor<T, 1>), dim3((unsigned)np_), dim3(64), 32 * p.d * sizeof(double), st, X, V, Xp, Vp, nbrp, n, mp, mv, p,
                        Ap, Dp, status);
   else
-    hipLaunchKernelGGL((k_pred_factor<T, 2>), dim3((unsigned)np_), dim3(64), 0, st, X, V, Xp, Vp, nbrp, n, mp, mv, p,
+    hipLaunchKernelGGL((k_pred_factor<T, 2>), dim3((unsigned)np_), dim3(64), 32 * p.d * sizeof(double), st, X, V, Xp, Vp, nbrp, n, mp, mv, p,
                        Ap, Dp, status);
 }
 template <typename T>
@@ -686,10 +691,10 @@ template <typename T>
 void launch_factor(hipStream_t st, const double* X, const T* V, const int32_t* nbr, int64_t n, int mp, int mv,
                    const CovParams& p, T* A, double* D, T* U, int* status, Batch bt, const int* perm) {
   if (mv + 1 <= 16)
-    hipLaunchKernelGGL((k_factor<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, nbr, n, mp, mv, p, A, D, U, status,
+    hipLaunchKernelGGL((k_factor<T, 1>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, nbr, n, mp, mv, p, A, D, U, status,
                        bt, perm);
   else
-    hipLaunchKernelGGL((k_factor<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, nbr, n, mp, mv, p, A, D, U, status,
+    hipLaunchKernelGGL((k_factor<T, 2>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, nbr, n, mp, mv, p, A, D, U, status,
                        bt, perm);
 }
 
@@ -714,10 +719,10 @@ void launch_factor_bwd(hipStream_t st, const double* X, const T* V, const T* Vr,
                        int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status,
                        Batch bt, const int* perm) {
   if (mv + 2 <= 16)
-    hipLaunchKernelGGL((k_factor_bwd<T, 1>), dim3((unsigned)n), dim3(64), 0, st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
+    hipLaunchKernelGGL((k_factor_bwd<T, 1>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
                        n, mp, mv, p, Q1, Gs, Bs, tpart, status, bt, perm);
   else
-    hipLaunchKernelGGL((k_factor_bwd<T, 2>), dim3((unsigned)n), dim3(64), 0, st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
+    hipLaunchKernelGGL((k_factor_bwd<T, 2>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
                        n, mp, mv, p, Q1, Gs, Bs, tpart, status, bt, perm);
 }
 template void launch_factor_bwd<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
