@@ -379,6 +379,7 @@ def main():
 
     r32 = run_form(w, Xd, Zd, nbr, yd, "fp32", args.steps, args.warmup, grad)
     r64 = run_form(w, Xd, Zd, nbr, yd, "fp64", args.steps, args.warmup, grad)
+    r16 = run_form(w, Xd, Zd, nbr, yd, "bf16_in", args.steps, args.warmup, grad)
 
     fac_ms = r32["stages"].get("factor", float("nan"))
     nbytes = w.n * factor_bytes_per_point(w.m, w.m_v, w.d, 4)
@@ -405,6 +406,14 @@ def main():
         "fp32_nll": r32["nll"],
         "fp32_grad": r32["grad"],
         "fp32_rel_err_vs_fp64_gpu": abs(r32["nll"] - r64["nll"]) / abs(r64["nll"]),
+        "bf16_in": {"value": 1000.0 / r16["ms_per_step"], "unit": "evals/s", "ms_per_step": r16["ms_per_step"],
+                    "nll": r16["nll"], "grad": r16["grad"],
+                    "nll_rel_err_vs_fp64_gpu": abs(r16["nll"] - r64["nll"]) / abs(r64["nll"]),
+                    "nll_err_per_point_vs_fp64_gpu": abs(r16["nll"] - r64["nll"]) / w.n,
+                    "grad_err_vs_fp64_gpu": (None if r16["grad"] is None else
+                                             float(np.max(np.abs(np.subtract(r16["grad"], r64["grad"])))
+                                                   / np.max(np.abs(r64["grad"])))),
+                    "stage_ms": r16["stages"]},
         "stage_ms": {"fp32": r32["stages"], "fp64": r64["stages"]},
         "neighbour_search_s": knn_s,
         "roofline": {"bound": "hbm", "kernel": "k_factor<float>", "achieved": achieved, "peak": HBM_PEAK_GBS,

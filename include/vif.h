@@ -63,7 +63,17 @@ typedef enum { VIF_MATERN12 = 0, VIF_MATERN32 = 1, VIF_GAUSSIAN_ARD = 2 } vif_ke
 typedef enum { VIF_LIK_GAUSSIAN = 0, VIF_LIK_BERNOULLI_LOGIT = 1, VIF_LIK_POISSON_LOG = 2 } vif_likelihood;
 /* Arithmetic of the per-point factor, V / U storage and the low-rank
  * products. The m x m Cholesky factorisations, log-determinants and final
- * reductions are FP64 in every form. */
+ * reductions are FP64 in every form.
+ *  VIF_FP64    : FP64 throughout.
+ *  VIF_FP32    : V, U and the per-point factor (Gram, Cholesky, solves) in FP32.
+ *  VIF_BF16_IN : as VIF_FP32, but V and its range derivative are stored in
+ *                BF16 (rounded to nearest-even from the FP64 whitening) and
+ *                widened to FP32 on load, so the Gram of the gathered rows
+ *                has BF16 inputs and FP32 accumulation. Provided for
+ *                vif_build_factor, vif_nll and vif_nll_grad (and
+ *                vif_precond_solve, vif_export_factor); the Laplace, sampling,
+ *                feature and prediction entry points return VIF_E_ARG in this
+ *                form, and vif_batch_create accepts VIF_FP64 and VIF_FP32. */
 typedef enum { VIF_FP64 = 0, VIF_FP32 = 1, VIF_BF16_IN = 2 } vif_precision;
 
 typedef struct {

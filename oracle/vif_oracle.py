@@ -24,6 +24,9 @@ Sections / equations followed:
     differentiating eq. D_A_Vecchia directly (App. A prints Sigma_i and
     Sigma_mi where the D_i formula has Sigma_iN(i) and Sigma_mN(i), and drops
     the nugget tildes; the derivative of the equation itself is used).
+  * rounded-input form -- the NLL above in whitened coordinates with the
+    whitened features rounded to a narrower format (bfloat16) before the
+    factor build; the method is the same, only its input is rounded.
   * correlation neighbours -- Sec. 6 (correlation distance d_c with c_r the
     residual covariance); brute force over all earlier points, which is the
     set the cover tree of Alg. 3/4 also returns.
@@ -40,7 +43,7 @@ import math
 from typing import List, Optional, Sequence
 
 import numpy as np
-from scipy.linalg import cho_factor, cho_solve
+from scipy.linalg import cho_factor, cho_solve, solve_triangular
 
 MATERN12 = "matern12"
 MATERN32 = "matern32"
@@ -347,6 +350,59 @@ def nll_gaussian(model: Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray,
         quad -= float(u @ cho_solve(cM, u))
     nll = 0.5 * n * math.log(2.0 * math.pi) + 0.5 * logdet + 0.5 * quad
     return GaussianNLL(nll, logdet, quad, fac, ind)
+
+
+# ----------------------------------------------------------------------------
+# Rounded-input form: the whitened features stored in a narrower format
+# ----------------------------------------------------------------------------
+
+def bf16_round(a) -> np.ndarray:
+    """Nearest bfloat16 value of every entry, ties to even, returned as float64.
+
+    A bfloat16 is the upper half of an IEEE binary32 (sign, 8 exponent bits,
+    7 stored mantissa bits); the value is rounded from its binary32 rounding.
+    Finite inputs only."""
+    a = np.asarray(a, dtype=np.float64)
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    half = (u >> 16) & 1  # ties go to the even upper half
+    u = ((u + 0x7FFF + half) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64).reshape(a.shape)
+
+
+def nll_gaussian_rounded_v(model: Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray, y: np.ndarray,
+                           rnd) -> float:
+    """L_dagger (Sec. 2.1-2.2) computed in whitened coordinates with the
+    whitened features V = L_m^{-1} Sigma_mn (L_m L_m^T = Sigma_m, so
+    V^T V = Sigma_mn^T Sigma_m^{-1} Sigma_mn) replaced by rnd(V).
+
+    The predictive-process terms of R_i, r_i and D_i (eq. D_A_Vecchia) are
+    rnd(V) inner products; with G = B rnd(V)^T the SMW matrix of eq. def_M,
+    whitened by L_m, is M' = I + G^T D^{-1} G, and det M = det M' det Sigma_m
+    cancels the det(Sigma_m)^{-1} of Sylvester's theorem. With rnd the
+    identity this equals nll_gaussian up to rounding."""
+    n = X.shape[0]
+    m = Z.shape[0]
+    ind = inducing(model, X, Z)
+    if m:
+        V = rnd(solve_triangular(np.tril(ind.cf[0]), ind.Smn, lower=True))
+        eye = np.eye(m)
+        ind = Inducing(eye, V, cho_factor(eye, lower=True), V, np.einsum("ki,ki->i", V, V))
+    fac = vecchia_factor(model, X, ind, nbr)
+    D = fac.D
+    t = apply_B(nbr, fac.A, y)
+    logdet = float(np.sum(np.log(D)))
+    quad = float(t @ (t / D))
+    if m:
+        G = B_times_rows(nbr, fac.A, ind.Smn.T)
+        Mw = np.eye(m) + G.T @ (G / D[:, None])
+        try:
+            cM = cho_factor(Mw, lower=True)
+        except np.linalg.LinAlgError:
+            raise NotPositiveDefinite("M", -1)
+        logdet += 2.0 * np.sum(np.log(np.diag(cM[0])))
+        u = G.T @ (t / D)
+        quad -= float(u @ cho_solve(cM, u))
+    return 0.5 * n * math.log(2.0 * math.pi) + 0.5 * logdet + 0.5 * quad
 
 
 @dataclasses.dataclass

@@ -50,6 +50,7 @@ struct vif_ctx {
   double *Sm = nullptr, *Linv = nullptr, *Mp = nullptr, *LMinv = nullptr, *Mwork = nullptr;
   double* Vd = nullptr;  // n x mp, FP64 (factor storage in the FP64 form, and the neighbour search)
   float* Vf = nullptr;   // n x mp, FP32 storage (FP32 form)
+  bf16s* Vb = nullptr;   // n x mp, BF16 storage (BF16-input form)
   void* A = nullptr;     // n x m_v (double or float)
   void* U = nullptr;     // n x mp (double or float)
   double *D = nullptr, *yt = nullptr, *vnorm = nullptr;
@@ -154,9 +155,20 @@ static void harvest(vif_ctx* c) {
   }
 }
 
-static bool fp32_form(const vif_ctx* c) { return c->cfg.precision == VIF_FP32; }
+// FP32 arithmetic: the FP32 and the BF16-input forms
+static bool fp32_form(const vif_ctx* c) { return c->cfg.precision != VIF_FP64; }
+static bool bf16_form(const vif_ctx* c) { return c->cfg.precision == VIF_BF16_IN; }
 
 static size_t tsize(const vif_ctx* c) { return fp32_form(c) ? sizeof(float) : sizeof(double); }
+// bytes per stored entry of V and of its derivative Vr
+static size_t vsize(const vif_ctx* c) { return bf16_form(c) ? sizeof(bf16s) : tsize(c); }
+
+// The BF16-input form covers the factor build, the NLL and its gradient.
+static vif_status reject_bf16(vif_ctx* c, const char* fn) {
+  if (!bf16_form(c)) return VIF_OK;
+  return fail(c, VIF_E_ARG, "%s is provided in the FP64 and FP32 forms (the BF16-input form covers the factor build, "
+              "the NLL and its gradient)", fn);
+}
 
 static vif_status set_params(vif_ctx* c, const double* theta) {
   if (!theta) return fail(c, VIF_E_ARG, "theta is NULL");
@@ -243,7 +255,7 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   if (g.m < 0 || g.m > 1024 || g.m > g.n) return VIF_E_ARG;
   if (g.m_v < 0 || g.m_v > VIF_MAX_MV) return VIF_E_ARG;
   if (g.kernel < 0 || g.kernel > 2 || g.likelihood < 0 || g.likelihood > 2) return VIF_E_ARG;
-  if (g.precision != VIF_FP64 && g.precision != VIF_FP32) return VIF_E_ARG;
+  if (g.precision != VIF_FP64 && g.precision != VIF_FP32 && g.precision != VIF_BF16_IN) return VIF_E_ARG;
   if (g.kernel != VIF_GAUSSIAN_ARD && g.d > VIF_MAX_D) return VIF_E_ARG;
   vif_ctx* c = new vif_ctx();
   c->cfg = g;
@@ -267,7 +279,10 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   alloc((void**)&c->Mwork, sizeof(double) * mpa * mpa);
   alloc((void**)&c->Minv, sizeof(double) * mpa * mpa);
   alloc((void**)&c->Vd, sizeof(double) * n * mpa);
-  if (fp32_form(c)) alloc((void**)&c->Vf, sizeof(float) * n * mpa);
+  if (bf16_form(c))
+    alloc((void**)&c->Vb, sizeof(bf16s) * n * mpa);
+  else if (fp32_form(c))
+    alloc((void**)&c->Vf, sizeof(float) * n * mpa);
   alloc(&c->A, tsize(c) * n * (g.m_v > 0 ? g.m_v : 1));
   alloc(&c->U, tsize(c) * n * mpa);
   alloc((void**)&c->D, sizeof(double) * n);
@@ -294,7 +309,7 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
     alloc(&c->Q1, tsize(c) * n * mpa);
     alloc(&c->Gs, tsize(c) * n * mpa);
     alloc(&c->Bs, tsize(c) * n * mpa);
-    alloc(&c->Vr, tsize(c) * n * mpa);
+    alloc(&c->Vr, vsize(c) * n * mpa);
     alloc((void**)&c->tpart, sizeof(double) * n * 3);
     alloc((void**)&c->rowpart, sizeof(double) * mpa * 2);
     alloc((void**)&c->gred, sizeof(double) * (ceil_div(n, 4096) * 3 + ceil_div(mpa, 4096) * 2 + 16));
@@ -350,7 +365,7 @@ void vif_destroy(vif_ctx* c) {
   if (!c) return;
   if (c->st) hipStreamSynchronize(c->st); else hipDeviceSynchronize();
   if (c->st2) hipStreamSynchronize(c->st2);
-  void* bufs[] = {c->Sm, c->Linv, c->Mp, c->LMinv, c->Mwork, c->Vd, c->Vf, c->A, c->U, c->D, c->yt, c->vnorm,
+  void* bufs[] = {c->Sm, c->Linv, c->Mp, c->LMinv, c->Mwork, c->Vd, c->Vf, c->Vb, c->A, c->U, c->D, c->yt, c->vnorm,
                   c->partial, c->vecpart, c->vec, c->scal, c->status, c->nbr, c->Xc, c->Zc, c->Minv, c->wvec,
                   c->e, c->Smat, c->Tm, c->tmpm, c->MinvT, c->Ubar, c->Q1, c->Gs, c->Bs, c->Vr, c->tpart,
                   c->rowpart, c->gred, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx,
@@ -416,6 +431,8 @@ static vif_status build_inducing(vif_ctx* c, const double* X, const double* Z, b
   stage_begin(c, ST_WHITEN);
   if (fp64_V)
     launch_whiten<double>(c->st, X, Z, c->Linv, g.m, c->mp, g.n, c->cp, false, c->Vd);
+  else if (bf16_form(c))
+    launch_whiten<bf16s>(c->st, X, Z, c->Linv, g.m, c->mp, g.n, c->cp, false, c->Vb);
   else
     launch_whiten<float>(c->st, X, Z, c->Linv, g.m, c->mp, g.n, c->cp, false, c->Vf);
   stage_end(c, ST_WHITEN);
@@ -509,7 +526,9 @@ vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const 
   if (c->grad_seen && c->st2) {  // Vr for the gradient, on the second stream
     HIPCHK(c, hipEventRecord(c->ev_lm, c->st));
     HIPCHK(c, hipStreamWaitEvent(c->st2, c->ev_lm, 0));
-    if (f32)
+    if (bf16_form(c))
+      launch_whiten<bf16s>(c->st2, X, Z, c->Linv, g.m, c->mp, g.n, c->cp, true, (bf16s*)c->Vr);
+    else if (f32)
       launch_whiten<float>(c->st2, X, Z, c->Linv, g.m, c->mp, g.n, c->cp, true, (float*)c->Vr);
     else
       launch_whiten<double>(c->st2, X, Z, c->Linv, g.m, c->mp, g.n, c->cp, true, (double*)c->Vr);
@@ -518,7 +537,10 @@ vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const 
     c->vr_pending = true;
   }
   stage_begin(c, ST_FACTOR);
-  if (f32)
+  if (bf16_form(c))
+    launch_factor<float>(c->st, X, c->Vb, nbr, g.n, c->mp, g.m_v, c->cp, (float*)c->A, c->D, (float*)c->U, c->status,
+                         Batch{nullptr, nullptr}, vorder(c));
+  else if (f32)
     launch_factor<float>(c->st, X, c->Vf, nbr, g.n, c->mp, g.m_v, c->cp, (float*)c->A, c->D, (float*)c->U, c->status,
                          Batch{nullptr, nullptr}, vorder(c));
   else
@@ -619,11 +641,12 @@ __global__ void k_grad_final(const double* tp, int nt, const double* rp, int nr,
   out[2] = g2;
 }
 
-template <typename T>
+// T: arithmetic type; S: storage type of V and Vr
+template <typename T, typename S>
 static vif_status nll_grad_impl(vif_ctx* c, const double* y) {
   const vif_config& g = c->cfg;
   const int mp = c->mp;
-  const T* V = (const T*)(fp32_form(c) ? (const void*)c->Vf : (const void*)c->Vd);
+  const S* V = (const S*)(bf16_form(c) ? (const void*)c->Vb : fp32_form(c) ? (const void*)c->Vf : (const void*)c->Vd);
   const T* U = (const T*)c->U;
   stage_begin(c, ST_NLL);
   nll_tail(c, y);
@@ -644,12 +667,12 @@ static vif_status nll_grad_impl(vif_ctx* c, const double* y) {
       HIPCHK(c, hipStreamWaitEvent(c->st, c->ev_vr, 0));
       c->vr_pending = false;
     } else {
-      launch_whiten<T>(c->st, c->Xc, c->Zc, c->Linv, g.m, mp, g.n, c->cp, true, (T*)c->Vr);
+      launch_whiten<S>(c->st, c->Xc, c->Zc, c->Linv, g.m, mp, g.n, c->cp, true, (S*)c->Vr);
     }
     stage_end(c, ST_WDERIV);
   }
   stage_begin(c, ST_FBWD);
-  launch_factor_bwd<T>(c->st, c->Xc, V, (const T*)c->Vr, c->nbr, y, U, (const T*)c->Ubar, c->e, c->yt, c->D, g.n, mp,
+  launch_factor_bwd<T>(c->st, c->Xc, V, (const S*)c->Vr, c->nbr, y, U, (const T*)c->Ubar, c->e, c->yt, c->D, g.n, mp,
                        g.m_v, c->cp, (T*)c->Q1, (T*)c->Gs, (T*)c->Bs, c->tpart, c->status, Batch{nullptr, nullptr},
                        vorder(c));
   stage_end(c, ST_FBWD);
@@ -688,7 +711,9 @@ vif_status vif_nll_grad(vif_ctx* c, const double* y, double* nll_out, double* gr
   vif_status s = reset_status(c);
   if (s) return s;
   c->grad_seen = true;
-  s = fp32_form(c) ? nll_grad_impl<float>(c, y) : nll_grad_impl<double>(c, y);
+  s = bf16_form(c)   ? nll_grad_impl<float, bf16s>(c, y)
+      : fp32_form(c) ? nll_grad_impl<float, float>(c, y)
+                     : nll_grad_impl<double, double>(c, y);
   if (s) return s;
   HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * 16, hipMemcpyDeviceToHost, c->st));
   s = read_status(c, "vif_nll_grad");
@@ -1159,6 +1184,7 @@ extern "C" {
 
 vif_status vif_sample_prior(vif_ctx* c, const double* eps1, const double* eps2, double* b_out) {
   if (!c) return VIF_E_ARG;
+  if (bf16_form(c)) return reject_bf16(c, "vif_sample_prior");
   if (!c->built) return fail(c, VIF_E_STATE, "vif_sample_prior before a successful vif_build_factor");
   const vif_config& g = c->cfg;
   if (!eps2 || !b_out || (g.m > 0 && !eps1)) return fail(c, VIF_E_ARG, "NULL eps1, eps2 or b_out");
@@ -1180,6 +1206,7 @@ vif_status vif_sample_prior(vif_ctx* c, const double* eps1, const double* eps2, 
 
 vif_status vif_mlp_features(vif_ctx* c, const double* y, float* feat_out) {
   if (!c) return VIF_E_ARG;
+  if (bf16_form(c)) return reject_bf16(c, "vif_mlp_features");
   if (!c->built) return fail(c, VIF_E_STATE, "vif_mlp_features before a successful vif_build_factor");
   if (!y || !feat_out) return fail(c, VIF_E_ARG, "NULL y or feat_out");
   const vif_config& g = c->cfg;
@@ -1231,6 +1258,7 @@ vif_status vif_mlp_features(vif_ctx* c, const double* y, float* feat_out) {
 
 vif_status vif_laplace_mode(vif_ctx* c, const double* y, const double* b0, double* mode_out, vif_laplace_stats* st) {
   if (!c) return VIF_E_ARG;
+  if (bf16_form(c)) return reject_bf16(c, "vif_laplace_mode");
   if (!c->built) return fail(c, VIF_E_STATE, "vif_laplace_mode before a successful vif_build_factor");
   if (!y || !mode_out) return fail(c, VIF_E_ARG, "NULL y or mode_out");
   if (c->cfg.likelihood == VIF_LIK_GAUSSIAN && !(c->cfg.lik_param > 0))
@@ -1612,6 +1640,7 @@ extern "C" {
 vif_status vif_laplace_nll(vif_ctx* c, const double* y, const double* mode, int32_t ell, const double* eps_n,
                            const double* eps_m, double* nll_out, double* logdet_out) {
   if (!c) return VIF_E_ARG;
+  if (bf16_form(c)) return reject_bf16(c, "vif_laplace_nll");
   if (!c->built) return fail(c, VIF_E_STATE, "vif_laplace_nll before a successful vif_build_factor");
   const vif_config& g = c->cfg;
   if (!y || !mode || !eps_n || !nll_out || (g.m > 0 && !eps_m)) return fail(c, VIF_E_ARG, "NULL argument");
@@ -1632,6 +1661,7 @@ vif_status vif_laplace_nll(vif_ctx* c, const double* y, const double* mode, int3
 vif_status vif_laplace_nll_grad(vif_ctx* c, const double* y, const double* mode, int32_t ell, const double* eps_n,
                                 const double* eps_m, double* nll_out, double* grad_out) {
   if (!c) return VIF_E_ARG;
+  if (bf16_form(c)) return reject_bf16(c, "vif_laplace_nll_grad");
   if (!c->built) return fail(c, VIF_E_STATE, "vif_laplace_nll_grad before a successful vif_build_factor");
   const vif_config& g = c->cfg;
   if (!y || !mode || !eps_n || !nll_out || !grad_out || (g.m > 0 && !eps_m))
@@ -1748,6 +1778,7 @@ vif_status vif_select_neighbors_pred(vif_ctx* c, const double* Xp, int64_t np_, 
 vif_status vif_predict(vif_ctx* c, const double* y, const double* Xp, const int32_t* nbrp, int64_t np_,
                        double* mean_out, double* var_out) {
   if (!c) return VIF_E_ARG;
+  if (bf16_form(c)) return reject_bf16(c, "vif_predict");
   if (!c->built) return fail(c, VIF_E_STATE, "vif_predict before a successful vif_build_factor");
   const vif_config& g = c->cfg;
   if (!y || !Xp || !mean_out || np_ < 1 || (g.m_v > 0 && !nbrp)) return fail(c, VIF_E_ARG, "NULL argument");

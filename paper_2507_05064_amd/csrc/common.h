@@ -12,6 +12,31 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
+// BF16 storage of V in the BF16-input form: the upper 16 bits of an FP32.
+// Values are rounded to nearest-even when stored and widened exactly to FP32
+// when loaded, so every product of two stored values is exact in FP32.
+struct bf16s {
+  uint16_t u;
+};
+__device__ __forceinline__ float to_f32(bf16s h) { return __uint_as_float((uint32_t)h.u << 16); }
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ double to_f32(double v) { return v; }
+// four consecutive BF16 values (8-byte aligned) widened to FP32
+__device__ __forceinline__ f4 load4_bf16(const bf16s* p) {
+  const uint2 q = *reinterpret_cast<const uint2*>(p);
+  return f4{__uint_as_float(q.x << 16), __uint_as_float(q.x & 0xffff0000u), __uint_as_float(q.y << 16),
+            __uint_as_float(q.y & 0xffff0000u)};
+}
+// storage cast from the FP64 accumulator: plain casts, and FP32 -> BF16 by
+// round-to-nearest-even on the bit pattern (V is finite)
+template <typename S> __device__ __forceinline__ S store_cast(double v);
+template <> __device__ __forceinline__ double store_cast<double>(double v) { return v; }
+template <> __device__ __forceinline__ float store_cast<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ bf16s store_cast<bf16s>(double v) {
+  const uint32_t b = __float_as_uint((float)v);
+  return bf16s{(uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16)};
+}
+
 // Covariance c(x, x') = sigma1^2 r(t), t = ||(x - x') / lambda|| (Sec. 2,
 // Assumption 2; ARD transform of Sec. 6). Matern-1/2: e^{-t};
 // Matern-3/2: (1 + sqrt3 t) e^{-sqrt3 t}; Gaussian: e^{-t^2/2}.

@@ -10,8 +10,11 @@
 //     D_i = L[k][k]^2 and A_i = L_R^{-T} (L_R^{-1} r_i) by one backward sweep;
 //  4. U_i = (V_i - sum_j A_ij V_{N(i)_j}) / sqrt(D_i) (a row of D^{-1/2} B V^T)
 //     from the same rows (L1/L2 hits).
-// T is the arithmetic / storage type (double, float).
+// T is the arithmetic type (double, float); S the storage type of V: T, or
+// BF16 with T = float (the BF16-input form: rows widened to FP32 on load).
 #include <limits.h>
+
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -28,6 +31,15 @@ template <typename T> struct VecW;
 typedef double d1 __attribute__((ext_vector_type(1)));
 template <> struct VecW<double> { typedef d1 type; static constexpr int width = 1; };
 template <> struct VecW<float> { typedef f4 type; static constexpr int width = 4; };
+
+// four consecutive stored values as a vector of the arithmetic type
+__device__ __forceinline__ f4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
+__device__ __forceinline__ d4 ld4(const double* p) { return *reinterpret_cast<const d4*>(p); }
+__device__ __forceinline__ f4 ld4(const bf16s* p) { return load4_bf16(p); }
+// VecW-wide loads of the adjoint's row loop
+__device__ __forceinline__ f4 ldw(const float* p) { return *reinterpret_cast<const f4*>(p); }
+__device__ __forceinline__ d1 ldw(const double* p) { return *reinterpret_cast<const d1*>(p); }
+__device__ __forceinline__ f4 ldw(const bf16s* p) { return load4_bf16(p); }
 
 // sqrt(x) and 1/sqrt(x), 1/x: correctly rounded in FP64; in FP32 the
 // hardware reciprocal square root and reciprocal (1 ulp), far inside the
@@ -78,12 +90,12 @@ struct PointShared {
 // k + 1 (needs k + 2 <= 32): sh.GL[k + 1][j] then holds its dot products
 // with the rows j <= k (row k + 1 is not touched by the Cholesky).
 // Returns false (after flagging status) when the system is not PD.
-template <typename T, int NBLK>
-__device__ __forceinline__ bool factor_point(const double* __restrict__ X, const T* __restrict__ V,
+template <typename T, typename S, int NBLK>
+__device__ __forceinline__ bool factor_point(const double* __restrict__ X, const S* __restrict__ V,
                                              const int32_t* __restrict__ nbr, int64_t i, int mp, int mv,
                                              const CovParams& p, PointShared<T>& sh, double* xs, T (&Lrow)[32], int& k_out,
                                              T& D_out, int* status, const T* extra = nullptr,
-                                             T extra_scale = T(1), const T* own_v = nullptr,
+                                             T extra_scale = T(1), const S* own_v = nullptr,
                                              const double* own_x = nullptr, const int32_t* own_nbr = nullptr) {
   // own_v / own_x / own_nbr (prediction points): the point's own V row,
   // coordinates and neighbour row come from these, its neighbours (all < i)
@@ -104,8 +116,9 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
 
   // 1. Gram of the gathered rows
   const int r = lane & 15, g = lane >> 4;
-  const T* src = nullptr;
+  const void* src = nullptr;
   T scl = T(1);
+  int isx = 0;  // the row is `extra` (type T) rather than a stored V row (type S)
   if (own) {
     src = own_v;
   } else if (rowpt >= 0) {
@@ -113,17 +126,26 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
   } else if (extra != nullptr && lane == k + 1) {
     src = extra;
     scl = extra_scale;
+    isx = 1;
   }
   const unsigned long long srcbits = (unsigned long long)(uintptr_t)src;
-  const T* s0 = (const T*)(uintptr_t)__shfl(srcbits, r, 64);
-  const T* s1 = (const T*)(uintptr_t)__shfl(srcbits, 16 + r, 64);
+  const void* s0 = (const void*)(uintptr_t)__shfl(srcbits, r, 64);
+  const void* s1 = (const void*)(uintptr_t)__shfl(srcbits, 16 + r, 64);
   const T sc0 = __shfl(scl, r, 64), sc1 = __shfl(scl, 16 + r, 64);
+  const bool x0 = __shfl(isx, r, 64) != 0, x1 = __shfl(isx, 16 + r, 64) != 0;
+  auto row4 = [&](const void* q, bool x, int off) -> T4 {
+    if constexpr (std::is_same<S, T>::value) {
+      return ld4(static_cast<const T*>(q) + off);
+    } else {
+      return x ? ld4(static_cast<const T*>(q) + off) : ld4(static_cast<const S*>(q) + off);
+    }
+  };
   A4 acc00 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
   const T4 zero4 = {0, 0, 0, 0};
   for (int kk = 0; kk < mp; kk += 16) {
-    const T4 a0 = (s0 != nullptr) ? *reinterpret_cast<const T4*>(s0 + 4 * g + kk) * sc0 : zero4;
+    const T4 a0 = (s0 != nullptr) ? row4(s0, x0, 4 * g + kk) * sc0 : zero4;
     T4 a1 = zero4;
-    if (NBLK == 2) a1 = (s1 != nullptr) ? *reinterpret_cast<const T4*>(s1 + 4 * g + kk) * sc1 : zero4;
+    if (NBLK == 2) a1 = (s1 != nullptr) ? row4(s1, x1, 4 * g + kk) * sc1 : zero4;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       acc00 = mfma16(a0[t], a0[t], acc00);
@@ -213,8 +235,8 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
   return true;
 }
 
-template <typename T, int NBLK>
-__global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, const T* __restrict__ V,
+template <typename T, typename S, int NBLK>
+__global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, const S* __restrict__ V,
                                                const int32_t* __restrict__ nbr, int64_t n, int mp, int mv,
                                                CovParams p_in, T* __restrict__ Aout, double* __restrict__ Dout,
                                                T* __restrict__ U, int* status, Batch bt,
@@ -239,7 +261,7 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
     }
     p = q.cp;
   }
-  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, xs, Lrow, k, D, status)) {
+  if (!factor_point<T, S, NBLK>(X, V, nbr, i, mp, mv, p, sh, xs, Lrow, k, D, status)) {
     if (lane == 0) Dout[i] = __builtin_nan("");
     return;
   }
@@ -249,8 +271,8 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
   typedef typename Vec4<T>::type T4;
   const T rsd = T(1) / sqrt(D);
   for (int l = 4 * lane; l < mp; l += 256) {
-    T4 u = *reinterpret_cast<const T4*>(V + (size_t)i * mp + l);
-    for (int a = 0; a < k; ++a) u -= sh.As[a] * *reinterpret_cast<const T4*>(V + (size_t)sh.nbs[a] * mp + l);
+    T4 u = ld4(V + (size_t)i * mp + l);
+    for (int a = 0; a < k; ++a) u -= sh.As[a] * ld4(V + (size_t)sh.nbs[a] * mp + l);
     *reinterpret_cast<T4*>(U + (size_t)i * mp + l) = u * rsd;
   }
 }
@@ -276,9 +298,9 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
 //                             - (sqrt(D) beta_i) U_i^T].
 // tpart[i] = (d/dsigma1^2, d/drange, d/ds2) of the covariance entries of
 // R_i, r_i, c_ii plus the K(Z,X) dots.
-template <typename T, int NBLK>
-__global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X, const T* __restrict__ V,
-                                                   const T* __restrict__ Vr, const int32_t* __restrict__ nbr,
+template <typename T, typename S, int NBLK>
+__global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X, const S* __restrict__ V,
+                                                   const S* __restrict__ Vr, const int32_t* __restrict__ nbr,
                                                    const double* __restrict__ y, const T* __restrict__ U,
                                                    const T* __restrict__ Ubar, const double* __restrict__ e,
                                                    const double* __restrict__ yt, const double* __restrict__ Dfwd,
@@ -310,7 +332,7 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
     p = q.cp;
   }
   const T rsd = T(1) / sqrt(T(Dfwd[i]));
-  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, xs, Lrow, k, D, status, Ubar + (size_t)i * mp, rsd)) {
+  if (!factor_point<T, S, NBLK>(X, V, nbr, i, mp, mv, p, sh, xs, Lrow, k, D, status, Ubar + (size_t)i * mp, rsd)) {
     if (lane == 0) tpart[i * 3] = tpart[i * 3 + 1] = tpart[i * 3 + 2] = __builtin_nan("");
     return;
   }
@@ -383,13 +405,13 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   T tsv = 0, trv = 0;
   for (int l = VW * lane; l < mp; l += 64 * VW) {
     const size_t o = (size_t)i * mp + l;
-    const TW Vi = *reinterpret_cast<const TW*>(V + o), Ui = *reinterpret_cast<const TW*>(U + o);
-    const TW Vri = *reinterpret_cast<const TW*>(Vr + o);
+    const TW Vi = ldw(V + o), Ui = *reinterpret_cast<const TW*>(U + o);
+    const TW Vri = ldw(Vr + o);
     const TW u = *reinterpret_cast<const TW*>(Ubar + o) * rsd;
     TW al = TW(0), be = TW(0), alr = TW(0), ber = TW(0);
     for (int j = 0; j < k; ++j) {
       const size_t oj = (size_t)sh.nbs[j] * mp + l;
-      const TW v = *reinterpret_cast<const TW*>(V + oj), vr = *reinterpret_cast<const TW*>(Vr + oj);
+      const TW v = ldw(V + oj), vr = ldw(Vr + oj);
       const T aj = sh.As[j], rj = rho_s[j];
       al += aj * v;
       be += rj * v;
@@ -448,7 +470,7 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
   const int lane = threadIdx.x;
   const int myrow = lane & 31;
   const int64_t i = perm ? (int64_t)perm[blockIdx.x] : (int64_t)blockIdx.x;
-  if (!factor_point<T, NBLK>(X, V, nbr, i, mp, mv, p, sh, xs, Lrow, k, D, status)) {
+  if (!factor_point<T, T, NBLK>(X, V, nbr, i, mp, mv, p, sh, xs, Lrow, k, D, status)) {
     if (lane == 0) dD[i] = __builtin_nan("");
     return;
   }
@@ -617,7 +639,7 @@ __global__ __launch_bounds__(64) void k_pred_factor(const double* __restrict__ X
   T D;
   const int lane = threadIdx.x;
   const int64_t j = blockIdx.x;
-  if (!factor_point<T, NBLK>(X, V, nullptr, n, mp, mv, p, sh, xs, Lrow, k, D, status, nullptr, T(1),
+  if (!factor_point<T, T, NBLK>(X, V, nullptr, n, mp, mv, p, sh, xs, Lrow, k, D, status, nullptr, T(1),
                              Vp + (size_t)j * mp, Xp + (size_t)j * p.d, nbrp + (size_t)j * mv)) {
     if (lane == 0) Dp[j] = __builtin_nan("");
     return;
@@ -687,14 +709,14 @@ __global__ void k_ytilde(const T* __restrict__ A, const double* __restrict__ D, 
   yt[i] = s / sqrt(D[i]);
 }
 
-template <typename T>
-void launch_factor(hipStream_t st, const double* X, const T* V, const int32_t* nbr, int64_t n, int mp, int mv,
+template <typename T, typename S>
+void launch_factor(hipStream_t st, const double* X, const S* V, const int32_t* nbr, int64_t n, int mp, int mv,
                    const CovParams& p, T* A, double* D, T* U, int* status, Batch bt, const int* perm) {
   if (mv + 1 <= 16)
-    hipLaunchKernelGGL((k_factor<T, 1>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, nbr, n, mp, mv, p, A, D, U, status,
+    hipLaunchKernelGGL((k_factor<T, S, 1>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, nbr, n, mp, mv, p, A, D, U, status,
                        bt, perm);
   else
-    hipLaunchKernelGGL((k_factor<T, 2>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, nbr, n, mp, mv, p, A, D, U, status,
+    hipLaunchKernelGGL((k_factor<T, S, 2>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, nbr, n, mp, mv, p, A, D, U, status,
                        bt, perm);
 }
 
@@ -708,21 +730,23 @@ template void launch_factor<double>(hipStream_t, const double*, const double*, c
                                     const CovParams&, double*, double*, double*, int*, Batch, const int*);
 template void launch_factor<float>(hipStream_t, const double*, const float*, const int32_t*, int64_t, int, int,
                                    const CovParams&, float*, double*, float*, int*, Batch, const int*);
+template void launch_factor<float, bf16s>(hipStream_t, const double*, const bf16s*, const int32_t*, int64_t, int, int,
+                                          const CovParams&, float*, double*, float*, int*, Batch, const int*);
 template void launch_ytilde<double>(hipStream_t, const double*, const double*, const int32_t*, const double*, int64_t,
                                     int, double*);
 template void launch_ytilde<float>(hipStream_t, const float*, const double*, const int32_t*, const double*, int64_t,
                                    int, double*);
 
-template <typename T>
-void launch_factor_bwd(hipStream_t st, const double* X, const T* V, const T* Vr, const int32_t* nbr, const double* y,
+template <typename T, typename S>
+void launch_factor_bwd(hipStream_t st, const double* X, const S* V, const S* Vr, const int32_t* nbr, const double* y,
                        const T* U, const T* Ubar, const double* e, const double* yt, const double* D, int64_t n,
                        int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status,
                        Batch bt, const int* perm) {
   if (mv + 2 <= 16)
-    hipLaunchKernelGGL((k_factor_bwd<T, 1>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
+    hipLaunchKernelGGL((k_factor_bwd<T, S, 1>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
                        n, mp, mv, p, Q1, Gs, Bs, tpart, status, bt, perm);
   else
-    hipLaunchKernelGGL((k_factor_bwd<T, 2>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
+    hipLaunchKernelGGL((k_factor_bwd<T, S, 2>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
                        n, mp, mv, p, Q1, Gs, Bs, tpart, status, bt, perm);
 }
 template void launch_factor_bwd<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
@@ -733,3 +757,7 @@ template void launch_factor_bwd<float>(hipStream_t, const double*, const float*,
                                        const double*, const float*, const float*, const double*, const double*,
                                        const double*, int64_t, int, int, const CovParams&, float*, float*, float*,
                                        double*, int*, Batch, const int*);
+template void launch_factor_bwd<float, bf16s>(hipStream_t, const double*, const bf16s*, const bf16s*, const int32_t*,
+                                              const double*, const float*, const float*, const double*,
+                                              const double*, const double*, int64_t, int, int, const CovParams&,
+                                              float*, float*, float*, double*, int*, Batch, const int*);

@@ -12,6 +12,8 @@
 //             - 1/2 tr(L_m^{-T} Sm_bar L_m^{-1} dSigma_m/dtheta).
 #include <algorithm>
 
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -147,8 +149,8 @@ __global__ __launch_bounds__(256) void k_ubar(const T* __restrict__ U, const T* 
 // for one 64 x 64 block of the lower triangle (the full sum is symmetric).
 // Workgroups are numbered so that the blocks of one chunk run on one XCD
 // (consecutive workgroup ids go to different XCDs), sharing its L2.
-template <typename T>
-__global__ __launch_bounds__(256) void k_cross3_partial(const T* __restrict__ V, const T* __restrict__ Q1,
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void k_cross3_partial(const S* __restrict__ V, const T* __restrict__ Q1,
                                                         const T* __restrict__ U, const T* __restrict__ Gs,
                                                         const T* __restrict__ Bs, int64_t n, int mp, int chunk,
                                                         int nchunk, int nblk, double* __restrict__ partial) {
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(256) void k_cross3_partial(const T* __restrict__ V,
       // unconditional in-range loads, so that they issue together
       const bool ra = pv && rok[t], cb = pv && cok[t];
       const size_t oa = off + min(L0 + 16 * t + r, mp - 1), ob = off + min(C0 + 16 * t + r, mp - 1);
-      const T v1 = V[oa], w1 = Q1[ob], v2 = U[oa], w2 = Gs[ob], v3 = Bs[oa], w3 = U[ob];
+      const T v1 = to_f32(V[oa]), w1 = Q1[ob], v2 = U[oa], w2 = Gs[ob], v3 = Bs[oa], w3 = U[ob];
       a1[t] = ra ? v1 : T(0);
       b1[t] = cb ? w1 : T(0);
       a2[t] = ra ? -v2 : T(0);
@@ -221,15 +223,16 @@ __global__ __launch_bounds__(256) void k_cross3_partial(const T* __restrict__ V,
 // through LDS in slices of 8 points (coalesced 16-byte loads, the next slice
 // prefetched into registers while the MFMAs run on the current one), and the
 // 8 waves take the tiles in turn, each tile a 16 x 16 x 4 MFMA triple per 4
-// points. Each input row is read from memory once per chunk.
+// points. Each input row is read from memory once per chunk (V rows stored in
+// BF16 are widened to FP32 on the way to LDS).
 constexpr int kC3Slice = 8, kC3Pitch = 256 + 16;
 // largest m_p per form: the FP64 accumulators (8 registers per tile) limit a
 // wave to 12 tiles, i.e. 91 tiles over the 8 waves
 template <typename T> struct C3Max;
 template <> struct C3Max<float> { static constexpr int value = 256; };
 template <> struct C3Max<double> { static constexpr int value = 208; };
-template <typename T>
-__global__ __launch_bounds__(512) void k_cross3_tiles(const T* __restrict__ V, const T* __restrict__ Q1,
+template <typename T, typename S>
+__global__ __launch_bounds__(512) void k_cross3_tiles(const S* __restrict__ V, const T* __restrict__ Q1,
                                                       const T* __restrict__ U, const T* __restrict__ Gs,
                                                       const T* __restrict__ Bs, int64_t n, int mp, int chunk,
                                                       double* __restrict__ partial) {
@@ -246,7 +249,7 @@ __global__ __launch_bounds__(512) void k_cross3_tiles(const T* __restrict__ V, c
   const int nt = mp / 16, ntile = nt * (nt + 1) / 2;
   const int rowv = mp / VW;                      // 16-byte vectors per row
   const int nvec = 5 * kC3Slice * rowv;          // per slice
-  const T* src[5] = {V, Q1, U, Gs, Bs};
+  const T* src[5] = {nullptr, Q1, U, Gs, Bs};  // V (type S) is array 0
   constexpr int kPerThread = (5 * kC3Slice * (kMax / VW) + 511) / 512;
   TV pre[kPerThread];
   auto fetch = [&](int64_t p0) {
@@ -258,7 +261,16 @@ __global__ __launch_bounds__(512) void k_cross3_tiles(const T* __restrict__ V, c
         const int a = e / (kC3Slice * rowv), rem = e - a * kC3Slice * rowv;
         const int pp = rem / rowv, c4 = rem - pp * rowv;
         const int64_t p = p0 + pp;
-        if (p < pend) v = *reinterpret_cast<const TV*>(src[a] + (size_t)p * mp + c4 * VW);
+        if (p < pend) {
+          if constexpr (std::is_same<S, T>::value) {
+            v = *reinterpret_cast<const TV*>((a == 0 ? V : src[a]) + (size_t)p * mp + c4 * VW);
+          } else {  // BF16 V rows: VW = 4 entries (8 bytes) widened to FP32
+            if (a == 0)
+              v = load4_bf16(V + (size_t)p * mp + c4 * VW);
+            else
+              v = *reinterpret_cast<const TV*>(src[a] + (size_t)p * mp + c4 * VW);
+          }
+        }
       }
       pre[t] = v;
     }
@@ -488,15 +500,15 @@ void launch_ubar(hipStream_t st, const T* U, const T* Minv, const double* e, con
   dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(mp, 64));
   hipLaunchKernelGGL((k_ubar<T>), grid, dim3(256), 0, st, U, Minv, e, w, n, mp, Ubar, bt);
 }
-template <typename T>
-void launch_cross3_partial(hipStream_t st, const T* V, const T* Q1, const T* U, const T* Gs, const T* Bs, int64_t n,
+template <typename T, typename S>
+void launch_cross3_partial(hipStream_t st, const S* V, const T* Q1, const T* U, const T* Gs, const T* Bs, int64_t n,
                            int mp, int chunk, double* partial, int* nchunk_out, bool tiles) {
   if (tiles && mp <= C3Max<T>::value) {
     // one workgroup per chunk, at most 256 chunks (one per CU), chunk a multiple of the slice and >= the given one
     int64_t ch = std::max<int64_t>(chunk, ceil_div(n, 256));
     ch = ceil_div(ch, kC3Slice) * kC3Slice;
     const int nch = (int)ceil_div(n, ch);
-    hipLaunchKernelGGL((k_cross3_tiles<T>), dim3(nch), dim3(512), 0, st, V, Q1, U, Gs, Bs, n, mp, (int)ch, partial);
+    hipLaunchKernelGGL((k_cross3_tiles<T, S>), dim3(nch), dim3(512), 0, st, V, Q1, U, Gs, Bs, n, mp, (int)ch, partial);
     *nchunk_out = nch;
     return;
   }
@@ -504,7 +516,7 @@ void launch_cross3_partial(hipStream_t st, const T* V, const T* Q1, const T* U, 
   const int nb = (mp + 63) / 64;
   const int nblk = nb * (nb + 1) / 2;
   const int nwg = (int)(ceil_div(nchunk, 8) * 8 * nblk);
-  hipLaunchKernelGGL((k_cross3_partial<T>), dim3(nwg), dim3(256), 0, st, V, Q1, U, Gs, Bs, n, mp, chunk, nchunk, nblk,
+  hipLaunchKernelGGL((k_cross3_partial<T, S>), dim3(nwg), dim3(256), 0, st, V, Q1, U, Gs, Bs, n, mp, chunk, nchunk, nblk,
                      partial);
   *nchunk_out = nchunk;
 }
@@ -553,3 +565,5 @@ template void launch_cross3_partial<double>(hipStream_t, const double*, const do
                                             const double*, int64_t, int, int, double*, int*, bool);
 template void launch_cross3_partial<float>(hipStream_t, const float*, const float*, const float*, const float*,
                                            const float*, int64_t, int, int, double*, int*, bool);
+template void launch_cross3_partial<float, bf16s>(hipStream_t, const bf16s*, const float*, const float*, const float*,
+                                                  const float*, int64_t, int, int, double*, int*, bool);

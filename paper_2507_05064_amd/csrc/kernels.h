@@ -33,8 +33,9 @@ void launch_knn_pred(hipStream_t st, const double* Xq, const double* Vq, const d
                      const CovParams& p, int32_t* nbr);
 
 // factor.hip
-template <typename T>
-void launch_factor(hipStream_t st, const double* X, const T* V, const int32_t* nbr, int64_t n, int mp, int mv,
+// S: storage type of V (T, or bf16s in the BF16-input form with T = float)
+template <typename T, typename S = T>
+void launch_factor(hipStream_t st, const double* X, const S* V, const int32_t* nbr, int64_t n, int mp, int mv,
                    const CovParams& p, T* A, double* D, T* U, int* status, Batch bt = Batch{nullptr, nullptr},
                    const int* perm = nullptr);
 template <typename T>
@@ -52,8 +53,8 @@ void launch_vec_reduce(hipStream_t st, const double* partial, int nchunk, int le
                        Batch bt = Batch{nullptr, nullptr}, int nprob = 1);
 
 // factor.hip (adjoint)
-template <typename T>
-void launch_factor_bwd(hipStream_t st, const double* X, const T* V, const T* Vr, const int32_t* nbr, const double* y,
+template <typename T, typename S = T>
+void launch_factor_bwd(hipStream_t st, const double* X, const S* V, const S* Vr, const int32_t* nbr, const double* y,
                        const T* U, const T* Ubar, const double* e, const double* yt, const double* D, int64_t n,
                        int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status,
                        Batch bt = Batch{nullptr, nullptr}, const int* perm = nullptr);
@@ -70,8 +71,8 @@ void launch_resid(hipStream_t st, const T* U, const double* w, const double* yt,
 template <typename T>
 void launch_ubar(hipStream_t st, const T* U, const T* Minv, const double* e, const double* w, int64_t n, int mp,
                  T* Ubar, Batch bt = Batch{nullptr, nullptr});
-template <typename T>
-void launch_cross3_partial(hipStream_t st, const T* V, const T* Q1, const T* U, const T* Gs, const T* Bs, int64_t n,
+template <typename T, typename S = T>
+void launch_cross3_partial(hipStream_t st, const S* V, const T* Q1, const T* U, const T* Gs, const T* Bs, int64_t n,
                            int mp, int chunk, double* partial, int* nchunk_out, bool tiles = false);
 void launch_reduce_sym(hipStream_t st, const double* partial, int nchunk, int mp, double* out,
                        Batch bt = Batch{nullptr, nullptr}, int nprob = 1);

@@ -9,7 +9,8 @@
 // coalesced loads, transposed so that the MFMA A operand reads 16
 // consecutive rows; each lane evaluates the four K(z_j, x_p) it feeds as the
 // B operand of FP64 MFMA 16x16x4. Blocks above the diagonal are skipped.
-// Always FP64 arithmetic; the store casts to the storage type.
+// Always FP64 arithmetic; the store casts to the storage type (FP64, FP32
+// or BF16).
 #include "common.h"
 #include "kernels.h"
 
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ X, co
   for (int rb = 0; rb < 8; ++rb) {
     if (rb < nrb) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) vrow[rb * 16 + acc_row<double>(lane, v)] = (T)acc[rb][v];
+      for (int v = 0; v < 4; ++v) vrow[rb * 16 + acc_row<double>(lane, v)] = store_cast<T>(acc[rb][v]);
     }
   }
 }
@@ -119,5 +120,7 @@ template void launch_whiten<double>(hipStream_t, const double*, const double*, c
                                     const CovParams&, bool, double*, Batch);
 template void launch_whiten<float>(hipStream_t, const double*, const double*, const double*, int, int, int64_t,
                                    const CovParams&, bool, float*, Batch);
+template void launch_whiten<bf16s>(hipStream_t, const double*, const double*, const double*, int, int, int64_t,
+                                   const CovParams&, bool, bf16s*, Batch);
 template void launch_rownorm<double>(hipStream_t, const double*, int64_t, int, double*);
 template void launch_rownorm<float>(hipStream_t, const float*, int64_t, int, double*);

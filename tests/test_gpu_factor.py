@@ -8,6 +8,14 @@ relative, or 1e-5 per point when the NLL is small (it is a sum of n terms
 and can be near zero) -- the per-point systems are formed and factored in
 FP32 (unit roundoff 6e-8) with condition numbers up to ~1/s2 = 100 (C1), so
 each term carries up to ~1e-5 relative error.
+BF16-input form: V is rounded to BF16 (unit roundoff 2^-9 = 2e-3) before
+the per-point Gram, so an entry of the residual covariance K - V V^T moves
+by up to ~2^-9 |V_a| |V_b| against a conditional variance D_i of the order
+of the nugget (0.01-0.05): D_i moves by up to a few percent. The form is
+checked twice: against the oracle evaluated with the same BF16 rounding of
+V (nll_gaussian_rounded_v with bf16_round), where only the FP32 arithmetic
+differs (FP32 bar, 1e-5 per point); and against the unrounded oracle, with
+the bar 3e-3 max(|NLL|, n) for the NLL and 5e-2 max|g| for the gradient.
 """
 import numpy as np
 import pytest
@@ -74,6 +82,34 @@ def test_c1_nll_fp32(c1):
     ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
     nll_g = ctx.nll(to_dev(y))
     assert abs(nll_g - nll_o) <= 2e-5 * abs(nll_o), (nll_g, nll_o)
+
+
+def test_c1_nll_bf16_input(c1):
+    w, X, Z, model, ind, nbr, y = c1
+    print(f"[gpu] C1 NLL bf16_in", flush=True)
+    nll_o = vo.nll_gaussian(model, X, Z, nbr, y).nll
+    nll_r = vo.nll_gaussian_rounded_v(model, X, Z, nbr, y, vo.bf16_round)
+    ctx = _ctx(w, precision="bf16_in")
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    nll_g = ctx.nll(to_dev(y))
+    bar = max(abs(nll_o), w.n)
+    assert abs(nll_g - nll_r) <= 1e-5 * bar, (nll_g, nll_r)
+    assert abs(nll_g - nll_o) <= 3e-3 * bar, (nll_g, nll_o)
+    # the FP32 form on the same inputs is closer to the oracle: the BF16
+    # rounding of V is what moves the result
+    ctx32 = _ctx(w, precision="fp32")
+    ctx32.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    assert abs(ctx32.nll(to_dev(y)) - nll_o) < abs(nll_g - nll_o)
+
+
+def test_bf16_input_form_rejects_other_entry_points(c1):
+    from paper_2507_05064_amd.vif import VifError
+    w, X, Z, model, ind, nbr, y = c1
+    ctx = _ctx(w, precision="bf16_in")
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    with pytest.raises(VifError) as e:
+        ctx.laplace_mode(to_dev(y))
+    assert e.value.code == 1 and "BF16-input" in str(e.value)
 
 
 @pytest.mark.parametrize("n,m,mv", [(1, 0, 5), (2, 1, 3), (7, 3, 10), (33, 5, 15), (300, 0, 12),
@@ -148,11 +184,13 @@ def test_not_pd_is_reported():
 
 
 @pytest.mark.parametrize("n,m,mv,prec", [(400, 20, 8, "fp64"), (1500, 50, 10, "fp64"), (517, 33, 30, "fp64"),
-                                         (300, 0, 6, "fp64"), (300, 17, 0, "fp64"), (1500, 50, 10, "fp32")])
+                                              (300, 0, 6, "fp64"), (300, 17, 0, "fp64"), (1500, 50, 10, "fp32"),
+                                         (1500, 50, 10, "bf16_in"), (517, 33, 30, "bf16_in")])
 def test_gradient_matches_oracle(n, m, mv, prec):
     """Adjoint gradient (GPU) vs the oracle's forward-mode gradient at a
     perturbed theta (1.3 sigma1^2, 0.8 range, 1.5 nugget) where the gradient
-    is far from zero. FP64: relative 1e-8 of max|g|; FP32: 1e-3 of max|g|."""
+    is far from zero. FP64: relative 1e-8 of max|g|; FP32: 1e-3 of max|g|;
+    BF16-input: 5e-2 of max|g|."""
     w = vi.scaled(vi.config1(), n, m=m, m_v=mv)
     X, Z, model = problem(w)
     theta = w.theta * np.array([1.3, 0.8, 1.5])
@@ -165,19 +203,23 @@ def test_gradient_matches_oracle(n, m, mv, prec):
     ctx = _ctx(w, precision=prec)
     ctx.build_factor(to_dev(X), to_dev(Z) if m else None, nbr_to_dev(nbr) if mv else None, theta)
     nll_g, g_g = ctx.nll_grad(to_dev(y), 3)
-    tol = 1e-8 if prec == "fp64" else 1e-3
+    tol = {"fp64": 1e-8, "fp32": 1e-3, "bf16_in": 5e-2}[prec]
     nerr = abs(nll_g - nll_o)
     if prec == "fp64":
         assert nerr <= 1e-10 * abs(nll_o), (nll_g, nll_o)
-    else:
+    elif prec == "fp32":
         assert nerr <= 1e-5 * max(abs(nll_o), n), (nll_g, nll_o)
+    else:
+        nll_r = vo.nll_gaussian_rounded_v(model, X, Z, nbr, y, vo.bf16_round)
+        assert abs(nll_g - nll_r) <= 1e-5 * max(abs(nll_o), n), (nll_g, nll_r)
+        assert nerr <= 3e-3 * max(abs(nll_o), n), (nll_g, nll_o)
     assert np.max(np.abs(g_g - g_o)) <= tol * np.max(np.abs(g_o)), (g_g, g_o)
     # a second call on the same factor is bit-identical (no atomics in the sums)
     nll_2, g_2 = ctx.nll_grad(to_dev(y), 3)
     assert nll_2 == nll_g and np.array_equal(g_2, g_g)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16_in"])
 def test_repeated_gradient_evaluations_match_fresh_contexts(prec):
     """After its first gradient a context starts the derivative whitening of
     each later build on a second stream; a sequence of build + gradient (and

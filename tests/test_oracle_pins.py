@@ -180,3 +180,56 @@ def test_not_positive_definite_is_reported():
     nbr = vo.neighbours(model, X, ind, 5)
     with pytest.raises(vo.NotPositiveDefinite):
         vo.vecchia_factor(model, X, ind, nbr)
+
+
+def test_bf16_round_is_nearest_even_bfloat16():
+    """bf16_round against torch's binary32 -> bfloat16 conversion (its own
+    round-to-nearest-even) over many magnitudes, and hand-checked ties: the
+    spacing of bfloat16 at 1 is 2^-7, so 1 + 2^-8 is a tie that goes to 1 and
+    1 + 3 2^-8 one that goes to 1 + 2^-6."""
+    import torch
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal(20000) * 10.0 ** rng.uniform(-8, 8, 20000)
+    ref = torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).double().numpy()
+    assert np.array_equal(vo.bf16_round(a), ref)
+    ties = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8), 2 + 2.0 ** -7])
+    assert np.array_equal(vo.bf16_round(ties), [1.0, 1 + 2.0 ** -6, -1.0, 2.0])
+    assert np.array_equal(vo.bf16_round([0.0, 1.0, -0.5, 2.0 ** -100]), [0.0, 1.0, -0.5, 2.0 ** -100])
+
+
+@pytest.mark.parametrize("m,mv", [(0, 5), (10, 6), (25, 3)])
+def test_whitened_nll_without_rounding_equals_nll(m, mv):
+    """The whitened evaluation (L_m^{-1} features, M' = I + G^T D^{-1} G)
+    with no rounding equals the Sigma_m^{-1} form of nll_gaussian and the
+    dense VIF NLL."""
+    model, X, Z, y = _small_problem(n=110, m=m)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, mv)
+    ref = vo.nll_gaussian(model, X, Z, nbr, y)
+    got = vo.nll_gaussian_rounded_v(model, X, Z, nbr, y, lambda v: v)
+    assert abs(got - ref.nll) <= 1e-11 * abs(ref.nll)
+    dense = dr.gaussian_nll_dense(dr.vif_cov(model, X, Z, nbr, ref.factor.A, ref.factor.D), y)
+    assert abs(got - dense) <= 1e-10 * abs(dense)
+
+
+def test_bf16_rounded_features_stay_within_the_form_bar():
+    """C1 with y from the exact GP: rounding V to bfloat16 moves the NLL by
+    ~1.5e-3 per point (the nugget 0.01 makes D_i small against the rounding
+    of V_a . V_b), inside the bar 3e-3 max(|NLL|, n) that the GPU tests use
+    for the BF16-input form against the unrounded oracle; rounding to binary32
+    instead moves it by less than 1e-5 per point."""
+    w = vi.config1()
+    rng = np.random.default_rng(4)
+    X = vi.coords(w)
+    Z = vi.inducing_points(w, X)
+    model = vo.Model.from_theta(w.kernel, w.theta, w.tau_m)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, w.m_v)
+    y = np.linalg.cholesky(dr.exact_cov(model, X)) @ rng.standard_normal(w.n)
+    ref = vo.nll_gaussian(model, X, Z, nbr, y).nll
+    e16 = abs(vo.nll_gaussian_rounded_v(model, X, Z, nbr, y, vo.bf16_round) - ref)
+    e32 = abs(vo.nll_gaussian_rounded_v(model, X, Z, nbr, y, lambda v: v.astype(np.float32).astype(np.float64)) - ref)
+    bar = max(abs(ref), w.n)
+    assert e16 <= 3e-3 * bar
+    assert e32 <= 1e-5 * bar
+    assert e16 > 10 * e32
