@@ -386,6 +386,173 @@ __global__ __launch_bounds__(CWG) void k_chol_inv(double* __restrict__ S, double
   }
 }
 
+// The same outputs for m_p <= 16 kRegNt, with the matrix held in registers.
+// The lower 16 x 16 tiles (i >= j, packed row order) are dealt round-robin
+// to the 8 waves; each wave keeps one register slot (4 doubles per lane) per
+// tile it owns. Step k (one tile column):
+//  1. the owner of A_kk factors and inverts it (chol_inv16): L_kk, X_kk;
+//  2. panel L_ik = A_ik X_kk^T (i > k) and row X_kj = X_kk B_kj (j < k) of
+//     X = L^{-1}, each from its owner's slot, published in LDS;
+//  3. trailing update A_ij -= L_ik L_jk^T (i >= j > k) and the right-hand
+//     side of L X = I, B_ij -= L_ik X_kj (i > k >= j), operands from LDS.
+// A slot holds A_ij (transposed accumulator layout: lane (c, g) has
+// A_ij[c][g + 4v], which is the MFMA B operand of A_ij^T) until its panel
+// step j, then B_ij (plain accumulator layout: B_ij[g + 4v][c]) until its
+// row step i. Entries beyond m are identity padding. Two barriers per step,
+// no global reads after the initial load.
+constexpr int kRegNt = 13;
+constexpr int kRegSlots = (kRegNt * (kRegNt + 1) / 2 + CNW - 1) / CNW;
+__global__ __launch_bounds__(CWG) void k_chol_inv_reg(double* __restrict__ S, double* __restrict__ Linv, int m,
+                                                       int mp, double* out, int* status, int code_base,
+                                                       int ostride) {
+  {
+    const size_t mo = (size_t)blockIdx.x * mp * mp;
+    S += mo;
+    Linv += mo;
+    out += (size_t)blockIdx.x * ostride;
+  }
+  constexpr int LP = 17;  // row pitch of the published tiles
+  __shared__ double P[kRegNt][16][LP];   // panel column k: L_ik, row-major
+  __shared__ double XR[kRegNt][16][LP];  // row k of X: X_kj, row-major
+  __shared__ double Dt[16][CB + 1], Lo[16][CB + 1], Xo[16][CB + 1];
+  __shared__ double Dbuf[2 * CB];
+  __shared__ double red[CNW];
+  __shared__ int s_fail;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c = lane & 15, g = lane >> 4;
+  const int nt = mp / 16, ntile = nt * (nt + 1) / 2;
+  if (tid == 0) s_fail = 0;
+  // entries of Linv outside the computed lower part are zero
+  for (int q = tid; q < mp * mp; q += CWG) {
+    const int R = q / mp, C = q % mp;
+    if (!(R < m && C < m && C <= R)) Linv[q] = 0.0;
+  }
+  int ti0[kRegSlots], tj0[kRegSlots];  // tile of each slot (ti0 = -1: none); wave-uniform
+  double r[kRegSlots][4];
+#pragma unroll
+  for (int s = 0; s < kRegSlots; ++s) {
+    const int t = w + CNW * s;
+    int i = 0, rem = t < ntile ? t : 0;
+    while (rem > i) { rem -= i + 1; ++i; }
+    ti0[s] = __builtin_amdgcn_readfirstlane(t < ntile ? i : -1);
+    tj0[s] = __builtin_amdgcn_readfirstlane(rem);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      // transposed layout: A[row c][col g + 4v] of tile (i, rem); lower part of the diagonal tiles only
+      const int R = i * 16 + c, C = rem * 16 + g + 4 * v;
+      const bool real = R < m && C < m && C <= R;
+      const double a = ldm(S, R, C, mp, real);
+      r[s][v] = real ? a : (R == C ? 1.0 : 0.0);
+    }
+  }
+  double ldacc = 0.0;  // sum of log L_jj over this wave's diagonal tiles
+  __syncthreads();
+  for (int k = 0; k < nt; ++k) {
+    // the slots' tile coordinates pass through an empty asm each step, so
+    // that the LDS addresses derived from them are formed in the step from
+    // scalars instead of being hoisted into (many) vector registers
+    int ti[kRegSlots], tj[kRegSlots];
+#pragma unroll
+    for (int s = 0; s < kRegSlots; ++s) {
+      ti[s] = ti0[s];
+      tj[s] = tj0[s];
+      asm volatile("" : "+s"(ti[s]), "+s"(tj[s]));
+    }
+    // 1. diagonal tile
+    const int tk = k * (k + 1) / 2 + k;
+    if (w == tk % CNW) {
+      const int sk = tk / CNW;
+#pragma unroll
+      for (int s = 0; s < kRegSlots; ++s)
+        if (s == sk)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Dt[c][g + 4 * v] = r[s][v];
+      wave_sync();
+      const int fail = chol_inv16(&Dt[0][0], &Lo[0][0], &Xo[0][0], Dbuf, lane);
+      if (fail) {
+        if (lane == 0) s_fail = k * 16 + fail;
+      } else {
+        for (int q = lane; q < 256; q += 64) {
+          const int rr = q >> 4, cc = q & 15, R = k * 16 + rr, C = k * 16 + cc;
+          if (R < m && cc <= rr) {
+            S[(size_t)R * mp + C] = Lo[rr][cc];
+            Linv[(size_t)R * mp + C] = Xo[rr][cc];
+          }
+        }
+        if (g == 0 && k * 16 + c < m) ldacc += log(Lo[c][c]);
+      }
+    }
+    __syncthreads();
+    if (s_fail) {
+      if (tid == 0) {
+        status[0] = VIF_DEV_NOT_PD;
+        status[1] = code_base;
+        status[2] = s_fail - 1;
+        status[5] = blockIdx.x;
+      }
+      return;
+    }
+    // 2. panel column k and row k of X
+#pragma unroll
+    for (int s = 0; s < kRegSlots; ++s) {
+      if (tj[s] == k && ti[s] > k) {  // L_ik^T = X_kk A_ik^T
+        d4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int st = 0; st < 4; ++st) acc = mfma16(Xo[c][4 * st + g], r[s][st], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int C = g + 4 * v;
+          P[ti[s]][c][C] = acc[v];
+          const int R = ti[s] * 16 + c;
+          if (R < m && k * 16 + C < m) S[(size_t)R * mp + k * 16 + C] = acc[v];
+          r[s][v] = 0.0;  // the slot now holds B_ik
+        }
+      } else if (ti[s] == k && tj[s] < k) {  // X_kj = X_kk B_kj
+        d4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int st = 0; st < 4; ++st) acc = mfma16(Xo[c][4 * st + g], r[s][st], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = g + 4 * v;
+          XR[tj[s]][rr][c] = acc[v];
+          const int R = k * 16 + rr, C = tj[s] * 16 + c;
+          if (R < m && C < m) Linv[(size_t)R * mp + C] = acc[v];
+        }
+      }
+    }
+    if (w == tk % CNW)
+      for (int q = lane; q < 256; q += 64) XR[k][q >> 4][q & 15] = Xo[q >> 4][q & 15];
+    __syncthreads();
+    // 3. trailing update and right-hand side update
+#pragma unroll
+    for (int s = 0; s < kRegSlots; ++s) {
+      if (tj[s] > k) {  // A_ij^T -= L_jk L_ik^T
+        d4 acc = {r[s][0], r[s][1], r[s][2], r[s][3]};
+#pragma unroll
+        for (int st = 0; st < 4; ++st) acc = mfma16(-P[tj[s]][c][4 * st + g], P[ti[s]][c][4 * st + g], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) r[s][v] = acc[v];
+      } else if (ti[s] > k) {  // B_ij -= L_ik X_kj  (j <= k)
+        d4 acc = {r[s][0], r[s][1], r[s][2], r[s][3]};
+#pragma unroll
+        for (int st = 0; st < 4; ++st) acc = mfma16(-P[ti[s]][c][4 * st + g], XR[tj[s]][4 * st + g][c], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) r[s][v] = acc[v];
+      }
+    }
+  }
+  // log det = 2 sum log L_jj
+  ldacc = wave_sum(ldacc);
+  if (lane == 0) red[w] = ldacc;
+  __syncthreads();
+  if (tid == 0) {
+    double sacc = 0.0;
+    for (int q = 0; q < CNW; ++q) sacc += red[q];
+    out[0] = 2.0 * sacc;
+  }
+}
+
 // M' = I + scale * sum_chunks partial over the lower triangle (every entry c <= l is
 // written by k_gram_partial) -- one thread per element.
 __global__ void k_reduce_gram(const double* partial, int nchunk, int mp, double scale, double* Mp, Batch bt) {
@@ -440,7 +607,10 @@ void launch_cov_zz(hipStream_t st, const double* Z, int m, int mp, const CovPara
 }
 void launch_chol_inv(hipStream_t st, double* S, double* Linv, double* work, int m, int mp, double* out, int* status,
                      int code, int nmat, int ostride) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(nmat), dim3(CWG), 0, st, S, Linv, work, m, mp, out, status, code, ostride);
+  if (mp <= 16 * kRegNt)
+    hipLaunchKernelGGL(k_chol_inv_reg, dim3(nmat), dim3(CWG), 0, st, S, Linv, m, mp, out, status, code, ostride);
+  else
+    hipLaunchKernelGGL(k_chol_inv, dim3(nmat), dim3(CWG), 0, st, S, Linv, work, m, mp, out, status, code, ostride);
 }
 void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp, double scale, Batch bt,
                         int nprob) {
