@@ -120,6 +120,20 @@ __device__ __forceinline__ double strided_sum(const double* __restrict__ p, int 
   return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
+// Sum over `count` chunk partials p[c * stride] of one entry, split over the
+// four waves of a 256-thread workgroup (wave g takes chunks g, g + 4, ...,
+// each with eight loads in flight); the wave sums are added in a fixed order
+// through LDS (red: 4 x 64 doubles). Every thread of the block must call it;
+// `act` says whether this thread's entry exists. The result is valid in wave 0.
+__device__ __forceinline__ double chunk_sum4(const double* __restrict__ p, int count, size_t stride, bool act,
+                                             double (*red)[64]) {
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int cnt = (count - g + 3) / 4;  // chunks g, g + 4, ... below count
+  red[g][lane] = act ? strided_sum(p + (size_t)g * stride, cnt, 4 * stride) : 0.0;
+  __syncthreads();
+  return (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -56,92 +56,122 @@ __device__ __forceinline__ double ldm(const double* M, int i, int j, int mp, boo
 #define CWG 512
 #define CNW (CWG / 64)
 
+// value of v in lane src (src uniform across the wave)
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, src);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sqrt(d) and 1/sqrt(d) for d > 0: the hardware reciprocal square root
+// refined by two Newton steps y <- y + y (1 - d y^2) / 2 (each doubles the
+// correct bits, so about 2^-22 becomes full double precision), and
+// sqrt(d) = d y; both within two ulps, without the long correctly rounded
+// division and square-root sequences on the factorisation's critical path
+__device__ __forceinline__ void sqrt_rsqrt(double d, double& sq, double& rs) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  rs = y;
+  sq = d * y;
+}
+
+// value of v in lane src of each row of 16 lanes, for every lane of that row
+// (DPP row_newbcast; src a constant once the caller's loops are unrolled)
+__device__ __forceinline__ int row_bcast_i(int v, int src) {
+  switch (src) {
+    case 0: return __builtin_amdgcn_update_dpp(v, v, 0x150, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_update_dpp(v, v, 0x151, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(v, v, 0x152, 0xF, 0xF, false);
+    case 3: return __builtin_amdgcn_update_dpp(v, v, 0x153, 0xF, 0xF, false);
+    case 4: return __builtin_amdgcn_update_dpp(v, v, 0x154, 0xF, 0xF, false);
+    case 5: return __builtin_amdgcn_update_dpp(v, v, 0x155, 0xF, 0xF, false);
+    case 6: return __builtin_amdgcn_update_dpp(v, v, 0x156, 0xF, 0xF, false);
+    case 7: return __builtin_amdgcn_update_dpp(v, v, 0x157, 0xF, 0xF, false);
+    case 8: return __builtin_amdgcn_update_dpp(v, v, 0x158, 0xF, 0xF, false);
+    case 9: return __builtin_amdgcn_update_dpp(v, v, 0x159, 0xF, 0xF, false);
+    case 10: return __builtin_amdgcn_update_dpp(v, v, 0x15A, 0xF, 0xF, false);
+    case 11: return __builtin_amdgcn_update_dpp(v, v, 0x15B, 0xF, 0xF, false);
+    case 12: return __builtin_amdgcn_update_dpp(v, v, 0x15C, 0xF, 0xF, false);
+    case 13: return __builtin_amdgcn_update_dpp(v, v, 0x15D, 0xF, 0xF, false);
+    case 14: return __builtin_amdgcn_update_dpp(v, v, 0x15E, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_update_dpp(v, v, 0x15F, 0xF, 0xF, false);
+  }
+}
+__device__ __forceinline__ double row_bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = row_bcast_i((int)b, src), hi = row_bcast_i((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Cholesky and inverse of one SPD 16 x 16 tile on one wave. T (input, lower
 // part read), Lo and Xo are row-major with row stride CB + 1; Lo gets L and
-// Xo gets L^{-1} (upper parts zero). The 136 entries of the lower triangle
-// are dealt to the 64 lanes (entry e = lane + 64 s in packed row order) and
-// kept in registers. The factorisation runs as LDL^T (one reciprocal per
-// step, square roots applied at the end); the inverse goes row by row (row u
-// is final once scaled by 1/L_uu; every later row t subtracts L_tu times it).
-// Each step is one LDS broadcast and a branch-free update of the lane's
-// entries. buf: 32 doubles of LDS. Returns 0, or 1 + the column whose pivot
-// was not positive.
-__device__ int chol_inv16(const double* T, double* Lo, double* Xo, double* buf, int lane) {
+// Xo gets L^{-1} (upper parts zero). Each row of 16 lanes holds the whole
+// tile, one matrix row per lane, and all exchanges are DPP broadcasts within
+// the row (no LDS round trips, no barriers). Factorisation by columns: at
+// step b row i forms s_i = T_ib - sum_{q<b} L_iq L_bq (L_bq broadcast from
+// lane b), the pivot s_b likewise, L_bb = sqrt(s_b), L_ib = s_i / L_bb.
+// Inverse by columns, one column j per lane: X_tj = (delta_tj -
+// sum_{j<=q<t} L_tq X_qj) / L_tt, the L_tq and 1/L_tt broadcast from lane t.
+// A failed pivot is recorded and the remaining (NaN) arithmetic discarded.
+// Returns 0, or 1 + the first column whose pivot was not positive.
+__device__ __forceinline__ int chol_inv16(const double* T, double* Lo, double* Xo, double* buf, int lane) {
+  (void)buf;
   constexpr int LD = CB + 1;
-  int ei[3], ej[3];
-  double a[3];
+  const int i = lane & 15;
+  double a[16];
 #pragma unroll
-  for (int sl = 0; sl < 3; ++sl) {
-    const int e = lane + 64 * sl;
-    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= e) ++i;
-    while (i * (i + 1) / 2 > e) --i;
-    const bool ok = e < 136;
-    ei[sl] = ok ? i : 16;  // 16 marks an unused slot
-    ej[sl] = ok ? e - i * (i + 1) / 2 : 16;
-    a[sl] = ok ? T[ei[sl] * LD + ej[sl]] : 0.0;
+  for (int j = 0; j < 16; ++j) {
+    const double v = T[i * LD + j];
+    a[j] = (j <= i) ? v : 0.0;
   }
-  for (int k = 0; k < 16; ++k) {
-    double* col = buf + 16 * (k & 1);
+  int fail = 0;
+  double myrd = 0.0;  // 1 / L_ii
 #pragma unroll
-    for (int sl = 0; sl < 3; ++sl)
-      if (ej[sl] == k) col[ei[sl]] = a[sl];
-    wave_sync();
-    const double akk = col[k];
-    double ci[3], cj[3];
+  for (int b = 0; b < 16; ++b) {
+    double s0 = a[b], s1 = 0.0;
 #pragma unroll
-    for (int sl = 0; sl < 3; ++sl) {
-      ci[sl] = col[min(ei[sl], 15)];
-      cj[sl] = col[min(ej[sl], 15)];
+    for (int q = 0; q < b; ++q) {
+      const double lbq = row_bcast(a[q], b);
+      if (q & 1)
+        s1 = fma(-a[q], lbq, s1);
+      else
+        s0 = fma(-a[q], lbq, s0);
     }
-    if (!(akk > 0.0 && isfinite(akk))) return k + 1;
-    const double rk = 1.0 / akk;
-#pragma unroll
-    for (int sl = 0; sl < 3; ++sl) {
-      const double upd = fma(-ci[sl] * rk, cj[sl], a[sl]);
-      a[sl] = (ej[sl] > k && ej[sl] < 16) ? upd : a[sl];
-    }
+    const double sv = s0 + s1;
+    const double d = row_bcast(sv, b);
+    if (!(d > 0.0 && d < __builtin_huge_val()) && fail == 0) fail = b + 1;
+    double lbb, il;
+    sqrt_rsqrt(d, lbb, il);
+    if (i == b) myrd = il;
+    a[b] = (i == b) ? lbb : (i > b ? sv * il : 0.0);
   }
-  wave_sync();
+  fail = __builtin_amdgcn_readfirstlane(fail);
+  if (fail) return fail;
+  // column j = i of X: x[t] = X_tj
+  double x[16];
 #pragma unroll
-  for (int sl = 0; sl < 3; ++sl)
-    if (ei[sl] == ej[sl] && ei[sl] < 16) {
-      const double sq = sqrt(a[sl]);
-      buf[ei[sl]] = sq;
-      buf[16 + ei[sl]] = 1.0 / sq;
+  for (int t = 0; t < 16; ++t) {
+    double s0 = (t == i) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < t; ++q) {
+      const double ltq = row_bcast(a[q], t);
+      if (q & 1)
+        s1 = fma(-ltq, x[q], s1);
+      else
+        s0 = fma(-ltq, x[q], s0);
     }
-  for (int q = lane; q < 256; q += 64) {
-    Lo[(q >> 4) * LD + (q & 15)] = 0.0;
-    Xo[(q >> 4) * LD + (q & 15)] = 0.0;
+    x[t] = (t < i) ? 0.0 : (s0 + s1) * row_bcast(myrd, t);
   }
-  wave_sync();
+  if (lane < 16) {
 #pragma unroll
-  for (int sl = 0; sl < 3; ++sl) {
-    const int jj = min(ej[sl], 15);
-    a[sl] = (ei[sl] == ej[sl]) ? buf[jj] : a[sl] * buf[16 + jj];
-    if (ei[sl] < 16) Lo[ei[sl] * LD + ej[sl]] = a[sl];
-    a[sl] = (ei[sl] == ej[sl]) ? 1.0 : 0.0;
-  }
-  wave_sync();
-  for (int u = 0; u < 16; ++u) {
-    const double iu = buf[16 + u];
-#pragma unroll
-    for (int sl = 0; sl < 3; ++sl)
-      if (ei[sl] == u) {
-        a[sl] *= iu;
-        Xo[u * LD + ej[sl]] = a[sl];
-      }
-    wave_sync();
-    double lt[3], rv[3];
-#pragma unroll
-    for (int sl = 0; sl < 3; ++sl) {
-      lt[sl] = Lo[min(ei[sl], 15) * LD + u];
-      rv[sl] = Xo[u * LD + min(ej[sl], 15)];
-    }
-#pragma unroll
-    for (int sl = 0; sl < 3; ++sl) {
-      const double upd = fma(-lt[sl], rv[sl], a[sl]);
-      a[sl] = (ei[sl] > u && ei[sl] < 16 && ej[sl] <= u) ? upd : a[sl];
+    for (int t = 0; t < 16; ++t) {
+      Lo[i * LD + t] = a[t];
+      Xo[t * LD + i] = x[t];
     }
   }
   wave_sync();
@@ -423,11 +453,10 @@ __global__ __launch_bounds__(CWG) void k_chol_inv_reg(double* __restrict__ S, do
   const int c = lane & 15, g = lane >> 4;
   const int nt = mp / 16, ntile = nt * (nt + 1) / 2;
   if (tid == 0) s_fail = 0;
-  // entries of Linv outside the computed lower part are zero
-  for (int q = tid; q < mp * mp; q += CWG) {
-    const int R = q / mp, C = q % mp;
-    if (!(R < m && C < m && C <= R)) Linv[q] = 0.0;
-  }
+  // entries of Linv outside the computed lower part are zero (row R by wave, columns by lane)
+  for (int R = w; R < mp; R += CNW)
+    for (int C = lane; C < mp; C += 64)
+      if (!(R < m && C < m && C <= R)) Linv[(size_t)R * mp + C] = 0.0;
   int ti0[kRegSlots], tj0[kRegSlots];  // tile of each slot (ti0 = -1: none); wave-uniform
   double r[kRegSlots][4];
 #pragma unroll
@@ -437,15 +466,25 @@ __global__ __launch_bounds__(CWG) void k_chol_inv_reg(double* __restrict__ S, do
     while (rem > i) { rem -= i + 1; ++i; }
     ti0[s] = __builtin_amdgcn_readfirstlane(t < ntile ? i : -1);
     tj0[s] = __builtin_amdgcn_readfirstlane(rem);
+  }
+  // every slot's entries loaded together (one round trip), then masked:
+  // transposed layout A[row c][col g + 4v] of tile (ti0, tj0), lower part of
+  // the diagonal tiles only, identity padding beyond m
+#pragma unroll
+  for (int s = 0; s < kRegSlots; ++s)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      // transposed layout: A[row c][col g + 4v] of tile (i, rem); lower part of the diagonal tiles only
-      const int R = i * 16 + c, C = rem * 16 + g + 4 * v;
-      const bool real = R < m && C < m && C <= R;
-      const double a = ldm(S, R, C, mp, real);
-      r[s][v] = real ? a : (R == C ? 1.0 : 0.0);
+      const int R = max(ti0[s], 0) * 16 + c, C = tj0[s] * 16 + g + 4 * v;
+      r[s][v] = S[(size_t)min(R, mp - 1) * mp + min(C, mp - 1)];
     }
-  }
+#pragma unroll
+  for (int s = 0; s < kRegSlots; ++s)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int R = max(ti0[s], 0) * 16 + c, C = tj0[s] * 16 + g + 4 * v;
+      const bool real = R < m && C < m && C <= R;
+      r[s][v] = real ? r[s][v] : (R == C ? 1.0 : 0.0);
+    }
   double ldacc = 0.0;  // sum of log L_jj over this wave's diagonal tiles
   __syncthreads();
   for (int k = 0; k < nt; ++k) {
@@ -555,18 +594,21 @@ __global__ __launch_bounds__(CWG) void k_chol_inv_reg(double* __restrict__ S, do
 
 // M' = I + scale * sum_chunks partial over the lower triangle (every entry c <= l is
 // written by k_gram_partial) -- one thread per element.
-__global__ void k_reduce_gram(const double* partial, int nchunk, int mp, double scale, double* Mp, Batch bt) {
+__global__ __launch_bounds__(256) void k_reduce_gram(const double* partial, int nchunk, int mp, double scale,
+                                                     double* Mp, Batch bt) {
+  __shared__ double red[4][64];
   if (bt.bp) {  // problem blockIdx.y: its chunk range
     const BatchProb& pb = bt.bp[blockIdx.y];
     partial += (size_t)pb.cbeg * mp * mp;
     nchunk = pb.nchunk;
     Mp += (size_t)blockIdx.y * mp * mp;
   }
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= (int64_t)mp * mp) return;
+  // 64 entries per workgroup, their chunk sums split over the 4 waves
+  const int64_t q = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
   const int l = (int)(q / mp), c = (int)(q % mp);
-  const double s = (c <= l) ? strided_sum(partial + q, nchunk, (size_t)mp * mp) : 0.0;
-  Mp[q] = ((l == c) ? 1.0 : 0.0) + scale * s;
+  const bool inside = q < (int64_t)mp * mp;
+  const double s = chunk_sum4(partial + (inside ? q : 0), nchunk, (size_t)mp * mp, inside && c <= l, red);
+  if (threadIdx.x < 64 && inside) Mp[q] = ((l == c) ? 1.0 : 0.0) + (c <= l ? scale * s : 0.0);
 }
 
 // Final Gaussian NLL. vec[0..mp) holds U^T yt, scal[0] = sum log D,
@@ -615,7 +657,7 @@ void launch_chol_inv(hipStream_t st, double* S, double* Linv, double* work, int 
 void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp, double scale, Batch bt,
                         int nprob) {
   const int64_t total = (int64_t)mp * mp;
-  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)ceil_div(total, 256), nprob), dim3(256), 0, st, partial, nchunk,
+  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)ceil_div(total, 64), nprob), dim3(256), 0, st, partial, nchunk,
                      mp, scale, Mp, bt);
 }
 void launch_nll_final(hipStream_t st, const double* LMinv, const double* vec, const double* scal, int m, int mp,

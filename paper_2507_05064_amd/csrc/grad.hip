@@ -329,19 +329,25 @@ __global__ __launch_bounds__(512) void k_cross3_tiles(const S* __restrict__ V, c
 }
 
 // out = sum of the partials' lower triangles, mirrored to a full symmetric matrix
-__global__ void k_reduce_sym(const double* __restrict__ partial, int nchunk, int mp, double* __restrict__ out,
-                             Batch bt) {
+__global__ __launch_bounds__(256) void k_reduce_sym(const double* __restrict__ partial, int nchunk, int mp,
+                                                    double* __restrict__ out, Batch bt) {
+  __shared__ double red[4][64];
   if (bt.bp) {  // problem blockIdx.y: its chunk range
     const BatchProb& pb = bt.bp[blockIdx.y];
     partial += (size_t)pb.cbeg * mp * mp;
     nchunk = pb.nchunk;
     out += (size_t)blockIdx.y * mp * mp;
   }
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= (int64_t)mp * mp) return;
+  // 64 entries per workgroup, their chunk sums split over the 4 waves; only
+  // the lower triangle is summed, and written to both mirror positions
+  const int64_t q = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
   const int l = (int)(q / mp), c = (int)(q % mp);
-  const size_t src = (c <= l) ? (size_t)q : (size_t)c * mp + l;
-  out[q] = strided_sum(partial + src, nchunk, (size_t)mp * mp);
+  const bool act = q < (int64_t)mp * mp && c <= l;
+  const double s = chunk_sum4(partial + (act ? q : 0), nchunk, (size_t)mp * mp, act, red);
+  if (threadIdx.x < 64 && act) {
+    out[q] = s;
+    out[(size_t)c * mp + l] = s;
+  }
 }
 
 // -1/2 sum_ab Tm_ab dSigma_m[a][b]/dtheta for (sigma1^2, range): one block per row.
@@ -522,7 +528,7 @@ void launch_cross3_partial(hipStream_t st, const S* V, const T* Q1, const T* U, 
 }
 void launch_reduce_sym(hipStream_t st, const double* partial, int nchunk, int mp, double* out, Batch bt, int nprob) {
   const int64_t total = (int64_t)mp * mp;
-  hipLaunchKernelGGL(k_reduce_sym, dim3((unsigned)ceil_div(total, 256), nprob), dim3(256), 0, st, partial, nchunk, mp,
+  hipLaunchKernelGGL(k_reduce_sym, dim3((unsigned)ceil_div(total, 64), nprob), dim3(256), 0, st, partial, nchunk, mp,
                      out, bt);
 }
 void launch_sigma_m_grad(hipStream_t st, const double* Tm, const double* Z, int m, int mp, const CovParams& p,

@@ -194,17 +194,20 @@ __global__ __launch_bounds__(256) void k_uty_partial(const T* __restrict__ U, co
   }
 }
 
-__global__ void k_vec_reduce(const double* __restrict__ partial, int nchunk, int len, double* __restrict__ out,
-                             Batch bt) {
+__global__ __launch_bounds__(256) void k_vec_reduce(const double* __restrict__ partial, int nchunk, int len,
+                                                    double* __restrict__ out, Batch bt) {
+  __shared__ double red[4][64];
   if (bt.bp) {  // problem blockIdx.y: its chunk range; outputs len apart
     const BatchProb& pb = bt.bp[blockIdx.y];
     partial += (size_t)pb.cbeg * len;
     nchunk = pb.nchunk;
     out += (size_t)blockIdx.y * len;
   }
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= len) return;
-  out[j] = strided_sum(partial + j, nchunk, (size_t)len);
+  // 64 entries per workgroup, their chunk sums split over the 4 waves
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+  const bool act = j < len;
+  const double s = chunk_sum4(partial + (act ? j : 0), nchunk, (size_t)len, act, red);
+  if (threadIdx.x < 64 && act) out[j] = s;
 }
 
 template <typename T>
@@ -236,7 +239,7 @@ void launch_uty_partial(hipStream_t st, const T* U, const double* yt, const doub
 }
 
 void launch_vec_reduce(hipStream_t st, const double* partial, int nchunk, int len, double* out, Batch bt, int nprob) {
-  hipLaunchKernelGGL(k_vec_reduce, dim3((unsigned)ceil_div(len, 256), nprob), dim3(256), 0, st, partial, nchunk, len,
+  hipLaunchKernelGGL(k_vec_reduce, dim3((unsigned)ceil_div(len, 64), nprob), dim3(256), 0, st, partial, nchunk, len,
                      out, bt);
 }
 
