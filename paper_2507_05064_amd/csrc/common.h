@@ -68,6 +68,27 @@ __device__ __forceinline__ T cov_profile_dls(int kernel, T t2, T inv_ls) {
   return T(3) * t2 * exp(-s3 * t) * inv_ls;                         // 3 t^2 e^{-sqrt3 t} / lambda
 }
 
+// FP32 forms of both: the hardware exponential (2^x) and square root, each
+// within two ulps, instead of the correctly rounded library sequences; the
+// FP32 form's per-point systems carry ~1e-5 relative error, far above this
+__device__ __forceinline__ float fast_expf(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+template <>
+__device__ __forceinline__ float cov_profile<float>(int kernel, float t2) {
+  if (kernel == 2) return fast_expf(-0.5f * t2);
+  const float t = __builtin_amdgcn_sqrtf(t2);
+  if (kernel == 0) return fast_expf(-t);
+  const float s3 = 1.7320508075688772f;
+  return (1.0f + s3 * t) * fast_expf(-s3 * t);
+}
+template <>
+__device__ __forceinline__ float cov_profile_dls<float>(int kernel, float t2, float inv_ls) {
+  const float t = __builtin_amdgcn_sqrtf(t2);
+  if (kernel == 2) return t2 * fast_expf(-0.5f * t2) * inv_ls;
+  if (kernel == 0) return t * fast_expf(-t) * inv_ls;
+  const float s3 = 1.7320508075688772f;
+  return 3.0f * t2 * fast_expf(-s3 * t) * inv_ls;
+}
+
 template <typename T>
 __device__ __forceinline__ T scaled_sqdist(const CovParams& p, const double* a, const double* b) {
   T s = 0;

@@ -173,7 +173,7 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
   const int myrow = lane & 31;
   const int ne = (k + 1) * (k + 2) / 2;
   for (int e = lane; e < ne; e += 64) {
-    int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    int a = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);  // corrected below
     while ((a + 1) * (a + 2) / 2 <= e) ++a;
     while (a * (a + 1) / 2 > e) --a;
     const int b = e - a * (a + 1) / 2;
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   {
     const int ne = (k + 1) * (k + 2) / 2;
     for (int e = lane; e < ne; e += 64) {
-      int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+      int a = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);  // corrected below
       while ((a + 1) * (a + 2) / 2 <= e) ++a;
       while (a * (a + 1) / 2 > e) --a;
       const int b = e - a * (a + 1) / 2;
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
   {
     const int ne = (k + 1) * (k + 2) / 2;
     for (int e = lane; e < ne; e += 64) {
-      int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+      int a = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);  // corrected below
       while ((a + 1) * (a + 2) / 2 <= e) ++a;
       while (a * (a + 1) / 2 > e) --a;
       const int b = e - a * (a + 1) / 2;
