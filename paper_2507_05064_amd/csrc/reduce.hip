@@ -41,21 +41,32 @@ __global__ __launch_bounds__(256) void k_gram_partial(const T* __restrict__ U, i
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = A4{0, 0, 0, 0};
-  for (int64_t p0 = pbeg; p0 < pend; p0 += 4) {
-    const int64_t pp = p0 + g;
-    const bool pv = pp < pend;
-    const T* row = U + (size_t)(pv ? pp : pbeg) * mp;
-    T a[2], b[2];
+  // 16 points per iteration: their 16 loads per lane issue together
+  for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
+    T a[4][2], b[4][2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {  // unconditional in-range loads, so they issue together
-      const T av = row[min(L0 + 16 * t + r, mp - 1)], bv = row[min(C0 + 16 * t + r, mp - 1)];
-      a[t] = (pv && rok[t]) ? av : T(0);
-      b[t] = (pv && cok[t]) ? bv : T(0);
+    for (int u = 0; u < 4; ++u) {
+      const int64_t pp = p0 + 4 * u + g;
+      const T* row = U + (size_t)(pp < pend ? pp : pbeg) * mp;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {  // unconditional in-range loads
+        a[u][t] = row[min(L0 + 16 * t + r, mp - 1)];
+        b[u][t] = row[min(C0 + 16 * t + r, mp - 1)];
+      }
     }
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int u = 0; u < 4; ++u) {
+      const bool pv = p0 + 4 * u + g < pend;
 #pragma unroll
-      for (int y = 0; y < 2; ++y) acc[x][y] = mfma16(a[x], b[y], acc[x][y]);
+      for (int t = 0; t < 2; ++t) {
+        a[u][t] = (pv && rok[t]) ? a[u][t] : T(0);
+        b[u][t] = (pv && cok[t]) ? b[u][t] : T(0);
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = mfma16(a[u][x], b[u][y], acc[x][y]);
+    }
   }
   double* out = partial + (size_t)blockIdx.x * mp * mp;
 #pragma unroll
