@@ -5,9 +5,8 @@
 // One workgroup = 64 points x 128 rows of V (blockIdx.y picks the rows);
 // each wave owns 16 points and the 8 row blocks of 16. The columns j of
 // K(Z, x) are taken 16 at a time: the workgroup stages the matching 128 x 16
-// slice of L_m^{-1} (lower triangular, zero padded to mp) in LDS with
-// coalesced loads, transposed so that the MFMA A operand reads 16
-// consecutive rows; each lane evaluates the four K(z_j, x_p) it feeds as the
+// slice of L_m^{-1} (lower triangular, zero padded to mp) in LDS,
+// transposed so that the MFMA A operand reads 16 consecutive rows; each lane evaluates the four K(z_j, x_p) it feeds as the
 // B operand of FP64 MFMA 16x16x4. Blocks above the diagonal are skipped.
 // Always FP64 arithmetic; the store casts to the storage type (FP64, FP32
 // or BF16).
@@ -43,17 +42,24 @@ __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ X, co
 #pragma unroll
   for (int r = 0; r < 8; ++r) acc[r] = d4{0.0, 0.0, 0.0, 0.0};
   const int jmax = min(m, l0 + nrb * 16);
-  // staging: thread -> (row, 2 consecutive columns); 8 threads cover a row's 16 columns
-  const int srow = tid >> 3, scol = 2 * (tid & 7);
+  // staging: thread -> (row srr, 8 consecutive columns from 8 shalf); in each
+  // LDS store the lanes of a wave write consecutive rows of one column, i.e.
+  // consecutive addresses (no bank conflicts)
+  const int srr = tid & (WROWS - 1), shalf = tid / WROWS;
   for (int jc = 0; jc < jmax; jc += WJC) {
     __syncthreads();
+    {
+      double2 v[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+      if (srr < nrb * 16) {
+        const double* src = Linv + (size_t)(l0 + srr) * mp + jc + 8 * shalf;
 #pragma unroll
-    for (int pass = 0; pass < WROWS / 32; ++pass) {
-      const int rr = srow + 32 * pass;
-      double2 v = {0.0, 0.0};
-      if (rr < nrb * 16) v = *reinterpret_cast<const double2*>(Linv + (size_t)(l0 + rr) * mp + jc + scol);
-      Ls[scol][rr] = v.x;
-      Ls[scol + 1][rr] = v.y;
+        for (int k = 0; k < 4; ++k) v[k] = *reinterpret_cast<const double2*>(src + 2 * k);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Ls[8 * shalf + 2 * k][srr] = v[k].x;
+        Ls[8 * shalf + 2 * k + 1][srr] = v[k].y;
+      }
     }
     double bv[WJC / 4];
 #pragma unroll
