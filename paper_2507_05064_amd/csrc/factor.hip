@@ -66,6 +66,15 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// the lane id passed through an empty asm: per-lane comparisons with it are
+// formed at each use, instead of being shared across the unrolled loops and
+// kept live in (spilled) scalar registers
+__device__ __forceinline__ int fresh_lane() {
+  int l = threadIdx.x;
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -200,12 +209,14 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
       T s = Lrow[b];
 #pragma unroll
       for (int q = 0; q < b; ++q) s -= Lrow[q] * Ls[b][q];
-      // a pivot below 32 ulps of the diagonal it came from is numerically zero
-      const bool piv_ok = (s > Lrow[b] * T(32) * PivEps<T>::value) && isfinite(s);
-      ok = __ballot(lane == b && piv_ok) != 0;
+      // the pivot s_b and the diagonal C_bb it came from (uniform); a pivot
+      // below 32 ulps of that diagonal is numerically zero
+      const T sb = lane_bcast(s, b), cb = lane_bcast(Lrow[b], b);
+      ok = (sb > cb * T(32) * PivEps<T>::value) && (sb < T(__builtin_huge_valf()));
       T lbb, il;
-      sqrt_and_rsqrt(lane_bcast(s, b), lbb, il);
-      if (ok && active && lane >= b) Lrow[b] = (lane == b) ? lbb : s * il;
+      sqrt_and_rsqrt(sb, lbb, il);
+      const int lid = fresh_lane();
+      if (ok && active && lid >= b) Lrow[b] = (lid == b) ? lbb : s * il;
       if (active) Ls[myrow][b] = Lrow[b];
       wave_sync();
     }
@@ -225,8 +236,9 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
   T Ab = 0;
   for (int a = k - 1; a >= 0; --a) {
     const T Aa = lane_bcast(accv * rdiag, a);
-    if (lane == a) Ab = Aa;
-    if (lane < a) accv -= Ls[a][myrow] * Aa;
+    const int lid = fresh_lane();
+    if (lid == a) Ab = Aa;
+    if (lid < a) accv -= Ls[a][myrow] * Aa;
   }
   if (lane < 32) sh.As[lane] = Ab;
   __syncthreads();
@@ -354,8 +366,9 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   for (int q = 0; q < 32; ++q) {
     if (q < k) {
       const T zq = lane_bcast(accz * rdiag, q);
-      if (lane == q) z = zq;
-      if (lane > q && lane < k) accz -= Lrow[q] * zq;
+      const int lid = fresh_lane();
+      if (lid == q) z = zq;
+      if (lid > q && lid < k) accz -= Lrow[q] * zq;
     }
   }
   // a' = L_R^{-T} z
@@ -363,8 +376,9 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
   T ap = 0;
   for (int a = k - 1; a >= 0; --a) {
     const T xa = lane_bcast(acc * rdiag, a);
-    if (lane == a) ap = xa;
-    if (lane < a) acc -= Ls[a][myrow] * xa;
+    const int lid = fresh_lane();
+    if (lid == a) ap = xa;
+    if (lid < a) acc -= Ls[a][myrow] * xa;
   }
   const T Aj = (lane < k) ? sh.As[myrow] : T(0);
   const T rho = (lane < k) ? ap - Dbar * Aj : T(0);
@@ -575,15 +589,17 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
   for (int q = 0; q < 32; ++q) {
     if (q < k) {
       const T zq = lane_bcast(accz * rdiag, q);
-      if (lane == q) z = zq;
-      if (lane > q && lane < k) accz -= Lrow[q] * zq;
+      const int lid = fresh_lane();
+      if (lid == q) z = zq;
+      if (lid > q && lid < k) accz -= Lrow[q] * zq;
     }
   }
   T acc = (lane < k) ? z : T(0), x = 0;
   for (int a = k - 1; a >= 0; --a) {
     const T xa = lane_bcast(acc * rdiag, a);
-    if (lane == a) x = xa;
-    if (lane < a) acc -= Ls[a][myrow] * xa;
+    const int lid = fresh_lane();
+    if (lid == a) x = xa;
+    if (lid < a) acc -= Ls[a][myrow] * xa;
   }
   if (lane < 32) dAs[lane] = (lane < k) ? x : T(0);
   __syncthreads();
