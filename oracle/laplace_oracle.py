@@ -258,6 +258,71 @@ def vifdu_logdet(prior: LatentVIF, W: np.ndarray) -> float:
 
 
 # ----------------------------------------------------------------------------
+# FITC preconditioner (Sec. 4.3.2; App. E.2) with the VIF's own inducing
+# points (k = m), used on the system of eq. pcls2
+# ----------------------------------------------------------------------------
+
+def fitc_dv(model: vo.Model, prior: LatentVIF, W: np.ndarray) -> np.ndarray:
+    """D_V = diag(Sigma - Sigma_kn^T Sigma_k^{-1} Sigma_kn) + W^{-1}; Sigma is the
+    covariance the VIF approximates (its diagonal sigma1^2 + s2, with the latent
+    jitter s2 = tau)."""
+    return (model.sigma1_sq + model.s2) - prior.ind.qdiag + 1.0 / W
+
+
+def fitc_dense(model: vo.Model, prior: LatentVIF, W: np.ndarray) -> np.ndarray:
+    """P = D_V + Sigma_kn^T Sigma_k^{-1} Sigma_kn, densely (small n)."""
+    P = np.diag(fitc_dv(model, prior, W))
+    if prior.ind.m:
+        P = P + prior.ind.Smn.T @ prior.ind.W
+    return P
+
+
+def fitc_solve(model: vo.Model, prior: LatentVIF, W: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """P^{-1} w = D_V^{-1} w - D_V^{-1} Sigma_kn^T M_V^{-1} Sigma_kn D_V^{-1} w with
+    M_V = Sigma_k + Sigma_kn D_V^{-1} Sigma_kn^T (App. E.2, Woodbury)."""
+    dv = fitc_dv(model, prior, W)
+    t = w / dv
+    if not prior.ind.m:
+        return t
+    S = prior.ind.Smn
+    MV = prior.ind.Sm + S @ (S.T / dv[:, None])
+    return t - (S.T @ np.linalg.solve(MV, S @ t)) / dv
+
+
+def fitc_logdet(model: vo.Model, prior: LatentVIF, W: np.ndarray) -> float:
+    """log det P = log det D_V - log det Sigma_k + log det M_V (Sylvester, App. E.2)."""
+    dv = fitc_dv(model, prior, W)
+    v = float(np.sum(np.log(dv)))
+    if prior.ind.m:
+        S = prior.ind.Smn
+        MV = prior.ind.Sm + S @ (S.T / dv[:, None])
+        v += -np.linalg.slogdet(prior.ind.Sm)[1] + np.linalg.slogdet(MV)[1]
+    return v
+
+
+def sigma_matvec(prior: LatentVIF, w: np.ndarray) -> np.ndarray:
+    """Sigma_dagger w = B^{-1} D B^{-T} w + Sigma_mn^T Sigma_m^{-1} Sigma_mn w."""
+    from scipy.sparse.linalg import spsolve_triangular
+    v = spsolve_triangular(prior.Bsp.T.tocsr(), w, lower=False)
+    out = spsolve_triangular(prior.Bsp.tocsr(), prior.fac.D * v, lower=True)
+    if prior.ind.m:
+        out = out + prior.ind.Smn.T @ (prior.ind.W @ w)
+    return out
+
+
+def newton_step_pcls2(model: vo.Model, prior: LatentVIF, lik: str, y: np.ndarray, b: np.ndarray,
+                      noise_var: float = 1.0, tol: float = 1e-12) -> np.ndarray:
+    """One Newton target b_{t+1} = (W + Sigma_dagger^{-1})^{-1}(W b + g) (eq.
+    one_it_newton_mode) through eq. pcls2: (W^{-1} + Sigma_dagger) u = Sigma_dagger
+    (W b + g) for u = W b_{t+1}, by conjugate gradients preconditioned with the
+    FITC preconditioner, then b_{t+1} = u / W."""
+    g, W, _ = grad_hess(lik, y, b, noise_var)
+    rhs = sigma_matvec(prior, W * b + g)
+    run = pcg_run(lambda v: v / W + sigma_matvec(prior, v), lambda r: fitc_solve(model, prior, W, r), rhs, tol=tol)
+    return run.x / W
+
+
+# ----------------------------------------------------------------------------
 # Laplace NLL and its gradient by stochastic Lanczos quadrature and stochastic
 # trace estimation (Sec. 4.2 eq. slq_v1 with the VIFDU preconditioner of
 # Sec. 4.3.1; gradient of App. B with the estimators of App. D)

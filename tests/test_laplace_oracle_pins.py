@@ -105,3 +105,41 @@ def test_laplace_logdet_decomposition_matches_dense():
     rhs = (-np.linalg.slogdet(prior.ind.Sm)[1] + np.sum(np.log(prior.fac.D)) + np.linalg.slogdet(WQ)[1]
            + np.linalg.slogdet(M1)[1])
     assert abs(lhs - rhs) < 1e-8 * abs(lhs)
+
+
+@pytest.mark.parametrize("m", [0, 12])
+def test_fitc_preconditioner_matches_its_definition(m):
+    """App. E.2: P = diag(Sigma - Sigma_kn^T Sigma_k^{-1} Sigma_kn) + W^{-1} +
+    Sigma_kn^T Sigma_k^{-1} Sigma_kn assembled here from dense covariance
+    matrices; the Woodbury solve equals a dense solve with it and the
+    Sylvester log-det its dense log-det."""
+    model, X, Z, nbr, prior, g = _latent(m=m)
+    n = X.shape[0]
+    W = g.uniform(0.05, 0.25, size=n)
+    Sig = vo.cov(model, X, X) + model.s2 * np.eye(n)
+    low = vo.cov(model, X, Z) @ np.linalg.solve(vo.cov(model, Z, Z) + model.tau_m * np.eye(m), vo.cov(model, Z, X)) \
+        if m else np.zeros((n, n))
+    P = np.diag(np.diag(Sig - low) + 1.0 / W) + low
+    np.testing.assert_allclose(lo.fitc_dense(model, prior, W), P, atol=1e-10)
+    w = g.normal(size=n)
+    np.testing.assert_allclose(lo.fitc_solve(model, prior, W, w), np.linalg.solve(P, w), rtol=1e-8, atol=1e-10)
+    assert abs(lo.fitc_logdet(model, prior, W) - np.linalg.slogdet(P)[1]) < 1e-9 * abs(np.linalg.slogdet(P)[1])
+
+
+@pytest.mark.parametrize("lik", [lo.BERNOULLI_LOGIT, lo.POISSON_LOG])
+def test_fitc_newton_step_through_pcls2_matches_dense_newton_step(lik):
+    """eq. pcls2: solving (W^{-1} + Sigma_dagger) u = Sigma_dagger (W b + g) by
+    FITC-preconditioned CG and taking u / W gives the same Newton target as the
+    dense solve of (W + Sigma_dagger^{-1}) b' = W b + g (eq. one_it_newton_mode);
+    and Sigma_dagger w from the triangular solves equals the dense covariance."""
+    model, X, Z, nbr, prior, g = _latent(n=150, m=10)
+    n = X.shape[0]
+    b = 0.5 * g.normal(size=n)
+    y = (g.uniform(size=n) < expit(b)).astype(float) if lik == lo.BERNOULLI_LOGIT else g.poisson(np.exp(b)).astype(float)
+    C = dr.vif_cov(model, X, Z, nbr, prior.fac.A, prior.fac.D)
+    w = g.normal(size=n)
+    np.testing.assert_allclose(lo.sigma_matvec(prior, w), C @ w, rtol=1e-9, atol=1e-10)
+    gr, W, _ = lo.grad_hess(lik, y, b)
+    ref = np.linalg.solve(np.linalg.inv(C) + np.diag(W), W * b + gr)
+    got = lo.newton_step_pcls2(model, prior, lik, y, b)
+    np.testing.assert_allclose(got, ref, rtol=1e-7, atol=1e-8)
