@@ -170,6 +170,25 @@ vif_status vif_nll_grad(vif_ctx* ctx, const double* y, double* nll_out, double* 
 vif_status vif_laplace_mode(vif_ctx* ctx, const double* y, const double* b0, double* mode_out,
                             vif_laplace_stats* st);
 
+/* Preconditioner of the mode finding's conjugate gradients (Sec. 4.3).
+ *  VIF_PRECOND_VIFDU (default): eq. pcls1 with the VIFDU preconditioner, as
+ *    described for vif_laplace_mode.
+ *  VIF_PRECOND_FITC: eq. pcls2 with the FITC preconditioner of Sec. 4.3.2 /
+ *    App. E.2, P = D_V + Sigma_kn^T Sigma_k^{-1} Sigma_kn with
+ *    D_V = diag(Sigma - Sigma_kn^T Sigma_k^{-1} Sigma_kn) + W^{-1}, taking the
+ *    VIF's own inducing points as the FITC set (k = m; diag(Sigma) =
+ *    sigma1^2 + s2). Each Newton system is solved for u = W b_{t+1}:
+ *    (W^{-1} + Sigma_dagger) u = Sigma_dagger (W b_t + g(b_t)), CG from
+ *    u = W b_t to ||r|| <= cfg.cg_tol ||Sigma_dagger (W b_t + g(b_t))||, with
+ *    Sigma_dagger w = B^{-1} D B^{-T} w + V^T V w and
+ *    P^{-1} r = D_V^{-1} r - D_V^{-1} V^T M_V^{-1} V D_V^{-1} r,
+ *    M_V = I + V D_V^{-1} V^T (whitened). The Newton steps, step halving and
+ *    stopping rule are those of vif_laplace_mode.
+ * The choice applies to vif_laplace_mode and vif_precond_solve; the Laplace
+ * NLL and its gradient keep VIFDU (eq. slq_v1). VIF_E_ARG for another kind. */
+typedef enum { VIF_PRECOND_VIFDU = 0, VIF_PRECOND_FITC = 1 } vif_precond;
+vif_status vif_set_preconditioner(vif_ctx* ctx, int32_t kind);
+
 /* A draw from the VIF prior N(0, Sigma_dagger) of the last build:
  * b = V^T eps1 + B^{-1} D^{1/2} eps2 (the predictive-process part through the
  * whitened features, V^T eps1 = Sigma_mn^T Sigma_m^{-1} L_m eps1, plus the
@@ -266,13 +285,16 @@ vif_status vif_select_neighbors_pred(vif_ctx* ctx, const double* Xp, int64_t n_p
 vif_status vif_predict(vif_ctx* ctx, const double* y, const double* Xp, const int32_t* nbrp, int64_t n_p,
                        double* mean_out, double* var_out);
 
-/* Applies the VIFDU preconditioner of Sec. 4.3.1 / App. E.1 for a given
- * diagonal W: z = P^{-1} r with P = B^T W B + Sigma_dagger^{-1}, in the
- * whitened form z = B^{-1} [E + E D^{-1/2} U M3'^{-1} U^T D^{-1/2} E] B^{-T} r,
- * E = diag(D / (1 + D W)), M3' = I + U^T diag(D W / (1 + D W)) U. This is
- * the preconditioner vif_laplace_mode uses at each Newton step. W, r and z
- * are device arrays of n doubles; z must not overlap r. Needs a built
- * factor; VIF_E_NOT_PD if M3' is not positive definite. */
+/* Applies the preconditioner chosen by vif_set_preconditioner for a given
+ * diagonal W. VIFDU (Sec. 4.3.1 / App. E.1): z = P^{-1} r with
+ * P = B^T W B + Sigma_dagger^{-1}, in the whitened form
+ * z = B^{-1} [E + E D^{-1/2} U M3'^{-1} U^T D^{-1/2} E] B^{-T} r,
+ * E = diag(D / (1 + D W)), M3' = I + U^T diag(D W / (1 + D W)) U. FITC
+ * (App. E.2): z = P^{-1} r with P = D_V + V^T V as described for
+ * vif_set_preconditioner. This is the preconditioner vif_laplace_mode uses
+ * at each Newton step. W, r and z are device arrays of n doubles (W > 0);
+ * z must not overlap r. Needs a built factor; VIF_E_NOT_PD if M3' (M_V) is
+ * not positive definite. */
 vif_status vif_precond_solve(vif_ctx* ctx, const double* W, const double* r, double* z);
 
 /* Copies the factor of the last build to device buffers A_out (n x m_v, the

@@ -31,6 +31,7 @@ struct StageTimer {
 struct vif_ctx {
   vif_config cfg;
   bool timing = false;
+  int precond = VIF_PRECOND_VIFDU;  // preconditioner of the mode finding (vif_set_preconditioner)
   StageTimer timers[ST_COUNT];
   hipStream_t st = nullptr;
   // second stream (Gaussian likelihood with inducing points): once a
@@ -238,6 +239,7 @@ static vif_status read_status(vif_ctx* c, const char* stage) {
     if (s[1] == 1) return fail(c, VIF_E_NOT_PD, "%s: Sigma_m not positive definite at column %d", stage, s[2]);
     if (s[1] == 2) return fail(c, VIF_E_NOT_PD, "%s: M' not positive definite at column %d", stage, s[2]);
     if (s[1] == 3) return fail(c, VIF_E_NOT_PD, "%s: M3' not positive definite at column %d", stage, s[2]);
+    if (s[1] == 4) return fail(c, VIF_E_NOT_PD, "%s: M_V (FITC) not positive definite at column %d", stage, s[2]);
     return fail(c, VIF_E_NOT_PD, "%s: residual system not positive definite at point %d", stage, s[2]);
   }
   if (s[0] == VIF_DEV_NAN) return fail(c, VIF_E_NAN, "%s: non-finite value at %d", stage, s[2]);
@@ -391,6 +393,15 @@ void vif_destroy(vif_ctx* c) {
 }
 
 const char* vif_last_error(const vif_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+vif_status vif_set_preconditioner(vif_ctx* c, int32_t kind) {
+  if (!c) return VIF_E_ARG;
+  if (kind != VIF_PRECOND_VIFDU && kind != VIF_PRECOND_FITC)
+    return fail(c, VIF_E_ARG, "unknown preconditioner %d (VIF_PRECOND_VIFDU or VIF_PRECOND_FITC)", kind);
+  if (kind == VIF_PRECOND_FITC && bf16_form(c)) return reject_bf16(c, "the FITC preconditioner");
+  c->precond = kind;
+  return VIF_OK;
+}
 
 vif_status vif_set_timing(vif_ctx* c, int enable) {
   if (!c) return VIF_E_ARG;
@@ -1005,6 +1016,117 @@ static void build_vifdu(vif_ctx* c, LapBufs& B) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// FITC preconditioner (Sec. 4.3.2; App. E.2) on the system of eq. pcls2, with
+// the VIF's inducing points, whitened (V = L_m^{-1} Sigma_mn): B.E holds
+// D_V^{-1} (B.t and B.sw are scratch of the build: d0 = diag(Sigma) - |V_i|^2
+// and D_V^{-1/2}), M3 / L3inv / M3inv hold M_V = I + V D_V^{-1} V^T, its
+// inverse factor and inverse.
+// ---------------------------------------------------------------------------
+template <typename T>
+static const T* form_V(vif_ctx* c) {
+  return (const T*)(fp32_form(c) ? (const void*)c->Vf : (const void*)c->Vd);
+}
+
+// D_V and M_V for the diagonal B.W
+template <typename T>
+static void build_fitc(vif_ctx* c, LapBufs& B) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  const int mp = c->mp;
+  const T* V = form_V<T>(c);
+  launch_fitc_d0<T>(c->st, V, n, mp, c->cp.sigma1_sq + c->cp.s2, B.t);
+  launch_fitc_idv(c->st, B.t, B.W, n, B.E, B.sw);
+  if (g.m > 0) {
+    int nchunk = 0;
+    launch_wgram_partial<T>(c->st, V, B.sw, n, mp, c->chunk, c->partial, &nchunk);
+    launch_reduce_gram(c->st, c->partial, nchunk, mp, c->M3);
+    launch_chol_inv(c->st, c->M3, c->L3inv, c->Mwork, g.m, mp, B.sc + 12, c->status, 4);
+    launch_gemm_sq(c->st, c->L3inv, c->L3inv, c->M3inv, mp, true, false);
+  }
+}
+
+// z = P^{-1} r = D_V^{-1} r - D_V^{-1} V^T M_V^{-1} V D_V^{-1} r
+template <typename T>
+static void fitc_apply(vif_ctx* c, LapBufs& B, const double* r, double* z) {
+  const vif_config& g = c->cfg;
+  const T* V = form_V<T>(c);
+  if (g.m > 0) {
+    launch_utv<T>(c->st, V, r, B.E, g.n, c->mp, c->chunk, B.upart);
+    launch_reduce_apply(c->st, B.upart, c->nchunk, c->mp, c->M3inv, B.cbuf, B.cp);
+  }
+  launch_fitc_post<T>(c->st, V, B.cp, r, B.E, g.n, c->mp, z);
+}
+
+// out = (W^{-1} + Sigma_dagger) w  (Sigma_dagger w alone when W is NULL),
+// Sigma_dagger w = B^{-1} D B^{-T} w + V^T V w
+template <typename T>
+static void sigma_matvec(vif_ctx* c, LapBufs& B, const double* w, const double* W, double* out) {
+  const vif_config& g = c->cfg;
+  const T* V = form_V<T>(c);
+  launch_trsv_bwd<T>(c->st, c->sb, (const T*)c->bcoef, w, B.xq, B.zq, B.v);
+  launch_mul(c->st, B.v, c->D, g.n, B.q);
+  launch_trsv_fwd<T>(c->st, c->sf, (const T*)c->fcoef, B.q, B.xq, B.zq, B.q2);
+  if (g.m > 0) {
+    launch_utv<T>(c->st, V, w, nullptr, g.n, c->mp, c->chunk, B.upart);
+    launch_colreduce(c->st, B.upart, c->nchunk, c->mp, B.ctmp);
+  }
+  launch_fitc_out<T>(c->st, V, B.ctmp, B.q2, w, W, g.n, c->mp, out);
+}
+
+// Newton target through eq. pcls2 with the FITC preconditioner: CG on
+// (W^{-1} + Sigma_dagger) u = Sigma_dagger (W b + g) from u = W b to
+// ||r|| <= cg_tol ||Sigma_dagger (W b + g)||; on return B.x holds the
+// increment u / W - b.
+template <typename T>
+static vif_status pcg_fitc(vif_ctx* c, LapBufs& B, int* iters, double* relres) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  double* dpart = B.part + ceil_div(n, 256);
+  launch_direct_rhs(c->st, B.W, B.b, B.g, n, B.tmp);
+  sigma_matvec<T>(c, B, B.tmp, nullptr, B.rhs);
+  launch_mul(c->st, B.W, B.b, n, B.x);
+  sigma_matvec<T>(c, B, B.x, B.W, B.Ap);
+  hipLaunchKernelGGL(k_sub, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->st, B.r, B.rhs, B.Ap, n);
+  fitc_apply<T>(c, B, B.r, B.z);
+  HIPCHK(c, hipMemcpyAsync(B.p, B.z, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+  launch_dot2(c->st, B.rhs, B.rhs, nullptr, nullptr, n, dpart, B.sc + 10);
+  launch_dot2(c->st, B.r, B.z, B.r, B.r, n, dpart, B.sc + 3);
+  hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, c->st, B.sc, B.sc + 3);
+  vif_status s = read_scalars(c, 11);
+  if (s) return s;
+  const double ref2 = c->hlsc[10], rr0 = c->hlsc[4];
+  const double thr = g.cg_tol * g.cg_tol * ref2;
+  *iters = 0;
+  *relres = ref2 > 0.0 ? sqrt(rr0 / ref2) : 0.0;
+  if (rr0 > thr) {
+    const int check = 4;
+    bool done = false;
+    for (int it = 1; it <= g.cg_maxit && !done; ++it) {
+      sigma_matvec<T>(c, B, B.p, B.W, B.Ap);
+      launch_dot2(c->st, B.p, B.Ap, nullptr, nullptr, n, dpart, B.sc + 1);
+      launch_cg_update(c->st, B.x, B.r, B.p, B.Ap, B.sc, n);
+      fitc_apply<T>(c, B, B.r, B.z);
+      launch_dot2(c->st, B.r, B.z, B.r, B.r, n, dpart, B.sc + 3);
+      launch_cg_dir(c->st, B.p, B.z, B.sc + 3, B.sc, n);
+      hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, c->st, B.sc, B.sc + 3);
+      if (it % check == 0 || it == g.cg_maxit) {
+        if ((s = read_scalars(c, 5))) return s;
+        const double rr = c->hlsc[4];
+        if (!isfinite(rr)) return fail(c, VIF_E_NAN, "conjugate gradients: non-finite residual at iteration %d", it);
+        *iters = it;
+        *relres = sqrt(rr / ref2);
+        if (rr <= thr) done = true;
+      }
+    }
+    if (!done)
+      return fail(c, VIF_E_CG_MAXIT, "conjugate gradients did not reach %g in %d iterations (relative residual %g)",
+                  g.cg_tol, g.cg_maxit, *relres);
+  }
+  launch_fitc_incr(c->st, B.x, B.W, B.b, n, B.x);
+  return VIF_OK;
+}
+
 // Preconditioned CG for the Newton increment (W + Sigma_dagger^{-1}) x = g - Sigma_dagger^{-1} b
 // (B.rhs). In the direct form of eq. one_it_newton_mode the unknown is b + x
 // with right-hand side W b + g; CG starts from whichever of b (x = 0) and 0
@@ -1112,10 +1234,15 @@ static vif_status laplace_impl(vif_ctx* c, const double* y, const double* b0, do
   for (int t = 1; t <= g.newton_maxit; ++t) {
     // rhs = g - Sigma^{-1} b ; VIFDU data for the current W
     hipLaunchKernelGGL(k_sub, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->st, B.rhs, B.g, B.sb, n);
-    build_vifdu(c, B);
     int its = 0;
     double rel = 0.0;
-    s = pcg<T>(c, B, &its, &rel);
+    if (c->precond == VIF_PRECOND_FITC) {
+      build_fitc<T>(c, B);
+      s = pcg_fitc<T>(c, B, &its, &rel);
+    } else {
+      build_vifdu(c, B);
+      s = pcg<T>(c, B, &its, &rel);
+    }
     if (t <= 64) S.pcg_iters[t - 1] = its;
     S.pcg_iters_total += its;
     S.pcg_rel_residual = rel;
@@ -1801,11 +1928,21 @@ vif_status vif_precond_solve(vif_ctx* c, const double* W, const double* r, doubl
   if ((s = ensure_schedules(c))) return s;
   LapBufs B = lap_bufs(c);
   HIPCHK(c, hipMemcpyAsync(B.W, W, sizeof(double) * c->cfg.n, hipMemcpyDeviceToDevice, c->st));
-  build_vifdu(c, B);
-  if (fp32_form(c))
-    vifdu_apply<float>(c, B, r, z);
-  else
-    vifdu_apply<double>(c, B, r, z);
+  if (c->precond == VIF_PRECOND_FITC) {
+    if (fp32_form(c)) {
+      build_fitc<float>(c, B);
+      fitc_apply<float>(c, B, r, z);
+    } else {
+      build_fitc<double>(c, B);
+      fitc_apply<double>(c, B, r, z);
+    }
+  } else {
+    build_vifdu(c, B);
+    if (fp32_form(c))
+      vifdu_apply<float>(c, B, r, z);
+    else
+      vifdu_apply<double>(c, B, r, z);
+  }
   HIPCHK(c, hipGetLastError());
   return read_status(c, "vif_precond_solve");
 }

@@ -59,6 +59,19 @@ void launch_factor_bwd(hipStream_t st, const double* X, const S* V, const S* Vr,
                        int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status,
                        Batch bt = Batch{nullptr, nullptr}, const int* perm = nullptr);
 
+// laplace.hip: FITC preconditioner pieces
+template <typename T>
+void launch_fitc_d0(hipStream_t st, const T* V, int64_t n, int mp, double s, double* d0);
+void launch_fitc_idv(hipStream_t st, const double* d0, const double* W, int64_t n, double* idv, double* sidv);
+template <typename T>
+void launch_fitc_post(hipStream_t st, const T* V, const double* c, const double* r, const double* idv, int64_t n,
+                      int mp, double* z);
+template <typename T>
+void launch_fitc_out(hipStream_t st, const T* V, const double* c, const double* q, const double* p, const double* W,
+                     int64_t n, int mp, double* out);
+void launch_mul(hipStream_t st, const double* a, const double* b, int64_t n, double* out);
+void launch_fitc_incr(hipStream_t st, const double* u, const double* W, const double* b, int64_t n, double* x);
+
 // grad.hip
 void launch_gemm_sq(hipStream_t st, const double* A, const double* B, double* C, int mp, bool ta, bool tb,
                     int nmat = 1);

@@ -338,7 +338,8 @@ __global__ __launch_bounds__(256) void k_q_plus_euc(const T* __restrict__ U, con
   }
 }
 
-// Weighted Gram partial: sum_p (sw_p U_p)(sw_p U_p)^T over a chunk, lower 64x64 blocks
+// Weighted Gram partial: sum_p (sw_p U_p)(sw_p U_p)^T over a chunk (sw: square-root
+// weights), lower 64x64 blocks
 template <typename T>
 __global__ __launch_bounds__(256) void k_wgram_partial(const T* __restrict__ U, const double* __restrict__ sw,
                                                        int64_t n, int mp, int chunk, double* __restrict__ partial) {
@@ -437,6 +438,92 @@ __global__ __launch_bounds__(256) void k_add_ve(const T* __restrict__ V, const d
 }
 
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// FITC preconditioner (Sec. 4.3.2; App. E.2) with the VIF's inducing points,
+// whitened: with V = L_m^{-1} Sigma_mn, Sigma_kn^T Sigma_k^{-1} Sigma_kn = V^T V
+// and M_V = Sigma_k + Sigma_kn D_V^{-1} Sigma_kn^T becomes I + V D_V^{-1} V^T.
+// ---------------------------------------------------------------------------
+
+// d0_i = s - |V_i|^2, the part of D_V that does not depend on W (s = the
+// diagonal of the approximated covariance); one wave per point
+template <typename T>
+__global__ __launch_bounds__(256) void k_fitc_d0(const T* __restrict__ V, int64_t n, int mp, double s,
+                                                 double* __restrict__ d0) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  double a = 0.0;
+  for (int l = lane; l < mp; l += 64) {
+    const double v = (double)V[(size_t)i * mp + l];
+    a += v * v;
+  }
+  a = wave_sum(a);
+  if (lane == 0) d0[i] = s - a;
+}
+
+// idv_i = 1 / D_V,i = 1 / (d0_i + 1 / W_i) and sidv_i = sqrt(idv_i) (the
+// square-root weight of the Gram M_V = I + sum_i idv_i V_i V_i^T)
+__global__ void k_fitc_idv(const double* __restrict__ d0, const double* __restrict__ W, int64_t n,
+                           double* __restrict__ idv, double* __restrict__ sidv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double v = 1.0 / (d0[i] + 1.0 / W[i]);
+    idv[i] = v;
+    sidv[i] = sqrt(v);
+  }
+}
+
+// z_i = idv_i (r_i - V_i . c): the Woodbury tail of P^{-1} r with
+// c = M_V^{-1} V D_V^{-1} r; four points per wave
+template <typename T>
+__global__ __launch_bounds__(256) void k_fitc_post(const T* __restrict__ V, const double* __restrict__ c,
+                                                   const double* __restrict__ r, const double* __restrict__ idv,
+                                                   int64_t n, int mp, double* __restrict__ z) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
+  if (i0 >= n) return;
+  double s[4];
+  dot4_rows<T>(V, c, i0, n, mp, s);
+  if (lane < 4 && i0 + lane < n) {
+    const int64_t i = i0 + lane;
+    const double sv = lane == 0 ? s[0] : lane == 1 ? s[1] : lane == 2 ? s[2] : s[3];
+    z[i] = idv[i] * (r[i] - sv);
+  }
+}
+
+// out_i = p_i / W_i (if W is given) + q_i + V_i . c: (W^{-1} + Sigma_dagger) p
+// with q = B^{-1} D B^{-T} p and c = V p; four points per wave
+template <typename T>
+__global__ __launch_bounds__(256) void k_fitc_out(const T* __restrict__ V, const double* __restrict__ c,
+                                                  const double* __restrict__ q, const double* __restrict__ p,
+                                                  const double* __restrict__ W, int64_t n, int mp,
+                                                  double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
+  if (i0 >= n) return;
+  double s[4];
+  dot4_rows<T>(V, c, i0, n, mp, s);
+  if (lane < 4 && i0 + lane < n) {
+    const int64_t i = i0 + lane;
+    const double sv = lane == 0 ? s[0] : lane == 1 ? s[1] : lane == 2 ? s[2] : s[3];
+    out[i] = (W ? p[i] / W[i] : 0.0) + q[i] + sv;
+  }
+}
+
+// out = a .* b
+__global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                      double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] * b[i];
+}
+
+// x_i = u_i / W_i - b_i (in place allowed): the Newton increment from u = W b_{t+1}
+__global__ void k_fitc_incr(const double* u, const double* __restrict__ W, const double* __restrict__ b, int64_t n,
+                            double* x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = u[i] / W[i] - b[i];
+}
+
 static inline dim3 g1(int64_t n, int bs = 256) { return dim3((unsigned)ceil_div(n, bs)); }
 
 void launch_lik(hipStream_t st, int lik, double lpar, const double* y, const double* b, int64_t n, double* g,
@@ -536,6 +623,40 @@ template void launch_add_ve<double>(hipStream_t, const double*, const double*, c
                                     double*);
 template void launch_add_ve<float>(hipStream_t, const float*, const double*, const double*, int64_t, int, int,
                                    double*);
+
+template <typename T>
+void launch_fitc_d0(hipStream_t st, const T* V, int64_t n, int mp, double s, double* d0) {
+  hipLaunchKernelGGL((k_fitc_d0<T>), g1(n, 4), dim3(256), 0, st, V, n, mp, s, d0);
+}
+void launch_fitc_idv(hipStream_t st, const double* d0, const double* W, int64_t n, double* idv, double* sidv) {
+  hipLaunchKernelGGL(k_fitc_idv, g1(n), dim3(256), 0, st, d0, W, n, idv, sidv);
+}
+template <typename T>
+void launch_fitc_post(hipStream_t st, const T* V, const double* c, const double* r, const double* idv, int64_t n,
+                      int mp, double* z) {
+  hipLaunchKernelGGL((k_fitc_post<T>), g1(n, 16), dim3(256), 0, st, V, c, r, idv, n, mp, z);
+}
+template <typename T>
+void launch_fitc_out(hipStream_t st, const T* V, const double* c, const double* q, const double* p, const double* W,
+                     int64_t n, int mp, double* out) {
+  hipLaunchKernelGGL((k_fitc_out<T>), g1(n, 16), dim3(256), 0, st, V, c, q, p, W, n, mp, out);
+}
+void launch_mul(hipStream_t st, const double* a, const double* b, int64_t n, double* out) {
+  hipLaunchKernelGGL(k_mul, g1(n), dim3(256), 0, st, a, b, n, out);
+}
+void launch_fitc_incr(hipStream_t st, const double* u, const double* W, const double* b, int64_t n, double* x) {
+  hipLaunchKernelGGL(k_fitc_incr, g1(n), dim3(256), 0, st, u, W, b, n, x);
+}
+template void launch_fitc_d0<double>(hipStream_t, const double*, int64_t, int, double, double*);
+template void launch_fitc_d0<float>(hipStream_t, const float*, int64_t, int, double, double*);
+template void launch_fitc_post<double>(hipStream_t, const double*, const double*, const double*, const double*,
+                                       int64_t, int, double*);
+template void launch_fitc_post<float>(hipStream_t, const float*, const double*, const double*, const double*,
+                                      int64_t, int, double*);
+template void launch_fitc_out<double>(hipStream_t, const double*, const double*, const double*, const double*,
+                                      const double*, int64_t, int, double*);
+template void launch_fitc_out<float>(hipStream_t, const float*, const double*, const double*, const double*,
+                                     const double*, int64_t, int, double*);
 
 #define INST(T)                                                                                                    \
   template void launch_bw<T>(hipStream_t, const T*, const double*, const int32_t*, const double*, int64_t, int,    \

@@ -23,6 +23,7 @@ FP64, FP32, BF16_IN = 0, 1, 2
 KERNELS = {"matern12": MATERN12, "matern32": MATERN32, "gaussian_ard": GAUSSIAN_ARD}
 LIKELIHOODS = {"gaussian": LIK_GAUSSIAN, "bernoulli_logit": LIK_BERNOULLI_LOGIT, "poisson_log": LIK_POISSON_LOG}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16_in": BF16_IN}
+PRECONDITIONERS = {"vifdu": 0, "fitc": 1}
 
 STATUS = {0: "VIF_OK", 1: "VIF_E_ARG", 2: "VIF_E_NAN", 3: "VIF_E_NOT_PD", 4: "VIF_E_CG_MAXIT",
           5: "VIF_E_NEWTON", 6: "VIF_E_HIP", 7: "VIF_E_OOM", 8: "VIF_E_STATE"}
@@ -66,7 +67,7 @@ EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors"
            "vif_nll_grad", "vif_export_factor", "vif_set_timing", "vif_timing_stages", "vif_timing_stage_name",
            "vif_get_timing", "vif_laplace_mode", "vif_mlp_num_params", "vif_mlp_workspace_floats",
            "vif_mlp_forward", "vif_mlp_backward", "vif_mlp_adam", "vif_mlp_features", "vif_sample_prior",
-           "vif_precond_solve", "vif_batch_create", "vif_batch_destroy", "vif_batch_last_error",
+           "vif_precond_solve", "vif_set_preconditioner", "vif_batch_create", "vif_batch_destroy", "vif_batch_last_error",
            "vif_batch_nll_grad", "vif_laplace_nll", "vif_laplace_nll_grad", "vif_select_neighbors_pred",
            "vif_predict"]
 
@@ -108,6 +109,8 @@ def load_library(path: Optional[str] = None):
     lib.vif_laplace_mode.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vif_laplace_stats)]
     lib.vif_laplace_mode.restype = ctypes.c_int
     lib.vif_precond_solve.argtypes = [vp, vp, vp, vp]
+    lib.vif_set_preconditioner.argtypes = [vp, ctypes.c_int32]
+    lib.vif_set_preconditioner.restype = ctypes.c_int
     lib.vif_precond_solve.restype = ctypes.c_int
     lib.vif_laplace_nll.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, dp, dp]
     lib.vif_laplace_nll.restype = ctypes.c_int
@@ -224,6 +227,10 @@ class VifContext:
         D = torch.empty(self.n, dtype=torch.float64, device="cuda")
         self._check(self.lib.vif_export_factor(self.h, _ptr(A) if self.m_v else None, _ptr(D)))
         return A, D
+
+    def set_preconditioner(self, kind: str):
+        """'vifdu' (default) or 'fitc': the preconditioner of the mode finding and of precond_solve."""
+        self._check(self.lib.vif_set_preconditioner(self.h, PRECONDITIONERS[kind]))
 
     def set_timing(self, enable: bool = True):
         self._check(self.lib.vif_set_timing(self.h, int(enable)))
