@@ -132,12 +132,15 @@ def laplace_leg(reps, warmup, log):
             build_ms.append(ev[0].elapsed_time(ev[1]))
     out = {}
     modes = {}
-    for form in ("zero", "warm"):
+    # VIFDU (eq. pcls1) from zero and from the learned start, then the same
+    # with the FITC preconditioner (eq. pcls2)
+    for form in ("zero", "warm", "fitc_zero", "fitc_warm"):
+        ctx.set_preconditioner("fitc" if form.startswith("fitc") else "vifdu")
         ms, st = [], None
         for r in range(warmup + reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            if form == "zero":
+            if form.endswith("zero"):
                 mode, st, _ = ctx.laplace_mode(prob.y)
             else:
                 b0 = mlp.forward(ctx.mlp_features(prob.y), double=True)
@@ -157,12 +160,14 @@ def laplace_leg(reps, warmup, log):
     out["net_rel_err"] = float(torch.linalg.norm(b0 - ref) / torch.linalg.norm(ref))
     out["mode_rel_diff"] = float(torch.linalg.norm(modes["warm"] - ref) / torch.linalg.norm(ref))
     out["speedup_warm_vs_zero"] = out["zero"]["mode_ms_median"] / out["warm"]["mode_ms_median"]
+    out["fitc_mode_rel_diff_vs_vifdu"] = float(torch.linalg.norm(modes["fitc_zero"] - ref) / torch.linalg.norm(ref))
+    out["fitc_speedup_warm_vs_zero"] = out["fitc_zero"]["mode_ms_median"] / out["fitc_warm"]["mode_ms_median"]
     out["factor_build_ms_median"] = _pct(build_ms, 50)
     out["mlp_train_s"] = train_s
     out["reps"] = reps
     out["workload"] = (f"Bernoulli-logit latent VIF: n={w.n} d={w.d} ARD Gaussian (var 1, length scales "
                        f"0.2..0.6), m={w.m} kMeans++ inducing points, m_v={w.m_v}, b from the VIF prior, "
-                       f"Newton + VIFDU-PCG (tol 1e-6), FP64")
+                       f"Newton + PCG (tol 1e-6) with the VIFDU (zero, warm) or FITC (fitc_*) preconditioner, FP64")
     ctx.close()
     return out
 
