@@ -483,6 +483,42 @@ def laplace_nll_slq(prior: LatentVIF, lik: str, y: np.ndarray, mode: np.ndarray,
     return LaplaceSLQ(nll, logdet, terms, runs)
 
 
+def fitc_probes(model: vo.Model, prior: LatentVIF, W: np.ndarray, e1: np.ndarray, e3: np.ndarray) -> np.ndarray:
+    """Probe vectors z ~ N(0, P) for the FITC preconditioner (App. E.2) from
+    standard normals e1 (n x l) and e3 (k x l): z = D_V^{1/2} e1 +
+    Sigma_kn^T L_k^{-T} e3 with Sigma_k = L_k L_k^T, so that
+    Cov(z) = D_V + Sigma_kn^T Sigma_k^{-1} Sigma_kn = P."""
+    Z = np.sqrt(fitc_dv(model, prior, W))[:, None] * e1
+    if prior.ind.m:
+        Lm = np.tril(prior.ind.cf[0])
+        Z = Z + prior.ind.Smn.T @ np.linalg.solve(Lm.T, e3)
+    return Z
+
+
+def laplace_nll_slq_fitc(model: vo.Model, prior: LatentVIF, lik: str, y: np.ndarray, mode: np.ndarray,
+                         Z: np.ndarray, noise_var: float = 1.0, tol: float = 1e-10, psolve=None,
+                         logdet_P=None) -> LaplaceSLQ:
+    """eq. log_det_VIFLA with log det(Sigma_dagger W + I) = log det W + log det P
+    + log det(P^{-1/2} (W^{-1} + Sigma_dagger) P^{-1/2}), the last by SLQ in the
+    form of eq. slq_v2 over the probes Z (columns, z ~ N(0, P)), normalised by
+    ||P^{-1/2} z||^2 = z^T P^{-1} z. Default P: FITC at W(mode); psolve /
+    logdet_P override it."""
+    _, W, _ = grad_hess(lik, y, mode, noise_var)
+    if psolve is None:
+        psolve = lambda v: fitc_solve(model, prior, W, v)
+        logdet_P = fitc_logdet(model, prior, W)
+    matvec = lambda v: v / W + sigma_matvec(prior, v)
+    runs, terms = [], []
+    for k in range(Z.shape[1]):
+        run = pcg_run(matvec, psolve, Z[:, k], tol)
+        runs.append(run)
+        terms.append(run.bPb * e1_log_e1(lanczos_from_cg(run.alphas, run.betas)) if run.iters else 0.0)
+    terms = np.array(terms)
+    logdet = float(np.sum(np.log(W))) + logdet_P + float(np.mean(terms))
+    nll = float(-np.sum(loglik(lik, y, mode, noise_var)) + 0.5 * mode @ prior.prec_matvec(mode) + 0.5 * logdet)
+    return LaplaceSLQ(nll, logdet, terms, runs)
+
+
 def laplace_grad_dense(prior: LatentVIF, tangents, lik: str, y: np.ndarray, mode: np.ndarray,
                        noise_var: float = 1.0) -> np.ndarray:
     """Exact gradient of eq. log_det_VIFLA at small n (App. B): for each theta_p

@@ -143,3 +143,53 @@ def test_slq_and_ste_are_unbiased():
     assert np.all(np.abs(gs.mean(0) - exact_g) <= 4 * se_g + 1e-9 * np.abs(exact_g)), (gs.mean(0), exact_g, se_g)
     # the control variate does not increase the spread (summed over components)
     assert np.sum(gs.var(0)) <= 1.05 * np.sum(gs0.var(0))
+
+
+def test_fitc_probe_covariance_is_fitc():
+    """FITC probes (App. E.2) have covariance exactly the FITC preconditioner,
+    checked on the linear map they come from."""
+    model, X, Z, nbr, prior, y, mode = _latent(n=60, m=8)
+    W = _W(lo.BERNOULLI_LOGIT, y, mode)
+    n, m = 60, 8
+    F1 = lo.fitc_probes(model, prior, W, np.eye(n), np.zeros((m, n)))
+    F3 = lo.fitc_probes(model, prior, W, np.zeros((n, m)), np.eye(m))
+    P = lo.fitc_dense(model, prior, W)
+    assert np.max(np.abs(F1 @ F1.T + F3 @ F3.T - P)) <= 1e-9 * np.max(np.abs(P))
+
+
+@pytest.mark.parametrize("lik", [lo.BERNOULLI_LOGIT, lo.POISSON_LOG])
+def test_slq_v2_with_exact_preconditioner_is_exact(lik):
+    """eq. slq_v2 with P = W^{-1} + Sigma_dagger itself: every Lanczos matrix
+    is [1], the SLQ term vanishes, and log det W + log det P is the exact
+    log det(Sigma_dagger W + I): the NLL equals the dense Laplace NLL."""
+    model, X, Z, nbr, prior, y, mode = _latent(lik=lik)
+    W = _W(lik, y, mode)
+    A2 = np.diag(1.0 / W) + lo.dense_cov(prior)
+    Zp = np.random.default_rng(2).standard_normal((prior.n, 3))
+    res = lo.laplace_nll_slq_fitc(model, prior, lik, y, mode, Zp, tol=1e-8,
+                                  psolve=lambda v: np.linalg.solve(A2, v), logdet_P=np.linalg.slogdet(A2)[1])
+    for run in res.runs:
+        T = lo.lanczos_from_cg(run.alphas, run.betas)
+        assert run.iters == 1 and abs(T[0, 0] - 1.0) <= 1e-10
+    ref = lo.laplace_nll_dense(prior, lik, y, mode)
+    assert abs(res.nll - ref) <= 1e-9 * abs(ref)
+
+
+def test_slq_v2_full_krylov_equals_dense_quadratic_form():
+    """With the FITC preconditioner and CG run to the full Krylov space of
+    P^{-1/2} (W^{-1} + Sigma_dagger) P^{-1/2}, ||P^{-1/2} z||^2 e_1^T log(T) e_1
+    equals the dense quadratic form of the matrix logarithm."""
+    model, X, Z, nbr, prior, y, mode = _latent(n=30, m=4, mv=4)
+    W = _W(lo.BERNOULLI_LOGIT, y, mode)
+    A2 = np.diag(1.0 / W) + lo.dense_cov(prior)
+    P = lo.fitc_dense(model, prior, W)
+    lam, V = np.linalg.eigh(P)
+    Pmh = V @ np.diag(lam ** -0.5) @ V.T
+    mu, Q = np.linalg.eigh(Pmh @ A2 @ Pmh)
+    logC = Q @ np.diag(np.log(mu)) @ Q.T
+    z = np.random.default_rng(5).standard_normal(30)
+    run = lo.pcg_run(lambda v: A2 @ v, lambda v: lo.fitc_solve(model, prior, W, v), z, tol=1e-15, maxit=30)
+    est = run.bPb * lo.e1_log_e1(lo.lanczos_from_cg(run.alphas, run.betas))
+    ref = (Pmh @ z) @ logC @ (Pmh @ z)
+    assert abs(run.bPb - z @ np.linalg.solve(P, z)) <= 1e-12 * run.bPb
+    assert abs(est - ref) <= 1e-8 * max(1.0, abs(ref))
