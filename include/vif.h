@@ -184,8 +184,14 @@ vif_status vif_laplace_mode(vif_ctx* ctx, const double* y, const double* b0, dou
  *    P^{-1} r = D_V^{-1} r - D_V^{-1} V^T M_V^{-1} V D_V^{-1} r,
  *    M_V = I + V D_V^{-1} V^T (whitened). The Newton steps, step halving and
  *    stopping rule are those of vif_laplace_mode.
- * The choice applies to vif_laplace_mode and vif_precond_solve; the Laplace
- * NLL and its gradient keep VIFDU (eq. slq_v1). VIF_E_ARG for another kind. */
+ * The choice applies to vif_laplace_mode, vif_precond_solve and
+ * vif_laplace_nll: with FITC, log det(Sigma_dagger W + I) is taken in the
+ * form of eq. slq_v2, sum log W + log det P + the SLQ term of
+ * P^{-1/2} (W^{-1} + Sigma_dagger) P^{-1/2}, log det P = sum log D_V +
+ * log det M_V, with probes z_k = D_V^{1/2} e1_k + V^T e3_k (the e2 rows of
+ * eps_n are not used). vif_laplace_nll_grad always uses VIFDU (eq. slq_v1),
+ * whose solves its trace estimates reuse. VIF_E_ARG for another kind; the
+ * BF16-input form has no FITC. */
 typedef enum { VIF_PRECOND_VIFDU = 0, VIF_PRECOND_FITC = 1 } vif_precond;
 vif_status vif_set_preconditioner(vif_ctx* ctx, int32_t kind);
 

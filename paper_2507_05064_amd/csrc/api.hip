@@ -1413,13 +1413,16 @@ __global__ void k_export_A(const void* A, bool f32, int64_t count, double* out) 
 // initial rhs^T P^{-1} rhs and (when q0 is set) P^{-1} rhs.
 template <typename T>
 static vif_status pcg_plain(vif_ctx* c, LapBufs& B, const double* rhs, double* x, double* alog, double* blog,
-                            double* q0, int* iters, double* rz0) {
+                            double* q0, int* iters, double* rz0, bool fitc = false) {
   const vif_config& g = c->cfg;
   const int64_t n = g.n;
   double* dpart = B.part + ceil_div(n, 256);
   HIPCHK(c, hipMemsetAsync(x, 0, sizeof(double) * n, c->st));
   HIPCHK(c, hipMemcpyAsync(B.r, rhs, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
-  vifdu_apply<T>(c, B, B.r, B.z);
+  if (fitc)
+    fitc_apply<T>(c, B, B.r, B.z);
+  else
+    vifdu_apply<T>(c, B, B.r, B.z);
   if (q0) HIPCHK(c, hipMemcpyAsync(q0, B.z, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(B.p, B.z, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
   launch_dot2(c->st, B.r, B.z, B.r, B.r, n, dpart, B.sc + 3);
@@ -1433,10 +1436,16 @@ static vif_status pcg_plain(vif_ctx* c, LapBufs& B, const double* rhs, double* x
   if (!(rr0 > 0.0)) return VIF_OK;
   const int check = 4;
   for (int it = 1; it <= g.cg_maxit; ++it) {
-    prec_matvec<T>(c, B, B.p, B.W, B.Ap);
+    if (fitc)
+      sigma_matvec<T>(c, B, B.p, B.W, B.Ap);  // (W^{-1} + Sigma_dagger) p, eq. pcls2
+    else
+      prec_matvec<T>(c, B, B.p, B.W, B.Ap);   // (W + Sigma_dagger^{-1}) p, eq. pcls1
     launch_dot2(c->st, B.p, B.Ap, nullptr, nullptr, n, dpart, B.sc + 1);
     launch_cg_update(c->st, x, B.r, B.p, B.Ap, B.sc, n);
-    vifdu_apply<T>(c, B, B.r, B.z);
+    if (fitc)
+      fitc_apply<T>(c, B, B.r, B.z);
+    else
+      vifdu_apply<T>(c, B, B.r, B.z);
     launch_dot2(c->st, B.r, B.z, B.r, B.r, n, dpart, B.sc + 3);
     if (alog) launch_log_ab(c->st, B.sc, alog + it - 1, blog + it - 1);
     launch_cg_dir(c->st, B.p, B.z, B.sc + 3, B.sc, n);
@@ -1500,7 +1509,7 @@ static void prior_draw(vif_ctx* c, LapBufs& B, const double* eps_m, const double
 // z_k = B^T W^{1/2} e1_k + Sigma_dagger^{-1} x_k ~ N(0, P).
 template <typename T>
 static vif_status laplace_nll_impl(vif_ctx* c, const double* y, const double* mode, int ell, const double* eps_n,
-                                   const double* eps_m, double* out3) {
+                                   const double* eps_m, double* out3, bool fitc = false) {
   const vif_config& g = c->cfg;
   const int64_t n = g.n;
   const int mp = c->mp;
@@ -1511,6 +1520,51 @@ static vif_status laplace_nll_impl(vif_ctx* c, const double* y, const double* mo
   const int nlb = (int)ceil_div(n, 256);
   double* dpart = B.part + nlb;
   if (g.m > 0) launch_gemm_sq(c->st, c->LMinv, c->LMinv, c->Minv, mp, true, false);
+  if (fitc) {
+    // eq. slq_v2 with the FITC preconditioner at W(mode): log det(Sigma_dagger W + I)
+    // = sum log W + (sum log D_V + log det M_V) + SLQ term, probes z = D_V^{1/2} e1 + V^T e3
+    launch_lik(c->st, g.likelihood, g.lik_param, y, mode, n, B.g, B.W, B.part);
+    hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, B.part, nlb, B.sc + 9);
+    build_fitc<T>(c, B);
+    prec_matvec<T>(c, B, mode, nullptr, B.sd);
+    launch_dot2(c->st, mode, B.sd, nullptr, nullptr, n, dpart, B.sc + 7);
+    const int nb = launch_sum_log_ratio(c->st, B.W, B.E, n, B.part);
+    hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, B.part, nb, B.sc + 10);
+    if ((s = read_scalars(c, 13))) return s;
+    const double loglik = c->hlsc[9], bsb = c->hlsc[7], lwdv = c->hlsc[10];
+    const double ldMV = g.m > 0 ? c->hlsc[12] : 0.0;
+    std::vector<int> its(ell);
+    std::vector<double> rz(ell);
+    const T* V = form_V<T>(c);
+    for (int k = 0; k < ell; ++k) {
+      const double* e1 = eps_n + (size_t)(2 * k) * n;
+      launch_div(c->st, e1, B.sw, n, B.t);  // D_V^{1/2} e1 (B.sw = D_V^{-1/2})
+      if (g.m > 0)
+        launch_add_ve<T>(c->st, V, eps_m + (size_t)k * g.m, B.t, n, mp, g.m, B.rhs);
+      else
+        HIPCHK(c, hipMemcpyAsync(B.rhs, B.t, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+      s = pcg_plain<T>(c, B, B.rhs, c->slq_u + (size_t)k * n, c->slq_a + (size_t)k * c->slq_ld,
+                       c->slq_b + (size_t)k * c->slq_ld, c->slq_q + (size_t)k * n, &its[k], &rz[k], true);
+      if (s) return s;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->slq_iters, its.data(), sizeof(int) * ell, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->slq_rz, rz.data(), sizeof(double) * ell, hipMemcpyHostToDevice, c->st));
+    launch_slq_terms(c->st, c->slq_a, c->slq_b, c->slq_iters, c->slq_rz, ell, c->slq_ld, c->slq_work, c->slq_terms);
+    std::vector<double> terms(ell);
+    HIPCHK(c, hipMemcpyAsync(terms.data(), c->slq_terms, sizeof(double) * ell, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    double mean = 0.0;
+    for (int k = 0; k < ell; ++k) {
+      if (!isfinite(terms[k])) return fail(c, VIF_E_NAN, "SLQ: Lanczos quadrature failed for probe %d", k);
+      mean += terms[k];
+    }
+    mean /= ell;
+    const double logdet = lwdv + ldMV + mean;
+    out3[0] = -loglik + 0.5 * bsb + 0.5 * logdet;
+    out3[1] = logdet;
+    out3[2] = mean;
+    return VIF_OK;
+  }
   // likelihood terms at the mode, VIFDU for W(mode)
   launch_lik(c->st, g.likelihood, g.lik_param, y, mode, n, B.g, B.W, B.part);
   hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, B.part, nlb, B.sc + 9);
@@ -1775,8 +1829,9 @@ vif_status vif_laplace_nll(vif_ctx* c, const double* y, const double* mode, int3
   vif_status s = reset_status(c);
   if (s) return s;
   double out3[3];
-  s = fp32_form(c) ? laplace_nll_impl<float>(c, y, mode, ell, eps_n, eps_m, out3)
-                   : laplace_nll_impl<double>(c, y, mode, ell, eps_n, eps_m, out3);
+  const bool fitc = c->precond == VIF_PRECOND_FITC;
+  s = fp32_form(c) ? laplace_nll_impl<float>(c, y, mode, ell, eps_n, eps_m, out3, fitc)
+                   : laplace_nll_impl<double>(c, y, mode, ell, eps_n, eps_m, out3, fitc);
   if (s) return s;
   if ((s = read_status(c, "vif_laplace_nll"))) return s;
   *nll_out = out3[0];

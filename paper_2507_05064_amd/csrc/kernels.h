@@ -70,6 +70,8 @@ template <typename T>
 void launch_fitc_out(hipStream_t st, const T* V, const double* c, const double* q, const double* p, const double* W,
                      int64_t n, int mp, double* out);
 void launch_mul(hipStream_t st, const double* a, const double* b, int64_t n, double* out);
+void launch_div(hipStream_t st, const double* a, const double* b, int64_t n, double* out);
+int launch_sum_log_ratio(hipStream_t st, const double* a, const double* b, int64_t n, double* part);
 void launch_fitc_incr(hipStream_t st, const double* u, const double* W, const double* b, int64_t n, double* x);
 
 // grad.hip

@@ -517,6 +517,13 @@ __global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b
   if (i < n) out[i] = a[i] * b[i];
 }
 
+// out = a ./ b
+__global__ void k_div(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                      double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] / b[i];
+}
+
 // x_i = u_i / W_i - b_i (in place allowed): the Newton increment from u = W b_{t+1}
 __global__ void k_fitc_incr(const double* u, const double* __restrict__ W, const double* __restrict__ b, int64_t n,
                             double* x) {
@@ -643,6 +650,9 @@ void launch_fitc_out(hipStream_t st, const T* V, const double* c, const double* 
 }
 void launch_mul(hipStream_t st, const double* a, const double* b, int64_t n, double* out) {
   hipLaunchKernelGGL(k_mul, g1(n), dim3(256), 0, st, a, b, n, out);
+}
+void launch_div(hipStream_t st, const double* a, const double* b, int64_t n, double* out) {
+  hipLaunchKernelGGL(k_div, g1(n), dim3(256), 0, st, a, b, n, out);
 }
 void launch_fitc_incr(hipStream_t st, const double* u, const double* W, const double* b, int64_t n, double* x) {
   hipLaunchKernelGGL(k_fitc_incr, g1(n), dim3(256), 0, st, u, W, b, n, x);

@@ -108,6 +108,19 @@ __global__ __launch_bounds__(256) void k_sum_log1p_dw(const double* __restrict__
   if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// partial sums (one per 256 points) of log(a_i / b_i): with a = W and b =
+// D_V^{-1}, sum log W_i + sum log D_V,i (the FITC form of the Laplace log-det)
+__global__ __launch_bounds__(256) void k_sum_log_ratio(const double* __restrict__ a, const double* __restrict__ b,
+                                                       int64_t n, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double v = (i < n) ? log(a[i] / b[i]) : 0.0;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 // s_i += sqrt(W_i) e_i
 __global__ void k_add_sqrtw(double* __restrict__ s, const double* __restrict__ W, const double* __restrict__ e,
                             int64_t n) {
@@ -126,6 +139,11 @@ void launch_slq_terms(hipStream_t st, const double* alog, const double* blog, co
 int launch_sum_log1p_dw(hipStream_t st, const double* D, const double* W, int64_t n, double* part) {
   const int nb = (int)ceil_div(n, 256);
   hipLaunchKernelGGL(k_sum_log1p_dw, dim3(nb), dim3(256), 0, st, D, W, n, part);
+  return nb;
+}
+int launch_sum_log_ratio(hipStream_t st, const double* a, const double* b, int64_t n, double* part) {
+  const int nb = (int)ceil_div(n, 256);
+  hipLaunchKernelGGL(k_sum_log_ratio, dim3(nb), dim3(256), 0, st, a, b, n, part);
   return nb;
 }
 void launch_add_sqrtw(hipStream_t st, double* s, const double* W, const double* e, int64_t n) {
