@@ -249,8 +249,10 @@ vif_status vif_mlp_features(vif_ctx* ctx, const double* y, float* feat_out);
  * V^T e3 = Sigma_mn^T L_m^{-T} e3. nll_out (host) gets the NLL, logdet_out
  * (host, may be NULL) the estimate of log det(Sigma_dagger W + I). The solves
  * A^{-1} z_k and P^{-1} z_k are kept in the context for a following gradient
- * call. The first call with a given ell allocates its workspace. Errors:
- * VIF_E_CG_MAXIT, VIF_E_NOT_PD (M3'), VIF_E_NAN. */
+ * call. The first call with a given ell allocates its workspace. With
+ * VIF_PRECOND_FITC set (vif_set_preconditioner) the log-determinant takes the
+ * FITC form of eq. slq_v2 described there instead. Errors: VIF_E_CG_MAXIT,
+ * VIF_E_NOT_PD (M3' or M_V), VIF_E_NAN. */
 vif_status vif_laplace_nll(vif_ctx* ctx, const double* y, const double* mode, int32_t ell, const double* eps_n,
                            const double* eps_m, double* nll_out, double* logdet_out);
 
