@@ -8,6 +8,8 @@
 //   P^{-1} w = B^{-1} [E + E D^{-1/2} U M3'^{-1} U^T D^{-1/2} E] B^{-T} w,
 //   E = diag(D_i / (1 + D_i W_i)),  M3' = I + U^T diag(D_i W_i / (1 + D_i W_i)) U,
 // the congruences (by L_m) of the paper's M and M_3 forms.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -364,21 +366,35 @@ __global__ __launch_bounds__(256) void k_wgram_partial(const T* __restrict__ U, 
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = A4{0, 0, 0, 0};
-  for (int64_t p0 = pbeg; p0 < pend; p0 += 4) {
-    const int64_t pp = p0 + g;
-    const bool pv = pp < pend;
-    const T* row = U + (size_t)(pv ? pp : pbeg) * mp;
-    const T s = pv ? (T)sw[pp] : T(0);
-    T a[2], b[2];
+  // 16 points per iteration: their loads (unconditional, in range) issue together
+  for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
+    T a[4][2], b[4][2], sv[4];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      a[t] = (pv && rok[t]) ? row[L0 + 16 * t + r] * s : T(0);
-      b[t] = (pv && cok[t]) ? row[C0 + 16 * t + r] * s : T(0);
+    for (int u = 0; u < 4; ++u) {
+      const int64_t pp = p0 + 4 * u + g;
+      const int64_t pc = pp < pend ? pp : pbeg;
+      const T* row = U + (size_t)pc * mp;
+      sv[u] = (T)sw[pc];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[u][t] = row[min(L0 + 16 * t + r, mp - 1)];
+        b[u][t] = row[min(C0 + 16 * t + r, mp - 1)];
+      }
     }
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int u = 0; u < 4; ++u) {
+      const bool pv = p0 + 4 * u + g < pend;
+      const T s = pv ? sv[u] : T(0);
 #pragma unroll
-      for (int yy = 0; yy < 2; ++yy) acc[x][yy] = mfma16(a[x], b[yy], acc[x][yy]);
+      for (int t = 0; t < 2; ++t) {
+        a[u][t] = rok[t] ? a[u][t] * s : T(0);
+        b[u][t] = cok[t] ? b[u][t] * s : T(0);
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int yy = 0; yy < 2; ++yy) acc[x][yy] = mfma16(a[u][x], b[u][yy], acc[x][yy]);
+    }
   }
   double* out = partial + (size_t)blockIdx.x * mp * mp;
 #pragma unroll
@@ -600,6 +616,9 @@ void launch_q_plus_euc(hipStream_t st, const T* U, const double* c, const double
 template <typename T>
 void launch_wgram_partial(hipStream_t st, const T* U, const double* sw, int64_t n, int mp, int chunk, double* partial,
                           int* nchunk_out) {
+  // at most 96 chunks (mp^2 doubles of partials each; the m_p / 64 lower
+  // blocks of every chunk still give thousands of workgroups)
+  chunk = (int)std::max<int64_t>(chunk, ceil_div(ceil_div(n, 96), 16) * 16);
   const int nchunk = (int)ceil_div(n, chunk);
   const int nb = (mp + 63) / 64;
   hipLaunchKernelGGL((k_wgram_partial<T>), dim3(nchunk, nb * (nb + 1) / 2), dim3(256), 0, st, U, sw, n, mp, chunk,
