@@ -64,6 +64,25 @@ def test_fitc_mode_matches_oracle(lik, n, m, mv, d, kernel, ls):
     assert abs(st["psi"] - ref.psi) <= 1e-9 * abs(ref.psi)
 
 
+@pytest.mark.parametrize("prec,mv", [("fp32", 10), ("fp64", 0)])
+def test_fitc_mode_fp32_form_and_no_neighbours(prec, mv):
+    """The FP32 form (FP32 factor, V and U; FP64 m x m parts and reductions)
+    with FITC reaches the oracle's mode within 1e-4 of max|mode| (the FP32
+    factor's own accuracy); with m_v = 0 (B = I, FITC-like prior) the FP64
+    form within 1e-8."""
+    from paper_2507_05064_amd.vif import VifContext
+    w, X, Z, model, nbr, prior, y = _problem(lo.POISSON_LOG, 1000, 25, mv, 2, vo.MATERN32, (0.1,))
+    print(f"[gpu] fitc mode {prec} m_v={mv}", flush=True)
+    ref = lo.find_mode(prior, lo.POISSON_LOG, y, tol=1e-14, solver="dense")
+    ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=lo.POISSON_LOG, precision=prec,
+                     tau_m=w.tau_m, cg_tol=1e-12 if prec == "fp64" else 1e-8, cg_maxit=5000, newton_tol=1e-14)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr) if mv else None, w.theta)
+    ctx.set_preconditioner("fitc")
+    mode, st, _ = ctx.laplace_mode(to_dev(y), raise_on_error=False)
+    err = np.max(np.abs(mode.cpu().numpy() - ref.mode)) / np.max(np.abs(ref.mode))
+    assert err <= (1e-8 if prec == "fp64" else 1e-4), (err, st)
+
+
 def test_fitc_and_vifdu_reach_the_same_mode():
     """At the default tolerances (CG 1e-6) both preconditioners stop at the
     same mode up to the CG tolerance, from zero and from a perturbed start."""
