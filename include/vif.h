@@ -286,8 +286,9 @@ vif_status vif_select_neighbors_pred(vif_ctx* ctx, const double* Xp, int64_t n_p
  * B_po holding -A^p over the training neighbours nbrp (from
  * vif_select_neighbors_pred or the caller), A^p by eq. D_A_Vecchia for the
  * prediction point. For a Gaussian context y is the response; for a latent
- * context pass the mode: the result is then the predictive mean of the
- * latent process, Cov(b_p, b) Sigma_dagger^{-1} b~. Device arrays: y (n), Xp
+ * context pass the mode: the result is then omega_p of Prop. 3.1, the
+ * latent predictive mean of the VIF-Laplace approximation (the same
+ * expression with b~ in place of y and the latent factor). Device arrays: y (n), Xp
  * (n_p x d), nbrp (n_p x m_v), mean_out (n_p). var_out must be NULL
  * (predictive variances are not provided). */
 vif_status vif_predict(vif_ctx* ctx, const double* y, const double* Xp, const int32_t* nbrp, int64_t n_p,

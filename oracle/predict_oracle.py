@@ -71,3 +71,12 @@ def predictive_mean(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarr
         low = np.zeros(npred)
         inner = y
     return low - Bpo @ inner
+
+
+def laplace_predictive_mean(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray, mode: np.ndarray,
+                            Xp: np.ndarray, nbr_p: np.ndarray) -> np.ndarray:
+    """omega_p of Prop. 3.1: the latent predictive mean of the VIF-Laplace
+    approximation, the expression of Prop. 2.1's mean with the mode b~ in
+    place of y and the latent factor (s2 = the jitter tau) in place of the
+    Gaussian one."""
+    return predictive_mean(model, X, Z, nbr, mode, Xp, nbr_p)

@@ -63,3 +63,24 @@ def test_predict_rejects_variances():
                              ctypes.c_void_p(nbrp.data_ptr()), 10, ctypes.c_void_p(mu.data_ptr()),
                              ctypes.c_void_p(var.data_ptr()))
     assert rc == 1
+
+
+def test_laplace_predictive_mean_matches_oracle():
+    """Prop. 3.1: on a latent (Bernoulli-logit) context, vif_predict with the
+    mode b~ in place of y gives the latent predictive mean omega_p; compared
+    with the oracle at the oracle's mode, within 1e-8 of max|omega| (the
+    latent factor carries the jitter tau = 1e-6, as in the mode tests)."""
+    from oracle import laplace_oracle as lo
+    from paper_2507_05064_amd.vif import VifContext
+    from tests.test_gpu_laplace import _problem
+    w, X, Z, model, nbr, prior, y = _problem(lo.BERNOULLI_LOGIT, 900, 20, 10)
+    Xp = vi.coords(vi.scaled(w, 200), 77)
+    nbr_p = po.prediction_neighbours(model, X, Z, Xp, w.m_v)
+    mode = lo.find_mode(prior, lo.BERNOULLI_LOGIT, y, tol=1e-14, solver="dense").mode
+    ref = po.laplace_predictive_mean(model, X, Z, nbr, mode, Xp, nbr_p)
+    print("[gpu] laplace predictive mean n=900 n_p=200", flush=True)
+    ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=lo.BERNOULLI_LOGIT, precision="fp64",
+                     tau_m=w.tau_m)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    om = ctx.predict(to_dev(mode), to_dev(Xp), nbr_to_dev(nbr_p)).cpu().numpy()
+    assert np.max(np.abs(om - ref)) <= 1e-8 * np.max(np.abs(ref)), np.max(np.abs(om - ref))

@@ -89,3 +89,21 @@ def test_prediction_neighbours_are_smallest_keys():
         keys = vo.neighbour_keys(model, XA, indA, 80 + j, np.arange(80))
         ref = sorted(range(80), key=lambda c: (keys[c], c))[:7]
         assert list(nbr_p[j]) == ref
+
+
+@pytest.mark.parametrize("m", [0, 6])
+def test_laplace_predictive_mean_with_full_conditioning_is_the_latent_conditional(m):
+    """Prop. 3.1 with m_v = n - 1: omega_p = Sigma_pn (Sigma + tau I)^{-1} b~,
+    the exact conditional mean of the latent process given its value b~ at
+    the training inputs (tau the latent jitter)."""
+    model, X, Xp, Z, y = _setup(m=m)
+    lat = vo.Model(model.kernel, model.sigma1_sq, model.ls, 1e-4)
+    n = X.shape[0]
+    b = np.random.default_rng(9).standard_normal(n)
+    nbr = -np.ones((n, n - 1), dtype=np.int64)
+    for i in range(n):
+        nbr[i, :i] = np.arange(i)
+    nbr_p = np.tile(np.arange(n), (Xp.shape[0], 1))
+    om = po.laplace_predictive_mean(lat, X, Z, nbr, b, Xp, nbr_p)
+    ref = vo.cov(lat, Xp, X) @ np.linalg.solve(vo.cov(lat, X, X) + lat.s2 * np.eye(n), b)
+    assert np.max(np.abs(om - ref)) <= 1e-7 * np.max(np.abs(ref))
