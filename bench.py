@@ -99,6 +99,28 @@ def run_form(w, Xd, Zd, nbr, yd, precision, steps, warmup, grad):
                 stages={k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1] > 0})
 
 
+def estimate_leg(w, Xd, Zd, yd, precision="fp32"):
+    """L-BFGS estimation of (sigma1^2, range, s2) at C2 from a perturbed start,
+    every evaluation on the GPU, neighbours re-selected at power-of-two
+    iterations and at convergence (one whole estimation, timed once)."""
+    import torch
+    from paper_2507_05064_amd.estimate import estimate_gaussian
+    from paper_2507_05064_amd.vif import VifContext
+    ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=w.likelihood, precision=precision,
+                     tau_m=w.tau_m)
+    theta0 = w.theta * np.array([1.5, 0.7, 2.0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = estimate_gaussian(ctx, Xd, Zd, yd, theta0, reselect=True)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ctx.close()
+    return {"seconds": sec, "theta0": [float(v) for v in theta0], "theta_hat": [float(v) for v in res["theta"]],
+            "theta_true": [float(v) for v in w.theta], "nll": res["nll"], "iterations": res["iterations"],
+            "evaluations": res["evaluations"], "reselections": res["reselections"], "restarts": res["restarts"],
+            "lbfgs_message": res["message"], "form": precision}
+
+
 def _pct(v, q):
     return float(np.percentile(np.asarray(v), q))
 
@@ -436,6 +458,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "bytes_per_launch": nbytes, "avg_launch_ms": fac_ms},
     }
+    res["estimate"] = {"fp32": estimate_leg(w, Xd, Zd, yd, "fp32"), "fp64": estimate_leg(w, Xd, Zd, yd, "fp64")}
     if not args.no_batch:
         res["batch"] = batch_leg(args.steps, args.warmup, lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_laplace:
