@@ -10,13 +10,15 @@ Sigma_dagger^{-1} y = Q y - Q Sigma_mn^T M^{-1} Sigma_mn Q y, Q = B^T D^{-1} B.
 Reading (Q12, the paper is silent): a prediction point conditions only on
 training points -- its m_v nearest training points by the residual
 correlation of Sec. 6 -- so B_p = I and row p of B_po holds -A^p over N(p),
-with A^p from eq. D_A_Vecchia applied to the prediction point.
+with A^p from eq. D_A_Vecchia applied to the prediction point. The
+predictive variances are the diagonal of Sigma_dagger^p of the same
+proposition (App. C.1).
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as sp
-from scipy.linalg import cho_factor, cho_solve
+from scipy.linalg import cho_factor, cho_solve, solve_triangular
 
 from oracle import vif_oracle as vo
 
@@ -71,6 +73,47 @@ def predictive_mean(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarr
         low = np.zeros(npred)
         inner = y
     return low - Bpo @ inner
+
+
+def predictive_variance(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray, Xp: np.ndarray,
+                        nbr_p: np.ndarray) -> np.ndarray:
+    """Diagonal of Sigma_dagger^p of Prop. 2.1 (eq. pred_VIF; App. C.1), the
+    predictive variances of y^p, with B_p = I, written densely in the
+    paper's first (unexpanded) form:
+      Sigma^p = D_p + B_po Q^{-1} B_po^T + S_pm S_m^{-1} S_mp
+                - L Sigma_dagger^{-1} L^T,
+      L = S_pm S_m^{-1} S_mn - B_po Q^{-1},  Q^{-1} = B^{-1} D B^{-T},
+      Sigma_dagger = S_nm S_m^{-1} S_mn + Q^{-1}.
+    D_p carries the nugget (the response), as the training D does. Dense in
+    n: small cases only."""
+    n, npred = X.shape[0], Xp.shape[0]
+    ind = vo.inducing(model, X, Z)
+    fac = vo.vecchia_factor(model, X, ind, nbr)
+    B = np.eye(n)
+    for s_ in range(nbr.shape[1]):
+        v = nbr[:, s_] >= 0
+        B[np.nonzero(v)[0], nbr[v, s_]] = -fac.A[v, s_]
+    Binv = solve_triangular(B, np.eye(n), lower=True)
+    Qinv = Binv @ (fac.D[:, None] * Binv.T)
+    XA = np.vstack([X, Xp])
+    indA = vo.inducing(model, XA, Z)
+    Ap, Dp = vo.vecchia_factor_points(model, XA, indA, nbr_p, n + np.arange(npred))
+    Bpo = np.zeros((npred, n))
+    for s_ in range(nbr_p.shape[1]):
+        v = nbr_p[:, s_] >= 0
+        Bpo[np.nonzero(v)[0], nbr_p[v, s_]] = -Ap[v, s_]
+    if ind.m:
+        Smnp = vo.cov(model, Z, Xp)
+        low_pn = Smnp.T @ cho_solve(ind.cf, ind.Smn)        # S_pm S_m^{-1} S_mn
+        low_pp = np.einsum("ip,ip->p", Smnp, cho_solve(ind.cf, Smnp))
+        Sdag = ind.Smn.T @ cho_solve(ind.cf, ind.Smn) + Qinv
+    else:
+        low_pn = np.zeros((npred, n))
+        low_pp = np.zeros(npred)
+        Sdag = Qinv
+    L = low_pn - Bpo @ Qinv
+    cS = cho_factor(Sdag, lower=True)
+    return Dp + np.einsum("pi,pi->p", Bpo @ Qinv, Bpo) + low_pp - np.einsum("pi,ip->p", L, cho_solve(cS, L.T))
 
 
 def laplace_predictive_mean(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray, mode: np.ndarray,

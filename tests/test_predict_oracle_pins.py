@@ -6,7 +6,11 @@
     Q_pn (Q_nn + diag(K - Q_nn) + s2 I)^{-1} y, Q = K_.m K_m^{-1} K_m.;
   * in general, the conditional mean of the joint covariance that
     eq. vecchia_pred defines, built densely (B_p = I);
-  * the prediction neighbours are the brute-force smallest keys."""
+  * the prediction neighbours are the brute-force smallest keys.
+The predictive variances (diagonal of Sigma_dagger^p, App. C.1) are pinned
+the same way: the exact GP variance under full conditioning, the FITC
+variance with no neighbours, the conditional variance of the dense joint
+covariance, and D_p alone when m = 0."""
 import numpy as np
 import pytest
 
@@ -107,3 +111,73 @@ def test_laplace_predictive_mean_with_full_conditioning_is_the_latent_conditiona
     om = po.laplace_predictive_mean(lat, X, Z, nbr, b, Xp, nbr_p)
     ref = vo.cov(lat, Xp, X) @ np.linalg.solve(vo.cov(lat, X, X) + lat.s2 * np.eye(n), b)
     assert np.max(np.abs(om - ref)) <= 1e-7 * np.max(np.abs(ref))
+
+
+def _joint_cov(model, X, Xp, Z, nbr, nbr_p):
+    """Dense joint covariance of (y, y^p) under eq. vecchia_pred with B_p = I."""
+    n, npred = X.shape[0], Xp.shape[0]
+    ind = vo.inducing(model, X, Z)
+    XA = np.vstack([X, Xp])
+    indA = vo.inducing(model, XA, Z)
+    fac = vo.vecchia_factor(model, X, ind, nbr)
+    Ap, Dp = vo.vecchia_factor_points(model, XA, indA, nbr_p, n + np.arange(npred))
+    N = n + npred
+    BJ = np.eye(N)
+    for i in range(n):
+        for s_ in range(nbr.shape[1]):
+            if nbr[i, s_] >= 0:
+                BJ[i, nbr[i, s_]] = -fac.A[i, s_]
+    for j in range(npred):
+        for s_ in range(nbr_p.shape[1]):
+            if nbr_p[j, s_] >= 0:
+                BJ[n + j, nbr_p[j, s_]] = -Ap[j, s_]
+    res = np.linalg.inv(BJ.T @ np.diag(1.0 / np.concatenate([fac.D, Dp])) @ BJ)
+    if Z.shape[0]:
+        Kzm = vo.cov(model, Z, XA)
+        res = res + Kzm.T @ np.linalg.solve(vo.cov(model, Z, Z), Kzm)
+    return res, Dp
+
+
+@pytest.mark.parametrize("m", [0, 12])
+def test_full_conditioning_gives_exact_gp_variance(m):
+    model, X, Xp, Z, y = _setup(m=m)
+    n = X.shape[0]
+    nbr = -np.ones((n, n - 1), dtype=np.int64)
+    for i in range(n):
+        nbr[i, :i] = np.arange(i)
+    nbr_p = np.tile(np.arange(n), (Xp.shape[0], 1))
+    var = po.predictive_variance(model, X, Z, nbr, Xp, nbr_p)
+    Kpn = vo.cov(model, Xp, X)
+    ref = model.sigma1_sq + model.s2 - np.einsum(
+        "pi,ip->p", Kpn, np.linalg.solve(vo.cov(model, X, X) + model.s2 * np.eye(n), Kpn.T))
+    assert np.max(np.abs(var - ref)) <= 1e-8 * np.max(ref)
+
+
+def test_no_neighbours_gives_fitc_variance():
+    model, X, Xp, Z, y = _setup()
+    n = X.shape[0]
+    var = po.predictive_variance(model, X, Z, np.zeros((n, 0), dtype=np.int64), Xp,
+                                 np.zeros((Xp.shape[0], 0), dtype=np.int64))
+    Kmm = vo.cov(model, Z, Z)
+    Kmn, Kmp = vo.cov(model, Z, X), vo.cov(model, Z, Xp)
+    Q = Kmn.T @ np.linalg.solve(Kmm, Kmn)
+    S = Q + np.diag(np.diag(vo.cov(model, X, X) - Q)) + model.s2 * np.eye(n)
+    Qpn = Kmp.T @ np.linalg.solve(Kmm, Kmn)
+    ref = model.sigma1_sq + model.s2 - np.einsum("pi,ip->p", Qpn, np.linalg.solve(S, Qpn.T))
+    assert np.max(np.abs(var - ref)) <= 1e-9 * np.max(ref)
+
+
+@pytest.mark.parametrize("m", [0, 12])
+def test_variance_is_the_conditional_of_the_joint_vecchia_covariance(m):
+    model, X, Xp, Z, y = _setup(n=120, npred=15, m=m)
+    n, mv = X.shape[0], 5
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, mv)
+    nbr_p = po.prediction_neighbours(model, X, Z, Xp, mv)
+    var = po.predictive_variance(model, X, Z, nbr, Xp, nbr_p)
+    C, Dp = _joint_cov(model, X, Xp, Z, nbr, nbr_p)
+    ref = np.diag(C[n:, n:]) - np.einsum("pi,ip->p", C[n:, :n], np.linalg.solve(C[:n, :n], C[:n, n:]))
+    assert np.max(np.abs(var - ref)) <= 1e-8 * np.max(ref)
+    if m == 0:  # pure Vecchia: the prediction point's own conditional variance
+        assert np.max(np.abs(var - Dp)) <= 1e-10 * np.max(Dp)
+    assert np.all(var >= Dp - 1e-10)
