@@ -289,8 +289,14 @@ vif_status vif_select_neighbors_pred(vif_ctx* ctx, const double* Xp, int64_t n_p
  * context pass the mode: the result is then omega_p of Prop. 3.1, the
  * latent predictive mean of the VIF-Laplace approximation (the same
  * expression with b~ in place of y and the latent factor). Device arrays: y (n), Xp
- * (n_p x d), nbrp (n_p x m_v), mean_out (n_p). var_out must be NULL
- * (predictive variances are not provided). */
+ * (n_p x d), nbrp (n_p x m_v), mean_out (n_p).
+ * var_out (device, n_p doubles, or NULL to skip): the predictive variances
+ * of y^p, the diagonal of Sigma_dagger^p of Prop. 2.1 (App. C.1) with
+ * B_p = I, computed as D^p_j + u_j^T M'^{-1} u_j with
+ * u_j = L_m^{-1} Sigma_mj - sum_a A^p_ja L_m^{-1} Sigma_m,N(j)_a (the
+ * proposition's expansion with the B^{-1} terms cancelled); D^p carries the
+ * nugget. Gaussian contexts only: VIF_E_ARG on a latent context (its
+ * variances need the simulation of Alg. 1). */
 vif_status vif_predict(vif_ctx* ctx, const double* y, const double* Xp, const int32_t* nbrp, int64_t n_p,
                        double* mean_out, double* var_out);
 

@@ -110,7 +110,7 @@ struct vif_ctx {
   int lg_slot_cap = 0;
   // prediction workspace (grown on demand)
   int64_t pred_cap = 0;
-  void *pred_Vp = nullptr, *pred_Ap = nullptr;
+  void *pred_Vp = nullptr, *pred_Ap = nullptr, *pred_u = nullptr, *pred_Lt = nullptr;
   double *pred_Vpd = nullptr, *pred_vn = nullptr, *pred_Dp = nullptr;
 };
 
@@ -376,7 +376,7 @@ void vif_destroy(vif_ctx* c) {
                   c->slq_q, c->slq_iters, c->lg_Ut, c->lg_Ut3, c->lg_dV, c->lg_dU[0], c->lg_dU[1], c->lg_dU[2],
                   c->lg_dA[0], c->lg_dA[1], c->lg_dA[2], c->lg_MT, c->lg_M3T, c->lg_PhiT, c->lg_dD[0],
                   c->lg_dD[1], c->lg_dD[2], c->lg_mm, c->lg_vec, c->lg_part, c->lg_slots, c->pred_Vp,
-                  c->pred_Ap, c->pred_Vpd, c->pred_vn, c->pred_Dp, c->vorder};
+                  c->pred_Ap, c->pred_u, c->pred_Lt, c->pred_Vpd, c->pred_vn, c->pred_Dp, c->vorder};
   for (void* b : bufs)
     if (b) hipFree(b);
   for (int t = 0; t < ST_COUNT; ++t) {
@@ -1874,10 +1874,10 @@ vif_status vif_laplace_nll_grad(vif_ctx* c, const double* y, const double* mode,
 static vif_status ensure_pred(vif_ctx* c, int64_t np_) {
   if (np_ <= c->pred_cap) return VIF_OK;
   HIPCHK(c, hipStreamSynchronize(c->st));
-  void* old[] = {c->pred_Vp, c->pred_Ap, c->pred_Vpd, c->pred_vn, c->pred_Dp};
+  void* old[] = {c->pred_Vp, c->pred_Ap, c->pred_u, c->pred_Lt, c->pred_Vpd, c->pred_vn, c->pred_Dp};
   for (void* q : old)
     if (q) hipFree(q);
-  c->pred_Vp = c->pred_Ap = nullptr;
+  c->pred_Vp = c->pred_Ap = c->pred_u = c->pred_Lt = nullptr;
   c->pred_Vpd = c->pred_vn = c->pred_Dp = nullptr;
   c->pred_cap = 0;
   const size_t mpa = c->mp > 0 ? c->mp : 1, mva = c->cfg.m_v > 0 ? c->cfg.m_v : 1;
@@ -1887,6 +1887,8 @@ static vif_status ensure_pred(vif_ctx* c, int64_t np_) {
   };
   alloc(&c->pred_Vp, tsize(c) * np_ * mpa);
   alloc(&c->pred_Ap, tsize(c) * np_ * mva);
+  alloc(&c->pred_u, tsize(c) * np_ * mpa);
+  alloc(&c->pred_Lt, tsize(c) * mpa * mpa);
   alloc((void**)&c->pred_Vpd, sizeof(double) * np_ * mpa);
   alloc((void**)&c->pred_vn, sizeof(double) * np_);
   alloc((void**)&c->pred_Dp, sizeof(double) * np_);
@@ -1901,7 +1903,7 @@ static vif_status ensure_pred(vif_ctx* c, int64_t np_) {
 // Sigma_mn^T M^{-1} Sigma_mn B^T D^{-1} B y = V w).
 template <typename T>
 static vif_status predict_impl(vif_ctx* c, const double* y, const double* Xp, const int32_t* nbrp, int64_t np_,
-                               double* mean) {
+                               double* mean, double* var) {
   const vif_config& g = c->cfg;
   const int64_t n = g.n;
   const int mp = c->mp, mv = g.m_v;
@@ -1927,6 +1929,23 @@ static vif_status predict_impl(vif_ctx* c, const double* y, const double* Xp, co
     HIPCHK(c, hipMemcpyAsync(r, y, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
   }
   launch_pred_mean<T>(c->st, Vp, c1, (const T*)c->pred_Ap, nbrp, r, np_, mp, mv, mean);
+  if (var) {
+    // Var(y^p_j | y) = D^p_j + |L_M'^{-1} u_j|^2, u_j = Vp_j - sum_a A^p_ja V_{N(j)_a}:
+    // the App. C.1 expansion of Sigma_dagger^p with B_p = I, whitened, where
+    // every term with (B^T D^{-1} B)^{-1} or M' itself cancels. The rows
+    // S = u L_M'^{-T} go to pred_Vpd (n_p x mp doubles, free during a predict).
+    if (g.m > 0) {
+      T* u = (T*)c->pred_u;
+      T* Lt = (T*)c->pred_Lt;
+      T* S = (T*)c->pred_Vpd;
+      launch_pred_u<T>(c->st, Vp, V, (const T*)c->pred_Ap, nbrp, np_, mp, mv, u);
+      launch_transpose_cast<T>(c->st, c->LMinv, mp, Lt);
+      launch_rowmm<T>(c->st, u, Lt, nullptr, 1.0, 0.0, np_, mp, S);
+      launch_pred_var<T>(c->st, S, c->pred_Dp, np_, mp, var);
+    } else {
+      launch_pred_var<T>(c->st, (const T*)nullptr, c->pred_Dp, np_, 0, var);
+    }
+  }
   HIPCHK(c, hipGetLastError());
   return VIF_OK;
 }
@@ -1964,12 +1983,13 @@ vif_status vif_predict(vif_ctx* c, const double* y, const double* Xp, const int3
   if (!c->built) return fail(c, VIF_E_STATE, "vif_predict before a successful vif_build_factor");
   const vif_config& g = c->cfg;
   if (!y || !Xp || !mean_out || np_ < 1 || (g.m_v > 0 && !nbrp)) return fail(c, VIF_E_ARG, "NULL argument");
-  if (var_out) return fail(c, VIF_E_ARG, "predictive variances are not provided (pass var_out = NULL)");
+  if (var_out && g.likelihood != VIF_LIK_GAUSSIAN)
+    return fail(c, VIF_E_ARG, "predictive variances need the Gaussian likelihood (pass var_out = NULL)");
   vif_status s = reset_status(c);
   if (s) return s;
   if ((s = ensure_pred(c, np_))) return s;
-  s = fp32_form(c) ? predict_impl<float>(c, y, Xp, nbrp, np_, mean_out)
-                   : predict_impl<double>(c, y, Xp, nbrp, np_, mean_out);
+  s = fp32_form(c) ? predict_impl<float>(c, y, Xp, nbrp, np_, mean_out, var_out)
+                   : predict_impl<double>(c, y, Xp, nbrp, np_, mean_out, var_out);
   if (s) return s;
   return read_status(c, "vif_predict");
 }

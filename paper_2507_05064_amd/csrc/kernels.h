@@ -198,6 +198,13 @@ void launch_pred_factor(hipStream_t st, const double* X, const T* V, const doubl
 template <typename T>
 void launch_pred_mean(hipStream_t st, const T* Vp, const double* c, const T* Ap, const int32_t* nbrp,
                       const double* r, int64_t np_, int mp, int mv, double* mu);
+template <typename T>
+void launch_pred_u(hipStream_t st, const T* Vp, const T* V, const T* Ap, const int32_t* nbrp, int64_t np_, int mp,
+                   int mv, T* u);
+template <typename T>
+void launch_transpose_cast(hipStream_t st, const double* L, int mp, T* out);
+template <typename T>
+void launch_pred_var(hipStream_t st, const T* S, const double* Dp, int64_t np_, int mp, double* var);
 
 // SLQ / Laplace likelihood (slq.hip)
 void launch_log_ab(hipStream_t st, const double* sc, double* alog, double* blog);

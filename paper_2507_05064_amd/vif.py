@@ -282,12 +282,15 @@ class VifContext:
         self._check(self.lib.vif_select_neighbors_pred(self.h, _ptr(Xp), Xp.shape[0], _ptr(nbrp)))
         return nbrp
 
-    def predict(self, y: torch.Tensor, Xp: torch.Tensor, nbrp: torch.Tensor) -> torch.Tensor:
-        """Posterior predictive mean at Xp (Prop. 2.1); y = response, or the mode for a latent model."""
+    def predict(self, y: torch.Tensor, Xp: torch.Tensor, nbrp: torch.Tensor, variances: bool = False):
+        """Posterior predictive mean at Xp (Prop. 2.1); y = response, or the
+        mode for a latent model. With variances=True returns (mean, var), var
+        the predictive variances of y^p (Gaussian contexts)."""
         mu = torch.empty(Xp.shape[0], dtype=torch.float64, device="cuda")
+        var = torch.empty(Xp.shape[0], dtype=torch.float64, device="cuda") if variances else None
         self._check(self.lib.vif_predict(self.h, _ptr(y), _ptr(Xp), _ptr(nbrp) if self.m_v else None, Xp.shape[0],
-                                         _ptr(mu), None))
-        return mu
+                                         _ptr(mu), _ptr(var) if variances else None))
+        return (mu, var) if variances else mu
 
     def precond_solve(self, W: torch.Tensor, r: torch.Tensor) -> torch.Tensor:
         z = torch.empty(self.n, dtype=torch.float64, device="cuda")

@@ -1,7 +1,9 @@
 """GPU parity of prediction (Prop. 2.1, B_p = I): prediction neighbours
 bit-exact as sets against the oracle's brute force (near-ties in key within
 1e-12 accepted), and the predictive mean against the oracle on the same
-neighbour sets: FP64 within 1e-10 of max|mu|, FP32 form within 1e-4."""
+neighbour sets: FP64 within 1e-10 of max|mu|, FP32 form within 1e-4. The
+predictive variances (diagonal of Sigma_dagger^p, App. C.1) to the same
+bars relative to max var."""
 import numpy as np
 import pytest
 import torch
@@ -50,11 +52,33 @@ def test_predict_matches_oracle(n, npred, m, mv, prec):
     assert np.max(np.abs(mu - ref)) <= tol * np.max(np.abs(ref)), np.max(np.abs(mu - ref))
 
 
-def test_predict_rejects_variances():
+@pytest.mark.parametrize("n,npred,m,mv,prec", [(1000, 300, 25, 10, "fp64"), (777, 129, 0, 7, "fp64"),
+                                               (1000, 300, 25, 10, "fp32"), (1500, 1000, 100, 12, "fp64"),
+                                               (1500, 1000, 100, 12, "fp32"), (600, 70, 17, 20, "fp64")])
+def test_predictive_variances_match_oracle(n, npred, m, mv, prec):
+    from paper_2507_05064_amd.vif import VifContext
+    w, model, X, Xp, Z, nbr, y = _setup(n, npred, m, mv, seed=3 * n + npred)
+    nbr_p = po.prediction_neighbours(model, X, Z, Xp, mv)
+    ref_mu = po.predictive_mean(model, X, Z, nbr, y, Xp, nbr_p)
+    ref = po.predictive_variance(model, X, Z, nbr, Xp, nbr_p)
+    print(f"[gpu] predictive variances n={n} n_p={npred} m={m} m_v={mv} {prec}", flush=True)
+    ctx = VifContext(n, 2, m, mv, kernel=model.kernel, precision=prec)
+    ctx.build_factor(to_dev(X), to_dev(Z) if m else None, nbr_to_dev(nbr), model.theta)
+    mu, var = ctx.predict(to_dev(y), to_dev(Xp), nbr_to_dev(nbr_p), variances=True)
+    mu, var = mu.cpu().numpy(), var.cpu().numpy()
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    assert np.max(np.abs(mu - ref_mu)) <= tol * np.max(np.abs(ref_mu))
+    assert np.max(np.abs(var - ref)) <= tol * np.max(ref), np.max(np.abs(var - ref))
+    # the mean alone is unchanged by asking for the variances
+    mu2 = ctx.predict(to_dev(y), to_dev(Xp), nbr_to_dev(nbr_p)).cpu().numpy()
+    assert np.array_equal(mu, mu2)
+
+
+def test_predict_rejects_variances_on_latent_context():
     from paper_2507_05064_amd.vif import VifContext, VifError
     import ctypes
     w, model, X, Xp, Z, nbr, y = _setup(300, 10, 10, 5, seed=1)
-    ctx = VifContext(300, 2, 10, 5, kernel=model.kernel)
+    ctx = VifContext(300, 2, 10, 5, kernel=model.kernel, likelihood="bernoulli_logit")
     ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), model.theta)
     var = torch.empty(10, dtype=torch.float64, device="cuda")
     mu = torch.empty(10, dtype=torch.float64, device="cuda")
