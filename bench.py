@@ -121,6 +121,49 @@ def estimate_leg(w, Xd, Zd, yd, precision="fp32"):
             "lbfgs_message": res["message"], "form": precision}
 
 
+def predict_leg(w, Xd, Zd, nbr, yd, n_pred=100_000, reps=5):
+    """Prediction at C2 (Prop. 2.1, B_p = I) at n_pred seeded uniform points:
+    the prediction-neighbour search once, then the predictive mean alone and
+    mean plus variances (median of reps calls after one warm-up), FP64 and
+    FP32 forms on the same neighbour sets; the FP32 results against FP64's."""
+    import torch
+    import vif_inputs as vi
+    from paper_2507_05064_amd.vif import VifContext
+    Xp = torch.from_numpy(vi.coords(vi.scaled(w, n_pred), 1)).to("cuda")
+    out, res = {}, {}
+    for prec in ("fp64", "fp32"):
+        ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=w.likelihood, precision=prec,
+                         tau_m=w.tau_m)
+        ctx.build_factor(Xd, Zd, nbr, w.theta)
+        if prec == "fp64":
+            ctx.select_neighbors_pred(Xp)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nbrp = ctx.select_neighbors_pred(Xp)
+            torch.cuda.synchronize()
+            out["neighbour_search_s"] = time.perf_counter() - t0
+        times = {"mean": [], "mean_var": []}
+        for r in range(reps + 1):
+            for key in times:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                got = ctx.predict(yd, Xp, nbrp, variances=(key == "mean_var"))
+                torch.cuda.synchronize()
+                if r:
+                    times[key].append(time.perf_counter() - t0)
+        mu, var = got
+        res[prec] = (mu.cpu().numpy(), var.cpu().numpy())
+        out[prec] = {"mean_ms": 1e3 * float(np.median(times["mean"])),
+                     "mean_var_ms": 1e3 * float(np.median(times["mean_var"])),
+                     "points_per_s_mean_var": n_pred / float(np.median(times["mean_var"]))}
+        ctx.close()
+    (m64, v64), (m32, v32) = res["fp64"], res["fp32"]
+    out.update({"n_pred": n_pred, "var_min": float(v64.min()), "var_max": float(v64.max()),
+                "fp32_mean_rel_diff": float(np.max(np.abs(m32 - m64)) / np.max(np.abs(m64))),
+                "fp32_var_rel_diff": float(np.max(np.abs(v32 - v64)) / np.max(v64))})
+    return out
+
+
 def _pct(v, q):
     return float(np.percentile(np.asarray(v), q))
 
@@ -458,6 +501,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "bytes_per_launch": nbytes, "avg_launch_ms": fac_ms},
     }
+    res["predict"] = predict_leg(w, Xd, Zd, nbr, yd)
     res["estimate"] = {"fp32": estimate_leg(w, Xd, Zd, yd, "fp32"), "fp64": estimate_leg(w, Xd, Zd, yd, "fp64")}
     if not args.no_batch:
         res["batch"] = batch_leg(args.steps, args.warmup, lambda msg: print(msg, file=sys.stderr, flush=True))
