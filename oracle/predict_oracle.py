@@ -75,17 +75,11 @@ def predictive_mean(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarr
     return low - Bpo @ inner
 
 
-def predictive_variance(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray, Xp: np.ndarray,
-                        nbr_p: np.ndarray) -> np.ndarray:
-    """Diagonal of Sigma_dagger^p of Prop. 2.1 (eq. pred_VIF; App. C.1), the
-    predictive variances of y^p, with B_p = I, written densely in the
-    paper's first (unexpanded) form:
-      Sigma^p = D_p + B_po Q^{-1} B_po^T + S_pm S_m^{-1} S_mp
-                - L Sigma_dagger^{-1} L^T,
-      L = S_pm S_m^{-1} S_mn - B_po Q^{-1},  Q^{-1} = B^{-1} D B^{-T},
-      Sigma_dagger = S_nm S_m^{-1} S_mn + Q^{-1}.
-    D_p carries the nugget (the response), as the training D does. Dense in
-    n: small cases only."""
+def _dense_operators(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray, Xp: np.ndarray,
+                     nbr_p: np.ndarray):
+    """The dense pieces of Prop. 2.1 with B_p = I: D_p, B_po, Q^{-1} =
+    B^{-1} D B^{-T}, S_pm S_m^{-1} S_mn, diag(S_pm S_m^{-1} S_mp), and
+    Sigma_dagger = S_nm S_m^{-1} S_mn + Q^{-1}. Small cases only."""
     n, npred = X.shape[0], Xp.shape[0]
     ind = vo.inducing(model, X, Z)
     fac = vo.vecchia_factor(model, X, ind, nbr)
@@ -111,9 +105,83 @@ def predictive_variance(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.n
         low_pn = np.zeros((npred, n))
         low_pp = np.zeros(npred)
         Sdag = Qinv
-    L = low_pn - Bpo @ Qinv
-    cS = cho_factor(Sdag, lower=True)
-    return Dp + np.einsum("pi,pi->p", Bpo @ Qinv, Bpo) + low_pp - np.einsum("pi,ip->p", L, cho_solve(cS, L.T))
+    return dict(ind=ind, fac=fac, B=B, Binv=Binv, Qinv=Qinv, Dp=Dp, Bpo=Bpo, low_pn=low_pn, low_pp=low_pp,
+                Sdag=Sdag)
+
+
+def predictive_variance(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray, Xp: np.ndarray,
+                        nbr_p: np.ndarray) -> np.ndarray:
+    """Diagonal of Sigma_dagger^p of Prop. 2.1 (eq. pred_VIF; App. C.1), the
+    predictive variances of y^p, with B_p = I, written densely in the
+    paper's first (unexpanded) form:
+      Sigma^p = D_p + B_po Q^{-1} B_po^T + S_pm S_m^{-1} S_mp
+                - L Sigma_dagger^{-1} L^T,
+      L = S_pm S_m^{-1} S_mn - B_po Q^{-1},  Q^{-1} = B^{-1} D B^{-T},
+      Sigma_dagger = S_nm S_m^{-1} S_mn + Q^{-1}.
+    D_p carries the nugget (the response), as the training D does. Dense in
+    n: small cases only. With the latent factor (s2 = the jitter tau) it is
+    the first part, eq. Part1, of the Laplace predictive variances."""
+    o = _dense_operators(model, X, Z, nbr, Xp, nbr_p)
+    Bpo, Qinv = o["Bpo"], o["Qinv"]
+    L = o["low_pn"] - Bpo @ Qinv
+    cS = cho_factor(o["Sdag"], lower=True)
+    return (o["Dp"] + np.einsum("pi,pi->p", Bpo @ Qinv, Bpo) + o["low_pp"]
+            - np.einsum("pi,ip->p", L, cho_solve(cS, L.T)))
+
+
+def laplace_predictive_variance(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray, W: np.ndarray,
+                                Xp: np.ndarray, nbr_p: np.ndarray) -> np.ndarray:
+    """diag(Omega_p), the latent predictive variances of Prop. 3.1 at a mode
+    with negative log-likelihood Hessian W (eq. CovPredNG), exactly and
+    densely, split as in Sec. 4.4: eq. Part1 (predictive_variance on the
+    latent factor) plus eq. Part2,
+      diag(L Sigma_dagger^{-1} (Sigma_dagger^{-1} + W)^{-1} Sigma_dagger^{-1} L^T)."""
+    o = _dense_operators(model, X, Z, nbr, Xp, nbr_p)
+    L = o["low_pn"] - o["Bpo"] @ o["Qinv"]
+    Y = np.linalg.solve(o["Sdag"], L.T)                      # Sigma_dagger^{-1} L^T
+    K = np.linalg.inv(o["Sdag"]) + np.diag(W)
+    part2 = np.einsum("ip,ip->p", Y, np.linalg.solve(K, Y))
+    return predictive_variance(model, X, Z, nbr, Xp, nbr_p) + part2
+
+
+def laplace_predictive_variance_sbpv(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray,
+                                     W: np.ndarray, Xp: np.ndarray, nbr_p: np.ndarray, e1: np.ndarray,
+                                     e2: np.ndarray, e3: np.ndarray) -> np.ndarray:
+    """The simulation-based estimator of Alg. 1 (SBPV) for diag(Omega_p),
+    with exact dense solves in place of CG. e1, e2: l x n and e3: l x m
+    standard normal draws (sample i in row i). For each sample:
+      z4 = S_nm S_m^{-1/2} e3 + B^{-1} D^{1/2} e1   ~ N(0, Sigma_dagger)
+      z5 = Sigma_dagger^{-1} z4 (by the Woodbury form Q - Q S_nm M^{-1} S_mn Q,
+           M = S_m + S_mn Q S_nm, Q = B^T D^{-1} B)
+      z6 = z5 + W^{1/2} e2                          ~ N(0, Sigma_dagger^{-1} + W)
+      z7 = (Sigma_dagger^{-1} + W)^{-1} z6
+      z8 = L Sigma_dagger^{-1} z7,
+    and the estimate is eq. Part1 + mean of z8 * z8. S_m^{1/2} is the lower
+    Cholesky factor of S_m."""
+    o = _dense_operators(model, X, Z, nbr, Xp, nbr_p)
+    ind, fac, B = o["ind"], o["fac"], o["B"]
+    n = X.shape[0]
+    Q = B.T @ (B / fac.D[:, None])
+    if ind.m:
+        Lm = np.linalg.cholesky(ind.Sm)
+        Vt = solve_triangular(Lm, ind.Smn, lower=True).T      # S_nm S_m^{-T/2}
+        M = ind.Sm + ind.Smn @ Q @ ind.Smn.T
+        QS = Q @ ind.Smn.T
+        Sdag_inv = Q - QS @ np.linalg.solve(M, QS.T)
+    else:
+        Vt = np.zeros((n, 0))
+        Sdag_inv = Q
+    L = o["low_pn"] - o["Bpo"] @ o["Qinv"]
+    acc = np.zeros(Xp.shape[0])
+    K = Sdag_inv + np.diag(W)
+    for i in range(e1.shape[0]):
+        z4 = Vt @ e3[i, :Vt.shape[1]] + o["Binv"] @ (np.sqrt(fac.D) * e1[i])
+        z5 = Sdag_inv @ z4
+        z6 = z5 + np.sqrt(W) * e2[i]
+        z7 = np.linalg.solve(K, z6)
+        z8 = L @ (Sdag_inv @ z7)
+        acc += z8 * z8
+    return predictive_variance(model, X, Z, nbr, Xp, nbr_p) + acc / e1.shape[0]
 
 
 def laplace_predictive_mean(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray, mode: np.ndarray,

@@ -181,3 +181,54 @@ def test_variance_is_the_conditional_of_the_joint_vecchia_covariance(m):
     if m == 0:  # pure Vecchia: the prediction point's own conditional variance
         assert np.max(np.abs(var - Dp)) <= 1e-10 * np.max(Dp)
     assert np.all(var >= Dp - 1e-10)
+
+
+def _latent_setup(n=120, npred=15, m=12, mv=5, tau=1e-4, seed=0):
+    model, X, Xp, Z, y = _setup(n=n, npred=npred, m=m, seed=seed)
+    lat = vo.Model(model.kernel, model.sigma1_sq, model.ls, tau)
+    ind = vo.inducing(lat, X, Z)
+    nbr = vo.neighbours(lat, X, ind, mv)
+    nbr_p = po.prediction_neighbours(lat, X, Z, Xp, mv)
+    W = np.random.default_rng(seed + 5).uniform(0.05, 0.25, n)   # logistic-like curvatures
+    return lat, X, Xp, Z, nbr, nbr_p, W
+
+
+@pytest.mark.parametrize("m", [0, 12])
+def test_laplace_variance_is_the_laplace_conditional_of_the_joint_covariance(m):
+    """Omega_p (Prop. 3.1) against its definition: with b | y ~ N(b~, (W + C^{-1})^{-1})
+    and b_p | b Gaussian under the dense joint covariance C of eq. vecchia_pred,
+    Var(b_p | y) = C_pp - C_pn C^{-1} C_np + C_pn C^{-1} (W + C^{-1})^{-1} C^{-1} C_np."""
+    lat, X, Xp, Z, nbr, nbr_p, W = _latent_setup(m=m)
+    n = X.shape[0]
+    om = po.laplace_predictive_variance(lat, X, Z, nbr, W, Xp, nbr_p)
+    C, _ = _joint_cov(lat, X, Xp, Z, nbr, nbr_p)
+    Cnn_inv = np.linalg.inv(C[:n, :n])
+    G = Cnn_inv @ C[:n, n:]
+    ref = (np.diag(C[n:, n:]) - np.einsum("ip,ip->p", C[:n, n:], G)
+           + np.einsum("ip,ip->p", G, np.linalg.solve(np.diag(W) + Cnn_inv, G)))
+    assert np.max(np.abs(om - ref)) <= 1e-7 * np.max(ref)
+
+
+def test_laplace_variance_without_curvature_is_the_prior_variance():
+    """W -> 0 (an uninformative likelihood): Omega_p -> diag(C_pp)."""
+    lat, X, Xp, Z, nbr, nbr_p, W = _latent_setup()
+    om = po.laplace_predictive_variance(lat, X, Z, nbr, np.full(X.shape[0], 1e-10), Xp, nbr_p)
+    C, _ = _joint_cov(lat, X, Xp, Z, nbr, nbr_p)
+    ref = np.diag(C[X.shape[0]:, X.shape[0]:])
+    assert np.max(np.abs(om - ref)) <= 1e-6 * np.max(ref)
+
+
+def test_sbpv_is_unbiased():
+    """Alg. 1 (Prop. PropPredVar): the mean of z8 * z8 over many samples
+    approaches eq. Part2; each z8_p ~ N(0, Part2_p), so the standard error of
+    the mean of l squares is Part2_p sqrt(2 / l); bound at 5 of them."""
+    lat, X, Xp, Z, nbr, nbr_p, W = _latent_setup(n=60, npred=6, m=8, mv=4, seed=2)
+    ell = 20000
+    rng = np.random.default_rng(11)
+    e1, e2 = rng.standard_normal((ell, 60)), rng.standard_normal((ell, 60))
+    e3 = rng.standard_normal((ell, 8))
+    est = po.laplace_predictive_variance_sbpv(lat, X, Z, nbr, W, Xp, nbr_p, e1, e2, e3)
+    exact = po.laplace_predictive_variance(lat, X, Z, nbr, W, Xp, nbr_p)
+    part2 = exact - po.predictive_variance(lat, X, Z, nbr, Xp, nbr_p)
+    assert np.all(part2 > 0)
+    assert np.all(np.abs(est - exact) <= 5 * part2 * np.sqrt(2.0 / ell)), (est - exact) / part2
