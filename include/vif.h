@@ -300,6 +300,28 @@ vif_status vif_select_neighbors_pred(vif_ctx* ctx, const double* Xp, int64_t n_p
 vif_status vif_predict(vif_ctx* ctx, const double* y, const double* Xp, const int32_t* nbrp, int64_t n_p,
                        double* mean_out, double* var_out);
 
+/* Latent predictive mean and variances of the VIF-Laplace approximation at
+ * n_p points (Prop. 3.1, B_p = I), given the mode (normally from
+ * vif_laplace_mode) and the response y, on a latent context. mean_out gets
+ * omega_p (as vif_predict with the mode). var_out gets diag(Omega_p),
+ * split as in Sec. 4.4 into eq. Part1 -- computed exactly, as vif_predict's
+ * variances on the latent factor -- and eq. Part2, estimated by the
+ * simulation of Alg. 1 (SBPV) with ell samples: for sample k,
+ *   z4 = V^T e3_k + B^{-1} D^{1/2} e1_k                ~ N(0, Sigma_dagger),
+ *   z6 = Sigma_dagger^{-1} z4 + W^{1/2} e2_k           ~ N(0, Sigma_dagger^{-1} + W),
+ *   z7 = (W + Sigma_dagger^{-1})^{-1} z6 by VIFDU-preconditioned CG to cfg.cg_tol,
+ *   z8 = L Sigma_dagger^{-1} z7 (L the prediction/training cross-covariance),
+ * and eq. Part2 ~ mean_k z8 * z8 (unbiased; Prop. PropPredVar). W = W(mode).
+ * Standard normals come from the caller (device): eps_n ((2 ell) x n: rows
+ * e1_0, e2_0, e1_1, e2_1, ...) and eps_m (ell x m; NULL when m = 0). Device
+ * arrays: y, mode (n), Xp (n_p x d), nbrp (n_p x m_v, from
+ * vif_select_neighbors_pred), mean_out, var_out (n_p). cg_iters_out (host,
+ * may be NULL): CG iterations over all samples. Errors: VIF_E_ARG on a
+ * Gaussian context, VIF_E_CG_MAXIT, VIF_E_NOT_PD (M3'), VIF_E_NAN. */
+vif_status vif_laplace_predict(vif_ctx* ctx, const double* y, const double* mode, const double* Xp,
+                               const int32_t* nbrp, int64_t n_p, int32_t ell, const double* eps_n,
+                               const double* eps_m, double* mean_out, double* var_out, int32_t* cg_iters_out);
+
 /* Applies the preconditioner chosen by vif_set_preconditioner for a given
  * diagonal W. VIFDU (Sec. 4.3.1 / App. E.1): z = P^{-1} r with
  * P = B^T W B + Sigma_dagger^{-1}, in the whitened form

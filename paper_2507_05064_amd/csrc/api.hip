@@ -111,7 +111,7 @@ struct vif_ctx {
   // prediction workspace (grown on demand)
   int64_t pred_cap = 0;
   void *pred_Vp = nullptr, *pred_Ap = nullptr, *pred_u = nullptr, *pred_Lt = nullptr;
-  double *pred_Vpd = nullptr, *pred_vn = nullptr, *pred_Dp = nullptr;
+  double *pred_Vpd = nullptr, *pred_vn = nullptr, *pred_Dp = nullptr, *pred_z8 = nullptr;
 };
 
 static vif_status fail(vif_ctx* c, vif_status s, const char* fmt, ...) {
@@ -376,7 +376,7 @@ void vif_destroy(vif_ctx* c) {
                   c->slq_q, c->slq_iters, c->lg_Ut, c->lg_Ut3, c->lg_dV, c->lg_dU[0], c->lg_dU[1], c->lg_dU[2],
                   c->lg_dA[0], c->lg_dA[1], c->lg_dA[2], c->lg_MT, c->lg_M3T, c->lg_PhiT, c->lg_dD[0],
                   c->lg_dD[1], c->lg_dD[2], c->lg_mm, c->lg_vec, c->lg_part, c->lg_slots, c->pred_Vp,
-                  c->pred_Ap, c->pred_u, c->pred_Lt, c->pred_Vpd, c->pred_vn, c->pred_Dp, c->vorder};
+                  c->pred_Ap, c->pred_u, c->pred_Lt, c->pred_Vpd, c->pred_vn, c->pred_Dp, c->pred_z8, c->vorder};
   for (void* b : bufs)
     if (b) hipFree(b);
   for (int t = 0; t < ST_COUNT; ++t) {
@@ -1874,11 +1874,11 @@ vif_status vif_laplace_nll_grad(vif_ctx* c, const double* y, const double* mode,
 static vif_status ensure_pred(vif_ctx* c, int64_t np_) {
   if (np_ <= c->pred_cap) return VIF_OK;
   HIPCHK(c, hipStreamSynchronize(c->st));
-  void* old[] = {c->pred_Vp, c->pred_Ap, c->pred_u, c->pred_Lt, c->pred_Vpd, c->pred_vn, c->pred_Dp};
+  void* old[] = {c->pred_Vp, c->pred_Ap, c->pred_u, c->pred_Lt, c->pred_Vpd, c->pred_vn, c->pred_Dp, c->pred_z8};
   for (void* q : old)
     if (q) hipFree(q);
   c->pred_Vp = c->pred_Ap = c->pred_u = c->pred_Lt = nullptr;
-  c->pred_Vpd = c->pred_vn = c->pred_Dp = nullptr;
+  c->pred_Vpd = c->pred_vn = c->pred_Dp = c->pred_z8 = nullptr;
   c->pred_cap = 0;
   const size_t mpa = c->mp > 0 ? c->mp : 1, mva = c->cfg.m_v > 0 ? c->cfg.m_v : 1;
   hipError_t e = hipSuccess;
@@ -1892,32 +1892,42 @@ static vif_status ensure_pred(vif_ctx* c, int64_t np_) {
   alloc((void**)&c->pred_Vpd, sizeof(double) * np_ * mpa);
   alloc((void**)&c->pred_vn, sizeof(double) * np_);
   alloc((void**)&c->pred_Dp, sizeof(double) * np_);
+  alloc((void**)&c->pred_z8, sizeof(double) * np_);
   if (e != hipSuccess) return fail(c, e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP, "prediction workspace");
   c->pred_cap = np_;
   return VIF_OK;
 }
 
+// Vp (the prediction points' whitened rows), A^p and D^p: the part of
+// prediction that does not depend on y.
+template <typename T>
+static void pred_setup(vif_ctx* c, const double* Xp, const int32_t* nbrp, int64_t np_) {
+  const vif_config& g = c->cfg;
+  const T* V = (const T*)(fp32_form(c) ? (const void*)c->Vf : (const void*)c->Vd);
+  T* Vp = (T*)c->pred_Vp;
+  if (g.m > 0) launch_whiten<T>(c->st, Xp, c->Zc, c->Linv, g.m, c->mp, np_, c->cp, false, Vp);
+  launch_pred_factor<T>(c->st, c->Xc, V, Xp, Vp, nbrp, g.n, np_, c->mp, g.m_v, c->cp, (T*)c->pred_Ap, c->pred_Dp,
+                        c->status);
+}
+
 // mu_p = Vp . (U^T e) + sum_a A^p_a (y - V w)_{N(p)_a}, e = yt - U w,
 // w = M'^{-1} U^T yt, yt = D^{-1/2} B y: Prop. 2.1 with B_p = I, whitened
 // (Sigma_mnp^T Sigma_m^{-1} Sigma_mn Sigma_dagger^{-1} y = Vp . U^T e and
-// Sigma_mn^T M^{-1} Sigma_mn B^T D^{-1} B y = V w).
+// Sigma_mn^T M^{-1} Sigma_mn B^T D^{-1} B y = V w). This is L Sigma_dagger^{-1} y
+// for the cross-covariance L = Sigma_mnp^T Sigma_m^{-1} Sigma_mn - B_po Q^{-1}
+// of the prediction and training points. Needs pred_setup and c->Minv;
+// scratch B.t, B.s, B.tmp, B.cp, B.ctmp.
 template <typename T>
-static vif_status predict_impl(vif_ctx* c, const double* y, const double* Xp, const int32_t* nbrp, int64_t np_,
-                               double* mean, double* var) {
+static vif_status pred_mean_apply(vif_ctx* c, LapBufs& B, const double* y, const int32_t* nbrp, int64_t np_,
+                                  double* mean) {
   const vif_config& g = c->cfg;
   const int64_t n = g.n;
   const int mp = c->mp, mv = g.m_v;
-  LapBufs B = lap_bufs(c);
   const T* V = (const T*)(fp32_form(c) ? (const void*)c->Vf : (const void*)c->Vd);
   const T* U = (const T*)c->U;
-  T* Vp = (T*)c->pred_Vp;
-  if (g.m > 0) launch_whiten<T>(c->st, Xp, c->Zc, c->Linv, g.m, mp, np_, c->cp, false, Vp);
-  launch_pred_factor<T>(c->st, c->Xc, V, Xp, Vp, nbrp, n, np_, mp, mv, c->cp, (T*)c->pred_Ap, c->pred_Dp,
-                        c->status);
   double *yt = B.t, *e = B.s, *r = B.tmp, *w = B.cp, *c1 = B.ctmp;
   launch_ytilde<T>(c->st, (const T*)c->A, c->D, c->nbr, y, n, mv, yt);
   if (g.m > 0) {
-    launch_gemm_sq(c->st, c->LMinv, c->LMinv, c->Minv, mp, true, false);
     launch_utv<T>(c->st, U, yt, nullptr, n, mp, c->chunk, B.upart);
     launch_reduce_apply(c->st, B.upart, c->nchunk, mp, c->Minv, B.cbuf, w);
     launch_t_minus_uc<T>(c->st, U, w, yt, nullptr, n, mp, e);
@@ -1928,24 +1938,89 @@ static vif_status predict_impl(vif_ctx* c, const double* y, const double* Xp, co
   } else {
     HIPCHK(c, hipMemcpyAsync(r, y, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
   }
-  launch_pred_mean<T>(c->st, Vp, c1, (const T*)c->pred_Ap, nbrp, r, np_, mp, mv, mean);
-  if (var) {
-    // Var(y^p_j | y) = D^p_j + |L_M'^{-1} u_j|^2, u_j = Vp_j - sum_a A^p_ja V_{N(j)_a}:
-    // the App. C.1 expansion of Sigma_dagger^p with B_p = I, whitened, where
-    // every term with (B^T D^{-1} B)^{-1} or M' itself cancels. The rows
-    // S = u L_M'^{-T} go to pred_Vpd (n_p x mp doubles, free during a predict).
-    if (g.m > 0) {
-      T* u = (T*)c->pred_u;
-      T* Lt = (T*)c->pred_Lt;
-      T* S = (T*)c->pred_Vpd;
-      launch_pred_u<T>(c->st, Vp, V, (const T*)c->pred_Ap, nbrp, np_, mp, mv, u);
-      launch_transpose_cast<T>(c->st, c->LMinv, mp, Lt);
-      launch_rowmm<T>(c->st, u, Lt, nullptr, 1.0, 0.0, np_, mp, S);
-      launch_pred_var<T>(c->st, S, c->pred_Dp, np_, mp, var);
-    } else {
-      launch_pred_var<T>(c->st, (const T*)nullptr, c->pred_Dp, np_, 0, var);
-    }
+  launch_pred_mean<T>(c->st, (const T*)c->pred_Vp, c1, (const T*)c->pred_Ap, nbrp, r, np_, mp, mv, mean);
+  return VIF_OK;
+}
+
+// Var(y^p_j | y) = D^p_j + |L_M'^{-1} u_j|^2, u_j = Vp_j - sum_a A^p_ja V_{N(j)_a}:
+// the App. C.1 expansion of Sigma_dagger^p with B_p = I, whitened, where
+// every term with (B^T D^{-1} B)^{-1} or M' itself cancels. The rows
+// S = u L_M'^{-T} go to pred_Vpd (n_p x mp doubles, free during a predict).
+// On a latent factor this is eq. Part1 of the Laplace predictive variances.
+template <typename T>
+static void pred_var_apply(vif_ctx* c, const int32_t* nbrp, int64_t np_, double* var) {
+  const vif_config& g = c->cfg;
+  const int mp = c->mp;
+  if (g.m > 0) {
+    const T* V = (const T*)(fp32_form(c) ? (const void*)c->Vf : (const void*)c->Vd);
+    T* u = (T*)c->pred_u;
+    T* Lt = (T*)c->pred_Lt;
+    T* S = (T*)c->pred_Vpd;
+    launch_pred_u<T>(c->st, (const T*)c->pred_Vp, V, (const T*)c->pred_Ap, nbrp, np_, mp, g.m_v, u);
+    launch_transpose_cast<T>(c->st, c->LMinv, mp, Lt);
+    launch_rowmm<T>(c->st, u, Lt, nullptr, 1.0, 0.0, np_, mp, S);
+    launch_pred_var<T>(c->st, S, c->pred_Dp, np_, mp, var);
+  } else {
+    launch_pred_var<T>(c->st, (const T*)nullptr, c->pred_Dp, np_, 0, var);
   }
+}
+
+template <typename T>
+static vif_status predict_impl(vif_ctx* c, const double* y, const double* Xp, const int32_t* nbrp, int64_t np_,
+                               double* mean, double* var) {
+  LapBufs B = lap_bufs(c);
+  pred_setup<T>(c, Xp, nbrp, np_);
+  if (c->cfg.m > 0) launch_gemm_sq(c->st, c->LMinv, c->LMinv, c->Minv, c->mp, true, false);
+  vif_status s = pred_mean_apply<T>(c, B, y, nbrp, np_, mean);
+  if (s) return s;
+  if (var) pred_var_apply<T>(c, nbrp, np_, var);
+  HIPCHK(c, hipGetLastError());
+  return VIF_OK;
+}
+
+__global__ void k_acc_sq(double* __restrict__ acc, const double* __restrict__ z, int64_t n, double scale) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) acc[i] += scale * z[i] * z[i];
+}
+
+// diag(Omega_p) of Prop. 3.1 by Alg. 1 (SBPV), variances only: eq. Part1 by
+// pred_var_apply on the latent factor, eq. Part2 as the mean of z8 * z8 over
+// ell samples with
+//   z4 = V^T e_m + B^{-1} D^{1/2} e_prior ~ N(0, Sigma_dagger)  (prior_draw)
+//   z6 = Sigma_dagger^{-1} z4 + W^{1/2} e_W ~ N(0, Sigma_dagger^{-1} + W)
+//   z7 = (W + Sigma_dagger^{-1})^{-1} z6  (VIFDU-preconditioned CG, eq. pcls1)
+//   z8 = L Sigma_dagger^{-1} z7            (pred_mean_apply with z7 as y).
+template <typename T>
+static vif_status laplace_predvar_impl(vif_ctx* c, const double* y, const double* mode, const double* Xp,
+                                       const int32_t* nbrp, int64_t np_, int ell, const double* eps_n,
+                                       const double* eps_m, double* mean, double* var, int* cg_iters) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  LapBufs B = lap_bufs(c);
+  vif_status s = ensure_schedules(c);
+  if (s) return s;
+  launch_lik(c->st, g.likelihood, g.lik_param, y, mode, n, B.g, B.W, B.part);
+  if (g.m > 0) launch_gemm_sq(c->st, c->LMinv, c->LMinv, c->Minv, c->mp, true, false);
+  build_vifdu(c, B);
+  pred_setup<T>(c, Xp, nbrp, np_);
+  if ((s = pred_mean_apply<T>(c, B, mode, nbrp, np_, mean))) return s;  // omega_p (Prop. 3.1)
+  pred_var_apply<T>(c, nbrp, np_, var);              // eq. Part1
+  double* z8 = c->pred_z8;
+  int total = 0;
+  for (int k = 0; k < ell; ++k) {
+    const double* e_prior = eps_n + (size_t)(2 * k) * n;
+    const double* e_w = eps_n + (size_t)(2 * k + 1) * n;
+    prior_draw<T>(c, B, g.m > 0 ? eps_m + (size_t)k * g.m : nullptr, e_prior, B.sb);
+    prec_matvec<T>(c, B, B.sb, nullptr, B.rhs);
+    launch_add_sqrtw(c->st, B.rhs, B.W, e_w, n);
+    int its = 0;
+    double rz0 = 0.0;
+    if ((s = pcg_plain<T>(c, B, B.rhs, B.x, nullptr, nullptr, nullptr, &its, &rz0))) return s;
+    total += its;
+    if ((s = pred_mean_apply<T>(c, B, B.x, nbrp, np_, z8))) return s;
+    hipLaunchKernelGGL(k_acc_sq, dim3((unsigned)ceil_div(np_, 256)), dim3(256), 0, c->st, var, z8, np_, 1.0 / ell);
+  }
+  if (cg_iters) *cg_iters = total;
   HIPCHK(c, hipGetLastError());
   return VIF_OK;
 }
@@ -1992,6 +2067,29 @@ vif_status vif_predict(vif_ctx* c, const double* y, const double* Xp, const int3
                    : predict_impl<double>(c, y, Xp, nbrp, np_, mean_out, var_out);
   if (s) return s;
   return read_status(c, "vif_predict");
+}
+
+vif_status vif_laplace_predict(vif_ctx* c, const double* y, const double* mode, const double* Xp,
+                               const int32_t* nbrp, int64_t np_, int32_t ell, const double* eps_n,
+                               const double* eps_m, double* mean_out, double* var_out, int32_t* cg_iters_out) {
+  if (!c) return VIF_E_ARG;
+  if (bf16_form(c)) return reject_bf16(c, "vif_laplace_predict");
+  if (!c->built) return fail(c, VIF_E_STATE, "vif_laplace_predict before a successful vif_build_factor");
+  const vif_config& g = c->cfg;
+  if (g.likelihood == VIF_LIK_GAUSSIAN) return fail(c, VIF_E_ARG, "vif_laplace_predict needs a latent likelihood");
+  if (!y || !mode || !Xp || !mean_out || !var_out || np_ < 1 || (g.m_v > 0 && !nbrp) || ell < 1 || !eps_n ||
+      (g.m > 0 && !eps_m))
+    return fail(c, VIF_E_ARG, "NULL argument, no prediction points or ell < 1");
+  vif_status s = reset_status(c);
+  if (s) return s;
+  if ((s = ensure_pred(c, np_))) return s;
+  int its = 0;
+  s = fp32_form(c) ? laplace_predvar_impl<float>(c, y, mode, Xp, nbrp, np_, ell, eps_n, eps_m, mean_out, var_out, &its)
+                   : laplace_predvar_impl<double>(c, y, mode, Xp, nbrp, np_, ell, eps_n, eps_m, mean_out, var_out,
+                                                  &its);
+  if (s) return s;
+  if (cg_iters_out) *cg_iters_out = its;
+  return read_status(c, "vif_laplace_predict");
 }
 
 vif_status vif_precond_solve(vif_ctx* c, const double* W, const double* r, double* z) {

@@ -69,7 +69,7 @@ EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors"
            "vif_mlp_forward", "vif_mlp_backward", "vif_mlp_adam", "vif_mlp_features", "vif_sample_prior",
            "vif_precond_solve", "vif_set_preconditioner", "vif_batch_create", "vif_batch_destroy", "vif_batch_last_error",
            "vif_batch_nll_grad", "vif_laplace_nll", "vif_laplace_nll_grad", "vif_select_neighbors_pred",
-           "vif_predict"]
+           "vif_predict", "vif_laplace_predict"]
 
 
 def load_library(path: Optional[str] = None):
@@ -120,6 +120,9 @@ def load_library(path: Optional[str] = None):
     lib.vif_select_neighbors_pred.restype = ctypes.c_int
     lib.vif_predict.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp]
     lib.vif_predict.restype = ctypes.c_int
+    lib.vif_laplace_predict.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp, vp, vp,
+                                        ctypes.POINTER(ctypes.c_int32)]
+    lib.vif_laplace_predict.restype = ctypes.c_int
     lib.vif_batch_create.argtypes = [ctypes.POINTER(vif_batch_config), ctypes.POINTER(ctypes.c_int64), vp,
                                      ctypes.POINTER(vp)]
     lib.vif_batch_create.restype = ctypes.c_int
@@ -291,6 +294,21 @@ class VifContext:
         self._check(self.lib.vif_predict(self.h, _ptr(y), _ptr(Xp), _ptr(nbrp) if self.m_v else None, Xp.shape[0],
                                          _ptr(mu), _ptr(var) if variances else None))
         return (mu, var) if variances else mu
+
+    def laplace_predict(self, y: torch.Tensor, mode: torch.Tensor, Xp: torch.Tensor, nbrp: torch.Tensor,
+                        eps_n: torch.Tensor, eps_m: Optional[torch.Tensor]):
+        """(omega_p, diag(Omega_p), total CG iterations): the latent predictive
+        mean and variances of Prop. 3.1 at the mode, the variances by Alg. 1
+        with ell = eps_n.shape[0] // 2 samples."""
+        ell = eps_n.shape[0] // 2
+        mu = torch.empty(Xp.shape[0], dtype=torch.float64, device="cuda")
+        var = torch.empty(Xp.shape[0], dtype=torch.float64, device="cuda")
+        its = ctypes.c_int32()
+        self._check(self.lib.vif_laplace_predict(self.h, _ptr(y), _ptr(mode), _ptr(Xp),
+                                                 _ptr(nbrp) if self.m_v else None, Xp.shape[0], ell, _ptr(eps_n),
+                                                 _ptr(eps_m) if self.m else None, _ptr(mu), _ptr(var),
+                                                 ctypes.byref(its)))
+        return mu, var, its.value
 
     def precond_solve(self, W: torch.Tensor, r: torch.Tensor) -> torch.Tensor:
         z = torch.empty(self.n, dtype=torch.float64, device="cuda")
