@@ -229,6 +229,23 @@ def laplace_leg(reps, warmup, log):
     out["fitc_speedup_warm_vs_zero"] = out["fitc_zero"]["mode_ms_median"] / out["fitc_warm"]["mode_ms_median"]
     out["factor_build_ms_median"] = _pct(build_ms, 50)
     out["mlp_train_s"] = train_s
+    # latent prediction at the mode (Prop. 3.1): omega_p and diag(Omega_p) by
+    # Alg. 1 with 10 samples at 50000 seeded uniform points
+    n_pred, ell = 50_000, 10
+    Xp = torch.from_numpy(vi.coords(vi.scaled(w, n_pred), 2)).to("cuda")
+    nbrp = ctx.select_neighbors_pred(Xp)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    eps_n = torch.randn((2 * ell, w.n), dtype=torch.float64, device="cuda", generator=g)
+    eps_m = torch.randn((ell, w.m), dtype=torch.float64, device="cuda", generator=g)
+    ctx.set_preconditioner("vifdu")
+    ctx.laplace_predict(prob.y, ref, Xp, nbrp, eps_n[:2], eps_m[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, var, its = ctx.laplace_predict(prob.y, ref, Xp, nbrp, eps_n, eps_m)
+    torch.cuda.synchronize()
+    out["predict_sbpv"] = {"n_pred": n_pred, "samples": ell, "seconds": time.perf_counter() - t0,
+                           "cg_iters_total": its, "var_min": float(var.min()), "var_max": float(var.max())}
+    log(f"laplace predict: {out['predict_sbpv']}")
     out["reps"] = reps
     out["workload"] = (f"Bernoulli-logit latent VIF: n={w.n} d={w.d} ARD Gaussian (var 1, length scales "
                        f"0.2..0.6), m={w.m} kMeans++ inducing points, m_v={w.m_v}, b from the VIF prior, "
