@@ -48,7 +48,9 @@ from scipy.linalg import cho_factor, cho_solve, solve_triangular
 MATERN12 = "matern12"
 MATERN32 = "matern32"
 GAUSSIAN_ARD = "gaussian_ard"
+MATERN52 = "matern52"
 SQRT3 = math.sqrt(3.0)
+SQRT5 = math.sqrt(5.0)
 
 
 class NotPositiveDefinite(ArithmeticError):
@@ -59,7 +61,7 @@ class NotPositiveDefinite(ArithmeticError):
 
 @dataclasses.dataclass
 class Model:
-    """kernel: one of MATERN12, MATERN32, GAUSSIAN_ARD.
+    """kernel: one of MATERN12, MATERN32, MATERN52, GAUSSIAN_ARD.
     ls: length scale(s) -- one entry (range rho, isotropic) or d entries (ARD).
     s2: diagonal of the data covariance (Gaussian nugget sigma^2, or latent
         jitter tau). tau_m: fixed jitter on Sigma_m."""
@@ -97,6 +99,8 @@ def _profile(kernel: str, t: np.ndarray) -> np.ndarray:
         return (1.0 + SQRT3 * t) * np.exp(-SQRT3 * t)
     if kernel == GAUSSIAN_ARD:
         return np.exp(-0.5 * t * t)
+    if kernel == MATERN52:
+        return (1.0 + SQRT5 * t + (5.0 / 3.0) * t * t) * np.exp(-SQRT5 * t)
     raise ValueError(kernel)
 
 
@@ -109,6 +113,8 @@ def _profile_dt_over_t(kernel: str, t: np.ndarray) -> np.ndarray:
         return -3.0 * np.exp(-SQRT3 * t)
     if kernel == GAUSSIAN_ARD:
         return -np.exp(-0.5 * t * t)
+    if kernel == MATERN52:
+        return -(5.0 / 3.0) * (1.0 + SQRT5 * t) * np.exp(-SQRT5 * t)
     raise ValueError(kernel)
 
 

@@ -21,7 +21,7 @@ def _matern_general(nu, t):
     return 2 ** (1 - nu) / special.gamma(nu) * z ** nu * special.kv(nu, z)
 
 
-@pytest.mark.parametrize("kernel,nu", [(vo.MATERN12, 0.5), (vo.MATERN32, 1.5)])
+@pytest.mark.parametrize("kernel,nu", [(vo.MATERN12, 0.5), (vo.MATERN32, 1.5), (vo.MATERN52, 2.5)])
 def test_matern_matches_bessel_form(kernel, nu):
     g = np.random.default_rng(0)
     X1, X2 = g.uniform(size=(7, 3)), g.uniform(size=(5, 3))
@@ -40,7 +40,7 @@ def test_gaussian_ard_matches_normal_density_ratio():
     np.testing.assert_allclose(vo.cov(model, X1, X2), ref, rtol=1e-12)
 
 
-@pytest.mark.parametrize("kernel,ls", [(vo.MATERN12, [0.2]), (vo.MATERN32, [0.15]),
+@pytest.mark.parametrize("kernel,ls", [(vo.MATERN12, [0.2]), (vo.MATERN32, [0.15]), (vo.MATERN52, [0.12]),
                                        (vo.GAUSSIAN_ARD, [0.2, 0.4, 0.3])])
 def test_cov_grads_match_finite_differences(kernel, ls):
     g = np.random.default_rng(2)
@@ -79,6 +79,17 @@ def test_full_conditioning_gives_exact_gp(m):
     res = vo.nll_gaussian(model, X, Z, nbr, y)
     ref = dr.gaussian_nll_dense(dr.exact_cov(model, X), y)
     assert abs(res.nll - ref) <= 1e-10 * abs(ref)
+
+
+def test_full_conditioning_gives_exact_gp_matern52():
+    """The same pin with the Matern-5/2 kernel (the smoothest kernel, whose
+    residual process is the worst conditioned)."""
+    model, X, Z, y = _small_problem(n=100, m=6, kernel=vo.MATERN52, ls=(0.1,), s2=0.05)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, X.shape[0] - 1)
+    res = vo.nll_gaussian(model, X, Z, nbr, y)
+    ref = dr.gaussian_nll_dense(dr.exact_cov(model, X), y)
+    assert abs(res.nll - ref) <= 1e-9 * abs(ref)
 
 
 def test_full_conditioning_factor_reproduces_residual_covariance():
