@@ -59,7 +59,7 @@ typedef enum {
   VIF_E_STATE = 8      /* call order violated (e.g. nll before build) */
 } vif_status;
 
-typedef enum { VIF_MATERN12 = 0, VIF_MATERN32 = 1, VIF_GAUSSIAN_ARD = 2 } vif_kernel;
+typedef enum { VIF_MATERN12 = 0, VIF_MATERN32 = 1, VIF_GAUSSIAN_ARD = 2, VIF_MATERN52 = 3 } vif_kernel;
 typedef enum { VIF_LIK_GAUSSIAN = 0, VIF_LIK_BERNOULLI_LOGIT = 1, VIF_LIK_POISSON_LOG = 2 } vif_likelihood;
 /* Arithmetic of the per-point factor, V / U storage and the low-rank
  * products. The m x m Cholesky factorisations, log-determinants and final
@@ -361,7 +361,7 @@ typedef struct {
   int32_t d;          /* input dimension, 1..8 */
   int32_t m;          /* inducing points per problem, 1..1024 */
   int32_t m_v;        /* neighbours per point, 0..30 */
-  int32_t kernel;     /* VIF_MATERN12 or VIF_MATERN32 (one range per problem) */
+  int32_t kernel;     /* VIF_MATERN12, VIF_MATERN32 or VIF_MATERN52 (one range per problem) */
   int32_t precision;  /* VIF_FP64 or VIF_FP32 */
   double tau_m;       /* jitter added to every Sigma_m */
 } vif_batch_config;

@@ -256,7 +256,7 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   if (g.d < 1 || g.d > VIF_MAX_D) return VIF_E_ARG;
   if (g.m < 0 || g.m > 1024 || g.m > g.n) return VIF_E_ARG;
   if (g.m_v < 0 || g.m_v > VIF_MAX_MV) return VIF_E_ARG;
-  if (g.kernel < 0 || g.kernel > 2 || g.likelihood < 0 || g.likelihood > 2) return VIF_E_ARG;
+  if (g.kernel < 0 || g.kernel > 3 || g.likelihood < 0 || g.likelihood > 2) return VIF_E_ARG;
   if (g.precision != VIF_FP64 && g.precision != VIF_FP32 && g.precision != VIF_BF16_IN) return VIF_E_ARG;
   if (g.kernel != VIF_GAUSSIAN_ARD && g.d > VIF_MAX_D) return VIF_E_ARG;
   vif_ctx* c = new vif_ctx();

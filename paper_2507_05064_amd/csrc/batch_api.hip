@@ -106,7 +106,7 @@ vif_status vif_batch_create(const vif_batch_config* cfg, const int64_t* n, void*
   const vif_batch_config& g = *cfg;
   if (g.nprob < 1 || g.d < 1 || g.d > VIF_MAX_D || g.m < 1 || g.m > 1024 || g.m_v < 0 || g.m_v > VIF_MAX_MV - 1)
     return VIF_E_ARG;
-  if (g.kernel != VIF_MATERN12 && g.kernel != VIF_MATERN32) return VIF_E_ARG;
+  if (g.kernel != VIF_MATERN12 && g.kernel != VIF_MATERN32 && g.kernel != VIF_MATERN52) return VIF_E_ARG;
   if (g.precision != VIF_FP64 && g.precision != VIF_FP32) return VIF_E_ARG;
   vif_batch* b = new vif_batch();
   b->cfg = g;

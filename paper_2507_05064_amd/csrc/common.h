@@ -39,9 +39,10 @@ template <> __device__ __forceinline__ bf16s store_cast<bf16s>(double v) {
 
 // Covariance c(x, x') = sigma1^2 r(t), t = ||(x - x') / lambda|| (Sec. 2,
 // Assumption 2; ARD transform of Sec. 6). Matern-1/2: e^{-t};
-// Matern-3/2: (1 + sqrt3 t) e^{-sqrt3 t}; Gaussian: e^{-t^2/2}.
+// Matern-3/2: (1 + sqrt3 t) e^{-sqrt3 t}; Gaussian: e^{-t^2/2};
+// Matern-5/2: (1 + sqrt5 t + 5 t^2 / 3) e^{-sqrt5 t}.
 struct CovParams {
-  int kernel;  // 0 Matern-1/2, 1 Matern-3/2, 2 Gaussian
+  int kernel;  // 0 Matern-1/2, 1 Matern-3/2, 2 Gaussian, 3 Matern-5/2
   int d;
   double sigma1_sq;
   double s2;                // nugget (Gaussian) or latent jitter tau
@@ -54,6 +55,10 @@ __device__ __forceinline__ T cov_profile(int kernel, T t2) {
   if (kernel == 2) return exp(T(-0.5) * t2);
   T t = sqrt(t2);
   if (kernel == 0) return exp(-t);
+  if (kernel == 3) {
+    const T s5 = T(2.23606797749979);
+    return (T(1) + s5 * t + T(5.0 / 3.0) * t2) * exp(-s5 * t);
+  }
   const T s3 = T(1.7320508075688772);
   return (T(1) + s3 * t) * exp(-s3 * t);
 }
@@ -64,6 +69,10 @@ __device__ __forceinline__ T cov_profile_dls(int kernel, T t2, T inv_ls) {
   T t = sqrt(t2);
   if (kernel == 2) return t2 * exp(T(-0.5) * t2) * inv_ls;        // t^2 e^{-t^2/2} / lambda
   if (kernel == 0) return t * exp(-t) * inv_ls;                     // t e^{-t} / lambda
+  if (kernel == 3) {  // r'(t) = -(5/3) t (1 + sqrt5 t) e^{-sqrt5 t}
+    const T s5 = T(2.23606797749979);
+    return T(5.0 / 3.0) * t2 * (T(1) + s5 * t) * exp(-s5 * t) * inv_ls;
+  }
   const T s3 = T(1.7320508075688772);
   return T(3) * t2 * exp(-s3 * t) * inv_ls;                         // 3 t^2 e^{-sqrt3 t} / lambda
 }
@@ -77,6 +86,10 @@ __device__ __forceinline__ float cov_profile<float>(int kernel, float t2) {
   if (kernel == 2) return fast_expf(-0.5f * t2);
   const float t = __builtin_amdgcn_sqrtf(t2);
   if (kernel == 0) return fast_expf(-t);
+  if (kernel == 3) {
+    const float s5 = 2.23606797749979f;
+    return (1.0f + s5 * t + (5.0f / 3.0f) * t2) * fast_expf(-s5 * t);
+  }
   const float s3 = 1.7320508075688772f;
   return (1.0f + s3 * t) * fast_expf(-s3 * t);
 }
@@ -85,6 +98,10 @@ __device__ __forceinline__ float cov_profile_dls<float>(int kernel, float t2, fl
   const float t = __builtin_amdgcn_sqrtf(t2);
   if (kernel == 2) return t2 * fast_expf(-0.5f * t2) * inv_ls;
   if (kernel == 0) return t * fast_expf(-t) * inv_ls;
+  if (kernel == 3) {
+    const float s5 = 2.23606797749979f;
+    return (5.0f / 3.0f) * t2 * (1.0f + s5 * t) * fast_expf(-s5 * t) * inv_ls;
+  }
   const float s3 = 1.7320508075688772f;
   return 3.0f * t2 * fast_expf(-s3 * t) * inv_ls;
 }
