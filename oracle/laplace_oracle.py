@@ -32,6 +32,7 @@ from oracle import vif_oracle as vo
 BERNOULLI_LOGIT = "bernoulli_logit"
 POISSON_LOG = "poisson_log"
 GAUSSIAN = "gaussian"
+GAMMA_LOG = "gamma_log"
 
 
 # ----------------------------------------------------------------------------
@@ -40,12 +41,17 @@ GAUSSIAN = "gaussian"
 # ----------------------------------------------------------------------------
 
 def loglik(lik: str, y: np.ndarray, b: np.ndarray, noise_var: float = 1.0) -> np.ndarray:
+    """noise_var: the Gaussian noise variance, or the Gamma shape a (Gamma
+    with log link: mean e^b, variance e^{2b} / a)."""
     if lik == BERNOULLI_LOGIT:
         return y * b - np.logaddexp(0.0, b)
     if lik == POISSON_LOG:
         return y * b - np.exp(b) - gammaln(y + 1.0)
     if lik == GAUSSIAN:
         return -0.5 * math.log(2 * math.pi * noise_var) - 0.5 * (y - b) ** 2 / noise_var
+    if lik == GAMMA_LOG:
+        a = noise_var
+        return a * math.log(a) - gammaln(a) + (a - 1.0) * np.log(y) - a * b - a * y * np.exp(-b)
     raise ValueError(lik)
 
 
@@ -60,6 +66,9 @@ def grad_hess(lik: str, y: np.ndarray, b: np.ndarray, noise_var: float = 1.0):
         return y - mu, mu, mu
     if lik == GAUSSIAN:
         return (y - b) / noise_var, np.full_like(b, 1.0 / noise_var), np.zeros_like(b)
+    if lik == GAMMA_LOG:
+        W = noise_var * y * np.exp(-b)
+        return W - noise_var, W, -W
     raise ValueError(lik)
 
 

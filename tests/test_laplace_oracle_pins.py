@@ -143,3 +143,23 @@ def test_fitc_newton_step_through_pcls2_matches_dense_newton_step(lik):
     ref = np.linalg.solve(np.linalg.inv(C) + np.diag(W), W * b + gr)
     got = lo.newton_step_pcls2(model, prior, lik, y, b)
     np.testing.assert_allclose(got, ref, rtol=1e-7, atol=1e-8)
+
+
+@pytest.mark.parametrize("a", [1.0, 2.5])
+def test_gamma_likelihood_matches_scipy_and_derivatives(a):
+    """Gamma with log link: log p(y|b) is scipy's Gamma log-density with
+    shape a and scale e^b / a (mean e^b); g, W and W' match central finite
+    differences of it (W = -d^2 log p / db^2, W' = dW/db)."""
+    from scipy import stats
+    g_ = np.random.default_rng(3)
+    b = g_.normal(size=25)
+    y = g_.gamma(2.0, size=25) + 0.05
+    lp = lo.loglik(lo.GAMMA_LOG, y, b, a)
+    np.testing.assert_allclose(lp, stats.gamma.logpdf(y, a, scale=np.exp(b) / a), rtol=1e-12, atol=1e-12)
+    g, W, dW = lo.grad_hess(lo.GAMMA_LOG, y, b, a)
+    f = lambda bb: stats.gamma.logpdf(y, a, scale=np.exp(bb) / a)
+    h = 1e-4
+    np.testing.assert_allclose(g, (f(b + h) - f(b - h)) / (2 * h), rtol=1e-7, atol=1e-8)
+    np.testing.assert_allclose(W, -(f(b + h) - 2 * f(b) + f(b - h)) / h ** 2, rtol=1e-5, atol=1e-6)
+    Wf = lambda bb: lo.grad_hess(lo.GAMMA_LOG, y, bb, a)[1]
+    np.testing.assert_allclose(dW, (Wf(b + h) - Wf(b - h)) / (2 * h), rtol=1e-7, atol=1e-8)
