@@ -60,7 +60,12 @@ typedef enum {
 } vif_status;
 
 typedef enum { VIF_MATERN12 = 0, VIF_MATERN32 = 1, VIF_GAUSSIAN_ARD = 2, VIF_MATERN52 = 3 } vif_kernel;
-typedef enum { VIF_LIK_GAUSSIAN = 0, VIF_LIK_BERNOULLI_LOGIT = 1, VIF_LIK_POISSON_LOG = 2 } vif_likelihood;
+typedef enum {
+  VIF_LIK_GAUSSIAN = 0,
+  VIF_LIK_BERNOULLI_LOGIT = 1,
+  VIF_LIK_POISSON_LOG = 2,
+  VIF_LIK_GAMMA_LOG = 3 /* Gamma with log link: mean e^b, shape cfg.lik_param (> 0) */
+} vif_likelihood;
 /* Arithmetic of the per-point factor, V / U storage and the low-rank
  * products. The m x m Cholesky factorisations, log-determinants and final
  * reductions are FP64 in every form.
@@ -90,7 +95,7 @@ typedef struct {
   int32_t cg_maxit;
   int32_t newton_maxit;
   double newton_tol;  /* stop when |Psi_{t+1} - Psi_t| <= newton_tol (1 + |Psi_{t+1}|) */
-  double lik_param;   /* Gaussian likelihood in vif_laplace_mode: the noise variance */
+  double lik_param;   /* Gaussian likelihood in vif_laplace_mode: the noise variance; Gamma: the shape */
 } vif_config;
 
 /* Statistics of one Laplace mode search (vif_laplace_mode). */

@@ -256,7 +256,8 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   if (g.d < 1 || g.d > VIF_MAX_D) return VIF_E_ARG;
   if (g.m < 0 || g.m > 1024 || g.m > g.n) return VIF_E_ARG;
   if (g.m_v < 0 || g.m_v > VIF_MAX_MV) return VIF_E_ARG;
-  if (g.kernel < 0 || g.kernel > 3 || g.likelihood < 0 || g.likelihood > 2) return VIF_E_ARG;
+  if (g.kernel < 0 || g.kernel > 3 || g.likelihood < 0 || g.likelihood > 3) return VIF_E_ARG;
+  if (g.likelihood == VIF_LIK_GAMMA_LOG && !(g.lik_param > 0.0)) return VIF_E_ARG;
   if (g.precision != VIF_FP64 && g.precision != VIF_FP32 && g.precision != VIF_BF16_IN) return VIF_E_ARG;
   if (g.kernel != VIF_GAUSSIAN_ARD && g.d > VIF_MAX_D) return VIF_E_ARG;
   vif_ctx* c = new vif_ctx();
@@ -1337,6 +1338,8 @@ vif_status vif_mlp_features(vif_ctx* c, const double* y, float* feat_out) {
   if (!c->built) return fail(c, VIF_E_STATE, "vif_mlp_features before a successful vif_build_factor");
   if (!y || !feat_out) return fail(c, VIF_E_ARG, "NULL y or feat_out");
   const vif_config& g = c->cfg;
+  if (g.likelihood == VIF_LIK_GAMMA_LOG)
+    return fail(c, VIF_E_ARG, "vif_mlp_features: the warm-start features cover Bernoulli-logit, Poisson-log and Gaussian");
   double lls = 0.0;
   const int L = (g.kernel == VIF_GAUSSIAN_ARD) ? g.d : 1;
   for (int k = 0; k < L; ++k) lls += 1.0 / c->cp.inv_ls[k];
@@ -1711,7 +1714,7 @@ static vif_status laplace_grad_impl(vif_ctx* c, const double* y, const double* m
   double* slots = c->lg_slots;
   // slot layout: [p * (2 + 2 ell) + 0] f(b, b), [+1] f(v, b), [+2 + k] f(u_k, q_k), [+2 + ell + k] g(q_k)
   double* tslots = slots + 3 * (2 + 2 * ell);  // traces: 4 per parameter
-  launch_lik_dW(c->st, g.likelihood, g.lik_param, mode, n, dW);
+  launch_lik_dW(c->st, g.likelihood, g.lik_param, y, mode, n, dW);
   // Ut = U M'^{-1}, Ut3 = U M3'^{-1}, u3u_i = Ut3_i . U_i
   if (m > 0) {
     to_form<T>(c, c->Minv, (int64_t)mp * mp, c->lg_MT);

@@ -214,7 +214,7 @@ int launch_sum_log1p_dw(hipStream_t st, const double* D, const double* W, int64_
 void launch_add_sqrtw(hipStream_t st, double* s, const double* W, const double* e, int64_t n);
 
 // Laplace NLL gradient (lapgrad.hip)
-void launch_lik_dW(hipStream_t st, int lik, double lpar, const double* b, int64_t n, double* dW);
+void launch_lik_dW(hipStream_t st, int lik, double lpar, const double* y, const double* b, int64_t n, double* dW);
 template <typename T>
 void launch_rowmm(hipStream_t st, const T* A, const T* M, const T* Cadd, double alpha, double beta, int64_t n, int mp,
                   T* out);

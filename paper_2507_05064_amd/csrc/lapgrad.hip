@@ -14,17 +14,19 @@
 #include "kernels.h"
 
 // dW/db = -d^3 log p / db^3 (the derivative of eq. W_diag)
-__device__ __forceinline__ double lik_dW(int lik, double lpar, double b) {
+__device__ __forceinline__ double lik_dW(int lik, double lpar, double y, double b) {
   if (lik == 1) {
     const double pi = 1.0 / (1.0 + exp(-b));
     return pi * (1.0 - pi) * (1.0 - 2.0 * pi);
   }
   if (lik == 2) return exp(b);
+  if (lik == 3) return -lpar * y * exp(-b);  // Gamma, log link: W = a y e^{-b}
   return 0.0;
 }
-__global__ void k_lik_dW(int lik, double lpar, const double* __restrict__ b, int64_t n, double* __restrict__ dW) {
+__global__ void k_lik_dW(int lik, double lpar, const double* __restrict__ y, const double* __restrict__ b, int64_t n,
+                         double* __restrict__ dW) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dW[i] = lik_dW(lik, lpar, b[i]);
+  if (i < n) dW[i] = lik_dW(lik, lpar, y[i], b[i]);
 }
 
 // out = beta * Cadd + alpha * A M  (A: n x mp rows, M: mp x mp, both T);
@@ -270,8 +272,8 @@ __global__ void k_sum_cols(const double* __restrict__ part, int nb, int cols, do
 // ---------------------------------------------------------------------------
 static inline dim3 gN(int64_t n, int per = 256) { return dim3((unsigned)ceil_div(n, per)); }
 
-void launch_lik_dW(hipStream_t st, int lik, double lpar, const double* b, int64_t n, double* dW) {
-  hipLaunchKernelGGL(k_lik_dW, gN(n), dim3(256), 0, st, lik, lpar, b, n, dW);
+void launch_lik_dW(hipStream_t st, int lik, double lpar, const double* y, const double* b, int64_t n, double* dW) {
+  hipLaunchKernelGGL(k_lik_dW, gN(n), dim3(256), 0, st, lik, lpar, y, b, n, dW);
 }
 template <typename T>
 void launch_rowmm(hipStream_t st, const T* A, const T* M, const T* Cadd, double alpha, double beta, int64_t n, int mp,

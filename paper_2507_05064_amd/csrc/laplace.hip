@@ -13,7 +13,8 @@
 #include "common.h"
 #include "kernels.h"
 
-// --- likelihoods: Bernoulli-logit, Poisson-log, Gaussian with noise variance lp ---
+// --- likelihoods: Bernoulli-logit, Poisson-log, Gaussian with noise variance lpar,
+// Gamma with log link and shape lpar (mean e^b) ---
 __device__ __forceinline__ void lik_terms(int lik, double lpar, double y, double b, double& logp, double& g,
                                           double& W) {
   if (lik == 1) {  // Bernoulli, logit link
@@ -26,6 +27,11 @@ __device__ __forceinline__ void lik_terms(int lik, double lpar, double y, double
     logp = y * b - mu - lgamma(y + 1.0);
     g = y - mu;
     W = mu;
+  } else if (lik == 3) {  // Gamma, log link, shape lpar
+    const double ye = y * exp(-b);
+    logp = lpar * log(lpar) - lgamma(lpar) + (lpar - 1.0) * log(y) - lpar * b - lpar * ye;
+    g = lpar * (ye - 1.0);
+    W = lpar * ye;
   } else {  // Gaussian with noise variance lpar
     logp = -0.9189385332046727 - 0.5 * log(lpar) - 0.5 * (y - b) * (y - b) / lpar;
     g = (y - b) / lpar;

@@ -18,10 +18,11 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvif.so"
 _lib = None
 
 MATERN12, MATERN32, GAUSSIAN_ARD, MATERN52 = 0, 1, 2, 3
-LIK_GAUSSIAN, LIK_BERNOULLI_LOGIT, LIK_POISSON_LOG = 0, 1, 2
+LIK_GAUSSIAN, LIK_BERNOULLI_LOGIT, LIK_POISSON_LOG, LIK_GAMMA_LOG = 0, 1, 2, 3
 FP64, FP32, BF16_IN = 0, 1, 2
 KERNELS = {"matern12": MATERN12, "matern32": MATERN32, "gaussian_ard": GAUSSIAN_ARD, "matern52": MATERN52}
-LIKELIHOODS = {"gaussian": LIK_GAUSSIAN, "bernoulli_logit": LIK_BERNOULLI_LOGIT, "poisson_log": LIK_POISSON_LOG}
+LIKELIHOODS = {"gaussian": LIK_GAUSSIAN, "bernoulli_logit": LIK_BERNOULLI_LOGIT, "poisson_log": LIK_POISSON_LOG,
+               "gamma_log": LIK_GAMMA_LOG}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16_in": BF16_IN}
 PRECONDITIONERS = {"vifdu": 0, "fitc": 1}
 

@@ -33,6 +33,8 @@ def _problem(lik, n, m, mv, d=2, kernel=vo.MATERN32, ls=(0.15,), seed=3):
         y = vi.bernoulli_from_uniform(expit(b), u)
     elif lik == lo.POISSON_LOG:
         y = vi.poisson_from_uniform(np.exp(b), u)
+    elif lik == lo.GAMMA_LOG:
+        y = vi.gamma_from_uniform(np.exp(b), 1.0, u)
     else:
         y = b + 0.5 * eps2[::-1]
     return w, X, Z, model, nbr, prior, y
@@ -48,6 +50,7 @@ def _ctx(w, lik, **kw):
     (lo.BERNOULLI_LOGIT, 900, 0, 8, 2, vo.MATERN32, (0.1,)),
     (lo.POISSON_LOG, 1000, 25, 12, 2, vo.MATERN12, (0.1,)),
     (lo.POISSON_LOG, 700, 16, 30, 2, vo.MATERN32, (0.1,)),
+    (lo.GAMMA_LOG, 800, 20, 10, 2, vo.MATERN32, (0.1,)),
 ])
 def test_mode_matches_oracle(lik, n, m, mv, d, kernel, ls):
     w, X, Z, model, nbr, prior, y = _problem(lik, n, m, mv, d, kernel, ls)

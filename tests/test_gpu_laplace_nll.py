@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("lik,n,m,mv,ell", [(lo.BERNOULLI_LOGIT, 700, 17, 8, 6), (lo.POISSON_LOG, 1500, 30, 12, 4),
-                                            (lo.POISSON_LOG, 900, 0, 10, 3)])
+                                            (lo.POISSON_LOG, 900, 0, 10, 3), (lo.GAMMA_LOG, 800, 20, 10, 4)])
 def test_laplace_nll_matches_oracle(lik, n, m, mv, ell):
     from paper_2507_05064_amd.vif import VifContext
     model, X, Z, nbr, prior, y, mode = _latent(n=n, m=m, mv=mv, lik=lik, seed=n)
@@ -39,7 +39,8 @@ def test_laplace_nll_matches_oracle(lik, n, m, mv, ell):
 @pytest.mark.parametrize("lik,n,m,mv,ell,prec", [(lo.POISSON_LOG, 800, 20, 8, 5, "fp64"),
                                                  (lo.BERNOULLI_LOGIT, 1200, 25, 12, 4, "fp64"),
                                                  (lo.POISSON_LOG, 700, 0, 10, 3, "fp64"),
-                                                 (lo.POISSON_LOG, 800, 20, 8, 5, "fp32")])
+                                                 (lo.POISSON_LOG, 800, 20, 8, 5, "fp32"),
+                                                 (lo.GAMMA_LOG, 800, 20, 8, 4, "fp64")])
 def test_laplace_grad_matches_oracle(lik, n, m, mv, ell, prec):
     """Gradient by STE with control variates (App. D) against the oracle's
     estimator on the same probes: FP64 within 1e-6 of max|g| (CG to 1e-11 on

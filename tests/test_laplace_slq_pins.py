@@ -35,7 +35,12 @@ def _latent(n=120, m=10, mv=6, lik=lo.BERNOULLI_LOGIT, seed=0, theta=(1.0, 0.15,
     g = np.random.default_rng(seed + 7)
     b = np.linalg.cholesky(lo.dense_cov(prior)) @ g.standard_normal(n)
     u = g.uniform(size=n)
-    y = vi.bernoulli_from_uniform(expit(b), u) if lik == lo.BERNOULLI_LOGIT else vi.poisson_from_uniform(np.exp(b), u)
+    if lik == lo.BERNOULLI_LOGIT:
+        y = vi.bernoulli_from_uniform(expit(b), u)
+    elif lik == lo.GAMMA_LOG:
+        y = vi.gamma_from_uniform(np.exp(b), 1.0, u)
+    else:
+        y = vi.poisson_from_uniform(np.exp(b), u)
     mode = lo.find_mode(prior, lik, y, tol=1e-14, solver="dense").mode
     return model, X, Z, nbr, prior, y, mode
 

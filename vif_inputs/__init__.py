@@ -188,6 +188,12 @@ def probe_normals(w: Workload, ell: int, problem: int = 0):
             g.standard_normal((w.n, ell)))
 
 
+def gamma_from_uniform(mean: np.ndarray, shape: float, u: np.ndarray) -> np.ndarray:
+    """Inverse-CDF Gamma draw with the given mean and shape from given uniforms."""
+    from scipy import stats
+    return stats.gamma.ppf(u, shape, scale=mean / shape)
+
+
 def poisson_from_uniform(rate: np.ndarray, u: np.ndarray) -> np.ndarray:
     """Inverse-CDF Poisson draw from given uniforms (any rate)."""
     out = np.zeros(rate.shape, dtype=np.float64)
