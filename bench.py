@@ -133,7 +133,7 @@ def predict_leg(w, Xd, Zd, nbr, yd, n_pred=100_000, reps=5):
     out, res = {}, {}
     for prec in ("fp64", "fp32"):
         ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=w.likelihood, precision=prec,
-                         tau_m=w.tau_m)
+                         tau_m=w.tau_m, max_pred=n_pred)
         ctx.build_factor(Xd, Zd, nbr, w.theta)
         if prec == "fp64":
             ctx.select_neighbors_pred(Xp)
@@ -185,7 +185,7 @@ def laplace_leg(reps, warmup, log):
     train_s = time.perf_counter() - t0
     del feat, target
     prob = ws.make_problem(w, 0)
-    ctx = ws.context_for(prob, cg_tol=1e-6)
+    ctx = ws.context_for(prob, cg_tol=1e-6, max_pred=50_000)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     build_ms = []
     for r in range(warmup + reps):
@@ -321,7 +321,7 @@ def c5_leg(reps, log, ell=50):
     Z = vi.inducing_points(w, X)
     Xd, Zd = torch.as_tensor(X, device="cuda"), torch.as_tensor(Z, device="cuda")
     ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=w.likelihood, precision="fp32",
-                     tau_m=w.tau_m, cg_tol=1e-6, cg_maxit=2000)
+                     tau_m=w.tau_m, cg_tol=1e-6, cg_maxit=2000, max_probes=ell)
     nbr = ctx.select_neighbors(Xd, Zd, w.theta)
     ctx.build_factor(Xd, Zd, nbr, w.theta)
     eps1, eps2, u = vi.prior_noise(w)

@@ -96,6 +96,12 @@ typedef struct {
   int32_t newton_maxit;
   double newton_tol;  /* stop when |Psi_{t+1} - Psi_t| <= newton_tol (1 + |Psi_{t+1}|) */
   double lik_param;   /* Gaussian likelihood in vif_laplace_mode: the noise variance; Gamma: the shape */
+  /* Workspace maxima: vif_create sizes the probe and prediction workspace
+   * for them, so that no later call allocates device memory. */
+  int32_t max_probes; /* most probes (ell) of vif_laplace_nll / vif_laplace_nll_grad, 0..1024; 0 on a
+                         Gaussian-likelihood context (those calls then return VIF_E_ARG) */
+  int64_t max_pred;   /* most prediction points (n_p) of vif_select_neighbors_pred, vif_predict and
+                         vif_laplace_predict; 0 = no prediction */
 } vif_config;
 
 /* Statistics of one Laplace mode search (vif_laplace_mode). */
@@ -118,7 +124,11 @@ typedef struct {
 typedef struct vif_ctx vif_ctx;
 
 /* Allocates the context and all device workspace for the sizes in cfg on the
- * current HIP device; no later call allocates. */
+ * current HIP device, including the probe workspace for cfg.max_probes
+ * probes and the prediction workspace for cfg.max_pred points; no later call
+ * allocates device memory. A later call asking for more probes or prediction
+ * points than configured returns VIF_E_ARG. VIF_E_ARG for invalid sizes,
+ * VIF_E_OOM when device memory runs out. */
 vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out);
 void vif_destroy(vif_ctx* ctx);
 const char* vif_last_error(const vif_ctx* ctx);
@@ -171,7 +181,8 @@ vif_status vif_nll_grad(vif_ctx* ctx, const double* y, double* nll_out, double* 
  * Newton step from it ends with a higher objective than Psi(0); otherwise
  * the search restarts from zero (the fallback). The converged mode does not
  * depend on the start. On VIF_E_NEWTON / VIF_E_CG_MAXIT, mode_out still
- * holds the last iterate and st the history. */
+ * holds the last iterate and st the history. y must be finite (and > 0 for
+ * the Gamma likelihood), else VIF_E_ARG naming the point. */
 vif_status vif_laplace_mode(vif_ctx* ctx, const double* y, const double* b0, double* mode_out,
                             vif_laplace_stats* st);
 
@@ -254,7 +265,8 @@ vif_status vif_mlp_features(vif_ctx* ctx, const double* y, float* feat_out);
  * V^T e3 = Sigma_mn^T L_m^{-T} e3. nll_out (host) gets the NLL, logdet_out
  * (host, may be NULL) the estimate of log det(Sigma_dagger W + I). The solves
  * A^{-1} z_k and P^{-1} z_k are kept in the context for a following gradient
- * call. The first call with a given ell allocates its workspace. With
+ * call. 1 <= ell <= cfg.max_probes, else VIF_E_ARG. y must be finite (and
+ * > 0 for the Gamma likelihood), else VIF_E_ARG naming the point. With
  * VIF_PRECOND_FITC set (vif_set_preconditioner) the log-determinant takes the
  * FITC form of eq. slq_v2 described there instead. Errors: VIF_E_CG_MAXIT,
  * VIF_E_NOT_PD (M3' or M_V), VIF_E_NAN. */
@@ -274,7 +286,7 @@ vif_status vif_laplace_nll(vif_ctx* ctx, const double* y, const double* mode, in
  * identity); the diagonal (A^{-1})_ii dW_i likewise with one pooled
  * coefficient. Derivatives of the factor are taken in forward mode (eq.
  * D_A_Vecchia differentiated) for each parameter. grad_out: host, 3
- * doubles. ell >= 2. */
+ * doubles. 2 <= ell <= cfg.max_probes. */
 vif_status vif_laplace_nll_grad(vif_ctx* ctx, const double* y, const double* mode, int32_t ell, const double* eps_n,
                                 const double* eps_m, double* nll_out, double* grad_out);
 
@@ -282,7 +294,8 @@ vif_status vif_laplace_nll_grad(vif_ctx* ctx, const double* y, const double* mod
  * training points of the last build with the smallest 1 - |rho| (residual
  * correlation, as for vif_select_neighbors; ties to the smaller index).
  * Prediction points condition on training points only (so B_p = I in
- * Prop. 2.1). nbrp_out: device, n_p x m_v int32, training indices. */
+ * Prop. 2.1). nbrp_out: device, n_p x m_v int32, training indices.
+ * 1 <= n_p <= cfg.max_pred. */
 vif_status vif_select_neighbors_pred(vif_ctx* ctx, const double* Xp, int64_t n_p, int32_t* nbrp_out);
 
 /* Posterior predictive mean at n_p points (Prop. 2.1 with B_p = I):
@@ -301,7 +314,9 @@ vif_status vif_select_neighbors_pred(vif_ctx* ctx, const double* Xp, int64_t n_p
  * u_j = L_m^{-1} Sigma_mj - sum_a A^p_ja L_m^{-1} Sigma_m,N(j)_a (the
  * proposition's expansion with the B^{-1} terms cancelled); D^p carries the
  * nugget. Gaussian contexts only: VIF_E_ARG on a latent context (its
- * variances need the simulation of Alg. 1). */
+ * variances need the simulation of Alg. 1). 1 <= n_p <= cfg.max_pred. nbrp
+ * is checked before any gather: entries -1 or 0 <= q < n, distinct, -1 only
+ * in a trailing run, else VIF_E_ARG naming the prediction point. */
 vif_status vif_predict(vif_ctx* ctx, const double* y, const double* Xp, const int32_t* nbrp, int64_t n_p,
                        double* mean_out, double* var_out);
 
@@ -321,8 +336,10 @@ vif_status vif_predict(vif_ctx* ctx, const double* y, const double* Xp, const in
  * e1_0, e2_0, e1_1, e2_1, ...) and eps_m (ell x m; NULL when m = 0). Device
  * arrays: y, mode (n), Xp (n_p x d), nbrp (n_p x m_v, from
  * vif_select_neighbors_pred), mean_out, var_out (n_p). cg_iters_out (host,
- * may be NULL): CG iterations over all samples. Errors: VIF_E_ARG on a
- * Gaussian context, VIF_E_CG_MAXIT, VIF_E_NOT_PD (M3'), VIF_E_NAN. */
+ * may be NULL): CG iterations over all samples. 1 <= n_p <= cfg.max_pred;
+ * nbrp and y are checked as for vif_predict and vif_laplace_nll. Errors:
+ * VIF_E_ARG on a Gaussian context, VIF_E_CG_MAXIT, VIF_E_NOT_PD (M3'),
+ * VIF_E_NAN. */
 vif_status vif_laplace_predict(vif_ctx* ctx, const double* y, const double* mode, const double* Xp,
                                const int32_t* nbrp, int64_t n_p, int32_t ell, const double* eps_n,
                                const double* eps_m, double* mean_out, double* var_out, int32_t* cg_iters_out);

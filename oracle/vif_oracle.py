@@ -207,24 +207,52 @@ def neighbour_keys(model: Model, X: np.ndarray, ind: Inducing, i: int,
     return 1.0 - np.abs(rho)
 
 
+def neighbour_keys_rows(model: Model, X: np.ndarray, ind: Inducing, qs: np.ndarray, jmax: int) -> np.ndarray:
+    """The keys of neighbour_keys for several query points at once: row r
+    holds 1 - |rho_{qs[r], j}| for j < jmax (the low-rank part of c_r as one
+    matrix product instead of one vector product per query)."""
+    var = residual_variance(model, ind)
+    c = cov(model, X[qs], X[:jmax])
+    if ind.m:
+        c = c - ind.Smn[:, qs].T @ ind.W[:, :jmax]
+    vi, vj = var[qs][:, None], var[None, :jmax]
+    ok = (vi > 0) & (vj > 0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rho = np.where(ok, c / np.sqrt(np.where(ok, vi * vj, 1.0)), 0.0)
+    rho = np.where(np.abs(rho) < 1e-10, 0.0, rho)
+    return 1.0 - np.abs(rho)
+
+
 def neighbours(model: Model, X: np.ndarray, ind: Inducing, m_v: int,
-               queries: Optional[Sequence[int]] = None) -> np.ndarray:
+               queries: Optional[Sequence[int]] = None, block: int = 32) -> np.ndarray:
     """N(i) for each query i (0-based): all earlier points when i <= m_v,
     otherwise the m_v earlier points with the smallest keys, ordered by
-    (key, index). Rows are padded with -1. Brute force over j < i."""
+    (key, index). Rows are padded with -1. Brute force over j < i; the keys
+    of `block` queries are formed together (neighbour_keys_rows)."""
     n = X.shape[0]
     qs = np.arange(n) if queries is None else np.asarray(queries)
     out = np.full((qs.size, max(m_v, 0)), -1, dtype=np.int64)
+    if m_v == 0:
+        return out
+    late = []
     for r, i in enumerate(qs):
-        if m_v == 0 or i == 0:
+        if i == 0:
             continue
         if i <= m_v:
             out[r, :i] = np.arange(i)
             continue
-        cand = np.arange(i)
-        key = neighbour_keys(model, X, ind, int(i), cand)
-        order = np.lexsort((cand, key))[:m_v]
-        out[r] = cand[order]
+        late.append(r)
+    late = np.array(late, dtype=np.int64)
+    # queries of similar index share a block, so each block's key matrix is short
+    late = late[np.argsort(qs[late], kind="stable")]
+    for s in range(0, late.size, block):
+        rows = late[s:s + block]
+        q = qs[rows]
+        K = neighbour_keys_rows(model, X, ind, q, int(q.max()))
+        for r, i, key in zip(rows, q, K):
+            cand = np.arange(i)
+            order = np.lexsort((cand, key[:i]))[:m_v]
+            out[r] = cand[order]
     return out
 
 
@@ -304,6 +332,26 @@ def apply_B(nbr: np.ndarray, A: np.ndarray, w: np.ndarray) -> np.ndarray:
         v = valid[:, s]
         out[v] -= A[v, s] * w[nbr[v, s]]
     return out
+
+
+def prior_sample(nbr: np.ndarray, fac: Factor, ind: Inducing, eps1: np.ndarray, eps2: np.ndarray) -> np.ndarray:
+    """A draw from N(0, Sigma^l + B^{-1} D B^{-T}) (Sec. 2.1) given standard
+    normals eps1 (m) and eps2 (n): Sigma_mn^T L_m^{-T} eps1 has covariance
+    Sigma_mn^T Sigma_m^{-1} Sigma_mn, and B^{-1} D^{1/2} eps2 the residual
+    covariance B^{-1} D B^{-T} (B^{-1} by a sparse triangular solve)."""
+    import scipy.sparse as sp
+    from scipy.sparse.linalg import spsolve_triangular
+    n = nbr.shape[0]
+    valid = nbr >= 0
+    rows = [np.arange(n)] + [np.nonzero(valid[:, s])[0] for s in range(nbr.shape[1])]
+    cols = [np.arange(n)] + [nbr[valid[:, s], s] for s in range(nbr.shape[1])]
+    vals = [np.ones(n)] + [-fac.A[valid[:, s], s] for s in range(nbr.shape[1])]
+    B = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    b = spsolve_triangular(B, np.sqrt(fac.D) * eps2, lower=True)
+    if ind.m:
+        L = np.tril(ind.cf[0])
+        b = b + ind.Smn.T @ solve_triangular(L.T, eps1, lower=False)
+    return b
 
 
 def B_times_rows(nbr: np.ndarray, A: np.ndarray, Y: np.ndarray) -> np.ndarray:

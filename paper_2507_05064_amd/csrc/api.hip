@@ -224,7 +224,7 @@ __global__ void k_check_nbr(const int32_t* nbr, const int32_t* own, int64_t n, i
 }
 
 static vif_status reset_status(vif_ctx* c) {
-  const int init[8] = {0, 0, 0x7fffffff, 0, 0, 0, 0, 0};
+  const int init[8] = {0, 0, 0x7fffffff, 0, 0, 0, 0, 0x7fffffff};
   HIPCHK(c, hipMemcpyAsync(c->status, init, sizeof init, hipMemcpyHostToDevice, c->st));
   return VIF_OK;
 }
@@ -235,6 +235,8 @@ static vif_status read_status(vif_ctx* c, const char* stage) {
   harvest(c);
   const int* s = c->hstatus;
   if (s[3]) return fail(c, VIF_E_ARG, "%s: invalid neighbour list at point %d", stage, s[2]);
+  if (s[6]) return fail(c, VIF_E_ARG, "%s: invalid response at point %d (not finite, or <= 0 for the Gamma likelihood)",
+                        stage, s[7]);
   if (s[0] == VIF_DEV_NOT_PD) {
     if (s[1] == 1) return fail(c, VIF_E_NOT_PD, "%s: Sigma_m not positive definite at column %d", stage, s[2]);
     if (s[1] == 2) return fail(c, VIF_E_NOT_PD, "%s: M' not positive definite at column %d", stage, s[2]);
@@ -245,6 +247,64 @@ static vif_status read_status(vif_ctx* c, const char* stage) {
   if (s[0] == VIF_DEV_NAN) return fail(c, VIF_E_NAN, "%s: non-finite value at %d", stage, s[2]);
   return VIF_OK;
 }
+
+// Responses: finite, and > 0 for the Gamma likelihood (log y enters its
+// density). Flags status[6] and the first bad index in status[7].
+__global__ void k_check_y(const double* __restrict__ y, int64_t n, int gamma, int* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = y[i];
+  if (!isfinite(v) || (gamma && !(v > 0.0))) {
+    status[6] = 1;
+    atomicMin(&status[7], (int)i);
+  }
+}
+
+// Conditioning sets of prediction points: entries -1 or 0 <= q < n (training
+// points), distinct, -1 only in a trailing run (status[3], first bad point
+// in status[2]).
+__global__ void k_check_pred_nbr(const int32_t* __restrict__ nbrp, int64_t np_, int mv, int64_t n, int* status) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= np_) return;
+  bool bad = false, seen_pad = false;
+  for (int a = 0; a < mv; ++a) {
+    const int q = nbrp[j * mv + a];
+    if (q < 0) {
+      if (q != -1) bad = true;
+      seen_pad = true;
+      continue;
+    }
+    if (seen_pad || q >= n) bad = true;
+    for (int b = 0; b < a; ++b)
+      if (nbrp[j * mv + b] == q) bad = true;
+  }
+  if (bad) {
+    status[3] = 1;
+    atomicMin(&status[2], (int)j);
+  }
+}
+
+// Both checks run after reset_status and read the status before any kernel
+// gathers through the checked arrays.
+static vif_status check_response(vif_ctx* c, const double* y, const char* fn) {
+  hipLaunchKernelGGL(k_check_y, dim3((unsigned)ceil_div(c->cfg.n, 256)), dim3(256), 0, c->st, y, c->cfg.n,
+                     c->cfg.likelihood == VIF_LIK_GAMMA_LOG ? 1 : 0, c->status);
+  HIPCHK(c, hipGetLastError());
+  return read_status(c, fn);
+}
+
+static vif_status check_pred_nbr(vif_ctx* c, const int32_t* nbrp, int64_t np_, const char* fn) {
+  if (c->cfg.m_v == 0) return VIF_OK;
+  hipLaunchKernelGGL(k_check_pred_nbr, dim3((unsigned)ceil_div(np_, 256)), dim3(256), 0, c->st, nbrp, np_,
+                     c->cfg.m_v, c->cfg.n, c->status);
+  HIPCHK(c, hipGetLastError());
+  return read_status(c, fn);
+}
+
+static vif_status alloc_slq(vif_ctx* c, int ell);
+static vif_status alloc_lapgrad(vif_ctx* c, int nslot);
+static vif_status alloc_pred(vif_ctx* c, int64_t np_);
+static int lapgrad_slots(int ell);
 
 extern "C" {
 
@@ -260,6 +320,9 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   if (g.likelihood == VIF_LIK_GAMMA_LOG && !(g.lik_param > 0.0)) return VIF_E_ARG;
   if (g.precision != VIF_FP64 && g.precision != VIF_FP32 && g.precision != VIF_BF16_IN) return VIF_E_ARG;
   if (g.kernel != VIF_GAUSSIAN_ARD && g.d > VIF_MAX_D) return VIF_E_ARG;
+  if (g.max_probes < 0 || g.max_probes > VIF_MAX_PROBES || g.max_pred < 0 || g.max_pred > (int64_t)0x7ffffff0)
+    return VIF_E_ARG;
+  if (g.max_probes > 0 && g.likelihood == VIF_LIK_GAUSSIAN) return VIF_E_ARG;
   vif_ctx* c = new vif_ctx();
   c->cfg = g;
   c->st = (hipStream_t)hip_stream;
@@ -359,6 +422,17 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   if (e != hipSuccess) {
     vif_destroy(c);
     return (e == hipErrorOutOfMemory) ? VIF_E_OOM : VIF_E_HIP;
+  }
+  // probe (SLQ / STE) and prediction workspace, sized by the configured maxima
+  vif_status ws = VIF_OK;
+  if (g.max_probes > 0) {
+    ws = alloc_slq(c, g.max_probes);
+    if (!ws) ws = alloc_lapgrad(c, lapgrad_slots(g.max_probes));
+  }
+  if (!ws && g.max_pred > 0) ws = alloc_pred(c, g.max_pred);
+  if (ws) {
+    vif_destroy(c);
+    return ws;
   }
   *out = c;
   return VIF_OK;
@@ -1395,6 +1469,7 @@ vif_status vif_laplace_mode(vif_ctx* c, const double* y, const double* b0, doubl
     return fail(c, VIF_E_ARG, "Gaussian likelihood needs lik_param (noise variance) > 0");
   vif_status s = reset_status(c);
   if (s) return s;
+  if ((s = check_response(c, y, "vif_laplace_mode"))) return s;
   stage_begin(c, ST_LAPLACE);
   s = fp32_form(c) ? laplace_impl<float>(c, y, b0, mode_out, st) : laplace_impl<double>(c, y, b0, mode_out, st);
   stage_end(c, ST_LAPLACE);
@@ -1464,14 +1539,9 @@ static vif_status pcg_plain(vif_ctx* c, LapBufs& B, const double* rhs, double* x
   return fail(c, VIF_E_CG_MAXIT, "conjugate gradients did not reach %g in %d iterations", g.cg_tol, g.cg_maxit);
 }
 
-static vif_status ensure_slq(vif_ctx* c, int ell) {
+// SLQ / STE workspace for up to ell probes, allocated by vif_create.
+static vif_status alloc_slq(vif_ctx* c, int ell) {
   const int ld = c->cfg.cg_maxit + 4;
-  if (ell <= c->slq_ell && ld <= c->slq_ld) return VIF_OK;
-  HIPCHK(c, hipStreamSynchronize(c->st));
-  void* old[] = {c->slq_a, c->slq_b, c->slq_rz, c->slq_terms, c->slq_work, c->slq_u, c->slq_q, c->slq_iters};
-  for (void* p : old)
-    if (p) hipFree(p);
-  c->slq_ell = c->slq_ld = 0;
   const size_t n = c->cfg.n;
   hipError_t e = hipSuccess;
   auto alloc = [&](void** p, size_t bytes) {
@@ -1486,10 +1556,15 @@ static vif_status ensure_slq(vif_ctx* c, int ell) {
   alloc((void**)&c->slq_u, sizeof(double) * ell * n);
   alloc((void**)&c->slq_q, sizeof(double) * ell * n);
   alloc((void**)&c->slq_iters, sizeof(int) * ell);
-  if (e != hipSuccess) return fail(c, e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP, "SLQ workspace: %s",
-                                   hipGetErrorString(e));
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP;
   c->slq_ell = ell;
   c->slq_ld = ld;
+  return VIF_OK;
+}
+
+static vif_status check_probes(vif_ctx* c, int ell, const char* fn) {
+  if (ell > c->slq_ell)
+    return fail(c, VIF_E_ARG, "%s: ell = %d probes exceeds the context's max_probes = %d", fn, ell, c->slq_ell);
   return VIF_OK;
 }
 
@@ -1519,7 +1594,6 @@ static vif_status laplace_nll_impl(vif_ctx* c, const double* y, const double* mo
   LapBufs B = lap_bufs(c);
   vif_status s = ensure_schedules(c);
   if (s) return s;
-  if ((s = ensure_slq(c, ell))) return s;
   const int nlb = (int)ceil_div(n, 256);
   double* dpart = B.part + nlb;
   if (g.m > 0) launch_gemm_sq(c->st, c->LMinv, c->LMinv, c->Minv, mp, true, false);
@@ -1617,38 +1691,35 @@ static vif_status laplace_nll_impl(vif_ctx* c, const double* y, const double* mo
   return VIF_OK;
 }
 
-static vif_status ensure_lapgrad(vif_ctx* c, int nslot) {
+static int lapgrad_slots(int ell) { return 3 * (2 + 2 * ell) + 16; }
+
+// Laplace-gradient workspace (tangents per parameter, per-point vectors and
+// the per-probe scalar slots for up to max_probes probes), allocated by vif_create.
+static vif_status alloc_lapgrad(vif_ctx* c, int nslot) {
   const size_t n = c->cfg.n, mpa = c->mp > 0 ? c->mp : 1, mva = c->cfg.m_v > 0 ? c->cfg.m_v : 1;
   const size_t ts = tsize(c);
   hipError_t e = hipSuccess;
   auto alloc = [&](void** p, size_t bytes) {
     if (e == hipSuccess) e = hipMalloc(p, bytes);
   };
-  if (!c->lg_ready) {
-    alloc(&c->lg_Ut, ts * n * mpa);
-    alloc(&c->lg_Ut3, ts * n * mpa);
-    alloc(&c->lg_dV, ts * n * mpa);
-    for (int k = 0; k < 3; ++k) {
-      alloc(&c->lg_dU[k], ts * n * mpa);
-      alloc(&c->lg_dA[k], ts * n * mva);
-      alloc((void**)&c->lg_dD[k], sizeof(double) * n);
-    }
-    alloc(&c->lg_MT, ts * mpa * mpa);
-    alloc(&c->lg_M3T, ts * mpa * mpa);
-    alloc(&c->lg_PhiT, ts * mpa * mpa);
-    alloc((void**)&c->lg_mm, sizeof(double) * mpa * mpa * 2);
-    alloc((void**)&c->lg_vec, sizeof(double) * n * 22 + sizeof(double) * mpa * 4);
-    alloc((void**)&c->lg_part, sizeof(double) * (ceil_div(n, 4) * 4 + 64));
-    if (e != hipSuccess) return fail(c, e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP, "gradient workspace");
-    c->lg_ready = true;
+  alloc(&c->lg_Ut, ts * n * mpa);
+  alloc(&c->lg_Ut3, ts * n * mpa);
+  alloc(&c->lg_dV, ts * n * mpa);
+  for (int k = 0; k < 3; ++k) {
+    alloc(&c->lg_dU[k], ts * n * mpa);
+    alloc(&c->lg_dA[k], ts * n * mva);
+    alloc((void**)&c->lg_dD[k], sizeof(double) * n);
   }
-  if (nslot > c->lg_slot_cap) {
-    if (c->lg_slots) hipFree(c->lg_slots);
-    c->lg_slots = nullptr;
-    alloc((void**)&c->lg_slots, sizeof(double) * nslot);
-    if (e != hipSuccess) return fail(c, VIF_E_OOM, "gradient slots");
-    c->lg_slot_cap = nslot;
-  }
+  alloc(&c->lg_MT, ts * mpa * mpa);
+  alloc(&c->lg_M3T, ts * mpa * mpa);
+  alloc(&c->lg_PhiT, ts * mpa * mpa);
+  alloc((void**)&c->lg_mm, sizeof(double) * mpa * mpa * 2);
+  alloc((void**)&c->lg_vec, sizeof(double) * n * 22 + sizeof(double) * mpa * 4);
+  alloc((void**)&c->lg_part, sizeof(double) * (ceil_div(n, 4) * 4 + 64));
+  alloc((void**)&c->lg_slots, sizeof(double) * nslot);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP;
+  c->lg_ready = true;
+  c->lg_slot_cap = nslot;
   return VIF_OK;
 }
 
@@ -1690,7 +1761,7 @@ static vif_status laplace_grad_impl(vif_ctx* c, const double* y, const double* m
   const int64_t n = g.n;
   const int mp = c->mp, mv = g.m_v, m = g.m;
   const int nslot = 3 * (2 + 2 * ell) + 16;
-  vif_status s = ensure_lapgrad(c, nslot);
+  vif_status s = nslot <= c->lg_slot_cap ? VIF_OK : check_probes(c, ell, "vif_laplace_nll_grad");
   if (s) return s;
   LapBufs B = lap_bufs(c);
   const T* U = (const T*)c->U;
@@ -1829,8 +1900,10 @@ vif_status vif_laplace_nll(vif_ctx* c, const double* y, const double* mode, int3
   const vif_config& g = c->cfg;
   if (!y || !mode || !eps_n || !nll_out || (g.m > 0 && !eps_m)) return fail(c, VIF_E_ARG, "NULL argument");
   if (ell < 1) return fail(c, VIF_E_ARG, "need at least one probe (got %d)", ell);
-  vif_status s = reset_status(c);
+  vif_status s = check_probes(c, ell, "vif_laplace_nll");
   if (s) return s;
+  if ((s = reset_status(c))) return s;
+  if ((s = check_response(c, y, "vif_laplace_nll"))) return s;
   double out3[3];
   const bool fitc = c->precond == VIF_PRECOND_FITC;
   s = fp32_form(c) ? laplace_nll_impl<float>(c, y, mode, ell, eps_n, eps_m, out3, fitc)
@@ -1854,8 +1927,10 @@ vif_status vif_laplace_nll_grad(vif_ctx* c, const double* y, const double* mode,
   if (ell < 2) return fail(c, VIF_E_ARG, "the control variates need at least two probes (got %d)", ell);
   if (g.kernel == VIF_GAUSSIAN_ARD)
     return fail(c, VIF_E_ARG, "vif_laplace_nll_grad supports the isotropic kernels (one length scale)");
-  vif_status s = reset_status(c);
+  vif_status s = check_probes(c, ell, "vif_laplace_nll_grad");
   if (s) return s;
+  if ((s = reset_status(c))) return s;
+  if ((s = check_response(c, y, "vif_laplace_nll_grad"))) return s;
   double out3[3];
   if (fp32_form(c)) {
     s = laplace_nll_impl<float>(c, y, mode, ell, eps_n, eps_m, out3);
@@ -1874,15 +1949,8 @@ vif_status vif_laplace_nll_grad(vif_ctx* c, const double* y, const double* mode,
 
 }  // extern "C"
 
-static vif_status ensure_pred(vif_ctx* c, int64_t np_) {
-  if (np_ <= c->pred_cap) return VIF_OK;
-  HIPCHK(c, hipStreamSynchronize(c->st));
-  void* old[] = {c->pred_Vp, c->pred_Ap, c->pred_u, c->pred_Lt, c->pred_Vpd, c->pred_vn, c->pred_Dp, c->pred_z8};
-  for (void* q : old)
-    if (q) hipFree(q);
-  c->pred_Vp = c->pred_Ap = c->pred_u = c->pred_Lt = nullptr;
-  c->pred_Vpd = c->pred_vn = c->pred_Dp = c->pred_z8 = nullptr;
-  c->pred_cap = 0;
+// Prediction workspace for up to np_ points, allocated by vif_create.
+static vif_status alloc_pred(vif_ctx* c, int64_t np_) {
   const size_t mpa = c->mp > 0 ? c->mp : 1, mva = c->cfg.m_v > 0 ? c->cfg.m_v : 1;
   hipError_t e = hipSuccess;
   auto alloc = [&](void** q, size_t bytes) {
@@ -1896,8 +1964,15 @@ static vif_status ensure_pred(vif_ctx* c, int64_t np_) {
   alloc((void**)&c->pred_vn, sizeof(double) * np_);
   alloc((void**)&c->pred_Dp, sizeof(double) * np_);
   alloc((void**)&c->pred_z8, sizeof(double) * np_);
-  if (e != hipSuccess) return fail(c, e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP, "prediction workspace");
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP;
   c->pred_cap = np_;
+  return VIF_OK;
+}
+
+static vif_status check_pred(vif_ctx* c, int64_t np_, const char* fn) {
+  if (np_ > c->pred_cap)
+    return fail(c, VIF_E_ARG, "%s: n_p = %lld prediction points exceeds the context's max_pred = %lld", fn,
+                (long long)np_, (long long)c->pred_cap);
   return VIF_OK;
 }
 
@@ -1941,7 +2016,7 @@ static vif_status pred_mean_apply(vif_ctx* c, LapBufs& B, const double* y, const
   } else {
     HIPCHK(c, hipMemcpyAsync(r, y, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
   }
-  launch_pred_mean<T>(c->st, (const T*)c->pred_Vp, c1, (const T*)c->pred_Ap, nbrp, r, np_, mp, mv, mean);
+  launch_pred_mean<T>(c->st, (const T*)c->pred_Vp, c1, (const T*)c->pred_Ap, nbrp, r, n, np_, mp, mv, mean);
   return VIF_OK;
 }
 
@@ -1959,7 +2034,7 @@ static void pred_var_apply(vif_ctx* c, const int32_t* nbrp, int64_t np_, double*
     T* u = (T*)c->pred_u;
     T* Lt = (T*)c->pred_Lt;
     T* S = (T*)c->pred_Vpd;
-    launch_pred_u<T>(c->st, (const T*)c->pred_Vp, V, (const T*)c->pred_Ap, nbrp, np_, mp, g.m_v, u);
+    launch_pred_u<T>(c->st, (const T*)c->pred_Vp, V, (const T*)c->pred_Ap, nbrp, g.n, np_, mp, g.m_v, u);
     launch_transpose_cast<T>(c->st, c->LMinv, mp, Lt);
     launch_rowmm<T>(c->st, u, Lt, nullptr, 1.0, 0.0, np_, mp, S);
     launch_pred_var<T>(c->st, S, c->pred_Dp, np_, mp, var);
@@ -2036,9 +2111,9 @@ vif_status vif_select_neighbors_pred(vif_ctx* c, const double* Xp, int64_t np_, 
   if (!Xp || !nbrp_out || np_ < 1) return fail(c, VIF_E_ARG, "NULL Xp / nbrp_out or no prediction points");
   const vif_config& g = c->cfg;
   if (g.m_v == 0) return VIF_OK;
-  vif_status s = reset_status(c);
+  vif_status s = check_pred(c, np_, "vif_select_neighbors_pred");
   if (s) return s;
-  if ((s = ensure_pred(c, np_))) return s;
+  if ((s = reset_status(c))) return s;
   if (g.m > 0) {
     if ((s = build_inducing(c, c->Xc, c->Zc, true))) return s;  // FP64 V of the training points
     launch_rownorm<double>(c->st, c->Vd, g.n, c->mp, c->vnorm);
@@ -2063,9 +2138,10 @@ vif_status vif_predict(vif_ctx* c, const double* y, const double* Xp, const int3
   if (!y || !Xp || !mean_out || np_ < 1 || (g.m_v > 0 && !nbrp)) return fail(c, VIF_E_ARG, "NULL argument");
   if (var_out && g.likelihood != VIF_LIK_GAUSSIAN)
     return fail(c, VIF_E_ARG, "predictive variances need the Gaussian likelihood (pass var_out = NULL)");
-  vif_status s = reset_status(c);
+  vif_status s = check_pred(c, np_, "vif_predict");
   if (s) return s;
-  if ((s = ensure_pred(c, np_))) return s;
+  if ((s = reset_status(c))) return s;
+  if ((s = check_pred_nbr(c, nbrp, np_, "vif_predict"))) return s;
   s = fp32_form(c) ? predict_impl<float>(c, y, Xp, nbrp, np_, mean_out, var_out)
                    : predict_impl<double>(c, y, Xp, nbrp, np_, mean_out, var_out);
   if (s) return s;
@@ -2083,9 +2159,11 @@ vif_status vif_laplace_predict(vif_ctx* c, const double* y, const double* mode, 
   if (!y || !mode || !Xp || !mean_out || !var_out || np_ < 1 || (g.m_v > 0 && !nbrp) || ell < 1 || !eps_n ||
       (g.m > 0 && !eps_m))
     return fail(c, VIF_E_ARG, "NULL argument, no prediction points or ell < 1");
-  vif_status s = reset_status(c);
+  vif_status s = check_pred(c, np_, "vif_laplace_predict");
   if (s) return s;
-  if ((s = ensure_pred(c, np_))) return s;
+  if ((s = reset_status(c))) return s;
+  if ((s = check_response(c, y, "vif_laplace_predict"))) return s;
+  if ((s = check_pred_nbr(c, nbrp, np_, "vif_laplace_predict"))) return s;
   int its = 0;
   s = fp32_form(c) ? laplace_predvar_impl<float>(c, y, mode, Xp, nbrp, np_, ell, eps_n, eps_m, mean_out, var_out, &its)
                    : laplace_predvar_impl<double>(c, y, mode, Xp, nbrp, np_, ell, eps_n, eps_m, mean_out, var_out,

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #define VIF_MAX_D 8
+#define VIF_MAX_PROBES 1024  // SLQ / STE probes a context can be sized for
 #define VIF_MAX_MV 31  // the per-point system (m_v neighbours + the point) fits 32 MFMA rows
 
 typedef double d4 __attribute__((ext_vector_type(4)));

@@ -668,8 +668,8 @@ __global__ __launch_bounds__(64) void k_pred_factor(const double* __restrict__ X
 template <typename T>
 __global__ __launch_bounds__(256) void k_pred_mean(const T* __restrict__ Vp, const double* __restrict__ c,
                                                    const T* __restrict__ Ap, const int32_t* __restrict__ nbrp,
-                                                   const double* __restrict__ r, int64_t np_, int mp, int mv,
-                                                   double* __restrict__ mu) {
+                                                   const double* __restrict__ r, int64_t n, int64_t np_, int mp,
+                                                   int mv, double* __restrict__ mu) {
   const int lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= np_) return;
@@ -677,7 +677,7 @@ __global__ __launch_bounds__(256) void k_pred_mean(const T* __restrict__ Vp, con
   for (int l = lane; l < mp; l += 64) s += (double)Vp[(size_t)j * mp + l] * c[l];
   if (lane < mv) {
     const int q = nbrp[j * mv + lane];
-    if (q >= 0) s += (double)Ap[j * mv + lane] * r[q];
+    if (q >= 0 && q < n) s += (double)Ap[j * mv + lane] * r[q];
   }
   s = wave_sum(s);
   if (lane == 0) mu[j] = s;
@@ -696,8 +696,8 @@ void launch_pred_factor(hipStream_t st, const double* X, const T* V, const doubl
 }
 template <typename T>
 void launch_pred_mean(hipStream_t st, const T* Vp, const double* c, const T* Ap, const int32_t* nbrp,
-                      const double* r, int64_t np_, int mp, int mv, double* mu) {
-  hipLaunchKernelGGL((k_pred_mean<T>), dim3((unsigned)ceil_div(np_, 4)), dim3(256), 0, st, Vp, c, Ap, nbrp, r, np_,
+                      const double* r, int64_t n, int64_t np_, int mp, int mv, double* mu) {
+  hipLaunchKernelGGL((k_pred_mean<T>), dim3((unsigned)ceil_div(np_, 4)), dim3(256), 0, st, Vp, c, Ap, nbrp, r, n, np_,
                      mp, mv, mu);
 }
 template void launch_pred_factor<double>(hipStream_t, const double*, const double*, const double*, const double*,
@@ -707,9 +707,9 @@ template void launch_pred_factor<float>(hipStream_t, const double*, const float*
                                         const int32_t*, int64_t, int64_t, int, int, const CovParams&, float*, double*,
                                         int*);
 template void launch_pred_mean<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
-                                       const double*, int64_t, int, int, double*);
+                                       const double*, int64_t, int64_t, int, int, double*);
 template void launch_pred_mean<float>(hipStream_t, const float*, const double*, const float*, const int32_t*,
-                                      const double*, int64_t, int, int, double*);
+                                      const double*, int64_t, int64_t, int, int, double*);
 
 // yt_i = (y_i - sum_j A_ij y_{N(i)_j}) / sqrt(D_i)  (a row of D^{-1/2} B y)
 template <typename T>

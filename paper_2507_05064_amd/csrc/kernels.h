@@ -197,10 +197,10 @@ void launch_pred_factor(hipStream_t st, const double* X, const T* V, const doubl
                         double* Dp, int* status);
 template <typename T>
 void launch_pred_mean(hipStream_t st, const T* Vp, const double* c, const T* Ap, const int32_t* nbrp,
-                      const double* r, int64_t np_, int mp, int mv, double* mu);
+                      const double* r, int64_t n, int64_t np_, int mp, int mv, double* mu);
 template <typename T>
-void launch_pred_u(hipStream_t st, const T* Vp, const T* V, const T* Ap, const int32_t* nbrp, int64_t np_, int mp,
-                   int mv, T* u);
+void launch_pred_u(hipStream_t st, const T* Vp, const T* V, const T* Ap, const int32_t* nbrp, int64_t n, int64_t np_,
+                   int mp, int mv, T* u);
 template <typename T>
 void launch_transpose_cast(hipStream_t st, const double* L, int mp, T* out);
 template <typename T>

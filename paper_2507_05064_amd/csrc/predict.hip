@@ -15,7 +15,7 @@
 template <typename T>
 __global__ __launch_bounds__(256) void k_pred_u(const T* __restrict__ Vp, const T* __restrict__ V,
                                                 const T* __restrict__ Ap, const int32_t* __restrict__ nbrp,
-                                                int64_t np_, int mp, int mv, T* __restrict__ u) {
+                                                int64_t n, int64_t np_, int mp, int mv, T* __restrict__ u) {
   const int lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= np_) return;
@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void k_pred_u(const T* __restrict__ Vp, const 
     double s = (double)Vp[(size_t)j * mp + l];
     for (int a = 0; a < mv; ++a) {
       const int q = nbrp[j * mv + a];
-      if (q >= 0) s -= (double)Ap[j * mv + a] * (double)V[(size_t)q * mp + l];
+      if (q >= 0 && q < n) s -= (double)Ap[j * mv + a] * (double)V[(size_t)q * mp + l];
     }
     u[(size_t)j * mp + l] = (T)s;
   }
@@ -56,10 +56,10 @@ __global__ __launch_bounds__(256) void k_pred_var(const T* __restrict__ S, const
 }
 
 template <typename T>
-void launch_pred_u(hipStream_t st, const T* Vp, const T* V, const T* Ap, const int32_t* nbrp, int64_t np_, int mp,
-                   int mv, T* u) {
-  hipLaunchKernelGGL((k_pred_u<T>), dim3((unsigned)ceil_div(np_, 4)), dim3(256), 0, st, Vp, V, Ap, nbrp, np_, mp, mv,
-                     u);
+void launch_pred_u(hipStream_t st, const T* Vp, const T* V, const T* Ap, const int32_t* nbrp, int64_t n, int64_t np_,
+                   int mp, int mv, T* u) {
+  hipLaunchKernelGGL((k_pred_u<T>), dim3((unsigned)ceil_div(np_, 4)), dim3(256), 0, st, Vp, V, Ap, nbrp, n, np_, mp,
+                     mv, u);
 }
 template <typename T>
 void launch_transpose_cast(hipStream_t st, const double* L, int mp, T* out) {
@@ -71,9 +71,9 @@ void launch_pred_var(hipStream_t st, const T* S, const double* Dp, int64_t np_, 
   hipLaunchKernelGGL((k_pred_var<T>), dim3((unsigned)ceil_div(np_, 4)), dim3(256), 0, st, S, Dp, np_, mp, var);
 }
 template void launch_pred_u<double>(hipStream_t, const double*, const double*, const double*, const int32_t*, int64_t,
-                                    int, int, double*);
+                                    int64_t, int, int, double*);
 template void launch_pred_u<float>(hipStream_t, const float*, const float*, const float*, const int32_t*, int64_t,
-                                   int, int, float*);
+                                   int64_t, int, int, float*);
 template void launch_transpose_cast<double>(hipStream_t, const double*, int, double*);
 template void launch_transpose_cast<float>(hipStream_t, const double*, int, float*);
 template void launch_pred_var<double>(hipStream_t, const double*, const double*, int64_t, int, double*);

@@ -40,7 +40,8 @@ class vif_config(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("m", ctypes.c_int32), ("m_v", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("likelihood", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("tau_m", ctypes.c_double), ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
-                ("newton_maxit", ctypes.c_int32), ("newton_tol", ctypes.c_double), ("lik_param", ctypes.c_double)]
+                ("newton_maxit", ctypes.c_int32), ("newton_tol", ctypes.c_double), ("lik_param", ctypes.c_double),
+                ("max_probes", ctypes.c_int32), ("max_pred", ctypes.c_int64)]
 
 
 class vif_batch_config(ctypes.Structure):
@@ -169,17 +170,18 @@ def _dbl_array(x: Sequence[float]):
 
 
 class VifContext:
-    """One vif_ctx (workspace sized for n, d, m, m_v) on torch's current stream."""
+    """One vif_ctx (workspace sized for n, d, m, m_v, max_probes probes and
+    max_pred prediction points) on torch's current stream."""
 
     def __init__(self, n: int, d: int, m: int, m_v: int, kernel: str = "matern32",
                  likelihood: str = "gaussian", precision: str = "fp64", tau_m: float = 0.0,
                  cg_tol: float = 1e-6, cg_maxit: int = 1000, newton_maxit: int = 100, newton_tol: float = 1e-9,
-                 lik_param: float = 1.0):
+                 lik_param: float = 1.0, max_probes: int = 0, max_pred: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the VIF library has no CPU path")
         self.lib = load_library()
         self.cfg = vif_config(n, d, m, m_v, KERNELS[kernel], LIKELIHOODS[likelihood], PRECISIONS[precision],
-                              tau_m, cg_tol, cg_maxit, newton_maxit, newton_tol, lik_param)
+                              tau_m, cg_tol, cg_maxit, newton_maxit, newton_tol, lik_param, max_probes, max_pred)
         self.stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()
         rc = self.lib.vif_create(ctypes.byref(self.cfg), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))

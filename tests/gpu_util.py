@@ -48,3 +48,33 @@ def factor_rel_err(A_g, D_g, A_o, D_o):
     ea = np.max(np.abs(A_g - A_o)) / max(np.max(np.abs(A_o)), 1e-300) if A_o.size else 0.0
     ed = np.max(np.abs(D_g - D_o) / np.abs(D_o))
     return ea, ed
+
+
+def euclidean_neighbours(X, mv, k=64):
+    """A valid conditioning list independent of both the GPU and the oracle's
+    selection: the m_v Euclidean-nearest earlier points (any list of earlier
+    points defines a VIF factor, Sec. 2.1), from a k-d tree queried with a
+    growing number of candidates until each row holds min(i, m_v) earlier
+    points (ties in distance to the smaller index)."""
+    from scipy.spatial import cKDTree
+    n = X.shape[0]
+    tree = cKDTree(X)
+    nbr = -np.ones((n, mv), np.int32)
+    todo = np.arange(n)
+    while todo.size:
+        kk = min(n, k)
+        dist, idx = tree.query(X[todo], k=kk)
+        idx = idx.reshape(todo.size, kk)
+        dist = dist.reshape(todo.size, kk)
+        earlier = idx < todo[:, None]
+        key = np.where(earlier, dist, np.inf)
+        order = np.lexsort((idx, key), axis=1)[:, :mv]
+        sel = np.take_along_axis(idx, order, axis=1)
+        ok_sel = np.take_along_axis(earlier, order, axis=1)
+        cnt = earlier.sum(1)
+        done = (cnt >= np.minimum(todo, mv)) | (kk == n)
+        rows = todo[done]
+        nbr[rows] = np.where(ok_sel[done], sel[done], -1)
+        todo = todo[~done]
+        k *= 4
+    return nbr

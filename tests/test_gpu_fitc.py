@@ -127,7 +127,8 @@ def test_fitc_laplace_nll_matches_oracle(lik, n, m, mv, ell):
     Zp = lo.fitc_probes(model, prior, W, e1, e3)
     ref = lo.laplace_nll_slq_fitc(model, prior, lik, y, mode, Zp, tol=1e-11)
     print(f"[gpu] fitc laplace nll {lik} n={n} m={m} m_v={mv} ell={ell}", flush=True)
-    ctx = VifContext(n, 2, m, mv, kernel=model.kernel, likelihood=lik, precision="fp64", cg_tol=1e-11, cg_maxit=2000)
+    ctx = VifContext(n, 2, m, mv, kernel=model.kernel, likelihood=lik, precision="fp64", cg_tol=1e-11, cg_maxit=2000,
+                     max_probes=ell)
     ctx.build_factor(to_dev(X), to_dev(Z) if m else None, nbr_to_dev(nbr), model.theta)
     ctx.set_preconditioner("fitc")
     eps_n = np.empty((2 * ell, n))

@@ -1,0 +1,234 @@
+"""GPU parity at the shapes of the latent workloads with many inducing
+points, where the m x m factorisations take the blocked path (m rounded up
+to 16 exceeds 208) and the m x m partial sums take their large-m forms:
+
+  * ARD Gaussian kernel in d = 5 (length scales 0.2..0.6), latent jitter
+    tau = 1e-6, Sigma_m jitter 1e-8, m_v = 30, Bernoulli-logit (the shape of
+    the n = 200k classification workload), m in {209, 257, 500};
+  * Matern-1/2 kernel (range 0.05), tau = 1e-6, m_v = 20, Poisson-log (the
+    shape of the n = 10^6 count workload), m = 500;
+  * Gaussian likelihood (Matern-3/2 and Matern-1/2, nugget 0.05) NLL and
+    adjoint gradient at m in {209, 257, 500}.
+
+Inducing points are k-means++ centres (Sec. 6) for the latent shapes and a
+random subset for the Gaussian ones, as in the workloads. n = 3000 keeps the
+oracle's dense Newton solves within seconds.
+
+Bars: neighbour sets equal (near-ties within 1e-12 in key logged); A within
+1e-10 of max|A| and D within 1e-10 relative (the whitened per-point systems
+of the latent shapes have condition numbers up to ~1/tau = 1e6, and the
+oracle solves them unwhitened, so the two factors agree to ~1e-16 * 1e6
+relative); NLL within 1e-10 relative; gradient within 1e-8 of max|g|; the
+VIFDU and FITC solves within 1e-8 of max|z|; the converged mode within 1e-8
+of max|mode| (both sides to Newton tolerance 1e-14, CG 1e-12).
+"""
+import functools
+
+import numpy as np
+import pytest
+from scipy.special import expit
+
+import vif_inputs as vi
+from oracle import laplace_oracle as lo
+from oracle import vif_oracle as vo
+from tests import dense_ref as dr
+from tests.gpu_util import compare_neighbour_sets, factor_rel_err, nbr_to_dev, to_dev
+
+pytestmark = pytest.mark.gpu
+
+ARD_LS = (0.2, 0.3, 0.4, 0.5, 0.6)
+LATENT = {
+    "ard209": (vo.GAUSSIAN_ARD, ARD_LS, 5, 209, 30, lo.BERNOULLI_LOGIT),
+    "ard257": (vo.GAUSSIAN_ARD, ARD_LS, 5, 257, 30, lo.BERNOULLI_LOGIT),
+    "ard500": (vo.GAUSSIAN_ARD, ARD_LS, 5, 500, 30, lo.BERNOULLI_LOGIT),
+    "m12_500": (vo.MATERN12, (0.05,), 2, 500, 20, lo.POISSON_LOG),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def _latent(case, n=3000):
+    kern, ls, d, m, mv, lik = LATENT[case]
+    tau_m = 1e-8 if kern == vo.GAUSSIAN_ARD else 0.0
+    w = vi.Workload(f"large-m {case}", 13, n, d, m, mv, kern, 1.0, np.array(ls, float), 1e-6, tau_m, lik,
+                    "kmeanspp")
+    X = vi.coords(w)
+    Z = vi.inducing_points(w, X)
+    model = vo.Model(kern, 1.0, np.array(ls, float), w.s2, tau_m)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, mv)
+    prior = lo.LatentVIF.build(model, X, Z, nbr)
+    eps1, eps2, u = vi.prior_noise(w)
+    b = np.linalg.cholesky(lo.dense_cov(prior)) @ eps2
+    if lik == lo.BERNOULLI_LOGIT:
+        y = vi.bernoulli_from_uniform(expit(b), u)
+    else:
+        y = vi.poisson_from_uniform(np.exp(b), u)
+    return w, X, Z, model, ind, nbr, prior, y
+
+
+@functools.lru_cache(maxsize=None)
+def _latent_mode(case):
+    w, X, Z, model, ind, nbr, prior, y = _latent(case)
+    return lo.find_mode(prior, w.likelihood, y, tol=1e-14, solver="dense")
+
+
+def _ctx(w, precision="fp64", **kw):
+    from paper_2507_05064_amd.vif import VifContext
+    return VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=w.likelihood, precision=precision,
+                      tau_m=w.tau_m, **kw)
+
+
+@pytest.mark.parametrize("case", list(LATENT))
+def test_latent_neighbours_and_factor(case):
+    w, X, Z, model, ind, nbr, prior, y = _latent(case)
+    print(f"[gpu] large-m neighbours + factor {case} n={w.n} m={w.m} m_v={w.m_v}", flush=True)
+    ctx = _ctx(w)
+    nbr_g = ctx.select_neighbors(to_dev(X), to_dev(Z), w.theta).cpu().numpy()
+    exact, ties = compare_neighbour_sets(model, X, ind, nbr, nbr_g)
+    assert exact + ties == w.n and ties <= 3, (exact, ties)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    A_g, D_g = (t.cpu().numpy() for t in ctx.export_factor())
+    ea, ed = factor_rel_err(A_g, D_g, prior.fac.A, prior.fac.D)
+    print(f"[gpu]   A err {ea:.3e} D err {ed:.3e}", flush=True)
+    assert ea <= 1e-10 and ed <= 1e-10, (ea, ed)
+
+
+@pytest.mark.parametrize("case", list(LATENT))
+def test_latent_precond_solves(case):
+    w, X, Z, model, ind, nbr, prior, y = _latent(case)
+    print(f"[gpu] large-m VIFDU / FITC solves {case}", flush=True)
+    g = np.random.default_rng(w.m)
+    W = g.uniform(0.05, 0.25, w.n)
+    r = g.standard_normal(w.n)
+    ctx = _ctx(w)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    z = ctx.precond_solve(to_dev(W), to_dev(r)).cpu().numpy()
+    ref = lo.vifdu_solve(prior, W, r)
+    ev = np.max(np.abs(z - ref)) / np.max(np.abs(ref))
+    ctx.set_preconditioner("fitc")
+    zf = ctx.precond_solve(to_dev(W), to_dev(r)).cpu().numpy()
+    reff = lo.fitc_solve(model, prior, W, r)
+    ef = np.max(np.abs(zf - reff)) / np.max(np.abs(reff))
+    print(f"[gpu]   VIFDU err {ev:.3e} FITC err {ef:.3e}", flush=True)
+    assert ev <= 1e-8 and ef <= 1e-8, (ev, ef)
+
+
+@pytest.mark.parametrize("case,precond", [("ard209", "vifdu"), ("ard500", "vifdu"), ("ard500", "fitc"),
+                                          ("m12_500", "vifdu"), ("m12_500", "fitc")])
+def test_latent_mode(case, precond):
+    w, X, Z, model, ind, nbr, prior, y = _latent(case)
+    print(f"[gpu] large-m mode {case} {precond}", flush=True)
+    ref = _latent_mode(case)
+    ctx = _ctx(w, cg_tol=1e-12, cg_maxit=5000, newton_tol=1e-14)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    ctx.set_preconditioner(precond)
+    mode, st, _ = ctx.laplace_mode(to_dev(y))
+    err = np.max(np.abs(mode.cpu().numpy() - ref.mode)) / np.max(np.abs(ref.mode))
+    print(f"[gpu]   mode err {err:.3e} newton {st['newton_iters']} pcg {st['pcg_iters_total']}", flush=True)
+    assert err <= 1e-8, (err, st)
+    assert st["converged"]
+    assert abs(st["psi"] - ref.psi) <= 1e-9 * abs(ref.psi)
+
+
+@pytest.mark.parametrize("corruption", ["nan_weights", "wrong_sign"])
+def test_warm_start_fallback_with_a_corrupted_network(corruption):
+    """A corrupted warm start must not change the result: with NaN network
+    weights the start's objective is not finite; with an output of the wrong
+    sign and large magnitude (b0 = 20 (1 - 2y)) the first Newton step from it
+    ends far below the objective at zero. Either way the search restarts
+    from zero (start_used = 0) and reaches the zero start's mode."""
+    import torch
+    from paper_2507_05064_amd.vif import WarmStartMLP
+    w, X, Z, model, ind, nbr, prior, y = _latent("ard209")
+    print(f"[gpu] warm-start fallback, {corruption}", flush=True)
+    ctx = _ctx(w, cg_tol=1e-10, cg_maxit=5000, newton_tol=1e-12)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
+    yd = to_dev(y)
+    mode0, st0, _ = ctx.laplace_mode(yd)
+    if corruption == "nan_weights":
+        mlp = WarmStartMLP(H=128, seed=3)
+        mlp.params.fill_(float("nan"))
+        b0 = mlp.forward(ctx.mlp_features(yd), double=True)
+        assert not bool(torch.isfinite(b0).any())
+    else:
+        b0 = 20.0 * (1.0 - 2.0 * yd)
+    mode1, st1, _ = ctx.laplace_mode(yd, b0)
+    assert st1["start_used"] == 0 and st1["converged"], st1
+    err = float(torch.max(torch.abs(mode1 - mode0)) / torch.max(torch.abs(mode0)))
+    assert err <= 1e-12, err
+
+
+def test_laplace_nll_grad_matern12_large_m():
+    """Laplace NLL (SLQ) and gradient (STE with control variates) with the
+    Matern-1/2 kernel and m = 500 against the oracle's estimator on the same
+    probes (FP64: NLL 1e-8 relative, gradient 1e-6 of max|g|; FP32 factor:
+    1e-4 and 1e-2), which exercises the Matern-1/2 range derivative in the
+    factor tangents and the m x m tangents at m_p = 512."""
+    from paper_2507_05064_amd.vif import VifContext
+    n, m, mv, ell = 1500, 500, 20, 4
+    w = vi.Workload("lap-grad m12", 14, n, 2, m, mv, vo.MATERN12, 1.0, np.array([0.1]), 1e-4, 0.0,
+                    lo.POISSON_LOG, "kmeanspp")
+    X = vi.coords(w)
+    Z = vi.inducing_points(w, X)
+    model = vo.Model(vo.MATERN12, 1.0, np.array([0.1]), w.s2)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, mv)
+    prior = lo.LatentVIF.build(model, X, Z, nbr)
+    eps1, eps2, u = vi.prior_noise(w)
+    b = np.linalg.cholesky(lo.dense_cov(prior)) @ eps2
+    y = vi.poisson_from_uniform(np.exp(b), u)
+    mode = lo.find_mode(prior, lo.POISSON_LOG, y, tol=1e-14, solver="dense").mode
+    tg = vo.factor_tangents(model, X, Z, ind, nbr, prior.fac)
+    W = lo.grad_hess(lo.POISSON_LOG, y, mode)[1]
+    g = np.random.default_rng(n + 7)
+    e1, e2, e3 = g.standard_normal((n, ell)), g.standard_normal((n, ell)), g.standard_normal((m, ell))
+    Zp = lo.vifdu_probes(prior, W, e1, e2, e3)
+    slq = lo.laplace_nll_slq(prior, lo.POISSON_LOG, y, mode, Zp, tol=1e-11)
+    ref = lo.laplace_grad_ste(prior, tg, lo.POISSON_LOG, y, mode, slq, tol=1e-11)
+    eps_n = np.empty((2 * ell, n))
+    eps_n[0::2], eps_n[1::2] = e1.T, e2.T
+    for prec in ("fp64", "fp32"):
+        print(f"[gpu] laplace nll+grad matern12 m={m} {prec}", flush=True)
+        ctx = VifContext(n, 2, m, mv, kernel=vo.MATERN12, likelihood=lo.POISSON_LOG, precision=prec,
+                         cg_tol=1e-11, cg_maxit=3000, max_probes=ell)
+        ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), model.theta)
+        nll, grad = ctx.laplace_nll_grad(to_dev(y), to_dev(mode), to_dev(eps_n), to_dev(e3.T))
+        en = abs(nll - slq.nll) / abs(slq.nll)
+        eg = np.max(np.abs(grad - ref)) / np.max(np.abs(ref))
+        print(f"[gpu]   nll err {en:.3e} grad err {eg:.3e}", flush=True)
+        if prec == "fp64":
+            assert en <= 1e-8 and eg <= 1e-6, (en, eg, grad, ref)
+        else:
+            assert en <= 1e-4 and eg <= 1e-2, (en, eg, grad, ref)
+
+
+@pytest.mark.parametrize("kern,m", [(vo.MATERN32, 209), (vo.MATERN32, 257), (vo.MATERN32, 500), (vo.MATERN12, 500)])
+def test_gaussian_nll_grad_large_m(kern, m):
+    """Gaussian-likelihood NLL and adjoint gradient at m_p > 208 (blocked m x m
+    Cholesky of Sigma_m and M', large-m Gram and cross partial sums), FP64
+    against the oracle (1e-10, 1e-8 of max|g|) and FP32 (NLL 1e-5 relative,
+    gradient 1e-3 of max|g|), at a perturbed theta."""
+    n, mv = 3000, 20
+    w = vi.Workload(f"gauss large-m {kern} {m}", 15, n, 2, m, mv, kern, 1.0, np.array([0.05]), 0.05, 0.0,
+                    vi.GAUSSIAN, "subset")
+    X = vi.coords(w)
+    Z = vi.inducing_points(w, X)
+    model = vo.Model(kern, 1.0, np.array([0.05]), 0.05)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, mv)
+    y = np.random.default_rng(m).standard_normal(n)
+    theta = np.array([1.3, 0.04, 0.075])
+    pm = vo.Model.from_theta(kern, theta)
+    nll_o, g_o = vo.nll_gaussian_grad(pm, X, Z, nbr, y)
+    for prec in ("fp64", "fp32"):
+        print(f"[gpu] gaussian nll+grad {kern} m={m} {prec}", flush=True)
+        ctx = _ctx(w, precision=prec)
+        ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), theta)
+        nll_g, g_g = ctx.nll_grad(to_dev(y), 3)
+        en = abs(nll_g - nll_o) / abs(nll_o)
+        eg = np.max(np.abs(g_g - g_o)) / np.max(np.abs(g_o))
+        print(f"[gpu]   nll err {en:.3e} grad err {eg:.3e}", flush=True)
+        if prec == "fp64":
+            assert en <= 1e-10 and eg <= 1e-8, (en, eg)
+        else:
+            assert en <= 1e-5 and eg <= 1e-3, (en, eg)

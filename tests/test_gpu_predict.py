@@ -36,7 +36,7 @@ def test_predict_matches_oracle(n, npred, m, mv, prec):
     nbr_p = po.prediction_neighbours(model, X, Z, Xp, mv)
     ref = po.predictive_mean(model, X, Z, nbr, y, Xp, nbr_p)
     print(f"[gpu] predict n={n} n_p={npred} m={m} m_v={mv} {prec}", flush=True)
-    ctx = VifContext(n, 2, m, mv, kernel=model.kernel, precision=prec)
+    ctx = VifContext(n, 2, m, mv, kernel=model.kernel, precision=prec, max_pred=npred)
     ctx.build_factor(to_dev(X), to_dev(Z) if m else None, nbr_to_dev(nbr), model.theta)
     g = ctx.select_neighbors_pred(to_dev(Xp)).cpu().numpy()
     same = [set(g[j]) == set(nbr_p[j]) for j in range(npred)]
@@ -62,7 +62,7 @@ def test_predictive_variances_match_oracle(n, npred, m, mv, prec):
     ref_mu = po.predictive_mean(model, X, Z, nbr, y, Xp, nbr_p)
     ref = po.predictive_variance(model, X, Z, nbr, Xp, nbr_p)
     print(f"[gpu] predictive variances n={n} n_p={npred} m={m} m_v={mv} {prec}", flush=True)
-    ctx = VifContext(n, 2, m, mv, kernel=model.kernel, precision=prec)
+    ctx = VifContext(n, 2, m, mv, kernel=model.kernel, precision=prec, max_pred=npred)
     ctx.build_factor(to_dev(X), to_dev(Z) if m else None, nbr_to_dev(nbr), model.theta)
     mu, var = ctx.predict(to_dev(y), to_dev(Xp), nbr_to_dev(nbr_p), variances=True)
     mu, var = mu.cpu().numpy(), var.cpu().numpy()
@@ -78,7 +78,7 @@ def test_predict_rejects_variances_on_latent_context():
     from paper_2507_05064_amd.vif import VifContext, VifError
     import ctypes
     w, model, X, Xp, Z, nbr, y = _setup(300, 10, 10, 5, seed=1)
-    ctx = VifContext(300, 2, 10, 5, kernel=model.kernel, likelihood="bernoulli_logit")
+    ctx = VifContext(300, 2, 10, 5, kernel=model.kernel, likelihood="bernoulli_logit", max_pred=10)
     ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), model.theta)
     var = torch.empty(10, dtype=torch.float64, device="cuda")
     mu = torch.empty(10, dtype=torch.float64, device="cuda")
@@ -104,7 +104,7 @@ def test_laplace_predictive_mean_matches_oracle():
     ref = po.laplace_predictive_mean(model, X, Z, nbr, mode, Xp, nbr_p)
     print("[gpu] laplace predictive mean n=900 n_p=200", flush=True)
     ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=lo.BERNOULLI_LOGIT, precision="fp64",
-                     tau_m=w.tau_m)
+                     tau_m=w.tau_m, max_pred=200)
     ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), w.theta)
     om = ctx.predict(to_dev(mode), to_dev(Xp), nbr_to_dev(nbr_p)).cpu().numpy()
     assert np.max(np.abs(om - ref)) <= 1e-8 * np.max(np.abs(ref)), np.max(np.abs(om - ref))
@@ -133,7 +133,7 @@ def test_laplace_predictive_variances_match_oracle(prec, m):
     ref = po.laplace_predictive_variance_sbpv(model, X, Z, nbr, W, Xp, nbr_p, eps_n[0::2], eps_n[1::2], eps_m)
     print(f"[gpu] laplace predictive variances n=900 n_p=150 m={m} ell={ell} {prec}", flush=True)
     ctx = VifContext(w.n, w.d, m, w.m_v, kernel=w.kernel, likelihood=lo.BERNOULLI_LOGIT, precision=prec,
-                     tau_m=w.tau_m, cg_tol=1e-12)
+                     tau_m=w.tau_m, cg_tol=1e-12, max_pred=150)
     ctx.build_factor(to_dev(X), to_dev(Z) if m else None, nbr_to_dev(nbr), w.theta)
     mu, var, its = ctx.laplace_predict(to_dev(y), to_dev(mode), to_dev(Xp), nbr_to_dev(nbr_p), to_dev(eps_n),
                                        to_dev(eps_m) if m else None)
@@ -143,3 +143,41 @@ def test_laplace_predictive_variances_match_oracle(prec, m):
     assert np.max(np.abs(var - ref)) <= tol * np.max(ref), np.max(np.abs(var - ref)) / np.max(ref)
     mu2 = ctx.predict(to_dev(mode), to_dev(Xp), nbr_to_dev(nbr_p)).cpu().numpy()
     assert np.max(np.abs(mu - mu2)) <= 1e-12 * np.max(np.abs(mu2))
+
+
+@pytest.mark.parametrize("bad", ["out_of_range", "negative", "duplicate", "gap"])
+def test_invalid_prediction_neighbours_are_rejected(bad):
+    """A caller-supplied prediction list is checked before any gather: an
+    index >= n, a negative index other than -1, a repeated index or a -1
+    before the end of a row gives VIF_E_ARG naming the prediction point."""
+    from paper_2507_05064_amd.vif import VifContext, VifError
+    w, model, X, Xp, Z, nbr, y = _setup(400, 30, 12, 6, seed=9)
+    nbr_p = po.prediction_neighbours(model, X, Z, Xp, 6).astype(np.int32)
+    j = 17
+    if bad == "out_of_range":
+        nbr_p[j, 2] = 400
+    elif bad == "negative":
+        nbr_p[j, 2] = -7
+    elif bad == "duplicate":
+        nbr_p[j, 3] = nbr_p[j, 1]
+    else:
+        nbr_p[j, 1] = -1
+    ctx = VifContext(400, 2, 12, 6, kernel=model.kernel, max_pred=30)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), model.theta)
+    with pytest.raises(VifError) as e:
+        ctx.predict(to_dev(y), to_dev(Xp), nbr_to_dev(nbr_p), variances=True)
+    assert e.value.code == 1 and f"point {j}" in str(e.value)
+
+
+def test_prediction_beyond_max_pred_is_rejected():
+    """The prediction workspace is sized once, at creation, for max_pred
+    points: a call with more is VIF_E_ARG (and allocates nothing)."""
+    from paper_2507_05064_amd.vif import VifContext, VifError
+    w, model, X, Xp, Z, nbr, y = _setup(400, 30, 12, 6, seed=9)
+    ctx = VifContext(400, 2, 12, 6, kernel=model.kernel, max_pred=29)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), model.theta)
+    with pytest.raises(VifError) as e:
+        ctx.select_neighbors_pred(to_dev(Xp))
+    assert e.value.code == 1 and "max_pred" in str(e.value)
+    nbrp = ctx.select_neighbors_pred(to_dev(Xp[:29]))
+    assert nbrp.shape == (29, 6)

@@ -23,7 +23,7 @@ from oracle import vif_oracle as vo
 from tests import dense_ref as dr
 
 
-def _latent(n=120, m=10, mv=6, lik=lo.BERNOULLI_LOGIT, seed=0, theta=(1.0, 0.15, 1e-4)):
+def _latent(n=120, m=10, mv=6, lik=lo.BERNOULLI_LOGIT, seed=0, theta=(1.0, 0.15, 1e-4), shape=1.0):
     w = vi.Workload("slq", 12, n, 2, m, mv, vo.MATERN32, theta[0], np.array([theta[1]]), theta[2], 0.0, lik,
                     "subset")
     X = vi.coords(w, seed)
@@ -38,10 +38,10 @@ def _latent(n=120, m=10, mv=6, lik=lo.BERNOULLI_LOGIT, seed=0, theta=(1.0, 0.15,
     if lik == lo.BERNOULLI_LOGIT:
         y = vi.bernoulli_from_uniform(expit(b), u)
     elif lik == lo.GAMMA_LOG:
-        y = vi.gamma_from_uniform(np.exp(b), 1.0, u)
+        y = vi.gamma_from_uniform(np.exp(b), shape, u)
     else:
         y = vi.poisson_from_uniform(np.exp(b), u)
-    mode = lo.find_mode(prior, lik, y, tol=1e-14, solver="dense").mode
+    mode = lo.find_mode(prior, lik, y, noise_var=shape, tol=1e-14, solver="dense").mode
     return model, X, Z, nbr, prior, y, mode
 
 

@@ -129,3 +129,17 @@ def test_pins_detect_planted_mistakes(monkeypatch, mistake):
     worst = max(float(np.max(np.abs(vo.neighbour_keys(model, X, ind, i, np.arange(i)) - K[i, :i])))
                 for i in range(1, X.shape[0]))
     assert worst > 1e-6, worst
+
+
+@pytest.mark.parametrize("kernel,ls,s2,m,tau_m", CASES[:2] + CASES[4:5])
+def test_block_keys_equal_dense_keys(kernel, ls, s2, m, tau_m):
+    """The keys of several queries formed at once (the block form used by
+    the neighbour selection and the sampled-query checks) against the dense
+    residual correlation."""
+    model, X, Z = _problem(kernel, ls, s2, m, tau_m=tau_m)
+    ind = vo.inducing(model, X, Z)
+    K = _dense_keys(model, X, Z)
+    qs = np.array([149, 17, 80, 5, 120])
+    Kb = vo.neighbour_keys_rows(model, X, ind, qs, 150)
+    for r, i in enumerate(qs):  # candidates are the earlier points j < i
+        assert np.max(np.abs(Kb[r, :i] - K[i, :i])) <= 1e-11

@@ -244,3 +244,18 @@ def test_bf16_rounded_features_stay_within_the_form_bar():
     assert e16 <= 3e-3 * bar
     assert e32 <= 1e-5 * bar
     assert e16 > 10 * e32
+
+
+def test_prior_sample_has_the_vif_covariance():
+    """The prior draw is a linear map of (eps1, eps2); its covariance, from
+    the map applied to identity columns, equals the dense VIF covariance
+    Sigma^l + B^{-1} D B^{-T} (Sec. 2.1)."""
+    model, X, Z, y = _small_problem(n=70, m=6)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, 5)
+    fac = vo.vecchia_factor(model, X, ind, nbr)
+    n, m = 70, 6
+    F1 = np.column_stack([vo.prior_sample(nbr, fac, ind, e, np.zeros(n)) for e in np.eye(m)])
+    F2 = np.column_stack([vo.prior_sample(nbr, fac, ind, np.zeros(m), e) for e in np.eye(n)])
+    C = F1 @ F1.T + F2 @ F2.T
+    np.testing.assert_allclose(C, dr.vif_cov(model, X, Z, nbr, fac.A, fac.D), atol=1e-12)

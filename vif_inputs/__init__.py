@@ -13,7 +13,7 @@ variance 1) at the sizes of the five benchmark configurations.
 
 Seeds: ``numpy.random.default_rng(SeedSequence([250705064, config, stream]))``
 with streams 0 coordinates, 1 inducing points, 2 ordering, 3 response / latent
-noise, 4 probes, 5 MLP initialisation and minibatches.
+noise, 4 probes, 5 MLP initialisation and minibatches, 6 sampled query points.
 """
 from __future__ import annotations
 
@@ -32,7 +32,7 @@ GAUSSIAN = "gaussian"
 BERNOULLI_LOGIT = "bernoulli_logit"
 POISSON_LOG = "poisson_log"
 
-STREAM_COORDS, STREAM_INDUCING, STREAM_ORDER, STREAM_NOISE, STREAM_PROBES, STREAM_MLP = range(6)
+STREAM_COORDS, STREAM_INDUCING, STREAM_ORDER, STREAM_NOISE, STREAM_PROBES, STREAM_MLP, STREAM_QUERIES = range(7)
 
 
 def rng(config: int, stream: int, extra: int = 0) -> np.random.Generator:
@@ -165,6 +165,16 @@ def kmeanspp(T: np.ndarray, m: int, g: np.random.Generator, lloyd_iters: int = 1
         nz = counts > 0
         centers[nz] = sums[nz] / counts[nz, None]
     return centers
+
+
+def query_sample(w: Workload, count: int, problem: int = 0) -> np.ndarray:
+    """Sorted distinct point indices in [m_v + 1, n) (points that choose among
+    more earlier points than they keep), drawn uniformly, plus the last
+    point; for checking conditioning sets of a large workload point by point."""
+    g = rng(w.config, STREAM_QUERIES, problem)
+    lo = min(w.m_v + 1, w.n - 1)
+    q = g.choice(np.arange(lo, w.n - 1), size=min(count, w.n - 1 - lo), replace=False)
+    return np.unique(np.append(q, w.n - 1))
 
 
 def normals(w: Workload, count: int, stream: int = STREAM_NOISE, problem: int = 0) -> np.ndarray:
