@@ -232,6 +232,20 @@ int64_t vif_mlp_workspace_floats(int64_t n, int32_t F, int32_t H);
  * X is n x F row-major. */
 vif_status vif_mlp_forward(const float* params, const float* X, int64_t n, int32_t F, int32_t H, float* ws,
                            float* out, double* out64, void* stream);
+/* vif_mlp_forward without a workspace argument and without any device
+ * allocation, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The hidden
+ * layers go to a fixed 24 MiB array in the library's device memory, one per
+ * GPU, held until the process ends; any n is processed in chunks of
+ * floor(6 Mi / (3 H)) rows rounded down to 64 (16384 rows at H = 128).
+ * Limits as for vif_mlp_forward (1 <= F <= 64, 16 <= H <= 512, n >= 1; at
+ * least one of out, out64 non-NULL), else VIF_E_ARG; VIF_E_HIP if the
+ * array's device address cannot be obtained. The stream's device must be the
+ * current device. Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams or host threads) race and give
+ * wrong results. The outputs equal vif_mlp_forward's bit for bit. */
+vif_status vif_mlp_forward_noalloc(const float* params, const float* X, int64_t n, int32_t F, int32_t H, float* out,
+                                   double* out64, void* stream);
 /* grad (P floats) = d/dparams of mean_i (network(X)_i - target_i)^2;
  * loss_out (host, may be NULL) = that mean (synchronises the stream). */
 vif_status vif_mlp_backward(const float* params, const float* X, const float* target, int64_t n, int32_t F,

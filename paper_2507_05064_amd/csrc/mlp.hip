@@ -6,6 +6,7 @@
 // Flat parameter layout: W1 (F x H), b1 (H), W2 (H x H), b2, W3 (H x H), b3,
 // w4 (H), b4 (1), row-major (input index first).
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/vif.h"
 #include "common.h"
@@ -315,6 +316,44 @@ static void wgrad(hipStream_t st, const float* A, const float* G, int64_t n, int
 
 static bool mlp_args_ok(int64_t n, int F, int H) { return n >= 1 && F >= 1 && F <= 64 && H >= 16 && H <= 512; }
 
+// The network on n rows with the hidden layers h1, h2, h3 (n x H each) in ws.
+static void forward_rows(hipStream_t st, const float* params, const float* X, int64_t n, int F, int H, float* ws,
+                         float* out, double* out64) {
+  const MlpLayout L = layout(F, H);
+  float* h1 = ws;
+  float* h2 = h1 + n * H;
+  float* h3 = h2 + n * H;
+  gemm(st, X, params + L.W1, params + L.b1, nullptr, n, F, H, false, true, h1);
+  gemm(st, h1, params + L.W2, params + L.b2, nullptr, n, H, H, false, true, h2);
+  gemm(st, h2, params + L.W3, params + L.b3, nullptr, n, H, H, false, true, h3);
+  hipLaunchKernelGGL(k_mlp_out, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, h3, params + L.w4, params + L.b4, n,
+                     H, out, out64);
+}
+
+// Workspace of vif_mlp_forward_noalloc: one array per device, in the code
+// object's device memory (no allocation call), held until the process ends.
+// Host code never passes the array's name to a kernel: it stands for a host
+// address there. The device address comes from hipGetSymbolAddress, taken
+// once per device with that device current and kept in scratch_addr.
+static constexpr int64_t kScratchFloats = 6 * 1024 * 1024;  // 24 MiB
+static __device__ __align__(256) float scratch[kScratchFloats];
+static constexpr int kMaxDevices = 64;
+static float* scratch_addr[kMaxDevices];
+static std::mutex scratch_mu;
+
+static vif_status scratch_on_current_device(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return VIF_E_HIP;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return VIF_E_HIP;
+    scratch_addr[dev] = (float*)p;
+  }
+  *out = scratch_addr[dev];
+  return VIF_OK;
+}
+
 extern "C" {
 
 int64_t vif_mlp_num_params(int32_t F, int32_t H) { return layout(F, H).P; }
@@ -330,16 +369,23 @@ int64_t vif_mlp_workspace_floats(int64_t n, int32_t F, int32_t H) {
 vif_status vif_mlp_forward(const float* params, const float* X, int64_t n, int32_t F, int32_t H, float* ws,
                            float* out, double* out64, void* stream) {
   if (!params || !X || !ws || !mlp_args_ok(n, F, H)) return VIF_E_ARG;
+  forward_rows((hipStream_t)stream, params, X, n, F, H, ws, out, out64);
+  return hipGetLastError() == hipSuccess ? VIF_OK : VIF_E_HIP;
+}
+
+vif_status vif_mlp_forward_noalloc(const float* params, const float* X, int64_t n, int32_t F, int32_t H, float* out,
+                                   double* out64, void* stream) {
+  if (!params || !X || (!out && !out64) || !mlp_args_ok(n, F, H)) return VIF_E_ARG;
+  float* ws = nullptr;
+  const vif_status s = scratch_on_current_device(&ws);
+  if (s) return s;
+  // the three hidden layers of a chunk of rows fill at most the scratch array
+  const int64_t rows = kScratchFloats / (3 * (int64_t)H) / 64 * 64;
   hipStream_t st = (hipStream_t)stream;
-  const MlpLayout L = layout(F, H);
-  float* h1 = ws;
-  float* h2 = h1 + n * H;
-  float* h3 = h2 + n * H;
-  gemm(st, X, params + L.W1, params + L.b1, nullptr, n, F, H, false, true, h1);
-  gemm(st, h1, params + L.W2, params + L.b2, nullptr, n, H, H, false, true, h2);
-  gemm(st, h2, params + L.W3, params + L.b3, nullptr, n, H, H, false, true, h3);
-  hipLaunchKernelGGL(k_mlp_out, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, h3, params + L.w4, params + L.b4, n,
-                     H, out, out64);
+  for (int64_t r0 = 0; r0 < n; r0 += rows) {
+    const int64_t cnt = std::min(rows, n - r0);
+    forward_rows(st, params, X + r0 * F, cnt, F, H, ws, out ? out + r0 : nullptr, out64 ? out64 + r0 : nullptr);
+  }
   return hipGetLastError() == hipSuccess ? VIF_OK : VIF_E_HIP;
 }
 

@@ -71,7 +71,7 @@ EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors"
            "vif_mlp_forward", "vif_mlp_backward", "vif_mlp_adam", "vif_mlp_features", "vif_sample_prior",
            "vif_precond_solve", "vif_set_preconditioner", "vif_batch_create", "vif_batch_destroy", "vif_batch_last_error",
            "vif_batch_nll_grad", "vif_laplace_nll", "vif_laplace_nll_grad", "vif_select_neighbors_pred",
-           "vif_predict", "vif_laplace_predict"]
+           "vif_predict", "vif_laplace_predict", "vif_mlp_forward_noalloc"]
 
 
 def load_library(path: Optional[str] = None):
@@ -140,6 +140,8 @@ def load_library(path: Optional[str] = None):
     lib.vif_mlp_workspace_floats.restype = ctypes.c_int64
     lib.vif_mlp_forward.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
     lib.vif_mlp_forward.restype = ctypes.c_int
+    lib.vif_mlp_forward_noalloc.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+    lib.vif_mlp_forward_noalloc.restype = ctypes.c_int
     lib.vif_mlp_backward.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp, vp, dp, vp]
     lib.vif_mlp_backward.restype = ctypes.c_int
     lib.vif_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -445,6 +447,17 @@ class WarmStartMLP:
         _mlp_call(self.lib.vif_mlp_forward(_ptr(self.params), _ptr(X), n, self.F, self.H, _ptr(self._workspace(n)),
                                            None if double else _ptr(out), _ptr(out) if double else None, st),
                   "vif_mlp_forward")
+        return out
+
+    def forward_noalloc(self, X: torch.Tensor, double: bool = False) -> torch.Tensor:
+        """As forward, through vif_mlp_forward_noalloc (no workspace: the
+        library's fixed per-device array holds the hidden layers)."""
+        n = X.shape[0]
+        out = torch.empty(n, dtype=torch.float64 if double else torch.float32, device=X.device)
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        _mlp_call(self.lib.vif_mlp_forward_noalloc(_ptr(self.params), _ptr(X), n, self.F, self.H,
+                                                   None if double else _ptr(out), _ptr(out) if double else None, st),
+                  "vif_mlp_forward_noalloc")
         return out
 
     def loss_grad(self, X: torch.Tensor, target: torch.Tensor):
