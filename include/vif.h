@@ -144,6 +144,24 @@ const char* vif_last_error(const vif_ctx* ctx);
 vif_status vif_select_neighbors(vif_ctx* ctx, const double* X, const double* Z,
                                 const double* theta, int32_t* nbr_out);
 
+/* Inducing points by k-means++ (Sec. 6: kMeans++ on the transformed inputs
+ * q(s) = s / lambda, eq. cov_trans_iso, so that dimensions with long length
+ * scales count less). Without Z_init: D^2 seeding -- the first centre is the
+ * point with index floor(unif[0] n), centre c the first point (in index
+ * order) whose running sum of squared transformed distances to the nearest
+ * chosen centre exceeds unif[c] times their total -- then lloyd_iters Lloyd
+ * iterations (every point to its nearest centre, the smaller index on a tie;
+ * each centre to the mean of its points, a centre without points stays).
+ * With Z_init (device, m x d, e.g. the previous optimisation iteration's
+ * inducing points, as the paper suggests) only the Lloyd iterations run,
+ * from Z_init. X: device n x d; theta: host, its length scales are used
+ * (one range for the isotropic kernels); unif: HOST array of m uniforms in
+ * [0, 1) (ignored with Z_init); Z_out: device m x d (original coordinates);
+ * seed_idx_out: host m int32 (may be NULL), the seeded points' indices.
+ * Sums run in a fixed order: a repeated call gives the same points. m > 0. */
+vif_status vif_select_inducing(vif_ctx* ctx, const double* X, const double* theta, const double* unif,
+                               const double* Z_init, int32_t lloyd_iters, double* Z_out, int32_t* seed_idx_out);
+
 /* Builds Sigma_m, L_m, V and the residual factor (A_i, D_i) of
  * eq. D_A_Vecchia for every point, plus U = D^{-1/2} B V^T and the Woodbury
  * matrix M' = I + U^T U, whose congruence L_m M' L_m^T is M of eq. def_M.
@@ -158,9 +176,12 @@ vif_status vif_build_factor(vif_ctx* ctx, const double* X, const double* Z,
  *   yt = D^{-1/2} B y, s = L_{M'}^{-1} U^T yt.  nll_out: host double. */
 vif_status vif_nll(vif_ctx* ctx, const double* y, double* nll_out);
 
-/* NLL and its gradient w.r.t. theta (Sec. 2.2, App. A) by a hand-written
- * reverse-mode adjoint of the factor build; the per-point factors are
- * recomputed, not stored. Requires the likelihood to be Gaussian.
+/* NLL and its gradient w.r.t. theta (Sec. 2.2, App. A). Isotropic kernels:
+ * a hand-written reverse-mode adjoint of the factor build (the per-point
+ * factors are recomputed, not stored). ARD kernel (theta with d length
+ * scales, eq. cov_trans_iso): forward-mode tangents of eq. D_A_Vecchia, one
+ * parameter at a time (FP64 and FP32 forms; VIF_E_ARG in the BF16-input
+ * form). Requires the likelihood to be Gaussian.
  * grad_out: host double[1 + L + 1] in the layout of theta. */
 vif_status vif_nll_grad(vif_ctx* ctx, const double* y, double* nll_out, double* grad_out);
 
@@ -288,8 +309,8 @@ vif_status vif_laplace_nll(vif_ctx* ctx, const double* y, const double* mode, in
                            const double* eps_m, double* nll_out, double* logdet_out);
 
 /* The Laplace NLL as vif_laplace_nll plus its gradient (App. B) with
- * respect to theta = (sigma1^2, range, s2) (isotropic kernels; s2 = the
- * latent jitter):
+ * respect to theta = (sigma1^2, lambda_1..lambda_L, s2) (L = d for the ARD
+ * kernel, else the range; s2 = the latent jitter):
  *   dL/dtheta_p = 1/2 b^T dSigma^{-1} b + 1/2 [d log det Sigma_dagger + tr(A^{-1} dSigma^{-1})]
  *                 - v^T dSigma^{-1} b,   v = A^{-1} dL/db,
  *   dL/db_i = 1/2 (A^{-1})_ii dW_ii/db_i (the dependence of the mode on theta).
@@ -299,8 +320,11 @@ vif_status vif_laplace_nll(vif_ctx* ctx, const double* y, const double* mode, in
  * control-variate coefficient and tr(P^{-1} dP) exact (VIFDU log-det
  * identity); the diagonal (A^{-1})_ii dW_i likewise with one pooled
  * coefficient. Derivatives of the factor are taken in forward mode (eq.
- * D_A_Vecchia differentiated) for each parameter. grad_out: host, 3
- * doubles. 2 <= ell <= cfg.max_probes. */
+ * D_A_Vecchia differentiated) for each parameter. grad_out: host, L + 2
+ * doubles in the layout of theta. 2 <= ell <= cfg.max_probes. The probe
+ * solves run as one block of conjugate-gradient iterations per 64 probes
+ * (each operator pass made once for the block, each probe with its own
+ * coefficients and stopping rule). */
 vif_status vif_laplace_nll_grad(vif_ctx* ctx, const double* y, const double* mode, int32_t ell, const double* eps_n,
                                 const double* eps_m, double* nll_out, double* grad_out);
 

@@ -16,6 +16,8 @@
 
 enum Stage { ST_INDUCING = 0, ST_WHITEN, ST_FACTOR, ST_GRAM, ST_MCHOL, ST_NLL, ST_KNN, ST_GPREP, ST_UBAR,
              ST_FBWD, ST_VBAR, ST_SGRAD, ST_WDERIV, ST_REV, ST_LAPLACE, ST_COUNT };
+static constexpr int kBlkVecs = 16;  // n x L vectors of the many-right-hand-side workspace
+
 static const char* kStageNames[ST_COUNT] = {
     "inducing_chol", "whiten", "factor", "woodbury_gram", "woodbury_chol", "nll_tail", "knn", "grad_prep",
     "grad_ubar_gemm", "grad_factor_bwd", "grad_vbar", "grad_sigma_m", "grad_whiten_deriv", "reverse_lists",
@@ -103,12 +105,25 @@ struct vif_ctx {
   // Laplace-gradient workspace (first gradient call): tangents per parameter
   // and per-point work vectors
   bool lg_ready = false;
-  void *lg_Ut = nullptr, *lg_Ut3 = nullptr, *lg_dV = nullptr, *lg_dU[3] = {nullptr, nullptr, nullptr};
-  void *lg_dA[3] = {nullptr, nullptr, nullptr}, *lg_MT = nullptr, *lg_M3T = nullptr, *lg_PhiT = nullptr;
-  double *lg_dD[3] = {nullptr, nullptr, nullptr}, *lg_mm = nullptr, *lg_vec = nullptr, *lg_part = nullptr;
+  void *lg_Ut = nullptr, *lg_Ut3 = nullptr, *lg_dV = nullptr, *lg_dU[VIF_MAX_D + 2] = {};
+  void *lg_dA[VIF_MAX_D + 2] = {}, *lg_MT = nullptr, *lg_M3T = nullptr, *lg_PhiT = nullptr;
+  double *lg_dD[VIF_MAX_D + 2] = {}, *lg_mm = nullptr, *lg_vec = nullptr, *lg_part = nullptr;
   double* lg_slots = nullptr;
   int lg_slot_cap = 0;
-  // prediction workspace (grown on demand)
+  // many-right-hand-side workspace of the probe solves (sized with the probe
+  // workspace): kBlkVecs vectors of n x blk_cap, three mp x blk_cap blocks,
+  // partial sums and per-column CG scalars
+  // k-means++ inducing-point selection
+  double *km_dist = nullptr, *km_bsum = nullptr, *km_C = nullptr, *km_part = nullptr;
+  int *km_idx = nullptr, *km_assign = nullptr;
+  // forward-mode Gaussian gradient (ARD kernel): one parameter's tangents
+  void* fd_dA = nullptr;
+  double *fd_dD = nullptr, *fd_mm = nullptr;
+  void* fd_PhiT = nullptr;
+  int blk_cap = 0;
+  double *blk = nullptr, *blk_mm = nullptr, *blk_part = nullptr, *blk_cs = nullptr;
+  int* blk_int = nullptr;
+  // prediction workspace
   int64_t pred_cap = 0;
   void *pred_Vp = nullptr, *pred_Ap = nullptr, *pred_u = nullptr, *pred_Lt = nullptr;
   double *pred_Vpd = nullptr, *pred_vn = nullptr, *pred_Dp = nullptr, *pred_z8 = nullptr;
@@ -187,6 +202,7 @@ static vif_status set_params(vif_ctx* c, const double* theta) {
   p.sigma1_sq = theta[0];
   p.s2 = theta[L + 1];
   for (int k = 0; k < VIF_MAX_D; ++k) p.inv_ls[k] = (k < g.d) ? 1.0 / theta[1 + (L == 1 ? 0 : k)] : 0.0;
+  p.dparam = -1;
   c->cp = p;
   return VIF_OK;
 }
@@ -304,7 +320,8 @@ static vif_status check_pred_nbr(vif_ctx* c, const int32_t* nbrp, int64_t np_, c
 static vif_status alloc_slq(vif_ctx* c, int ell);
 static vif_status alloc_lapgrad(vif_ctx* c, int nslot);
 static vif_status alloc_pred(vif_ctx* c, int64_t np_);
-static int lapgrad_slots(int ell);
+static int lapgrad_slots(int ell, int P);
+static int n_params(const vif_config& g);
 
 extern "C" {
 
@@ -357,12 +374,20 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   alloc((void**)&c->partial, sizeof(double) * (size_t)c->nchunk * mpa * mpa);
   alloc((void**)&c->vecpart, sizeof(double) * (size_t)c->nchunk * (mpa + 2));
   alloc((void**)&c->vec, sizeof(double) * (mpa + 2));
-  alloc((void**)&c->scal, sizeof(double) * 16);
+  alloc((void**)&c->scal, sizeof(double) * 32);
   alloc((void**)&c->status, sizeof(int) * 8);
   alloc((void**)&c->nbr, sizeof(int32_t) * n * (g.m_v > 0 ? g.m_v : 1));
   alloc((void**)&c->vorder, sizeof(int) * n);
   alloc((void**)&c->Xc, sizeof(double) * n * g.d);
   alloc((void**)&c->Zc, sizeof(double) * (g.m > 0 ? g.m : 1) * g.d);
+  if (g.m > 0) {
+    alloc((void**)&c->km_dist, sizeof(double) * n);
+    alloc((void**)&c->km_bsum, sizeof(double) * kmeans_blocks(n));
+    alloc((void**)&c->km_C, sizeof(double) * g.m * g.d);
+    alloc((void**)&c->km_part, sizeof(double) * kmeans_chunks(n) * g.m * (g.d + 1));
+    alloc((void**)&c->km_idx, sizeof(int) * g.m);
+    alloc((void**)&c->km_assign, sizeof(int) * n);
+  }
   if (g.likelihood == VIF_LIK_GAUSSIAN) {
     const size_t mvn = (size_t)n * (g.m_v > 0 ? g.m_v : 1);
     alloc((void**)&c->Smat, sizeof(double) * mpa * mpa);
@@ -379,6 +404,12 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
     alloc((void**)&c->tpart, sizeof(double) * n * 3);
     alloc((void**)&c->rowpart, sizeof(double) * mpa * 2);
     alloc((void**)&c->gred, sizeof(double) * (ceil_div(n, 4096) * 3 + ceil_div(mpa, 4096) * 2 + 16));
+    if (g.kernel == VIF_GAUSSIAN_ARD) {
+      alloc(&c->fd_dA, tsize(c) * mvn);
+      alloc((void**)&c->fd_dD, sizeof(double) * n);
+      alloc((void**)&c->fd_mm, sizeof(double) * 2 * mpa * mpa);
+      alloc(&c->fd_PhiT, tsize(c) * mpa * mpa);
+    }
   }
   {
     const size_t mvn = (size_t)n * (g.m_v > 0 ? g.m_v : 1);
@@ -417,7 +448,7 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_lm, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_vr, hipEventDisableTiming);
   }
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->hscal, sizeof(double) * 16, 0);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->hscal, sizeof(double) * 32, 0);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->hstatus, sizeof(int) * 8, 0);
   if (e != hipSuccess) {
     vif_destroy(c);
@@ -427,7 +458,7 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   vif_status ws = VIF_OK;
   if (g.max_probes > 0) {
     ws = alloc_slq(c, g.max_probes);
-    if (!ws) ws = alloc_lapgrad(c, lapgrad_slots(g.max_probes));
+    if (!ws) ws = alloc_lapgrad(c, lapgrad_slots(g.max_probes, n_params(g)));
   }
   if (!ws && g.max_pred > 0) ws = alloc_pred(c, g.max_pred);
   if (ws) {
@@ -448,12 +479,19 @@ void vif_destroy(vif_ctx* c) {
                   c->rowpart, c->gred, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx,
                   c->fwd_order, c->fwd_lvl, c->bwd_order, c->bwd_lvl, c->lv, c->lm, c->M3, c->M3inv, c->L3inv,
                   c->lsc, c->lpart, c->fcol, c->bptr, c->bcol, c->bsrc, c->fsrc, c->fsplit, c->bsplit, c->fcoef, c->bcoef, c->slq_a, c->slq_b, c->slq_rz, c->slq_terms, c->slq_work, c->slq_u,
-                  c->slq_q, c->slq_iters, c->lg_Ut, c->lg_Ut3, c->lg_dV, c->lg_dU[0], c->lg_dU[1], c->lg_dU[2],
-                  c->lg_dA[0], c->lg_dA[1], c->lg_dA[2], c->lg_MT, c->lg_M3T, c->lg_PhiT, c->lg_dD[0],
-                  c->lg_dD[1], c->lg_dD[2], c->lg_mm, c->lg_vec, c->lg_part, c->lg_slots, c->pred_Vp,
-                  c->pred_Ap, c->pred_u, c->pred_Lt, c->pred_Vpd, c->pred_vn, c->pred_Dp, c->pred_z8, c->vorder};
+                  c->slq_q, c->slq_iters, c->lg_Ut, c->lg_Ut3, c->lg_dV, c->lg_MT, c->lg_M3T, c->lg_PhiT, c->lg_mm, c->lg_vec, c->lg_part, c->lg_slots, c->pred_Vp,
+                  c->pred_Ap, c->pred_u, c->pred_Lt, c->pred_Vpd, c->pred_vn, c->pred_Dp, c->pred_z8, c->vorder,
+                  c->blk, c->blk_mm, c->blk_part, c->blk_cs, c->blk_int};
   for (void* b : bufs)
     if (b) hipFree(b);
+  for (int k = 0; k < VIF_MAX_D + 2; ++k) {
+    if (c->lg_dU[k]) hipFree(c->lg_dU[k]);
+    if (c->lg_dA[k]) hipFree(c->lg_dA[k]);
+    if (c->lg_dD[k]) hipFree(c->lg_dD[k]);
+  }
+  for (void* q : {c->fd_dA, (void*)c->fd_dD, (void*)c->fd_mm, c->fd_PhiT, (void*)c->km_dist, (void*)c->km_bsum,
+                  (void*)c->km_C, (void*)c->km_part, (void*)c->km_idx, (void*)c->km_assign})
+    if (q) hipFree(q);
   for (int t = 0; t < ST_COUNT; ++t) {
     if (c->timers[t].b) hipEventDestroy(c->timers[t].b);
     if (c->timers[t].e) hipEventDestroy(c->timers[t].e);
@@ -783,6 +821,40 @@ static vif_status nll_grad_impl(vif_ctx* c, const double* y) {
   return VIF_OK;
 }
 
+template <typename T>
+static void factor_tangent(vif_ctx* c, int p, T* dVbuf, double* mm, T* PhiT, T* dA, double* dD, T* dU);
+static int n_params(const vif_config& g);
+__global__ void k_sum_part(const double* part, int nb, double* out);
+
+// NLL and its gradient by forward-mode tangents, one parameter at a time
+// (the ARD kernel: d + 2 parameters): per parameter the factor tangents of
+// eq. D_A_Vecchia (factor_tangent) and the per-point terms of the NLL's
+// derivative (k_gauss_fwd_terms). Gradient entries go to scal[8 + p].
+template <typename T>
+static vif_status nll_grad_fwd_impl(vif_ctx* c, const double* y) {
+  const vif_config& g = c->cfg;
+  const int mp = c->mp;
+  const T* U = (const T*)c->U;
+  stage_begin(c, ST_NLL);
+  nll_tail(c, y);
+  stage_end(c, ST_NLL);
+  if (g.m > 0) {
+    launch_gemm_sq(c->st, c->LMinv, c->LMinv, c->Minv, mp, true, false);
+    launch_prep_w<T>(c->st, c->Minv, c->vec, mp, c->wvec, (T*)c->MinvT);
+    launch_rowmm<T>(c->st, U, (const T*)c->MinvT, nullptr, 1.0, 0.0, g.n, mp, (T*)c->Q1);  // U M'^{-1}
+  }
+  launch_resid<T>(c->st, U, c->wvec, c->yt, g.n, mp, c->e);
+  for (int p = 0; p < n_params(g); ++p) {
+    factor_tangent<T>(c, p, (T*)c->Gs, c->fd_mm, (T*)c->fd_PhiT, (T*)c->fd_dA, c->fd_dD, (T*)c->Bs);
+    const int nb = launch_gauss_fwd_terms<T>(c->st, (const T*)c->Q1, (const T*)c->Bs, c->wvec, c->e,
+                                             (const T*)c->fd_dA, c->nbr, y, c->D, c->yt, c->fd_dD, g.n, mp, g.m_v,
+                                             c->tpart);
+    hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, c->tpart, nb, c->scal + 8 + p);
+  }
+  HIPCHK(c, hipGetLastError());
+  return VIF_OK;
+}
+
 extern "C" {
 
 vif_status vif_nll_grad(vif_ctx* c, const double* y, double* nll_out, double* grad_out) {
@@ -791,23 +863,28 @@ vif_status vif_nll_grad(vif_ctx* c, const double* y, double* nll_out, double* gr
   if (!y || !nll_out || !grad_out) return fail(c, VIF_E_ARG, "NULL y, nll_out or grad_out");
   const vif_config& g = c->cfg;
   if (g.likelihood != VIF_LIK_GAUSSIAN) return fail(c, VIF_E_ARG, "vif_nll_grad needs the Gaussian likelihood");
-  if (g.kernel == VIF_GAUSSIAN_ARD)
-    return fail(c, VIF_E_ARG, "vif_nll_grad supports the isotropic kernels (one length scale)");
+  const bool ard = g.kernel == VIF_GAUSSIAN_ARD;
+  if (ard && bf16_form(c))
+    return fail(c, VIF_E_ARG, "vif_nll_grad with the ARD kernel is provided in the FP64 and FP32 forms");
   if (g.m_v > VIF_MAX_MV - 1) return fail(c, VIF_E_ARG, "vif_nll_grad supports m_v <= %d", VIF_MAX_MV - 1);
   vif_status s = reset_status(c);
   if (s) return s;
   c->grad_seen = true;
-  s = bf16_form(c)   ? nll_grad_impl<float, bf16s>(c, y)
-      : fp32_form(c) ? nll_grad_impl<float, float>(c, y)
-                     : nll_grad_impl<double, double>(c, y);
+  const int P = n_params(g);
+  if (ard)
+    s = fp32_form(c) ? nll_grad_fwd_impl<float>(c, y) : nll_grad_fwd_impl<double>(c, y);
+  else
+    s = bf16_form(c)   ? nll_grad_impl<float, bf16s>(c, y)
+        : fp32_form(c) ? nll_grad_impl<float, float>(c, y)
+                       : nll_grad_impl<double, double>(c, y);
   if (s) return s;
-  HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * 16, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * (8 + P), hipMemcpyDeviceToHost, c->st));
   s = read_status(c, "vif_nll_grad");
   if (s) return s;
   *nll_out = c->hscal[4];
-  for (int k = 0; k < 3; ++k) grad_out[k] = c->hscal[8 + k];
+  for (int k = 0; k < P; ++k) grad_out[k] = c->hscal[8 + k];
   if (!isfinite(*nll_out)) return fail(c, VIF_E_NAN, "NLL is not finite");
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < P; ++k)
     if (!isfinite(grad_out[k])) return fail(c, VIF_E_NAN, "gradient entry %d is not finite", k);
   return VIF_OK;
 }
@@ -1556,15 +1633,127 @@ static vif_status alloc_slq(vif_ctx* c, int ell) {
   alloc((void**)&c->slq_u, sizeof(double) * ell * n);
   alloc((void**)&c->slq_q, sizeof(double) * ell * n);
   alloc((void**)&c->slq_iters, sizeof(int) * ell);
+  const int L = std::min(ell, kBlockCols);
+  const size_t mpa = c->mp > 0 ? c->mp : 1;
+  const size_t npart = std::max((size_t)utx_chunks(n) * mpa, 2 * (size_t)ceil_div(n, 1024));
+  alloc((void**)&c->blk, sizeof(double) * kBlkVecs * n * L);
+  alloc((void**)&c->blk_mm, sizeof(double) * 3 * mpa * L);
+  alloc((void**)&c->blk_part, sizeof(double) * npart * L);
+  alloc((void**)&c->blk_cs, sizeof(double) * 11 * L);
+  alloc((void**)&c->blk_int, sizeof(int) * 4);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP;
   c->slq_ell = ell;
   c->slq_ld = ld;
+  c->blk_cap = L;
   return VIF_OK;
+}
+
+// Views of the many-right-hand-side workspace: blocks of up to cap vectors,
+// each n x cap (row-major, cap columns), used n x L for a block of L <= cap.
+struct BlkBufs {
+  int cap;
+  double *x, *r, *z, *p, *ap, *t, *s, *q, *qd, *q2, *xq, *zq, *rhs, *e1, *u, *w;
+  double *cm, *cm2, *cm3;  // mp x cap
+  double *part, *cs, *dots, *beta;
+  int *nact, *bad;
+};
+
+static BlkBufs blk_bufs(vif_ctx* c) {
+  BlkBufs K;
+  K.cap = c->blk_cap;
+  const size_t nl = (size_t)c->cfg.n * K.cap;
+  double** f[kBlkVecs] = {&K.x, &K.r, &K.z, &K.p, &K.ap, &K.t, &K.s, &K.q, &K.qd, &K.q2, &K.xq, &K.zq, &K.rhs, &K.e1,
+                          &K.u, &K.w};
+  for (int k = 0; k < kBlkVecs; ++k) *f[k] = c->blk + k * nl;
+  const size_t ml = (size_t)(c->mp > 0 ? c->mp : 1) * K.cap;
+  K.cm = c->blk_mm;
+  K.cm2 = c->blk_mm + ml;
+  K.cm3 = c->blk_mm + 2 * ml;
+  K.part = c->blk_part;
+  K.cs = c->blk_cs;
+  K.dots = c->blk_cs + 8 * K.cap;
+  K.beta = c->blk_cs + 10 * K.cap;
+  K.nact = c->blk_int;
+  K.bad = c->blk_int + 1;
+  return K;
 }
 
 static vif_status check_probes(vif_ctx* c, int ell, const char* fn) {
   if (ell > c->slq_ell)
     return fail(c, VIF_E_ARG, "%s: ell = %d probes exceeds the context's max_probes = %d", fn, ell, c->slq_ell);
+  return VIF_OK;
+}
+
+// out = Sigma_dagger^{-1} x (+ W x when W is given) for a block of L vectors:
+// the whitened Woodbury form B^T D^{-1/2} (t - U M'^{-1} U^T t), t = D^{-1/2} B x
+template <typename T>
+static void blk_prec_matvec(vif_ctx* c, BlkBufs& K, const double* x, int L, const double* W, double* out) {
+  const vif_config& g = c->cfg;
+  const T* U = (const T*)c->U;
+  launch_bw_multi<T>(c->st, (const T*)c->A, c->D, c->nbr, x, g.n, g.m_v, L, K.t);
+  if (g.m > 0) launch_utx<T>(c->st, U, K.t, g.n, c->mp, L, c->Minv, K.part, K.cm2, K.cm);
+  launch_rowmm_multi<T>(c->st, U, K.cm, K.t, nullptr, c->D, g.n, c->mp, L, 0, K.s);
+  launch_btw_multi<T>(c->st, (const T*)c->A, c->rev_ptr, c->rev_idx, K.s, W, x, g.n, g.m_v, L, out);
+}
+
+// z = P^{-1} r (VIFDU of the current E and M3') for a block of L vectors
+template <typename T>
+static void blk_vifdu_apply(vif_ctx* c, BlkBufs& K, LapBufs& B, const double* r, int L, double* z) {
+  const vif_config& g = c->cfg;
+  const T* U = (const T*)c->U;
+  launch_trsv_bwd_multi<T>(c->st, c->sb, (const T*)c->bcoef, r, L, K.xq, K.zq, K.w);
+  launch_scale_e_multi(c->st, K.w, B.E, c->D, g.n, L, K.q, K.qd);
+  if (g.m > 0) launch_utx<T>(c->st, U, K.qd, g.n, c->mp, L, c->M3inv, K.part, K.cm2, K.cm);
+  launch_rowmm_multi<T>(c->st, U, K.cm, K.q, B.E, c->D, g.n, c->mp, L, 1, K.q2);
+  launch_trsv_fwd_multi<T>(c->st, c->sf, (const T*)c->fcoef, K.q2, L, K.xq, K.zq, z);
+}
+
+// L independent preconditioned CG solves A x_l = rhs_l (A = W + Sigma_dagger^{-1},
+// VIFDU), from x = 0, each to its own rule ||r_l|| <= cg_tol ||rhs_l||, with
+// every operator pass made once for the block. Per column: alpha_j, beta_j
+// logged at alog / blog (column l at l * ld), the iteration count, rz0 =
+// rhs^T P^{-1} rhs, and q0 = P^{-1} rhs. All scalars stay on the device; the
+// host reads the number of unfinished columns every fourth iteration.
+template <typename T>
+static vif_status pcg_block(vif_ctx* c, LapBufs& B, BlkBufs& K, const double* rhs, int L, double* x, double* q0,
+                            double* alog, double* blog, int ld, double* rz0, int* iters) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  const size_t bytes = sizeof(double) * n * L;
+  HIPCHK(c, hipMemsetAsync(x, 0, bytes, c->st));
+  HIPCHK(c, hipMemsetAsync(K.bad, 0, sizeof(int), c->st));
+  HIPCHK(c, hipMemcpyAsync(K.r, rhs, bytes, hipMemcpyDeviceToDevice, c->st));
+  blk_vifdu_apply<T>(c, K, B, K.r, L, K.z);
+  if (q0) HIPCHK(c, hipMemcpyAsync(q0, K.z, bytes, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(K.p, K.z, bytes, hipMemcpyDeviceToDevice, c->st));
+  launch_coldot_multi(c->st, K.r, K.z, K.r, K.r, n, L, K.part, K.dots);
+  launch_cg_init_multi(c->st, K.cs, K.dots, g.cg_tol * g.cg_tol, L, rz0, K.nact);
+  int nact = 0;
+  HIPCHK(c, hipMemcpyAsync(&nact, K.nact, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  int it = 0;
+  for (it = 1; it <= g.cg_maxit && nact > 0; ++it) {
+    blk_prec_matvec<T>(c, K, K.p, L, B.W, K.ap);
+    launch_coldot_multi(c->st, K.p, K.ap, nullptr, nullptr, n, L, K.part, K.cs + L);  // pAp
+    launch_cg_step_multi(c->st, x, K.r, K.p, K.ap, K.cs, n, L);
+    blk_vifdu_apply<T>(c, K, B, K.r, L, K.z);
+    launch_coldot_multi(c->st, K.r, K.z, K.r, K.r, n, L, K.part, K.dots);
+    launch_cg_beta_multi(c->st, K.cs, K.dots, it, L, ld, alog, blog, K.beta, K.nact);
+    launch_cg_dir_multi(c->st, K.p, K.z, K.beta, n, L);
+    if (it % 4 == 0 || it == g.cg_maxit) {
+      HIPCHK(c, hipMemcpyAsync(&nact, K.nact, sizeof(int), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipStreamSynchronize(c->st));
+    }
+  }
+  launch_cg_iters_multi(c->st, K.cs, L, iters, K.bad);
+  int bad = 0;
+  HIPCHK(c, hipMemcpyAsync(&bad, K.bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  HIPCHK(c, hipGetLastError());
+  if (bad) return fail(c, VIF_E_NAN, "conjugate gradients (probe block): non-finite residual");
+  if (nact > 0)
+    return fail(c, VIF_E_CG_MAXIT, "conjugate gradients (probe block) did not reach %g in %d iterations", g.cg_tol,
+                g.cg_maxit);
   return VIF_OK;
 }
 
@@ -1653,27 +1842,35 @@ static vif_status laplace_nll_impl(vif_ctx* c, const double* y, const double* mo
   if ((s = read_scalars(c, 13))) return s;
   const double loglik = c->hlsc[9], bsb = c->hlsc[7], l1p = c->hlsc[10];
   const double ldM3 = g.m > 0 ? c->hlsc[12] : 0.0;
-  std::vector<int> its(ell);
-  std::vector<double> rz(ell);
   const T* U = (const T*)c->U;
-  for (int k = 0; k < ell; ++k) {
-    const double* e1 = eps_n + (size_t)(2 * k) * n;
-    const double* e2 = eps_n + (size_t)(2 * k + 1) * n;
-    prior_draw<T>(c, B, g.m > 0 ? eps_m + (size_t)k * g.m : nullptr, e2, B.tmp);
-    launch_bw<T>(c->st, (const T*)c->A, c->D, c->nbr, B.tmp, n, g.m_v, B.t);
+  const T* V = form_V<T>(c);
+  const T* A = (const T*)c->A;
+  BlkBufs K = blk_bufs(c);
+  for (int k0 = 0; k0 < ell; k0 += K.cap) {
+    const int L = std::min(K.cap, ell - k0);
+    // prior draws x = B^{-1} D^{1/2} e2 + V^T e3 for the block's probes
+    launch_cols_to_block(c->st, eps_n, 2 * n, n, k0, n, L, K.e1);
+    launch_sqrtd_multi(c->st, c->D, K.e1, n, L, K.t);
+    launch_trsv_fwd_multi<T>(c->st, c->sf, (const T*)c->fcoef, K.t, L, K.xq, K.zq, K.x);
     if (g.m > 0) {
-      launch_utv<T>(c->st, U, B.t, nullptr, n, mp, c->chunk, B.upart);
-      launch_reduce_apply(c->st, B.upart, c->nchunk, mp, c->Minv, B.cbuf, B.cp);
+      launch_eps_m_block(c->st, eps_m, g.m, mp, k0, L, K.cm3);
+      launch_rowmm_multi<T>(c->st, V, K.cm3, K.x, nullptr, nullptr, n, mp, L, 3, K.u);
+    } else {
+      HIPCHK(c, hipMemcpyAsync(K.u, K.x, sizeof(double) * n * L, hipMemcpyDeviceToDevice, c->st));
     }
-    launch_t_minus_uc<T>(c->st, U, B.cp, B.t, c->D, n, mp, B.s);
-    launch_add_sqrtw(c->st, B.s, B.W, e1, n);
-    launch_btw<T>(c->st, (const T*)c->A, c->rev_ptr, c->rev_idx, B.s, nullptr, nullptr, n, g.m_v, B.rhs);
-    s = pcg_plain<T>(c, B, B.rhs, c->slq_u + (size_t)k * n, c->slq_a + (size_t)k * c->slq_ld,
-                     c->slq_b + (size_t)k * c->slq_ld, c->slq_q + (size_t)k * n, &its[k], &rz[k]);
+    // z = B^T (D^{-1/2}(t - U M'^{-1} U^T t) + W^{1/2} e1), t = D^{-1/2} B x
+    launch_bw_multi<T>(c->st, A, c->D, c->nbr, K.u, n, g.m_v, L, K.t);
+    if (g.m > 0) launch_utx<T>(c->st, U, K.t, n, mp, L, c->Minv, K.part, K.cm2, K.cm);
+    launch_rowmm_multi<T>(c->st, U, K.cm, K.t, nullptr, c->D, n, mp, L, 0, K.s);
+    launch_cols_to_block(c->st, eps_n, 2 * n, 0, k0, n, L, K.e1);
+    launch_add_sqrtw_multi(c->st, K.s, B.W, K.e1, n, L);
+    launch_btw_multi<T>(c->st, A, c->rev_ptr, c->rev_idx, K.s, nullptr, nullptr, n, g.m_v, L, K.rhs);
+    s = pcg_block<T>(c, B, K, K.rhs, L, K.u, K.e1, c->slq_a + (size_t)k0 * c->slq_ld,
+                     c->slq_b + (size_t)k0 * c->slq_ld, c->slq_ld, c->slq_rz + k0, c->slq_iters + k0);
     if (s) return s;
+    launch_block_to_cols(c->st, K.u, n, L, k0, c->slq_u);  // u_k = A^{-1} z_k
+    launch_block_to_cols(c->st, K.e1, n, L, k0, c->slq_q);  // q_k = P^{-1} z_k
   }
-  HIPCHK(c, hipMemcpyAsync(c->slq_iters, its.data(), sizeof(int) * ell, hipMemcpyHostToDevice, c->st));
-  HIPCHK(c, hipMemcpyAsync(c->slq_rz, rz.data(), sizeof(double) * ell, hipMemcpyHostToDevice, c->st));
   launch_slq_terms(c->st, c->slq_a, c->slq_b, c->slq_iters, c->slq_rz, ell, c->slq_ld, c->slq_work, c->slq_terms);
   std::vector<double> terms(ell);
   HIPCHK(c, hipMemcpyAsync(terms.data(), c->slq_terms, sizeof(double) * ell, hipMemcpyDeviceToHost, c->st));
@@ -1691,7 +1888,53 @@ static vif_status laplace_nll_impl(vif_ctx* c, const double* y, const double* mo
   return VIF_OK;
 }
 
-static int lapgrad_slots(int ell) { return 3 * (2 + 2 * ell) + 16; }
+// Parameters of theta = (sigma1^2, lambda_1..lambda_L, s2): L = d for the ARD
+// kernel, 1 otherwise. For parameter p: which = 0 (sigma1^2), 1 (a length
+// scale; the covariance parameters select it through dparam) or 2 (s2).
+static int n_params(const vif_config& g) { return (g.kernel == VIF_GAUSSIAN_ARD ? g.d : 1) + 2; }
+static int param_which(const vif_config& g, int p) {
+  const int P = n_params(g);
+  return p == 0 ? 0 : (p == P - 1 ? 2 : 1);
+}
+static CovParams param_cov(const vif_ctx* c, int p) {
+  CovParams q = c->cp;
+  q.dparam = (c->cfg.kernel == VIF_GAUSSIAN_ARD && param_which(c->cfg, p) == 1) ? p - 1 : -1;
+  return q;
+}
+
+// Factor tangents (dA, dD, dU) for parameter p by the forward-mode derivative
+// of eq. D_A_Vecchia, with dV = L_m^{-1} dK(Z, X) - V Phi(L_m^{-1} dSigma_m L_m^{-T})^T
+// (the whitened features' tangent) built in dVbuf; mm: two mp x mp scratch
+// matrices, PhiT: mp x mp in the form's type.
+template <typename T>
+static void factor_tangent(vif_ctx* c, int p, T* dVbuf, double* mm, T* PhiT, T* dA, double* dD, T* dU) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  const int mp = c->mp, m = g.m;
+  const int which = param_which(g, p);
+  const CovParams cpp = param_cov(c, p);
+  const T* V = (const T*)(fp32_form(c) ? (const void*)c->Vf : (const void*)c->Vd);
+  const T* dVp = nullptr;
+  if (which < 2 && m > 0) {
+    double* dSm = mm;
+    double* Pm = mm + (size_t)mp * mp;
+    launch_cov_zz_d(c->st, c->Zc, m, mp, cpp, which, dSm);
+    launch_gemm_sq(c->st, dSm, c->Linv, c->Mwork, mp, false, true);
+    launch_gemm_sq(c->st, c->Linv, c->Mwork, Pm, mp, false, false);
+    launch_phi_t<T>(c->st, Pm, m, mp, PhiT);
+    if (which == 0) {
+      launch_rowmm<T>(c->st, V, PhiT, V, -1.0, 1.0 / c->cp.sigma1_sq, n, mp, dVbuf);
+    } else {
+      launch_whiten<T>(c->st, c->Xc, c->Zc, c->Linv, m, mp, n, cpp, true, dVbuf);
+      launch_rowmm<T>(c->st, V, PhiT, dVbuf, -1.0, 1.0, n, mp, dVbuf);
+    }
+    dVp = dVbuf;
+  }
+  launch_factor_jvp<T>(c->st, c->Xc, V, dVp, c->nbr, (const T*)c->U, n, mp, g.m_v, cpp, which, dA, dD, dU, c->status,
+                       vorder(c));
+}
+
+static int lapgrad_slots(int ell, int P) { return P * (2 + 2 * ell) + 4 * P; }
 
 // Laplace-gradient workspace (tangents per parameter, per-point vectors and
 // the per-probe scalar slots for up to max_probes probes), allocated by vif_create.
@@ -1705,7 +1948,7 @@ static vif_status alloc_lapgrad(vif_ctx* c, int nslot) {
   alloc(&c->lg_Ut, ts * n * mpa);
   alloc(&c->lg_Ut3, ts * n * mpa);
   alloc(&c->lg_dV, ts * n * mpa);
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < n_params(c->cfg); ++k) {
     alloc(&c->lg_dU[k], ts * n * mpa);
     alloc(&c->lg_dA[k], ts * n * mva);
     alloc((void**)&c->lg_dD[k], sizeof(double) * n);
@@ -1760,7 +2003,8 @@ static vif_status laplace_grad_impl(vif_ctx* c, const double* y, const double* m
   const vif_config& g = c->cfg;
   const int64_t n = g.n;
   const int mp = c->mp, mv = g.m_v, m = g.m;
-  const int nslot = 3 * (2 + 2 * ell) + 16;
+  const int P = n_params(g);
+  const int nslot = lapgrad_slots(ell, P);
   vif_status s = nslot <= c->lg_slot_cap ? VIF_OK : check_probes(c, ell, "vif_laplace_nll_grad");
   if (s) return s;
   LapBufs B = lap_bufs(c);
@@ -1784,7 +2028,7 @@ static vif_status laplace_grad_impl(vif_ctx* c, const double* y, const double* m
   double* part = c->lg_part;
   double* slots = c->lg_slots;
   // slot layout: [p * (2 + 2 ell) + 0] f(b, b), [+1] f(v, b), [+2 + k] f(u_k, q_k), [+2 + ell + k] g(q_k)
-  double* tslots = slots + 3 * (2 + 2 * ell);  // traces: 4 per parameter
+  double* tslots = slots + P * (2 + 2 * ell);  // traces: 4 per parameter
   launch_lik_dW(c->st, g.likelihood, g.lik_param, y, mode, n, dW);
   // Ut = U M'^{-1}, Ut3 = U M3'^{-1}, u3u_i = Ut3_i . U_i
   if (m > 0) {
@@ -1808,29 +2052,11 @@ static vif_status laplace_grad_impl(vif_ctx* c, const double* y, const double* m
   if ((s = pcg_plain<T>(c, B, dLdb, vsol, nullptr, nullptr, nullptr, &vits, &vrz))) return s;
   vec_prep<T>(c, B, mode, Pb);
   vec_prep<T>(c, B, vsol, Pv);
-  // tangents of the factor for sigma1^2, range, s2
-  for (int p = 0; p < 3; ++p) {
+  // tangents of the factor for sigma1^2, the length scale(s), s2
+  for (int p = 0; p < P; ++p) {
     T* dU = (T*)c->lg_dU[p];
     T* dA = (T*)c->lg_dA[p];
-    const T* dVp = nullptr;
-    if (p < 2 && m > 0) {
-      double* dSm = c->lg_mm;
-      double* Pm = c->lg_mm + (size_t)mp * mp;
-      launch_cov_zz_d(c->st, c->Zc, m, mp, c->cp, p, dSm);
-      launch_gemm_sq(c->st, dSm, c->Linv, c->Mwork, mp, false, true);
-      launch_gemm_sq(c->st, c->Linv, c->Mwork, Pm, mp, false, false);
-      launch_phi_t<T>(c->st, Pm, m, mp, (T*)c->lg_PhiT);
-      T* dV = (T*)c->lg_dV;
-      if (p == 0) {
-        launch_rowmm<T>(c->st, V, (const T*)c->lg_PhiT, V, -1.0, 1.0 / c->cp.sigma1_sq, n, mp, dV);
-      } else {
-        launch_whiten<T>(c->st, c->Xc, c->Zc, c->Linv, m, mp, n, c->cp, true, dV);
-        launch_rowmm<T>(c->st, V, (const T*)c->lg_PhiT, dV, -1.0, 1.0, n, mp, dV);
-      }
-      dVp = dV;
-    }
-    launch_factor_jvp<T>(c->st, c->Xc, V, dVp, c->nbr, U, n, mp, mv, c->cp, p, dA, c->lg_dD[p], dU, c->status,
-                         vorder(c));
+    factor_tangent<T>(c, p, (T*)c->lg_dV, c->lg_mm, (T*)c->lg_PhiT, dA, c->lg_dD[p], dU);
     nb = launch_trace_terms<T>(c->st, (const T*)c->lg_Ut, (const T*)c->lg_Ut3, U, dU, c->D, c->lg_dD[p], B.W, n, mp,
                                part);
     launch_sum_cols(c->st, part, nb, 4, tslots + 4 * p);
@@ -1845,32 +2071,42 @@ static vif_status laplace_grad_impl(vif_ctx* c, const double* y, const double* m
     nb = launch_bilin(c->st, Pv.t, Pv.s, dBv, aUv, Pb.t, Pb.s, dBb, aUb, c->D, c->lg_dD[p], nullptr, n, part);
     hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, part, nb, fs + 1);
   }
-  // per probe: f(u_k, q_k) and g(q_k) for each parameter
-  for (int k = 0; k < ell; ++k) {
-    const double* uk = c->slq_u + (size_t)k * n;
-    const double* qk = c->slq_q + (size_t)k * n;
-    vec_prep<T>(c, B, uk, Pu);
-    vec_prep<T>(c, B, qk, Pq);
-    for (int p = 0; p < 3; ++p) {
+  // per probe: f(u_k, q_k) and g(q_k) for each parameter, a block of probes
+  // at a time (every pass over U and dU made once for the block)
+  BlkBufs K = blk_bufs(c);
+  for (int k0 = 0; k0 < ell; k0 += K.cap) {
+    const int L = std::min(K.cap, ell - k0);
+    double *Xu = K.x, *Xq = K.r, *Tu = K.t, *Su = K.s, *Tq = K.z, *Sq = K.p;
+    double *Au = K.cm, *Aq = K.cm3, *dBu = K.q, *aUu = K.qd, *dBq = K.q2, *aUq = K.ap;
+    launch_cols_to_block(c->st, c->slq_u, n, 0, k0, n, L, Xu);
+    launch_cols_to_block(c->st, c->slq_q, n, 0, k0, n, L, Xq);
+    // t = D^{-1/2} B x, a = M'^{-1} U^T t, s = t - U a (as vec_prep)
+    launch_bw_multi<T>(c->st, (const T*)c->A, c->D, c->nbr, Xu, n, mv, L, Tu);
+    if (m > 0) launch_utx<T>(c->st, U, Tu, n, mp, L, c->Minv, K.part, K.cm2, Au);
+    launch_rowmm_multi<T>(c->st, U, Au, Tu, nullptr, nullptr, n, mp, L, 0, Su);
+    launch_bw_multi<T>(c->st, (const T*)c->A, c->D, c->nbr, Xq, n, mv, L, Tq);
+    if (m > 0) launch_utx<T>(c->st, U, Tq, n, mp, L, c->Minv, K.part, K.cm2, Aq);
+    launch_rowmm_multi<T>(c->st, U, Aq, Tq, nullptr, nullptr, n, mp, L, 0, Sq);
+    for (int p = 0; p < P; ++p) {
       const T* dU = (const T*)c->lg_dU[p];
       const T* dA = (const T*)c->lg_dA[p];
       double* fs = slots + (size_t)p * (2 + 2 * ell);
-      launch_dbx<T>(c->st, dA, c->nbr, uk, n, mv, dBx);
-      launch_rowvec<T>(c->st, dU, Pu.a, n, mp, aUx);
-      launch_dbx<T>(c->st, dA, c->nbr, qk, n, mv, dBq);
-      launch_rowvec<T>(c->st, dU, Pq.a, n, mp, aUb);  // aUb reused for dU a_q
-      nb = launch_bilin(c->st, Pu.t, Pu.s, dBx, aUx, Pq.t, Pq.s, dBq, aUb, c->D, c->lg_dD[p], nullptr, n, part);
-      hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, part, nb, fs + 2 + k);
-      nb = launch_bilin(c->st, Pq.t, Pq.s, dBq, aUb, Pq.t, Pq.s, dBq, aUb, c->D, c->lg_dD[p], B.W, n, part);
-      hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, part, nb, fs + 2 + ell + k);
+      launch_dbx_multi<T>(c->st, dA, c->nbr, Xu, n, mv, L, dBu);
+      launch_rowmm_multi<T>(c->st, dU, Au, nullptr, nullptr, nullptr, n, mp, L, 2, aUu);
+      launch_dbx_multi<T>(c->st, dA, c->nbr, Xq, n, mv, L, dBq);
+      launch_rowmm_multi<T>(c->st, dU, Aq, nullptr, nullptr, nullptr, n, mp, L, 2, aUq);
+      launch_bilin_multi(c->st, Tu, Su, dBu, aUu, Tq, Sq, dBq, aUq, c->D, c->lg_dD[p], nullptr, n, L, K.part,
+                         fs + 2 + k0);
+      launch_bilin_multi(c->st, Tq, Sq, dBq, aUq, Tq, Sq, dBq, aUq, c->D, c->lg_dD[p], B.W, n, L, K.part,
+                         fs + 2 + ell + k0);
     }
   }
   std::vector<double> hs(nslot);
   HIPCHK(c, hipMemcpyAsync(hs.data(), slots, sizeof(double) * nslot, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
-  for (int p = 0; p < 3; ++p) {
+  for (int p = 0; p < P; ++p) {
     const double* fs = hs.data() + (size_t)p * (2 + 2 * ell);
-    const double* ts = hs.data() + 3 * (2 + 2 * ell) + 4 * p;
+    const double* ts = hs.data() + P * (2 + 2 * ell) + 4 * p;
     const double dlogdetS = ts[0] + ts[1];          // sum dD/D + tr(M'^{-1} dM')
     const double trP = ts[3] - ts[0] + ts[2] - ts[1];  // d log det P (W fixed)
     double fm = 0.0;
@@ -1925,8 +2161,6 @@ vif_status vif_laplace_nll_grad(vif_ctx* c, const double* y, const double* mode,
   if (!y || !mode || !eps_n || !nll_out || !grad_out || (g.m > 0 && !eps_m))
     return fail(c, VIF_E_ARG, "NULL argument");
   if (ell < 2) return fail(c, VIF_E_ARG, "the control variates need at least two probes (got %d)", ell);
-  if (g.kernel == VIF_GAUSSIAN_ARD)
-    return fail(c, VIF_E_ARG, "vif_laplace_nll_grad supports the isotropic kernels (one length scale)");
   vif_status s = check_probes(c, ell, "vif_laplace_nll_grad");
   if (s) return s;
   if ((s = reset_status(c))) return s;
@@ -1942,7 +2176,7 @@ vif_status vif_laplace_nll_grad(vif_ctx* c, const double* y, const double* mode,
   if (s) return s;
   if ((s = read_status(c, "vif_laplace_nll_grad"))) return s;
   *nll_out = out3[0];
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < n_params(g); ++k)
     if (!isfinite(grad_out[k])) return fail(c, VIF_E_NAN, "gradient entry %d is not finite", k);
   return VIF_OK;
 }
@@ -2104,6 +2338,35 @@ static vif_status laplace_predvar_impl(vif_ctx* c, const double* y, const double
 }
 
 extern "C" {
+
+vif_status vif_select_inducing(vif_ctx* c, const double* X, const double* theta, const double* unif,
+                               const double* Z_init, int32_t lloyd_iters, double* Z_out, int32_t* seed_idx_out) {
+  if (!c) return VIF_E_ARG;
+  const vif_config& g = c->cfg;
+  if (g.m == 0) return fail(c, VIF_E_ARG, "vif_select_inducing needs m > 0");
+  if (!X || !theta || !Z_out || (!Z_init && !unif) || lloyd_iters < 0)
+    return fail(c, VIF_E_ARG, "NULL X, theta or Z_out, no uniforms without Z_init, or lloyd_iters < 0");
+  const int L = (g.kernel == VIF_GAUSSIAN_ARD) ? g.d : 1;
+  double lam[VIF_MAX_D];
+  for (int k = 0; k < g.d; ++k) {
+    lam[k] = theta[1 + (L == 1 ? 0 : k)];
+    if (!(lam[k] > 0) || !isfinite(lam[k])) return fail(c, VIF_E_ARG, "length scale %d must be > 0", k);
+  }
+  if (!Z_init) {
+    for (int k = 0; k < g.m; ++k)
+      if (!(unif[k] >= 0.0 && unif[k] < 1.0)) return fail(c, VIF_E_ARG, "uniform %d is not in [0, 1)", k);
+    launch_kmeans_seed(c->st, X, g.n, g.d, lam, g.m, unif, c->km_dist, c->km_bsum, c->km_C, c->km_idx);
+  } else {
+    launch_km_scale(c->st, Z_init, g.m, g.d, lam, true, c->km_C);
+  }
+  launch_kmeans_lloyd(c->st, X, g.n, g.d, lam, g.m, lloyd_iters, c->km_assign, c->km_part, c->km_C);
+  launch_km_scale(c->st, c->km_C, g.m, g.d, lam, false, Z_out);
+  HIPCHK(c, hipGetLastError());
+  if (seed_idx_out && !Z_init)
+    HIPCHK(c, hipMemcpyAsync(seed_idx_out, c->km_idx, sizeof(int) * g.m, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return VIF_OK;
+}
 
 vif_status vif_select_neighbors_pred(vif_ctx* c, const double* Xp, int64_t np_, int32_t* nbrp_out) {
   if (!c) return VIF_E_ARG;

@@ -265,6 +265,7 @@ vif_status vif_batch_nll_grad(vif_batch* b, const double* X, const double* Z, co
     c.sigma1_sq = th[0];
     c.s2 = th[2];
     for (int k = 0; k < VIF_MAX_D; ++k) c.inv_ls[k] = (k < g.d) ? 1.0 / th[1] : 0.0;
+    c.dparam = -1;
   }
   hipStream_t st = b->st;
   const int init[8] = {0, 0, 0x7fffffff, 0, 0, 0, 0, 0};

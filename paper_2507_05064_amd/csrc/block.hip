@@ -1,0 +1,597 @@
+// Many right-hand sides at once: the probe vectors of the stochastic
+// estimators (SLQ of eq. slq_v1 and the trace estimates of App. B / App. D)
+// are independent conjugate-gradient solves with the same matrix and
+// preconditioner, so every operator pass is made once for all of them.
+//
+// A block of L <= 64 vectors is stored n x L, row-major: a point's L values
+// are contiguous, so a gather by neighbour index reads one L-wide burst and
+// the elementwise and row-gather kernels give one lane to each column. The
+// low-rank products with U (n x mp) are MFMA contractions with the block:
+// U^T X (mp x L, split over point chunks) and U C (n x L). The triangular
+// solves walk the same level schedule as the single-vector solves, one launch
+// per level, each level reading its rows once for all L columns.
+#include "common.h"
+#include "kernels.h"
+
+// ------------------------------------------------------------ elementwise
+// xq[q][l] = x[order[q]][l]
+__global__ void k_perm_gather_multi(const int* __restrict__ order, const double* __restrict__ x, int64_t n, int L,
+                                    double* __restrict__ xq) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * L) return;
+  const int64_t q = e / L;
+  xq[e] = x[(int64_t)order[q] * L + (e - q * L)];
+}
+// z[order[q]][l] = zq[q][l]
+__global__ void k_perm_scatter_multi(const int* __restrict__ order, const double* __restrict__ zq, int64_t n, int L,
+                                     double* __restrict__ z) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * L) return;
+  const int64_t q = e / L;
+  z[(int64_t)order[q] * L + (e - q * L)] = zq[e];
+}
+
+// out[i][l] = src[(k0 + l) * stride + off + i]: columns of a block from
+// vectors stored one after another (probe normals, kept solutions)
+__global__ void k_cols_to_block(const double* __restrict__ src, int64_t stride, int64_t off, int k0, int64_t n, int L,
+                                double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * L) return;
+  const int64_t i = e / L;
+  const int l = (int)(e - i * L);
+  out[e] = src[(int64_t)(k0 + l) * stride + off + i];
+}
+// dst[(k0 + l) * n + i] = blk[i][l]
+__global__ void k_block_to_cols(const double* __restrict__ blk, int64_t n, int L, int k0, double* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * L) return;
+  const int64_t i = e / L;
+  const int l = (int)(e - i * L);
+  dst[(int64_t)(k0 + l) * n + i] = blk[e];
+}
+// out[k][l] = k < m ? eps[(k0 + l) * m + k] : 0   (mp x L, the e3 normals)
+__global__ void k_eps_m_block(const double* __restrict__ eps, int m, int mp, int k0, int L, double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mp * L) return;
+  const int k = e / L, l = e - k * L;
+  out[e] = k < m ? eps[(int64_t)(k0 + l) * m + k] : 0.0;
+}
+
+// out[i][l] = sqrt(D_i) x[i][l]
+__global__ void k_sqrtd_multi(const double* __restrict__ D, const double* __restrict__ x, int64_t n, int L,
+                              double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * L) return;
+  out[e] = sqrt(D[e / L]) * x[e];
+}
+// s[i][l] += sqrt(W_i) e[i][l]
+__global__ void k_add_sqrtw_multi(double* __restrict__ s, const double* __restrict__ W, const double* __restrict__ e1,
+                                  int64_t n, int L) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * L) return;
+  s[e] += sqrt(W[e / L]) * e1[e];
+}
+// q = E v, qd = q / sqrt(D)
+__global__ void k_scale_e_multi(const double* __restrict__ v, const double* __restrict__ E, const double* __restrict__ D,
+                                int64_t n, int L, double* __restrict__ q, double* __restrict__ qd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * L) return;
+  const int64_t i = e / L;
+  const double qq = E[i] * v[e];
+  q[e] = qq;
+  qd[e] = qq / sqrt(D[i]);
+}
+
+// ------------------------------------------------------------ B and B^T
+// out[i][l] = (x[i][l] - sum_a A_ia x[N(i)_a][l]) * (D ? D_i^{-1/2} : 1); one wave per point
+template <typename T>
+__global__ __launch_bounds__(256) void k_bw_multi(const T* __restrict__ A, const double* __restrict__ D,
+                                                  const int32_t* __restrict__ nbr, const double* __restrict__ x,
+                                                  int64_t n, int mv, int L, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n || lane >= L) return;
+  double s = x[i * L + lane];
+  for (int a = 0; a < mv; ++a) {
+    const int j = nbr[i * mv + a];
+    if (j >= 0) s -= (double)A[i * mv + a] * x[(int64_t)j * L + lane];
+  }
+  out[i * L + lane] = D ? s / sqrt(D[i]) : s;
+}
+
+// out[i][l] = -sum_a dA_ia x[N(i)_a][l]   (dB x, dB_{i,N(i)} = -dA_i)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dbx_multi(const T* __restrict__ dA, const int32_t* __restrict__ nbr,
+                                                   const double* __restrict__ x, int64_t n, int mv, int L,
+                                                   double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n || lane >= L) return;
+  double s = 0.0;
+  for (int a = 0; a < mv; ++a) {
+    const int j = nbr[i * mv + a];
+    if (j >= 0) s -= (double)dA[i * mv + a] * x[(int64_t)j * L + lane];
+  }
+  out[i * L + lane] = s;
+}
+
+// out[j][l] = s[j][l] - sum_{(q, slot): N(q)_slot = j} A_{q,slot} s[q][l] + (W ? W_j p[j][l] : 0)
+template <typename T>
+__global__ __launch_bounds__(256) void k_btw_multi(const T* __restrict__ A, const int* __restrict__ rev_ptr,
+                                                   const int* __restrict__ rev_idx, const double* __restrict__ s,
+                                                   const double* __restrict__ W, const double* __restrict__ p,
+                                                   int64_t n, int mv, int L, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n || lane >= L) return;
+  double v = 0.0;
+  const int end = rev_ptr[j + 1];
+  for (int q = rev_ptr[j]; q < end; ++q) {
+    const int idx = rev_idx[q];
+    v += (double)A[idx] * s[(int64_t)(idx / mv) * L + lane];
+  }
+  out[j * L + lane] = s[j * L + lane] - v + (W ? W[j] * p[j * L + lane] : 0.0);
+}
+
+// one level of B^{-1} (positions [beg, end), row q: m_v slots of positions
+// and coefficients): zq[q][l] = xq[q][l] + sum_a coef_qa zq[col_qa][l]
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_fwd_level_multi(int beg, int end, const int* __restrict__ col,
+                                                              const T* __restrict__ coef,
+                                                              const double* __restrict__ xq, int mv, int L,
+                                                              double* zq) {
+  const int lane = threadIdx.x & 63;
+  const int q = beg + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= end || lane >= L) return;
+  double s = xq[(int64_t)q * L + lane];
+  for (int a = 0; a < mv; ++a) {
+    const int cq = col[(size_t)q * mv + a];
+    if (cq >= 0) s += (double)coef[(size_t)q * mv + a] * zq[(int64_t)cq * L + lane];
+  }
+  zq[(int64_t)q * L + lane] = s;
+}
+
+// one level of B^{-T} (CSR rows by position)
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_bwd_level_multi(int beg, int end, const int* __restrict__ ptr,
+                                                              const int* __restrict__ col, const T* __restrict__ coef,
+                                                              const double* __restrict__ xq, int L, double* zq) {
+  const int lane = threadIdx.x & 63;
+  const int q = beg + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= end || lane >= L) return;
+  double s = xq[(int64_t)q * L + lane];
+  const int e1 = ptr[q + 1];
+  for (int a = ptr[q]; a < e1; ++a) s += (double)coef[a] * zq[(int64_t)col[a] * L + lane];
+  zq[(int64_t)q * L + lane] = s;
+}
+
+// ------------------------------------------------------------ low-rank products
+// part[chunk][k][l] = sum_{i in chunk} U[i][k] x[i][l] (f64 MFMA 16x16x4: the
+// chunk's points are the contraction index). Workgroup = (chunk, 128 rows k):
+// 32-point tiles of U and x staged in LDS, wave w owns rows 32w..32w+31 of
+// its 128 (two 16-row tiles) and the L columns (up to four 16-column tiles).
+template <typename T>
+__global__ __launch_bounds__(256) void k_utx_partial(const T* __restrict__ U, const double* __restrict__ x, int64_t n,
+                                                     int mp, int L, int64_t chunk, double* __restrict__ part) {
+  __shared__ double sU[32][129];
+  __shared__ double sX[32][65];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int k0 = blockIdx.y * 128;
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk, pend = min(n, pbeg + chunk);
+  const int nt = (L + 15) / 16;
+  d4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[a][t] = d4{0, 0, 0, 0};
+  for (int64_t p0 = pbeg; p0 < pend; p0 += 32) {
+    for (int e = threadIdx.x; e < 32 * 128; e += 256) {
+      const int pt = e >> 7, k = e & 127;
+      const int64_t i = p0 + pt;
+      sU[pt][k] = (i < pend && k0 + k < mp) ? (double)U[(size_t)i * mp + k0 + k] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+      const int pt = e >> 6, l = e & 63;
+      const int64_t i = p0 + pt;
+      sX[pt][l] = (i < pend && l < L) ? x[i * L + l] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4) {
+      const double a0 = sU[kk + g][32 * w + r], a1 = sU[kk + g][32 * w + 16 + r];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < nt) {
+          const double b = sX[kk + g][16 * t + r];
+          acc[0][t] = mfma16(a0, b, acc[0][t]);
+          acc[1][t] = mfma16(a1, b, acc[1][t]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* out = part + (size_t)blockIdx.x * mp * L;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = k0 + 32 * w + 16 * a + acc_row<double>(lane, v), l = 16 * t + r;
+        if (t < nt && k < mp && l < L) out[(size_t)k * L + l] = acc[a][t][v];
+      }
+}
+
+// out = Minv (sum over chunks of part), mp x L (Minv: mp x mp, symmetric)
+__global__ void k_utx_reduce(const double* __restrict__ part, int nchunk, int mp, int L, double* __restrict__ sum) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mp * L) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * mp * L + e];
+  sum[e] = s;
+}
+__global__ void k_sym_apply_multi(const double* __restrict__ Minv, const double* __restrict__ cin, int mp, int L,
+                                  double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mp * L) return;
+  const int k = e / L, l = e - k * L;
+  const double* row = Minv + (size_t)k * mp;
+  double s = 0.0;
+  for (int j = 0; j < mp; ++j) s += row[j] * cin[(size_t)j * L + l];
+  out[e] = s;
+}
+
+// (U C)[i][l] for a 64-point tile (f64 MFMA; 64 x 32 tiles of U and 32 x L
+// tiles of C staged in LDS), combined per mode:
+//   0: out = (t - U C) f,  f = D^{-1/2} (D given) or 1
+//   1: out = t + E (U C) D^{-1/2}
+//   2: out = U C
+//   3: out = t + U C
+template <typename T>
+__global__ __launch_bounds__(256) void k_rowmm_multi(const T* __restrict__ U, const double* __restrict__ C,
+                                                     const double* __restrict__ t, const double* __restrict__ E,
+                                                     const double* __restrict__ D, int64_t n, int mp, int L, int mode,
+                                                     double* __restrict__ out) {
+  __shared__ double sU[64][33];
+  __shared__ double sC[32][65];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int nt = (L + 15) / 16;
+  d4 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = d4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < mp; k0 += 32) {
+    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+      const int pt = e >> 5, k = e & 31;
+      const int64_t i = p0 + pt;
+      sU[pt][k] = (i < n && k0 + k < mp) ? (double)U[(size_t)i * mp + k0 + k] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+      const int k = e >> 6, l = e & 63;
+      sC[k][l] = (k0 + k < mp && l < L) ? C[(size_t)(k0 + k) * L + l] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4) {
+      const double a = sU[16 * w + r][kk + g];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (u < nt) acc[u] = mfma16(a, sC[kk + g][16 * u + r], acc[u]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = p0 + 16 * w + acc_row<double>(lane, v);
+      const int l = 16 * u + r;
+      if (u < nt && i < n && l < L) {
+        const double uc = acc[u][v];
+        const int64_t e = i * L + l;
+        double o;
+        if (mode == 0)
+          o = D ? (t[e] - uc) / sqrt(D[i]) : t[e] - uc;
+        else if (mode == 1)
+          o = t[e] + E[i] * uc / sqrt(D[i]);
+        else if (mode == 2)
+          o = uc;
+        else
+          o = t[e] + uc;
+        out[e] = o;
+      }
+    }
+}
+
+// ------------------------------------------------------------ column reductions
+// part[blk][c][l] = sum over the block's points of a_c[i][l] b_c[i][l], c < nc
+// (nc = 1 or 2); 4 waves stride over the block's 1024 points, fixed order
+__global__ __launch_bounds__(256) void k_coldot_multi(const double* __restrict__ a0, const double* __restrict__ b0,
+                                                      const double* __restrict__ a1, const double* __restrict__ b1,
+                                                      int64_t n, int L, double* __restrict__ part) {
+  __shared__ double red[2][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * 1024;
+  double s0 = 0.0, s1 = 0.0;
+  if (lane < L)
+    for (int64_t i = i0 + w; i < min(n, i0 + 1024); i += 4) {
+      const int64_t e = i * L + lane;
+      s0 += a0[e] * b0[e];
+      if (a1) s1 += a1[e] * b1[e];
+    }
+  red[0][w][lane] = s0;
+  red[1][w][lane] = s1;
+  __syncthreads();
+  if (w == 0 && lane < L) {
+    part[((size_t)blockIdx.x * 2) * L + lane] = (red[0][0][lane] + red[0][1][lane]) + (red[0][2][lane] + red[0][3][lane]);
+    part[((size_t)blockIdx.x * 2 + 1) * L + lane] =
+        (red[1][0][lane] + red[1][1][lane]) + (red[1][2][lane] + red[1][3][lane]);
+  }
+}
+// out[c][l] = sum_blk part[blk][c][l] (fixed order)
+__global__ void k_coldot_final(const double* __restrict__ part, int nb, int L, double* __restrict__ out) {
+  const int e = threadIdx.x;  // c * L + l, 2 L <= 128
+  if (e >= 2 * L) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[(size_t)b * 2 * L + e];
+  out[e] = s;
+}
+
+// ------------------------------------------------------------ CG per column
+// cs layout (per column l, stride L): [0] rz [1] pAp [2] rz_new [3] rr
+// [4] thr [5] alpha [6] active (1 / 0) [7] iterations
+__global__ void k_cg_alpha_multi(double* __restrict__ cs, int L) {
+  const int l = threadIdx.x;
+  if (l >= L) return;
+  cs[5 * L + l] = cs[6 * L + l] > 0.0 ? cs[0 * L + l] / cs[1 * L + l] : 0.0;
+}
+// x += alpha p, r -= alpha Ap (columns with alpha = 0 stay as they are)
+__global__ void k_cg_update_multi(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                                  const double* __restrict__ Ap, const double* __restrict__ cs, int64_t n, int L) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * L) return;
+  const double a = cs[5 * L + e % L];
+  if (a != 0.0) {
+    x[e] += a * p[e];
+    r[e] -= a * Ap[e];
+  }
+}
+// after z = P^{-1} r and the new rz, rr: log alpha_it and beta_it of the
+// active columns, test each column's own stopping rule, beta for the
+// direction update (0 for finished columns); ndone counts active columns
+__global__ void k_cg_beta_multi(double* __restrict__ cs, const double* __restrict__ dots, int it, int L, int ld,
+                                double* __restrict__ alog, double* __restrict__ blog, double* __restrict__ beta,
+                                int* __restrict__ nactive) {
+  const int l = threadIdx.x;  // one wave, lanes over the columns
+  double b = 0.0;
+  if (l < L && cs[6 * L + l] > 0.0) {
+    const double rzn = dots[l], rr = dots[L + l], rz = cs[0 * L + l];
+    b = rzn / rz;
+    if (alog) {
+      alog[(size_t)l * ld + it - 1] = cs[5 * L + l];
+      blog[(size_t)l * ld + it - 1] = b;
+    }
+    cs[0 * L + l] = rzn;
+    cs[3 * L + l] = rr;
+    cs[7 * L + l] = it;
+    if (!isfinite(rr)) {
+      cs[6 * L + l] = -1.0;  // non-finite: stop, reported by the host
+      b = 0.0;
+    } else if (!(rr > cs[4 * L + l])) {
+      cs[6 * L + l] = 0.0;
+      b = 0.0;
+    }
+  }
+  if (l < L) beta[l] = b;
+  const int cnt = __popcll(__ballot(l < L && cs[6 * L + l] > 0.0));
+  if (l == 0) nactive[0] = cnt;
+}
+// p = z + beta p
+__global__ void k_cg_dir_multi(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ beta,
+                               int64_t n, int L) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * L) return;
+  p[e] = z[e] + beta[e % L] * p[e];
+}
+// start: rz = r.z, rr = r.r, thr = tol^2 rr, active = rr > 0, iterations 0
+__global__ void k_cg_init_multi(double* __restrict__ cs, const double* __restrict__ dots, double tol2, int L,
+                                double* __restrict__ rz0, int* __restrict__ nactive) {
+  const int l = threadIdx.x;  // one wave
+  bool act = false;
+  if (l < L) {
+    const double rz = dots[l], rr = dots[L + l];
+    act = rr > 0.0;
+    cs[0 * L + l] = rz;
+    cs[3 * L + l] = rr;
+    cs[4 * L + l] = tol2 * rr;
+    cs[5 * L + l] = 0.0;
+    cs[6 * L + l] = act ? 1.0 : 0.0;
+    cs[7 * L + l] = 0.0;
+    if (rz0) rz0[l] = rz;
+  }
+  const int cnt = __popcll(__ballot(act));
+  if (l == 0) nactive[0] = cnt;
+}
+// iteration counts of the finished solves (int), and whether any failed
+__global__ void k_cg_iters_multi(const double* __restrict__ cs, int L, int* __restrict__ iters, int* __restrict__ bad) {
+  const int l = threadIdx.x;
+  if (l >= L) return;
+  iters[l] = (int)cs[7 * L + l];
+  if (cs[6 * L + l] < 0.0) bad[0] = 1;
+}
+
+// ------------------------------------------------------------ gradient forms
+// per-block, per-column partials of the bilinear form of App. B used by the
+// single-vector k_bilin:
+//   f_i = dt_u s_w + s_u dt_w - s_u (dU a_w)_i - s_w (dU a_u)_i,
+//   dt = dB x D^{-1/2} - dD / (2 D) t,  plus, when W is set (u = w),
+//   2 sqrt(D_i) t_u W_i (dB u)_i
+__global__ __launch_bounds__(256) void k_bilin_multi(const double* __restrict__ tu, const double* __restrict__ su,
+                                                     const double* __restrict__ bu, const double* __restrict__ au,
+                                                     const double* __restrict__ tw, const double* __restrict__ sw,
+                                                     const double* __restrict__ bw, const double* __restrict__ aw,
+                                                     const double* __restrict__ D, const double* __restrict__ dD,
+                                                     const double* __restrict__ W, int64_t n, int L,
+                                                     double* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * 1024;
+  double acc = 0.0;
+  if (lane < L)
+    for (int64_t i = i0 + w; i < min(n, i0 + 1024); i += 4) {
+      const int64_t e = i * L + lane;
+      const double rs = 1.0 / sqrt(D[i]), h = 0.5 * dD[i] / D[i];
+      const double dtu = bu[e] * rs - h * tu[e], dtw = bw[e] * rs - h * tw[e];
+      double v = dtu * sw[e] + su[e] * dtw - su[e] * aw[e] - sw[e] * au[e];
+      if (W) v += 2.0 * sqrt(D[i]) * tu[e] * W[i] * bu[e];
+      acc += v;
+    }
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && lane < L) part[(size_t)blockIdx.x * L + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+// out[l] = sum_blk part[blk][l]
+__global__ void k_colsum_final(const double* __restrict__ part, int nb, int L, double* __restrict__ out) {
+  const int l = threadIdx.x;
+  if (l >= L) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[(size_t)b * L + l];
+  out[l] = s;
+}
+
+// ------------------------------------------------------------ launchers
+static inline dim3 gE(int64_t cnt) { return dim3((unsigned)ceil_div(cnt, 256)); }
+
+void launch_cols_to_block(hipStream_t st, const double* src, int64_t stride, int64_t off, int k0, int64_t n, int L,
+                          double* out) {
+  hipLaunchKernelGGL(k_cols_to_block, gE(n * L), dim3(256), 0, st, src, stride, off, k0, n, L, out);
+}
+void launch_block_to_cols(hipStream_t st, const double* blk, int64_t n, int L, int k0, double* dst) {
+  hipLaunchKernelGGL(k_block_to_cols, gE(n * L), dim3(256), 0, st, blk, n, L, k0, dst);
+}
+void launch_eps_m_block(hipStream_t st, const double* eps, int m, int mp, int k0, int L, double* out) {
+  hipLaunchKernelGGL(k_eps_m_block, gE((int64_t)mp * L), dim3(256), 0, st, eps, m, mp, k0, L, out);
+}
+void launch_sqrtd_multi(hipStream_t st, const double* D, const double* x, int64_t n, int L, double* out) {
+  hipLaunchKernelGGL(k_sqrtd_multi, gE(n * L), dim3(256), 0, st, D, x, n, L, out);
+}
+void launch_add_sqrtw_multi(hipStream_t st, double* s, const double* W, const double* e1, int64_t n, int L) {
+  hipLaunchKernelGGL(k_add_sqrtw_multi, gE(n * L), dim3(256), 0, st, s, W, e1, n, L);
+}
+void launch_scale_e_multi(hipStream_t st, const double* v, const double* E, const double* D, int64_t n, int L,
+                          double* q, double* qd) {
+  hipLaunchKernelGGL(k_scale_e_multi, gE(n * L), dim3(256), 0, st, v, E, D, n, L, q, qd);
+}
+template <typename T>
+void launch_bw_multi(hipStream_t st, const T* A, const double* D, const int32_t* nbr, const double* x, int64_t n,
+                     int mv, int L, double* out) {
+  hipLaunchKernelGGL((k_bw_multi<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, A, D, nbr, x, n, mv, L, out);
+}
+template <typename T>
+void launch_dbx_multi(hipStream_t st, const T* dA, const int32_t* nbr, const double* x, int64_t n, int mv, int L,
+                      double* out) {
+  hipLaunchKernelGGL((k_dbx_multi<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, dA, nbr, x, n, mv, L, out);
+}
+template <typename T>
+void launch_btw_multi(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s,
+                      const double* W, const double* p, int64_t n, int mv, int L, double* out) {
+  hipLaunchKernelGGL((k_btw_multi<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, A, rev_ptr, rev_idx, s, W, p,
+                     n, mv, L, out);
+}
+template <typename T>
+void launch_trsv_fwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, int L, double* xq,
+                           double* zq, double* z) {
+  const int64_t n = s.n;
+  hipLaunchKernelGGL(k_perm_gather_multi, gE(n * L), dim3(256), 0, st, s.order, x, n, L, xq);
+  for (int lv = 0; lv < s.nlev; ++lv) {
+    const int beg = s.hlvl[lv], end = s.hlvl[lv + 1];
+    hipLaunchKernelGGL((k_trsv_fwd_level_multi<T>), dim3((unsigned)ceil_div(end - beg, 4)), dim3(256), 0, st, beg, end,
+                       s.col, coef, xq, s.mv, L, zq);
+  }
+  hipLaunchKernelGGL(k_perm_scatter_multi, gE(n * L), dim3(256), 0, st, s.order, zq, n, L, z);
+}
+template <typename T>
+void launch_trsv_bwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, int L, double* xq,
+                           double* zq, double* z) {
+  const int64_t n = s.n;
+  hipLaunchKernelGGL(k_perm_gather_multi, gE(n * L), dim3(256), 0, st, s.order, x, n, L, xq);
+  for (int lv = 0; lv < s.nlev; ++lv) {
+    const int beg = s.hlvl[lv], end = s.hlvl[lv + 1];
+    hipLaunchKernelGGL((k_trsv_bwd_level_multi<T>), dim3((unsigned)ceil_div(end - beg, 4)), dim3(256), 0, st, beg, end,
+                       s.ptr, s.col, coef, xq, L, zq);
+  }
+  hipLaunchKernelGGL(k_perm_scatter_multi, gE(n * L), dim3(256), 0, st, s.order, zq, n, L, z);
+}
+int utx_chunks(int64_t n) { return (int)std::min<int64_t>(128, ceil_div(n, 32)); }
+template <typename T>
+void launch_utx(hipStream_t st, const T* U, const double* x, int64_t n, int mp, int L, const double* Minv,
+                double* part, double* sum, double* out) {
+  const int nch = utx_chunks(n);
+  const int64_t chunk = ceil_div(ceil_div(n, nch), 32) * 32;
+  const int nchunk = (int)ceil_div(n, chunk);
+  hipLaunchKernelGGL((k_utx_partial<T>), dim3((unsigned)nchunk, (unsigned)ceil_div(mp, 128)), dim3(256), 0, st, U, x,
+                     n, mp, L, chunk, part);
+  hipLaunchKernelGGL(k_utx_reduce, gE((int64_t)mp * L), dim3(256), 0, st, part, nchunk, mp, L, Minv ? sum : out);
+  if (Minv) hipLaunchKernelGGL(k_sym_apply_multi, gE((int64_t)mp * L), dim3(256), 0, st, Minv, sum, mp, L, out);
+}
+template <typename T>
+void launch_rowmm_multi(hipStream_t st, const T* U, const double* C, const double* t, const double* E,
+                        const double* D, int64_t n, int mp, int L, int mode, double* out) {
+  hipLaunchKernelGGL((k_rowmm_multi<T>), dim3((unsigned)ceil_div(n, 64)), dim3(256), 0, st, U, C, t, E, D, n, mp, L,
+                     mode, out);
+}
+int launch_coldot_multi(hipStream_t st, const double* a0, const double* b0, const double* a1, const double* b1,
+                        int64_t n, int L, double* part, double* out) {
+  const int nb = (int)ceil_div(n, 1024);
+  hipLaunchKernelGGL(k_coldot_multi, dim3((unsigned)nb), dim3(256), 0, st, a0, b0, a1, b1, n, L, part);
+  hipLaunchKernelGGL(k_coldot_final, dim3(1), dim3(128), 0, st, part, nb, L, out);
+  return nb;
+}
+void launch_cg_init_multi(hipStream_t st, double* cs, const double* dots, double tol2, int L, double* rz0,
+                          int* nactive) {
+  hipLaunchKernelGGL(k_cg_init_multi, dim3(1), dim3(64), 0, st, cs, dots, tol2, L, rz0, nactive);
+}
+void launch_cg_step_multi(hipStream_t st, double* x, double* r, const double* p, const double* Ap, double* cs,
+                          int64_t n, int L) {
+  hipLaunchKernelGGL(k_cg_alpha_multi, dim3(1), dim3(64), 0, st, cs, L);
+  hipLaunchKernelGGL(k_cg_update_multi, gE(n * L), dim3(256), 0, st, x, r, p, Ap, cs, n, L);
+}
+void launch_cg_beta_multi(hipStream_t st, double* cs, const double* dots, int it, int L, int ld, double* alog,
+                          double* blog, double* beta, int* nactive) {
+  hipLaunchKernelGGL(k_cg_beta_multi, dim3(1), dim3(64), 0, st, cs, dots, it, L, ld, alog, blog, beta, nactive);
+}
+void launch_cg_dir_multi(hipStream_t st, double* p, const double* z, const double* beta, int64_t n, int L) {
+  hipLaunchKernelGGL(k_cg_dir_multi, gE(n * L), dim3(256), 0, st, p, z, beta, n, L);
+}
+void launch_cg_iters_multi(hipStream_t st, const double* cs, int L, int* iters, int* bad) {
+  hipLaunchKernelGGL(k_cg_iters_multi, dim3(1), dim3(64), 0, st, cs, L, iters, bad);
+}
+int launch_bilin_multi(hipStream_t st, const double* tu, const double* su, const double* bu, const double* au,
+                       const double* tw, const double* sw, const double* bw, const double* aw, const double* D,
+                       const double* dD, const double* W, int64_t n, int L, double* part, double* out) {
+  const int nb = (int)ceil_div(n, 1024);
+  hipLaunchKernelGGL(k_bilin_multi, dim3((unsigned)nb), dim3(256), 0, st, tu, su, bu, au, tw, sw, bw, aw, D, dD, W, n,
+                     L, part);
+  hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, st, part, nb, L, out);
+  return nb;
+}
+
+#define INST(T)                                                                                                   \
+  template void launch_bw_multi<T>(hipStream_t, const T*, const double*, const int32_t*, const double*, int64_t,  \
+                                   int, int, double*);                                                           \
+  template void launch_dbx_multi<T>(hipStream_t, const T*, const int32_t*, const double*, int64_t, int, int,      \
+                                    double*);                                                                    \
+  template void launch_btw_multi<T>(hipStream_t, const T*, const int*, const int*, const double*, const double*,  \
+                                    const double*, int64_t, int, int, double*);                                  \
+  template void launch_trsv_fwd_multi<T>(hipStream_t, const TriSchedule&, const T*, const double*, int, double*,  \
+                                         double*, double*);                                                      \
+  template void launch_trsv_bwd_multi<T>(hipStream_t, const TriSchedule&, const T*, const double*, int, double*,  \
+                                         double*, double*);                                                      \
+  template void launch_utx<T>(hipStream_t, const T*, const double*, int64_t, int, int, const double*, double*,    \
+                              double*, double*);                                                                 \
+  template void launch_rowmm_multi<T>(hipStream_t, const T*, const double*, const double*, const double*,         \
+                                      const double*, int64_t, int, int, int, double*);
+INST(double)
+INST(float)

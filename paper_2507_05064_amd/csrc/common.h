@@ -48,6 +48,7 @@ struct CovParams {
   double sigma1_sq;
   double s2;                // nugget (Gaussian) or latent jitter tau
   double inv_ls[VIF_MAX_D];  // 1 / lambda_k (isotropic: all equal)
+  int dparam;                // length-scale derivatives: -1 the range (isotropic), k the ARD length scale k
 };
 
 template <typename T>
@@ -123,6 +124,19 @@ __device__ __forceinline__ T scaled_sqdist(const CovParams& p, const double* a, 
 template <typename T>
 __device__ __forceinline__ T cov_eval(const CovParams& p, const double* a, const double* b) {
   return T(p.sigma1_sq) * cov_profile<T>(p.kernel, scaled_sqdist<T>(p, a, b));
+}
+
+// d c(a, b) / d lambda for the length scale selected by p.dparam, given t2 =
+// ||(a - b) / lambda||^2: the range of an isotropic kernel (dparam < 0), or
+// the ARD length scale k = dparam of the Gaussian kernel, where
+// c = sigma1^2 e^{-t^2/2} and dc/dlambda_k = c (a_k - b_k)^2 / lambda_k^3 (Sec. 6,
+// eq. cov_trans_iso with q(s) = s / lambda).
+template <typename T>
+__device__ __forceinline__ T cov_dlength(const CovParams& p, const double* a, const double* b, T t2) {
+  if (p.dparam < 0) return T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2, T(p.inv_ls[0]));
+  const int k = p.dparam;
+  const T z = T((a[k] - b[k]) * p.inv_ls[k]);
+  return T(p.sigma1_sq) * cov_profile<T>(p.kernel, t2) * z * z * T(p.inv_ls[k]);
 }
 
 // ---------------------------------------------------------------------------

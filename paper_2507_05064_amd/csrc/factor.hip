@@ -114,8 +114,22 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
   const int lane = threadIdx.x;
   int nbv = (lane < mv) ? (own_nbr ? own_nbr[lane] : nbr[i * mv + lane]) : -1;
   if (nbv >= i) nbv = -1;  // invalid entry (reported by the list check): never gather out of range
-  const int k = __popcll(__ballot(nbv >= 0));
-  const int rowpt = (lane < k) ? nbv : (lane == k ? (int)i : -1);
+  const unsigned long long valid = __ballot(nbv >= 0);
+  const int k = __popcll(valid);
+  // lane j < k takes the j-th valid entry: a row with -1 before a valid entry
+  // (invalid input, rejected by the list check after the build) still yields
+  // k in-range row indices in lanes 0..k-1, which every later gather reads
+  int src_lane = 0;
+  {
+    int seen = 0;
+    for (int b = 0; b < 32; ++b)
+      if ((valid >> b) & 1ull) {
+        if (seen == lane) src_lane = b;
+        ++seen;
+      }
+  }
+  const int nbc = __shfl(nbv, src_lane, 64);
+  const int rowpt = (lane < k) ? nbc : (lane == k ? (int)i : -1);
   const bool own = own_v != nullptr && lane == k;
   if (lane < 32) {
     sh.nbs[lane] = rowpt;
@@ -547,8 +561,7 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
         dk = (which == 0) ? T(1) : T(0);
       } else {
         const T t2 = scaled_sqdist<T>(p, xs + a * p.d, xs + b * p.d);
-        dk = (which == 0) ? cov_profile<T>(p.kernel, t2)
-                          : T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2, T(p.inv_ls[0]));
+        dk = (which == 0) ? cov_profile<T>(p.kernel, t2) : cov_dlength<T>(p, xs + a * p.d, xs + b * p.d, t2);
       }
       if (dV != nullptr) dk -= Xc[a][b] + Xc[b][a];
       Xc[a][b] = dk;

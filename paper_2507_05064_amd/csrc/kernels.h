@@ -240,3 +240,72 @@ int launch_diag_ste(hipStream_t st, const double* us, const double* qs, int ell,
 void launch_diag_final(hipStream_t st, const double* Sh, const double* Sg, const double* tr, double c, int ell,
                        int64_t n, double* out);
 void launch_sum_cols(hipStream_t st, const double* part, int nb, int cols, double* out);
+
+// ---- many right-hand sides (block.hip): blocks of L <= kBlockCols vectors, n x L row-major
+constexpr int kBlockCols = 64;
+void launch_cols_to_block(hipStream_t st, const double* src, int64_t stride, int64_t off, int k0, int64_t n, int L,
+                          double* out);
+void launch_block_to_cols(hipStream_t st, const double* blk, int64_t n, int L, int k0, double* dst);
+void launch_eps_m_block(hipStream_t st, const double* eps, int m, int mp, int k0, int L, double* out);
+void launch_sqrtd_multi(hipStream_t st, const double* D, const double* x, int64_t n, int L, double* out);
+void launch_add_sqrtw_multi(hipStream_t st, double* s, const double* W, const double* e1, int64_t n, int L);
+void launch_scale_e_multi(hipStream_t st, const double* v, const double* E, const double* D, int64_t n, int L,
+                          double* q, double* qd);
+template <typename T>
+void launch_bw_multi(hipStream_t st, const T* A, const double* D, const int32_t* nbr, const double* x, int64_t n,
+                     int mv, int L, double* out);
+template <typename T>
+void launch_dbx_multi(hipStream_t st, const T* dA, const int32_t* nbr, const double* x, int64_t n, int mv, int L,
+                      double* out);
+template <typename T>
+void launch_btw_multi(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s,
+                      const double* W, const double* p, int64_t n, int mv, int L, double* out);
+template <typename T>
+void launch_trsv_fwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, int L, double* xq,
+                           double* zq, double* z);
+template <typename T>
+void launch_trsv_bwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, int L, double* xq,
+                           double* zq, double* z);
+int utx_chunks(int64_t n);
+// out (mp x L) = Minv (U^T x), or U^T x when Minv is null; part: utx_chunks(n) x mp x L, sum: mp x L
+template <typename T>
+void launch_utx(hipStream_t st, const T* U, const double* x, int64_t n, int mp, int L, const double* Minv,
+                double* part, double* sum, double* out);
+// modes: 0 (t - U C) D^{-1/2} (D may be null), 1 t + E (U C) D^{-1/2}, 2 U C, 3 t + U C
+template <typename T>
+void launch_rowmm_multi(hipStream_t st, const T* U, const double* C, const double* t, const double* E,
+                        const double* D, int64_t n, int mp, int L, int mode, double* out);
+// out[0..L) = columns of a0 . b0, out[L..2L) = a1 . b1 (a1 may be null); part: ceil(n / 1024) x 2 L
+int launch_coldot_multi(hipStream_t st, const double* a0, const double* b0, const double* a1, const double* b1,
+                        int64_t n, int L, double* part, double* out);
+void launch_cg_init_multi(hipStream_t st, double* cs, const double* dots, double tol2, int L, double* rz0,
+                          int* nactive);
+void launch_cg_step_multi(hipStream_t st, double* x, double* r, const double* p, const double* Ap, double* cs,
+                          int64_t n, int L);
+void launch_cg_beta_multi(hipStream_t st, double* cs, const double* dots, int it, int L, int ld, double* alog,
+                          double* blog, double* beta, int* nactive);
+void launch_cg_dir_multi(hipStream_t st, double* p, const double* z, const double* beta, int64_t n, int L);
+void launch_cg_iters_multi(hipStream_t st, const double* cs, int L, int* iters, int* bad);
+// out[0..L) = column sums of the App. B bilinear form (see block.hip); part: ceil(n / 1024) x L
+int launch_bilin_multi(hipStream_t st, const double* tu, const double* su, const double* bu, const double* au,
+                       const double* tw, const double* sw, const double* bw, const double* aw, const double* D,
+                       const double* dD, const double* W, int64_t n, int L, double* part, double* out);
+
+// per-block partials of the forward-mode Gaussian NLL derivative along one parameter (lapgrad.hip)
+template <typename T>
+int launch_gauss_fwd_terms(hipStream_t st, const T* Ut, const T* dU, const double* w, const double* e, const T* dA,
+                           const int32_t* nbr, const double* y, const double* D, const double* yt, const double* dD,
+                           int64_t n, int mp, int mv, double* part);
+
+// ---- k-means++ inducing points in the transformed space (inducing.hip); lam_h: host length scales (d)
+int kmeans_blocks(int64_t n);
+int kmeans_chunks(int64_t n);
+// D^2 seeding with the host uniforms unif[0..m): C (m x d, transformed), idx (m), dist2 (n), bsum (kmeans_blocks)
+void launch_kmeans_seed(hipStream_t st, const double* X, int64_t n, int d, const double* lam_h, int m,
+                        const double* unif, double* dist2, double* bsum, double* C, int* idx);
+// iters Lloyd steps on C (m x d, transformed); assign (n), part (kmeans_chunks x m x (d + 1))
+void launch_kmeans_lloyd(hipStream_t st, const double* X, int64_t n, int d, const double* lam_h, int m, int iters,
+                         int* assign, double* part, double* C);
+// out = in / lambda (to_q) or in * lambda, cnt rows of d
+void launch_km_scale(hipStream_t st, const double* in, int64_t cnt, int d, const double* lam_h, bool to_q,
+                     double* out);

@@ -82,7 +82,8 @@ __global__ void k_phi_t(const double* __restrict__ P, int m, int mp, T* __restri
   out[q] = (T)v;
 }
 
-// d Sigma_m / d theta: which 0 = sigma1^2 (the correlation matrix), 1 = range
+// d Sigma_m / d theta: which 0 = sigma1^2 (the correlation matrix), 1 = the
+// length scale selected by p.dparam (the range, or an ARD length scale)
 __global__ void k_cov_zz_d(const double* Z, int m, int mp, CovParams p, int which, double* S) {
   const int a = blockIdx.y;
   for (int b = threadIdx.x; b < mp; b += blockDim.x) {
@@ -90,7 +91,7 @@ __global__ void k_cov_zz_d(const double* Z, int m, int mp, CovParams p, int whic
     if (a < m && b < m) {
       const double t2 = scaled_sqdist<double>(p, Z + (size_t)a * p.d, Z + (size_t)b * p.d);
       if (which == 0) v = cov_profile<double>(p.kernel, t2);
-      else if (a != b) v = p.sigma1_sq * cov_profile_dls<double>(p.kernel, t2, p.inv_ls[0]);
+      else if (a != b) v = cov_dlength<double>(p, Z + (size_t)a * p.d, Z + (size_t)b * p.d, t2);
     }
     S[(size_t)a * mp + b] = v;
   }
@@ -269,6 +270,48 @@ __global__ void k_sum_cols(const double* __restrict__ part, int nb, int cols, do
   }
 }
 
+// Forward-mode derivative of the Gaussian NLL (Sec. 2.2; the whitened form
+// n/2 log 2pi + (log det M' + sum log D)/2 + (yt.yt - yt^T U M'^{-1} U^T yt)/2)
+// along one parameter, per point, from the factor tangents dA, dD, dU:
+//   dD_i / (2 D_i) + Ut_i . dU_i + e_i dyt_i - e_i (dU_i . w),
+// Ut = U M'^{-1}, w = M'^{-1} U^T yt, e = yt - U w,
+// dyt_i = -(sum_j dA_ij y_{N(i)_j}) / sqrt(D_i) - yt_i dD_i / (2 D_i)
+// (d log det M' = 2 tr(M'^{-1} U^T dU); the quadratic part's derivative is
+// e . dyt - e^T dU w). One wave per point; per-block partial sums.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gauss_fwd_terms(const T* __restrict__ Ut, const T* __restrict__ dU,
+                                                         const double* __restrict__ w, const double* __restrict__ e,
+                                                         const T* __restrict__ dA, const int32_t* __restrict__ nbr,
+                                                         const double* __restrict__ y, const double* __restrict__ D,
+                                                         const double* __restrict__ yt, const double* __restrict__ dD,
+                                                         int64_t n, int mp, int mv, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  double v = 0.0;
+  if (i < n) {
+    double s1 = 0.0, s2 = 0.0, sy = 0.0;
+    for (int l = lane; l < mp; l += 64) {
+      const double du = (double)dU[(size_t)i * mp + l];
+      s1 += (double)Ut[(size_t)i * mp + l] * du;
+      s2 += du * w[l];
+    }
+    if (lane < mv) {
+      const int j = nbr[i * mv + lane];
+      if (j >= 0) sy = (double)dA[i * mv + lane] * y[j];
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    sy = wave_sum(sy);
+    const double hd = 0.5 * dD[i] / D[i];
+    const double dyt = -sy / sqrt(D[i]) - yt[i] * hd;
+    v = hd + s1 + e[i] * (dyt - s2);
+  }
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // ---------------------------------------------------------------------------
 static inline dim3 gN(int64_t n, int per = 256) { return dim3((unsigned)ceil_div(n, per)); }
 
@@ -284,6 +327,15 @@ void launch_rowmm(hipStream_t st, const T* A, const T* M, const T* Cadd, double 
 template <typename T>
 void launch_phi_t(hipStream_t st, const double* P, int m, int mp, T* out) {
   hipLaunchKernelGGL((k_phi_t<T>), gN((int64_t)mp * mp), dim3(256), 0, st, P, m, mp, out);
+}
+template <typename T>
+int launch_gauss_fwd_terms(hipStream_t st, const T* Ut, const T* dU, const double* w, const double* e, const T* dA,
+                           const int32_t* nbr, const double* y, const double* D, const double* yt, const double* dD,
+                           int64_t n, int mp, int mv, double* part) {
+  const int nb = (int)ceil_div(n, 4);
+  hipLaunchKernelGGL((k_gauss_fwd_terms<T>), dim3(nb), dim3(256), 0, st, Ut, dU, w, e, dA, nbr, y, D, yt, dD, n, mp,
+                     mv, part);
+  return nb;
 }
 void launch_cov_zz_d(hipStream_t st, const double* Z, int m, int mp, const CovParams& p, int which, double* S) {
   hipLaunchKernelGGL(k_cov_zz_d, dim3(1, mp), dim3(256), 0, st, Z, m, mp, p, which, S);
@@ -334,6 +386,9 @@ void launch_sum_cols(hipStream_t st, const double* part, int nb, int cols, doubl
 #define INST(T)                                                                                                    \
   template void launch_rowmm<T>(hipStream_t, const T*, const T*, const T*, double, double, int64_t, int, T*);     \
   template void launch_phi_t<T>(hipStream_t, const double*, int, int, T*);                                        \
+  template int launch_gauss_fwd_terms<T>(hipStream_t, const T*, const T*, const double*, const double*, const T*,  \
+                                         const int32_t*, const double*, const double*, const double*,            \
+                                         const double*, int64_t, int, int, double*);                              \
   template void launch_rowvec<T>(hipStream_t, const T*, const double*, int64_t, int, double*);                    \
   template void launch_rowdot<T>(hipStream_t, const T*, const T*, int64_t, int, double*);                         \
   template void launch_dbx<T>(hipStream_t, const T*, const int32_t*, const double*, int64_t, int, double*);       \

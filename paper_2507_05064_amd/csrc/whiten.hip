@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_whiten(const double* __restrict__ X, co
       double b = 0.0;
       if (j < m && pvalid) {
         const double t2 = scaled_sqdist<double>(p, Z + (size_t)j * p.d, xp);
-        b = DERIV ? p.sigma1_sq * cov_profile_dls<double>(p.kernel, t2, p.inv_ls[0])
+        b = DERIV ? cov_dlength<double>(p, Z + (size_t)j * p.d, xp, t2)
                   : p.sigma1_sq * cov_profile<double>(p.kernel, t2);
       }
       bv[q] = b;

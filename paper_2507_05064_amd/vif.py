@@ -71,7 +71,7 @@ EXPORTS = ["vif_create", "vif_destroy", "vif_last_error", "vif_select_neighbors"
            "vif_mlp_forward", "vif_mlp_backward", "vif_mlp_adam", "vif_mlp_features", "vif_sample_prior",
            "vif_precond_solve", "vif_set_preconditioner", "vif_batch_create", "vif_batch_destroy", "vif_batch_last_error",
            "vif_batch_nll_grad", "vif_laplace_nll", "vif_laplace_nll_grad", "vif_select_neighbors_pred",
-           "vif_predict", "vif_laplace_predict", "vif_mlp_forward_noalloc"]
+           "vif_predict", "vif_laplace_predict", "vif_mlp_forward_noalloc", "vif_select_inducing"]
 
 
 def load_library(path: Optional[str] = None):
@@ -118,6 +118,8 @@ def load_library(path: Optional[str] = None):
     lib.vif_laplace_nll.restype = ctypes.c_int
     lib.vif_laplace_nll_grad.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, dp, dp]
     lib.vif_laplace_nll_grad.restype = ctypes.c_int
+    lib.vif_select_inducing.argtypes = [vp, vp, dp, dp, vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.vif_select_inducing.restype = ctypes.c_int
     lib.vif_select_neighbors_pred.argtypes = [vp, vp, ctypes.c_int64, vp]
     lib.vif_select_neighbors_pred.restype = ctypes.c_int
     lib.vif_predict.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp]
@@ -191,6 +193,7 @@ class VifContext:
             raise VifError(rc, "vif_create failed")
         self.h = h
         self.n, self.d, self.m, self.m_v = n, d, m, m_v
+        self.n_theta = (d if kernel == "gaussian_ard" else 1) + 2
 
     def close(self):
         if getattr(self, "h", None):
@@ -276,14 +279,27 @@ class VifContext:
 
     def laplace_nll_grad(self, y: torch.Tensor, mode: torch.Tensor, eps_n: torch.Tensor,
                          eps_m: Optional[torch.Tensor]):
-        """(NLL, gradient w.r.t. (sigma1^2, range, s2)) with ell = eps_n.shape[0] // 2 probes."""
+        """(NLL, gradient w.r.t. theta = (sigma1^2, length scale(s), s2)) with
+        ell = eps_n.shape[0] // 2 probes."""
         ell = eps_n.shape[0] // 2
         nll = ctypes.c_double()
-        g = np.zeros(3)
+        g = np.zeros(self.n_theta)
         self._check(self.lib.vif_laplace_nll_grad(self.h, _ptr(y), _ptr(mode), ell, _ptr(eps_n),
                                                   _ptr(eps_m) if self.m else None, ctypes.byref(nll),
                                                   g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return nll.value, g
+
+    def select_inducing(self, X: torch.Tensor, theta, unif=None, Z_init: Optional[torch.Tensor] = None,
+                        lloyd_iters: int = 10, return_seed: bool = False):
+        """k-means++ inducing points in the transformed space q(s) = s / lambda
+        (vif_select_inducing): D^2 seeding with the given uniforms (m values),
+        or Lloyd iterations from Z_init."""
+        Z = torch.empty((self.m, self.d), dtype=torch.float64, device="cuda")
+        th, thp = _dbl_array(theta)
+        ua, up = _dbl_array(unif) if unif is not None else (None, None)
+        idx = (ctypes.c_int32 * self.m)()
+        self._check(self.lib.vif_select_inducing(self.h, _ptr(X), thp, up, _ptr(Z_init), lloyd_iters, _ptr(Z), idx))
+        return (Z, np.array(idx[:], dtype=np.int64)) if return_seed else Z
 
     def select_neighbors_pred(self, Xp: torch.Tensor) -> torch.Tensor:
         nbrp = torch.full((Xp.shape[0], max(self.m_v, 1)), -1, dtype=torch.int32, device="cuda")

@@ -19,6 +19,7 @@ class _OracleCtx:
         self.theta = None
         self.nbr = None
         self.selected_at = []  # iteration counts seen by select_neighbors calls
+        self.inducing_at = []  # (theta, previous points) of select_inducing calls
         self.iter_hint = 0
 
     def select_neighbors(self, X, Z, theta):
@@ -27,12 +28,21 @@ class _OracleCtx:
         return vo.neighbours(model, X, vo.inducing(model, X, Z), self.m_v)
 
     def build_factor(self, X, Z, nbr, theta):
-        self.theta, self.nbr = np.array(theta, float), nbr
+        self.theta, self.nbr, self.Zb = np.array(theta, float), nbr, Z
 
     def nll_grad(self, y, k):
         model = vo.Model.from_theta(self.w.kernel, self.theta, self.w.tau_m)
-        nll, g = vo.nll_gaussian_grad(model, self.X, self.Z, self.nbr, y)
+        nll, g = vo.nll_gaussian_grad(model, self.X, self.Zb, self.nbr, y)
         return nll, np.asarray(g)
+
+    @property
+    def m(self):
+        return self.Z.shape[0]
+
+    def select_inducing(self, X, theta, Z_init=None, lloyd_iters=10):
+        from oracle import inducing_oracle as io
+        self.inducing_at.append((np.array(theta, float), np.array(Z_init)))
+        return io.select_inducing(X, np.asarray(theta[1:-1]), self.m, None, lloyd_iters, Z_init=Z_init)
 
 
 def _setup(n=300):
@@ -77,3 +87,27 @@ def test_reselection_schedule_and_final_check():
     ctx.build_factor(X, Z, nbr0, theta0)
     assert res["nll"] < ctx.nll_grad(y, 3)[0]
     assert np.max(np.abs(res["grad_log_theta"])) <= 1e-3
+
+
+def test_inducing_points_move_with_the_length_scales():
+    """With inducing_iters set, the inducing points are re-selected (Lloyd
+    iterations from the current points, in the space of the current length
+    scales) at the same iterations as the neighbours, each re-selection
+    starting from the previous one's points; the neighbours are then chosen
+    with the new points, and the result carries the final points."""
+    from paper_2507_05064_amd.estimate import estimate_gaussian
+    g = np.random.default_rng(7)
+    n, d = 260, 2
+    w = vi.Workload("ard est", 18, n, d, 12, 5, vo.GAUSSIAN_ARD, 1.0, np.array([0.2, 0.4]), 0.05, 1e-8, vi.GAUSSIAN,
+                    "subset")
+    X = g.uniform(size=(n, d))
+    Z = X[:12].copy()
+    y = g.standard_normal(n)
+    ctx = _OracleCtx(w, X, Z, y)
+    theta0 = np.array([1.2, 0.3, 0.25, 0.08])
+    res = estimate_gaussian(ctx, X, Z, y, theta0, reselect=True, inducing_iters=3, maxiter=12)
+    assert res["inducing_reselections"] == len(ctx.inducing_at) >= 2
+    assert res["reselections"] == len(ctx.selected_at)
+    # each re-selection starts from the previous one's points
+    np.testing.assert_array_equal(ctx.inducing_at[0][1], Z)
+    assert np.max(np.abs(res["Z"] - Z)) > 0

@@ -1,0 +1,92 @@
+"""Gradients with the ARD Gaussian kernel (Sec. 6, eq. cov_trans_iso: one
+length scale per input dimension), theta = (sigma1^2, lambda_1..lambda_d, s2):
+
+  * the Gaussian NLL gradient (forward-mode tangents of eq. D_A_Vecchia on
+    the GPU) against the oracle's forward-mode gradient at a perturbed theta:
+    FP64 NLL 1e-10 relative and gradient 1e-8 of max|g|; FP32 NLL 1e-5 of the
+    magnitude of the NLL's terms and gradient 1e-3 of max|g|; including a
+    case with m_p > 208 (blocked m x m factorisations);
+  * the Laplace NLL gradient (App. B, STE with control variates, App. D)
+    against the oracle's estimator on the same probes: FP64 within 1e-6 of
+    max|g| (both sides' CG to 1e-11), the NLL within 1e-8 relative.
+The oracle's gradient is itself pinned to central differences for the ARD
+kernel (tests/test_oracle_pins.py)."""
+import numpy as np
+import pytest
+from scipy.special import expit
+
+import vif_inputs as vi
+from oracle import laplace_oracle as lo
+from oracle import vif_oracle as vo
+from tests import dense_ref as dr
+from tests.gpu_util import nbr_to_dev, nll_sum_magnitude, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,d,m,mv,prec", [(1200, 3, 30, 10, "fp64"), (1200, 3, 30, 10, "fp32"),
+                                           (2000, 5, 257, 12, "fp64"), (600, 2, 0, 8, "fp64")])
+def test_gaussian_ard_gradient_matches_oracle(n, d, m, mv, prec):
+    from paper_2507_05064_amd.vif import VifContext
+    ls = np.linspace(0.2, 0.6, d)
+    w = vi.Workload("ard grad", 16, n, d, m, mv, vo.GAUSSIAN_ARD, 1.0, ls, 0.05, 1e-8, vi.GAUSSIAN,
+                    "kmeanspp" if m else "subset")
+    X = vi.coords(w)
+    Z = vi.inducing_points(w, X) if m else np.zeros((0, d))
+    theta = np.concatenate([[1.3], 0.8 * ls, [0.075]])
+    model = vo.Model.from_theta(vo.GAUSSIAN_ARD, theta, w.tau_m)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, mv)
+    y = np.linalg.cholesky(dr.exact_cov(vo.Model.from_theta(vo.GAUSSIAN_ARD, w.theta, w.tau_m), X)) @ \
+        np.random.default_rng(n + d).standard_normal(n)
+    nll_o, g_o = vo.nll_gaussian_grad(model, X, Z, nbr, y)
+    print(f"[gpu] ARD gradient n={n} d={d} m={m} m_v={mv} {prec}", flush=True)
+    ctx = VifContext(n, d, m, mv, kernel="gaussian_ard", precision=prec, tau_m=w.tau_m)
+    ctx.build_factor(to_dev(X), to_dev(Z) if m else None, nbr_to_dev(nbr), theta)
+    nll_g, g_g = ctx.nll_grad(to_dev(y), d + 2)
+    en = abs(nll_g - nll_o)
+    eg = np.max(np.abs(g_g - g_o)) / np.max(np.abs(g_o))
+    print(f"[gpu]   NLL err {en / abs(nll_o):.3e} relative, grad err {eg:.3e}", flush=True)
+    if prec == "fp64":
+        assert en <= 1e-10 * abs(nll_o) and eg <= 1e-8, (nll_g, nll_o, g_g, g_o)
+    else:
+        assert en <= 1e-5 * nll_sum_magnitude(model, X, Z, nbr, y) and eg <= 1e-3, (nll_g, nll_o, g_g, g_o)
+    # every length scale matters: the gradient differs across dimensions
+    assert len(set(np.round(g_o[1:-1], 6))) == d
+
+
+def test_laplace_ard_gradient_matches_oracle():
+    from paper_2507_05064_amd.vif import VifContext
+    n, d, m, mv, ell = 800, 3, 20, 8, 4
+    ls = np.array([0.2, 0.35, 0.5])
+    w = vi.Workload("ard lap grad", 17, n, d, m, mv, vo.GAUSSIAN_ARD, 1.0, ls, 1e-4, 1e-8, lo.BERNOULLI_LOGIT,
+                    "kmeanspp")
+    X = vi.coords(w)
+    Z = vi.inducing_points(w, X)
+    model = vo.Model(vo.GAUSSIAN_ARD, 1.0, ls, w.s2, w.tau_m)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, mv)
+    prior = lo.LatentVIF.build(model, X, Z, nbr)
+    eps1, eps2, u = vi.prior_noise(w)
+    b = np.linalg.cholesky(lo.dense_cov(prior)) @ eps2
+    y = vi.bernoulli_from_uniform(expit(b), u)
+    mode = lo.find_mode(prior, lo.BERNOULLI_LOGIT, y, tol=1e-14, solver="dense").mode
+    tg = vo.factor_tangents(model, X, Z, ind, nbr, prior.fac)
+    W = lo.grad_hess(lo.BERNOULLI_LOGIT, y, mode)[1]
+    g = np.random.default_rng(n + 9)
+    e1, e2, e3 = g.standard_normal((n, ell)), g.standard_normal((n, ell)), g.standard_normal((m, ell))
+    Zp = lo.vifdu_probes(prior, W, e1, e2, e3)
+    slq = lo.laplace_nll_slq(prior, lo.BERNOULLI_LOGIT, y, mode, Zp, tol=1e-11)
+    ref = lo.laplace_grad_ste(prior, tg, lo.BERNOULLI_LOGIT, y, mode, slq, tol=1e-11)
+    print(f"[gpu] Laplace ARD gradient n={n} d={d} m={m} m_v={mv} ell={ell}", flush=True)
+    ctx = VifContext(n, d, m, mv, kernel="gaussian_ard", likelihood=lo.BERNOULLI_LOGIT, precision="fp64",
+                     tau_m=w.tau_m, cg_tol=1e-11, cg_maxit=3000, max_probes=ell)
+    ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), model.theta)
+    eps_n = np.empty((2 * ell, n))
+    eps_n[0::2], eps_n[1::2] = e1.T, e2.T
+    nll, grad = ctx.laplace_nll_grad(to_dev(y), to_dev(mode), to_dev(eps_n), to_dev(e3.T))
+    eg = np.max(np.abs(grad - ref)) / np.max(np.abs(ref))
+    print(f"[gpu]   nll err {abs(nll - slq.nll) / abs(slq.nll):.3e} grad err {eg:.3e}", flush=True)
+    assert grad.shape == (d + 2,)
+    assert abs(nll - slq.nll) <= 1e-8 * abs(slq.nll), (nll, slq.nll)
+    assert eg <= 1e-6, (grad, ref)
