@@ -43,12 +43,34 @@ def factor_bytes_per_point(m: int, mv: int, d: int, tsize: int) -> int:
     return (mv + 1) * m * tsize + mv * 4 + (mv + 1) * d * 8 + m * tsize + mv * tsize + 8
 
 
-def measured_traffic():
-    """HBM bytes per launch of the factor kernel from the committed counter
-    summary, if it was taken on the current kernel source (else None)."""
+def factor_bwd_bytes_per_point(m: int, mv: int, d: int, tsize: int) -> int:
+    """Algorithmic HBM bytes of the adjoint factor kernel for one point: gather
+    the (m_v + 1) rows of V and of V_rho (the range derivative of V), read the
+    point's U and Ubar rows, the neighbour indices, the m_v + 1 coordinates,
+    the m_v responses of the neighbours and e_i, yt_i, D_i; write the three
+    coefficient rows (S + G, sqrt(D) G, sqrt(D) beta) and three gradient
+    partials."""
+    return (2 * (mv + 1) * m * tsize + 2 * m * tsize + mv * 4 + (mv + 1) * d * 8 + mv * 8 + 24
+            + 3 * m * tsize + 24)
+
+
+def pcg_iter_bytes(n: int, m: int, mv: int) -> int:
+    """Algorithmic HBM bytes of one VIFDU-preconditioned CG iteration (FP64):
+    the operator (W + Sigma_dagger^{-1}) p passes over U twice (U^T t, U c) and
+    over the sparse factor twice (B w, B^T s); the preconditioner passes over U
+    twice (U^T q, U c) and over the factor twice (B^{-T}, B^{-1}); a pass over
+    the factor reads m_v coefficients (8 B) and indices (4 B) per row; 41
+    n-vector reads and writes of the recurrences and diagonal scalings."""
+    return 4 * n * m * 8 + 4 * n * mv * 12 + 41 * n * 8
+
+
+def measured_traffic(kernel: str = "k_factor"):
+    """HBM bytes per launch of `kernel` (k_factor or k_factor_bwd, FP32, C2)
+    from the committed counter summary, if it was taken on the current kernel
+    source (else None)."""
     import hashlib
     try:
-        txt = open(os.path.join(ROOT, "profiles", "k_factor_fp32_c2_pmc.md")).read()
+        txt = open(os.path.join(ROOT, "profiles", f"{kernel}_fp32_c2_pmc.md")).read()
         src = open(os.path.join(ROOT, "paper_2507_05064_amd", "csrc", "factor.hip"), "rb").read()
     except OSError:
         return None
@@ -219,6 +241,16 @@ def laplace_leg(reps, warmup, log):
                      "pcg_iters": st["pcg_iters"], "halvings": st["halvings"], "start_used": st["start_used"],
                      "psi": st["psi"], "levels_fwd": st["levels_fwd"], "levels_bwd": st["levels_bwd"],
                      "wide_fwd": st["wide_fwd"], "wide_bwd": st["wide_bwd"]}
+        if form.endswith("zero"):
+            # one more solve with per-stage HIP events (outside the timed
+            # reps: the events synchronise at the end of every PCG solve)
+            ctx.set_timing(True)
+            _, st_t, _ = ctx.laplace_mode(prob.y)
+            tm = ctx.timing()
+            ctx.set_timing(False)
+            pcg_ms, _ = tm["laplace_pcg"]
+            out[form]["pcg_ms_total"] = pcg_ms
+            out[form]["pcg_ms_per_iter"] = pcg_ms / max(st_t["pcg_iters_total"], 1)
         log(f"laplace {form}: {out[form]}")
     b0 = mlp.forward(ctx.mlp_features(prob.y), double=True)
     ref = modes["zero"]
@@ -228,6 +260,14 @@ def laplace_leg(reps, warmup, log):
     out["fitc_mode_rel_diff_vs_vifdu"] = float(torch.linalg.norm(modes["fitc_zero"] - ref) / torch.linalg.norm(ref))
     out["fitc_speedup_warm_vs_zero"] = out["fitc_zero"]["mode_ms_median"] / out["fitc_warm"]["mode_ms_median"]
     out["factor_build_ms_median"] = _pct(build_ms, 50)
+    it_bytes = pcg_iter_bytes(w.n, w.m, w.m_v)
+    it_ms = out["zero"]["pcg_ms_per_iter"]
+    ach = it_bytes / (it_ms * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": "one VIFDU-preconditioned CG iteration (all its kernels)",
+                       "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                       "traffic": None, "bytes_per_iter": it_bytes, "ms_per_iter": it_ms,
+                       "timing": "HIP events around each Newton step's CG solve on the library stream, "
+                                 "summed over one mode solve from zero, divided by its CG iterations"}
     out["mlp_train_s"] = train_s
     # latent prediction at the mode (Prop. 3.1): omega_p and diag(Omega_p) by
     # Alg. 1 with 10 samples at 50000 seeded uniform points
@@ -377,18 +417,9 @@ def c5_leg(reps, log, ell=50):
     return res
 
 
-def cpu_baseline(w, budget_points=6000):
-    """Oracle (FP64 numpy) NLL + forward-mode gradient on the first
-    `budget_points` points of the same workload (the prefix is itself a VIF
-    problem: its conditioning sets only reach earlier points), scaled by
-    n / budget_points to evaluations per second at full n."""
+def _oracle_c2_seconds(w, budget_points):
     from oracle import vif_oracle as vo
     import vif_inputs as vi
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
     X = vi.coords(w)[:budget_points]
     Z = vi.inducing_points(w, vi.coords(w))
     model = vo.Model(w.kernel, w.sigma1_sq, np.asarray(w.lengthscales, float), w.s2, w.tau_m)
@@ -397,17 +428,74 @@ def cpu_baseline(w, budget_points=6000):
     y = vi.normals(w, budget_points, stream=vi.STREAM_NOISE) * math.sqrt(w.sigma1_sq + w.s2)
     t0 = time.perf_counter()
     vo.nll_gaussian_grad(model, X, Z, nbr, y)
-    sec = time.perf_counter() - t0
-    sec_full = sec * w.n / budget_points
-    return {"value": 1.0 / sec_full, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+    return time.perf_counter() - t0
+
+
+def _oracle_c3_mode(n0):
+    """The oracle's Laplace mode (Newton with Jacobi-preconditioned CG) on a
+    C3-shaped problem of n0 points: inputs of C3's distribution, m = 500
+    k-means++ inducing points, m_v = 30, b from the latent VIF prior,
+    Bernoulli responses, Newton tolerance 1e-9 as on the GPU."""
+    from scipy.special import expit
+    from oracle import laplace_oracle as lo
+    from oracle import vif_oracle as vo
+    import vif_inputs as vi
+    w = vi.scaled(vi.config3(), n0)
+    X = vi.coords(w)
+    Z = vi.inducing_points(w, X)
+    model = vo.Model(w.kernel, w.sigma1_sq, np.asarray(w.lengthscales, float), w.s2, w.tau_m)
+    ind = vo.inducing(model, X, Z)
+    nbr = vo.neighbours(model, X, ind, w.m_v)
+    prior = lo.LatentVIF.build(model, X, Z, nbr)
+    eps1, eps2, u = vi.prior_noise(w)
+    b = vo.prior_sample(nbr, prior.fac, ind, eps1, eps2)
+    y = vi.bernoulli_from_uniform(expit(b), u)
+
+    def run():
+        t0 = time.perf_counter()
+        r = lo.find_mode(prior, lo.BERNOULLI_LOGIT, y, tol=1e-9, solver="cg")
+        return time.perf_counter() - t0, r.iters
+
+    return run
+
+
+def cpu_baseline(w, budget_points=6000, c3_points=1500):
+    """The oracle (FP64 numpy/scipy) on the host cores, with numpy's BLAS
+    threads and with one thread:
+      * C2: NLL + forward-mode gradient on the first `budget_points` points of
+        the same workload (the prefix is itself a VIF problem: its
+        conditioning sets only reach earlier points), scaled by
+        n / budget_points to evaluations per second at full n;
+      * C3: the oracle's Laplace mode on a C3-shaped problem of `c3_points`
+        points (not scaled: its CG iteration counts depend on n)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    sec = _oracle_c2_seconds(w, budget_points)
+    with threadpool_limits(1):
+        sec1 = _oracle_c2_seconds(w, budget_points)
+    run = _oracle_c3_mode(c3_points)
+    c3_sec, c3_it = run()
+    with threadpool_limits(1):
+        c3_sec1, _ = run()
+    scale = w.n / budget_points
+    return {"value": 1.0 / (sec * scale), "unit": "evals/s", "cores": int(threads), "kind": "oracle",
             "sample": f"NLL + forward-mode gradient on the first {budget_points} of {w.n} points "
-                      f"({sec:.1f} s), scaled linearly to n={w.n}"}
+                      f"({sec:.1f} s), scaled linearly to n={w.n}",
+            "single_thread": {"value": 1.0 / (sec1 * scale), "unit": "evals/s", "cores": 1,
+                              "sample": f"the same with one BLAS thread ({sec1:.1f} s)"},
+            "c3_mode": {"seconds": c3_sec, "seconds_one_thread": c3_sec1, "newton_iters": int(c3_it),
+                        "cores": int(threads), "n": c3_points,
+                        "sample": f"oracle Laplace mode (Newton, Jacobi-preconditioned CG to 1e-12, Newton "
+                                  f"tolerance 1e-9) on a C3-shaped problem of {c3_points} points (d=5 ARD "
+                                  f"Gaussian, m=500 k-means++ inducing points, m_v=30, Bernoulli-logit); "
+                                  f"not scaled to n=200000"}}
 
 
 def counters_mode(w):
-    """Workload for `rocprofv3 --pmc`: the factor kernel at C2 (FP32) and a
-    plain device copy of 1 GiB, whose FETCH_SIZE / WRITE_SIZE readings give
-    the counters' scale against known bytes."""
+    """Workload for `rocprofv3 --pmc`: five factor builds and NLL + gradient
+    evaluations at C2 (FP32), then five plain device copies of 1 GiB, whose
+    FETCH_SIZE / WRITE_SIZE readings give the counters' scale against known
+    bytes."""
     import torch
     import vif_inputs as vi
     from paper_2507_05064_amd.vif import VifContext
@@ -416,14 +504,17 @@ def counters_mode(w):
     Xd, Zd = torch.as_tensor(X, device="cuda"), torch.as_tensor(Z, device="cuda")
     ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, precision="fp32", tau_m=w.tau_m)
     nbr = ctx.select_neighbors(Xd, Zd, w.theta)
+    y = torch.as_tensor(vi.normals(w, w.n, stream=vi.STREAM_NOISE) * math.sqrt(w.sigma1_sq + w.s2), device="cuda")
     for _ in range(5):
         ctx.build_factor(Xd, Zd, nbr, w.theta)
+        ctx.nll_grad(y, w.theta.size)
     a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)  # 1 GiB
     b = torch.empty_like(a)
     for _ in range(5):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"factor_bytes_per_launch": w.n * factor_bytes_per_point(w.m, w.m_v, w.d, 4),
+                      "factor_bwd_bytes_per_launch": w.n * factor_bwd_bytes_per_point(w.m, w.m_v, w.d, 4),
                       "copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8}))
 
 
@@ -440,6 +531,8 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="hardware-counter mode: 5 FP32 factor builds of the C2 workload and 5 copies of a 1 GiB "
                          "buffer (the counters' scale reference), nothing timed")
+    ap.add_argument("--c2-only", action="store_true",
+                    help="only the n = 100k NLL + gradient step in its three forms (for kernel traces and counters)")
     ap.add_argument("--c5", action="store_true",
                     help="also run the n = 1M Poisson leg (Laplace NLL + gradient; a few minutes of set-up)")
     args = ap.parse_args()
@@ -482,6 +575,12 @@ def main():
     fac_ms = r32["stages"].get("factor", float("nan"))
     nbytes = w.n * factor_bytes_per_point(w.m, w.m_v, w.d, 4)
     achieved = nbytes / (fac_ms * 1e-3) / 1e9
+    bwd_ms = r32["stages"].get("grad_factor_bwd", float("nan"))
+    bwd_bytes = w.n * factor_bwd_bytes_per_point(w.m, w.m_v, w.d, 4)
+    bwd_achieved = bwd_bytes / (bwd_ms * 1e-3) / 1e9
+    nll_rel16 = abs(r16["nll"] - r64["nll"]) / abs(r64["nll"])
+    grad_err16 = (None if r16["grad"] is None else
+                  float(np.max(np.abs(np.subtract(r16["grad"], r64["grad"]))) / np.max(np.abs(r64["grad"]))))
     res = {
         "metric": METRIC,
         "value": 1000.0 / r32["ms_per_step"],
@@ -506,18 +605,27 @@ def main():
         "fp32_rel_err_vs_fp64_gpu": abs(r32["nll"] - r64["nll"]) / abs(r64["nll"]),
         "bf16_in": {"value": 1000.0 / r16["ms_per_step"], "unit": "evals/s", "ms_per_step": r16["ms_per_step"],
                     "nll": r16["nll"], "grad": r16["grad"],
-                    "nll_rel_err_vs_fp64_gpu": abs(r16["nll"] - r64["nll"]) / abs(r64["nll"]),
+                    "nll_rel_err_vs_fp64_gpu": nll_rel16,
                     "nll_err_per_point_vs_fp64_gpu": abs(r16["nll"] - r64["nll"]) / w.n,
-                    "grad_err_vs_fp64_gpu": (None if r16["grad"] is None else
-                                             float(np.max(np.abs(np.subtract(r16["grad"], r64["grad"])))
-                                                   / np.max(np.abs(r64["grad"])))),
+                    "grad_err_vs_fp64_gpu": grad_err16,
+                    # the BF16-input bar: NLL within 1e-3 relative, gradient within 5e-2 of max |g|
+                    "within_bar": bool(nll_rel16 <= 1e-3 and (grad_err16 is None or grad_err16 <= 5e-2)),
                     "stage_ms": r16["stages"]},
         "stage_ms": {"fp32": r32["stages"], "fp64": r64["stages"]},
         "neighbour_search_s": knn_s,
-        "roofline": {"bound": "hbm", "kernel": "k_factor<float>", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "bytes_per_launch": nbytes, "avg_launch_ms": fac_ms},
+        # the dominant kernel of the step: the adjoint of the per-point factor
+        "roofline": {"bound": "hbm", "kernel": "k_factor_bwd<float>", "achieved": bwd_achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bwd_achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("k_factor_bwd"), "bytes_per_launch": bwd_bytes,
+                     "avg_launch_ms": bwd_ms},
+        "roofline_factor": {"bound": "hbm", "kernel": "k_factor<float>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                            "traffic": measured_traffic("k_factor"), "bytes_per_launch": nbytes,
+                            "avg_launch_ms": fac_ms},
     }
+    if args.c2_only:
+        print(json.dumps(res))
+        return
     res["predict"] = predict_leg(w, Xd, Zd, nbr, yd)
     res["estimate"] = {"fp32": estimate_leg(w, Xd, Zd, yd, "fp32"), "fp64": estimate_leg(w, Xd, Zd, yd, "fp64")}
     if not args.no_batch:

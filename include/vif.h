@@ -403,8 +403,12 @@ vif_status vif_export_factor(vif_ctx* ctx, double* A_out, double* D_out);
  * stream; the elapsed times are added up at the call's own synchronisation
  * point. vif_set_timing also clears the totals. Stage names (see
  * vif_timing_stage_name): inducing_chol, whiten, factor, woodbury_gram,
- * woodbury_chol, nll_tail, knn, and the gradient stages. ms_out / count_out
- * are host arrays of nstage entries. */
+ * woodbury_chol, nll_tail, knn, the gradient stages, laplace_mode (one per
+ * vif_laplace_mode call) and laplace_pcg (one per Newton step: its
+ * conjugate-gradient solve, added at the end of each solve; divide by the
+ * reported PCG iterations for a per-iteration time). ms_out / count_out are
+ * host arrays of nstage entries. Timing synchronises the stream at the end
+ * of every PCG solve. */
 vif_status vif_set_timing(vif_ctx* ctx, int enable);
 int vif_timing_stages(void);
 const char* vif_timing_stage_name(int stage);

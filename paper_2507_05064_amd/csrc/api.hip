@@ -15,13 +15,13 @@
 #include "kernels.h"
 
 enum Stage { ST_INDUCING = 0, ST_WHITEN, ST_FACTOR, ST_GRAM, ST_MCHOL, ST_NLL, ST_KNN, ST_GPREP, ST_UBAR,
-             ST_FBWD, ST_VBAR, ST_SGRAD, ST_WDERIV, ST_REV, ST_LAPLACE, ST_COUNT };
+             ST_FBWD, ST_VBAR, ST_SGRAD, ST_WDERIV, ST_REV, ST_LAPLACE, ST_PCG, ST_COUNT };
 static constexpr int kBlkVecs = 16;  // n x L vectors of the many-right-hand-side workspace
 
 static const char* kStageNames[ST_COUNT] = {
     "inducing_chol", "whiten", "factor", "woodbury_gram", "woodbury_chol", "nll_tail", "knn", "grad_prep",
     "grad_ubar_gemm", "grad_factor_bwd", "grad_vbar", "grad_sigma_m", "grad_whiten_deriv", "reverse_lists",
-    "laplace_mode"};
+    "laplace_mode", "laplace_pcg"};
 
 struct StageTimer {
   hipEvent_t b = nullptr, e = nullptr;
@@ -155,6 +155,14 @@ static void stage_end(vif_ctx* c, int s) {
     hipEventRecord(c->timers[s].e, c->st);
     c->timers[s].pending = true;
   }
+}
+// Ends a stage that can run several times per call: waits for its end event
+// and adds its time at once.
+static void harvest(vif_ctx* c);
+static void stage_end_sync(vif_ctx* c, int s) {
+  if (!c->timing) return;
+  stage_end(c, s);
+  if (hipEventSynchronize(c->timers[s].e) == hipSuccess) harvest(c);
 }
 // After a stream synchronisation: add the elapsed time of every recorded stage.
 static void harvest(vif_ctx* c) {
@@ -1390,11 +1398,14 @@ static vif_status laplace_impl(vif_ctx* c, const double* y, const double* b0, do
     double rel = 0.0;
     if (c->precond == VIF_PRECOND_FITC) {
       build_fitc<T>(c, B);
+      stage_begin(c, ST_PCG);
       s = pcg_fitc<T>(c, B, &its, &rel);
     } else {
       build_vifdu(c, B);
+      stage_begin(c, ST_PCG);
       s = pcg<T>(c, B, &its, &rel);
     }
+    stage_end_sync(c, ST_PCG);
     if (t <= 64) S.pcg_iters[t - 1] = its;
     S.pcg_iters_total += its;
     S.pcg_rel_residual = rel;
