@@ -600,3 +600,93 @@ def laplace_grad_ste(prior: LatentVIF, tangents, lik: str, y: np.ndarray, mode: 
         val = 0.5 * mode @ dPrec @ mode + 0.5 * (np.trace(Si @ dS) + that) - v @ dPrec @ mode
         out.append(val)
     return np.array(out)
+
+
+# ----------------------------------------------------------------------------
+# The gradient with the FITC preconditioner on the system of eq. pcls2
+# (App. D, second form of the trace estimate; the preconditioner's
+# log-determinant derivatives of App. E.2)
+# ----------------------------------------------------------------------------
+
+def fitc_diag_slope(model: vo.Model, p: int, n_params: int) -> float:
+    """d(sigma1^2 + s2)/dtheta_p: the diagonal of the covariance the FITC
+    preconditioner uses depends on sigma1^2 (p = 0) and s2 (the last)."""
+    return 1.0 if p in (0, n_params - 1) else 0.0
+
+
+def fitc_tangent_dense(model: vo.Model, prior: LatentVIF, tg: vo.FactorTangent, dsig: float) -> np.ndarray:
+    """dP/dtheta_p for P = D_V + Q, Q = Sigma_mn^T Sigma_m^{-1} Sigma_mn and
+    D_V = diag(sigma1^2 + s2 - Q_ii) + W^{-1} (App. E.2), W held fixed:
+    dP = dsig I - diag(dQ) + dQ."""
+    n = prior.n
+    dQ = np.zeros((n, n))
+    if prior.ind.m:
+        Wm = prior.ind.W
+        dQ = tg.dSmn.T @ Wm + Wm.T @ tg.dSmn - Wm.T @ tg.dSm @ Wm
+    return dQ + np.diag(dsig - np.diag(dQ))
+
+
+def laplace_grad_ste_fitc(model: vo.Model, prior: LatentVIF, tangents, lik: str, y: np.ndarray, mode: np.ndarray,
+                          slq: LaplaceSLQ, noise_var: float = 1.0, tol: float = 1e-10, control_variate: bool = True,
+                          psolve=None, dP_list=None, trP_list=None, pinv_diag=None) -> np.ndarray:
+    """The gradient of eq. log_det_VIFLA (App. B) with the trace estimates in
+    the form of the system of eq. pcls2, A2 = W^{-1} + Sigma_dagger, over the
+    probes of `slq` (z_k ~ N(0, P) for the FITC preconditioner P, u_k =
+    A2^{-1} z_k, q_k = P^{-1} z_k, as laplace_nll_slq_fitc leaves them):
+      d log det(Sigma W + I)/dtheta_p (W fixed) = tr(A2^{-1} dSigma)
+        ~ mean_k [u_k^T dSigma q_k - c q_k^T dP q_k] + c tr(P^{-1} dP),
+      c the variance-minimising control-variate coefficient (App. D);
+      dL/db_i = 1/2 dW_i [(W + Sigma^{-1})^{-1}]_ii
+              = 1/2 (dW_i / W_i - dW_i (A2^{-1})_ii / W_i^2),
+      (A2^{-1})_ii ~ mean_k u_k,i q_k,i with the control variate q_k,i^2
+      (mean diag(P^{-1})), one pooled coefficient;
+      v = (W + Sigma^{-1})^{-1} dL/db = W^{-1} x - W^{-1} A2^{-1} W^{-1} x, x = dL/db;
+      grad_p = 1/2 b^T dSigma^{-1} b + 1/2 tr(A2^{-1} dSigma) - v^T dSigma^{-1} b,
+    with dSigma^{-1} = -Sigma^{-1} dSigma Sigma^{-1}. psolve, dP_list (dense dP
+    per parameter), trP_list and pinv_diag (diag P^{-1}) replace the FITC
+    preconditioner's (e.g. by the exact A2, for which the estimates are exact)."""
+    _, W, dW = grad_hess(lik, y, mode, noise_var)
+    S = dense_cov(prior)
+    A2 = np.diag(1.0 / W) + S
+    if psolve is None:
+        Pd = fitc_dense(model, prior, W)
+        Pi = np.linalg.inv(Pd)
+        psolve = lambda v: fitc_solve(model, prior, W, v)
+        pinv_diag = np.diag(Pi).copy()
+        nP = len(tangents)
+        dP_list = [fitc_tangent_dense(model, prior, tg, fitc_diag_slope(model, p, nP))
+                   for p, tg in enumerate(tangents)]
+        trP_list = [float(np.trace(Pi @ dP)) for dP in dP_list]
+    U = np.column_stack([r.x for r in slq.runs])
+    Q = np.column_stack([r.pz0 for r in slq.runs])
+    # diagonal of A2^{-1}, weighted by dW / W^2
+    wgt = dW / (W * W)
+    h = U * Q * wgt[:, None]
+    gq = Q * Q * wgt[:, None]
+    trq = wgt * pinv_diag
+    cb = 0.0
+    if control_variate:
+        dg = gq - trq[:, None]
+        den = float(np.sum(dg * dg))
+        if den > 0:
+            cb = float(np.sum((h - h.mean(1, keepdims=True)) * dg)) / den
+    dhat = np.mean(h - cb * gq, axis=1) + cb * trq
+    dLdb = 0.5 * (dW / W - dhat)
+    x = dLdb / W
+    v = x - pcg_run(lambda t: A2 @ t, psolve, x, tol).x / W
+    sb = prior.prec_matvec(mode)
+    sv = prior.prec_matvec(v)
+    out = []
+    for p, tg in enumerate(tangents):
+        dS = cov_tangent_dense(prior, tg)
+        f = np.einsum("ik,ik->k", U, dS @ Q)
+        g = np.einsum("ik,ik->k", Q, dP_list[p] @ Q)
+        trP = trP_list[p]
+        c = 0.0
+        if control_variate:
+            den = float(np.sum((g - trP) ** 2))
+            if den > 0:
+                c = float(np.sum((f - f.mean()) * (g - trP))) / den
+        that = float(np.mean(f - c * g)) + c * trP
+        out.append(-0.5 * sb @ dS @ sb + 0.5 * that + sv @ dS @ sb)
+    return np.array(out)
