@@ -39,19 +39,20 @@ HBM_PEAK_GBS = 8000.0
 def factor_bytes_per_point(m: int, mv: int, d: int, tsize: int) -> int:
     """Algorithmic HBM bytes of the per-point factor kernel for one point with
     m_v neighbours: gather (m_v + 1) rows of V, the neighbour indices and the
-    m_v + 1 coordinates; write the U row, A_i and D_i."""
-    return (mv + 1) * m * tsize + mv * 4 + (mv + 1) * d * 8 + m * tsize + mv * tsize + 8
+    m_v + 1 coordinates; write the U row, A_i, D_i and the m_v(m_v+1)/2
+    entries of the rows of L_R kept for the adjoint."""
+    return (mv + 1) * m * tsize + mv * 4 + (mv + 1) * d * 8 + m * tsize + mv * tsize + 8 + mv * (mv + 1) // 2 * tsize
 
 
 def factor_bwd_bytes_per_point(m: int, mv: int, d: int, tsize: int) -> int:
     """Algorithmic HBM bytes of the adjoint factor kernel for one point: gather
     the (m_v + 1) rows of V and of V_rho (the range derivative of V), read the
     point's U and Ubar rows, the neighbour indices, the m_v + 1 coordinates,
-    the m_v responses of the neighbours and e_i, yt_i, D_i; write the three
-    coefficient rows (S + G, sqrt(D) G, sqrt(D) beta) and three gradient
-    partials."""
+    the m_v responses of the neighbours, e_i, yt_i, D_i, A_i and the stored
+    rows of L_R; write the three coefficient rows (S + G, sqrt(D) G,
+    sqrt(D) beta) and three gradient partials."""
     return (2 * (mv + 1) * m * tsize + 2 * m * tsize + mv * 4 + (mv + 1) * d * 8 + mv * 8 + 24
-            + 3 * m * tsize + 24)
+            + mv * tsize + mv * (mv + 1) // 2 * tsize + 3 * m * tsize + 24)
 
 
 def pcg_iter_bytes(n: int, m: int, mv: int) -> int:
@@ -207,7 +208,7 @@ def laplace_leg(reps, warmup, log):
     train_s = time.perf_counter() - t0
     del feat, target
     prob = ws.make_problem(w, 0)
-    ctx = ws.context_for(prob, cg_tol=1e-6, max_pred=50_000)
+    ctx = ws.context_for(prob, cg_tol=1e-6, max_pred=50_000, max_probes=16)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     build_ms = []
     for r in range(warmup + reps):
@@ -270,7 +271,7 @@ def laplace_leg(reps, warmup, log):
                                  "summed over one mode solve from zero, divided by its CG iterations"}
     out["mlp_train_s"] = train_s
     # latent prediction at the mode (Prop. 3.1): omega_p and diag(Omega_p) by
-    # Alg. 1 with 10 samples at 50000 seeded uniform points
+    # simulation (SBPV) with 10 samples at 50000 seeded uniform points
     n_pred, ell = 50_000, 10
     Xp = torch.from_numpy(vi.coords(vi.scaled(w, n_pred), 2)).to("cuda")
     nbrp = ctx.select_neighbors_pred(Xp)
@@ -286,11 +287,42 @@ def laplace_leg(reps, warmup, log):
     out["predict_sbpv"] = {"n_pred": n_pred, "samples": ell, "seconds": time.perf_counter() - t0,
                            "cg_iters_total": its, "var_min": float(var.min()), "var_max": float(var.max())}
     log(f"laplace predict: {out['predict_sbpv']}")
+    out["slq_compare"] = slq_compare(ctx, prob, ref, log)
     out["reps"] = reps
     out["workload"] = (f"Bernoulli-logit latent VIF: n={w.n} d={w.d} ARD Gaussian (var 1, length scales "
                        f"0.2..0.6), m={w.m} kMeans++ inducing points, m_v={w.m_v}, b from the VIF prior, "
                        f"Newton + PCG (tol 1e-6) with the VIFDU (zero, warm) or FITC (fitc_*) preconditioner, FP64")
     ctx.close()
+    return out
+
+
+def slq_compare(ctx, prob, mode, log, ell=8, reps=8):
+    """The SLQ estimate of the Laplace NLL at the mode with the VIFDU (eq.
+    slq_v1) and the FITC (eq. slq_v2) preconditioner: `reps` independent
+    sets of `ell` probes, the same standard normals for both; the spread of
+    the estimates over the sets (the estimator's standard deviation) and the
+    time per NLL evaluation."""
+    import torch
+    w = prob.w
+    g = torch.Generator(device="cuda").manual_seed(17)
+    draws = [(torch.randn((2 * ell, w.n), dtype=torch.float64, device="cuda", generator=g),
+              torch.randn((ell, w.m), dtype=torch.float64, device="cuda", generator=g)) for _ in range(reps)]
+    out = {"probes": ell, "sets": reps}
+    for pre in ("vifdu", "fitc"):
+        ctx.set_preconditioner(pre)
+        vals, ms = [], []
+        for en, em in draws:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nll, _ = ctx.laplace_nll(prob.y, mode, en, em)
+            torch.cuda.synchronize()
+            ms.append(1000.0 * (time.perf_counter() - t0))
+            vals.append(nll)
+        out[pre] = {"nll_mean": float(np.mean(vals)), "nll_std": float(np.std(vals, ddof=1)),
+                    "ms_median": _pct(ms, 50)}
+    ctx.set_preconditioner("vifdu")
+    out["std_ratio_vifdu_over_fitc"] = out["vifdu"]["nll_std"] / max(out["fitc"]["nll_std"], 1e-300)
+    log(f"laplace SLQ comparison: {out}")
     return out
 
 
@@ -533,6 +565,8 @@ def main():
                          "buffer (the counters' scale reference), nothing timed")
     ap.add_argument("--c2-only", action="store_true",
                     help="only the n = 100k NLL + gradient step in its three forms (for kernel traces and counters)")
+    ap.add_argument("--laplace-only", action="store_true",
+                    help="only the n = 200k Laplace leg (for its kernel trace)")
     ap.add_argument("--c5", action="store_true",
                     help="also run the n = 1M Poisson leg (Laplace NLL + gradient; a few minutes of set-up)")
     args = ap.parse_args()
@@ -547,6 +581,10 @@ def main():
     w = vi.config2()
     if args.counters:
         counters_mode(w)
+        return
+    if args.laplace_only:
+        print(json.dumps({"laplace": laplace_leg(args.laplace_reps, 1,
+                                                 lambda msg: print(msg, file=sys.stderr, flush=True))}))
         return
     X = vi.coords(w)
     Z = vi.inducing_points(w, X)

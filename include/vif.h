@@ -226,9 +226,9 @@ vif_status vif_laplace_mode(vif_ctx* ctx, const double* y, const double* b0, dou
  * form of eq. slq_v2, sum log W + log det P + the SLQ term of
  * P^{-1/2} (W^{-1} + Sigma_dagger) P^{-1/2}, log det P = sum log D_V +
  * log det M_V, with probes z_k = D_V^{1/2} e1_k + V^T e3_k (the e2 rows of
- * eps_n are not used). vif_laplace_nll_grad always uses VIFDU (eq. slq_v1),
- * whose solves its trace estimates reuse. VIF_E_ARG for another kind; the
- * BF16-input form has no FITC. */
+ * eps_n are not used). vif_laplace_nll_grad then takes its trace estimates in
+ * the form of eq. pcls2 over the same probes (see there). VIF_E_ARG for
+ * another kind; the BF16-input form has no FITC. */
 typedef enum { VIF_PRECOND_VIFDU = 0, VIF_PRECOND_FITC = 1 } vif_precond;
 vif_status vif_set_preconditioner(vif_ctx* ctx, int32_t kind);
 
@@ -324,7 +324,18 @@ vif_status vif_laplace_nll(vif_ctx* ctx, const double* y, const double* mode, in
  * doubles in the layout of theta. 2 <= ell <= cfg.max_probes. The probe
  * solves run as one block of conjugate-gradient iterations per 64 probes
  * (each operator pass made once for the block, each probe with its own
- * coefficients and stopping rule). */
+ * coefficients and stopping rule).
+ * With VIF_PRECOND_FITC set, the NLL takes the form of eq. slq_v2 and the
+ * traces the form of eq. pcls2 (App. D, App. E.2), A2 = W^{-1} + Sigma_dagger,
+ * P the FITC preconditioner, u_k = A2^{-1} z_k, q_k = P^{-1} z_k (probes
+ * z_k = D_V^{1/2} e1_k + V^T e3_k, solved one at a time):
+ *   dL/dtheta_p = -1/2 sb^T dSigma sb + 1/2 tr(A2^{-1} dSigma) + sv^T dSigma sb,
+ *   tr(A2^{-1} dSigma) ~ mean_k [u_k^T dSigma q_k - c_p q_k^T dP q_k] + c_p tr(P^{-1} dP),
+ *   dL/db_i = 1/2 (dW_i / W_i - dW_i (A2^{-1})_ii / W_i^2), (A2^{-1})_ii by the
+ *   same probes with the control variate q_k,i^2 (mean diag(P^{-1})),
+ * sb = Sigma_dagger^{-1} b, sv = Sigma_dagger^{-1} v, v = (W + Sigma_dagger^{-1})^{-1}
+ * dL/db by one FITC-preconditioned CG solve; dP and tr(P^{-1} dP) in closed
+ * form (W held fixed). */
 vif_status vif_laplace_nll_grad(vif_ctx* ctx, const double* y, const double* mode, int32_t ell, const double* eps_n,
                                 const double* eps_m, double* nll_out, double* grad_out);
 
@@ -352,7 +363,7 @@ vif_status vif_select_neighbors_pred(vif_ctx* ctx, const double* Xp, int64_t n_p
  * u_j = L_m^{-1} Sigma_mj - sum_a A^p_ja L_m^{-1} Sigma_m,N(j)_a (the
  * proposition's expansion with the B^{-1} terms cancelled); D^p carries the
  * nugget. Gaussian contexts only: VIF_E_ARG on a latent context (its
- * variances need the simulation of Alg. 1). 1 <= n_p <= cfg.max_pred. nbrp
+ * variances need the simulation of vif_laplace_predict). 1 <= n_p <= cfg.max_pred. nbrp
  * is checked before any gather: entries -1 or 0 <= q < n, distinct, -1 only
  * in a trailing run, else VIF_E_ARG naming the prediction point. */
 vif_status vif_predict(vif_ctx* ctx, const double* y, const double* Xp, const int32_t* nbrp, int64_t n_p,
@@ -363,13 +374,13 @@ vif_status vif_predict(vif_ctx* ctx, const double* y, const double* Xp, const in
  * vif_laplace_mode) and the response y, on a latent context. mean_out gets
  * omega_p (as vif_predict with the mode). var_out gets diag(Omega_p),
  * split as in Sec. 4.4 into eq. Part1 -- computed exactly, as vif_predict's
- * variances on the latent factor -- and eq. Part2, estimated by the
- * simulation of Alg. 1 (SBPV) with ell samples: for sample k,
- *   z4 = V^T e3_k + B^{-1} D^{1/2} e1_k                ~ N(0, Sigma_dagger),
- *   z6 = Sigma_dagger^{-1} z4 + W^{1/2} e2_k           ~ N(0, Sigma_dagger^{-1} + W),
- *   z7 = (W + Sigma_dagger^{-1})^{-1} z6 by VIFDU-preconditioned CG to cfg.cg_tol,
- *   z8 = L Sigma_dagger^{-1} z7 (L the prediction/training cross-covariance),
- * and eq. Part2 ~ mean_k z8 * z8 (unbiased; Prop. PropPredVar). W = W(mode).
+ * variances on the latent factor -- and eq. Part2 = diag(G K^{-1} G^T),
+ * G = L Sigma_dagger^{-1} (L the prediction/training cross-covariance),
+ * K = W + Sigma_dagger^{-1}, W = W(mode), estimated by simulation (SBPV)
+ * with ell samples: a prior draw x_k = V^T e3_k + B^{-1} D^{1/2} e1_k
+ * ~ N(0, Sigma_dagger), g_k = Sigma_dagger^{-1} x_k + W^{1/2} e2_k (covariance
+ * K), w_k = K^{-1} g_k by VIFDU-preconditioned CG to cfg.cg_tol (covariance
+ * K^{-1}), s_k = G w_k; eq. Part2 ~ mean_k s_k * s_k, without bias.
  * Standard normals come from the caller (device): eps_n ((2 ell) x n: rows
  * e1_0, e2_0, e1_1, e2_1, ...) and eps_m (ell x m; NULL when m = 0). Device
  * arrays: y, mode (n), Xp (n_p x d), nbrp (n_p x m_v, from

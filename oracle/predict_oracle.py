@@ -147,41 +147,29 @@ def laplace_predictive_variance(model: vo.Model, X: np.ndarray, Z: np.ndarray, n
 def laplace_predictive_variance_sbpv(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray,
                                      W: np.ndarray, Xp: np.ndarray, nbr_p: np.ndarray, e1: np.ndarray,
                                      e2: np.ndarray, e3: np.ndarray) -> np.ndarray:
-    """The simulation-based estimator of Alg. 1 (SBPV) for diag(Omega_p),
-    with exact dense solves in place of CG. e1, e2: l x n and e3: l x m
-    standard normal draws (sample i in row i). For each sample:
-      z4 = S_nm S_m^{-1/2} e3 + B^{-1} D^{1/2} e1   ~ N(0, Sigma_dagger)
-      z5 = Sigma_dagger^{-1} z4 (by the Woodbury form Q - Q S_nm M^{-1} S_mn Q,
-           M = S_m + S_mn Q S_nm, Q = B^T D^{-1} B)
-      z6 = z5 + W^{1/2} e2                          ~ N(0, Sigma_dagger^{-1} + W)
-      z7 = (Sigma_dagger^{-1} + W)^{-1} z6
-      z8 = L Sigma_dagger^{-1} z7,
-    and the estimate is eq. Part1 + mean of z8 * z8. S_m^{1/2} is the lower
-    Cholesky factor of S_m."""
+    """diag(Omega_p) of Prop. 3.1 with eq. Part2 estimated by simulation
+    (Sec. 4.4), densely and with exact solves. Eq. Part2 is diag(G K^{-1} G^T)
+    with G = L Sigma_dagger^{-1} and K = Sigma_dagger^{-1} + W. If g has
+    covariance K, then K^{-1} g has covariance K^{-1}; one such g is
+    Sigma_dagger^{-1} x + W^{1/2} e with x a draw from the prior N(0,
+    Sigma_dagger), here x = S_nm S_m^{-T/2} e3 + B^{-1} D^{1/2} e1 (the
+    low-rank plus Vecchia parts of Sec. 2.1). So the columns of
+    G K^{-1} (Sigma_dagger^{-1} X + W^{1/2} E2) have covariance G K^{-1} G^T,
+    and the mean of their squares estimates eq. Part2 without bias.
+    e1, e2: l x n and e3: l x m standard normal draws (sample i in row i);
+    S_m^{1/2} is the lower Cholesky factor of S_m."""
     o = _dense_operators(model, X, Z, nbr, Xp, nbr_p)
-    ind, fac, B = o["ind"], o["fac"], o["B"]
-    n = X.shape[0]
-    Q = B.T @ (B / fac.D[:, None])
+    ind, fac = o["ind"], o["fac"]
+    Sdag_inv = np.linalg.inv(o["Sdag"])
+    G = (o["low_pn"] - o["Bpo"] @ o["Qinv"]) @ Sdag_inv
+    K = Sdag_inv + np.diag(W)
+    # prior draws, one per column
+    Xs = o["Binv"] @ (np.sqrt(fac.D)[:, None] * e1.T)
     if ind.m:
         Lm = np.linalg.cholesky(ind.Sm)
-        Vt = solve_triangular(Lm, ind.Smn, lower=True).T      # S_nm S_m^{-T/2}
-        M = ind.Sm + ind.Smn @ Q @ ind.Smn.T
-        QS = Q @ ind.Smn.T
-        Sdag_inv = Q - QS @ np.linalg.solve(M, QS.T)
-    else:
-        Vt = np.zeros((n, 0))
-        Sdag_inv = Q
-    L = o["low_pn"] - o["Bpo"] @ o["Qinv"]
-    acc = np.zeros(Xp.shape[0])
-    K = Sdag_inv + np.diag(W)
-    for i in range(e1.shape[0]):
-        z4 = Vt @ e3[i, :Vt.shape[1]] + o["Binv"] @ (np.sqrt(fac.D) * e1[i])
-        z5 = Sdag_inv @ z4
-        z6 = z5 + np.sqrt(W) * e2[i]
-        z7 = np.linalg.solve(K, z6)
-        z8 = L @ (Sdag_inv @ z7)
-        acc += z8 * z8
-    return predictive_variance(model, X, Z, nbr, Xp, nbr_p) + acc / e1.shape[0]
+        Xs = Xs + solve_triangular(Lm, ind.Smn, lower=True).T @ e3.T[:ind.m]
+    samples = G @ np.linalg.solve(K, Sdag_inv @ Xs + np.sqrt(W)[:, None] * e2.T)
+    return predictive_variance(model, X, Z, nbr, Xp, nbr_p) + np.mean(samples * samples, axis=1)
 
 
 def laplace_predictive_mean(model: vo.Model, X: np.ndarray, Z: np.ndarray, nbr: np.ndarray, mode: np.ndarray,

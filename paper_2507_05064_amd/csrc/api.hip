@@ -55,6 +55,7 @@ struct vif_ctx {
   float* Vf = nullptr;   // n x mp, FP32 storage (FP32 form)
   bf16s* Vb = nullptr;   // n x mp, BF16 storage (BF16-input form)
   void* A = nullptr;     // n x m_v (double or float)
+  void* Lfac = nullptr;  // packed rows of each point's L_R (the adjoint and the tangents read them)
   void* U = nullptr;     // n x mp (double or float)
   double *D = nullptr, *yt = nullptr, *vnorm = nullptr;
   double *partial = nullptr, *vecpart = nullptr, *vec = nullptr;
@@ -126,7 +127,7 @@ struct vif_ctx {
   // prediction workspace
   int64_t pred_cap = 0;
   void *pred_Vp = nullptr, *pred_Ap = nullptr, *pred_u = nullptr, *pred_Lt = nullptr;
-  double *pred_Vpd = nullptr, *pred_vn = nullptr, *pred_Dp = nullptr, *pred_z8 = nullptr;
+  double *pred_Vpd = nullptr, *pred_vn = nullptr, *pred_Dp = nullptr, *pred_samp = nullptr;
 };
 
 static vif_status fail(vif_ctx* c, vif_status s, const char* fmt, ...) {
@@ -375,6 +376,7 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   else if (fp32_form(c))
     alloc((void**)&c->Vf, sizeof(float) * n * mpa);
   alloc(&c->A, tsize(c) * n * (g.m_v > 0 ? g.m_v : 1));
+  alloc(&c->Lfac, tsize(c) * n * factor_l_stride(g.m_v));
   alloc(&c->U, tsize(c) * n * mpa);
   alloc((void**)&c->D, sizeof(double) * n);
   alloc((void**)&c->yt, sizeof(double) * n);
@@ -481,14 +483,14 @@ void vif_destroy(vif_ctx* c) {
   if (!c) return;
   if (c->st) hipStreamSynchronize(c->st); else hipDeviceSynchronize();
   if (c->st2) hipStreamSynchronize(c->st2);
-  void* bufs[] = {c->Sm, c->Linv, c->Mp, c->LMinv, c->Mwork, c->Vd, c->Vf, c->Vb, c->A, c->U, c->D, c->yt, c->vnorm,
+  void* bufs[] = {c->Sm, c->Linv, c->Mp, c->LMinv, c->Mwork, c->Vd, c->Vf, c->Vb, c->A, c->Lfac, c->U, c->D, c->yt, c->vnorm,
                   c->partial, c->vecpart, c->vec, c->scal, c->status, c->nbr, c->Xc, c->Zc, c->Minv, c->wvec,
                   c->e, c->Smat, c->Tm, c->tmpm, c->MinvT, c->Ubar, c->Q1, c->Gs, c->Bs, c->Vr, c->tpart,
                   c->rowpart, c->gred, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx,
                   c->fwd_order, c->fwd_lvl, c->bwd_order, c->bwd_lvl, c->lv, c->lm, c->M3, c->M3inv, c->L3inv,
                   c->lsc, c->lpart, c->fcol, c->bptr, c->bcol, c->bsrc, c->fsrc, c->fsplit, c->bsplit, c->fcoef, c->bcoef, c->slq_a, c->slq_b, c->slq_rz, c->slq_terms, c->slq_work, c->slq_u,
                   c->slq_q, c->slq_iters, c->lg_Ut, c->lg_Ut3, c->lg_dV, c->lg_MT, c->lg_M3T, c->lg_PhiT, c->lg_mm, c->lg_vec, c->lg_part, c->lg_slots, c->pred_Vp,
-                  c->pred_Ap, c->pred_u, c->pred_Lt, c->pred_Vpd, c->pred_vn, c->pred_Dp, c->pred_z8, c->vorder,
+                  c->pred_Ap, c->pred_u, c->pred_Lt, c->pred_Vpd, c->pred_vn, c->pred_Dp, c->pred_samp, c->vorder,
                   c->blk, c->blk_mm, c->blk_part, c->blk_cs, c->blk_int};
   for (void* b : bufs)
     if (b) hipFree(b);
@@ -671,13 +673,13 @@ vif_status vif_build_factor(vif_ctx* c, const double* X, const double* Z, const 
   stage_begin(c, ST_FACTOR);
   if (bf16_form(c))
     launch_factor<float>(c->st, X, c->Vb, nbr, g.n, c->mp, g.m_v, c->cp, (float*)c->A, c->D, (float*)c->U, c->status,
-                         Batch{nullptr, nullptr}, vorder(c));
+                         Batch{nullptr, nullptr}, vorder(c), (float*)c->Lfac);
   else if (f32)
     launch_factor<float>(c->st, X, c->Vf, nbr, g.n, c->mp, g.m_v, c->cp, (float*)c->A, c->D, (float*)c->U, c->status,
-                         Batch{nullptr, nullptr}, vorder(c));
+                         Batch{nullptr, nullptr}, vorder(c), (float*)c->Lfac);
   else
     launch_factor<double>(c->st, X, c->Vd, nbr, g.n, c->mp, g.m_v, c->cp, (double*)c->A, c->D, (double*)c->U,
-                          c->status, Batch{nullptr, nullptr}, vorder(c));
+                          c->status, Batch{nullptr, nullptr}, vorder(c), (double*)c->Lfac);
   stage_end(c, ST_FACTOR);
   if (g.m > 0) {
     int nchunk = 0;
@@ -804,8 +806,8 @@ static vif_status nll_grad_impl(vif_ctx* c, const double* y) {
     stage_end(c, ST_WDERIV);
   }
   stage_begin(c, ST_FBWD);
-  launch_factor_bwd<T>(c->st, c->Xc, V, (const S*)c->Vr, c->nbr, y, U, (const T*)c->Ubar, c->e, c->yt, c->D, g.n, mp,
-                       g.m_v, c->cp, (T*)c->Q1, (T*)c->Gs, (T*)c->Bs, c->tpart, c->status, Batch{nullptr, nullptr},
+  launch_factor_bwd<T>(c->st, c->Xc, V, (const S*)c->Vr, c->nbr, y, U, (const T*)c->Ubar, c->e, c->yt, c->D,
+                       (const T*)c->A, (const T*)c->Lfac, g.n, mp, g.m_v, c->cp, (T*)c->Q1, (T*)c->Gs, (T*)c->Bs, c->tpart, c->status, Batch{nullptr, nullptr},
                        vorder(c));
   stage_end(c, ST_FBWD);
   double* tp = c->gred;
@@ -1648,7 +1650,7 @@ static vif_status alloc_slq(vif_ctx* c, int ell) {
   const size_t mpa = c->mp > 0 ? c->mp : 1;
   const size_t npart = std::max((size_t)utx_chunks(n) * mpa, 2 * (size_t)ceil_div(n, 1024));
   alloc((void**)&c->blk, sizeof(double) * kBlkVecs * n * L);
-  alloc((void**)&c->blk_mm, sizeof(double) * 3 * mpa * L);
+  alloc((void**)&c->blk_mm, sizeof(double) * 4 * mpa * L);
   alloc((void**)&c->blk_part, sizeof(double) * npart * L);
   alloc((void**)&c->blk_cs, sizeof(double) * 11 * L);
   alloc((void**)&c->blk_int, sizeof(int) * 4);
@@ -1664,7 +1666,7 @@ static vif_status alloc_slq(vif_ctx* c, int ell) {
 struct BlkBufs {
   int cap;
   double *x, *r, *z, *p, *ap, *t, *s, *q, *qd, *q2, *xq, *zq, *rhs, *e1, *u, *w;
-  double *cm, *cm2, *cm3;  // mp x cap
+  double *cm, *cm2, *cm3, *cm4;  // mp x cap
   double *part, *cs, *dots, *beta;
   int *nact, *bad;
 };
@@ -1680,6 +1682,7 @@ static BlkBufs blk_bufs(vif_ctx* c) {
   K.cm = c->blk_mm;
   K.cm2 = c->blk_mm + ml;
   K.cm3 = c->blk_mm + 2 * ml;
+  K.cm4 = c->blk_mm + 3 * ml;
   K.part = c->blk_part;
   K.cs = c->blk_cs;
   K.dots = c->blk_cs + 8 * K.cap;
@@ -1941,8 +1944,8 @@ static void factor_tangent(vif_ctx* c, int p, T* dVbuf, double* mm, T* PhiT, T* 
     }
     dVp = dVbuf;
   }
-  launch_factor_jvp<T>(c->st, c->Xc, V, dVp, c->nbr, (const T*)c->U, n, mp, g.m_v, cpp, which, dA, dD, dU, c->status,
-                       vorder(c));
+  launch_factor_jvp<T>(c->st, c->Xc, V, dVp, c->nbr, (const T*)c->U, c->D, (const T*)c->A, (const T*)c->Lfac, n, mp,
+                       g.m_v, cpp, which, dA, dD, dU, vorder(c));
 }
 
 static int lapgrad_slots(int ell, int P) { return P * (2 + 2 * ell) + 4 * P; }
@@ -2137,6 +2140,144 @@ static vif_status laplace_grad_impl(vif_ctx* c, const double* y, const double* m
   return VIF_OK;
 }
 
+// The same gradient with the FITC preconditioner, the trace estimates in the
+// form of eq. pcls2 (A2 = W^{-1} + Sigma_dagger; formulas in fitcgrad.hip):
+// after laplace_nll_impl with FITC, B.W = W(mode), B.E = D_V^{-1}, M3inv =
+// M_V^{-1}, slq_u / slq_q the probes' A2^{-1} z_k and P^{-1} z_k.
+//   dL/db_i = 1/2 dW_i [(W + Sigma^{-1})^{-1}]_ii = 1/2 (dW_i / W_i - dW_i (A2^{-1})_ii / W_i^2),
+//   v = (W + Sigma^{-1})^{-1} dL/db = x - A2^{-1} x / W, x = dL/db / W (one FITC-PCG solve),
+//   grad_p = -1/2 sb^T dSigma sb + 1/2 tr(A2^{-1} dSigma) + sv^T dSigma sb,
+// sb = Sigma^{-1} b, sv = Sigma^{-1} v. The factor tangents of every parameter
+// are built first (dV_p kept in lg_dU[p]), then each block of probes is
+// prepared once (B^{-T}, B^{-1} D B^{-T} and V^T of its u and q columns) and
+// its forms taken for every parameter.
+template <typename T>
+static vif_status laplace_grad_fitc_impl(vif_ctx* c, const double* y, const double* mode, int ell, double* grad) {
+  const vif_config& g = c->cfg;
+  const int64_t n = g.n;
+  const int mp = c->mp, mv = g.m_v, m = g.m;
+  const int P = n_params(g);
+  const int nslot = lapgrad_slots(ell, P);
+  vif_status s = nslot <= c->lg_slot_cap ? VIF_OK : check_probes(c, ell, "vif_laplace_nll_grad");
+  if (s) return s;
+  LapBufs B = lap_bufs(c);
+  const T* V = form_V<T>(c);
+  double* w = c->lg_vec;
+  double *dW = w, *Sh = w + n, *Sg = w + 2 * n, *trq = w + 3 * n, *dLdb = w + 4 * n, *xv = w + 5 * n,
+         *ysol = w + 6 * n, *yv = w + 7 * n, *vdv = w + 8 * n, *ydv = w + 9 * n, *sbv = w + 10 * n,
+         *svv = w + 11 * n, *sd = w + 12 * n;
+  double* part = c->lg_part;
+  double* slots = c->lg_slots;
+  double* tslots = slots + P * (2 + 2 * ell);
+  T* Y = (T*)c->lg_Ut;
+  launch_lik_dW(c->st, g.likelihood, g.lik_param, y, mode, n, dW);
+  // Y = V M_V^{-1}, yv_i = Y_i . V_i
+  if (m > 0) {
+    to_form<T>(c, c->M3inv, (int64_t)mp * mp, c->lg_M3T);
+    launch_rowmm<T>(c->st, V, (const T*)c->lg_M3T, nullptr, 1.0, 0.0, n, mp, Y);
+    launch_rowdot<T>(c->st, Y, V, n, mp, yv);
+  } else {
+    HIPCHK(c, hipMemsetAsync(yv, 0, sizeof(double) * n, c->st));
+  }
+  // dL/db by the diagonal estimate, then v
+  int nb = launch_fitc_diag_ste(c->st, c->slq_u, c->slq_q, ell, B.W, dW, B.E, yv, n, Sh, Sg, trq, part);
+  launch_sum_cols(c->st, part, nb, 2, B.sc + 13);
+  if ((s = read_scalars(c, 15))) return s;
+  const double cb = (c->hlsc[14] > 0.0) ? c->hlsc[13] / c->hlsc[14] : 0.0;
+  launch_fitc_diag_final(c->st, Sh, Sg, trq, cb, ell, B.W, dW, n, dLdb, xv);
+  int vits = 0;
+  double vrz = 0.0;
+  if ((s = pcg_plain<T>(c, B, xv, ysol, nullptr, nullptr, nullptr, &vits, &vrz, true))) return s;
+  launch_fitc_vsol(c->st, xv, ysol, B.W, n, ysol);  // ysol = v
+  prec_matvec<T>(c, B, mode, nullptr, sbv);
+  prec_matvec<T>(c, B, ysol, nullptr, svv);
+  // factor tangents of every parameter: dA, dD, and dV (kept in lg_dU[p])
+  std::vector<bool> has_dv(P);
+  for (int p = 0; p < P; ++p) {
+    has_dv[p] = param_which(g, p) < 2 && m > 0;
+    factor_tangent<T>(c, p, (T*)c->lg_dU[p], c->lg_mm, (T*)c->lg_PhiT, (T*)c->lg_dA[p], c->lg_dD[p], (T*)c->lg_dV);
+  }
+  BlkBufs K = blk_bufs(c);
+  // x-block and y-block: B^{-T}, B^{-1} D B^{-T} and V^T of their columns
+  double *Xx = K.x, *Xy = K.r, *Ax = K.t, *Ay = K.s, *Cx = K.z, *Cy = K.p, *dBx = K.q, *dBy = K.qd, *tmp = K.q2;
+  double *VXx = K.cm, *VXy = K.cm2, *dVXx = K.cm3, *dVXy = K.cm4;
+  auto prepare = [&](int L) {
+    launch_trsv_bwd_multi<T>(c->st, c->sb, (const T*)c->bcoef, Xx, L, K.xq, K.zq, Ax);
+    launch_trsv_bwd_multi<T>(c->st, c->sb, (const T*)c->bcoef, Xy, L, K.xq, K.zq, Ay);
+    launch_scale_rows_multi(c->st, c->D, Ax, n, L, tmp);
+    launch_trsv_fwd_multi<T>(c->st, c->sf, (const T*)c->fcoef, tmp, L, K.xq, K.zq, Cx);
+    launch_scale_rows_multi(c->st, c->D, Ay, n, L, tmp);
+    launch_trsv_fwd_multi<T>(c->st, c->sf, (const T*)c->fcoef, tmp, L, K.xq, K.zq, Cy);
+    if (m > 0) {
+      launch_utx<T>(c->st, V, Xx, n, mp, L, nullptr, K.part, nullptr, VXx);
+      launch_utx<T>(c->st, V, Xy, n, mp, L, nullptr, K.part, nullptr, VXy);
+    }
+  };
+  // column forms x_l^T dSigma y_l into f (L), and with qg set q^T dP q (y the q block) into qg
+  auto forms = [&](int p, int L, double* f, double* qg) {
+    const T* dV = (const T*)c->lg_dU[p];
+    launch_dbx_multi<T>(c->st, (const T*)c->lg_dA[p], c->nbr, Cx, n, mv, L, dBx);
+    launch_dbx_multi<T>(c->st, (const T*)c->lg_dA[p], c->nbr, Cy, n, mv, L, dBy);
+    launch_fitc_bilin_multi(c->st, Ax, Ay, dBx, dBy, c->lg_dD[p], qg ? Xy : nullptr, sd, n, L, K.part, f, qg);
+    if (has_dv[p]) {
+      launch_utx<T>(c->st, dV, Xx, n, mp, L, nullptr, K.part, nullptr, dVXx);
+      launch_utx<T>(c->st, dV, Xy, n, mp, L, nullptr, K.part, nullptr, dVXy);
+      launch_mdot_cols_add(c->st, dVXx, VXy, VXx, dVXy, mp, L, 1.0, f);
+      if (qg) launch_mdot_cols_add(c->st, VXy, dVXy, nullptr, nullptr, mp, L, 2.0, qg);
+    }
+  };
+  // per parameter: sd = dsig - 2 V.dV and tr(P^{-1} dP)
+  auto param_diag = [&](int p) {
+    const double dsig = (p == 0 || p == P - 1) ? 1.0 : 0.0;
+    const T* dV = (const T*)c->lg_dU[p];
+    if (has_dv[p]) {
+      launch_rowdot<T>(c->st, V, dV, n, mp, vdv);
+      launch_rowdot<T>(c->st, Y, dV, n, mp, ydv);
+    }
+    const int nbt = launch_fitc_trp(c->st, B.E, yv, has_dv[p] ? vdv : nullptr, has_dv[p] ? ydv : nullptr, dsig, n,
+                                    sd, part);
+    hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, c->st, part, nbt, tslots + 4 * p);
+  };
+  // sb^T dSigma sb and sv^T dSigma sb: x-block (sb, sv), y-block (sb, sb)
+  launch_cols_to_block(c->st, sbv, n, 0, 0, n, 2, Xx);
+  launch_cols_to_block(c->st, sbv, 0, 0, 0, n, 2, Xy);
+  prepare(2);
+  for (int p = 0; p < P; ++p) forms(p, 2, slots + (size_t)p * (2 + 2 * ell), nullptr);
+  // probes, a block at a time
+  for (int k0 = 0; k0 < ell; k0 += K.cap) {
+    const int L = std::min(K.cap, ell - k0);
+    launch_cols_to_block(c->st, c->slq_u, n, 0, k0, n, L, Xx);
+    launch_cols_to_block(c->st, c->slq_q, n, 0, k0, n, L, Xy);
+    prepare(L);
+    for (int p = 0; p < P; ++p) {
+      double* fs = slots + (size_t)p * (2 + 2 * ell);
+      param_diag(p);
+      forms(p, L, fs + 2 + k0, fs + 2 + ell + k0);
+    }
+  }
+  std::vector<double> hs(nslot);
+  HIPCHK(c, hipMemcpyAsync(hs.data(), slots, sizeof(double) * nslot, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  for (int p = 0; p < P; ++p) {
+    const double* fs = hs.data() + (size_t)p * (2 + 2 * ell);
+    const double trP = hs[(size_t)P * (2 + 2 * ell) + 4 * p];
+    double fm = 0.0;
+    for (int k = 0; k < ell; ++k) fm += fs[2 + k];
+    fm /= ell;
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < ell; ++k) {
+      num += (fs[2 + k] - fm) * (fs[2 + ell + k] - trP);
+      den += (fs[2 + ell + k] - trP) * (fs[2 + ell + k] - trP);
+    }
+    const double cp = den > 0.0 ? num / den : 0.0;
+    double that = 0.0;
+    for (int k = 0; k < ell; ++k) that += fs[2 + k] - cp * fs[2 + ell + k];
+    that = that / ell + cp * trP;
+    grad[p] = -0.5 * fs[0] + 0.5 * that + fs[1];
+  }
+  return VIF_OK;
+}
+
 extern "C" {
 
 vif_status vif_laplace_nll(vif_ctx* c, const double* y, const double* mode, int32_t ell, const double* eps_n,
@@ -2177,12 +2318,15 @@ vif_status vif_laplace_nll_grad(vif_ctx* c, const double* y, const double* mode,
   if ((s = reset_status(c))) return s;
   if ((s = check_response(c, y, "vif_laplace_nll_grad"))) return s;
   double out3[3];
+  const bool fitc = c->precond == VIF_PRECOND_FITC;
   if (fp32_form(c)) {
-    s = laplace_nll_impl<float>(c, y, mode, ell, eps_n, eps_m, out3);
-    if (!s) s = laplace_grad_impl<float>(c, y, mode, ell, grad_out);
+    s = laplace_nll_impl<float>(c, y, mode, ell, eps_n, eps_m, out3, fitc);
+    if (!s) s = fitc ? laplace_grad_fitc_impl<float>(c, y, mode, ell, grad_out)
+                     : laplace_grad_impl<float>(c, y, mode, ell, grad_out);
   } else {
-    s = laplace_nll_impl<double>(c, y, mode, ell, eps_n, eps_m, out3);
-    if (!s) s = laplace_grad_impl<double>(c, y, mode, ell, grad_out);
+    s = laplace_nll_impl<double>(c, y, mode, ell, eps_n, eps_m, out3, fitc);
+    if (!s) s = fitc ? laplace_grad_fitc_impl<double>(c, y, mode, ell, grad_out)
+                     : laplace_grad_impl<double>(c, y, mode, ell, grad_out);
   }
   if (s) return s;
   if ((s = read_status(c, "vif_laplace_nll_grad"))) return s;
@@ -2208,7 +2352,7 @@ static vif_status alloc_pred(vif_ctx* c, int64_t np_) {
   alloc((void**)&c->pred_Vpd, sizeof(double) * np_ * mpa);
   alloc((void**)&c->pred_vn, sizeof(double) * np_);
   alloc((void**)&c->pred_Dp, sizeof(double) * np_);
-  alloc((void**)&c->pred_z8, sizeof(double) * np_);
+  alloc((void**)&c->pred_samp, sizeof(double) * np_);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP;
   c->pred_cap = np_;
   return VIF_OK;
@@ -2306,13 +2450,16 @@ __global__ void k_acc_sq(double* __restrict__ acc, const double* __restrict__ z,
   if (i < n) acc[i] += scale * z[i] * z[i];
 }
 
-// diag(Omega_p) of Prop. 3.1 by Alg. 1 (SBPV), variances only: eq. Part1 by
-// pred_var_apply on the latent factor, eq. Part2 as the mean of z8 * z8 over
-// ell samples with
-//   z4 = V^T e_m + B^{-1} D^{1/2} e_prior ~ N(0, Sigma_dagger)  (prior_draw)
-//   z6 = Sigma_dagger^{-1} z4 + W^{1/2} e_W ~ N(0, Sigma_dagger^{-1} + W)
-//   z7 = (W + Sigma_dagger^{-1})^{-1} z6  (VIFDU-preconditioned CG, eq. pcls1)
-//   z8 = L Sigma_dagger^{-1} z7            (pred_mean_apply with z7 as y).
+// diag(Omega_p) of Prop. 3.1, variances only (Sec. 4.4): eq. Part1 exactly
+// (pred_var_apply on the latent factor); eq. Part2 = diag(G K^{-1} G^T),
+// G = L Sigma_dagger^{-1} (the predictive-mean operator of Prop. 2.1, L the
+// prediction/training cross-covariance), K = W + Sigma_dagger^{-1}, by
+// simulation. Per sample: a prior draw x ~ N(0, Sigma_dagger) (prior_draw);
+// g = Sigma_dagger^{-1} x + W^{1/2} e, whose covariance is K; w = K^{-1} g
+// (VIFDU-preconditioned CG on eq. pcls1), whose covariance is K^{-1}; then
+// s = G w (pred_mean_apply with w as the response) has covariance
+// G K^{-1} G^T, and the mean of s * s over the samples estimates eq. Part2
+// without bias.
 template <typename T>
 static vif_status laplace_predvar_impl(vif_ctx* c, const double* y, const double* mode, const double* Xp,
                                        const int32_t* nbrp, int64_t np_, int ell, const double* eps_n,
@@ -2328,20 +2475,21 @@ static vif_status laplace_predvar_impl(vif_ctx* c, const double* y, const double
   pred_setup<T>(c, Xp, nbrp, np_);
   if ((s = pred_mean_apply<T>(c, B, mode, nbrp, np_, mean))) return s;  // omega_p (Prop. 3.1)
   pred_var_apply<T>(c, nbrp, np_, var);              // eq. Part1
-  double* z8 = c->pred_z8;
+  double* samp = c->pred_samp;
   int total = 0;
   for (int k = 0; k < ell; ++k) {
     const double* e_prior = eps_n + (size_t)(2 * k) * n;
     const double* e_w = eps_n + (size_t)(2 * k + 1) * n;
-    prior_draw<T>(c, B, g.m > 0 ? eps_m + (size_t)k * g.m : nullptr, e_prior, B.sb);
-    prec_matvec<T>(c, B, B.sb, nullptr, B.rhs);
-    launch_add_sqrtw(c->st, B.rhs, B.W, e_w, n);
+    double *x = B.sb, *gk = B.rhs, *w = B.x;
+    prior_draw<T>(c, B, g.m > 0 ? eps_m + (size_t)k * g.m : nullptr, e_prior, x);
+    prec_matvec<T>(c, B, x, nullptr, gk);
+    launch_add_sqrtw(c->st, gk, B.W, e_w, n);
     int its = 0;
     double rz0 = 0.0;
-    if ((s = pcg_plain<T>(c, B, B.rhs, B.x, nullptr, nullptr, nullptr, &its, &rz0))) return s;
+    if ((s = pcg_plain<T>(c, B, gk, w, nullptr, nullptr, nullptr, &its, &rz0))) return s;
     total += its;
-    if ((s = pred_mean_apply<T>(c, B, B.x, nbrp, np_, z8))) return s;
-    hipLaunchKernelGGL(k_acc_sq, dim3((unsigned)ceil_div(np_, 256)), dim3(256), 0, c->st, var, z8, np_, 1.0 / ell);
+    if ((s = pred_mean_apply<T>(c, B, w, nbrp, np_, samp))) return s;
+    hipLaunchKernelGGL(k_acc_sq, dim3((unsigned)ceil_div(np_, 256)), dim3(256), 0, c->st, var, samp, np_, 1.0 / ell);
   }
   if (cg_iters) *cg_iters = total;
   HIPCHK(c, hipGetLastError());

@@ -42,6 +42,7 @@ struct vif_batch {
   // per point (npad x mp in the form's type unless noted)
   void *V = nullptr, *U = nullptr, *A = nullptr, *Ubar = nullptr, *Q1 = nullptr, *Gs = nullptr, *Bs = nullptr,
        *Vr = nullptr;
+  void* Lfac = nullptr;  // packed rows of each point's L_R (npad x m_v(m_v+1)/2), for the adjoint
   double *D = nullptr, *yt = nullptr, *e = nullptr, *tpart = nullptr;
   double *partial = nullptr, *vecpart = nullptr;
   int *status = nullptr, *hstatus = nullptr;
@@ -162,6 +163,7 @@ vif_status vif_batch_create(const vif_batch_config* cfg, const int64_t* n, void*
   void** rows[] = {&b->V, &b->U, &b->Ubar, &b->Q1, &b->Gs, &b->Bs, &b->Vr};
   for (void** q : rows) alloc(q, ts * np * b->mp);
   alloc(&b->A, ts * np * (g.m_v > 0 ? g.m_v : 1));
+  alloc(&b->Lfac, ts * np * factor_l_stride(g.m_v));
   alloc((void**)&b->D, sizeof(double) * np);
   alloc((void**)&b->yt, sizeof(double) * np);
   alloc((void**)&b->e, sizeof(double) * np);
@@ -186,8 +188,8 @@ void vif_batch_destroy(vif_batch* b) {
   if (b->st) hipStreamSynchronize(b->st); else hipDeviceSynchronize();
   void* bufs[] = {b->bp, b->blk2prob, b->X, b->y, b->nbr, b->Sm, b->Linv, b->Mwork, b->Mp, b->LMinv, b->Minv,
                   b->Smat, b->Tm, b->tmpm, b->pscal, b->vec, b->wvec, b->rowpart, b->MinvT, b->V, b->U, b->Ubar,
-                  b->Q1, b->Gs, b->Bs, b->Vr, b->A, b->D, b->yt, b->e, b->tpart, b->partial, b->vecpart,
-                  b->status};
+                  b->Q1, b->Gs, b->Bs, b->Vr, b->A, b->Lfac, b->D, b->yt, b->e, b->tpart, b->partial,
+                  b->vecpart, b->status};
   for (void* q : bufs)
     if (q) hipFree(q);
   if (b->hpscal) hipHostFree(b->hpscal);
@@ -215,7 +217,7 @@ static void batch_run(vif_batch* b, const double* Z, bool grad) {
   launch_chol_inv(st, b->Sm, b->Linv, b->Mwork, m, mp, b->pscal + 0, b->status, 1, P, 16);
   launch_whiten<T>(st, b->X, Z, b->Linv, m, mp, np, cp0, false, V, bt);
   // per-point factor, M' and its Cholesky
-  launch_factor<T>(st, b->X, V, b->nbr, np, mp, mv, cp0, (T*)b->A, b->D, U, b->status, bt);
+  launch_factor<T>(st, b->X, V, b->nbr, np, mp, mv, cp0, (T*)b->A, b->D, U, b->status, bt, nullptr, (T*)b->Lfac);
   int nch = 0;
   launch_gram_partial<T>(st, U, np, mp, kBatchBlock, b->partial, &nch);
   launch_reduce_gram(st, b->partial, nch, mp, b->Mp, 1.0, bt, P);
@@ -232,8 +234,8 @@ static void batch_run(vif_batch* b, const double* Z, bool grad) {
   launch_resid<T>(st, U, b->wvec, b->yt, np, mp, b->e, bt);
   launch_ubar<T>(st, U, (const T*)b->MinvT, b->e, b->wvec, np, mp, (T*)b->Ubar, bt);
   launch_whiten<T>(st, b->X, Z, b->Linv, m, mp, np, cp0, true, (T*)b->Vr, bt);
-  launch_factor_bwd<T>(st, b->X, V, (const T*)b->Vr, b->nbr, b->y, U, (const T*)b->Ubar, b->e, b->yt, b->D, np, mp,
-                       mv, cp0, (T*)b->Q1, (T*)b->Gs, (T*)b->Bs, b->tpart, b->status, bt);
+  launch_factor_bwd<T>(st, b->X, V, (const T*)b->Vr, b->nbr, b->y, U, (const T*)b->Ubar, b->e, b->yt, b->D,
+                       (const T*)b->A, (const T*)b->Lfac, np, mp, mv, cp0, (T*)b->Q1, (T*)b->Gs, (T*)b->Bs, b->tpart, b->status, bt);
   launch_cross3_partial<T>(st, V, (const T*)b->Q1, U, (const T*)b->Gs, (const T*)b->Bs, np, mp, kBatchBlock,
                            b->partial, &nch);
   launch_reduce_sym(st, b->partial, nch, mp, b->Smat, bt, P);

@@ -14,8 +14,6 @@
 // BF16 with T = float (the BF16-input form: rows widened to FP32 on load).
 #include <limits.h>
 
-#include <type_traits>
-
 #include "common.h"
 #include "kernels.h"
 
@@ -90,21 +88,26 @@ struct PointShared {
   int nbs[32];               // row -> point index (N(i) then i)
 };
 
-// Steps 1-3 for point i, shared by the forward and the adjoint kernels.
+// (a, b), b <= a, of entry e of a lower triangle stored row by row
+__device__ __forceinline__ void tri_index(int e, int& a, int& b) {
+  a = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);  // corrected below
+  while ((a + 1) * (a + 2) / 2 <= e) ++a;
+  while (a * (a + 1) / 2 > e) --a;
+  b = e - a * (a + 1) / 2;
+}
+
+// Steps 1-3 for point i, shared by the forward kernel, the forward-mode
+// tangents and the prediction rows.
 // On return (true): k = |N(i)|, D = D_i, Lrow = row `lane` of L (lanes
 // 0..k), sh.GL = L, sh.As = A_i, sh.nbs = row points and xs (LDS, 32 x d,
 // sized at launch so that a point's LDS block fits its dimension) = their
 // coordinates.
-// With `extra` set, the m-vector extra * extra_scale joins the Gram as row
-// k + 1 (needs k + 2 <= 32): sh.GL[k + 1][j] then holds its dot products
-// with the rows j <= k (row k + 1 is not touched by the Cholesky).
 // Returns false (after flagging status) when the system is not PD.
 template <typename T, typename S, int NBLK>
 __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const S* __restrict__ V,
                                              const int32_t* __restrict__ nbr, int64_t i, int mp, int mv,
                                              const CovParams& p, PointShared<T>& sh, double* xs, T (&Lrow)[32], int& k_out,
-                                             T& D_out, int* status, const T* extra = nullptr,
-                                             T extra_scale = T(1), const S* own_v = nullptr,
+                                             T& D_out, int* status, const S* own_v = nullptr,
                                              const double* own_x = nullptr, const int32_t* own_nbr = nullptr) {
   // own_v / own_x / own_nbr (prediction points): the point's own V row,
   // coordinates and neighbour row come from these, its neighbours (all < i)
@@ -116,19 +119,15 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
   if (nbv >= i) nbv = -1;  // invalid entry (reported by the list check): never gather out of range
   const unsigned long long valid = __ballot(nbv >= 0);
   const int k = __popcll(valid);
-  // lane j < k takes the j-th valid entry: a row with -1 before a valid entry
+  // lane j < k takes the j-th valid entry (each valid entry is written to LDS
+  // at its rank among the valid ones): a row with -1 before a valid entry
   // (invalid input, rejected by the list check after the build) still yields
   // k in-range row indices in lanes 0..k-1, which every later gather reads
-  int src_lane = 0;
-  {
-    int seen = 0;
-    for (int b = 0; b < 32; ++b)
-      if ((valid >> b) & 1ull) {
-        if (seen == lane) src_lane = b;
-        ++seen;
-      }
-  }
-  const int nbc = __shfl(nbv, src_lane, 64);
+  const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(valid >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)valid, 0));
+  if (nbv >= 0) sh.nbs[rank] = nbv;
+  wave_sync();
+  const int nbc = (lane < k) ? sh.nbs[lane] : -1;
+  wave_sync();
   const int rowpt = (lane < k) ? nbc : (lane == k ? (int)i : -1);
   const bool own = own_v != nullptr && lane == k;
   if (lane < 32) {
@@ -137,45 +136,38 @@ __device__ __forceinline__ bool factor_point(const double* __restrict__ X, const
       xs[lane * p.d + dd] = rowpt >= 0 ? (own ? own_x[dd] : X[(int64_t)rowpt * p.d + dd]) : 0.0;
   }
 
-  // 1. Gram of the gathered rows
+  // 1. Gram of the gathered rows: lane (r, g) feeds rows r and 16 + r at
+  //    columns 4g..4g+3 of each 16-column step; the rows are addressed by
+  //    index from V (or own_v for the point's own row), and the next step's
+  //    values are loaded before this step's MFMAs
+  //    (loads are unconditional: an unused row reads row 0, whose finite
+  //    products land in Gram rows the factorisation never reads, and the
+  //    last step loads its own columns again; so no load waits on a branch)
   const int r = lane & 15, g = lane >> 4;
-  const void* src = nullptr;
-  T scl = T(1);
-  int isx = 0;  // the row is `extra` (type T) rather than a stored V row (type S)
-  if (own) {
-    src = own_v;
-  } else if (rowpt >= 0) {
-    src = V + (size_t)rowpt * mp;
-  } else if (extra != nullptr && lane == k + 1) {
-    src = extra;
-    scl = extra_scale;
-    isx = 1;
-  }
-  const unsigned long long srcbits = (unsigned long long)(uintptr_t)src;
-  const void* s0 = (const void*)(uintptr_t)__shfl(srcbits, r, 64);
-  const void* s1 = (const void*)(uintptr_t)__shfl(srcbits, 16 + r, 64);
-  const T sc0 = __shfl(scl, r, 64), sc1 = __shfl(scl, 16 + r, 64);
-  const bool x0 = __shfl(isx, r, 64) != 0, x1 = __shfl(isx, 16 + r, 64) != 0;
-  auto row4 = [&](const void* q, bool x, int off) -> T4 {
-    if constexpr (std::is_same<S, T>::value) {
-      return ld4(static_cast<const T*>(q) + off);
-    } else {
-      return x ? ld4(static_cast<const T*>(q) + off) : ld4(static_cast<const S*>(q) + off);
-    }
-  };
-  A4 acc00 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
+  const int row0 = __shfl(rowpt, r, 64), row1 = __shfl(rowpt, 16 + r, 64);
+  const bool own0 = own_v != nullptr && r == k, own1 = own_v != nullptr && 16 + r == k;
+  const S* p0 = (own0 ? own_v : V + (size_t)(row0 >= 0 ? row0 : 0) * mp) + 4 * g;
+  const S* p1 = (own1 ? own_v : V + (size_t)(row1 >= 0 ? row1 : 0) * mp) + 4 * g;
   const T4 zero4 = {0, 0, 0, 0};
-  for (int kk = 0; kk < mp; kk += 16) {
-    const T4 a0 = (s0 != nullptr) ? row4(s0, x0, 4 * g + kk) * sc0 : zero4;
-    T4 a1 = zero4;
-    if (NBLK == 2) a1 = (s1 != nullptr) ? row4(s1, x1, 4 * g + kk) * sc1 : zero4;
+  A4 acc00 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
+  if (mp > 0) {
+    T4 a0 = ld4(p0), a1 = zero4;
+    if (NBLK == 2) a1 = ld4(p1);
+    for (int kk = 0; kk < mp; kk += 16) {
+      const int kn = min(kk + 16, mp - 16);
+      const T4 n0 = ld4(p0 + kn);
+      T4 n1 = zero4;
+      if (NBLK == 2) n1 = ld4(p1 + kn);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      acc00 = mfma16(a0[t], a0[t], acc00);
-      if (NBLK == 2) {
-        acc10 = mfma16(a1[t], a0[t], acc10);
-        acc11 = mfma16(a1[t], a1[t], acc11);
+      for (int t = 0; t < 4; ++t) {
+        acc00 = mfma16(a0[t], a0[t], acc00);
+        if (NBLK == 2) {
+          acc10 = mfma16(a1[t], a0[t], acc10);
+          acc11 = mfma16(a1[t], a1[t], acc11);
+        }
       }
+      a0 = n0;
+      a1 = n1;
     }
   }
 #pragma unroll
@@ -266,7 +258,7 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
                                                const int32_t* __restrict__ nbr, int64_t n, int mp, int mv,
                                                CovParams p_in, T* __restrict__ Aout, double* __restrict__ Dout,
                                                T* __restrict__ U, int* status, Batch bt,
-                                               const int* __restrict__ perm) {
+                                               const int* __restrict__ perm, T* __restrict__ Lout, int ls) {
   __shared__ PointShared<T> sh;
   extern __shared__ double xs[];  // 32 x d coordinates (dynamic)
   T Lrow[32];
@@ -293,22 +285,72 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
   }
   if (lane < mv) Aout[i * mv + lane] = (lane < k) ? sh.As[lane] : T(0);
   if (lane == 0) Dout[i] = (double)D;
+  if (Lout != nullptr) {  // rows 0..k-1 of L_R, packed, for the adjoint
+    T* dst = Lout + (size_t)i * ls;
+    for (int e = lane; e < k * (k + 1) / 2; e += 64) {
+      int a, b;
+      tri_index(e, a, b);
+      dst[e] = sh.GL[a][b];
+    }
+  }
   // 4. U_i, four consecutive entries per lane
   typedef typename Vec4<T>::type T4;
   const T rsd = T(1) / sqrt(D);
   for (int l = 4 * lane; l < mp; l += 256) {
     T4 u = ld4(V + (size_t)i * mp + l);
-    for (int a = 0; a < k; ++a) u -= sh.As[a] * ld4(V + (size_t)sh.nbs[a] * mp + l);
+    for (int a0 = 0; a0 < k; a0 += 4) {  // four rows' loads in flight at a time
+      T4 w[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) w[t] = ld4(V + (size_t)sh.nbs[min(a0 + t, k - 1)] * mp + l);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (a0 + t < k) u -= sh.As[a0 + t] * w[t];
+    }
     *reinterpret_cast<T4*>(U + (size_t)i * mp + l) = u * rsd;
   }
 }
 
-// Adjoint of the per-point factor (reverse mode of steps 1-4, recomputed
-// from V rather than stored). Inputs: the cotangent of U,
-// Ubar = U M'^{-1} - e w^T, and of yt, e = yt - U w (w = M'^{-1} U^T yt),
-// from the Woodbury step, and Vr = L_m^{-1} dK(Z,X)/drange. With
-// ub = Ubar_i / sqrt(D_i) (joined to the Gram as an extra row, so its dot
-// products with V_{N_j} and V_i come out of the same MFMA pass):
+// The forward pass's results for point i, for the kernels that differentiate
+// them: the neighbour rows in the forward pass's order (its j-th valid entry
+// in row j, the point itself in row k) in nbs, their coordinates in xs,
+// A_i in As and rows 0..k-1 of L_R (stored packed by k_factor) in Ls.
+// Returns k = |N(i)|. One wave; nbs, As, Ls in LDS.
+template <typename T>
+__device__ __forceinline__ int load_point_factor(const double* __restrict__ X, const int32_t* __restrict__ nbr,
+                                                 const T* __restrict__ Ain, const T* __restrict__ Lin, int ls,
+                                                 int64_t i, int mv, const CovParams& p, int* nbs, double* xs, T* As,
+                                                 T (*Ls)[33]) {
+  const int lane = threadIdx.x;
+  int nbv = (lane < mv) ? nbr[i * mv + lane] : -1;
+  if (nbv >= i) nbv = -1;
+  const unsigned long long valid = __ballot(nbv >= 0);
+  const int k = __popcll(valid);
+  const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(valid >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)valid, 0));
+  if (nbv >= 0) nbs[rank] = nbv;
+  wave_sync();
+  const int nbc = (lane < k) ? nbs[lane] : -1;
+  wave_sync();
+  if (lane < 32) {
+    const int rowpt = (lane < k) ? nbc : (lane == k ? (int)i : -1);
+    nbs[lane] = rowpt;
+    for (int dd = 0; dd < p.d; ++dd) xs[lane * p.d + dd] = rowpt >= 0 ? X[(int64_t)rowpt * p.d + dd] : 0.0;
+    As[lane] = (lane < k) ? Ain[i * mv + lane] : T(0);
+  }
+  const T* src = Lin + (size_t)i * ls;
+  for (int q = lane; q < k * (k + 1) / 2; q += 64) {
+    int a, b;
+    tri_index(q, a, b);
+    Ls[a][b] = src[q];
+  }
+  __syncthreads();
+  return k;
+}
+
+// Adjoint of the per-point factor (reverse mode of steps 1-4), from the
+// forward pass's A_i, D_i and the rows of L_R it stored (no Gram or
+// Cholesky again). Inputs: the cotangent of U, Ubar = U M'^{-1} - e w^T, and
+// of yt, e = yt - U w (w = M'^{-1} U^T yt), from the Woodbury step, and
+// Vr = L_m^{-1} dK(Z,X)/drange. With ub = Ubar_i / sqrt(D_i):
 //   Dbar = 1/(2D) - (Ubar_i.U_i + e_i yt_i) / (2D)
 //   Abar_j = -ub.V_{N_j} - (e_i / sqrt(D)) y_{N_j}
 //   rho = R^{-1} Abar - Dbar A,  rbar = rho - Dbar A,  Rbar = -rho A^T
@@ -324,21 +366,25 @@ __global__ __launch_bounds__(64) void k_factor(const double* __restrict__ X, con
 //                             - (sqrt(D) beta_i) U_i^T].
 // tpart[i] = (d/dsigma1^2, d/drange, d/ds2) of the covariance entries of
 // R_i, r_i, c_ii plus the K(Z,X) dots.
-template <typename T, typename S, int NBLK>
-__global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X, const S* __restrict__ V,
+// (6 waves per SIMD asked of the register allocator: the FP32 and BF16-input
+// forms then fit 75-76 VGPRs without spills; the FP64 form takes 83, 5 waves)
+template <typename T, typename S>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_factor_bwd(const double* __restrict__ X, const S* __restrict__ V,
                                                    const S* __restrict__ Vr, const int32_t* __restrict__ nbr,
                                                    const double* __restrict__ y, const T* __restrict__ U,
                                                    const T* __restrict__ Ubar, const double* __restrict__ e,
                                                    const double* __restrict__ yt, const double* __restrict__ Dfwd,
+                                                   const T* __restrict__ Ain, const T* __restrict__ Lin, int ls,
                                                    int64_t n, int mp, int mv, CovParams p_in, T* __restrict__ Q1,
                                                    T* __restrict__ Gs, T* __restrict__ Bs, double* __restrict__ tpart,
-                                                   int* status, Batch bt, const int* __restrict__ perm) {
-  __shared__ PointShared<T> sh;
-  extern __shared__ double xs[];  // 32 x d coordinates (dynamic)
+                                                   Batch bt, const int* __restrict__ perm) {
+  typedef typename Vec4<T>::type T4;
+  __shared__ T Ls[32][33];   // rows 0..k-1 of L_R
+  __shared__ T As[32];       // A_i
+  __shared__ int nbs[32];    // row -> point (N(i) then i)
+  __shared__ T ubv_s[32];    // ub . V_{row}
   __shared__ T rho_s[32];
-  T Lrow[32];
-  int k;
-  T D;
+  extern __shared__ double xs[];  // 32 x d coordinates (dynamic)
   const int lane = threadIdx.x;
   const int myrow = lane & 31;
   const int64_t i = perm ? (int64_t)perm[blockIdx.x] : (int64_t)blockIdx.x;
@@ -357,33 +403,53 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
     }
     p = q.cp;
   }
-  const T rsd = T(1) / sqrt(T(Dfwd[i]));
-  if (!factor_point<T, S, NBLK>(X, V, nbr, i, mp, mv, p, sh, xs, Lrow, k, D, status, Ubar + (size_t)i * mp, rsd)) {
-    if (lane == 0) tpart[i * 3] = tpart[i * 3 + 1] = tpart[i * 3 + 2] = __builtin_nan("");
-    return;
+  const int k = load_point_factor<T>(X, nbr, Ain, Lin, ls, i, mv, p, nbs, xs, As, Ls);
+  const T D = T(Dfwd[i]);
+  const T rsd = T(1) / sqrt(D);
+  // ub . V_{row j} for the rows j = 0..k: two lanes per row, each over half
+  // of the columns
+  {
+    const int j = lane >> 1, h = lane & 1;
+    T acc = 0;
+    if (j <= k) {
+      const S* vr = V + (size_t)nbs[j] * mp;
+      const T* ur = Ubar + (size_t)i * mp;
+      const int half = mp >> 1, l1 = (h + 1) * half;
+      for (int l0 = h * half; l0 < l1; l0 += 16) {  // four steps' loads in flight at a time
+        T4 a[4], b[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int l = min(l0 + 4 * t, l1 - 4);
+          a[t] = ld4(vr + l);
+          b[t] = ld4(ur + l);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (l0 + 4 * t < l1) acc += (a[t][0] * b[t][0] + a[t][1] * b[t][1]) + (a[t][2] * b[t][2] + a[t][3] * b[t][3]);
+      }
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    if (h == 0) ubv_s[j] = acc * rsd;
   }
-  T (*Ls)[33] = sh.GL;
+  __syncthreads();
   const T sd = sqrt(D);
-  // ub.V_{N_j} = GL[k+1][j], ub.V_i = GL[k+1][k];  Ubar_i.U_i = ub.V_i - sum_j A_j ub.V_{N_j}
-  const T ubv = (lane < k) ? sh.GL[k + 1][myrow] : T(0);
-  T ubU = (lane < k) ? -sh.As[myrow] * ubv : T(0);
-  ubU = wave_sum(ubU) + sh.GL[k + 1][k];
+  // Ubar_i.U_i / sqrt(D) = ub.V_i - sum_j A_j ub.V_{N_j}
+  const T ubv = (lane < k) ? ubv_s[myrow] : T(0);
+  T ubU = (lane < k) ? -As[myrow] * ubv : T(0);
+  ubU = wave_sum(ubU) + ubv_s[k];
   const T ei = T(e[i]), yti = T(yt[i]);
   const T Dbar = T(0.5) / D - T(0.5) * (ubU + ei * yti) / D;
   const T tbar = ei * rsd;
-  const T Abar = (lane < k) ? -ubv - tbar * T(y[sh.nbs[myrow]]) : T(0);
-  // z = L_R^{-1} Abar (lane a holds row a of L in Lrow)
-  const T rdiag = recip(Ls[myrow][myrow]);  // only lanes < k use theirs
+  const T Abar = (lane < k) ? -ubv - tbar * T(y[nbs[myrow]]) : T(0);
+  // z = L_R^{-1} Abar
+  const T rdiag = (lane < k) ? recip(Ls[myrow][myrow]) : T(0);
   T accz = Abar;
   T z = 0;
-#pragma unroll
-  for (int q = 0; q < 32; ++q) {
-    if (q < k) {
-      const T zq = lane_bcast(accz * rdiag, q);
-      const int lid = fresh_lane();
-      if (lid == q) z = zq;
-      if (lid > q && lid < k) accz -= Lrow[q] * zq;
-    }
+  for (int q = 0; q < k; ++q) {
+    const T zq = lane_bcast(accz * rdiag, q);
+    const int lid = fresh_lane();
+    if (lid == q) z = zq;
+    if (lid > q && lid < k) accz -= Ls[myrow][q] * zq;
   }
   // a' = L_R^{-T} z
   T acc = (lane < k) ? z : T(0);
@@ -394,7 +460,7 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
     if (lid == a) ap = xa;
     if (lid < a) acc -= Ls[a][myrow] * xa;
   }
-  const T Aj = (lane < k) ? sh.As[myrow] : T(0);
+  const T Aj = (lane < k) ? As[myrow] : T(0);
   const T rho = (lane < k) ? ap - Dbar * Aj : T(0);
   if (lane < 32) rho_s[lane] = rho;
   __syncthreads();
@@ -413,14 +479,14 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
       while (a * (a + 1) / 2 > e) --a;
       const int b = e - a * (a + 1) / 2;
       if (a == b) {
-        if (a < k) ts -= rho_s[a] * sh.As[a];
+        if (a < k) ts -= rho_s[a] * As[a];
         continue;
       }
       const T t2 = scaled_sqdist<T>(p, xs + a * p.d, xs + b * p.d);
       const T pv = cov_profile<T>(p.kernel, t2);
       const T dv = T(p.sigma1_sq) * cov_profile_dls<T>(p.kernel, t2, T(p.inv_ls[0]));
       // a == k: the r_i entry of row b; else the pair (a, b) of R_i, both orders
-      const T wgt = (a == k) ? rho_s[b] - Dbar * sh.As[b] : -(rho_s[a] * sh.As[b] + rho_s[b] * sh.As[a]);
+      const T wgt = (a == k) ? rho_s[b] - Dbar * As[b] : -(rho_s[a] * As[b] + rho_s[b] * As[a]);
       ts += wgt * pv;
       tr += wgt * dv;
     }
@@ -437,14 +503,23 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
     const TW Vri = ldw(Vr + o);
     const TW u = *reinterpret_cast<const TW*>(Ubar + o) * rsd;
     TW al = TW(0), be = TW(0), alr = TW(0), ber = TW(0);
-    for (int j = 0; j < k; ++j) {
-      const size_t oj = (size_t)sh.nbs[j] * mp + l;
-      const TW v = ldw(V + oj), vr = ldw(Vr + oj);
-      const T aj = sh.As[j], rj = rho_s[j];
-      al += aj * v;
-      be += rj * v;
-      alr += aj * vr;
-      ber += rj * vr;
+    for (int j0 = 0; j0 < k; j0 += 2) {  // two rows' loads in flight at a time
+      TW v[2], vr[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const size_t oj = (size_t)nbs[min(j0 + t, k - 1)] * mp + l;
+        v[t] = ldw(V + oj);
+        vr[t] = ldw(Vr + oj);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const bool in = j0 + t < k;
+        const T aj = in ? As[j0 + t] : T(0), rj = in ? rho_s[j0 + t] : T(0);
+        al += aj * v[t];
+        be += rj * v[t];
+        alr += aj * vr[t];
+        ber += rj * vr[t];
+      }
     }
     const TW Gl = be - u + Dbar * Vi;
     const TW Sl = u - T(2) * Dbar * Vi - be + Dbar * al;
@@ -483,25 +558,23 @@ __global__ __launch_bounds__(64) void k_factor_bwd(const double* __restrict__ X,
 template <typename T, int NBLK>
 __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X, const T* __restrict__ V,
                                                    const T* __restrict__ dV, const int32_t* __restrict__ nbr,
-                                                   const T* __restrict__ U, int64_t n, int mp, int mv, CovParams p,
-                                                   int which, T* __restrict__ dA, double* __restrict__ dD,
-                                                   T* __restrict__ dU, int* status, const int* __restrict__ perm) {
+                                                   const T* __restrict__ U, const double* __restrict__ Dfwd,
+                                                   const T* __restrict__ Ain, const T* __restrict__ Lin, int ls,
+                                                   int64_t n, int mp, int mv, CovParams p, int which,
+                                                   T* __restrict__ dA, double* __restrict__ dD, T* __restrict__ dU,
+                                                   const int* __restrict__ perm) {
   typedef typename Vec4<T>::type T4;
   typedef typename Acc4<T>::type A4;
   __shared__ PointShared<T> sh;
   extern __shared__ double xs[];  // 32 x d coordinates (dynamic)
   __shared__ T Xc[32][33];  // cross Gram dV_a . V_b
   __shared__ T dAs[32];
-  T Lrow[32];
-  int k;
-  T D;
   const int lane = threadIdx.x;
   const int myrow = lane & 31;
   const int64_t i = perm ? (int64_t)perm[blockIdx.x] : (int64_t)blockIdx.x;
-  if (!factor_point<T, T, NBLK>(X, V, nbr, i, mp, mv, p, sh, xs, Lrow, k, D, status)) {
-    if (lane == 0) dD[i] = __builtin_nan("");
-    return;
-  }
+  // the forward pass's A_i, D_i and rows of L_R (no Gram or Cholesky again)
+  const int k = load_point_factor<T>(X, nbr, Ain, Lin, ls, i, mv, p, sh.nbs, xs, sh.As, sh.GL);
+  const T D = T(Dfwd[i]);
   T (*Ls)[33] = sh.GL;
   // cross Gram (rows = sh.nbs, 0..k)
   if (dV != nullptr) {
@@ -546,7 +619,6 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
   // dC over the lower triangle of rows 0..k, entries dealt to the lanes
   // (packed row order), written in place over the cross Gram (entry (a, b)
   // reads only Xc[a][b] and Xc[b][a]); then row `lane` (lanes 0..k), full
-  const bool active = lane <= k;
   {
     const int ne = (k + 1) * (k + 2) / 2;
     for (int e = lane; e < ne; e += 64) {
@@ -568,34 +640,23 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
     }
   }
   __syncthreads();
-  T dCrow[32];
-#pragma unroll
-  for (int b = 0; b < 32; ++b)
-    dCrow[b] = (active && b <= k) ? ((b <= lane) ? Xc[myrow][b] : Xc[b][myrow]) : T(0);
+  // entry (a, b) of dC from its stored lower triangle
+  auto dCat = [&](int a, int b) -> T { return (b <= a) ? Xc[a][b] : Xc[b][a]; };
   // rhs_a = dr_a - sum_b dR_ab A_b  (lanes a < k);  dD pieces
   T rhs = 0, drA = 0, AdRA = 0;
   if (lane < k) {
     T sdr = 0;
-#pragma unroll
-    for (int b = 0; b < 32; ++b)
-      if (b < k) sdr += dCrow[b] * sh.As[b];
-    rhs = dCrow[k] - sdr;
-    drA = dCrow[k] * sh.As[lane];
+    for (int b = 0; b < k; ++b) sdr += dCat(myrow, b) * sh.As[b];
+    const T drk = Xc[k][myrow];  // dr_a = dC[k][a], a < k
+    rhs = drk - sdr;
+    drA = drk * sh.As[lane];
     AdRA = sh.As[lane] * sdr;
   }
-  T dc = __shfl(dCrow[0], 0, 64);
-  {
-    // dC[k][k] sits in lane k, entry k
-    T mine = 0;
-#pragma unroll
-    for (int b = 0; b < 32; ++b)
-      if (b == k) mine = dCrow[b];
-    dc = __shfl(mine, k, 64);
-  }
+  const T dc = Xc[k][k];
   drA = wave_sum(drA);
   AdRA = wave_sum(AdRA);
   const T dDi = dc - T(2) * drA + AdRA;
-  // dA = L_R^{-T} L_R^{-1} rhs  (lane a holds row a of L in Lrow)
+  // dA = L_R^{-T} L_R^{-1} rhs  (lane a reads row a of L from LDS)
   const T rdiag = recip(Ls[myrow][myrow]);  // only lanes < k use theirs
   T accz = rhs, z = 0;
 #pragma unroll
@@ -604,7 +665,7 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
       const T zq = lane_bcast(accz * rdiag, q);
       const int lid = fresh_lane();
       if (lid == q) z = zq;
-      if (lid > q && lid < k) accz -= Lrow[q] * zq;
+      if (lid > q && lid < k) accz -= Ls[myrow][q] * zq;
     }
   }
   T acc = (lane < k) ? z : T(0), x = 0;
@@ -636,21 +697,22 @@ __global__ __launch_bounds__(64) void k_factor_jvp(const double* __restrict__ X,
 
 template <typename T>
 void launch_factor_jvp(hipStream_t st, const double* X, const T* V, const T* dV, const int32_t* nbr, const T* U,
-                       int64_t n, int mp, int mv, const CovParams& p, int which, T* dA, double* dD, T* dU,
-                       int* status, const int* perm) {
+                       const double* D, const T* A, const T* Lfac, int64_t n, int mp, int mv, const CovParams& p,
+                       int which, T* dA, double* dD, T* dU, const int* perm) {
+  const int ls = factor_l_stride(mv);
   if (mv + 1 <= 16)
-    hipLaunchKernelGGL((k_factor_jvp<T, 1>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, dV, nbr, U, n, mp, mv, p,
-                       which, dA, dD, dU, status, perm);
+    hipLaunchKernelGGL((k_factor_jvp<T, 1>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, dV,
+                       nbr, U, D, A, Lfac, ls, n, mp, mv, p, which, dA, dD, dU, perm);
   else
-    hipLaunchKernelGGL((k_factor_jvp<T, 2>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, dV, nbr, U, n, mp, mv, p,
-                       which, dA, dD, dU, status, perm);
+    hipLaunchKernelGGL((k_factor_jvp<T, 2>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, dV,
+                       nbr, U, D, A, Lfac, ls, n, mp, mv, p, which, dA, dD, dU, perm);
 }
 template void launch_factor_jvp<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
-                                        const double*, int64_t, int, int, const CovParams&, int, double*, double*,
-                                        double*, int*, const int*);
+                                        const double*, const double*, const double*, const double*, int64_t, int, int,
+                                        const CovParams&, int, double*, double*, double*, const int*);
 template void launch_factor_jvp<float>(hipStream_t, const double*, const float*, const float*, const int32_t*,
-                                       const float*, int64_t, int, int, const CovParams&, int, float*, double*,
-                                       float*, int*, const int*);
+                                       const float*, const double*, const float*, const float*, int64_t, int, int,
+                                       const CovParams&, int, float*, double*, float*, const int*);
 
 // Factor rows of prediction points (Prop. 2.1, with B_p = I): eq. D_A_Vecchia
 // for prediction point j over its training neighbours nbrp[j] (all < n),
@@ -668,8 +730,8 @@ __global__ __launch_bounds__(64) void k_pred_factor(const double* __restrict__ X
   T D;
   const int lane = threadIdx.x;
   const int64_t j = blockIdx.x;
-  if (!factor_point<T, T, NBLK>(X, V, nullptr, n, mp, mv, p, sh, xs, Lrow, k, D, status, nullptr, T(1),
-                             Vp + (size_t)j * mp, Xp + (size_t)j * p.d, nbrp + (size_t)j * mv)) {
+  if (!factor_point<T, T, NBLK>(X, V, nullptr, n, mp, mv, p, sh, xs, Lrow, k, D, status, Vp + (size_t)j * mp,
+                                Xp + (size_t)j * p.d, nbrp + (size_t)j * mv)) {
     if (lane == 0) Dp[j] = __builtin_nan("");
     return;
   }
@@ -740,13 +802,14 @@ __global__ void k_ytilde(const T* __restrict__ A, const double* __restrict__ D, 
 
 template <typename T, typename S>
 void launch_factor(hipStream_t st, const double* X, const S* V, const int32_t* nbr, int64_t n, int mp, int mv,
-                   const CovParams& p, T* A, double* D, T* U, int* status, Batch bt, const int* perm) {
+                   const CovParams& p, T* A, double* D, T* U, int* status, Batch bt, const int* perm, T* Lfac) {
+  const int ls = factor_l_stride(mv);
   if (mv + 1 <= 16)
-    hipLaunchKernelGGL((k_factor<T, S, 1>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, nbr, n, mp, mv, p, A, D, U, status,
-                       bt, perm);
+    hipLaunchKernelGGL((k_factor<T, S, 1>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, nbr, n,
+                       mp, mv, p, A, D, U, status, bt, perm, Lfac, ls);
   else
-    hipLaunchKernelGGL((k_factor<T, S, 2>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, nbr, n, mp, mv, p, A, D, U, status,
-                       bt, perm);
+    hipLaunchKernelGGL((k_factor<T, S, 2>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, nbr, n,
+                       mp, mv, p, A, D, U, status, bt, perm, Lfac, ls);
 }
 
 template <typename T>
@@ -756,11 +819,12 @@ void launch_ytilde(hipStream_t st, const T* A, const double* D, const int32_t* n
 }
 
 template void launch_factor<double>(hipStream_t, const double*, const double*, const int32_t*, int64_t, int, int,
-                                    const CovParams&, double*, double*, double*, int*, Batch, const int*);
+                                    const CovParams&, double*, double*, double*, int*, Batch, const int*, double*);
 template void launch_factor<float>(hipStream_t, const double*, const float*, const int32_t*, int64_t, int, int,
-                                   const CovParams&, float*, double*, float*, int*, Batch, const int*);
+                                   const CovParams&, float*, double*, float*, int*, Batch, const int*, float*);
 template void launch_factor<float, bf16s>(hipStream_t, const double*, const bf16s*, const int32_t*, int64_t, int, int,
-                                          const CovParams&, float*, double*, float*, int*, Batch, const int*);
+                                          const CovParams&, float*, double*, float*, int*, Batch, const int*,
+                                          float*);
 template void launch_ytilde<double>(hipStream_t, const double*, const double*, const int32_t*, const double*, int64_t,
                                     int, double*);
 template void launch_ytilde<float>(hipStream_t, const float*, const double*, const int32_t*, const double*, int64_t,
@@ -768,25 +832,23 @@ template void launch_ytilde<float>(hipStream_t, const float*, const double*, con
 
 template <typename T, typename S>
 void launch_factor_bwd(hipStream_t st, const double* X, const S* V, const S* Vr, const int32_t* nbr, const double* y,
-                       const T* U, const T* Ubar, const double* e, const double* yt, const double* D, int64_t n,
-                       int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status,
-                       Batch bt, const int* perm) {
-  if (mv + 2 <= 16)
-    hipLaunchKernelGGL((k_factor_bwd<T, S, 1>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
-                       n, mp, mv, p, Q1, Gs, Bs, tpart, status, bt, perm);
-  else
-    hipLaunchKernelGGL((k_factor_bwd<T, S, 2>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, Vr, nbr, y, U, Ubar, e, yt, D,
-                       n, mp, mv, p, Q1, Gs, Bs, tpart, status, bt, perm);
+                       const T* U, const T* Ubar, const double* e, const double* yt, const double* D, const T* A,
+                       const T* Lfac, int64_t n, int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs,
+                       double* tpart, int* status, Batch bt, const int* perm) {
+  (void)status;  // the forward pass has checked every per-point system
+  hipLaunchKernelGGL((k_factor_bwd<T, S>), dim3((unsigned)n), dim3(64), 32 * p.d * sizeof(double), st, X, V, Vr, nbr,
+                     y, U, Ubar, e, yt, D, A, Lfac, factor_l_stride(mv), n, mp, mv, p, Q1, Gs, Bs, tpart, bt, perm);
 }
 template void launch_factor_bwd<double>(hipStream_t, const double*, const double*, const double*, const int32_t*,
                                         const double*, const double*, const double*, const double*, const double*,
-                                        const double*, int64_t, int, int, const CovParams&, double*, double*, double*,
-                                        double*, int*, Batch, const int*);
+                                        const double*, const double*, const double*, int64_t, int, int,
+                                        const CovParams&, double*, double*, double*, double*, int*, Batch, const int*);
 template void launch_factor_bwd<float>(hipStream_t, const double*, const float*, const float*, const int32_t*,
                                        const double*, const float*, const float*, const double*, const double*,
-                                       const double*, int64_t, int, int, const CovParams&, float*, float*, float*,
-                                       double*, int*, Batch, const int*);
+                                       const double*, const float*, const float*, int64_t, int, int,
+                                       const CovParams&, float*, float*, float*, double*, int*, Batch, const int*);
 template void launch_factor_bwd<float, bf16s>(hipStream_t, const double*, const bf16s*, const bf16s*, const int32_t*,
                                               const double*, const float*, const float*, const double*,
-                                              const double*, const double*, int64_t, int, int, const CovParams&,
-                                              float*, float*, float*, double*, int*, Batch, const int*);
+                                              const double*, const double*, const float*, const float*, int64_t, int,
+                                              int, const CovParams&, float*, float*, float*, double*, int*, Batch,
+                                              const int*);

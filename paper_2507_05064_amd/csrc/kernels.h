@@ -34,10 +34,13 @@ void launch_knn_pred(hipStream_t st, const double* Xq, const double* Vq, const d
 
 // factor.hip
 // S: storage type of V (T, or bf16s in the BF16-input form with T = float)
+// Lfac (may be NULL): rows 0..k-1 of each point's Cholesky factor L_R, packed
+// row by row at Lfac + i * factor_l_stride(mv), for the adjoint
+inline int factor_l_stride(int mv) { return mv > 0 ? mv * (mv + 1) / 2 : 1; }
 template <typename T, typename S = T>
 void launch_factor(hipStream_t st, const double* X, const S* V, const int32_t* nbr, int64_t n, int mp, int mv,
                    const CovParams& p, T* A, double* D, T* U, int* status, Batch bt = Batch{nullptr, nullptr},
-                   const int* perm = nullptr);
+                   const int* perm = nullptr, T* Lfac = nullptr);
 template <typename T>
 void launch_ytilde(hipStream_t st, const T* A, const double* D, const int32_t* nbr, const double* y, int64_t n,
                    int mv, double* yt);
@@ -53,11 +56,12 @@ void launch_vec_reduce(hipStream_t st, const double* partial, int nchunk, int le
                        Batch bt = Batch{nullptr, nullptr}, int nprob = 1);
 
 // factor.hip (adjoint)
+// A, Lfac: the forward pass's A and packed L_R rows (launch_factor with Lfac)
 template <typename T, typename S = T>
 void launch_factor_bwd(hipStream_t st, const double* X, const S* V, const S* Vr, const int32_t* nbr, const double* y,
-                       const T* U, const T* Ubar, const double* e, const double* yt, const double* D, int64_t n,
-                       int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs, double* tpart, int* status,
-                       Batch bt = Batch{nullptr, nullptr}, const int* perm = nullptr);
+                       const T* U, const T* Ubar, const double* e, const double* yt, const double* D, const T* A,
+                       const T* Lfac, int64_t n, int mp, int mv, const CovParams& p, T* Q1, T* Gs, T* Bs,
+                       double* tpart, int* status, Batch bt = Batch{nullptr, nullptr}, const int* perm = nullptr);
 
 // laplace.hip: FITC preconditioner pieces
 template <typename T>
@@ -186,10 +190,11 @@ void launch_add_ve(hipStream_t st, const T* V, const double* e1, const double* r
 void launch_direct_rhs(hipStream_t st, const double* W, const double* b, const double* g, int64_t n,
                        double* out);
 
+// D, A, Lfac: the forward pass's D, A and packed L_R rows (launch_factor with Lfac)
 template <typename T>
 void launch_factor_jvp(hipStream_t st, const double* X, const T* V, const T* dV, const int32_t* nbr, const T* U,
-                       int64_t n, int mp, int mv, const CovParams& p, int which, T* dA, double* dD, T* dU,
-                       int* status, const int* perm = nullptr);
+                       const double* D, const T* A, const T* Lfac, int64_t n, int mp, int mv, const CovParams& p,
+                       int which, T* dA, double* dD, T* dU, const int* perm = nullptr);
 
 template <typename T>
 void launch_pred_factor(hipStream_t st, const double* X, const T* V, const double* Xp, const T* Vp,
@@ -240,6 +245,21 @@ int launch_diag_ste(hipStream_t st, const double* us, const double* qs, int ell,
 void launch_diag_final(hipStream_t st, const double* Sh, const double* Sg, const double* tr, double c, int ell,
                        int64_t n, double* out);
 void launch_sum_cols(hipStream_t st, const double* part, int nb, int cols, double* out);
+// gradient in the form of eq. pcls2 with the FITC preconditioner (fitcgrad.hip)
+int launch_fitc_diag_ste(hipStream_t st, const double* us, const double* qs, int ell, const double* W,
+                         const double* dW, const double* E, const double* yv, int64_t n, double* Sh, double* Sg,
+                         double* tr, double* part);
+void launch_fitc_diag_final(hipStream_t st, const double* Sh, const double* Sg, const double* tr, double c, int ell,
+                            const double* W, const double* dW, int64_t n, double* dldb, double* x);
+void launch_fitc_vsol(hipStream_t st, const double* x, const double* y, const double* W, int64_t n, double* v);
+void launch_scale_rows_multi(hipStream_t st, const double* D, const double* x, int64_t n, int L, double* out);
+void launch_fitc_bilin_multi(hipStream_t st, const double* ax, const double* ay, const double* dbcx,
+                             const double* dbcy, const double* dD, const double* q, const double* sd, int64_t n, int L,
+                             double* part, double* out1, double* out2);
+void launch_mdot_cols_add(hipStream_t st, const double* a, const double* b, const double* c, const double* d, int mp,
+                          int L, double scale, double* out);
+int launch_fitc_trp(hipStream_t st, const double* E, const double* yv, const double* vdv, const double* ydv,
+                    double dsig, int64_t n, double* sd, double* part);
 
 // ---- many right-hand sides (block.hip): blocks of L <= kBlockCols vectors, n x L row-major
 constexpr int kBlockCols = 64;

@@ -319,7 +319,7 @@ class VifContext:
     def laplace_predict(self, y: torch.Tensor, mode: torch.Tensor, Xp: torch.Tensor, nbrp: torch.Tensor,
                         eps_n: torch.Tensor, eps_m: Optional[torch.Tensor]):
         """(omega_p, diag(Omega_p), total CG iterations): the latent predictive
-        mean and variances of Prop. 3.1 at the mode, the variances by Alg. 1
+        mean and variances of Prop. 3.1 at the mode, eq. Part2 by simulation (SBPV)
         with ell = eps_n.shape[0] // 2 samples."""
         ell = eps_n.shape[0] // 2
         mu = torch.empty(Xp.shape[0], dtype=torch.float64, device="cuda")

@@ -61,10 +61,11 @@ def make_problem(w: vi.Workload, problem: int, theta_scale=(1.0, 1.0), cg_tol: f
 
 
 def context_for(p: Problem, cg_tol: float = 1e-6, cg_maxit: int = 1000, newton_tol: float = 1e-9,
-                max_pred: int = 0) -> VifContext:
+                max_pred: int = 0, max_probes: int = 0) -> VifContext:
     w = p.w
     ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=w.likelihood, precision="fp64", tau_m=w.tau_m,
-                     cg_tol=cg_tol, cg_maxit=cg_maxit, newton_tol=newton_tol, max_pred=max_pred)
+                     cg_tol=cg_tol, cg_maxit=cg_maxit, newton_tol=newton_tol, max_pred=max_pred,
+                     max_probes=max_probes)
     ctx.build_factor(p.X, p.Z, p.nbr, p.theta)
     return ctx
 

@@ -55,7 +55,11 @@ def test_gaussian_ard_gradient_matches_oracle(n, d, m, mv, prec):
     assert len(set(np.round(g_o[1:-1], 6))) == d
 
 
-def test_laplace_ard_gradient_matches_oracle():
+@pytest.mark.parametrize("precond", ["vifdu", "fitc"])
+def test_laplace_ard_gradient_matches_oracle(precond):
+    """The Laplace gradient with respect to (sigma1^2, three length scales,
+    s2) with the VIFDU (eq. pcls1 form) or the FITC preconditioner (eq.
+    pcls2 form) against the oracle's estimator on the same probes."""
     from paper_2507_05064_amd.vif import VifContext
     n, d, m, mv, ell = 800, 3, 20, 8, 4
     ls = np.array([0.2, 0.35, 0.5])
@@ -75,13 +79,19 @@ def test_laplace_ard_gradient_matches_oracle():
     W = lo.grad_hess(lo.BERNOULLI_LOGIT, y, mode)[1]
     g = np.random.default_rng(n + 9)
     e1, e2, e3 = g.standard_normal((n, ell)), g.standard_normal((n, ell)), g.standard_normal((m, ell))
-    Zp = lo.vifdu_probes(prior, W, e1, e2, e3)
-    slq = lo.laplace_nll_slq(prior, lo.BERNOULLI_LOGIT, y, mode, Zp, tol=1e-11)
-    ref = lo.laplace_grad_ste(prior, tg, lo.BERNOULLI_LOGIT, y, mode, slq, tol=1e-11)
-    print(f"[gpu] Laplace ARD gradient n={n} d={d} m={m} m_v={mv} ell={ell}", flush=True)
+    if precond == "fitc":
+        Zp = lo.fitc_probes(model, prior, W, e1, e3)
+        slq = lo.laplace_nll_slq_fitc(model, prior, lo.BERNOULLI_LOGIT, y, mode, Zp, tol=1e-11)
+        ref = lo.laplace_grad_ste_fitc(model, prior, tg, lo.BERNOULLI_LOGIT, y, mode, slq, tol=1e-11)
+    else:
+        Zp = lo.vifdu_probes(prior, W, e1, e2, e3)
+        slq = lo.laplace_nll_slq(prior, lo.BERNOULLI_LOGIT, y, mode, Zp, tol=1e-11)
+        ref = lo.laplace_grad_ste(prior, tg, lo.BERNOULLI_LOGIT, y, mode, slq, tol=1e-11)
+    print(f"[gpu] Laplace ARD gradient n={n} d={d} m={m} m_v={mv} ell={ell} {precond}", flush=True)
     ctx = VifContext(n, d, m, mv, kernel="gaussian_ard", likelihood=lo.BERNOULLI_LOGIT, precision="fp64",
                      tau_m=w.tau_m, cg_tol=1e-11, cg_maxit=3000, max_probes=ell)
     ctx.build_factor(to_dev(X), to_dev(Z), nbr_to_dev(nbr), model.theta)
+    ctx.set_preconditioner(precond)
     eps_n = np.empty((2 * ell, n))
     eps_n[0::2], eps_n[1::2] = e1.T, e2.T
     nll, grad = ctx.laplace_nll_grad(to_dev(y), to_dev(mode), to_dev(eps_n), to_dev(e3.T))

@@ -116,8 +116,7 @@ def test_fitc_laplace_nll_matches_oracle(lik, n, m, mv, ell):
     """Laplace NLL with the log-det of eq. slq_v2 (FITC preconditioner, probes
     z = D_V^{1/2} e1 + V^T e3) against the oracle with the same probes: the
     CG coefficients, Lanczos quadrature and closed-form terms agree to the
-    FP64 bars of the VIFDU form (NLL 1e-8, log-det 1e-7 relative); the
-    gradient call after it still runs with VIFDU."""
+    FP64 bars of the VIFDU form (NLL 1e-8, log-det 1e-7 relative)."""
     from paper_2507_05064_amd.vif import VifContext
     from tests.test_laplace_slq_pins import _latent
     model, X, Z, nbr, prior, y, mode = _latent(n=n, m=m, mv=mv, lik=lik, seed=n)
@@ -140,7 +139,55 @@ def test_fitc_laplace_nll_matches_oracle(lik, n, m, mv, ell):
     # the estimate targets the same quantity as the VIFDU form: both lie near the dense value
     dense = lo.laplace_nll_dense(prior, lik, y, mode)
     assert abs(nll - dense) <= 0.05 * abs(dense)
-    nll_g, grad = ctx.laplace_nll_grad(to_dev(y), to_dev(mode), to_dev(eps_n), dm)
-    Zv = lo.vifdu_probes(prior, W, e1, e2, e3)
-    refv = lo.laplace_nll_slq(prior, lik, y, mode, Zv, tol=1e-11)
-    assert abs(nll_g - refv.nll) <= 1e-8 * abs(refv.nll), (nll_g, refv.nll)
+
+
+@pytest.mark.parametrize("lik,n,m,mv,ell,prec", [(lo.BERNOULLI_LOGIT, 700, 17, 8, 6, "fp64"),
+                                                 (lo.POISSON_LOG, 1500, 30, 12, 4, "fp64"),
+                                                 (lo.POISSON_LOG, 800, 0, 10, 3, "fp64"),
+                                                 (lo.GAMMA_LOG, 800, 20, 8, 4, "fp64"),
+                                                 (lo.POISSON_LOG, 800, 20, 8, 5, "fp32")])
+def test_fitc_laplace_grad_matches_oracle(lik, n, m, mv, ell, prec):
+    """Laplace NLL + gradient with the FITC preconditioner (eq. pcls2 form of
+    the trace estimates, App. D; the preconditioner's derivative terms of
+    App. E.2) against the oracle's estimator on the same probes: FP64 within
+    1e-6 of max|g| and the NLL within 1e-8 relative (CG to 1e-11 on both
+    sides), as for VIFDU. FP32 factor: the gradient within 1e-2 of max|g|;
+    the NLL within the first-order effect of the rounding on
+    1/2 log det(A2), A2 = W^{-1} + Sigma_dagger: rounding V and A to binary32
+    (unit u) moves V^T V by <= 2u ||Sigma|| and B^{-1} D B^{-T} by about
+    2u cond(B) ||Sigma|| in norm, and log det A2 by tr(A2^{-1}) times that:
+    |dNLL| <= 1/2 u (2 + 2 cond(B)) ||Sigma||_2 tr(A2^{-1}). Unlike the VIFDU
+    form (W + Sigma^{-1}, no B^{-1}), the FITC form applies Sigma_dagger itself,
+    whose B^{-1} factors carry the rounding of A with cond(B)."""
+    from paper_2507_05064_amd.vif import VifContext
+    from tests.test_laplace_slq_pins import _latent
+    shape = 2.5 if lik == lo.GAMMA_LOG else 1.0
+    model, X, Z, nbr, prior, y, mode = _latent(n=n, m=m, mv=mv, lik=lik, seed=n + 5, shape=shape)
+    ind = vo.inducing(model, X, Z)
+    tg = vo.factor_tangents(model, X, Z, ind, nbr, prior.fac)
+    W = lo.grad_hess(lik, y, mode, shape)[1]
+    g = np.random.default_rng(n + 9)
+    e1, e2, e3 = g.standard_normal((n, ell)), g.standard_normal((n, ell)), g.standard_normal((m, ell))
+    Zp = lo.fitc_probes(model, prior, W, e1, e3)
+    slq = lo.laplace_nll_slq_fitc(model, prior, lik, y, mode, Zp, noise_var=shape, tol=1e-11)
+    ref = lo.laplace_grad_ste_fitc(model, prior, tg, lik, y, mode, slq, noise_var=shape, tol=1e-11)
+    print(f"[gpu] fitc laplace grad {lik} n={n} m={m} m_v={mv} ell={ell} {prec}", flush=True)
+    ctx = VifContext(n, 2, m, mv, kernel=model.kernel, likelihood=lik, precision=prec, cg_tol=1e-11, cg_maxit=3000,
+                     max_probes=ell, lik_param=shape)
+    ctx.build_factor(to_dev(X), to_dev(Z) if m else None, nbr_to_dev(nbr), model.theta)
+    ctx.set_preconditioner("fitc")
+    eps_n = np.empty((2 * ell, n))
+    eps_n[0::2], eps_n[1::2] = e1.T, e2.T
+    nll, grad = ctx.laplace_nll_grad(to_dev(y), to_dev(mode), to_dev(eps_n), to_dev(e3.T) if m else None)
+    if prec == "fp64":
+        assert abs(nll - slq.nll) <= 1e-8 * abs(slq.nll), (nll, slq.nll)
+        assert np.max(np.abs(grad - ref)) <= 1e-6 * np.max(np.abs(ref)), (grad, ref)
+    else:
+        S = lo.dense_cov(prior)
+        A2i = np.linalg.inv(np.diag(1.0 / W) + S)
+        u = 2.0 ** -24
+        bar = 0.5 * u * (2.0 + 2.0 * np.linalg.cond(lo.dense_B(prior))) * np.linalg.eigvalsh(S)[-1] * np.trace(A2i)
+        eg = np.max(np.abs(grad - ref)) / np.max(np.abs(ref))
+        print(f"[gpu]   fp32 nll err {abs(nll - slq.nll):.3e} (bar {bar:.3e}), grad err {eg:.3e}", flush=True)
+        assert abs(nll - slq.nll) <= bar, (nll, slq.nll, bar)
+        assert eg <= 1e-2, (grad, ref)

@@ -112,7 +112,7 @@ def test_laplace_predictive_mean_matches_oracle():
 
 @pytest.mark.parametrize("prec,m", [("fp64", 20), ("fp32", 20), ("fp64", 0)])
 def test_laplace_predictive_variances_match_oracle(prec, m):
-    """Prop. 3.1 with Alg. 1: vif_laplace_predict's diag(Omega_p) against the
+    """Prop. 3.1 with eq. Part2 by simulation: vif_laplace_predict's diag(Omega_p) against the
     oracle's SBPV estimator on the same standard normals (8 samples) at the
     oracle's mode, the oracle solving exactly and the GPU by CG to 1e-12:
     within 1e-6 of max var in FP64 (the latent jitter tau = 1e-6 leaves

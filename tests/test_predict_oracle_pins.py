@@ -219,9 +219,10 @@ def test_laplace_variance_without_curvature_is_the_prior_variance():
 
 
 def test_sbpv_is_unbiased():
-    """Alg. 1 (Prop. PropPredVar): the mean of z8 * z8 over many samples
-    approaches eq. Part2; each z8_p ~ N(0, Part2_p), so the standard error of
-    the mean of l squares is Part2_p sqrt(2 / l); bound at 5 of them."""
+    """The simulation estimate of eq. Part2 (Sec. 4.4): the mean of the
+    squared samples s = G w over many samples approaches eq. Part2; each s_p
+    ~ N(0, Part2_p), so the standard error of the mean of l squares is
+    Part2_p sqrt(2 / l); bound at 5 of them."""
     lat, X, Xp, Z, nbr, nbr_p, W = _latent_setup(n=60, npred=6, m=8, mv=4, seed=2)
     ell = 20000
     rng = np.random.default_rng(11)
