@@ -191,6 +191,33 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v), q))
 
 
+def pcg_leg(reps, log):
+    """Only the C3 mode solves from zero (VIFDU and FITC), for kernel traces
+    and counters of the solve kernels: no network, no prediction, no SLQ."""
+    import torch
+    import vif_inputs as vi
+    from paper_2507_05064_amd import warmstart as ws
+    prob = ws.make_problem(vi.config3(), 0)
+    ctx = ws.context_for(prob, cg_tol=1e-6)
+    ctx.build_factor(prob.X, prob.Z, prob.nbr, prob.theta)
+    out = {}
+    for form in ("vifdu", "fitc"):
+        ctx.set_preconditioner(form)
+        ms = []
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st, _ = ctx.laplace_mode(prob.y)
+            torch.cuda.synchronize()
+            if r > 0:
+                ms.append(1000.0 * (time.perf_counter() - t0))
+        out[form] = {"mode_ms_median": _pct(ms, 50), "pcg_iters_total": st["pcg_iters_total"],
+                     "newton_iters": st["newton_iters"]}
+        log(f"pcg {form}: {out[form]}")
+    ctx.close()
+    return out
+
+
 def laplace_leg(reps, warmup, log):
     """Mode time and iterations, zero start vs learned warm start (FP64)."""
     import torch
@@ -563,6 +590,8 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="hardware-counter mode: 5 FP32 factor builds of the C2 workload and 5 copies of a 1 GiB "
                          "buffer (the counters' scale reference), nothing timed")
+    ap.add_argument("--pcg-only", action="store_true",
+                    help="only the n = 200k mode solves from zero, VIFDU and FITC (for kernel traces and counters)")
     ap.add_argument("--c2-only", action="store_true",
                     help="only the n = 100k NLL + gradient step in its three forms (for kernel traces and counters)")
     ap.add_argument("--laplace-only", action="store_true",
@@ -585,6 +614,9 @@ def main():
     if args.laplace_only:
         print(json.dumps({"laplace": laplace_leg(args.laplace_reps, 1,
                                                  lambda msg: print(msg, file=sys.stderr, flush=True))}))
+        return
+    if args.pcg_only:
+        print(json.dumps({"pcg": pcg_leg(args.laplace_reps, lambda msg: print(msg, file=sys.stderr, flush=True))}))
         return
     X = vi.coords(w)
     Z = vi.inducing_points(w, X)

@@ -81,14 +81,17 @@ struct vif_ctx {
   int *rev_cnt = nullptr, *rev_ptr = nullptr, *rev_cur = nullptr, *rev_idx = nullptr;
   // level schedules of the sparse triangular solves with B and B^T
   int *fwd_order = nullptr, *fwd_lvl = nullptr, *bwd_order = nullptr, *bwd_lvl = nullptr;
-  int nlev_f = 0, nlev_b = 0;
-  std::vector<int> hfwd_lvl, hbwd_lvl;  // host copies of the level offsets
+  int *fwd_slvl = nullptr, *bwd_slvl = nullptr;  // level offsets with mid-size levels split in two
+  int nlev_f = 0, nlev_b = 0, nslev_f = 0, nslev_b = 0;
+  std::vector<int> hfwd_lvl, hbwd_lvl;    // host copies of the level offsets
+  std::vector<int> hfwd_slvl, hbwd_slvl;  // and of the split ones
   bool lev_valid = false;
   // level-ordered rows of B and B^T (see trsv.hip) and their coefficients,
   // copied from A after each build
   int *fcol = nullptr, *bptr = nullptr, *bcol = nullptr, *bsrc = nullptr;
   int *fsrc = nullptr, *fsplit = nullptr, *bsplit = nullptr;
   std::vector<int> hfwd_run, hbwd_run;  // runs of small levels (level pairs)
+  std::vector<int> hfwd_pbase, hbwd_pbase;  // first padded row of each run
   void *fcoef = nullptr, *bcoef = nullptr;
   bool coef_valid = false;
   TriSchedule sf{}, sb{};
@@ -429,18 +432,22 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
     alloc((void**)&c->rev_idx, sizeof(int) * mvn);
     alloc((void**)&c->fwd_order, sizeof(int) * n);
     alloc((void**)&c->fwd_lvl, sizeof(int) * (n + 1));
+    alloc((void**)&c->fwd_slvl, sizeof(int) * (n + 1));
+    alloc((void**)&c->bwd_slvl, sizeof(int) * (n + 1));
     alloc((void**)&c->bwd_order, sizeof(int) * n);
     alloc((void**)&c->bwd_lvl, sizeof(int) * (n + 1));
     alloc((void**)&c->lv, sizeof(double) * n * 22);
-    alloc((void**)&c->fcol, sizeof(int) * mvn);
+    // B and B^T rows, then the padded run rows (at most n of kTrsvPad slots)
+    const size_t rowcap = trsv_pad_offset(mvn) + (size_t)kTrsvPad * n;
+    alloc((void**)&c->fcol, sizeof(int) * rowcap);
     alloc((void**)&c->bptr, sizeof(int) * (n + 1));
-    alloc((void**)&c->bcol, sizeof(int) * mvn);
-    alloc((void**)&c->bsrc, sizeof(int) * mvn);
-    alloc((void**)&c->fsrc, sizeof(int) * mvn);
+    alloc((void**)&c->bcol, sizeof(int) * rowcap);
+    alloc((void**)&c->bsrc, sizeof(int) * rowcap);
+    alloc((void**)&c->fsrc, sizeof(int) * rowcap);
     alloc((void**)&c->fsplit, sizeof(int) * n);
-    alloc((void**)&c->bsplit, sizeof(int) * n);
-    alloc(&c->fcoef, tsize(c) * mvn);
-    alloc(&c->bcoef, tsize(c) * mvn);
+    alloc((void**)&c->bsplit, sizeof(int) * 2 * n);
+    alloc(&c->fcoef, tsize(c) * rowcap);
+    alloc(&c->bcoef, tsize(c) * rowcap);
     alloc((void**)&c->lm, sizeof(double) * mpa * 4);
     alloc((void**)&c->M3, sizeof(double) * mpa * mpa);
     alloc((void**)&c->M3inv, sizeof(double) * mpa * mpa);
@@ -487,7 +494,7 @@ void vif_destroy(vif_ctx* c) {
                   c->partial, c->vecpart, c->vec, c->scal, c->status, c->nbr, c->Xc, c->Zc, c->Minv, c->wvec,
                   c->e, c->Smat, c->Tm, c->tmpm, c->MinvT, c->Ubar, c->Q1, c->Gs, c->Bs, c->Vr, c->tpart,
                   c->rowpart, c->gred, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx,
-                  c->fwd_order, c->fwd_lvl, c->bwd_order, c->bwd_lvl, c->lv, c->lm, c->M3, c->M3inv, c->L3inv,
+                  c->fwd_order, c->fwd_lvl, c->bwd_order, c->bwd_lvl, c->fwd_slvl, c->bwd_slvl, c->lv, c->lm, c->M3, c->M3inv, c->L3inv,
                   c->lsc, c->lpart, c->fcol, c->bptr, c->bcol, c->bsrc, c->fsrc, c->fsplit, c->bsplit, c->fcoef, c->bcoef, c->slq_a, c->slq_b, c->slq_rz, c->slq_terms, c->slq_work, c->slq_u,
                   c->slq_q, c->slq_iters, c->lg_Ut, c->lg_Ut3, c->lg_dV, c->lg_MT, c->lg_M3T, c->lg_PhiT, c->lg_mm, c->lg_vec, c->lg_part, c->lg_slots, c->pred_Vp,
                   c->pred_Ap, c->pred_u, c->pred_Lt, c->pred_Vpd, c->pred_vn, c->pred_Dp, c->pred_samp, c->vorder,
@@ -972,17 +979,35 @@ static vif_status ensure_schedules(vif_ctx* c) {
   c->nlev_b = schedule(rlev, bo, bp);
   c->hfwd_lvl = fp;
   c->hbwd_lvl = bp;
+  // the single-right-hand-side solves walk levels of kTrsvSmallLevel + 1 to
+  // 2 kTrsvSmallLevel points as two halves (the points of a level are
+  // independent), so that they join the one-workgroup runs
+  auto split_levels = [](const std::vector<int>& lp, int nl) {
+    std::vector<int> out(1, 0);
+    for (int L = 0; L < nl; ++L) {
+      const int cnt = lp[L + 1] - lp[L];
+      if (cnt > kTrsvSmallLevel && cnt <= 2 * kTrsvSmallLevel) out.push_back(lp[L] + (cnt + 1) / 2);
+      out.push_back(lp[L + 1]);
+    }
+    return out;
+  };
+  c->hfwd_slvl = split_levels(fp, c->nlev_f);
+  c->hbwd_slvl = split_levels(bp, c->nlev_b);
+  c->nslev_f = (int)c->hfwd_slvl.size() - 1;
+  c->nslev_b = (int)c->hbwd_slvl.size() - 1;
+  const std::vector<int>& fsp = c->hfwd_slvl;
+  const std::vector<int>& bsp = c->hbwd_slvl;
   // runs of small levels, and for each position in a run the run's first
   // position P0 (entries at positions >= P0 are inside the run)
-  trsv_runs(fp.data(), c->nlev_f, c->hfwd_run);
-  trsv_runs(bp.data(), c->nlev_b, c->hbwd_run);
+  trsv_runs(fsp.data(), c->nslev_f, c->hfwd_run);
+  trsv_runs(bsp.data(), c->nslev_b, c->hbwd_run);
   auto run_start = [&](const std::vector<int>& lp, const std::vector<int>& runs) {
     std::vector<int> p0(n, -1);
     for (size_t r = 0; r + 1 < runs.size(); r += 2)
       for (int q = lp[runs[r]]; q < lp[runs[r + 1]]; ++q) p0[q] = lp[runs[r]];
     return p0;
   };
-  const std::vector<int> fp0 = run_start(fp, c->hfwd_run), bp0 = run_start(bp, c->hbwd_run);
+  const std::vector<int> fp0 = run_start(fsp, c->hfwd_run), bp0 = run_start(bsp, c->hbwd_run);
   // level-ordered rows: B (fixed width m_v) and B^T (CSR over the points that
   // have the row's point as a neighbour, in increasing (point, slot) order);
   // in a run's rows the in-run entries are moved to the front (stable)
@@ -1054,6 +1079,43 @@ static vif_status ensure_schedules(vif_ctx* c) {
         bsplit[q] = e0 + nin;
       }
     }
+    // padded copies of the rows of run positions: their first kTrsvPad
+    // in-run entries (B^T: the rest stay in the CSR rows), behind the rows
+    // at element offset pad; pbase: the first padded row of each run
+    const size_t pad = trsv_pad_offset((size_t)n * mva);
+    auto pad_rows = [&](const std::vector<int>& lp, const std::vector<int>& runs, std::vector<int>& pbase,
+                        auto first, auto count, const std::vector<int>& col, const std::vector<int>& src,
+                        std::vector<int>& pcol, std::vector<int>& psrc) {
+      pbase.clear();
+      int64_t np = 0;
+      for (size_t r = 0; r + 1 < runs.size(); r += 2) {
+        pbase.push_back((int)np);
+        np += lp[runs[r + 1]] - lp[runs[r]];
+      }
+      pcol.assign((size_t)np * kTrsvPad, -1);
+      psrc.assign((size_t)np * kTrsvPad, -1);
+      for (size_t r = 0, rr = 0; r + 1 < runs.size(); r += 2, ++rr) {
+        const int P0 = lp[runs[r]], P1 = lp[runs[r + 1]];
+        for (int q = P0; q < P1; ++q) {
+          const size_t row = (size_t)(pbase[rr] + q - P0) * kTrsvPad;
+          const size_t e = first(q);
+          for (int j = 0; j < std::min(count(q), kTrsvPad); ++j) {
+            pcol[row + j] = col[e + j];
+            psrc[row + j] = src[e + j];
+          }
+        }
+      }
+      return np;
+    };
+    std::vector<int> bnin(n, 0);
+    for (int64_t q = 0; q < n; ++q) bnin[q] = bsplit[q] - bptr[q];
+    std::vector<int> fpcol, fpsrc, bpcol, bpsrc;
+    const int64_t fnpad = pad_rows(
+        fsp, c->hfwd_run, c->hfwd_pbase, [&](int q) { return (size_t)q * mv; }, [&](int q) { return fsplit[q]; },
+        fcol, fsrc, fpcol, fpsrc);
+    const int64_t npad = pad_rows(
+        bsp, c->hbwd_run, c->hbwd_pbase, [&](int q) { return (size_t)bptr[q]; }, [&](int q) { return bnin[q]; },
+        bcol, bsrc, bpcol, bpsrc);
     HIPCHK(c, hipMemcpyAsync(c->fcol, fcol.data(), sizeof(int) * fcol.size(), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->fsrc, fsrc.data(), sizeof(int) * fsrc.size(), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->fsplit, fsplit.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
@@ -1061,19 +1123,42 @@ static vif_status ensure_schedules(vif_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(c->bcol, bcol.data(), sizeof(int) * bcol.size(), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bsrc, bsrc.data(), sizeof(int) * bsrc.size(), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bsplit, bsplit.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bsplit + n, bnin.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
+    if (npad > 0) {
+      HIPCHK(c, hipMemcpyAsync(c->bcol + pad, bpcol.data(), sizeof(int) * bpcol.size(), hipMemcpyHostToDevice, c->st));
+      HIPCHK(c, hipMemcpyAsync(c->bsrc + pad, bpsrc.data(), sizeof(int) * bpsrc.size(), hipMemcpyHostToDevice, c->st));
+    }
+    if (fnpad > 0) {
+      HIPCHK(c, hipMemcpyAsync(c->fcol + pad, fpcol.data(), sizeof(int) * fpcol.size(), hipMemcpyHostToDevice, c->st));
+      HIPCHK(c, hipMemcpyAsync(c->fsrc + pad, fpsrc.data(), sizeof(int) * fpsrc.size(), hipMemcpyHostToDevice, c->st));
+    }
     HIPCHK(c, hipStreamSynchronize(c->st));  // the host vectors go out of scope
     c->sf = TriSchedule{(int)n, mv, c->nlev_f, (int64_t)n * mv, c->fwd_order, c->fwd_lvl, nullptr, nullptr,
                         c->fcol, c->fsrc, c->fsplit, c->hfwd_run.data(), (int)c->hfwd_run.size() / 2};
     c->sb = TriSchedule{(int)n, mv, c->nlev_b, ne, c->bwd_order, c->bwd_lvl, nullptr, c->bptr, c->bcol, c->bsrc,
                         c->bsplit, c->hbwd_run.data(), (int)c->hbwd_run.size() / 2};
+    c->sf.pad = (int64_t)pad;
+    c->sf.npad = fnpad;
+    c->sf.hpbase = c->hfwd_pbase.data();
+    c->sb.pad = (int64_t)pad;
+    c->sb.npad = npad;
+    c->sb.hpbase = c->hbwd_pbase.data();
   }
   HIPCHK(c, hipMemcpyAsync(c->fwd_order, fo.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->fwd_lvl, fp.data(), sizeof(int) * fp.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->fwd_slvl, fsp.data(), sizeof(int) * fsp.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->bwd_slvl, bsp.data(), sizeof(int) * bsp.size(), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->bwd_order, bo.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->bwd_lvl, bp.data(), sizeof(int) * bp.size(), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->sf.hlvl = c->hfwd_lvl.data();
   c->sb.hlvl = c->hbwd_lvl.data();
+  c->sf.slvl = c->fwd_slvl;
+  c->sf.hslvl = c->hfwd_slvl.data();
+  c->sf.nslev = c->nslev_f;
+  c->sb.slvl = c->bwd_slvl;
+  c->sb.hslvl = c->hbwd_slvl.data();
+  c->sb.nslev = c->nslev_b;
   c->lev_valid = true;
   c->coef_valid = false;
   return refresh_coef(c);

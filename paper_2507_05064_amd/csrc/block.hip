@@ -134,35 +134,69 @@ __global__ __launch_bounds__(256) void k_btw_multi(const T* __restrict__ A, cons
 }
 
 // one level of B^{-1} (positions [beg, end), row q: m_v slots of positions
-// and coefficients): zq[q][l] = xq[q][l] + sum_a coef_qa zq[col_qa][l]
+// and coefficients): zq[q][l] = xq[q][l] + sum_a coef_qa zq[col_qa][l]. One
+// wave per row (the row index uniform, so its slots load through the scalar
+// cache), lanes over the right-hand sides; the slots are taken eight at a
+// time with all eight gathers in flight. An empty slot gathers position 0 (a
+// valid address, not yet solved in the first level) and its value is
+// replaced by 0 before use.
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsv_fwd_level_multi(int beg, int end, const int* __restrict__ col,
                                                               const T* __restrict__ coef,
                                                               const double* __restrict__ xq, int mv, int L,
                                                               double* zq) {
   const int lane = threadIdx.x & 63;
-  const int q = beg + blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (q >= end || lane >= L) return;
-  double s = xq[(int64_t)q * L + lane];
-  for (int a = 0; a < mv; ++a) {
-    const int cq = col[(size_t)q * mv + a];
-    if (cq >= 0) s += (double)coef[(size_t)q * mv + a] * zq[(int64_t)cq * L + lane];
+  const int q = __builtin_amdgcn_readfirstlane(beg + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  if (q >= end) return;
+  const int ll = min(lane, L - 1);  // lanes past L read a valid column, write nothing
+  double s = xq[(int64_t)q * L + ll];
+  for (int a0 = 0; a0 < mv; a0 += 8) {
+    int c[8];
+    bool ok[8];
+    double w[8], z[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int a = min(a0 + k, mv - 1);
+      const int cq = col[(size_t)q * mv + a];
+      ok[k] = a0 + k < mv && cq >= 0;
+      c[k] = ok[k] ? cq : 0;
+      w[k] = ok[k] ? (double)coef[(size_t)q * mv + a] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) z[k] = zq[(int64_t)c[k] * L + ll];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s = fma(w[k], ok[k] ? z[k] : 0.0, s);
   }
-  zq[(int64_t)q * L + lane] = s;
+  if (lane < L) zq[(int64_t)q * L + lane] = s;
 }
 
-// one level of B^{-T} (CSR rows by position)
+// one level of B^{-T} (CSR rows by position), eight entries at a time as
+// above; the entries past a row's end repeat its last entry with weight 0
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsv_bwd_level_multi(int beg, int end, const int* __restrict__ ptr,
                                                               const int* __restrict__ col, const T* __restrict__ coef,
                                                               const double* __restrict__ xq, int L, double* zq) {
   const int lane = threadIdx.x & 63;
-  const int q = beg + blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (q >= end || lane >= L) return;
-  double s = xq[(int64_t)q * L + lane];
-  const int e1 = ptr[q + 1];
-  for (int a = ptr[q]; a < e1; ++a) s += (double)coef[a] * zq[(int64_t)col[a] * L + lane];
-  zq[(int64_t)q * L + lane] = s;
+  const int q = __builtin_amdgcn_readfirstlane(beg + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  if (q >= end) return;
+  const int ll = min(lane, L - 1);
+  double s = xq[(int64_t)q * L + ll];
+  const int e0 = ptr[q], e1 = ptr[q + 1];
+  for (int a0 = e0; a0 < e1; a0 += 8) {
+    int c[8];
+    double w[8], z[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int a = min(a0 + k, e1 - 1);
+      c[k] = col[a];
+      w[k] = a0 + k < e1 ? (double)coef[a] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) z[k] = zq[(int64_t)c[k] * L + ll];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s = fma(w[k], z[k], s);
+  }
+  if (lane < L) zq[(int64_t)q * L + lane] = s;
 }
 
 // ------------------------------------------------------------ low-rank products

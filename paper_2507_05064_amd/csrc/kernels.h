@@ -144,7 +144,7 @@ void launch_wgram_partial(hipStream_t st, const T* U, const double* sw, int64_t 
 // consecutive small levels are walked by one workgroup; inside a run's rows
 // the entries that point into the run come first, the rest (final before the
 // run starts) are folded into x by a parallel pre-pass.
-constexpr int kTrsvSmallLevel = 256;   // levels with more points get a whole-GPU launch
+constexpr int kTrsvSmallLevel = 128;   // levels with more points get a whole-GPU launch
 constexpr int kTrsvRunLevels = 2048;   // levels per run
 constexpr int kTrsvRunCap = 16384;     // positions per run (their z sit in LDS)
 struct TriSchedule {
@@ -157,10 +157,27 @@ struct TriSchedule {
   const int* col;    // B: n x m_v positions (-1 = none); B^T: positions of the entries
   const int* src;    // index into A (n x m_v) of each entry (-1 = none)
   const int* split;  // per position in a run: B: in-run entries of the row (they come first);
-                     // B^T: end of the in-run entries (row start + count)
-  const int* hrun;   // host: runs as level pairs [hrun[2r], hrun[2r + 1])
+                     // B^T: end of the in-run entries (row start + count), then (at
+                     // split + n) the count of in-run entries
+  const int* hrun;   // host: runs as pairs [hrun[2r], hrun[2r + 1]) of split levels (slvl)
   int nrun;
+  // the rows of run positions again, padded to kTrsvPad slots (the first
+  // kTrsvPad in-run entries), at element offset `pad` of col, src and the
+  // coefficient buffer; run r's rows start at padded row hpbase[r]
+  int64_t pad = 0;
+  int64_t npad = 0;  // padded rows
+  const int* hpbase = nullptr;
+  // level offsets of the single-right-hand-side solves: levels of
+  // kTrsvSmallLevel + 1 to 2 kTrsvSmallLevel points split in two halves;
+  // hrun indexes these
+  const int* slvl = nullptr;   // device (nslev + 1)
+  const int* hslvl = nullptr;  // host
+  int nslev = 0;
 };
+constexpr int kTrsvPad = 32;  // slots of a padded run row
+// element offset of the padded rows behind `ne` entries (16-byte aligned for
+// 4-byte and 8-byte elements); buffers hold trsv_pad_offset(ne) + kTrsvPad n
+inline size_t trsv_pad_offset(size_t ne) { return (ne + 3) & ~(size_t)3; }
 // runs of a level schedule (host): consecutive levels of <= kTrsvSmallLevel
 // points, at most kTrsvRunLevels levels and kTrsvRunCap positions each
 void trsv_runs(const int* hlvl, int nlev, std::vector<int>& runs);

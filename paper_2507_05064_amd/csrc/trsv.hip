@@ -10,24 +10,41 @@
 // contiguous memory, and the next level's rows can be loaded before the
 // current level's results are known.
 //
-// Small levels (at most kTrsvSmallLevel points) are walked by one workgroup,
-// a run of consecutive small levels per launch: each point gets G lanes (the
-// largest power of two with G * points <= 1024, at least 4), each lane up to
-// 8 entries held in registers, loaded two levels ahead. The run's positions
-// are contiguous and their z values live in LDS for the whole run, so a
-// level's dependence on earlier levels of the run is an LDS read and the
+// Small levels (at most kTrsvSmallLevel = 128 points) are walked by one
+// workgroup, a run of consecutive small levels per launch, with as many waves
+// as the run's widest level needs (8 points per wave, up to 16 waves); a
+// wave whose points lie beyond a level skips its arithmetic. The run's
+// positions are contiguous and their z values live in LDS for the whole run,
+// so a level's dependence on earlier levels of the run is an LDS read and the
 // barrier between levels waits for LDS only. A row's entries that point
 // before the run are final when the run starts: a parallel pre-pass over the
-// run's rows adds them into x, and the walk reads only the in-run entries
-// (stored first in each row). The run's z is written back once at its end.
+// run's rows adds them into x, and the walk reads only the in-run entries.
+// The run's z is written back once at its end.
+// The walk reads padded copies of the run's rows: kTrsvPad = 32 slots per
+// row holding its first 32 in-run entries (B rows have at most 31; a longer
+// B^T row takes the rest from its CSR row at its step). Each point gets 8
+// lanes and each lane 4 consecutive slots, so a wave's 8 rows are one
+// contiguous stretch of memory and its loads are 16 bytes per lane. The
+// loads are buffer loads through resources that span the run's rows (one
+// 32-bit offset per row, slots past the run's data read as zero by the
+// hardware's range check), issued four levels ahead into five rotating
+// register sets. Every load is unconditional and every loaded register is
+// read on every path, so the compiler counts the loads in flight exactly and
+// a level waits only for its own rows. Coefficients stay in their stored
+// type until used. The 8 partial sums of a point are added by three DPP
+// steps within the row of 16 lanes.
 // Larger levels get a launch of their own over the whole GPU (32 lanes per
 // point); kernel order on the stream separates them.
 #include "common.h"
 #include "kernels.h"
 
-constexpr int kPre = 8;  // entries per lane held in registers
+constexpr int kRunG = 8;   // lanes per point in a run
+constexpr int kPre = 4;    // consecutive slots per lane (kRunG * kPre = kTrsvPad)
+constexpr int kDepth = 4;  // register sets: rows are loaded kDepth - 1 levels ahead
+static_assert(kRunG * kPre == kTrsvPad, "a lane group holds a padded row");
+static_assert(kRunG * kTrsvSmallLevel == 1024, "a run level fills at most one 1024-thread workgroup");
 
-// barrier for LDS traffic only: outstanding global loads (the next level's
+// barrier for LDS traffic only: outstanding global loads (the next levels'
 // rows) stay in flight across it
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -35,37 +52,170 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-__device__ __forceinline__ int lanes_for(int cnt, int cap) {
-  int G = cap;
-  while (G > 4 && G * cnt > 1024) G >>= 1;
-  return G;
+// sum over each group of 8 lanes, in every lane of the group
+__device__ __forceinline__ double oct_sum(double v) {
+  v += __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1, 0, 3, 2]
+  v += __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2, 3, 0, 1]
+  v += __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false);  // row_half_mirror: the other quad
+  return v;
 }
 
-// One level's rows as loaded: raw values only. Loads are predicated (lanes
-// and whole waves without work issue none) and nothing is derived from a
-// loaded value until the row is used, so the loads of the levels ahead stay
-// in flight (a value used at load time would make the compiler wait for
-// them). Registers of slots that were not loaded are masked at use.
-struct RowRegs {
-  int c[kPre];     // loaded entry positions
-  double w[kPre];  // loaded coefficients
-  double x;
-  int q;     // position, or -1 for an idle lane group
-  int cnt;   // B: in-run entries of the row (loaded); B^T: first entry (loaded)
-  int e1;    // B^T: end of the in-run entries (loaded)
+// does this thread's wave hold a point of a level of cnt points? (uniform)
+__device__ __forceinline__ bool wave_has_rows(int cnt) {
+  const int first = (int)(threadIdx.x >> 6) * (64 / kRunG);
+  return __builtin_amdgcn_readfirstlane(first < cnt ? 1 : 0) != 0;
+}
+
+// buffer resource over `bytes` bytes from `base` (raw, untyped 32-bit data
+// format); loads at offsets at or past `bytes` return zero
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+// 16-byte vectors of coefficients
+template <typename T>
+struct CoefVec {
+  typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
+  static constexpr int per = 16 / sizeof(T);  // coefficients per vector
+  static constexpr int cnt = kPre / per;      // vectors per lane
 };
 
-// sum of w * z over the held in-run entries: entry slot a = lig + k G is
-// valid when a < lim; its z is read from LDS at position - P0
-__device__ __forceinline__ double row_sum(const RowRegs& r, int lig, int G, int lim, int P0, const double* zs) {
+// One level's row slots as loaded: raw values only, read at the level's step.
+template <typename T>
+struct RowRegs {
+  u4v c;                                          // four entry positions
+  typename CoefVec<T>::type w[CoefVec<T>::cnt];  // four coefficients
+  int n;                                          // in-run entries of the row
+};
+
+template <typename T>
+__device__ __forceinline__ void load_row(RowRegs<T>& r, __amdgpu_buffer_rsrc_t rc, __amdgpu_buffer_rsrc_t rw,
+                                         __amdgpu_buffer_rsrc_t rn, int q, int lig) {
+  r.n = (int)__builtin_amdgcn_raw_buffer_load_b32(rn, q * 4, 0, 0);
+  const int slot = q * kTrsvPad + lig * kPre;
+  r.c = __builtin_amdgcn_raw_buffer_load_b128(rc, slot * 4, 0, 0);
+#pragma unroll
+  for (int h = 0; h < CoefVec<T>::cnt; ++h)
+    r.w[h] = __builtin_bit_cast(typename CoefVec<T>::type,
+                                __builtin_amdgcn_raw_buffer_load_b128(rw, slot * (int)sizeof(T) + 16 * h, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ double coef_at(const RowRegs<T>& r, int k) {
+  return (double)r.w[k / CoefVec<T>::per][k % CoefVec<T>::per];
+}
+
+// marks every register of a loaded row as read: the compiler then waits for
+// the row's loads here on every path (idle waves included), so that no
+// register is left with a load pending on one path only, which would make it
+// drain all loads in flight before the register is reused
+template <typename T>
+__device__ __forceinline__ void consume(const RowRegs<T>& r) {
+  asm volatile("" ::"v"(r.c), "v"(r.n));
+#pragma unroll
+  for (int h = 0; h < CoefVec<T>::cnt; ++h) asm volatile("" ::"v"(r.w[h]));
+}
+
+// sum of w * z over the held in-run entries: slot k of lane lig is entry
+// 4 lig + k of the row and counts when it is below lim; its z is read from
+// LDS at position - P0. A slot that does not count reads zs[0] (finite: zs
+// holds x or z) with weight 0, so that every slot's read and product happen
+// on every path (no branch around a read of a loaded register).
+template <typename T>
+__device__ __forceinline__ double row_sum(const RowRegs<T>& r, int lig, int lim, int P0, const double* zs) {
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < kPre; ++k) {
-    const bool ok = r.q >= 0 && lig + k * G < lim;
-    const double z = zs[ok ? r.c[k] - P0 : 0];
-    s += ok ? r.w[k] * z : 0.0;
+    const bool ok = lig * kPre + k < lim;
+    const double w = ok ? coef_at(r, k) : 0.0;
+    s = fma(w, zs[ok ? (int)r.c[k] - P0 : 0], s);
   }
   return s;
+}
+
+// A run of small levels, either direction: the padded row of position q
+// (P0 <= q < P0 + np) at padded row prow + (q - P0) of pcol / pcoef, cnt[q]
+// in-run entries. A row with more than kTrsvPad of them (B^T only) takes the
+// rest from its CSR row (ovptr[q] on, ovcol / ovcoef), loaded at its step.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_trsv_run(const int* __restrict__ lvl, int L0, int L1,
+                                                   const int* __restrict__ pcol, const T* __restrict__ pcoef,
+                                                   int64_t prow, const int* __restrict__ cnt,
+                                                   const int* __restrict__ ovptr, const int* __restrict__ ovcol,
+                                                   const T* __restrict__ ovcoef, const double* __restrict__ xq,
+                                                   double* zq) {
+  __shared__ int slv[kTrsvRunLevels + 1];
+  __shared__ double zs[kTrsvRunCap];
+  const int nt = blockDim.x;
+  for (int t = threadIdx.x; t <= L1 - L0; t += nt) slv[t] = lvl[L0 + t];
+  __syncthreads();
+  // uniform values, so that the buffer resources sit in scalar registers
+  const int nL = L1 - L0, P0 = __builtin_amdgcn_readfirstlane(slv[0]);
+  const int np = __builtin_amdgcn_readfirstlane(slv[nL]) - P0;
+  const int grp = threadIdx.x / kRunG, lig = threadIdx.x % kRunG;
+  const __amdgpu_buffer_rsrc_t rc = span(pcol + prow * kTrsvPad, (int64_t)np * kTrsvPad * 4);
+  const __amdgpu_buffer_rsrc_t rw = span(pcoef + prow * kTrsvPad, (int64_t)np * kTrsvPad * sizeof(T));
+  const __amdgpu_buffer_rsrc_t rn = span(cnt + P0, (int64_t)np * 4);
+  // zs starts as the run's x; a point's step adds its sum
+  for (int t = threadIdx.x; t < np; t += nt) zs[t] = xq[P0 + t];
+  __syncthreads();
+  // the row of level L for the point of this lane group; a group past the
+  // level loads at an offset past the run (zeros, no memory access). Every
+  // lane issues the same loads on every path.
+  auto load = [&](RowRegs<T>& r, int L) {
+    const int beg = slv[L], cn = slv[L + 1] - beg;
+    load_row(r, rc, rw, rn, grp < cn ? beg + grp - P0 : np, lig);
+  };
+  auto step = [&](const RowRegs<T>& r, int L) {
+    const int beg = slv[L], cn = slv[L + 1] - beg;
+    consume(r);
+    if (wave_has_rows(cn)) {
+      const bool act = grp < cn;
+      const int nin = act ? r.n : 0;
+      double s = row_sum(r, lig, nin, P0, zs);
+      if (ovptr != nullptr && nin > kTrsvPad) {  // the rest, 4 per lane at a time
+        const int e0 = ovptr[beg + grp];
+        for (int a0 = kTrsvPad + lig; a0 < nin; a0 += 4 * kRunG) {
+          int cc[4];
+          double ww[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int a = a0 + k * kRunG;
+            cc[k] = a < nin ? ovcol[e0 + a] : P0;
+            ww[k] = a < nin ? (double)ovcoef[e0 + a] : 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) s += ww[k] * zs[cc[k] - P0];
+        }
+      }
+      s = oct_sum(s);
+      if (act && lig == 0) zs[beg + grp - P0] += s;
+    }
+    lds_barrier();
+  };
+  // kDepth register sets in rotation (no copies: a copy would wait for the
+  // loads still in flight); past the last level the last level is loaded
+  // again, unused, so that no load sits behind a branch. The loop body takes
+  // whole groups of kDepth levels and the last ones follow it: an exit from
+  // the middle of the body would join the loop's entry with a path on which
+  // other registers have loads pending.
+  RowRegs<T> R[kDepth];
+  const int Lmax = nL - 1;
+#pragma unroll
+  for (int j = 0; j < kDepth - 1; ++j) load(R[j], min(j, Lmax));
+  int L = 0;
+  for (; L + kDepth <= nL; L += kDepth) {
+#pragma unroll
+    for (int j = 0; j < kDepth; ++j) {
+      load(R[(j + kDepth - 1) % kDepth], min(L + j + kDepth - 1, Lmax));
+      step(R[j], L + j);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kDepth - 1; ++j)
+    if (L + j < nL) step(R[j], L + j);
+  for (int t = threadIdx.x; t < np; t += nt) zq[P0 + t] = zs[t];
 }
 
 // ---------------------------------------------------------------- B^{-1}
@@ -86,66 +236,6 @@ __global__ __launch_bounds__(256) void k_trsv_fwd_pre(int beg, int end, const in
 #pragma unroll
   for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
   if (lane == 0) xq[q] += s;
-}
-
-template <typename T>
-__device__ __forceinline__ void fwd_load(RowRegs& r, int q, bool active, int lig, int G, const int* col,
-                                         const T* coef, const int* nin, const double* xq, int mv, int P0) {
-  r.q = active ? q : -1;
-  if (active) {
-    r.cnt = nin[q];
-    r.x = xq[q];
-  }
-#pragma unroll
-  for (int k = 0; k < kPre; ++k) {
-    const int a = lig + k * G;
-    if (active && a < mv) {
-      r.c[k] = col[(size_t)q * mv + a];
-      r.w[k] = (double)coef[(size_t)q * mv + a];
-    }
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(1024) void k_trsv_fwd_run(const int* __restrict__ lvl, int L0, int L1,
-                                                       const int* __restrict__ col, const T* __restrict__ coef,
-                                                       const int* __restrict__ nin, const double* __restrict__ xq,
-                                                       int mv, double* zq) {
-  __shared__ int slv[kTrsvRunLevels + 1];
-  __shared__ double zs[kTrsvRunCap];
-  for (int t = threadIdx.x; t <= L1 - L0; t += 1024) slv[t] = lvl[L0 + t];
-  __syncthreads();
-  const int nL = L1 - L0, P0 = slv[0];
-  // rows are loaded two levels ahead (their offsets, then the entries: two
-  // dependent loads)
-  auto load = [&](RowRegs& r, int L) {
-    const int cn = slv[L + 1] - slv[L], Gn = lanes_for(cn, 32), gn = threadIdx.x / Gn;
-    fwd_load<T>(r, slv[L] + gn, gn < cn, threadIdx.x - gn * Gn, Gn, col, coef, nin, xq, mv, P0);
-  };
-  auto step = [&](const RowRegs& cur, int L) {
-    const int cnt = slv[L + 1] - slv[L];
-    const int G = lanes_for(cnt, 32), grp = threadIdx.x / G, lig = threadIdx.x - grp * G;
-    double s = row_sum(cur, lig, G, cur.q >= 0 ? min(cur.cnt, mv) : 0, P0, zs);
-    for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (cur.q >= 0 && lig == 0) zs[cur.q - P0] = cur.x + s;
-    lds_barrier();
-  };
-  // three register sets in rotation (no copies: a copy would wait for the
-  // loads still in flight)
-  RowRegs R0, R1, R2;
-  load(R0, 0);
-  if (nL > 1) load(R1, 1);
-  for (int L = 0; L < nL; L += 3) {
-    if (L + 2 < nL) load(R2, L + 2);
-    step(R0, L);
-    if (L + 1 >= nL) break;
-    if (L + 3 < nL) load(R0, L + 3);
-    step(R1, L + 1);
-    if (L + 2 >= nL) break;
-    if (L + 4 < nL) load(R1, L + 4);
-    step(R2, L + 2);
-  }
-  for (int t = threadIdx.x; t < slv[nL] - P0; t += 1024) zq[P0 + t] = zs[t];
 }
 
 // one large level of B^{-1}: 32 lanes per point (m_v <= 31)
@@ -185,82 +275,6 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_pre(int beg, int end, const in
   if (lane == 0) xq[q] += s;
 }
 
-template <typename T>
-__device__ __forceinline__ void bwd_load(RowRegs& r, int q, bool active, int lig, int G, const int* ptr,
-                                         const int* split, const int* col, const T* coef, const double* xq,
-                                         int P0, int64_t ne) {
-  r.q = active ? q : -1;
-  if (!active) return;
-  const int e0 = ptr[q], e1 = split[q];  // the entry addresses need them: one dependent load
-  r.cnt = e0;
-  r.e1 = e1;
-  r.x = xq[q];
-#pragma unroll
-  for (int k = 0; k < kPre; ++k) {
-    const int a = e0 + lig + k * G;
-    if (a < e1) {
-      r.c[k] = col[a];
-      r.w[k] = (double)coef[a];
-    }
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(1024) void k_trsv_bwd_run(const int* __restrict__ lvl, int L0, int L1,
-                                                       const int* __restrict__ ptr, const int* __restrict__ split,
-                                                       const int* __restrict__ col, const T* __restrict__ coef,
-                                                       const double* __restrict__ xq, int64_t ne, double* zq) {
-  __shared__ int slv[kTrsvRunLevels + 1];
-  __shared__ double zs[kTrsvRunCap];
-  for (int t = threadIdx.x; t <= L1 - L0; t += 1024) slv[t] = lvl[L0 + t];
-  __syncthreads();
-  const int nL = L1 - L0, P0 = slv[0];
-  // rows are loaded two levels ahead (their offsets, then the entries: two
-  // dependent loads)
-  auto load = [&](RowRegs& r, int L) {
-    const int cn = slv[L + 1] - slv[L], Gn = lanes_for(cn, 64), gn = threadIdx.x / Gn;
-    bwd_load<T>(r, slv[L] + gn, gn < cn, threadIdx.x - gn * Gn, Gn, ptr, split, col, coef, xq, P0, ne);
-  };
-  auto step = [&](const RowRegs& cur, int L) {
-    const int cnt = slv[L + 1] - slv[L];
-    const int G = lanes_for(cnt, 64), grp = threadIdx.x / G, lig = threadIdx.x - grp * G;
-    const int e0 = cur.q >= 0 ? cur.cnt : 0, e1 = cur.q >= 0 ? cur.e1 : 0;
-    double s = row_sum(cur, lig, G, e1 - e0, P0, zs);
-    // in-run parts longer than 8 G entries: the rest, 4 per lane at a time
-    for (int a0 = e0 + kPre * G + lig; a0 < e1; a0 += 4 * G) {
-      int cc[4];
-      double ww[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int a = a0 + k * G;
-        cc[k] = a < e1 ? col[a] : P0;
-        ww[k] = a < e1 ? (double)coef[a] : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) s += ww[k] * zs[cc[k] - P0];
-    }
-    for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (cur.q >= 0 && lig == 0) zs[cur.q - P0] = cur.x + s;
-    lds_barrier();
-  };
-  // three register sets in rotation (no copies: a copy would wait for the
-  // loads still in flight)
-  RowRegs R0, R1, R2;
-  load(R0, 0);
-  if (nL > 1) load(R1, 1);
-  for (int L = 0; L < nL; L += 3) {
-    if (L + 2 < nL) load(R2, L + 2);
-    step(R0, L);
-    if (L + 1 >= nL) break;
-    if (L + 3 < nL) load(R0, L + 3);
-    step(R1, L + 1);
-    if (L + 2 >= nL) break;
-    if (L + 4 < nL) load(R1, L + 4);
-    step(R2, L + 2);
-  }
-  for (int t = threadIdx.x; t < slv[nL] - P0; t += 1024) zq[P0 + t] = zs[t];
-}
-
 // one large level of B^{-T}: 32 lanes per point
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsv_bwd_wide(int beg, int end, const int* __restrict__ ptr,
@@ -296,6 +310,14 @@ __global__ void k_coef_src(const int* __restrict__ src, const T* __restrict__ A,
 }
 
 // ---------------------------------------------------------------- launchers
+// threads of the workgroup that walks levels [L0, L1): a wave per 16 points
+// of the widest level
+static int run_threads(const int* hlvl, int L0, int L1) {
+  int w = 1;
+  for (int L = L0; L < L1; ++L) w = std::max(w, hlvl[L + 1] - hlvl[L]);
+  return 64 * (int)ceil_div(w, 64 / kRunG);
+}
+
 void trsv_runs(const int* hlvl, int nlev, std::vector<int>& runs) {
   runs.clear();
   int L = 0;
@@ -320,20 +342,21 @@ void launch_trsv_fwd(hipStream_t st, const TriSchedule& s, const T* coef, const 
   const int64_t n = s.n;
   hipLaunchKernelGGL(k_perm_gather, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, s.order, x, n, xq);
   int L = 0, r = 0;
-  while (L < s.nlev) {
+  while (L < s.nslev) {
     if (r < s.nrun && s.hrun[2 * r] == L) {
-      const int L1 = s.hrun[2 * r + 1], P0 = s.hlvl[L], P1 = s.hlvl[L1];
+      const int L1 = s.hrun[2 * r + 1], P0 = s.hslvl[L], P1 = s.hslvl[L1];
       hipLaunchKernelGGL((k_trsv_fwd_pre<T>), dim3((unsigned)ceil_div(P1 - P0, 8)), dim3(256), 0, st, P0, P1,
                          s.col, coef, s.split, s.mv, zq, xq);
-      hipLaunchKernelGGL((k_trsv_fwd_run<T>), dim3(1), dim3(1024), 0, st, s.lvl, L, L1, s.col, coef, s.split, xq,
-                         s.mv, zq);
+      hipLaunchKernelGGL((k_trsv_run<T>), dim3(1), dim3(run_threads(s.hslvl, L, L1)), 0, st, s.slvl, L, L1,
+                         s.col + s.pad, coef + s.pad, (int64_t)s.hpbase[r], s.split, nullptr, nullptr, nullptr, xq,
+                         zq);
       L = L1;
       ++r;
       continue;
     }
-    const int cnt = s.hlvl[L + 1] - s.hlvl[L];
-    hipLaunchKernelGGL((k_trsv_fwd_wide<T>), dim3((unsigned)ceil_div(cnt, 8)), dim3(256), 0, st, s.hlvl[L],
-                       s.hlvl[L + 1], s.col, coef, xq, s.mv, zq);
+    const int cnt = s.hslvl[L + 1] - s.hslvl[L];
+    hipLaunchKernelGGL((k_trsv_fwd_wide<T>), dim3((unsigned)ceil_div(cnt, 8)), dim3(256), 0, st, s.hslvl[L],
+                       s.hslvl[L + 1], s.col, coef, xq, s.mv, zq);
     ++L;
   }
   hipLaunchKernelGGL(k_perm_scatter, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, s.order, zq, n, z);
@@ -345,20 +368,21 @@ void launch_trsv_bwd(hipStream_t st, const TriSchedule& s, const T* coef, const 
   const int64_t n = s.n;
   hipLaunchKernelGGL(k_perm_gather, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, s.order, x, n, xq);
   int L = 0, r = 0;
-  while (L < s.nlev) {
+  while (L < s.nslev) {
     if (r < s.nrun && s.hrun[2 * r] == L) {
-      const int L1 = s.hrun[2 * r + 1], P0 = s.hlvl[L], P1 = s.hlvl[L1];
+      const int L1 = s.hrun[2 * r + 1], P0 = s.hslvl[L], P1 = s.hslvl[L1];
       hipLaunchKernelGGL((k_trsv_bwd_pre<T>), dim3((unsigned)ceil_div(P1 - P0, 8)), dim3(256), 0, st, P0, P1,
                          s.ptr, s.split, s.col, coef, zq, xq);
-      hipLaunchKernelGGL((k_trsv_bwd_run<T>), dim3(1), dim3(1024), 0, st, s.lvl, L, L1, s.ptr, s.split, s.col, coef,
-                         xq, s.ne, zq);
+      hipLaunchKernelGGL((k_trsv_run<T>), dim3(1), dim3(run_threads(s.hslvl, L, L1)), 0, st, s.slvl, L, L1,
+                         s.col + s.pad, coef + s.pad, (int64_t)s.hpbase[r], s.split + s.n, s.ptr, s.col, coef, xq,
+                         zq);
       L = L1;
       ++r;
       continue;
     }
-    const int cnt = s.hlvl[L + 1] - s.hlvl[L];
-    hipLaunchKernelGGL((k_trsv_bwd_wide<T>), dim3((unsigned)ceil_div(cnt, 8)), dim3(256), 0, st, s.hlvl[L],
-                       s.hlvl[L + 1], s.ptr, s.col, coef, xq, zq);
+    const int cnt = s.hslvl[L + 1] - s.hslvl[L];
+    hipLaunchKernelGGL((k_trsv_bwd_wide<T>), dim3((unsigned)ceil_div(cnt, 8)), dim3(256), 0, st, s.hslvl[L],
+                       s.hslvl[L + 1], s.ptr, s.col, coef, xq, zq);
     ++L;
   }
   hipLaunchKernelGGL(k_perm_scatter, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, s.order, zq, n, z);
@@ -368,11 +392,17 @@ template <typename T>
 void launch_coef_fwd(hipStream_t st, const TriSchedule& s, const T* A, T* coef) {
   if (s.ne > 0) hipLaunchKernelGGL((k_coef_src<T>), dim3((unsigned)ceil_div(s.ne, 256)), dim3(256), 0, st, s.src, A,
                                    s.ne, coef);
+  const int64_t np = s.npad * kTrsvPad;  // the padded run rows
+  if (np > 0) hipLaunchKernelGGL((k_coef_src<T>), dim3((unsigned)ceil_div(np, 256)), dim3(256), 0, st, s.src + s.pad,
+                                 A, np, coef + s.pad);
 }
 template <typename T>
 void launch_coef_bwd(hipStream_t st, const TriSchedule& s, const T* A, T* coef) {
   if (s.ne > 0) hipLaunchKernelGGL((k_coef_src<T>), dim3((unsigned)ceil_div(s.ne, 256)), dim3(256), 0, st, s.src, A,
                                    s.ne, coef);
+  const int64_t np = s.npad * kTrsvPad;  // the padded run rows
+  if (np > 0) hipLaunchKernelGGL((k_coef_src<T>), dim3((unsigned)ceil_div(np, 256)), dim3(256), 0, st, s.src + s.pad,
+                                 A, np, coef + s.pad);
 }
 
 #define INST(T)                                                                                                    \
