@@ -92,6 +92,7 @@ struct vif_ctx {
   int *fsrc = nullptr, *fsplit = nullptr, *bsplit = nullptr;
   std::vector<int> hfwd_run, hbwd_run;  // runs of small levels (level pairs)
   std::vector<int> hfwd_pbase, hbwd_pbase;  // first padded row of each run
+  std::vector<int> hbwd_obase;              // B^T runs' blocks of entries past the padded slots
   void *fcoef = nullptr, *bcoef = nullptr;
   bool coef_valid = false;
   TriSchedule sf{}, sb{};
@@ -438,14 +439,14 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
     alloc((void**)&c->bwd_lvl, sizeof(int) * (n + 1));
     alloc((void**)&c->lv, sizeof(double) * n * 22);
     // B and B^T rows, then the padded run rows (at most n of kTrsvPad slots)
-    const size_t rowcap = trsv_pad_offset(mvn) + (size_t)kTrsvPad * n;
+    const size_t rowcap = trsv_pad_offset(mvn) + (size_t)kTrsvPad * n + mvn;  // rows, padded rows, run blocks
     alloc((void**)&c->fcol, sizeof(int) * rowcap);
     alloc((void**)&c->bptr, sizeof(int) * (n + 1));
     alloc((void**)&c->bcol, sizeof(int) * rowcap);
     alloc((void**)&c->bsrc, sizeof(int) * rowcap);
     alloc((void**)&c->fsrc, sizeof(int) * rowcap);
     alloc((void**)&c->fsplit, sizeof(int) * n);
-    alloc((void**)&c->bsplit, sizeof(int) * 2 * n);
+    alloc((void**)&c->bsplit, sizeof(int) * 3 * n);
     alloc(&c->fcoef, tsize(c) * rowcap);
     alloc(&c->bcoef, tsize(c) * rowcap);
     alloc((void**)&c->lm, sizeof(double) * mpa * 4);
@@ -980,13 +981,17 @@ static vif_status ensure_schedules(vif_ctx* c) {
   c->hfwd_lvl = fp;
   c->hbwd_lvl = bp;
   // the single-right-hand-side solves walk levels of kTrsvSmallLevel + 1 to
-  // 2 kTrsvSmallLevel points as two halves (the points of a level are
-  // independent), so that they join the one-workgroup runs
+  // kTrsvSplitMax points as consecutive parts of at most kTrsvSmallLevel
+  // (the points of a level are independent), so that they join the
+  // one-workgroup runs
   auto split_levels = [](const std::vector<int>& lp, int nl) {
     std::vector<int> out(1, 0);
     for (int L = 0; L < nl; ++L) {
       const int cnt = lp[L + 1] - lp[L];
-      if (cnt > kTrsvSmallLevel && cnt <= 2 * kTrsvSmallLevel) out.push_back(lp[L] + (cnt + 1) / 2);
+      if (cnt > kTrsvSmallLevel && cnt <= kTrsvSplitMax) {
+        const int parts = (cnt + kTrsvSmallLevel - 1) / kTrsvSmallLevel;
+        for (int k = 1; k < parts; ++k) out.push_back(lp[L] + (int)((int64_t)cnt * k / parts));
+      }
       out.push_back(lp[L + 1]);
     }
     return out;
@@ -1000,14 +1005,13 @@ static vif_status ensure_schedules(vif_ctx* c) {
   // runs of small levels, and for each position in a run the run's first
   // position P0 (entries at positions >= P0 are inside the run)
   trsv_runs(fsp.data(), c->nslev_f, c->hfwd_run);
-  trsv_runs(bsp.data(), c->nslev_b, c->hbwd_run);
   auto run_start = [&](const std::vector<int>& lp, const std::vector<int>& runs) {
     std::vector<int> p0(n, -1);
     for (size_t r = 0; r + 1 < runs.size(); r += 2)
       for (int q = lp[runs[r]]; q < lp[runs[r + 1]]; ++q) p0[q] = lp[runs[r]];
     return p0;
   };
-  const std::vector<int> fp0 = run_start(fsp, c->hfwd_run), bp0 = run_start(bsp, c->hbwd_run);
+  const std::vector<int> fp0 = run_start(fsp, c->hfwd_run);
   // level-ordered rows: B (fixed width m_v) and B^T (CSR over the points that
   // have the row's point as a neighbour, in increasing (point, slot) order);
   // in a run's rows the in-run entries are moved to the front (stable)
@@ -1053,6 +1057,14 @@ static vif_status ensure_schedules(vif_ctx* c) {
         bcol[e] = bpos[i];
         bsrc[e] = (int)(i * mv + a);
       }
+    // B^T runs: their rows' in-run entries past the padded slots are staged
+    // in LDS, at most kTrsvOvCap per run
+    trsv_runs(bsp.data(), c->nslev_b, c->hbwd_run, [&](int q, int P0) {
+      int cnt_in = 0;
+      for (int e = bptr[q]; e < bptr[q + 1]; ++e) cnt_in += bcol[e] >= P0;
+      return std::max(0, cnt_in - kTrsvPad);
+    });
+    const std::vector<int> bp0 = run_start(bsp, c->hbwd_run);
     std::vector<int> bsplit(n);
     {
       std::vector<int> tc, ts;
@@ -1109,6 +1121,22 @@ static vif_status ensure_schedules(vif_ctx* c) {
     };
     std::vector<int> bnin(n, 0);
     for (int64_t q = 0; q < n; ++q) bnin[q] = bsplit[q] - bptr[q];
+    // each B^T run's in-run entries past the padded slots, in one block per
+    // run; ovoff: a row's first entry in its run's block
+    std::vector<int> ovoff(n, 0), ovcol, ovsrc;
+    c->hbwd_obase.assign(1, 0);
+    for (size_t r = 0; r + 1 < c->hbwd_run.size(); r += 2) {
+      const int base = (int)ovcol.size();
+      for (int q = bsp[c->hbwd_run[r]]; q < bsp[c->hbwd_run[r + 1]]; ++q) {
+        ovoff[q] = (int)ovcol.size() - base;
+        for (int j = kTrsvPad; j < bnin[q]; ++j) {
+          ovcol.push_back(bcol[bptr[q] + j]);
+          ovsrc.push_back(bsrc[bptr[q] + j]);
+        }
+      }
+      c->hbwd_obase.push_back((int)ovcol.size());
+    }
+    const size_t ovo = pad + (size_t)kTrsvPad * n;  // element offset of the blocks
     std::vector<int> fpcol, fpsrc, bpcol, bpsrc;
     const int64_t fnpad = pad_rows(
         fsp, c->hfwd_run, c->hfwd_pbase, [&](int q) { return (size_t)q * mv; }, [&](int q) { return fsplit[q]; },
@@ -1124,6 +1152,11 @@ static vif_status ensure_schedules(vif_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(c->bsrc, bsrc.data(), sizeof(int) * bsrc.size(), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bsplit, bsplit.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bsplit + n, bnin.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bsplit + 2 * n, ovoff.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
+    if (!ovcol.empty()) {
+      HIPCHK(c, hipMemcpyAsync(c->bcol + ovo, ovcol.data(), sizeof(int) * ovcol.size(), hipMemcpyHostToDevice, c->st));
+      HIPCHK(c, hipMemcpyAsync(c->bsrc + ovo, ovsrc.data(), sizeof(int) * ovsrc.size(), hipMemcpyHostToDevice, c->st));
+    }
     if (npad > 0) {
       HIPCHK(c, hipMemcpyAsync(c->bcol + pad, bpcol.data(), sizeof(int) * bpcol.size(), hipMemcpyHostToDevice, c->st));
       HIPCHK(c, hipMemcpyAsync(c->bsrc + pad, bpsrc.data(), sizeof(int) * bpsrc.size(), hipMemcpyHostToDevice, c->st));
@@ -1143,6 +1176,9 @@ static vif_status ensure_schedules(vif_ctx* c) {
     c->sb.pad = (int64_t)pad;
     c->sb.npad = npad;
     c->sb.hpbase = c->hbwd_pbase.data();
+    c->sb.ov = (int64_t)ovo;
+    c->sb.nov = (int64_t)ovcol.size();
+    c->sb.hobase = c->hbwd_obase.data();
   }
   HIPCHK(c, hipMemcpyAsync(c->fwd_order, fo.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->fwd_lvl, fp.data(), sizeof(int) * fp.size(), hipMemcpyHostToDevice, c->st));
@@ -1547,8 +1583,8 @@ static vif_status laplace_impl(vif_ctx* c, const double* y, const double* b0, do
   S.converged = converged ? 1 : 0;
   S.levels_fwd = c->nlev_f;
   S.levels_bwd = c->nlev_b;
-  for (int L = 0; L < c->nlev_f; ++L) S.wide_fwd += (c->hfwd_lvl[L + 1] - c->hfwd_lvl[L] > kTrsvSmallLevel);
-  for (int L = 0; L < c->nlev_b; ++L) S.wide_bwd += (c->hbwd_lvl[L + 1] - c->hbwd_lvl[L] > kTrsvSmallLevel);
+  for (int L = 0; L < c->nlev_f; ++L) S.wide_fwd += (c->hfwd_lvl[L + 1] - c->hfwd_lvl[L] > kTrsvSplitMax);
+  for (int L = 0; L < c->nlev_b; ++L) S.wide_bwd += (c->hbwd_lvl[L + 1] - c->hbwd_lvl[L] > kTrsvSplitMax);
   HIPCHK(c, hipMemcpyAsync(mode_out, B.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
   HIPCHK(c, hipGetLastError());
   if ((s = read_status(c, "vif_laplace_mode"))) return s;

@@ -643,16 +643,255 @@ __global__ __launch_bounds__(WG) void k_nll_final(const double* LMinv, const dou
 }
 
 // ---------------------------------------------------------------------------
+// The same outputs for one matrix with m_p > 16 kRegNt, spread over the GPU
+// instead of one workgroup. Per 32-column block b: one wave factors and
+// inverts the diagonal block (k_chol_diag), then one launch over the
+// trailing lower 16x16 tiles forms each tile's panel rows L_ib = A_ib X_bb^T
+// from the block column as it was before the step and updates
+// A_ij -= L_ib L_jb^T (k_chol_trail; the diagonal tile of each row stores its
+// panel rows in `work`, so that no tile reads a panel another has
+// overwritten). After the last block the panels are copied into S
+// (k_chol_panels) and the off-diagonal blocks of X = L^{-1} follow one block
+// diagonal per launch, X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj
+// (k_chol_xblock). An error already recorded in status stops every later
+// launch, so the first failing pivot is the one reported.
+
+__global__ void k_zero(double* p, int64_t cnt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < cnt) p[e] = 0.0;
+}
+
+// diagonal block b: L_bb into S, X_bb = L_bb^{-1} into Linv, and
+// out[0] (+)= 2 sum log diag(L_bb); one wave (as 2 x 2 blocks of 16)
+__global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ S, double* __restrict__ Linv, int m, int mp,
+                                                  int b, double* out, int* status, int code_base) {
+  if (status[0] != 0) return;
+  __shared__ double Db[CB][CB + 1];
+  __shared__ double Di[CB][CB + 1];
+  __shared__ double Dt[16][CB + 1];
+  __shared__ double Dbuf[2 * CB];
+  const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+  const int kb = b * CB, nb = min(CB, m - kb);
+  for (int q = lane; q < CB * CB; q += 64) {
+    Db[q / CB][q % CB] = 0.0;
+    Di[q / CB][q % CB] = 0.0;
+  }
+  double a11[4], a21[4], a22[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int q = lane + 64 * t, i = q >> 4, j = q & 15;
+    a11[t] = ldm(S, kb + i, kb + j, mp, i < nb && j < nb);
+    const int kk = 4 * t + g;
+    a21[t] = ldm(S, kb + 16 + r, kb + kk, mp, 16 + r < nb && kk < nb);
+    const int i2 = acc_row<double>(lane, t);
+    a22[t] = ldm(S, kb + 16 + i2, kb + 16 + r, mp, 16 + i2 < nb && 16 + r < nb);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int q = lane + 64 * t, i = q >> 4, j = q & 15;
+    Dt[i][j] = (i < nb && j < nb) ? a11[t] : (i == j ? 1.0 : 0.0);
+  }
+  wave_sync();
+  int fail = chol_inv16(&Dt[0][0], &Db[0][0], &Di[0][0], Dbuf, lane);
+  if (!fail) {
+    d4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 4)  // L21 = A21 X11^T
+      acc = mfma16(a21[k0 / 4], Di[r][k0 + g], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Db[16 + acc_row<double>(lane, v)][r] = acc[v];
+    wave_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {  // A22 - L21 L21^T
+      const int i = acc_row<double>(lane, v);
+      acc[v] = (16 + i < nb && 16 + r < nb) ? a22[v] : (i == r ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 4) {
+      const double l = Db[16 + r][k0 + g];
+      acc = mfma16(-l, l, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Dt[acc_row<double>(lane, v)][r] = acc[v];
+    wave_sync();
+    fail = chol_inv16(&Dt[0][0], &Db[16][16], &Di[16][16], Dbuf, lane);
+    if (fail) {
+      fail += 16;
+    } else {
+      acc = d4{0, 0, 0, 0};
+#pragma unroll
+      for (int k0 = 0; k0 < 16; k0 += 4)  // T = L21 X11
+        acc = mfma16(Db[16 + r][k0 + g], Di[k0 + g][r], acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Dt[acc_row<double>(lane, v)][r] = acc[v];
+      wave_sync();
+      acc = d4{0, 0, 0, 0};
+#pragma unroll
+      for (int k0 = 0; k0 < 16; k0 += 4)  // X21 = -X22 T
+        acc = mfma16(-Di[16 + r][16 + k0 + g], Dt[k0 + g][r], acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Di[16 + acc_row<double>(lane, v)][r] = acc[v];
+      wave_sync();
+    }
+  }
+  if (fail) {
+    if (lane == 0) {
+      status[0] = VIF_DEV_NOT_PD;
+      status[1] = code_base;
+      status[2] = kb + fail - 1;
+      status[5] = 0;
+    }
+    return;
+  }
+  for (int q = lane; q < nb * nb; q += 64) {
+    const int rr = q / nb, cc = q % nb;
+    if (cc <= rr) {
+      S[(size_t)(kb + rr) * mp + kb + cc] = Db[rr][cc];
+      Linv[(size_t)(kb + rr) * mp + kb + cc] = Di[rr][cc];
+    }
+  }
+  double v = lane < nb ? log(Db[lane][lane]) : 0.0;
+  v = wave_sum(v);
+  if (lane == 0) out[0] = (b == 0 ? 0.0 : out[0]) + 2.0 * v;
+}
+
+// trailing update of step b, one 16x16 lower tile (i >= j) per wave, four
+// per workgroup; X_bb staged in LDS by the workgroup
+__global__ __launch_bounds__(256) void k_chol_trail(double* __restrict__ S, const double* __restrict__ Linv,
+                                                    double* __restrict__ work, int m, int mp, int b,
+                                                    const int* status) {
+  if (status[0] != 0) return;
+  __shared__ double X[CB][CB + 1];
+  __shared__ double P[4][2][16][CB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, g = lane >> 4;
+  const int kb = b * CB, nb = min(CB, m - kb), T0 = kb + nb;
+  const int nt = (m - T0 + 15) / 16, ntile = nt * (nt + 1) / 2;
+  for (int q = tid; q < CB * CB; q += 256) {
+    const int i = q / CB, k = q % CB;
+    X[i][k] = ldm(Linv, kb + i, kb + k, mp, i < nb && k < nb);
+  }
+  __syncthreads();
+  const int q = blockIdx.x * 4 + w;
+  if (q >= ntile) return;
+  int ti = 0, rem = q;
+  while (rem > ti) {
+    rem -= ti + 1;
+    ++ti;
+  }
+  const int tj = rem;
+  const int R0 = T0 + 16 * ti, C0 = T0 + 16 * tj;
+  // panel rows of tile rows R0 (h = 0) and C0 (h = 1): L[r][c] = sum_k A[r][k] X[c][k]
+  for (int h = 0; h < (ti == tj ? 1 : 2); ++h) {
+    const int row = (h == 0 ? R0 : C0) + r;
+    double a[CB / 4];
+#pragma unroll
+    for (int k0 = 0; k0 < CB; k0 += 4) a[k0 / 4] = ldm(S, row, kb + k0 + g, mp, row < m && k0 + g < nb);
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      d4 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int k0 = 0; k0 < CB; k0 += 4) acc = mfma16(a[k0 / 4], X[ct * 16 + r][k0 + g], acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) P[w][h][acc_row<double>(lane, v)][ct * 16 + r] = acc[v];
+    }
+  }
+  wave_sync();
+  const int hj = ti == tj ? 0 : 1;
+  d4 acc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int rr = R0 + acc_row<double>(lane, v), cc = C0 + r;
+    acc[v] = ldm(S, rr, cc, mp, rr < m && cc < m);
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < CB; k0 += 4) acc = mfma16(-P[w][0][r][k0 + g], P[w][hj][r][k0 + g], acc);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int rr = R0 + acc_row<double>(lane, v), cc = C0 + r;
+    if (rr < m && cc < m) S[(size_t)rr * mp + cc] = acc[v];
+  }
+  if (ti == tj)
+    for (int e = lane; e < 16 * CB; e += 64) {
+      const int rr = e / CB, cc = e % CB;
+      if (R0 + rr < m && cc < nb) work[(size_t)(R0 + rr) * mp + kb + cc] = P[w][0][rr][cc];
+    }
+}
+
+// S[i][j] = work[i][j] below the diagonal blocks (the panels of L)
+__global__ void k_chol_panels(double* __restrict__ S, const double* __restrict__ work, int m, int mp,
+                              const int* status) {
+  if (status[0] != 0) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)mp * mp) return;
+  const int i = (int)(e / mp), j = (int)(e % mp);
+  if (i < m && j < m && i / CB > j / CB) S[e] = work[e];
+}
+
+// one block diagonal of X = L^{-1}: block (i, j = i - s) per workgroup, one
+// 16x16 quadrant per wave; W = sum_{k=j}^{i-1} L_ik X_kj (eight MFMA steps'
+// loads in flight), then X_ij = -X_ii W with W exchanged in LDS
+__global__ __launch_bounds__(256) void k_chol_xblock(const double* __restrict__ S, double* __restrict__ Linv, int m,
+                                                     int mp, int s, const int* status) {
+  if (status[0] != 0) return;
+  __shared__ double W[CB][CB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, g = lane >> 4;
+  const int j = blockIdx.x, i = j + s;
+  const int R0 = i * CB + 16 * (w >> 1), C0 = j * CB + 16 * (w & 1);
+  d4 acc = {0, 0, 0, 0};
+  const int k1 = i * CB;
+  for (int k0 = j * CB; k0 < k1; k0 += 32) {
+    double a[8], bb[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int kk = k0 + 4 * t + g;
+      a[t] = ldm(S, R0 + r, kk, mp, R0 + r < m && kk < m);
+      bb[t] = ldm(Linv, kk, C0 + r, mp, kk < m && C0 + r < m);
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc = mfma16(a[t], bb[t], acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) W[16 * (w >> 1) + acc_row<double>(lane, v)][16 * (w & 1) + r] = acc[v];
+  __syncthreads();
+  d4 x = {0, 0, 0, 0};
+#pragma unroll
+  for (int t0 = 0; t0 < CB; t0 += 4) {
+    const double xa = ldm(Linv, R0 + r, i * CB + t0 + g, mp, R0 + r < m && i * CB + t0 + g < m);
+    x = mfma16(-xa, W[t0 + g][16 * (w & 1) + r], x);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int rr = R0 + acc_row<double>(lane, v), cc = C0 + r;
+    if (rr < m && cc < m) Linv[(size_t)rr * mp + cc] = x[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
 void launch_cov_zz(hipStream_t st, const double* Z, int m, int mp, const CovParams& p, double tau_m, double* S,
                    Batch bt, int nprob) {
   hipLaunchKernelGGL(k_cov_zz, dim3(1, mp, nprob), dim3(256), 0, st, Z, m, mp, p, tau_m, S, bt);
 }
 void launch_chol_inv(hipStream_t st, double* S, double* Linv, double* work, int m, int mp, double* out, int* status,
                      int code, int nmat, int ostride) {
-  if (mp <= 16 * kRegNt)
+  if (mp <= 16 * kRegNt) {
     hipLaunchKernelGGL(k_chol_inv_reg, dim3(nmat), dim3(CWG), 0, st, S, Linv, m, mp, out, status, code, ostride);
-  else
+  } else if (nmat > 1) {
     hipLaunchKernelGGL(k_chol_inv, dim3(nmat), dim3(CWG), 0, st, S, Linv, work, m, mp, out, status, code, ostride);
+  } else {
+    const int64_t mm = (int64_t)mp * mp;
+    const int nbk = (m + CB - 1) / CB;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)ceil_div(mm, 256)), dim3(256), 0, st, Linv, mm);
+    for (int b = 0; b < nbk; ++b) {
+      hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, st, S, Linv, m, mp, b, out, status, code);
+      const int T0 = std::min(m, (b + 1) * CB), nt = (m - T0 + 15) / 16, ntile = nt * (nt + 1) / 2;
+      if (ntile > 0)
+        hipLaunchKernelGGL(k_chol_trail, dim3((unsigned)ceil_div(ntile, 4)), dim3(256), 0, st, S, Linv, work, m, mp,
+                           b, status);
+    }
+    hipLaunchKernelGGL(k_chol_panels, dim3((unsigned)ceil_div(mm, 256)), dim3(256), 0, st, S, work, m, mp, status);
+    for (int s = 1; s < nbk; ++s)
+      hipLaunchKernelGGL(k_chol_xblock, dim3((unsigned)(nbk - s)), dim3(256), 0, st, S, Linv, m, mp, s, status);
+  }
 }
 void launch_reduce_gram(hipStream_t st, const double* partial, int nchunk, int mp, double* Mp, double scale, Batch bt,
                         int nprob) {

@@ -1,6 +1,8 @@
 // Host-side launchers of the VIF kernels (one translation unit per family).
 #pragma once
 
+#include <functional>
+
 #include <vector>
 #include "common.h"
 
@@ -144,7 +146,9 @@ void launch_wgram_partial(hipStream_t st, const T* U, const double* sw, int64_t 
 // consecutive small levels are walked by one workgroup; inside a run's rows
 // the entries that point into the run come first, the rest (final before the
 // run starts) are folded into x by a parallel pre-pass.
-constexpr int kTrsvSmallLevel = 128;   // levels with more points get a whole-GPU launch
+constexpr int kTrsvSmallLevel = 64;    // points per level of a one-workgroup run
+constexpr int kTrsvSplitMax = 512;     // larger levels get a whole-GPU launch; smaller ones
+                                       // are walked as parts of kTrsvSmallLevel points
 constexpr int kTrsvRunLevels = 2048;   // levels per run
 constexpr int kTrsvRunCap = 16384;     // positions per run (their z sit in LDS)
 struct TriSchedule {
@@ -168,19 +172,30 @@ struct TriSchedule {
   int64_t npad = 0;  // padded rows
   const int* hpbase = nullptr;
   // level offsets of the single-right-hand-side solves: levels of
-  // kTrsvSmallLevel + 1 to 2 kTrsvSmallLevel points split in two halves;
-  // hrun indexes these
+  // kTrsvSmallLevel + 1 to kTrsvSplitMax points split into parts of at most
+  // kTrsvSmallLevel; hrun indexes these
   const int* slvl = nullptr;   // device (nslev + 1)
   const int* hslvl = nullptr;  // host
   int nslev = 0;
+  // B^T only: the in-run entries of a run row past its first kTrsvPad, at
+  // element offset `ov` of col, src and the coefficient buffer; run r's
+  // block is [hobase[r], hobase[r + 1]) (at most kTrsvOvCap entries, staged
+  // in LDS by the run), a row's entries start at split[2 n + q] in it
+  int64_t ov = 0;
+  int64_t nov = 0;
+  const int* hobase = nullptr;
 };
-constexpr int kTrsvPad = 32;  // slots of a padded run row
+constexpr int kTrsvPad = 32;     // slots of a padded run row
+constexpr int kTrsvOvCap = 1792;  // in-run entries past the padded slots per run (held in LDS)
 // element offset of the padded rows behind `ne` entries (16-byte aligned for
 // 4-byte and 8-byte elements); buffers hold trsv_pad_offset(ne) + kTrsvPad n
 inline size_t trsv_pad_offset(size_t ne) { return (ne + 3) & ~(size_t)3; }
 // runs of a level schedule (host): consecutive levels of <= kTrsvSmallLevel
 // points, at most kTrsvRunLevels levels and kTrsvRunCap positions each
-void trsv_runs(const int* hlvl, int nlev, std::vector<int>& runs);
+// overflow(q, P0): in-run entries of row q past kTrsvPad when its run
+// starts at position P0 (runs hold at most kTrsvOvCap of them in total)
+void trsv_runs(const int* hlvl, int nlev, std::vector<int>& runs,
+               const std::function<int(int, int)>& overflow = nullptr);
 template <typename T>
 void launch_trsv_fwd(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, double* xq, double* zq,
                      double* z);

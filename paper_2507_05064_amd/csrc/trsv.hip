@@ -10,29 +10,33 @@
 // contiguous memory, and the next level's rows can be loaded before the
 // current level's results are known.
 //
-// Small levels (at most kTrsvSmallLevel = 128 points) are walked by one
-// workgroup, a run of consecutive small levels per launch, with as many waves
-// as the run's widest level needs (8 points per wave, up to 16 waves); a
-// wave whose points lie beyond a level skips its arithmetic. The run's
-// positions are contiguous and their z values live in LDS for the whole run,
-// so a level's dependence on earlier levels of the run is an LDS read and the
-// barrier between levels waits for LDS only. A row's entries that point
-// before the run are final when the run starts: a parallel pre-pass over the
-// run's rows adds them into x, and the walk reads only the in-run entries.
-// The run's z is written back once at its end.
+// Small levels (at most kTrsvSmallLevel = 64 points; the solve's schedule
+// walks levels of up to kTrsvSplitMax points as consecutive parts of at most
+// 64) are walked by one workgroup, a run of consecutive small levels per
+// launch, with as many waves as the run's widest level needs (8 points per
+// wave, up to 8 waves); a wave whose points lie beyond a level skips its
+// arithmetic. The run's positions are contiguous and their z values live in
+// LDS for the whole run, so a level's dependence on earlier levels of the
+// run is an LDS read and the barrier between levels waits for LDS only. A
+// row's entries that point before the run are final when the run starts: a
+// parallel pre-pass over the run's rows adds them into x, and the walk reads
+// only the in-run entries. The run's z is written back once at its end.
 // The walk reads padded copies of the run's rows: kTrsvPad = 32 slots per
-// row holding its first 32 in-run entries (B rows have at most 31; a longer
-// B^T row takes the rest from its CSR row at its step). Each point gets 8
+// row holding its first 32 in-run entries (B rows have at most 31; the
+// entries of longer B^T rows past the 32, which the early points of the
+// ordering have, are copied to LDS when the run starts, at most kTrsvOvCap
+// per run). Each point gets 8
 // lanes and each lane 4 consecutive slots, so a wave's 8 rows are one
 // contiguous stretch of memory and its loads are 16 bytes per lane. The
 // loads are buffer loads through resources that span the run's rows (one
 // 32-bit offset per row, slots past the run's data read as zero by the
-// hardware's range check), issued four levels ahead into five rotating
-// register sets. Every load is unconditional and every loaded register is
-// read on every path, so the compiler counts the loads in flight exactly and
-// a level waits only for its own rows. Coefficients stay in their stored
-// type until used. The 8 partial sums of a point are added by three DPP
-// steps within the row of 16 lanes.
+// hardware's range check), issued seven levels ahead into eight rotating
+// register sets: the rows come from HBM, and the distance covers its latency
+// at a few tenths of a microsecond per level. Every load is unconditional
+// and every loaded register is read on every path, so the compiler counts
+// the loads in flight exactly and a level waits only for its own rows.
+// Coefficients stay in their stored type until used. The 8 partial sums of a
+// point are added by three DPP steps within the row of 16 lanes.
 // Larger levels get a launch of their own over the whole GPU (32 lanes per
 // point); kernel order on the stream separates them.
 #include "common.h"
@@ -40,9 +44,9 @@
 
 constexpr int kRunG = 8;   // lanes per point in a run
 constexpr int kPre = 4;    // consecutive slots per lane (kRunG * kPre = kTrsvPad)
-constexpr int kDepth = 4;  // register sets: rows are loaded kDepth - 1 levels ahead
+constexpr int kDepth = 8;  // register sets: rows are loaded kDepth - 1 levels ahead
 static_assert(kRunG * kPre == kTrsvPad, "a lane group holds a padded row");
-static_assert(kRunG * kTrsvSmallLevel == 1024, "a run level fills at most one 1024-thread workgroup");
+static_assert(kRunG * kTrsvSmallLevel == 512, "a run level fills at most one 512-thread workgroup");
 
 // barrier for LDS traffic only: outstanding global loads (the next levels'
 // rows) stay in flight across it
@@ -87,12 +91,14 @@ struct RowRegs {
   u4v c;                                          // four entry positions
   typename CoefVec<T>::type w[CoefVec<T>::cnt];  // four coefficients
   int n;                                          // in-run entries of the row
+  int o;                                          // B^T: first entry past the padded slots in the run's block
 };
 
 template <typename T>
 __device__ __forceinline__ void load_row(RowRegs<T>& r, __amdgpu_buffer_rsrc_t rc, __amdgpu_buffer_rsrc_t rw,
-                                         __amdgpu_buffer_rsrc_t rn, int q, int lig) {
+                                         __amdgpu_buffer_rsrc_t rn, __amdgpu_buffer_rsrc_t ro, int q, int lig) {
   r.n = (int)__builtin_amdgcn_raw_buffer_load_b32(rn, q * 4, 0, 0);
+  r.o = (int)__builtin_amdgcn_raw_buffer_load_b32(ro, q * 4, 0, 0);
   const int slot = q * kTrsvPad + lig * kPre;
   r.c = __builtin_amdgcn_raw_buffer_load_b128(rc, slot * 4, 0, 0);
 #pragma unroll
@@ -112,7 +118,7 @@ __device__ __forceinline__ double coef_at(const RowRegs<T>& r, int k) {
 // drain all loads in flight before the register is reused
 template <typename T>
 __device__ __forceinline__ void consume(const RowRegs<T>& r) {
-  asm volatile("" ::"v"(r.c), "v"(r.n));
+  asm volatile("" ::"v"(r.c), "v"(r.n), "v"(r.o));
 #pragma unroll
   for (int h = 0; h < CoefVec<T>::cnt; ++h) asm volatile("" ::"v"(r.w[h]));
 }
@@ -136,17 +142,20 @@ __device__ __forceinline__ double row_sum(const RowRegs<T>& r, int lig, int lim,
 
 // A run of small levels, either direction: the padded row of position q
 // (P0 <= q < P0 + np) at padded row prow + (q - P0) of pcol / pcoef, cnt[q]
-// in-run entries. A row with more than kTrsvPad of them (B^T only) takes the
-// rest from its CSR row (ovptr[q] on, ovcol / ovcoef), loaded at its step.
+// in-run entries. A row with more than kTrsvPad of them (B^T only) finds the
+// rest at ovoff[q] in the run's block ovcol / ovcoef of nov entries, which
+// the run copies to LDS at its start (B: ovoff = cnt, nov = 0).
 template <typename T>
-__global__ __launch_bounds__(1024) void k_trsv_run(const int* __restrict__ lvl, int L0, int L1,
+__global__ __launch_bounds__(512) void k_trsv_run(const int* __restrict__ lvl, int L0, int L1,
                                                    const int* __restrict__ pcol, const T* __restrict__ pcoef,
                                                    int64_t prow, const int* __restrict__ cnt,
-                                                   const int* __restrict__ ovptr, const int* __restrict__ ovcol,
-                                                   const T* __restrict__ ovcoef, const double* __restrict__ xq,
-                                                   double* zq) {
+                                                   const int* __restrict__ ovoff, const int* __restrict__ ovcol,
+                                                   const T* __restrict__ ovcoef, int nov,
+                                                   const double* __restrict__ xq, double* zq) {
   __shared__ int slv[kTrsvRunLevels + 1];
   __shared__ double zs[kTrsvRunCap];
+  __shared__ int ovc[kTrsvOvCap];
+  __shared__ double ovw[kTrsvOvCap];
   const int nt = blockDim.x;
   for (int t = threadIdx.x; t <= L1 - L0; t += nt) slv[t] = lvl[L0 + t];
   __syncthreads();
@@ -157,15 +166,20 @@ __global__ __launch_bounds__(1024) void k_trsv_run(const int* __restrict__ lvl, 
   const __amdgpu_buffer_rsrc_t rc = span(pcol + prow * kTrsvPad, (int64_t)np * kTrsvPad * 4);
   const __amdgpu_buffer_rsrc_t rw = span(pcoef + prow * kTrsvPad, (int64_t)np * kTrsvPad * sizeof(T));
   const __amdgpu_buffer_rsrc_t rn = span(cnt + P0, (int64_t)np * 4);
+  const __amdgpu_buffer_rsrc_t ro = span(ovoff + P0, (int64_t)np * 4);
   // zs starts as the run's x; a point's step adds its sum
   for (int t = threadIdx.x; t < np; t += nt) zs[t] = xq[P0 + t];
+  for (int t = threadIdx.x; t < nov; t += nt) {
+    ovc[t] = ovcol[t];
+    ovw[t] = (double)ovcoef[t];
+  }
   __syncthreads();
   // the row of level L for the point of this lane group; a group past the
   // level loads at an offset past the run (zeros, no memory access). Every
   // lane issues the same loads on every path.
   auto load = [&](RowRegs<T>& r, int L) {
     const int beg = slv[L], cn = slv[L + 1] - beg;
-    load_row(r, rc, rw, rn, grp < cn ? beg + grp - P0 : np, lig);
+    load_row(r, rc, rw, rn, ro, grp < cn ? beg + grp - P0 : np, lig);
   };
   auto step = [&](const RowRegs<T>& r, int L) {
     const int beg = slv[L], cn = slv[L + 1] - beg;
@@ -174,20 +188,10 @@ __global__ __launch_bounds__(1024) void k_trsv_run(const int* __restrict__ lvl, 
       const bool act = grp < cn;
       const int nin = act ? r.n : 0;
       double s = row_sum(r, lig, nin, P0, zs);
-      if (ovptr != nullptr && nin > kTrsvPad) {  // the rest, 4 per lane at a time
-        const int e0 = ovptr[beg + grp];
-        for (int a0 = kTrsvPad + lig; a0 < nin; a0 += 4 * kRunG) {
-          int cc[4];
-          double ww[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int a = a0 + k * kRunG;
-            cc[k] = a < nin ? ovcol[e0 + a] : P0;
-            ww[k] = a < nin ? (double)ovcoef[e0 + a] : 0.0;
-          }
-#pragma unroll
-          for (int k = 0; k < 4; ++k) s += ww[k] * zs[cc[k] - P0];
-        }
+      // entries past the padded slots, from LDS
+      for (int a = kTrsvPad + lig; a < nin; a += kRunG) {
+        const int t = r.o + a - kTrsvPad;
+        s = fma(ovw[t], zs[ovc[t] - P0], s);
       }
       s = oct_sum(s);
       if (act && lig == 0) zs[beg + grp - P0] += s;
@@ -318,18 +322,30 @@ static int run_threads(const int* hlvl, int L0, int L1) {
   return 64 * (int)ceil_div(w, 64 / kRunG);
 }
 
-void trsv_runs(const int* hlvl, int nlev, std::vector<int>& runs) {
+void trsv_runs(const int* hlvl, int nlev, std::vector<int>& runs, const std::function<int(int, int)>& overflow) {
   runs.clear();
+  auto level_overflow = [&](int L, int P0) {
+    int o = 0;
+    if (overflow)
+      for (int q = hlvl[L]; q < hlvl[L + 1]; ++q) o += overflow(q, P0);
+    return o;
+  };
   int L = 0;
   while (L < nlev) {
     if (hlvl[L + 1] - hlvl[L] > kTrsvSmallLevel) {
       ++L;
       continue;
     }
-    int L1 = L + 1;
+    // a run's first level has no in-run entries
+    const int P0 = hlvl[L];
+    int L1 = L + 1, ov = 0;
     while (L1 < nlev && L1 - L < kTrsvRunLevels && hlvl[L1 + 1] - hlvl[L1] <= kTrsvSmallLevel &&
-           hlvl[L1 + 1] - hlvl[L] <= kTrsvRunCap)
+           hlvl[L1 + 1] - P0 <= kTrsvRunCap) {
+      const int o = level_overflow(L1, P0);
+      if (ov + o > kTrsvOvCap) break;
+      ov += o;
       ++L1;
+    }
     runs.push_back(L);
     runs.push_back(L1);
     L = L1;
@@ -348,7 +364,7 @@ void launch_trsv_fwd(hipStream_t st, const TriSchedule& s, const T* coef, const 
       hipLaunchKernelGGL((k_trsv_fwd_pre<T>), dim3((unsigned)ceil_div(P1 - P0, 8)), dim3(256), 0, st, P0, P1,
                          s.col, coef, s.split, s.mv, zq, xq);
       hipLaunchKernelGGL((k_trsv_run<T>), dim3(1), dim3(run_threads(s.hslvl, L, L1)), 0, st, s.slvl, L, L1,
-                         s.col + s.pad, coef + s.pad, (int64_t)s.hpbase[r], s.split, nullptr, nullptr, nullptr, xq,
+                         s.col + s.pad, coef + s.pad, (int64_t)s.hpbase[r], s.split, s.split, s.col, coef, 0, xq,
                          zq);
       L = L1;
       ++r;
@@ -374,7 +390,8 @@ void launch_trsv_bwd(hipStream_t st, const TriSchedule& s, const T* coef, const 
       hipLaunchKernelGGL((k_trsv_bwd_pre<T>), dim3((unsigned)ceil_div(P1 - P0, 8)), dim3(256), 0, st, P0, P1,
                          s.ptr, s.split, s.col, coef, zq, xq);
       hipLaunchKernelGGL((k_trsv_run<T>), dim3(1), dim3(run_threads(s.hslvl, L, L1)), 0, st, s.slvl, L, L1,
-                         s.col + s.pad, coef + s.pad, (int64_t)s.hpbase[r], s.split + s.n, s.ptr, s.col, coef, xq,
+                         s.col + s.pad, coef + s.pad, (int64_t)s.hpbase[r], s.split + s.n, s.split + 2 * (int64_t)s.n,
+                         s.col + s.ov + s.hobase[r], coef + s.ov + s.hobase[r], s.hobase[r + 1] - s.hobase[r], xq,
                          zq);
       L = L1;
       ++r;
@@ -403,6 +420,9 @@ void launch_coef_bwd(hipStream_t st, const TriSchedule& s, const T* A, T* coef) 
   const int64_t np = s.npad * kTrsvPad;  // the padded run rows
   if (np > 0) hipLaunchKernelGGL((k_coef_src<T>), dim3((unsigned)ceil_div(np, 256)), dim3(256), 0, st, s.src + s.pad,
                                  A, np, coef + s.pad);
+  if (s.nov > 0)  // the runs' entries past the padded slots
+    hipLaunchKernelGGL((k_coef_src<T>), dim3((unsigned)ceil_div(s.nov, 256)), dim3(256), 0, st, s.src + s.ov, A,
+                       s.nov, coef + s.ov);
 }
 
 #define INST(T)                                                                                                    \
