@@ -407,61 +407,98 @@ def batch_leg(steps, warmup, log):
 
 def c5_leg(reps, log, ell=50):
     """Poisson-log latent VIF at n = 1,000,000 in [0,1]^2 (Matern-1/2, variance
-    1, range 0.05, m = 500 k-means++ inducing points, m_v = 20), FP32 factor
-    with FP64 L_m and log-determinants: factor build, mode from the zero start,
-    then the Laplace NLL and its gradient with ell = 50 SLQ/STE probes (one
-    evaluation = build + mode + NLL + gradient)."""
+    1, range 0.05, m = 500 k-means++ inducing points selected on the GPU,
+    m_v = 20), FP32 factor with FP64 L_m and log-determinants. A warm-start
+    network is trained on two problems drawn on the same inputs (parameters
+    scaled, other prior draws), with modes by the method. One evaluation: the
+    factor build, the mode from the network's start (features and network
+    included), then the Laplace NLL and its gradient with ell = 50 SLQ/STE
+    probes. The warm-up pass also times the mode from zero (FITC and VIFDU)."""
     import torch
     import vif_inputs as vi
+    from paper_2507_05064_amd import warmstart as ws
     from paper_2507_05064_amd.vif import VifContext
     w = vi.config5()
     t0 = time.perf_counter()
     X = vi.coords(w)
-    Z = vi.inducing_points(w, X)
-    Xd, Zd = torch.as_tensor(X, device="cuda"), torch.as_tensor(Z, device="cuda")
+    Xd = torch.as_tensor(X, device="cuda")
     ctx = VifContext(w.n, w.d, w.m, w.m_v, kernel=w.kernel, likelihood=w.likelihood, precision="fp32",
                      tau_m=w.tau_m, cg_tol=1e-6, cg_maxit=2000, max_probes=ell)
+    unif = vi.rng(w.config, vi.STREAM_INDUCING, 0).uniform(size=w.m)
+    Zd = ctx.select_inducing(Xd, w.theta, unif=unif, lloyd_iters=10)
+    torch.cuda.synchronize()
+    t_ind = time.perf_counter() - t0
+    t1 = time.perf_counter()
     nbr = ctx.select_neighbors(Xd, Zd, w.theta)
-    ctx.build_factor(Xd, Zd, nbr, w.theta)
-    eps1, eps2, u = vi.prior_noise(w)
-    b = ctx.sample_prior(torch.as_tensor(eps1, device="cuda"), torch.as_tensor(eps2, device="cuda")).cpu().numpy()
-    yd = torch.as_tensor(vi.poisson_from_uniform(np.exp(b), u), device="cuda")
+    torch.cuda.synchronize()
+    t_knn = time.perf_counter() - t1
+    ctx.set_preconditioner("fitc")  # mode finding on eq. pcls2 with FITC
+
+    def draw(problem, theta):
+        ctx.build_factor(Xd, Zd, nbr, theta)
+        eps1, eps2, u = vi.prior_noise(w, problem)
+        b = ctx.sample_prior(torch.as_tensor(eps1, device="cuda"), torch.as_tensor(eps2, device="cuda"))
+        return torch.as_tensor(vi.poisson_from_uniform(np.exp(b.cpu().numpy()), u), device="cuda")
+
+    # warm-start network: training pairs from two problems on the same inputs
+    t1 = time.perf_counter()
+    feats, targets = [], []
+    for prob, sc in ((1, (0.8, 1.1)), (2, (1.25, 0.9))):
+        th = w.theta.copy()
+        th[0] *= sc[0]
+        th[1:-1] *= sc[1]
+        y_t = draw(prob, th)
+        mode_t, _, _ = ctx.laplace_mode(y_t)
+        feats.append(ctx.mlp_features(y_t))
+        targets.append(mode_t.float())
+    mlp = ws.train(torch.cat(feats), torch.cat(targets), epochs=10)
+    del feats, targets
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    yd = draw(0, w.theta)
     e3, e1, e2 = vi.probe_normals(w, ell)
     eps_n = np.empty((2 * ell, w.n))
     eps_n[0::2], eps_n[1::2] = e1.T, e2.T
     eps_nd, eps_md = torch.as_tensor(eps_n, device="cuda"), torch.as_tensor(np.ascontiguousarray(e3.T), device="cuda")
     del eps_n
-    log(f"c5: inputs in {time.perf_counter() - t0:.1f} s")
+    log(f"c5: inputs {time.perf_counter() - t0:.1f} s (inducing points {t_ind:.1f} s, neighbours {t_knn:.1f} s, "
+        f"warm-start training {t_train:.1f} s)")
     times = {"build": [], "mode": [], "nll_grad": []}
     out = None
-    vifdu_mode = None
+    zero = {}
     for r in range(reps + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.build_factor(Xd, Zd, nbr, w.theta)
         torch.cuda.synchronize()
-        if r == 0:  # the warm-up pass also times the mode with the VIFDU preconditioner
-            ctx.set_preconditioner("vifdu")
-            tv = time.perf_counter()
-            _, stv, _ = ctx.laplace_mode(yd)
-            torch.cuda.synchronize()
-            vifdu_mode = {"mode_ms": 1000 * (time.perf_counter() - tv), "newton_iters": stv["newton_iters"],
-                          "pcg_iters_total": stv["pcg_iters_total"]}
         t1 = time.perf_counter()
-        ctx.set_preconditioner("fitc")  # mode finding on eq. pcls2 with FITC
-        mode, st, _ = ctx.laplace_mode(yd)
+        b0 = mlp.forward(ctx.mlp_features(yd), double=True)
+        mode, st, _ = ctx.laplace_mode(yd, b0)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        ctx.set_preconditioner("vifdu")  # the gradient's trace estimates reuse VIFDU solves
+        ctx.set_preconditioner("vifdu")  # the gradient's trace estimates on VIFDU block solves (eq. slq_v1)
         nll, grad = ctx.laplace_nll_grad(yd, mode, eps_nd, eps_md)
+        ctx.set_preconditioner("fitc")
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        if r == 0:  # the warm-up pass also times the modes from zero
+            for form in ("vifdu", "fitc"):
+                ctx.set_preconditioner(form)
+                tv = time.perf_counter()
+                mode0, stz, _ = ctx.laplace_mode(yd)
+                torch.cuda.synchronize()
+                zero[form] = {"mode_ms": 1000 * (time.perf_counter() - tv), "newton_iters": stz["newton_iters"],
+                              "pcg_iters_total": stz["pcg_iters_total"], "psi": stz["psi"]}
         if r > 0:  # the first pass warms up
             times["build"].append(1000 * (t1 - t0))
             times["mode"].append(1000 * (t2 - t1))
             times["nll_grad"].append(1000 * (t3 - t2))
         out = dict(nll=nll, grad=[float(v) for v in grad], newton_iters=st["newton_iters"],
-                   pcg_iters_total=st["pcg_iters_total"], levels_fwd=st["levels_fwd"])
+                   pcg_iters_total=st["pcg_iters_total"], start_used=st["start_used"],
+                   levels_fwd=st["levels_fwd"],
+                   net_rel_err=float(torch.linalg.norm(b0 - mode) / torch.linalg.norm(mode)),
+                   mode_rel_diff_vs_zero_start=float(torch.linalg.norm(mode - mode0) / torch.linalg.norm(mode0)),
+                   psi=st["psi"])
         log(f"c5 rep {r}: build {1000 * (t1 - t0):.1f} ms, mode {1000 * (t2 - t1):.1f} ms, "
             f"nll+grad {1000 * (t3 - t2):.1f} ms, {out}")
     ctx.close()
@@ -469,10 +506,12 @@ def c5_leg(reps, log, ell=50):
     res["eval_ms_median"] = sum(res.values())
     res.update(out)
     res["probes"] = ell
-    res["mode_vifdu_warmup_pass"] = vifdu_mode
+    res["mode_from_zero_warmup_pass"] = zero
+    res["setup_s"] = {"inducing_points": t_ind, "neighbours": t_knn, "warm_start_training": t_train}
     res["workload"] = ("Poisson-log latent VIF: n=1000000 d=2 Matern-1/2 (var 1, range 0.05), m=500 k-means++ "
                        "inducing points, m_v=20, b from the VIF prior; FP32 factor; mode by Newton + FITC-PCG "
-                       "(tol 1e-6) from zero, Laplace NLL + gradient with 50 SLQ/STE probes (VIFDU)")
+                       "(tol 1e-6) from the learned warm start, Laplace NLL + gradient with 50 SLQ/STE probes "
+                       "(VIFDU, eq. slq_v1)")
     return res
 
 
@@ -596,8 +635,10 @@ def main():
                     help="only the n = 100k NLL + gradient step in its three forms (for kernel traces and counters)")
     ap.add_argument("--laplace-only", action="store_true",
                     help="only the n = 200k Laplace leg (for its kernel trace)")
-    ap.add_argument("--c5", action="store_true",
-                    help="also run the n = 1M Poisson leg (Laplace NLL + gradient; a few minutes of set-up)")
+    ap.add_argument("--skip-c5", action="store_true",
+                    help="leave out the n = 1M Poisson leg (its set-up, neighbour search and warm-start training, "
+                         "takes about a minute)")
+    ap.add_argument("--c5-only", action="store_true", help="only the n = 1M Poisson leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -614,6 +655,9 @@ def main():
     if args.laplace_only:
         print(json.dumps({"laplace": laplace_leg(args.laplace_reps, 1,
                                                  lambda msg: print(msg, file=sys.stderr, flush=True))}))
+        return
+    if args.c5_only:
+        print(json.dumps({"laplace_nll_grad_c5": c5_leg(2, lambda msg: print(msg, file=sys.stderr, flush=True))}))
         return
     if args.pcg_only:
         print(json.dumps({"pcg": pcg_leg(args.laplace_reps, lambda msg: print(msg, file=sys.stderr, flush=True))}))
@@ -702,7 +746,7 @@ def main():
         res["batch"] = batch_leg(args.steps, args.warmup, lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_laplace:
         res["laplace"] = laplace_leg(args.laplace_reps, 1, lambda msg: print(msg, file=sys.stderr, flush=True))
-    if args.c5:
+    if not args.skip_c5:
         res["laplace_nll_grad_c5"] = c5_leg(2, lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w)
