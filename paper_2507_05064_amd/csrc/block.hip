@@ -83,20 +83,38 @@ __global__ void k_scale_e_multi(const double* __restrict__ v, const double* __re
 }
 
 // ------------------------------------------------------------ B and B^T
-// out[i][l] = (x[i][l] - sum_a A_ia x[N(i)_a][l]) * (D ? D_i^{-1/2} : 1); one wave per point
+// One wave per row (the row index uniform, so its slots load through the
+// scalar cache), lanes over the right-hand sides; the slots are taken eight
+// at a time with the eight gathers in flight, in slot order. An empty slot
+// gathers row 0 with its value replaced by 0.
+// out[i][l] = (x[i][l] - sum_a A_ia x[N(i)_a][l]) * (D ? D_i^{-1/2} : 1)
 template <typename T>
 __global__ __launch_bounds__(256) void k_bw_multi(const T* __restrict__ A, const double* __restrict__ D,
                                                   const int32_t* __restrict__ nbr, const double* __restrict__ x,
                                                   int64_t n, int mv, int L, double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n || lane >= L) return;
-  double s = x[i * L + lane];
-  for (int a = 0; a < mv; ++a) {
-    const int j = nbr[i * mv + a];
-    if (j >= 0) s -= (double)A[i * mv + a] * x[(int64_t)j * L + lane];
+  const int64_t i = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  if (i >= n) return;
+  const int ll = min(lane, L - 1);  // lanes past L read a valid column, write nothing
+  double s = x[i * L + ll];
+  for (int a0 = 0; a0 < mv; a0 += 8) {
+    int c[8];
+    bool ok[8];
+    double w[8], z[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int a = min(a0 + k, mv - 1);
+      const int j = nbr[i * mv + a];
+      ok[k] = a0 + k < mv && j >= 0;
+      c[k] = ok[k] ? j : 0;
+      w[k] = ok[k] ? (double)A[i * mv + a] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) z[k] = x[(int64_t)c[k] * L + ll];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s -= w[k] * (ok[k] ? z[k] : 0.0);
   }
-  out[i * L + lane] = D ? s / sqrt(D[i]) : s;
+  if (lane < L) out[i * L + lane] = D ? s / sqrt(D[i]) : s;
 }
 
 // out[i][l] = -sum_a dA_ia x[N(i)_a][l]   (dB x, dB_{i,N(i)} = -dA_i)
@@ -105,14 +123,28 @@ __global__ __launch_bounds__(256) void k_dbx_multi(const T* __restrict__ dA, con
                                                    const double* __restrict__ x, int64_t n, int mv, int L,
                                                    double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n || lane >= L) return;
+  const int64_t i = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  if (i >= n) return;
+  const int ll = min(lane, L - 1);
   double s = 0.0;
-  for (int a = 0; a < mv; ++a) {
-    const int j = nbr[i * mv + a];
-    if (j >= 0) s -= (double)dA[i * mv + a] * x[(int64_t)j * L + lane];
+  for (int a0 = 0; a0 < mv; a0 += 8) {
+    int c[8];
+    bool ok[8];
+    double w[8], z[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int a = min(a0 + k, mv - 1);
+      const int j = nbr[i * mv + a];
+      ok[k] = a0 + k < mv && j >= 0;
+      c[k] = ok[k] ? j : 0;
+      w[k] = ok[k] ? (double)dA[i * mv + a] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) z[k] = x[(int64_t)c[k] * L + ll];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s -= w[k] * (ok[k] ? z[k] : 0.0);
   }
-  out[i * L + lane] = s;
+  if (lane < L) out[i * L + lane] = s;
 }
 
 // out[j][l] = s[j][l] - sum_{(q, slot): N(q)_slot = j} A_{q,slot} s[q][l] + (W ? W_j p[j][l] : 0)
@@ -122,15 +154,26 @@ __global__ __launch_bounds__(256) void k_btw_multi(const T* __restrict__ A, cons
                                                    const double* __restrict__ W, const double* __restrict__ p,
                                                    int64_t n, int mv, int L, double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= n || lane >= L) return;
+  const int64_t j = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  if (j >= n) return;
+  const int ll = min(lane, L - 1);
   double v = 0.0;
-  const int end = rev_ptr[j + 1];
-  for (int q = rev_ptr[j]; q < end; ++q) {
-    const int idx = rev_idx[q];
-    v += (double)A[idx] * s[(int64_t)(idx / mv) * L + lane];
+  const int q0 = rev_ptr[j], q1 = rev_ptr[j + 1];
+  for (int a0 = q0; a0 < q1; a0 += 8) {
+    int c[8];
+    double w[8], z[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int idx = rev_idx[min(a0 + k, q1 - 1)];
+      c[k] = idx / mv;
+      w[k] = a0 + k < q1 ? (double)A[idx] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) z[k] = s[(int64_t)c[k] * L + ll];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += w[k] * z[k];
   }
-  out[j * L + lane] = s[j * L + lane] - v + (W ? W[j] * p[j * L + lane] : 0.0);
+  if (lane < L) out[j * L + lane] = s[j * L + lane] - v + (W ? W[j] * p[j * L + lane] : 0.0);
 }
 
 // one level of B^{-1} (positions [beg, end), row q: m_v slots of positions

@@ -92,10 +92,24 @@ __global__ __launch_bounds__(256) void k_bw(const T* __restrict__ A, const doubl
   const int64_t i = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
   if (i >= n) return;  // whole 8-lane groups leave together
   double s = 0.0;
-  for (int a = lig; a < mv; a += 8) {
-    const int j = nbr[i * mv + a];
-    if (j >= 0) s += (double)A[i * mv + a] * w[j];
+  // slots lig, lig + 8, lig + 16, lig + 24 (m_v <= 31) with their gathers in
+  // flight together; an empty slot gathers w[i] with weight 0
+  int c[4];
+  bool ok[4];
+  double a[4], z[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int sl = lig + 8 * k;
+    const int j = sl < mv ? nbr[i * mv + sl] : -1;
+    ok[k] = j >= 0;
+    c[k] = ok[k] ? j : (int)i;
+    a[k] = ok[k] ? (double)A[i * mv + sl] : 0.0;
   }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) z[k] = w[c[k]];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (ok[k]) s += a[k] * z[k];
 #pragma unroll
   for (int o = 4; o > 0; o >>= 1) s += __shfl_xor(s, o, 8);
   if (lig == 0) t[i] = (w[i] - s) / sqrt(D[i]);
@@ -247,10 +261,23 @@ __global__ __launch_bounds__(256) void k_btw(const T* __restrict__ A, const int*
   const int64_t j = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
   if (j >= n) return;  // whole 8-lane groups leave together
   double v = 0.0;
-  const int end = rev_ptr[j + 1];
-  for (int q = rev_ptr[j] + lig; q < end; q += 8) {
-    const int idx = rev_idx[q];
-    v += (double)A[idx] * s[idx / mv];
+  const int beg = rev_ptr[j], end = rev_ptr[j + 1];
+  // this lane's entries beg + lig, beg + lig + 8, ... four at a time, their
+  // gathers in flight together (entries past the end repeat the row's last
+  // entry and are skipped)
+  for (int q0 = beg + lig; q0 < end; q0 += 32) {
+    int idx[4];
+    double a[4], z[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) idx[k] = rev_idx[min(q0 + 8 * k, end - 1)];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k] = (double)A[idx[k]];
+      z[k] = s[idx[k] / mv];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (q0 + 8 * k < end) v += a[k] * z[k];
   }
 #pragma unroll
   for (int o = 4; o > 0; o >>= 1) v += __shfl_xor(v, o, 8);
