@@ -489,6 +489,12 @@ def c5_leg(reps, log, ell=50):
                 torch.cuda.synchronize()
                 zero[form] = {"mode_ms": 1000 * (time.perf_counter() - tv), "newton_iters": stz["newton_iters"],
                               "pcg_iters_total": stz["pcg_iters_total"], "psi": stz["psi"]}
+            # the same NLL + gradient with the FITC preconditioner (eq. slq_v2, App. E.2)
+            tv = time.perf_counter()
+            nll_f, grad_f = ctx.laplace_nll_grad(yd, mode, eps_nd, eps_md)
+            torch.cuda.synchronize()
+            zero["fitc_nll_grad"] = {"ms": 1000 * (time.perf_counter() - tv), "nll": nll_f,
+                                     "grad": [float(v) for v in grad_f]}
         if r > 0:  # the first pass warms up
             times["build"].append(1000 * (t1 - t0))
             times["mode"].append(1000 * (t2 - t1))

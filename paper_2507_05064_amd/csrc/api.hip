@@ -1843,22 +1843,53 @@ static void blk_vifdu_apply(vif_ctx* c, BlkBufs& K, LapBufs& B, const double* r,
   launch_trsv_fwd_multi<T>(c->st, c->sf, (const T*)c->fcoef, K.q2, L, K.xq, K.zq, z);
 }
 
-// L independent preconditioned CG solves A x_l = rhs_l (A = W + Sigma_dagger^{-1},
-// VIFDU), from x = 0, each to its own rule ||r_l|| <= cg_tol ||rhs_l||, with
+// z = P^{-1} r (FITC of the current D_V and M_V) for a block of L vectors:
+// z = D_V^{-1} (r - V M_V^{-1} V^T D_V^{-1} r)
+template <typename T>
+static void blk_fitc_apply(vif_ctx* c, BlkBufs& K, LapBufs& B, const double* r, int L, double* z) {
+  const vif_config& g = c->cfg;
+  const T* V = form_V<T>(c);
+  if (g.m > 0) {
+    launch_scale_rows_multi(c->st, B.E, r, g.n, L, K.q);
+    launch_utx<T>(c->st, V, K.q, g.n, c->mp, L, c->M3inv, K.part, K.cm2, K.cm);
+  }
+  launch_rowmm_multi<T>(c->st, V, K.cm, r, B.E, nullptr, g.n, c->mp, L, 4, z);
+}
+
+// out = (W^{-1} + Sigma_dagger) p for a block of L vectors (eq. pcls2):
+// B^{-1} D B^{-T} p + V^T (V p) + p / W
+template <typename T>
+static void blk_sigma_matvec(vif_ctx* c, BlkBufs& K, const double* p, int L, const double* W, double* out) {
+  const vif_config& g = c->cfg;
+  const T* V = form_V<T>(c);
+  launch_trsv_bwd_multi<T>(c->st, c->sb, (const T*)c->bcoef, p, L, K.xq, K.zq, K.w);
+  launch_scale_rows_multi(c->st, c->D, K.w, g.n, L, K.q);
+  launch_trsv_fwd_multi<T>(c->st, c->sf, (const T*)c->fcoef, K.q, L, K.xq, K.zq, K.q2);
+  launch_add_rows_div_multi(c->st, K.q2, p, W, g.n, L, K.q2);
+  if (g.m > 0) launch_utx<T>(c->st, V, p, g.n, c->mp, L, nullptr, K.part, nullptr, K.cm);
+  launch_rowmm_multi<T>(c->st, V, K.cm, K.q2, nullptr, nullptr, g.n, c->mp, L, 3, out);
+}
+
+// L independent preconditioned CG solves A x_l = rhs_l (A = W + Sigma_dagger^{-1}
+// with the VIFDU preconditioner, or with fitc A = W^{-1} + Sigma_dagger and the
+// FITC one), from x = 0, each to its own rule ||r_l|| <= cg_tol ||rhs_l||, with
 // every operator pass made once for the block. Per column: alpha_j, beta_j
 // logged at alog / blog (column l at l * ld), the iteration count, rz0 =
 // rhs^T P^{-1} rhs, and q0 = P^{-1} rhs. All scalars stay on the device; the
 // host reads the number of unfinished columns every fourth iteration.
 template <typename T>
 static vif_status pcg_block(vif_ctx* c, LapBufs& B, BlkBufs& K, const double* rhs, int L, double* x, double* q0,
-                            double* alog, double* blog, int ld, double* rz0, int* iters) {
+                            double* alog, double* blog, int ld, double* rz0, int* iters, bool fitc = false) {
   const vif_config& g = c->cfg;
   const int64_t n = g.n;
   const size_t bytes = sizeof(double) * n * L;
   HIPCHK(c, hipMemsetAsync(x, 0, bytes, c->st));
   HIPCHK(c, hipMemsetAsync(K.bad, 0, sizeof(int), c->st));
   HIPCHK(c, hipMemcpyAsync(K.r, rhs, bytes, hipMemcpyDeviceToDevice, c->st));
-  blk_vifdu_apply<T>(c, K, B, K.r, L, K.z);
+  if (fitc)
+    blk_fitc_apply<T>(c, K, B, K.r, L, K.z);
+  else
+    blk_vifdu_apply<T>(c, K, B, K.r, L, K.z);
   if (q0) HIPCHK(c, hipMemcpyAsync(q0, K.z, bytes, hipMemcpyDeviceToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(K.p, K.z, bytes, hipMemcpyDeviceToDevice, c->st));
   launch_coldot_multi(c->st, K.r, K.z, K.r, K.r, n, L, K.part, K.dots);
@@ -1868,10 +1899,16 @@ static vif_status pcg_block(vif_ctx* c, LapBufs& B, BlkBufs& K, const double* rh
   HIPCHK(c, hipStreamSynchronize(c->st));
   int it = 0;
   for (it = 1; it <= g.cg_maxit && nact > 0; ++it) {
-    blk_prec_matvec<T>(c, K, K.p, L, B.W, K.ap);
+    if (fitc)
+      blk_sigma_matvec<T>(c, K, K.p, L, B.W, K.ap);
+    else
+      blk_prec_matvec<T>(c, K, K.p, L, B.W, K.ap);
     launch_coldot_multi(c->st, K.p, K.ap, nullptr, nullptr, n, L, K.part, K.cs + L);  // pAp
     launch_cg_step_multi(c->st, x, K.r, K.p, K.ap, K.cs, n, L);
-    blk_vifdu_apply<T>(c, K, B, K.r, L, K.z);
+    if (fitc)
+      blk_fitc_apply<T>(c, K, B, K.r, L, K.z);
+    else
+      blk_vifdu_apply<T>(c, K, B, K.r, L, K.z);
     launch_coldot_multi(c->st, K.r, K.z, K.r, K.r, n, L, K.part, K.dots);
     launch_cg_beta_multi(c->st, K.cs, K.dots, it, L, ld, alog, blog, K.beta, K.nact);
     launch_cg_dir_multi(c->st, K.p, K.z, K.beta, n, L);
@@ -1934,22 +1971,25 @@ static vif_status laplace_nll_impl(vif_ctx* c, const double* y, const double* mo
     if ((s = read_scalars(c, 13))) return s;
     const double loglik = c->hlsc[9], bsb = c->hlsc[7], lwdv = c->hlsc[10];
     const double ldMV = g.m > 0 ? c->hlsc[12] : 0.0;
-    std::vector<int> its(ell);
-    std::vector<double> rz(ell);
     const T* V = form_V<T>(c);
-    for (int k = 0; k < ell; ++k) {
-      const double* e1 = eps_n + (size_t)(2 * k) * n;
-      launch_div(c->st, e1, B.sw, n, B.t);  // D_V^{1/2} e1 (B.sw = D_V^{-1/2})
-      if (g.m > 0)
-        launch_add_ve<T>(c->st, V, eps_m + (size_t)k * g.m, B.t, n, mp, g.m, B.rhs);
-      else
-        HIPCHK(c, hipMemcpyAsync(B.rhs, B.t, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
-      s = pcg_plain<T>(c, B, B.rhs, c->slq_u + (size_t)k * n, c->slq_a + (size_t)k * c->slq_ld,
-                       c->slq_b + (size_t)k * c->slq_ld, c->slq_q + (size_t)k * n, &its[k], &rz[k], true);
+    BlkBufs K = blk_bufs(c);
+    for (int k0 = 0; k0 < ell; k0 += K.cap) {
+      const int L = std::min(K.cap, ell - k0);
+      // z_k = D_V^{1/2} e1_k + V^T e3_k (B.sw = D_V^{-1/2}), the block's probes
+      launch_cols_to_block(c->st, eps_n, 2 * n, 0, k0, n, L, K.e1);
+      launch_add_rows_div_multi(c->st, nullptr, K.e1, B.sw, n, L, K.t);
+      if (g.m > 0) {
+        launch_eps_m_block(c->st, eps_m, g.m, mp, k0, L, K.cm3);
+        launch_rowmm_multi<T>(c->st, V, K.cm3, K.t, nullptr, nullptr, n, mp, L, 3, K.rhs);
+      } else {
+        HIPCHK(c, hipMemcpyAsync(K.rhs, K.t, sizeof(double) * n * L, hipMemcpyDeviceToDevice, c->st));
+      }
+      s = pcg_block<T>(c, B, K, K.rhs, L, K.u, K.e1, c->slq_a + (size_t)k0 * c->slq_ld,
+                       c->slq_b + (size_t)k0 * c->slq_ld, c->slq_ld, c->slq_rz + k0, c->slq_iters + k0, true);
       if (s) return s;
+      launch_block_to_cols(c->st, K.u, n, L, k0, c->slq_u);  // u_k = A^{-1} z_k
+      launch_block_to_cols(c->st, K.e1, n, L, k0, c->slq_q);  // q_k = P^{-1} z_k
     }
-    HIPCHK(c, hipMemcpyAsync(c->slq_iters, its.data(), sizeof(int) * ell, hipMemcpyHostToDevice, c->st));
-    HIPCHK(c, hipMemcpyAsync(c->slq_rz, rz.data(), sizeof(double) * ell, hipMemcpyHostToDevice, c->st));
     launch_slq_terms(c->st, c->slq_a, c->slq_b, c->slq_iters, c->slq_rz, ell, c->slq_ld, c->slq_work, c->slq_terms);
     std::vector<double> terms(ell);
     HIPCHK(c, hipMemcpyAsync(terms.data(), c->slq_terms, sizeof(double) * ell, hipMemcpyDeviceToHost, c->st));

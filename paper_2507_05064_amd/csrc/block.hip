@@ -71,6 +71,15 @@ __global__ void k_add_sqrtw_multi(double* __restrict__ s, const double* __restri
   if (e >= n * L) return;
   s[e] += sqrt(W[e / L]) * e1[e];
 }
+// out[i][l] = (acc ? acc[i][l] : 0) + x[i][l] / w_i  (out may be acc)
+__global__ void k_add_rows_div_multi(const double* acc, const double* __restrict__ x, const double* __restrict__ w,
+                                     int64_t n, int L, double* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * L) return;
+  const double v = x[e] / w[e / L];
+  out[e] = acc ? acc[e] + v : v;
+}
+
 // q = E v, qd = q / sqrt(D)
 __global__ void k_scale_e_multi(const double* __restrict__ v, const double* __restrict__ E, const double* __restrict__ D,
                                 int64_t n, int L, double* __restrict__ q, double* __restrict__ qd) {
@@ -325,6 +334,7 @@ __global__ void k_sym_apply_multi(const double* __restrict__ Minv, const double*
 //   1: out = t + E (U C) D^{-1/2}
 //   2: out = U C
 //   3: out = t + U C
+//   4: out = E (t - U C)
 template <typename T>
 __global__ __launch_bounds__(256) void k_rowmm_multi(const T* __restrict__ U, const double* __restrict__ C,
                                                      const double* __restrict__ t, const double* __restrict__ E,
@@ -375,8 +385,10 @@ __global__ __launch_bounds__(256) void k_rowmm_multi(const T* __restrict__ U, co
           o = t[e] + E[i] * uc / sqrt(D[i]);
         else if (mode == 2)
           o = uc;
-        else
+        else if (mode == 3)
           o = t[e] + uc;
+        else
+          o = E[i] * (t[e] - uc);
         out[e] = o;
       }
     }
@@ -553,6 +565,10 @@ void launch_eps_m_block(hipStream_t st, const double* eps, int m, int mp, int k0
 }
 void launch_sqrtd_multi(hipStream_t st, const double* D, const double* x, int64_t n, int L, double* out) {
   hipLaunchKernelGGL(k_sqrtd_multi, gE(n * L), dim3(256), 0, st, D, x, n, L, out);
+}
+void launch_add_rows_div_multi(hipStream_t st, const double* acc, const double* x, const double* w, int64_t n, int L,
+                               double* out) {
+  hipLaunchKernelGGL(k_add_rows_div_multi, gE(n * L), dim3(256), 0, st, acc, x, w, n, L, out);
 }
 void launch_add_sqrtw_multi(hipStream_t st, double* s, const double* W, const double* e1, int64_t n, int L) {
   hipLaunchKernelGGL(k_add_sqrtw_multi, gE(n * L), dim3(256), 0, st, s, W, e1, n, L);

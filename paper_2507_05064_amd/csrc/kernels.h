@@ -301,6 +301,8 @@ void launch_block_to_cols(hipStream_t st, const double* blk, int64_t n, int L, i
 void launch_eps_m_block(hipStream_t st, const double* eps, int m, int mp, int k0, int L, double* out);
 void launch_sqrtd_multi(hipStream_t st, const double* D, const double* x, int64_t n, int L, double* out);
 void launch_add_sqrtw_multi(hipStream_t st, double* s, const double* W, const double* e1, int64_t n, int L);
+void launch_add_rows_div_multi(hipStream_t st, const double* acc, const double* x, const double* w, int64_t n, int L,
+                               double* out);
 void launch_scale_e_multi(hipStream_t st, const double* v, const double* E, const double* D, int64_t n, int L,
                           double* q, double* qd);
 template <typename T>
@@ -323,7 +325,7 @@ int utx_chunks(int64_t n);
 template <typename T>
 void launch_utx(hipStream_t st, const T* U, const double* x, int64_t n, int mp, int L, const double* Minv,
                 double* part, double* sum, double* out);
-// modes: 0 (t - U C) D^{-1/2} (D may be null), 1 t + E (U C) D^{-1/2}, 2 U C, 3 t + U C
+// modes: 0 (t - U C) D^{-1/2} (D may be null), 1 t + E (U C) D^{-1/2}, 2 U C, 3 t + U C, 4 E (t - U C)
 template <typename T>
 void launch_rowmm_multi(hipStream_t st, const T* U, const double* C, const double* t, const double* E,
                         const double* D, int64_t n, int mp, int L, int mode, double* out);
