@@ -49,6 +49,7 @@ struct vif_ctx {
   std::string err;
   CovParams cp{};
   int chunk = 2048, nchunk = 1;
+  int uchunk = 64, unchunk = 1;  // point chunks of the U^T v passes
   // device workspace
   double *Sm = nullptr, *Linv = nullptr, *Mp = nullptr, *LMinv = nullptr, *Mwork = nullptr;
   double* Vd = nullptr;  // n x mp, FP64 (factor storage in the FP64 form, and the neighbour search)
@@ -364,6 +365,10 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
   c->chunk = 256;
   while (ceil_div(n, c->chunk) > 512) c->chunk *= 2;
   c->nchunk = (int)ceil_div(n, c->chunk);
+  // the U^T v passes: about 1024 chunks (four workgroups per CU, a multiple
+  // of eight points, 64 at least)
+  c->uchunk = (int)std::max<int64_t>(64, (ceil_div(n, 1024) + 7) / 8 * 8);
+  c->unchunk = (int)ceil_div(n, c->uchunk);
   hipError_t e = hipSuccess;
   auto alloc = [&](void** p, size_t bytes) {
     if (e == hipSuccess) e = hipMalloc(p, bytes > 0 ? bytes : 16);
@@ -454,7 +459,7 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
     alloc((void**)&c->M3inv, sizeof(double) * mpa * mpa);
     alloc((void**)&c->L3inv, sizeof(double) * mpa * mpa);
     alloc((void**)&c->lsc, sizeof(double) * 64);
-    alloc((void**)&c->lpart, sizeof(double) * (3 * ceil_div(n, 256) + ceil_div(n, 2048) * 2 + (size_t)c->nchunk * mpa + 64));
+    alloc((void**)&c->lpart, sizeof(double) * (3 * ceil_div(n, 256) + ceil_div(n, 2048) * 2 + (size_t)(c->unchunk + kColSplit) * mpa + 64));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->hlsc, sizeof(double) * 64, 0);
   }
   for (int t = 0; t < ST_COUNT && e == hipSuccess; ++t) {
@@ -1233,8 +1238,8 @@ static void prec_matvec(vif_ctx* c, LapBufs& B, const double* w, const double* W
   const T* U = (const T*)c->U;
   launch_bw<T>(c->st, (const T*)c->A, c->D, c->nbr, w, g.n, g.m_v, B.t);
   if (g.m > 0) {
-    launch_utv<T>(c->st, U, B.t, nullptr, g.n, c->mp, c->chunk, B.upart);
-    launch_reduce_apply(c->st, B.upart, c->nchunk, c->mp, c->Minv, B.cbuf, B.cp);
+    launch_utv<T>(c->st, U, B.t, nullptr, g.n, c->mp, c->uchunk, B.upart);
+    launch_reduce_apply(c->st, B.upart, c->unchunk, c->mp, c->Minv, B.cbuf, B.cp);
   }
   launch_t_minus_uc<T>(c->st, U, B.cp, B.t, c->D, g.n, c->mp, B.s);
   launch_btw<T>(c->st, (const T*)c->A, c->rev_ptr, c->rev_idx, B.s, W, w, g.n, g.m_v, out);
@@ -1248,8 +1253,8 @@ static void vifdu_apply(vif_ctx* c, LapBufs& B, const double* r, double* z) {
   launch_trsv_bwd<T>(c->st, c->sb, (const T*)c->bcoef, r, B.xq, B.zq, B.v);
   launch_scale_e(c->st, B.v, B.E, c->D, g.n, B.q, B.qd);
   if (g.m > 0) {
-    launch_utv<T>(c->st, U, B.qd, nullptr, g.n, c->mp, c->chunk, B.upart);
-    launch_reduce_apply(c->st, B.upart, c->nchunk, c->mp, c->M3inv, B.cbuf, B.cp);
+    launch_utv<T>(c->st, U, B.qd, nullptr, g.n, c->mp, c->uchunk, B.upart);
+    launch_reduce_apply(c->st, B.upart, c->unchunk, c->mp, c->M3inv, B.cbuf, B.cp);
   }
   launch_q_plus_euc<T>(c->st, U, B.cp, B.q, B.E, c->D, g.n, c->mp, B.q2);
   launch_trsv_fwd<T>(c->st, c->sf, (const T*)c->fcoef, B.q2, B.xq, B.zq, z);
@@ -1335,8 +1340,8 @@ static void fitc_apply(vif_ctx* c, LapBufs& B, const double* r, double* z) {
   const vif_config& g = c->cfg;
   const T* V = form_V<T>(c);
   if (g.m > 0) {
-    launch_utv<T>(c->st, V, r, B.E, g.n, c->mp, c->chunk, B.upart);
-    launch_reduce_apply(c->st, B.upart, c->nchunk, c->mp, c->M3inv, B.cbuf, B.cp);
+    launch_utv<T>(c->st, V, r, B.E, g.n, c->mp, c->uchunk, B.upart);
+    launch_reduce_apply(c->st, B.upart, c->unchunk, c->mp, c->M3inv, B.cbuf, B.cp);
   }
   launch_fitc_post<T>(c->st, V, B.cp, r, B.E, g.n, c->mp, z);
 }
@@ -1351,8 +1356,8 @@ static void sigma_matvec(vif_ctx* c, LapBufs& B, const double* w, const double* 
   launch_mul(c->st, B.v, c->D, g.n, B.q);
   launch_trsv_fwd<T>(c->st, c->sf, (const T*)c->fcoef, B.q, B.xq, B.zq, B.q2);
   if (g.m > 0) {
-    launch_utv<T>(c->st, V, w, nullptr, g.n, c->mp, c->chunk, B.upart);
-    launch_colreduce(c->st, B.upart, c->nchunk, c->mp, B.ctmp);
+    launch_utv<T>(c->st, V, w, nullptr, g.n, c->mp, c->uchunk, B.upart);
+    launch_colreduce(c->st, B.upart, c->unchunk, c->mp, B.ctmp);
   }
   launch_fitc_out<T>(c->st, V, B.ctmp, B.q2, w, W, g.n, c->mp, out);
 }
@@ -1650,10 +1655,10 @@ vif_status vif_mlp_features(vif_ctx* c, const double* y, float* feat_out) {
     launch_gemm_sq(c->st, c->L3inv, c->L3inv, c->M3inv, mp, true, false);
     launch_shift(c->st, y, p0, g.n, B.tmp);
     if (f32)
-      launch_utv<float>(c->st, c->Vf, B.tmp, nullptr, g.n, mp, c->chunk, B.upart);
+      launch_utv<float>(c->st, c->Vf, B.tmp, nullptr, g.n, mp, c->uchunk, B.upart);
     else
-      launch_utv<double>(c->st, c->Vd, B.tmp, nullptr, g.n, mp, c->chunk, B.upart);
-    launch_reduce_apply(c->st, B.upart, c->nchunk, mp, c->M3inv, B.cbuf, B.cp);
+      launch_utv<double>(c->st, c->Vd, B.tmp, nullptr, g.n, mp, c->uchunk, B.upart);
+    launch_reduce_apply(c->st, B.upart, c->unchunk, mp, c->M3inv, B.cbuf, B.cp);
     HIPCHK(c, hipMemsetAsync(B.q, 0, sizeof(double) * g.n, c->st));
     if (f32)
       launch_add_ve<float>(c->st, c->Vf, B.cp, B.q, g.n, mp, g.m, B.q2);
@@ -2163,8 +2168,8 @@ static void vec_prep(vif_ctx* c, LapBufs& B, const double* x, VecPrep v) {
   const T* U = (const T*)c->U;
   launch_bw<T>(c->st, (const T*)c->A, c->D, c->nbr, x, g.n, g.m_v, v.t);
   if (g.m > 0) {
-    launch_utv<T>(c->st, U, v.t, nullptr, g.n, c->mp, c->chunk, B.upart);
-    launch_reduce_apply(c->st, B.upart, c->nchunk, c->mp, c->Minv, B.cbuf, v.a);
+    launch_utv<T>(c->st, U, v.t, nullptr, g.n, c->mp, c->uchunk, B.upart);
+    launch_reduce_apply(c->st, B.upart, c->unchunk, c->mp, c->Minv, B.cbuf, v.a);
   }
   launch_t_minus_uc<T>(c->st, U, v.a, v.t, nullptr, g.n, c->mp, v.s);
 }
@@ -2556,11 +2561,11 @@ static vif_status pred_mean_apply(vif_ctx* c, LapBufs& B, const double* y, const
   double *yt = B.t, *e = B.s, *r = B.tmp, *w = B.cp, *c1 = B.ctmp;
   launch_ytilde<T>(c->st, (const T*)c->A, c->D, c->nbr, y, n, mv, yt);
   if (g.m > 0) {
-    launch_utv<T>(c->st, U, yt, nullptr, n, mp, c->chunk, B.upart);
-    launch_reduce_apply(c->st, B.upart, c->nchunk, mp, c->Minv, B.cbuf, w);
+    launch_utv<T>(c->st, U, yt, nullptr, n, mp, c->uchunk, B.upart);
+    launch_reduce_apply(c->st, B.upart, c->unchunk, mp, c->Minv, B.cbuf, w);
     launch_t_minus_uc<T>(c->st, U, w, yt, nullptr, n, mp, e);
-    launch_utv<T>(c->st, U, e, nullptr, n, mp, c->chunk, B.upart);
-    launch_colreduce(c->st, B.upart, c->nchunk, mp, c1);
+    launch_utv<T>(c->st, U, e, nullptr, n, mp, c->uchunk, B.upart);
+    launch_colreduce(c->st, B.upart, c->unchunk, mp, c1);
     launch_rowvec<T>(c->st, V, w, n, mp, r);
     hipLaunchKernelGGL(k_sub, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->st, r, y, r, n);
   } else {

@@ -116,8 +116,11 @@ void launch_bw(hipStream_t st, const T* A, const double* D, const int32_t* nbr, 
 template <typename T>
 void launch_utv(hipStream_t st, const T* U, const double* v, const double* scale, int64_t n, int mp, int chunk,
                 double* partial);
-void launch_colreduce(hipStream_t st, const double* partial, int nchunk, int mp, double* out);
-void launch_reduce_apply(hipStream_t st, const double* partial, int nchunk, int mp, const double* Minv, double* cbuf,
+// column sums of nchunk x mp chunk partials; partial must hold (nchunk +
+// kColSplit) x mp doubles, the rows past nchunk being the second stage's scratch
+constexpr int kColSplit = 16;
+void launch_colreduce(hipStream_t st, double* partial, int nchunk, int mp, double* out);
+void launch_reduce_apply(hipStream_t st, double* partial, int nchunk, int mp, const double* Minv, double* cbuf,
                          double* out);
 template <typename T>
 void launch_t_minus_uc(hipStream_t st, const T* U, const double* c, const double* t, const double* D, int64_t n,

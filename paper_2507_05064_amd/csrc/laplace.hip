@@ -168,19 +168,31 @@ __global__ __launch_bounds__(256) void k_utv(const T* __restrict__ U, const doub
     partial[(size_t)blockIdx.x * mp + l] = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
 }
 
-// cbuf[l] = sum_chunks partial[chunk][l]: 64 columns per workgroup, the 4
-// waves take every 4th chunk, fixed-order combination
-__global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ partial, int nchunk, int mp,
-                                                   double* __restrict__ cbuf) {
+// Column sums of the chunk partials in two fixed-order stages:
+// part2[s][l] = sum of partial[c][l] over the chunks c of split s (a
+// contiguous range; 64 columns per workgroup, the 4 waves take every 4th
+// chunk of it), then out[l] = sum over s of part2[s][l].
+__global__ __launch_bounds__(256) void k_colreduce_split(const double* __restrict__ partial, int nchunk, int mp,
+                                                         double* __restrict__ part2) {
   __shared__ double red[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int l = blockIdx.x * 64 + lane;
+  const int per = (nchunk + kColSplit - 1) / kColSplit;
+  const int c0 = blockIdx.y * per, c1 = min(nchunk, c0 + per);
   double s = 0.0;
   if (l < mp)
-    for (int c = w; c < nchunk; c += 4) s += partial[(size_t)c * mp + l];
+    for (int c = c0 + w; c < c1; c += 4) s += partial[(size_t)c * mp + l];
   red[w][lane] = s;
   __syncthreads();
-  if (w == 0 && l < mp) cbuf[l] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+  if (w == 0 && l < mp) part2[(size_t)blockIdx.y * mp + l] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+__global__ void k_colreduce_final(const double* __restrict__ part2, int mp, double* __restrict__ out) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= mp) return;
+  double s = 0.0;
+  for (int k = 0; k < kColSplit; ++k) s += part2[(size_t)k * mp + l];
+  out[l] = s;
 }
 
 // out = Minv cbuf (Minv full mp x mp): one wave per row
@@ -601,12 +613,15 @@ void launch_utv(hipStream_t st, const T* U, const double* v, const double* scale
   hipLaunchKernelGGL((k_utv<T>), dim3((unsigned)ceil_div(n, chunk)), dim3(256), 0, st, U, v, scale, n, mp, chunk,
                      partial);
 }
-void launch_colreduce(hipStream_t st, const double* partial, int nchunk, int mp, double* out) {
-  hipLaunchKernelGGL(k_colreduce, dim3((unsigned)ceil_div(mp, 64)), dim3(256), 0, st, partial, nchunk, mp, out);
+void launch_colreduce(hipStream_t st, double* partial, int nchunk, int mp, double* out) {
+  double* part2 = partial + (size_t)nchunk * mp;
+  hipLaunchKernelGGL(k_colreduce_split, dim3((unsigned)ceil_div(mp, 64), kColSplit), dim3(256), 0, st, partial, nchunk,
+                     mp, part2);
+  hipLaunchKernelGGL(k_colreduce_final, dim3((unsigned)ceil_div(mp, 256)), dim3(256), 0, st, part2, mp, out);
 }
-void launch_reduce_apply(hipStream_t st, const double* partial, int nchunk, int mp, const double* Minv, double* cbuf,
+void launch_reduce_apply(hipStream_t st, double* partial, int nchunk, int mp, const double* Minv, double* cbuf,
                          double* out) {
-  hipLaunchKernelGGL(k_colreduce, dim3((unsigned)ceil_div(mp, 64)), dim3(256), 0, st, partial, nchunk, mp, cbuf);
+  launch_colreduce(st, partial, nchunk, mp, cbuf);
   hipLaunchKernelGGL(k_symv, dim3((unsigned)ceil_div(mp, 4)), dim3(256), 0, st, Minv, cbuf, mp, out);
 }
 template <typename T>
