@@ -92,68 +92,74 @@ __global__ void k_scale_e_multi(const double* __restrict__ v, const double* __re
 }
 
 // ------------------------------------------------------------ B and B^T
-// One wave per row (the row index uniform, so its slots load through the
-// scalar cache), lanes over the right-hand sides; the slots are taken eight
-// at a time with the eight gathers in flight, in slot order. An empty slot
-// gathers row 0 with its value replaced by 0.
-// out[i][l] = (x[i][l] - sum_a A_ia x[N(i)_a][l]) * (D ? D_i^{-1/2} : 1)
+// One wave per row. Its lanes are (entry group g, column l): Lp = 2^lsh >= L
+// columns and G = 64 / Lp groups, group g taking the row's entries g, g + G,
+// ... eight at a time with the eight gathers in flight, so that a row's
+// entries are spread over the whole wave whatever the number of right-hand
+// sides. The groups' sums are then added by a fixed xor tree (the same
+// order on every call). Lanes with l >= L read a valid column and write
+// nothing; an empty slot gathers row 0 with its weight 0 and its value
+// replaced by 0.
+__device__ __forceinline__ double group_sum(double s, int lsh) {
+  for (int o = 32; o >= (1 << lsh); o >>= 1) s += __shfl_xor(s, o);
+  return s;
+}
+
+// sum over the m_v slots a of row `row` of w[a] x[idx[a]][ll] (slots with a
+// negative index count 0); this lane's share: slots g, g + G, ...
 template <typename T>
-__global__ __launch_bounds__(256) void k_bw_multi(const T* __restrict__ A, const double* __restrict__ D,
-                                                  const int32_t* __restrict__ nbr, const double* __restrict__ x,
-                                                  int64_t n, int mv, int L, double* __restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  const int64_t i = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-  if (i >= n) return;
-  const int ll = min(lane, L - 1);  // lanes past L read a valid column, write nothing
-  double s = x[i * L + ll];
-  for (int a0 = 0; a0 < mv; a0 += 8) {
+__device__ __forceinline__ double slot_gather(const int32_t* __restrict__ idx, const T* __restrict__ w, int mv,
+                                              const double* __restrict__ x, int L, int ll, int g, int G) {
+  double s = 0.0;
+  for (int a0 = g; a0 < mv; a0 += 8 * G) {
     int c[8];
     bool ok[8];
-    double w[8], z[8];
+    double wv[8], z[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int a = min(a0 + k, mv - 1);
-      const int j = nbr[i * mv + a];
-      ok[k] = a0 + k < mv && j >= 0;
+      const int a = a0 + k * G;
+      const int j = idx[min(a, mv - 1)];
+      ok[k] = a < mv && j >= 0;
       c[k] = ok[k] ? j : 0;
-      w[k] = ok[k] ? (double)A[i * mv + a] : 0.0;
+      wv[k] = ok[k] ? (double)w[min(a, mv - 1)] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) z[k] = x[(int64_t)c[k] * L + ll];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) s -= w[k] * (ok[k] ? z[k] : 0.0);
+    for (int k = 0; k < 8; ++k) s = fma(wv[k], ok[k] ? z[k] : 0.0, s);
   }
-  if (lane < L) out[i * L + lane] = D ? s / sqrt(D[i]) : s;
+  return s;
+}
+
+// out[i][l] = (x[i][l] - sum_a A_ia x[N(i)_a][l]) * (D ? D_i^{-1/2} : 1)
+template <typename T>
+__global__ __launch_bounds__(256) void k_bw_multi(const T* __restrict__ A, const double* __restrict__ D,
+                                                  const int32_t* __restrict__ nbr, const double* __restrict__ x,
+                                                  int64_t n, int mv, int L, int lsh, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1), ll = min(l, L - 1);
+  double v = slot_gather<T>(nbr + i * mv, A + i * mv, mv, x, L, ll, g, 64 >> lsh);
+  v = group_sum(v, lsh);
+  if (g == 0 && l < L) {
+    const double s = x[i * L + l] - v;
+    out[i * L + l] = D ? s / sqrt(D[i]) : s;
+  }
 }
 
 // out[i][l] = -sum_a dA_ia x[N(i)_a][l]   (dB x, dB_{i,N(i)} = -dA_i)
 template <typename T>
 __global__ __launch_bounds__(256) void k_dbx_multi(const T* __restrict__ dA, const int32_t* __restrict__ nbr,
-                                                   const double* __restrict__ x, int64_t n, int mv, int L,
+                                                   const double* __restrict__ x, int64_t n, int mv, int L, int lsh,
                                                    double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n) return;
-  const int ll = min(lane, L - 1);
-  double s = 0.0;
-  for (int a0 = 0; a0 < mv; a0 += 8) {
-    int c[8];
-    bool ok[8];
-    double w[8], z[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int a = min(a0 + k, mv - 1);
-      const int j = nbr[i * mv + a];
-      ok[k] = a0 + k < mv && j >= 0;
-      c[k] = ok[k] ? j : 0;
-      w[k] = ok[k] ? (double)dA[i * mv + a] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) z[k] = x[(int64_t)c[k] * L + ll];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) s -= w[k] * (ok[k] ? z[k] : 0.0);
-  }
-  if (lane < L) out[i * L + lane] = s;
+  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1), ll = min(l, L - 1);
+  double v = slot_gather<T>(nbr + i * mv, dA + i * mv, mv, x, L, ll, g, 64 >> lsh);
+  v = group_sum(v, lsh);
+  if (g == 0 && l < L) out[i * L + l] = -v;
 }
 
 // out[j][l] = s[j][l] - sum_{(q, slot): N(q)_slot = j} A_{q,slot} s[q][l] + (W ? W_j p[j][l] : 0)
@@ -161,94 +167,79 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_btw_multi(const T* __restrict__ A, const int* __restrict__ rev_ptr,
                                                    const int* __restrict__ rev_idx, const double* __restrict__ s,
                                                    const double* __restrict__ W, const double* __restrict__ p,
-                                                   int64_t n, int mv, int L, double* __restrict__ out) {
+                                                   int64_t n, int mv, int L, int lsh, double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  const int64_t j = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= n) return;
-  const int ll = min(lane, L - 1);
+  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1), ll = min(l, L - 1), G = 64 >> lsh;
   double v = 0.0;
   const int q0 = rev_ptr[j], q1 = rev_ptr[j + 1];
-  for (int a0 = q0; a0 < q1; a0 += 8) {
+  for (int a0 = q0 + g; a0 < q1; a0 += 8 * G) {
     int c[8];
     double w[8], z[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int idx = rev_idx[min(a0 + k, q1 - 1)];
+      const int a = a0 + k * G;
+      const int idx = rev_idx[min(a, q1 - 1)];
       c[k] = idx / mv;
-      w[k] = a0 + k < q1 ? (double)A[idx] : 0.0;
+      w[k] = a < q1 ? (double)A[idx] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) z[k] = s[(int64_t)c[k] * L + ll];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v += w[k] * z[k];
+    for (int k = 0; k < 8; ++k) v = fma(w[k], z[k], v);
   }
-  if (lane < L) out[j * L + lane] = s[j * L + lane] - v + (W ? W[j] * p[j * L + lane] : 0.0);
+  v = group_sum(v, lsh);
+  if (g == 0 && l < L) out[j * L + l] = s[j * L + l] - v + (W ? W[j] * p[j * L + l] : 0.0);
 }
 
 // one level of B^{-1} (positions [beg, end), row q: m_v slots of positions
-// and coefficients): zq[q][l] = xq[q][l] + sum_a coef_qa zq[col_qa][l]. One
-// wave per row (the row index uniform, so its slots load through the scalar
-// cache), lanes over the right-hand sides; the slots are taken eight at a
-// time with all eight gathers in flight. An empty slot gathers position 0 (a
-// valid address, not yet solved in the first level) and its value is
-// replaced by 0 before use.
+// and coefficients): zq[q][l] = xq[q][l] + sum_a coef_qa zq[col_qa][l]. An
+// empty slot gathers position 0 (a valid address, not yet solved in the
+// first level) with its value replaced by 0.
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsv_fwd_level_multi(int beg, int end, const int* __restrict__ col,
                                                               const T* __restrict__ coef,
-                                                              const double* __restrict__ xq, int mv, int L,
+                                                              const double* __restrict__ xq, int mv, int L, int lsh,
                                                               double* zq) {
   const int lane = threadIdx.x & 63;
-  const int q = __builtin_amdgcn_readfirstlane(beg + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  const int q = beg + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
   if (q >= end) return;
-  const int ll = min(lane, L - 1);  // lanes past L read a valid column, write nothing
-  double s = xq[(int64_t)q * L + ll];
-  for (int a0 = 0; a0 < mv; a0 += 8) {
-    int c[8];
-    bool ok[8];
-    double w[8], z[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int a = min(a0 + k, mv - 1);
-      const int cq = col[(size_t)q * mv + a];
-      ok[k] = a0 + k < mv && cq >= 0;
-      c[k] = ok[k] ? cq : 0;
-      w[k] = ok[k] ? (double)coef[(size_t)q * mv + a] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) z[k] = zq[(int64_t)c[k] * L + ll];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) s = fma(w[k], ok[k] ? z[k] : 0.0, s);
-  }
-  if (lane < L) zq[(int64_t)q * L + lane] = s;
+  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1), ll = min(l, L - 1);
+  double v = slot_gather<T>(col + (size_t)q * mv, coef + (size_t)q * mv, mv, zq, L, ll, g, 64 >> lsh);
+  v = group_sum(v, lsh);
+  if (g == 0 && l < L) zq[(int64_t)q * L + l] = xq[(int64_t)q * L + l] + v;
 }
 
-// one level of B^{-T} (CSR rows by position), eight entries at a time as
-// above; the entries past a row's end repeat its last entry with weight 0
+// one level of B^{-T} (CSR rows by position); the entries past a row's end
+// repeat its last entry with weight 0
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsv_bwd_level_multi(int beg, int end, const int* __restrict__ ptr,
                                                               const int* __restrict__ col, const T* __restrict__ coef,
-                                                              const double* __restrict__ xq, int L, double* zq) {
+                                                              const double* __restrict__ xq, int L, int lsh,
+                                                              double* zq) {
   const int lane = threadIdx.x & 63;
-  const int q = __builtin_amdgcn_readfirstlane(beg + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  const int q = beg + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
   if (q >= end) return;
-  const int ll = min(lane, L - 1);
-  double s = xq[(int64_t)q * L + ll];
+  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1), ll = min(l, L - 1), G = 64 >> lsh;
+  double v = 0.0;
   const int e0 = ptr[q], e1 = ptr[q + 1];
-  for (int a0 = e0; a0 < e1; a0 += 8) {
+  for (int a0 = e0 + g; a0 < e1; a0 += 8 * G) {
     int c[8];
     double w[8], z[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int a = min(a0 + k, e1 - 1);
-      c[k] = col[a];
-      w[k] = a0 + k < e1 ? (double)coef[a] : 0.0;
+      const int a = a0 + k * G;
+      c[k] = col[min(a, e1 - 1)];
+      w[k] = a < e1 ? (double)coef[min(a, e1 - 1)] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) z[k] = zq[(int64_t)c[k] * L + ll];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) s = fma(w[k], z[k], s);
+    for (int k = 0; k < 8; ++k) v = fma(w[k], z[k], v);
   }
-  if (lane < L) zq[(int64_t)q * L + lane] = s;
+  v = group_sum(v, lsh);
+  if (g == 0 && l < L) zq[(int64_t)q * L + l] = xq[(int64_t)q * L + l] + v;
 }
 
 // ------------------------------------------------------------ low-rank products
@@ -552,6 +543,12 @@ __global__ void k_colsum_final(const double* __restrict__ part, int nb, int L, d
 
 // ------------------------------------------------------------ launchers
 static inline dim3 gE(int64_t cnt) { return dim3((unsigned)ceil_div(cnt, 256)); }
+// log2 of the lanes per entry group of the gather kernels: the least power of two >= L (L <= 64)
+static inline int col_shift(int L) {
+  int sh = 0;
+  while ((1 << sh) < L) ++sh;
+  return sh;
+}
 
 void launch_cols_to_block(hipStream_t st, const double* src, int64_t stride, int64_t off, int k0, int64_t n, int L,
                           double* out) {
@@ -580,18 +577,20 @@ void launch_scale_e_multi(hipStream_t st, const double* v, const double* E, cons
 template <typename T>
 void launch_bw_multi(hipStream_t st, const T* A, const double* D, const int32_t* nbr, const double* x, int64_t n,
                      int mv, int L, double* out) {
-  hipLaunchKernelGGL((k_bw_multi<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, A, D, nbr, x, n, mv, L, out);
+  hipLaunchKernelGGL((k_bw_multi<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, A, D, nbr, x, n, mv, L,
+                     col_shift(L), out);
 }
 template <typename T>
 void launch_dbx_multi(hipStream_t st, const T* dA, const int32_t* nbr, const double* x, int64_t n, int mv, int L,
                       double* out) {
-  hipLaunchKernelGGL((k_dbx_multi<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, dA, nbr, x, n, mv, L, out);
+  hipLaunchKernelGGL((k_dbx_multi<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, dA, nbr, x, n, mv, L,
+                     col_shift(L), out);
 }
 template <typename T>
 void launch_btw_multi(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s,
                       const double* W, const double* p, int64_t n, int mv, int L, double* out) {
   hipLaunchKernelGGL((k_btw_multi<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, A, rev_ptr, rev_idx, s, W, p,
-                     n, mv, L, out);
+                     n, mv, L, col_shift(L), out);
 }
 template <typename T>
 void launch_trsv_fwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, int L, double* xq,
@@ -601,7 +600,7 @@ void launch_trsv_fwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, 
   for (int lv = 0; lv < s.nlev; ++lv) {
     const int beg = s.hlvl[lv], end = s.hlvl[lv + 1];
     hipLaunchKernelGGL((k_trsv_fwd_level_multi<T>), dim3((unsigned)ceil_div(end - beg, 4)), dim3(256), 0, st, beg, end,
-                       s.col, coef, xq, s.mv, L, zq);
+                       s.col, coef, xq, s.mv, L, col_shift(L), zq);
   }
   hipLaunchKernelGGL(k_perm_scatter_multi, gE(n * L), dim3(256), 0, st, s.order, zq, n, L, z);
 }
@@ -613,7 +612,7 @@ void launch_trsv_bwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, 
   for (int lv = 0; lv < s.nlev; ++lv) {
     const int beg = s.hlvl[lv], end = s.hlvl[lv + 1];
     hipLaunchKernelGGL((k_trsv_bwd_level_multi<T>), dim3((unsigned)ceil_div(end - beg, 4)), dim3(256), 0, st, beg, end,
-                       s.ptr, s.col, coef, xq, L, zq);
+                       s.ptr, s.col, coef, xq, L, col_shift(L), zq);
   }
   hipLaunchKernelGGL(k_perm_scatter_multi, gE(n * L), dim3(256), 0, st, s.order, zq, n, L, z);
 }
