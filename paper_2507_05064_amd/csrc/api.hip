@@ -1777,7 +1777,8 @@ static vif_status alloc_slq(vif_ctx* c, int ell) {
   const size_t npart = std::max((size_t)utx_chunks(n) * mpa, 2 * (size_t)ceil_div(n, 1024));
   alloc((void**)&c->blk, sizeof(double) * kBlkVecs * n * L);
   alloc((void**)&c->blk_mm, sizeof(double) * 4 * mpa * L);
-  alloc((void**)&c->blk_part, sizeof(double) * npart * L);
+  const size_t nsmall = (size_t)(utx_small_chunks(n, (int)mpa) + kColSplit) * mpa * std::min(L, 16);
+  alloc((void**)&c->blk_part, sizeof(double) * std::max(npart * L, nsmall));
   alloc((void**)&c->blk_cs, sizeof(double) * 11 * L);
   alloc((void**)&c->blk_int, sizeof(int) * 4);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? VIF_E_OOM : VIF_E_HIP;

@@ -300,6 +300,51 @@ __global__ __launch_bounds__(256) void k_utx_partial(const T* __restrict__ U, co
       }
 }
 
+// part[chunk][k][l] = sum_{i in chunk} U[i][k] x[i][l] for L <= 16 right-hand
+// sides without LDS: the f64 MFMA 16x16x4 with the chunk's points as the
+// contraction index, four points per step. Lane (r, j) loads U[i0 + j][k0 +
+// r] (16 consecutive k of four rows per wave load) into the A operand of each
+// of the wave's 16-row k tiles and x[i0 + j][r] (zero for r >= L or past the
+// chunk) into B. Wave w of workgroup (chunk, y) owns the eight k tiles from
+// k = 128 (4y + w).
+template <typename T>
+__global__ __launch_bounds__(256) void k_utx_small(const T* __restrict__ U, const double* __restrict__ x, int64_t n,
+                                                   int mp, int L, int64_t chunk, double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, j = lane >> 4;
+  const int kw = ((int)blockIdx.y * 4 + w) * 128;
+  if (kw >= mp) return;
+  const int nt = min(8, (mp - kw) / 16);
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk, pend = min(n, pbeg + chunk);
+  const bool cok = r < L;
+  const int cc = min(r, L - 1);
+  d4 acc[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc[t] = d4{0, 0, 0, 0};
+#pragma unroll 2
+  for (int64_t i0 = pbeg; i0 < pend; i0 += 4) {
+    const int64_t i = i0 + j;
+    const bool iok = i < pend;
+    const int64_t ii = iok ? i : pend - 1;
+    const double b = (iok && cok) ? x[ii * L + cc] : 0.0;
+    const T* urow = U + (size_t)ii * mp + kw + r;
+    double a[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) a[t] = t < nt ? (double)urow[16 * t] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (t < nt) acc[t] = mfma16(a[t], b, acc[t]);
+  }
+  double* out = part + (size_t)blockIdx.x * mp * L;
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = kw + 16 * t + acc_row<double>(lane, v);
+      if (t < nt && r < L) out[(size_t)k * L + r] = acc[t][v];
+    }
+}
+
 // out = Minv (sum over chunks of part), mp x L (Minv: mp x mp, symmetric)
 __global__ void k_utx_reduce(const double* __restrict__ part, int nchunk, int mp, int L, double* __restrict__ sum) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -326,6 +371,74 @@ __global__ void k_sym_apply_multi(const double* __restrict__ Minv, const double*
 //   2: out = U C
 //   3: out = t + U C
 //   4: out = E (t - U C)
+__device__ __forceinline__ double rowmm_combine(int mode, double uc, const double* __restrict__ t,
+                                                const double* __restrict__ E, const double* __restrict__ D, int64_t i,
+                                                int64_t e) {
+  if (mode == 0) return D ? (t[e] - uc) / sqrt(D[i]) : t[e] - uc;
+  if (mode == 1) return t[e] + E[i] * uc / sqrt(D[i]);
+  if (mode == 2) return uc;
+  if (mode == 3) return t[e] + uc;
+  return E[i] * (t[e] - uc);
+}
+
+// four consecutive entries of a U row as doubles (16-byte loads; the row
+// start and k are multiples of 16 and 4 entries)
+__device__ __forceinline__ void load4(const double* __restrict__ p, double a[4]) {
+  const d2 x = *reinterpret_cast<const d2*>(p), y = *reinterpret_cast<const d2*>(p + 2);
+  a[0] = x[0];
+  a[1] = x[1];
+  a[2] = y[0];
+  a[3] = y[1];
+}
+__device__ __forceinline__ void load4(const float* __restrict__ p, double a[4]) {
+  typedef float __attribute__((ext_vector_type(4))) f4v;
+  const f4v x = *reinterpret_cast<const f4v*>(p);
+  a[0] = x[0];
+  a[1] = x[1];
+  a[2] = x[2];
+  a[3] = x[3];
+}
+
+// The same products for L <= 16 right-hand sides without LDS: one wave per
+// 16 points and one 16-column tile. The contraction index k is taken four
+// consecutive entries per 16-lane group: lane (r, j) loads U[p0 + r][kb + 4j
+// .. kb + 4j + 3] straight into the A operands of four f64 MFMA 16x16x4 steps
+// (step s pairs slot j with k = kb + 4j + s), and the matching C[k][r] (C is
+// mp x L and stays in cache) into B; columns r >= L are zero. Rows past n
+// read row n - 1 and write nothing.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rowmm_small(const T* __restrict__ U, const double* __restrict__ C,
+                                                     const double* __restrict__ t, const double* __restrict__ E,
+                                                     const double* __restrict__ D, int64_t n, int mp, int L, int mode,
+                                                     double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (p0 >= n) return;
+  const int r = lane & 15, j = lane >> 4;
+  const T* urow = U + (size_t)min(p0 + r, n - 1) * mp;
+  const bool cok = r < L;
+  const double* ccol = C + min(r, L - 1);
+  d4 acc = d4{0, 0, 0, 0};
+#pragma unroll 4
+  for (int kb = 0; kb < mp; kb += 16) {
+    const int k = kb + 4 * j;
+    double a[4], b[4];
+    load4(urow + k, a);
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) b[s2] = cok ? ccol[(size_t)(k + s2) * L] : 0.0;
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) acc = mfma16(a[s2], b[s2], acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t i = p0 + acc_row<double>(lane, v);
+    if (i < n && r < L) {
+      const int64_t e = i * L + r;
+      out[e] = rowmm_combine(mode, acc[v], t, E, D, i, e);
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_rowmm_multi(const T* __restrict__ U, const double* __restrict__ C,
                                                      const double* __restrict__ t, const double* __restrict__ E,
@@ -367,20 +480,8 @@ __global__ __launch_bounds__(256) void k_rowmm_multi(const T* __restrict__ U, co
       const int64_t i = p0 + 16 * w + acc_row<double>(lane, v);
       const int l = 16 * u + r;
       if (u < nt && i < n && l < L) {
-        const double uc = acc[u][v];
         const int64_t e = i * L + l;
-        double o;
-        if (mode == 0)
-          o = D ? (t[e] - uc) / sqrt(D[i]) : t[e] - uc;
-        else if (mode == 1)
-          o = t[e] + E[i] * uc / sqrt(D[i]);
-        else if (mode == 2)
-          o = uc;
-        else if (mode == 3)
-          o = t[e] + uc;
-        else
-          o = E[i] * (t[e] - uc);
-        out[e] = o;
+        out[e] = rowmm_combine(mode, acc[u][v], t, E, D, i, e);
       }
     }
 }
@@ -617,9 +718,27 @@ void launch_trsv_bwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, 
   hipLaunchKernelGGL(k_perm_scatter_multi, gE(n * L), dim3(256), 0, st, s.order, zq, n, L, z);
 }
 int utx_chunks(int64_t n) { return (int)std::min<int64_t>(128, ceil_div(n, 32)); }
+// the small-L form: about 1024 workgroups (chunks x ceil(mp / 512)), chunks
+// a multiple of four points
+static int64_t utx_small_chunk(int64_t n, int mp) {
+  const int64_t target = std::max<int64_t>(1, 1024 / ceil_div(mp, 512));
+  return std::max<int64_t>(64, ceil_div(ceil_div(n, target), 4) * 4);
+}
+int utx_small_chunks(int64_t n, int mp) { return (int)ceil_div(n, utx_small_chunk(n, mp)); }
 template <typename T>
 void launch_utx(hipStream_t st, const T* U, const double* x, int64_t n, int mp, int L, const double* Minv,
                 double* part, double* sum, double* out) {
+  if (L <= 16 && mp > 0) {
+    const int64_t chunk = utx_small_chunk(n, mp);
+    const int nchunk = (int)ceil_div(n, chunk);
+    hipLaunchKernelGGL((k_utx_small<T>), dim3((unsigned)nchunk, (unsigned)ceil_div(mp, 512)), dim3(256), 0, st, U, x,
+                       n, mp, L, chunk, part);
+    launch_colreduce(st, part, nchunk, mp * L, Minv ? sum : out);
+    if (Minv)  // out = Minv sum, the same 16-point MFMA form (Minv as a U of mp rows)
+      hipLaunchKernelGGL((k_rowmm_small<double>), dim3((unsigned)ceil_div(mp, 64)), dim3(256), 0, st, Minv, sum,
+                         nullptr, nullptr, nullptr, (int64_t)mp, mp, L, 2, out);
+    return;
+  }
   const int nch = utx_chunks(n);
   const int64_t chunk = ceil_div(ceil_div(n, nch), 32) * 32;
   const int nchunk = (int)ceil_div(n, chunk);
@@ -631,8 +750,12 @@ void launch_utx(hipStream_t st, const T* U, const double* x, int64_t n, int mp, 
 template <typename T>
 void launch_rowmm_multi(hipStream_t st, const T* U, const double* C, const double* t, const double* E,
                         const double* D, int64_t n, int mp, int L, int mode, double* out) {
-  hipLaunchKernelGGL((k_rowmm_multi<T>), dim3((unsigned)ceil_div(n, 64)), dim3(256), 0, st, U, C, t, E, D, n, mp, L,
-                     mode, out);
+  if (L <= 16 && mp > 0)
+    hipLaunchKernelGGL((k_rowmm_small<T>), dim3((unsigned)ceil_div(n, 64)), dim3(256), 0, st, U, C, t, E, D, n, mp, L,
+                       mode, out);
+  else
+    hipLaunchKernelGGL((k_rowmm_multi<T>), dim3((unsigned)ceil_div(n, 64)), dim3(256), 0, st, U, C, t, E, D, n, mp, L,
+                       mode, out);
 }
 int launch_coldot_multi(hipStream_t st, const double* a0, const double* b0, const double* a1, const double* b1,
                         int64_t n, int L, double* part, double* out) {
