@@ -1774,10 +1774,13 @@ static vif_status alloc_slq(vif_ctx* c, int ell) {
   alloc((void**)&c->slq_iters, sizeof(int) * ell);
   const int L = std::min(ell, kBlockCols);
   const size_t mpa = c->mp > 0 ? c->mp : 1;
-  const size_t npart = std::max((size_t)utx_chunks(n) * mpa, 2 * (size_t)ceil_div(n, 1024));
+  const size_t npart = 2 * (size_t)ceil_div(n, 1024);  // the column-dot partials
   alloc((void**)&c->blk, sizeof(double) * kBlkVecs * n * L);
   alloc((void**)&c->blk_mm, sizeof(double) * 4 * mpa * L);
-  const size_t nsmall = (size_t)(utx_small_chunks(n, (int)mpa) + kColSplit) * mpa * std::min(L, 16);
+  // the most the U^T X partials need for any block width up to L
+  size_t nsmall = 0;
+  for (int l = 1; l <= L; ++l)
+    nsmall = std::max(nsmall, (size_t)(utx_small_chunks(n, (int)mpa, l) + kColSplit) * mpa * l);
   alloc((void**)&c->blk_part, sizeof(double) * std::max(npart * L, nsmall));
   alloc((void**)&c->blk_cs, sizeof(double) * 11 * L);
   alloc((void**)&c->blk_int, sizeof(int) * 4);

@@ -243,129 +243,62 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_level_multi(int beg, int end, 
 }
 
 // ------------------------------------------------------------ low-rank products
-// part[chunk][k][l] = sum_{i in chunk} U[i][k] x[i][l] (f64 MFMA 16x16x4: the
-// chunk's points are the contraction index). Workgroup = (chunk, 128 rows k):
-// 32-point tiles of U and x staged in LDS, wave w owns rows 32w..32w+31 of
-// its 128 (two 16-row tiles) and the L columns (up to four 16-column tiles).
-template <typename T>
-__global__ __launch_bounds__(256) void k_utx_partial(const T* __restrict__ U, const double* __restrict__ x, int64_t n,
-                                                     int mp, int L, int64_t chunk, double* __restrict__ part) {
-  __shared__ double sU[32][129];
-  __shared__ double sX[32][65];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r = lane & 15, g = lane >> 4;
-  const int k0 = blockIdx.y * 128;
-  const int64_t pbeg = (int64_t)blockIdx.x * chunk, pend = min(n, pbeg + chunk);
-  const int nt = (L + 15) / 16;
-  d4 acc[2][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[a][t] = d4{0, 0, 0, 0};
-  for (int64_t p0 = pbeg; p0 < pend; p0 += 32) {
-    for (int e = threadIdx.x; e < 32 * 128; e += 256) {
-      const int pt = e >> 7, k = e & 127;
-      const int64_t i = p0 + pt;
-      sU[pt][k] = (i < pend && k0 + k < mp) ? (double)U[(size_t)i * mp + k0 + k] : 0.0;
-    }
-    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
-      const int pt = e >> 6, l = e & 63;
-      const int64_t i = p0 + pt;
-      sX[pt][l] = (i < pend && l < L) ? x[i * L + l] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 32; kk += 4) {
-      const double a0 = sU[kk + g][32 * w + r], a1 = sU[kk + g][32 * w + 16 + r];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (t < nt) {
-          const double b = sX[kk + g][16 * t + r];
-          acc[0][t] = mfma16(a0, b, acc[0][t]);
-          acc[1][t] = mfma16(a1, b, acc[1][t]);
-        }
-      }
-    }
-    __syncthreads();
-  }
-  double* out = part + (size_t)blockIdx.x * mp * L;
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int k = k0 + 32 * w + 16 * a + acc_row<double>(lane, v), l = 16 * t + r;
-        if (t < nt && k < mp && l < L) out[(size_t)k * L + l] = acc[a][t][v];
-      }
-}
-
-// part[chunk][k][l] = sum_{i in chunk} U[i][k] x[i][l] for L <= 16 right-hand
-// sides without LDS: the f64 MFMA 16x16x4 with the chunk's points as the
-// contraction index, four points per step. Lane (r, j) loads U[i0 + j][k0 +
-// r] (16 consecutive k of four rows per wave load) into the A operand of each
-// of the wave's 16-row k tiles and x[i0 + j][r] (zero for r >= L or past the
-// chunk) into B. Wave w of workgroup (chunk, y) owns the eight k tiles from
-// k = 128 (4y + w).
-template <typename T>
+// part[chunk][k][l] = sum_{i in chunk} U[i][k] x[i][l] without LDS: the f64
+// MFMA 16x16x4 with the chunk's points as the contraction index, four points
+// per step. Lane (r, j) loads U[i0 + j][k0 + r] (16 consecutive k of four
+// rows per wave load) into the A operand of each of the wave's KT 16-row k
+// tiles and x[i0 + j][16u + r] (zero for columns >= L or past the chunk) into
+// the B operand of column tile u (NT tiles, L <= 16 NT). Wave w of workgroup
+// (chunk, y) owns the KT k tiles from k = 16 KT (4y + w).
+template <typename T, int KT, int NT>
 __global__ __launch_bounds__(256) void k_utx_small(const T* __restrict__ U, const double* __restrict__ x, int64_t n,
                                                    int mp, int L, int64_t chunk, double* __restrict__ part) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = lane & 15, j = lane >> 4;
-  const int kw = ((int)blockIdx.y * 4 + w) * 128;
+  const int kw = ((int)blockIdx.y * 4 + w) * 16 * KT;
   if (kw >= mp) return;
-  const int nt = min(8, (mp - kw) / 16);
+  const int nt = min(KT, (mp - kw) / 16);
   const int64_t pbeg = (int64_t)blockIdx.x * chunk, pend = min(n, pbeg + chunk);
-  const bool cok = r < L;
-  const int cc = min(r, L - 1);
-  d4 acc[8];
+  d4 acc[KT][NT];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) acc[t] = d4{0, 0, 0, 0};
+  for (int t = 0; t < KT; ++t)
+#pragma unroll
+    for (int u = 0; u < NT; ++u) acc[t][u] = d4{0, 0, 0, 0};
 #pragma unroll 2
   for (int64_t i0 = pbeg; i0 < pend; i0 += 4) {
     const int64_t i = i0 + j;
     const bool iok = i < pend;
     const int64_t ii = iok ? i : pend - 1;
-    const double b = (iok && cok) ? x[ii * L + cc] : 0.0;
+    double b[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int col = 16 * u + r;
+      b[u] = (iok && col < L) ? x[ii * L + min(col, L - 1)] : 0.0;
+    }
     const T* urow = U + (size_t)ii * mp + kw + r;
-    double a[8];
+    double a[KT];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) a[t] = t < nt ? (double)urow[16 * t] : 0.0;
+    for (int t = 0; t < KT; ++t) a[t] = t < nt ? (double)urow[16 * t] : 0.0;
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
-      if (t < nt) acc[t] = mfma16(a[t], b, acc[t]);
+    for (int t = 0; t < KT; ++t)
+      if (t < nt)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) acc[t][u] = mfma16(a[t], b[u], acc[t][u]);
   }
   double* out = part + (size_t)blockIdx.x * mp * L;
 #pragma unroll
-  for (int t = 0; t < 8; ++t)
+  for (int t = 0; t < KT; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int k = kw + 16 * t + acc_row<double>(lane, v);
-      if (t < nt && r < L) out[(size_t)k * L + r] = acc[t][v];
-    }
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = kw + 16 * t + acc_row<double>(lane, v);
+        const int col = 16 * u + r;
+        if (t < nt && col < L) out[(size_t)k * L + col] = acc[t][u][v];
+      }
 }
 
-// out = Minv (sum over chunks of part), mp x L (Minv: mp x mp, symmetric)
-__global__ void k_utx_reduce(const double* __restrict__ part, int nchunk, int mp, int L, double* __restrict__ sum) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= mp * L) return;
-  double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * mp * L + e];
-  sum[e] = s;
-}
-__global__ void k_sym_apply_multi(const double* __restrict__ Minv, const double* __restrict__ cin, int mp, int L,
-                                  double* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= mp * L) return;
-  const int k = e / L, l = e - k * L;
-  const double* row = Minv + (size_t)k * mp;
-  double s = 0.0;
-  for (int j = 0; j < mp; ++j) s += row[j] * cin[(size_t)j * L + l];
-  out[e] = s;
-}
-
-// (U C)[i][l] for a 64-point tile (f64 MFMA; 64 x 32 tiles of U and 32 x L
-// tiles of C staged in LDS), combined per mode:
+// (U C)[i][l] (U: n x mp, C: mp x L) combined per mode:
 //   0: out = (t - U C) f,  f = D^{-1/2} (D given) or 1
 //   1: out = t + E (U C) D^{-1/2}
 //   2: out = U C
@@ -399,13 +332,13 @@ __device__ __forceinline__ void load4(const float* __restrict__ p, double a[4]) 
   a[3] = x[3];
 }
 
-// The same products for L <= 16 right-hand sides without LDS: one wave per
-// 16 points and one 16-column tile. The contraction index k is taken four
-// consecutive entries per 16-lane group: lane (r, j) loads U[p0 + r][kb + 4j
-// .. kb + 4j + 3] straight into the A operands of four f64 MFMA 16x16x4 steps
-// (step s pairs slot j with k = kb + 4j + s), and the matching C[k][r] (C is
-// mp x L and stays in cache) into B; columns r >= L are zero. Rows past n
-// read row n - 1 and write nothing.
+// The same products without LDS: one wave per 16 points and up to four
+// 16-column tiles. The contraction index k is taken four consecutive entries
+// per 16-lane group: lane (r, j) loads U[p0 + r][kb + 4j .. kb + 4j + 3]
+// straight into the A operands of four f64 MFMA 16x16x4 steps (step s pairs
+// slot j with k = kb + 4j + s), shared by the column tiles, and the matching
+// C[k][16u + r] (C is mp x L and stays in cache) into B; columns >= L are
+// zero. Rows past n read row n - 1 and write nothing.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rowmm_small(const T* __restrict__ U, const double* __restrict__ C,
                                                      const double* __restrict__ t, const double* __restrict__ E,
@@ -415,72 +348,37 @@ __global__ __launch_bounds__(256) void k_rowmm_small(const T* __restrict__ U, co
   const int64_t p0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
   if (p0 >= n) return;
   const int r = lane & 15, j = lane >> 4;
-  const T* urow = U + (size_t)min(p0 + r, n - 1) * mp;
-  const bool cok = r < L;
-  const double* ccol = C + min(r, L - 1);
-  d4 acc = d4{0, 0, 0, 0};
-#pragma unroll 4
-  for (int kb = 0; kb < mp; kb += 16) {
-    const int k = kb + 4 * j;
-    double a[4], b[4];
-    load4(urow + k, a);
-#pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) b[s2] = cok ? ccol[(size_t)(k + s2) * L] : 0.0;
-#pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) acc = mfma16(a[s2], b[s2], acc);
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int64_t i = p0 + acc_row<double>(lane, v);
-    if (i < n && r < L) {
-      const int64_t e = i * L + r;
-      out[e] = rowmm_combine(mode, acc[v], t, E, D, i, e);
-    }
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_rowmm_multi(const T* __restrict__ U, const double* __restrict__ C,
-                                                     const double* __restrict__ t, const double* __restrict__ E,
-                                                     const double* __restrict__ D, int64_t n, int mp, int L, int mode,
-                                                     double* __restrict__ out) {
-  __shared__ double sU[64][33];
-  __shared__ double sC[32][65];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r = lane & 15, g = lane >> 4;
-  const int64_t p0 = (int64_t)blockIdx.x * 64;
   const int nt = (L + 15) / 16;
+  const T* urow = U + (size_t)min(p0 + r, n - 1) * mp;
   d4 acc[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) acc[u] = d4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < mp; k0 += 32) {
-    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-      const int pt = e >> 5, k = e & 31;
-      const int64_t i = p0 + pt;
-      sU[pt][k] = (i < n && k0 + k < mp) ? (double)U[(size_t)i * mp + k0 + k] : 0.0;
-    }
-    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
-      const int k = e >> 6, l = e & 63;
-      sC[k][l] = (k0 + k < mp && l < L) ? C[(size_t)(k0 + k) * L + l] : 0.0;
-    }
-    __syncthreads();
+#pragma unroll 2
+  for (int kb = 0; kb < mp; kb += 16) {
+    const int k = kb + 4 * j;
+    double a[4];
+    load4(urow + k, a);
 #pragma unroll
-    for (int kk = 0; kk < 32; kk += 4) {
-      const double a = sU[16 * w + r][kk + g];
+    for (int u = 0; u < 4; ++u) {
+      if (u < nt) {
+        const int col = 16 * u + r;
+        const double* cp = C + min(col, L - 1);
+        double b[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (u < nt) acc[u] = mfma16(a, sC[kk + g][16 * u + r], acc[u]);
+        for (int s2 = 0; s2 < 4; ++s2) b[s2] = col < L ? cp[(size_t)(k + s2) * L] : 0.0;
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) acc[u] = mfma16(a[s2], b[s2], acc[u]);
+      }
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t i = p0 + 16 * w + acc_row<double>(lane, v);
-      const int l = 16 * u + r;
-      if (u < nt && i < n && l < L) {
-        const int64_t e = i * L + l;
+      const int64_t i = p0 + acc_row<double>(lane, v);
+      const int col = 16 * u + r;
+      if (u < nt && i < n && col < L) {
+        const int64_t e = i * L + col;
         out[e] = rowmm_combine(mode, acc[u][v], t, E, D, i, e);
       }
     }
@@ -717,45 +615,40 @@ void launch_trsv_bwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, 
   }
   hipLaunchKernelGGL(k_perm_scatter_multi, gE(n * L), dim3(256), 0, st, s.order, zq, n, L, z);
 }
-int utx_chunks(int64_t n) { return (int)std::min<int64_t>(128, ceil_div(n, 32)); }
-// the small-L form: about 1024 workgroups (chunks x ceil(mp / 512)), chunks
-// a multiple of four points
-static int64_t utx_small_chunk(int64_t n, int mp) {
-  const int64_t target = std::max<int64_t>(1, 1024 / ceil_div(mp, 512));
+// the register-direct form: about 1024 workgroups (chunks x k groups), a
+// workgroup's four waves covering 64 KT k; chunks a multiple of four points.
+// KT = 8 k tiles per wave for L <= 16, 2 for up to 64 columns.
+static int utx_kt(int L) { return L <= 16 ? 8 : 2; }
+static int64_t utx_small_chunk(int64_t n, int mp, int L) {
+  const int64_t target = std::max<int64_t>(1, 1024 / ceil_div(mp, 64 * utx_kt(L)));
   return std::max<int64_t>(64, ceil_div(ceil_div(n, target), 4) * 4);
 }
-int utx_small_chunks(int64_t n, int mp) { return (int)ceil_div(n, utx_small_chunk(n, mp)); }
+int utx_small_chunks(int64_t n, int mp, int L) { return (int)ceil_div(n, utx_small_chunk(n, mp, L)); }
 template <typename T>
 void launch_utx(hipStream_t st, const T* U, const double* x, int64_t n, int mp, int L, const double* Minv,
                 double* part, double* sum, double* out) {
-  if (L <= 16 && mp > 0) {
-    const int64_t chunk = utx_small_chunk(n, mp);
+  if (mp > 0) {  // (callers skip m = 0)
+    const int kt = utx_kt(L);
+    const int64_t chunk = utx_small_chunk(n, mp, L);
     const int nchunk = (int)ceil_div(n, chunk);
-    hipLaunchKernelGGL((k_utx_small<T>), dim3((unsigned)nchunk, (unsigned)ceil_div(mp, 512)), dim3(256), 0, st, U, x,
-                       n, mp, L, chunk, part);
+    const dim3 grid((unsigned)nchunk, (unsigned)ceil_div(mp, 64 * kt));
+    if (L <= 16)
+      hipLaunchKernelGGL((k_utx_small<T, 8, 1>), grid, dim3(256), 0, st, U, x, n, mp, L, chunk, part);
+    else if (L <= 32)
+      hipLaunchKernelGGL((k_utx_small<T, 2, 2>), grid, dim3(256), 0, st, U, x, n, mp, L, chunk, part);
+    else
+      hipLaunchKernelGGL((k_utx_small<T, 2, 4>), grid, dim3(256), 0, st, U, x, n, mp, L, chunk, part);
     launch_colreduce(st, part, nchunk, mp * L, Minv ? sum : out);
     if (Minv)  // out = Minv sum, the same 16-point MFMA form (Minv as a U of mp rows)
       hipLaunchKernelGGL((k_rowmm_small<double>), dim3((unsigned)ceil_div(mp, 64)), dim3(256), 0, st, Minv, sum,
                          nullptr, nullptr, nullptr, (int64_t)mp, mp, L, 2, out);
-    return;
   }
-  const int nch = utx_chunks(n);
-  const int64_t chunk = ceil_div(ceil_div(n, nch), 32) * 32;
-  const int nchunk = (int)ceil_div(n, chunk);
-  hipLaunchKernelGGL((k_utx_partial<T>), dim3((unsigned)nchunk, (unsigned)ceil_div(mp, 128)), dim3(256), 0, st, U, x,
-                     n, mp, L, chunk, part);
-  hipLaunchKernelGGL(k_utx_reduce, gE((int64_t)mp * L), dim3(256), 0, st, part, nchunk, mp, L, Minv ? sum : out);
-  if (Minv) hipLaunchKernelGGL(k_sym_apply_multi, gE((int64_t)mp * L), dim3(256), 0, st, Minv, sum, mp, L, out);
 }
 template <typename T>
 void launch_rowmm_multi(hipStream_t st, const T* U, const double* C, const double* t, const double* E,
                         const double* D, int64_t n, int mp, int L, int mode, double* out) {
-  if (L <= 16 && mp > 0)
-    hipLaunchKernelGGL((k_rowmm_small<T>), dim3((unsigned)ceil_div(n, 64)), dim3(256), 0, st, U, C, t, E, D, n, mp, L,
-                       mode, out);
-  else
-    hipLaunchKernelGGL((k_rowmm_multi<T>), dim3((unsigned)ceil_div(n, 64)), dim3(256), 0, st, U, C, t, E, D, n, mp, L,
-                       mode, out);
+  hipLaunchKernelGGL((k_rowmm_small<T>), dim3((unsigned)ceil_div(n, 64)), dim3(256), 0, st, U, C, t, E, D, n, mp, L,
+                     mode, out);
 }
 int launch_coldot_multi(hipStream_t st, const double* a0, const double* b0, const double* a1, const double* b1,
                         int64_t n, int L, double* part, double* out) {

@@ -323,10 +323,10 @@ void launch_trsv_fwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, 
 template <typename T>
 void launch_trsv_bwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, int L, double* xq,
                            double* zq, double* z);
-int utx_chunks(int64_t n);
-// chunks of the L <= 16 form of launch_utx; its part must hold (utx_small_chunks + kColSplit) x mp x L
-int utx_small_chunks(int64_t n, int mp);
-// out (mp x L) = Minv (U^T x), or U^T x when Minv is null; part: utx_chunks(n) x mp x L, sum: mp x L
+// point chunks of launch_utx (m > 0); its part must hold (utx_small_chunks + kColSplit) x mp x L
+int utx_small_chunks(int64_t n, int mp, int L);
+// out (mp x L) = Minv (U^T x), or U^T x when Minv is null; part: (utx_small_chunks + kColSplit) x mp x L,
+// sum: mp x L
 template <typename T>
 void launch_utx(hipStream_t st, const T* U, const double* x, int64_t n, int mp, int L, const double* Minv,
                 double* part, double* sum, double* out);
