@@ -10,6 +10,8 @@
 // U^T X (mp x L, split over point chunks) and U C (n x L). The triangular
 // solves walk the same level schedule as the single-vector solves, one launch
 // per level, each level reading its rows once for all L columns.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -92,29 +94,33 @@ __global__ void k_scale_e_multi(const double* __restrict__ v, const double* __re
 }
 
 // ------------------------------------------------------------ B and B^T
-// One wave per row. Its lanes are (entry group g, column l): Lp = 2^lsh >= L
-// columns and G = 64 / Lp groups, group g taking the row's entries g, g + G,
-// ... eight at a time with the eight gathers in flight, so that a row's
-// entries are spread over the whole wave whatever the number of right-hand
-// sides. The groups' sums are then added by a fixed xor tree (the same
-// order on every call). Lanes with l >= L read a valid column and write
-// nothing; an empty slot gathers row 0 with its weight 0 and its value
-// replaced by 0.
+// One wave per row. Its lanes are (entry group g, column l): for L <= 16,
+// Lp = 2^lsh >= L columns and G = 64 / Lp groups, one column per lane; for
+// more columns, Lp = 16 and G = 4, lane l carrying the NC = ceil(L / 16)
+// columns l, l + 16, .... Group g takes the row's entries g, g + G, ...
+// eight at a time with their gathers in flight, so that a row's entries are
+// spread over the wave whatever the number of right-hand sides. The groups'
+// sums are then added by a fixed xor tree (the same order on every call).
+// Columns >= L read a valid column and write nothing; an empty slot gathers
+// row 0 with its weight 0 and its value replaced by 0.
 __device__ __forceinline__ double group_sum(double s, int lsh) {
   for (int o = 32; o >= (1 << lsh); o >>= 1) s += __shfl_xor(s, o);
   return s;
 }
 
-// sum over the m_v slots a of row `row` of w[a] x[idx[a]][ll] (slots with a
-// negative index count 0); this lane's share: slots g, g + G, ...
-template <typename T>
-__device__ __forceinline__ double slot_gather(const int32_t* __restrict__ idx, const T* __restrict__ w, int mv,
-                                              const double* __restrict__ x, int L, int ll, int g, int G) {
-  double s = 0.0;
+// v[t] += sum over the m_v slots a of a row of w[a] x[idx[a]][l + 16 t]
+// (slots with a negative index count 0); this lane's share: slots g, g + G, ...
+template <typename T, int NC>
+__device__ __forceinline__ void slot_gather(const int32_t* __restrict__ idx, const T* __restrict__ w, int mv,
+                                            const double* __restrict__ x, int L, int l, int g, int G,
+                                            double v[NC]) {
+  int cl[NC];
+#pragma unroll
+  for (int t = 0; t < NC; ++t) cl[t] = min(l + 16 * t, L - 1);
   for (int a0 = g; a0 < mv; a0 += 8 * G) {
     int c[8];
     bool ok[8];
-    double wv[8], z[8];
+    double wv[8], z[8][NC];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int a = a0 + k * G;
@@ -124,46 +130,90 @@ __device__ __forceinline__ double slot_gather(const int32_t* __restrict__ idx, c
       wv[k] = ok[k] ? (double)w[min(a, mv - 1)] : 0.0;
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) z[k] = x[(int64_t)c[k] * L + ll];
+    for (int k = 0; k < 8; ++k)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) s = fma(wv[k], ok[k] ? z[k] : 0.0, s);
+      for (int t = 0; t < NC; ++t) z[k][t] = x[(int64_t)c[k] * L + cl[t]];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int t = 0; t < NC; ++t) v[t] = fma(wv[k], ok[k] ? z[k][t] : 0.0, v[t]);
   }
-  return s;
+}
+
+// the same over the CSR entries [e0, e1) of a row: column col[e] (or, with
+// rev set, the point rev_idx / m_v of the reverse list) and weight w[e] (or
+// A[rev_idx]); entries past the end repeat the last one with weight 0
+template <typename T, int NC>
+__device__ __forceinline__ void csr_gather(const int* __restrict__ col, const T* __restrict__ w, int e0, int e1,
+                                           int mv, bool rev, const double* __restrict__ x, int L, int l, int g,
+                                           int G, double v[NC]) {
+  int cl[NC];
+#pragma unroll
+  for (int t = 0; t < NC; ++t) cl[t] = min(l + 16 * t, L - 1);
+  for (int a0 = e0 + g; a0 < e1; a0 += 8 * G) {
+    int c[8];
+    double wv[8], z[8][NC];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int a = a0 + k * G;
+      const int e = col[min(a, e1 - 1)];
+      c[k] = rev ? e / mv : e;
+      wv[k] = a < e1 ? (double)w[rev ? e : min(a, e1 - 1)] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int t = 0; t < NC; ++t) z[k][t] = x[(int64_t)c[k] * L + cl[t]];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int t = 0; t < NC; ++t) v[t] = fma(wv[k], z[k][t], v[t]);
+  }
 }
 
 // out[i][l] = (x[i][l] - sum_a A_ia x[N(i)_a][l]) * (D ? D_i^{-1/2} : 1)
-template <typename T>
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_bw_multi(const T* __restrict__ A, const double* __restrict__ D,
                                                   const int32_t* __restrict__ nbr, const double* __restrict__ x,
                                                   int64_t n, int mv, int L, int lsh, double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n) return;
-  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1), ll = min(l, L - 1);
-  double v = slot_gather<T>(nbr + i * mv, A + i * mv, mv, x, L, ll, g, 64 >> lsh);
-  v = group_sum(v, lsh);
-  if (g == 0 && l < L) {
-    const double s = x[i * L + l] - v;
-    out[i * L + l] = D ? s / sqrt(D[i]) : s;
+  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1);
+  double v[NC] = {};
+  slot_gather<T, NC>(nbr + i * mv, A + i * mv, mv, x, L, l, g, 64 >> lsh, v);
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    v[t] = group_sum(v[t], lsh);
+    const int col = l + 16 * t;
+    if (g == 0 && col < L) {
+      const double s = x[i * L + col] - v[t];
+      out[i * L + col] = D ? s / sqrt(D[i]) : s;
+    }
   }
 }
 
 // out[i][l] = -sum_a dA_ia x[N(i)_a][l]   (dB x, dB_{i,N(i)} = -dA_i)
-template <typename T>
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_dbx_multi(const T* __restrict__ dA, const int32_t* __restrict__ nbr,
                                                    const double* __restrict__ x, int64_t n, int mv, int L, int lsh,
                                                    double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n) return;
-  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1), ll = min(l, L - 1);
-  double v = slot_gather<T>(nbr + i * mv, dA + i * mv, mv, x, L, ll, g, 64 >> lsh);
-  v = group_sum(v, lsh);
-  if (g == 0 && l < L) out[i * L + l] = -v;
+  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1);
+  double v[NC] = {};
+  slot_gather<T, NC>(nbr + i * mv, dA + i * mv, mv, x, L, l, g, 64 >> lsh, v);
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    v[t] = group_sum(v[t], lsh);
+    const int col = l + 16 * t;
+    if (g == 0 && col < L) out[i * L + col] = -v[t];
+  }
 }
 
 // out[j][l] = s[j][l] - sum_{(q, slot): N(q)_slot = j} A_{q,slot} s[q][l] + (W ? W_j p[j][l] : 0)
-template <typename T>
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_btw_multi(const T* __restrict__ A, const int* __restrict__ rev_ptr,
                                                    const int* __restrict__ rev_idx, const double* __restrict__ s,
                                                    const double* __restrict__ W, const double* __restrict__ p,
@@ -171,33 +221,22 @@ __global__ __launch_bounds__(256) void k_btw_multi(const T* __restrict__ A, cons
   const int lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= n) return;
-  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1), ll = min(l, L - 1), G = 64 >> lsh;
-  double v = 0.0;
-  const int q0 = rev_ptr[j], q1 = rev_ptr[j + 1];
-  for (int a0 = q0 + g; a0 < q1; a0 += 8 * G) {
-    int c[8];
-    double w[8], z[8];
+  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1);
+  double v[NC] = {};
+  csr_gather<T, NC>(rev_idx, A, rev_ptr[j], rev_ptr[j + 1], mv, true, s, L, l, g, 64 >> lsh, v);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int a = a0 + k * G;
-      const int idx = rev_idx[min(a, q1 - 1)];
-      c[k] = idx / mv;
-      w[k] = a < q1 ? (double)A[idx] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) z[k] = s[(int64_t)c[k] * L + ll];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v = fma(w[k], z[k], v);
+  for (int t = 0; t < NC; ++t) {
+    v[t] = group_sum(v[t], lsh);
+    const int col = l + 16 * t;
+    if (g == 0 && col < L) out[j * L + col] = s[j * L + col] - v[t] + (W ? W[j] * p[j * L + col] : 0.0);
   }
-  v = group_sum(v, lsh);
-  if (g == 0 && l < L) out[j * L + l] = s[j * L + l] - v + (W ? W[j] * p[j * L + l] : 0.0);
 }
 
 // one level of B^{-1} (positions [beg, end), row q: m_v slots of positions
 // and coefficients): zq[q][l] = xq[q][l] + sum_a coef_qa zq[col_qa][l]. An
 // empty slot gathers position 0 (a valid address, not yet solved in the
 // first level) with its value replaced by 0.
-template <typename T>
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_trsv_fwd_level_multi(int beg, int end, const int* __restrict__ col,
                                                               const T* __restrict__ coef,
                                                               const double* __restrict__ xq, int mv, int L, int lsh,
@@ -205,15 +244,19 @@ __global__ __launch_bounds__(256) void k_trsv_fwd_level_multi(int beg, int end, 
   const int lane = threadIdx.x & 63;
   const int q = beg + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
   if (q >= end) return;
-  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1), ll = min(l, L - 1);
-  double v = slot_gather<T>(col + (size_t)q * mv, coef + (size_t)q * mv, mv, zq, L, ll, g, 64 >> lsh);
-  v = group_sum(v, lsh);
-  if (g == 0 && l < L) zq[(int64_t)q * L + l] = xq[(int64_t)q * L + l] + v;
+  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1);
+  double v[NC] = {};
+  slot_gather<T, NC>(col + (size_t)q * mv, coef + (size_t)q * mv, mv, zq, L, l, g, 64 >> lsh, v);
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    v[t] = group_sum(v[t], lsh);
+    const int c = l + 16 * t;
+    if (g == 0 && c < L) zq[(int64_t)q * L + c] = xq[(int64_t)q * L + c] + v[t];
+  }
 }
 
-// one level of B^{-T} (CSR rows by position); the entries past a row's end
-// repeat its last entry with weight 0
-template <typename T>
+// one level of B^{-T} (CSR rows by position)
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_trsv_bwd_level_multi(int beg, int end, const int* __restrict__ ptr,
                                                               const int* __restrict__ col, const T* __restrict__ coef,
                                                               const double* __restrict__ xq, int L, int lsh,
@@ -221,25 +264,15 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_level_multi(int beg, int end, 
   const int lane = threadIdx.x & 63;
   const int q = beg + (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
   if (q >= end) return;
-  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1), ll = min(l, L - 1), G = 64 >> lsh;
-  double v = 0.0;
-  const int e0 = ptr[q], e1 = ptr[q + 1];
-  for (int a0 = e0 + g; a0 < e1; a0 += 8 * G) {
-    int c[8];
-    double w[8], z[8];
+  const int g = lane >> lsh, l = lane & ((1 << lsh) - 1);
+  double v[NC] = {};
+  csr_gather<T, NC>(col, coef, ptr[q], ptr[q + 1], 1, false, zq, L, l, g, 64 >> lsh, v);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int a = a0 + k * G;
-      c[k] = col[min(a, e1 - 1)];
-      w[k] = a < e1 ? (double)coef[min(a, e1 - 1)] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) z[k] = zq[(int64_t)c[k] * L + ll];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v = fma(w[k], z[k], v);
+  for (int t = 0; t < NC; ++t) {
+    v[t] = group_sum(v[t], lsh);
+    const int c = l + 16 * t;
+    if (g == 0 && c < L) zq[(int64_t)q * L + c] = xq[(int64_t)q * L + c] + v[t];
   }
-  v = group_sum(v, lsh);
-  if (g == 0 && l < L) zq[(int64_t)q * L + l] = xq[(int64_t)q * L + l] + v;
 }
 
 // ------------------------------------------------------------ low-rank products
@@ -542,11 +575,23 @@ __global__ void k_colsum_final(const double* __restrict__ part, int nb, int L, d
 
 // ------------------------------------------------------------ launchers
 static inline dim3 gE(int64_t cnt) { return dim3((unsigned)ceil_div(cnt, 256)); }
-// log2 of the lanes per entry group of the gather kernels: the least power of two >= L (L <= 64)
+// lanes of the gather kernels: log2 of the columns per entry group (the
+// least power of two >= L up to 16) and the columns per lane (L > 16: 2 to 4)
 static inline int col_shift(int L) {
   int sh = 0;
-  while ((1 << sh) < L) ++sh;
+  while ((1 << sh) < L && sh < 4) ++sh;
   return sh;
+}
+static inline int col_count(int L) { return L > 16 ? (L + 15) / 16 : 1; }
+// f(std::integral_constant<int, NC>) for NC = col_count(L)
+template <typename F>
+static void by_cols(int L, F f) {
+  switch (col_count(L)) {
+    case 1: f(std::integral_constant<int, 1>()); break;
+    case 2: f(std::integral_constant<int, 2>()); break;
+    case 3: f(std::integral_constant<int, 3>()); break;
+    default: f(std::integral_constant<int, 4>()); break;
+  }
 }
 
 void launch_cols_to_block(hipStream_t st, const double* src, int64_t stride, int64_t off, int k0, int64_t n, int L,
@@ -576,20 +621,26 @@ void launch_scale_e_multi(hipStream_t st, const double* v, const double* E, cons
 template <typename T>
 void launch_bw_multi(hipStream_t st, const T* A, const double* D, const int32_t* nbr, const double* x, int64_t n,
                      int mv, int L, double* out) {
-  hipLaunchKernelGGL((k_bw_multi<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, A, D, nbr, x, n, mv, L,
-                     col_shift(L), out);
+  by_cols(L, [&](auto nc) {
+    hipLaunchKernelGGL((k_bw_multi<T, decltype(nc)::value>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, A, D,
+                       nbr, x, n, mv, L, col_shift(L), out);
+  });
 }
 template <typename T>
 void launch_dbx_multi(hipStream_t st, const T* dA, const int32_t* nbr, const double* x, int64_t n, int mv, int L,
                       double* out) {
-  hipLaunchKernelGGL((k_dbx_multi<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, dA, nbr, x, n, mv, L,
-                     col_shift(L), out);
+  by_cols(L, [&](auto nc) {
+    hipLaunchKernelGGL((k_dbx_multi<T, decltype(nc)::value>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, dA,
+                       nbr, x, n, mv, L, col_shift(L), out);
+  });
 }
 template <typename T>
 void launch_btw_multi(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s,
                       const double* W, const double* p, int64_t n, int mv, int L, double* out) {
-  hipLaunchKernelGGL((k_btw_multi<T>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, A, rev_ptr, rev_idx, s, W, p,
-                     n, mv, L, col_shift(L), out);
+  by_cols(L, [&](auto nc) {
+    hipLaunchKernelGGL((k_btw_multi<T, decltype(nc)::value>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, A,
+                       rev_ptr, rev_idx, s, W, p, n, mv, L, col_shift(L), out);
+  });
 }
 template <typename T>
 void launch_trsv_fwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, int L, double* xq,
@@ -598,8 +649,10 @@ void launch_trsv_fwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, 
   hipLaunchKernelGGL(k_perm_gather_multi, gE(n * L), dim3(256), 0, st, s.order, x, n, L, xq);
   for (int lv = 0; lv < s.nlev; ++lv) {
     const int beg = s.hlvl[lv], end = s.hlvl[lv + 1];
-    hipLaunchKernelGGL((k_trsv_fwd_level_multi<T>), dim3((unsigned)ceil_div(end - beg, 4)), dim3(256), 0, st, beg, end,
-                       s.col, coef, xq, s.mv, L, col_shift(L), zq);
+    by_cols(L, [&](auto nc) {
+      hipLaunchKernelGGL((k_trsv_fwd_level_multi<T, decltype(nc)::value>), dim3((unsigned)ceil_div(end - beg, 4)),
+                         dim3(256), 0, st, beg, end, s.col, coef, xq, s.mv, L, col_shift(L), zq);
+    });
   }
   hipLaunchKernelGGL(k_perm_scatter_multi, gE(n * L), dim3(256), 0, st, s.order, zq, n, L, z);
 }
@@ -610,8 +663,10 @@ void launch_trsv_bwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, 
   hipLaunchKernelGGL(k_perm_gather_multi, gE(n * L), dim3(256), 0, st, s.order, x, n, L, xq);
   for (int lv = 0; lv < s.nlev; ++lv) {
     const int beg = s.hlvl[lv], end = s.hlvl[lv + 1];
-    hipLaunchKernelGGL((k_trsv_bwd_level_multi<T>), dim3((unsigned)ceil_div(end - beg, 4)), dim3(256), 0, st, beg, end,
-                       s.ptr, s.col, coef, xq, L, col_shift(L), zq);
+    by_cols(L, [&](auto nc) {
+      hipLaunchKernelGGL((k_trsv_bwd_level_multi<T, decltype(nc)::value>), dim3((unsigned)ceil_div(end - beg, 4)),
+                         dim3(256), 0, st, beg, end, s.ptr, s.col, coef, xq, L, col_shift(L), zq);
+    });
   }
   hipLaunchKernelGGL(k_perm_scatter_multi, gE(n * L), dim3(256), 0, st, s.order, zq, n, L, z);
 }
