@@ -417,6 +417,69 @@ __global__ __launch_bounds__(256) void k_rowmm_small(const T* __restrict__ U, co
     }
 }
 
+// U C for 17 to 64 right-hand sides with C staged in LDS: C (mp x L) is too
+// large to be read from cache by every wave, so a workgroup covers 128
+// points (wave w: points 16w and 64 + 16w onwards) and walks k in chunks of
+// 64 rows of C held in LDS; the A operands load U rows as in k_rowmm_small.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rowmm_lds(const T* __restrict__ U, const double* __restrict__ C,
+                                                   const double* __restrict__ t, const double* __restrict__ E,
+                                                   const double* __restrict__ D, int64_t n, int mp, int L, int mode,
+                                                   double* __restrict__ out) {
+  __shared__ double sC[64][65];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, j = lane >> 4;
+  const int nt = (L + 15) / 16;
+  const int64_t pw = (int64_t)blockIdx.x * 128 + 16 * w;
+  const T* urow[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) urow[h] = U + (size_t)min(pw + 64 * h + r, n - 1) * mp;
+  d4 acc[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[h][u] = d4{0, 0, 0, 0};
+  for (int kc = 0; kc < mp; kc += 64) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      const int kk = e >> 6, col = e & 63;
+      sC[kk][col] = (kc + kk < mp && col < L) ? C[(size_t)(kc + kk) * L + col] : 0.0;
+    }
+    __syncthreads();
+    const int kend = min(64, mp - kc);
+    for (int kb = 0; kb < kend; kb += 16) {
+      const int k = kb + 4 * j;
+      double a[2][4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) load4(urow[h] + kc + k, a[h]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u < nt) {
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2) {
+            const double b = sC[k + s2][16 * u + r];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) acc[h][u] = mfma16(a[h][s2], b, acc[h][u]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = pw + 64 * h + acc_row<double>(lane, v);
+        const int col = 16 * u + r;
+        if (u < nt && i < n && col < L) {
+          const int64_t e = i * L + col;
+          out[e] = rowmm_combine(mode, acc[h][u][v], t, E, D, i, e);
+        }
+      }
+}
+
 // ------------------------------------------------------------ column reductions
 // part[blk][c][l] = sum over the block's points of a_c[i][l] b_c[i][l], c < nc
 // (nc = 1 or 2); 4 waves stride over the block's 1024 points, fixed order
@@ -702,8 +765,12 @@ void launch_utx(hipStream_t st, const T* U, const double* x, int64_t n, int mp, 
 template <typename T>
 void launch_rowmm_multi(hipStream_t st, const T* U, const double* C, const double* t, const double* E,
                         const double* D, int64_t n, int mp, int L, int mode, double* out) {
-  hipLaunchKernelGGL((k_rowmm_small<T>), dim3((unsigned)ceil_div(n, 64)), dim3(256), 0, st, U, C, t, E, D, n, mp, L,
-                     mode, out);
+  if (L > 16 && mp > 0)
+    hipLaunchKernelGGL((k_rowmm_lds<T>), dim3((unsigned)ceil_div(n, 128)), dim3(256), 0, st, U, C, t, E, D, n, mp, L,
+                       mode, out);
+  else
+    hipLaunchKernelGGL((k_rowmm_small<T>), dim3((unsigned)ceil_div(n, 64)), dim3(256), 0, st, U, C, t, E, D, n, mp, L,
+                       mode, out);
 }
 int launch_coldot_multi(hipStream_t st, const double* a0, const double* b0, const double* a1, const double* b1,
                         int64_t n, int L, double* part, double* out) {

@@ -111,7 +111,7 @@ def test_set_preconditioner_rejects_unknown_kind():
 
 
 @pytest.mark.parametrize("lik,n,m,mv,ell", [(lo.BERNOULLI_LOGIT, 700, 17, 8, 6), (lo.POISSON_LOG, 1500, 30, 12, 4),
-                                            (lo.POISSON_LOG, 800, 0, 10, 3)])
+                                            (lo.POISSON_LOG, 800, 0, 10, 3), (lo.POISSON_LOG, 600, 20, 8, 20)])
 def test_fitc_laplace_nll_matches_oracle(lik, n, m, mv, ell):
     """Laplace NLL with the log-det of eq. slq_v2 (FITC preconditioner, probes
     z = D_V^{1/2} e1 + V^T e3) against the oracle with the same probes: the
@@ -145,7 +145,8 @@ def test_fitc_laplace_nll_matches_oracle(lik, n, m, mv, ell):
                                                  (lo.POISSON_LOG, 1500, 30, 12, 4, "fp64"),
                                                  (lo.POISSON_LOG, 800, 0, 10, 3, "fp64"),
                                                  (lo.GAMMA_LOG, 800, 20, 8, 4, "fp64"),
-                                                 (lo.POISSON_LOG, 800, 20, 8, 5, "fp32")])
+                                                 (lo.POISSON_LOG, 800, 20, 8, 5, "fp32"),
+                                                 (lo.BERNOULLI_LOGIT, 500, 17, 8, 33, "fp64")])
 def test_fitc_laplace_grad_matches_oracle(lik, n, m, mv, ell, prec):
     """Laplace NLL + gradient with the FITC preconditioner (eq. pcls2 form of
     the trace estimates, App. D; the preconditioner's derivative terms of

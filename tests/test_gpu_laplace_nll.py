@@ -17,7 +17,11 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("lik,n,m,mv,ell", [(lo.BERNOULLI_LOGIT, 700, 17, 8, 6), (lo.POISSON_LOG, 1500, 30, 12, 4),
-                                            (lo.POISSON_LOG, 900, 0, 10, 3), (lo.GAMMA_LOG, 800, 20, 10, 4)])
+                                            (lo.POISSON_LOG, 900, 0, 10, 3), (lo.GAMMA_LOG, 800, 20, 10, 4),
+                                            # wide probe blocks: 40 columns (three per lane, four column
+                                            # tiles, C staged in LDS over two k chunks at m_p = 80) and 70
+                                            # probes (a full block of 64, then 6)
+                                            (lo.POISSON_LOG, 600, 70, 8, 40), (lo.BERNOULLI_LOGIT, 500, 17, 8, 70)])
 def test_laplace_nll_matches_oracle(lik, n, m, mv, ell):
     from paper_2507_05064_amd.vif import VifContext
     model, X, Z, nbr, prior, y, mode = _latent(n=n, m=m, mv=mv, lik=lik, seed=n)
@@ -41,7 +45,8 @@ def test_laplace_nll_matches_oracle(lik, n, m, mv, ell):
                                                  (lo.BERNOULLI_LOGIT, 1200, 25, 12, 4, "fp64"),
                                                  (lo.POISSON_LOG, 700, 0, 10, 3, "fp64"),
                                                  (lo.POISSON_LOG, 800, 20, 8, 5, "fp32"),
-                                                 (lo.GAMMA_LOG, 800, 20, 8, 4, "fp64")])
+                                                 (lo.GAMMA_LOG, 800, 20, 8, 4, "fp64"),
+                                                 (lo.POISSON_LOG, 600, 20, 8, 24, "fp64")])
 def test_laplace_grad_matches_oracle(lik, n, m, mv, ell, prec):
     """Gradient by STE with control variates (App. D) against the oracle's
     estimator on the same probes: FP64 within 1e-6 of max|g| (CG to 1e-11 on
