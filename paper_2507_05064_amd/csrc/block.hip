@@ -95,8 +95,10 @@ __global__ void k_scale_e_multi(const double* __restrict__ v, const double* __re
 
 // ------------------------------------------------------------ B and B^T
 // One wave per row. Its lanes are (entry group g, column l): for L <= 16,
-// Lp = 2^lsh >= L columns and G = 64 / Lp groups, one column per lane; for
-// more columns, Lp = 16 and G = 4, lane l carrying the NC = ceil(L / 16)
+// Lp = 2^lsh >= L columns and G = 64 / Lp groups, one column per lane. Above
+// 16 columns the rows of m_v slots (B x, dB x, B^-1) keep one column per
+// lane in a single group, while the CSR rows (B^T w, B^-T), some of which
+// are long, use Lp = 16 and G = 4, lane l carrying the NC = ceil(L / 16)
 // columns l, l + 16, .... Group g takes the row's entries g, g + G, ...
 // eight at a time with their gathers in flight, so that a row's entries are
 // spread over the wave whatever the number of right-hand sides. The groups'
@@ -506,12 +508,14 @@ __global__ __launch_bounds__(256) void k_coldot_multi(const double* __restrict__
   }
 }
 // out[c][l] = sum_blk part[blk][c][l] (fixed order)
+// one wave per entry e = c L + l (2 L <= 128 of them), lane k taking the
+// blocks k, k + 64, ..., then a wave tree
 __global__ void k_coldot_final(const double* __restrict__ part, int nb, int L, double* __restrict__ out) {
-  const int e = threadIdx.x;  // c * L + l, 2 L <= 128
-  if (e >= 2 * L) return;
+  const int e = blockIdx.x, lane = threadIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[(size_t)b * 2 * L + e];
-  out[e] = s;
+  for (int b = lane; b < nb; b += 64) s += part[(size_t)b * 2 * L + e];
+  s = wave_sum(s);
+  if (lane == 0) out[e] = s;
 }
 
 // ------------------------------------------------------------ CG per column
@@ -646,6 +650,9 @@ static inline int col_shift(int L) {
   return sh;
 }
 static inline int col_count(int L) { return L > 16 ? (L + 15) / 16 : 1; }
+// the fixed-slot gathers (m_v entries per row) keep one column per lane:
+// above 16 columns the whole wave is one group
+static inline int slot_shift(int L) { return L > 16 ? 6 : col_shift(L); }
 // f(std::integral_constant<int, NC>) for NC = col_count(L)
 template <typename F>
 static void by_cols(int L, F f) {
@@ -684,18 +691,14 @@ void launch_scale_e_multi(hipStream_t st, const double* v, const double* E, cons
 template <typename T>
 void launch_bw_multi(hipStream_t st, const T* A, const double* D, const int32_t* nbr, const double* x, int64_t n,
                      int mv, int L, double* out) {
-  by_cols(L, [&](auto nc) {
-    hipLaunchKernelGGL((k_bw_multi<T, decltype(nc)::value>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, A, D,
-                       nbr, x, n, mv, L, col_shift(L), out);
-  });
+  hipLaunchKernelGGL((k_bw_multi<T, 1>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, A, D, nbr, x, n, mv, L,
+                     slot_shift(L), out);
 }
 template <typename T>
 void launch_dbx_multi(hipStream_t st, const T* dA, const int32_t* nbr, const double* x, int64_t n, int mv, int L,
                       double* out) {
-  by_cols(L, [&](auto nc) {
-    hipLaunchKernelGGL((k_dbx_multi<T, decltype(nc)::value>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, dA,
-                       nbr, x, n, mv, L, col_shift(L), out);
-  });
+  hipLaunchKernelGGL((k_dbx_multi<T, 1>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, dA, nbr, x, n, mv, L,
+                     slot_shift(L), out);
 }
 template <typename T>
 void launch_btw_multi(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s,
@@ -712,10 +715,8 @@ void launch_trsv_fwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, 
   hipLaunchKernelGGL(k_perm_gather_multi, gE(n * L), dim3(256), 0, st, s.order, x, n, L, xq);
   for (int lv = 0; lv < s.nlev; ++lv) {
     const int beg = s.hlvl[lv], end = s.hlvl[lv + 1];
-    by_cols(L, [&](auto nc) {
-      hipLaunchKernelGGL((k_trsv_fwd_level_multi<T, decltype(nc)::value>), dim3((unsigned)ceil_div(end - beg, 4)),
-                         dim3(256), 0, st, beg, end, s.col, coef, xq, s.mv, L, col_shift(L), zq);
-    });
+    hipLaunchKernelGGL((k_trsv_fwd_level_multi<T, 1>), dim3((unsigned)ceil_div(end - beg, 4)), dim3(256), 0, st, beg,
+                       end, s.col, coef, xq, s.mv, L, slot_shift(L), zq);
   }
   hipLaunchKernelGGL(k_perm_scatter_multi, gE(n * L), dim3(256), 0, st, s.order, zq, n, L, z);
 }
@@ -776,7 +777,7 @@ int launch_coldot_multi(hipStream_t st, const double* a0, const double* b0, cons
                         int64_t n, int L, double* part, double* out) {
   const int nb = (int)ceil_div(n, 1024);
   hipLaunchKernelGGL(k_coldot_multi, dim3((unsigned)nb), dim3(256), 0, st, a0, b0, a1, b1, n, L, part);
-  hipLaunchKernelGGL(k_coldot_final, dim3(1), dim3(128), 0, st, part, nb, L, out);
+  hipLaunchKernelGGL(k_coldot_final, dim3((unsigned)(2 * L)), dim3(64), 0, st, part, nb, L, out);
   return nb;
 }
 void launch_cg_init_multi(hipStream_t st, double* cs, const double* dots, double tol2, int L, double* rz0,

@@ -317,11 +317,18 @@ __global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ a, cons
   }
 }
 
-// sum the partials in a fixed order: out[0] = sum part[2b], out[1] = sum part[2b+1]
+// sum the partials in a fixed order: out[0] = sum part[2b], out[1] = sum
+// part[2b+1]; one wave, lane l taking b = l, l + 64, ..., then a wave tree
 __global__ void k_sum2(const double* __restrict__ part, int nb, double* __restrict__ out) {
-  if (threadIdx.x == 0) {
-    double s0 = 0.0, s1 = 0.0;
-    for (int b = 0; b < nb; ++b) { s0 += part[2 * b]; s1 += part[2 * b + 1]; }
+  const int lane = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (int b = lane; b < nb; b += 64) {
+    s0 += part[2 * b];
+    s1 += part[2 * b + 1];
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if (lane == 0) {
     out[0] = s0;
     out[1] = s1;
   }
