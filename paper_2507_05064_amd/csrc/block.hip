@@ -482,6 +482,61 @@ __global__ __launch_bounds__(256) void k_rowmm_lds(const T* __restrict__ U, cons
       }
 }
 
+// The same for 17 to 64 columns with X staged in LDS: the four waves of a
+// workgroup (each with its own k tiles) share each 64-point block of X, read
+// from memory once per workgroup instead of once per wave.
+template <typename T, int KT, int NT>
+__global__ __launch_bounds__(256) void k_utx_lds(const T* __restrict__ U, const double* __restrict__ x, int64_t n,
+                                                 int mp, int L, int64_t chunk, double* __restrict__ part) {
+  __shared__ double sx[64][16 * NT + 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, j = lane >> 4;
+  const int kw = ((int)blockIdx.y * 4 + w) * 16 * KT;
+  const int nt = kw < mp ? min(KT, (mp - kw) / 16) : 0;  // no early exit: the workgroup shares barriers
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk, pend = min(n, pbeg + chunk);
+  d4 acc[KT][NT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t)
+#pragma unroll
+    for (int u = 0; u < NT; ++u) acc[t][u] = d4{0, 0, 0, 0};
+  for (int64_t b0 = pbeg; b0 < pend; b0 += 64) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 16 * NT; e += 256) {
+      const int pt = e / (16 * NT), col = e - pt * (16 * NT);
+      const int64_t i = b0 + pt;
+      sx[pt][col] = (i < pend && col < L) ? x[i * L + col] : 0.0;
+    }
+    __syncthreads();
+    const int bend = (int)min((int64_t)64, pend - b0);
+    for (int s4 = 0; s4 < bend; s4 += 4) {
+      const int pt = s4 + j;  // < 64; past the chunk its staged X is zero
+      const int64_t ii = min(b0 + pt, pend - 1);
+      const T* urow = U + (size_t)ii * mp + kw + r;
+      double a[KT], b[NT];
+#pragma unroll
+      for (int t = 0; t < KT; ++t) a[t] = t < nt ? (double)urow[16 * t] : 0.0;
+#pragma unroll
+      for (int u = 0; u < NT; ++u) b[u] = sx[pt][16 * u + r];
+#pragma unroll
+      for (int t = 0; t < KT; ++t)
+        if (t < nt)
+#pragma unroll
+          for (int u = 0; u < NT; ++u) acc[t][u] = mfma16(a[t], b[u], acc[t][u]);
+    }
+  }
+  double* out = part + (size_t)blockIdx.x * mp * L;
+#pragma unroll
+  for (int t = 0; t < KT; ++t)
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = kw + 16 * t + acc_row<double>(lane, v);
+        const int col = 16 * u + r;
+        if (t < nt && col < L) out[(size_t)k * L + col] = acc[t][u][v];
+      }
+}
+
 // ------------------------------------------------------------ column reductions
 // part[blk][c][l] = sum over the block's points of a_c[i][l] b_c[i][l], c < nc
 // (nc = 1 or 2); 4 waves stride over the block's 1024 points, fixed order
@@ -754,9 +809,9 @@ void launch_utx(hipStream_t st, const T* U, const double* x, int64_t n, int mp, 
     if (L <= 16)
       hipLaunchKernelGGL((k_utx_small<T, 8, 1>), grid, dim3(256), 0, st, U, x, n, mp, L, chunk, part);
     else if (L <= 32)
-      hipLaunchKernelGGL((k_utx_small<T, 2, 2>), grid, dim3(256), 0, st, U, x, n, mp, L, chunk, part);
+      hipLaunchKernelGGL((k_utx_lds<T, 2, 2>), grid, dim3(256), 0, st, U, x, n, mp, L, chunk, part);
     else
-      hipLaunchKernelGGL((k_utx_small<T, 2, 4>), grid, dim3(256), 0, st, U, x, n, mp, L, chunk, part);
+      hipLaunchKernelGGL((k_utx_lds<T, 2, 4>), grid, dim3(256), 0, st, U, x, n, mp, L, chunk, part);
     launch_colreduce(st, part, nchunk, mp * L, Minv ? sum : out);
     if (Minv)  // out = Minv sum, the same 16-point MFMA form (Minv as a U of mp rows)
       hipLaunchKernelGGL((k_rowmm_small<double>), dim3((unsigned)ceil_div(mp, 64)), dim3(256), 0, st, Minv, sum,
