@@ -1276,13 +1276,14 @@ static vif_status read_scalars(vif_ctx* c, int count) {
   return VIF_OK;
 }
 
-// sum of the k_lik partials (one per 256 points) into sc[slot]
+// sum of the k_lik partials (one per 256 points) into sc[slot]: one wave,
+// lane k taking b = k, k + 64, ..., then a wave tree (a fixed order)
 __global__ void k_sum_part(const double* part, int nb, double* out) {
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[b];
-    out[0] = s;
-  }
+  const int lane = threadIdx.x;
+  double s = 0.0;
+  for (int b = lane; b < nb; b += 64) s += part[b];
+  s = wave_sum(s);
+  if (lane == 0) out[0] = s;
 }
 
 // VIFDU data for the diagonal B.W: E = D / (1 + D W), sw = D W / (1 + D W),

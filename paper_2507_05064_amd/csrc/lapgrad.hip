@@ -262,12 +262,14 @@ __global__ __launch_bounds__(256) void k_rowdot(const T* __restrict__ A, const T
 }
 
 // fixed-order sum of `cols` interleaved per-block partials into out[0..cols)
+// out[c] = sum over the blocks b of part[b][c]: one wave per column, lane k
+// taking b = k, k + 64, ..., then a wave tree (a fixed order)
 __global__ void k_sum_cols(const double* __restrict__ part, int nb, int cols, double* __restrict__ out) {
-  if (threadIdx.x < cols) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(size_t)b * cols + threadIdx.x];
-    out[threadIdx.x] = s;
-  }
+  const int c = blockIdx.x, lane = threadIdx.x;
+  double s = 0.0;
+  for (int b = lane; b < nb; b += 64) s += part[(size_t)b * cols + c];
+  s = wave_sum(s);
+  if (lane == 0) out[c] = s;
 }
 
 // Forward-mode derivative of the Gaussian NLL (Sec. 2.2; the whitened form
@@ -380,7 +382,7 @@ void launch_diag_final(hipStream_t st, const double* Sh, const double* Sg, const
   hipLaunchKernelGGL(k_diag_final, gN(n), dim3(256), 0, st, Sh, Sg, tr, c, ell, n, out);
 }
 void launch_sum_cols(hipStream_t st, const double* part, int nb, int cols, double* out) {
-  hipLaunchKernelGGL(k_sum_cols, dim3(1), dim3(64), 0, st, part, nb, cols, out);
+  hipLaunchKernelGGL(k_sum_cols, dim3((unsigned)cols), dim3(64), 0, st, part, nb, cols, out);
 }
 
 #define INST(T)                                                                                                    \
