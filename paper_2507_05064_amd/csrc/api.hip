@@ -80,6 +80,8 @@ struct vif_ctx {
   void *MinvT = nullptr, *Ubar = nullptr, *Q1 = nullptr, *Gs = nullptr, *Bs = nullptr, *Vr = nullptr;
   double *tpart = nullptr, *rowpart = nullptr, *gred = nullptr;
   int *rev_cnt = nullptr, *rev_ptr = nullptr, *rev_cur = nullptr, *rev_idx = nullptr;
+  int* rev_q = nullptr;     // the reverse lists' rows (rev_idx / m_v)
+  void* rev_a = nullptr;    // and coefficients A[rev_idx], in the form's type
   // level schedules of the sparse triangular solves with B and B^T
   int *fwd_order = nullptr, *fwd_lvl = nullptr, *bwd_order = nullptr, *bwd_lvl = nullptr;
   int *fwd_slvl = nullptr, *bwd_slvl = nullptr;  // level offsets with mid-size levels split in two
@@ -436,6 +438,8 @@ vif_status vif_create(const vif_config* cfg, void* hip_stream, vif_ctx** out) {
     alloc((void**)&c->rev_ptr, sizeof(int) * (n + 1));
     alloc((void**)&c->rev_cur, sizeof(int) * n);
     alloc((void**)&c->rev_idx, sizeof(int) * mvn);
+    alloc((void**)&c->rev_q, sizeof(int) * mvn);
+    alloc(&c->rev_a, tsize(c) * mvn);
     alloc((void**)&c->fwd_order, sizeof(int) * n);
     alloc((void**)&c->fwd_lvl, sizeof(int) * (n + 1));
     alloc((void**)&c->fwd_slvl, sizeof(int) * (n + 1));
@@ -499,7 +503,7 @@ void vif_destroy(vif_ctx* c) {
   void* bufs[] = {c->Sm, c->Linv, c->Mp, c->LMinv, c->Mwork, c->Vd, c->Vf, c->Vb, c->A, c->Lfac, c->U, c->D, c->yt, c->vnorm,
                   c->partial, c->vecpart, c->vec, c->scal, c->status, c->nbr, c->Xc, c->Zc, c->Minv, c->wvec,
                   c->e, c->Smat, c->Tm, c->tmpm, c->MinvT, c->Ubar, c->Q1, c->Gs, c->Bs, c->Vr, c->tpart,
-                  c->rowpart, c->gred, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx,
+                  c->rowpart, c->gred, c->rev_cnt, c->rev_ptr, c->rev_cur, c->rev_idx, c->rev_q, c->rev_a,
                   c->fwd_order, c->fwd_lvl, c->bwd_order, c->bwd_lvl, c->fwd_slvl, c->bwd_slvl, c->lv, c->lm, c->M3, c->M3inv, c->L3inv,
                   c->lsc, c->lpart, c->fcol, c->bptr, c->bcol, c->bsrc, c->fsrc, c->fsplit, c->bsplit, c->fcoef, c->bcoef, c->slq_a, c->slq_b, c->slq_rz, c->slq_terms, c->slq_work, c->slq_u,
                   c->slq_q, c->slq_iters, c->lg_Ut, c->lg_Ut3, c->lg_dV, c->lg_MT, c->lg_M3T, c->lg_PhiT, c->lg_mm, c->lg_vec, c->lg_part, c->lg_slots, c->pred_Vp,
@@ -925,12 +929,16 @@ static vif_status refresh_coef(vif_ctx* c) {
     c->coef_valid = true;
     return VIF_OK;
   }
+  const int64_t n = c->cfg.n;
+  const int mv = c->cfg.m_v;
   if (fp32_form(c)) {
     launch_coef_fwd<float>(c->st, c->sf, (const float*)c->A, (float*)c->fcoef);
     launch_coef_bwd<float>(c->st, c->sb, (const float*)c->A, (float*)c->bcoef);
+    launch_rev_coef<float>(c->st, c->rev_ptr, c->rev_idx, (const float*)c->A, n, mv, c->rev_q, (float*)c->rev_a);
   } else {
     launch_coef_fwd<double>(c->st, c->sf, (const double*)c->A, (double*)c->fcoef);
     launch_coef_bwd<double>(c->st, c->sb, (const double*)c->A, (double*)c->bcoef);
+    launch_rev_coef<double>(c->st, c->rev_ptr, c->rev_idx, (const double*)c->A, n, mv, c->rev_q, (double*)c->rev_a);
   }
   HIPCHK(c, hipGetLastError());
   c->coef_valid = true;
@@ -1242,7 +1250,7 @@ static void prec_matvec(vif_ctx* c, LapBufs& B, const double* w, const double* W
     launch_reduce_apply(c->st, B.upart, c->unchunk, c->mp, c->Minv, B.cbuf, B.cp);
   }
   launch_t_minus_uc<T>(c->st, U, B.cp, B.t, c->D, g.n, c->mp, B.s);
-  launch_btw<T>(c->st, (const T*)c->A, c->rev_ptr, c->rev_idx, B.s, W, w, g.n, g.m_v, out);
+  launch_btw<T>(c->st, c->rev_ptr, c->rev_q, (const T*)c->rev_a, B.s, W, w, g.n, out);
 }
 
 // z = P^{-1} r  (VIFDU; E and M3inv of the current W)
@@ -1838,7 +1846,7 @@ static void blk_prec_matvec(vif_ctx* c, BlkBufs& K, const double* x, int L, cons
   launch_bw_multi<T>(c->st, (const T*)c->A, c->D, c->nbr, x, g.n, g.m_v, L, K.t);
   if (g.m > 0) launch_utx<T>(c->st, U, K.t, g.n, c->mp, L, c->Minv, K.part, K.cm2, K.cm);
   launch_rowmm_multi<T>(c->st, U, K.cm, K.t, nullptr, c->D, g.n, c->mp, L, 0, K.s);
-  launch_btw_multi<T>(c->st, (const T*)c->A, c->rev_ptr, c->rev_idx, K.s, W, x, g.n, g.m_v, L, out);
+  launch_btw_multi<T>(c->st, c->rev_ptr, c->rev_q, (const T*)c->rev_a, K.s, W, x, g.n, L, out);
 }
 
 // z = P^{-1} r (VIFDU of the current E and M3') for a block of L vectors
@@ -2049,7 +2057,7 @@ static vif_status laplace_nll_impl(vif_ctx* c, const double* y, const double* mo
     launch_rowmm_multi<T>(c->st, U, K.cm, K.t, nullptr, c->D, n, mp, L, 0, K.s);
     launch_cols_to_block(c->st, eps_n, 2 * n, 0, k0, n, L, K.e1);
     launch_add_sqrtw_multi(c->st, K.s, B.W, K.e1, n, L);
-    launch_btw_multi<T>(c->st, A, c->rev_ptr, c->rev_idx, K.s, nullptr, nullptr, n, g.m_v, L, K.rhs);
+    launch_btw_multi<T>(c->st, c->rev_ptr, c->rev_q, (const T*)c->rev_a, K.s, nullptr, nullptr, n, L, K.rhs);
     s = pcg_block<T>(c, B, K, K.rhs, L, K.u, K.e1, c->slq_a + (size_t)k0 * c->slq_ld,
                      c->slq_b + (size_t)k0 * c->slq_ld, c->slq_ld, c->slq_rz + k0, c->slq_iters + k0);
     if (s) return s;

@@ -142,13 +142,11 @@ __device__ __forceinline__ void slot_gather(const int32_t* __restrict__ idx, con
   }
 }
 
-// the same over the CSR entries [e0, e1) of a row: column col[e] (or, with
-// rev set, the point rev_idx / m_v of the reverse list) and weight w[e] (or
-// A[rev_idx]); entries past the end repeat the last one with weight 0
+// the same over the CSR entries [e0, e1) of a row: column col[e], weight
+// w[e]; entries past the end repeat the last one with weight 0
 template <typename T, int NC>
 __device__ __forceinline__ void csr_gather(const int* __restrict__ col, const T* __restrict__ w, int e0, int e1,
-                                           int mv, bool rev, const double* __restrict__ x, int L, int l, int g,
-                                           int G, double v[NC]) {
+                                           const double* __restrict__ x, int L, int l, int g, int G, double v[NC]) {
   int cl[NC];
 #pragma unroll
   for (int t = 0; t < NC; ++t) cl[t] = min(l + 16 * t, L - 1);
@@ -158,9 +156,8 @@ __device__ __forceinline__ void csr_gather(const int* __restrict__ col, const T*
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int a = a0 + k * G;
-      const int e = col[min(a, e1 - 1)];
-      c[k] = rev ? e / mv : e;
-      wv[k] = a < e1 ? (double)w[rev ? e : min(a, e1 - 1)] : 0.0;
+      c[k] = col[min(a, e1 - 1)];
+      wv[k] = a < e1 ? (double)w[min(a, e1 - 1)] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k)
@@ -215,17 +212,18 @@ __global__ __launch_bounds__(256) void k_dbx_multi(const T* __restrict__ dA, con
 }
 
 // out[j][l] = s[j][l] - sum_{(q, slot): N(q)_slot = j} A_{q,slot} s[q][l] + (W ? W_j p[j][l] : 0)
+// (rev_q, rev_a: the reverse lists' rows and coefficients)
 template <typename T, int NC>
-__global__ __launch_bounds__(256) void k_btw_multi(const T* __restrict__ A, const int* __restrict__ rev_ptr,
-                                                   const int* __restrict__ rev_idx, const double* __restrict__ s,
+__global__ __launch_bounds__(256) void k_btw_multi(const int* __restrict__ rev_ptr, const int* __restrict__ rev_q,
+                                                   const T* __restrict__ rev_a, const double* __restrict__ s,
                                                    const double* __restrict__ W, const double* __restrict__ p,
-                                                   int64_t n, int mv, int L, int lsh, double* __restrict__ out) {
+                                                   int64_t n, int L, int lsh, double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= n) return;
   const int g = lane >> lsh, l = lane & ((1 << lsh) - 1);
   double v[NC] = {};
-  csr_gather<T, NC>(rev_idx, A, rev_ptr[j], rev_ptr[j + 1], mv, true, s, L, l, g, 64 >> lsh, v);
+  csr_gather<T, NC>(rev_q, rev_a, rev_ptr[j], rev_ptr[j + 1], s, L, l, g, 64 >> lsh, v);
 #pragma unroll
   for (int t = 0; t < NC; ++t) {
     v[t] = group_sum(v[t], lsh);
@@ -268,7 +266,7 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_level_multi(int beg, int end, 
   if (q >= end) return;
   const int g = lane >> lsh, l = lane & ((1 << lsh) - 1);
   double v[NC] = {};
-  csr_gather<T, NC>(col, coef, ptr[q], ptr[q + 1], 1, false, zq, L, l, g, 64 >> lsh, v);
+  csr_gather<T, NC>(col, coef, ptr[q], ptr[q + 1], zq, L, l, g, 64 >> lsh, v);
 #pragma unroll
   for (int t = 0; t < NC; ++t) {
     v[t] = group_sum(v[t], lsh);
@@ -756,11 +754,11 @@ void launch_dbx_multi(hipStream_t st, const T* dA, const int32_t* nbr, const dou
                      slot_shift(L), out);
 }
 template <typename T>
-void launch_btw_multi(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s,
-                      const double* W, const double* p, int64_t n, int mv, int L, double* out) {
+void launch_btw_multi(hipStream_t st, const int* rev_ptr, const int* rev_q, const T* rev_a, const double* s,
+                      const double* W, const double* p, int64_t n, int L, double* out) {
   by_cols(L, [&](auto nc) {
-    hipLaunchKernelGGL((k_btw_multi<T, decltype(nc)::value>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, A,
-                       rev_ptr, rev_idx, s, W, p, n, mv, L, col_shift(L), out);
+    hipLaunchKernelGGL((k_btw_multi<T, decltype(nc)::value>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st,
+                       rev_ptr, rev_q, rev_a, s, W, p, n, L, col_shift(L), out);
   });
 }
 template <typename T>
@@ -869,8 +867,8 @@ int launch_bilin_multi(hipStream_t st, const double* tu, const double* su, const
                                    int, int, double*);                                                           \
   template void launch_dbx_multi<T>(hipStream_t, const T*, const int32_t*, const double*, int64_t, int, int,      \
                                     double*);                                                                    \
-  template void launch_btw_multi<T>(hipStream_t, const T*, const int*, const int*, const double*, const double*,  \
-                                    const double*, int64_t, int, int, double*);                                  \
+  template void launch_btw_multi<T>(hipStream_t, const int*, const int*, const T*, const double*, const double*,  \
+                                    const double*, int64_t, int, double*);                                        \
   template void launch_trsv_fwd_multi<T>(hipStream_t, const TriSchedule&, const T*, const double*, int, double*,  \
                                          double*, double*);                                                      \
   template void launch_trsv_bwd_multi<T>(hipStream_t, const TriSchedule&, const T*, const double*, int, double*,  \

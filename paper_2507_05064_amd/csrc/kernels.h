@@ -126,8 +126,12 @@ template <typename T>
 void launch_t_minus_uc(hipStream_t st, const T* U, const double* c, const double* t, const double* D, int64_t n,
                        int mp, double* out);
 template <typename T>
-void launch_btw(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s, const double* W,
-                const double* p, int64_t n, int mv, double* out);
+void launch_btw(hipStream_t st, const int* rev_ptr, const int* rev_q, const T* rev_a, const double* s, const double* W,
+                const double* p, int64_t n, double* out);
+// rev_q[e] = rev_idx[e] / mv and rev_a[e] = A[rev_idx[e]] for the entries e < rev_ptr[n] of the reverse lists
+template <typename T>
+void launch_rev_coef(hipStream_t st, const int* rev_ptr, const int* rev_idx, const T* A, int64_t n, int mv, int* rev_q,
+                     T* rev_a);
 int launch_dot2(hipStream_t st, const double* a, const double* b, const double* c, const double* d, int64_t n,
                 double* part, double* out);
 void launch_cg_update(hipStream_t st, double* x, double* r, const double* p, const double* Ap, const double* sc,
@@ -315,8 +319,8 @@ template <typename T>
 void launch_dbx_multi(hipStream_t st, const T* dA, const int32_t* nbr, const double* x, int64_t n, int mv, int L,
                       double* out);
 template <typename T>
-void launch_btw_multi(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s,
-                      const double* W, const double* p, int64_t n, int mv, int L, double* out);
+void launch_btw_multi(hipStream_t st, const int* rev_ptr, const int* rev_q, const T* rev_a, const double* s,
+                      const double* W, const double* p, int64_t n, int L, double* out);
 template <typename T>
 void launch_trsv_fwd_multi(hipStream_t st, const TriSchedule& s, const T* coef, const double* x, int L, double* xq,
                            double* zq, double* z);

@@ -263,12 +263,25 @@ __global__ __launch_bounds__(256) void k_t_minus_uc(const T* __restrict__ U, con
   }
 }
 
+// the reverse lists' rows and coefficients in their own arrays: for every
+// entry e < rev_ptr[n] of the lists (entry = q m_v + slot with N(q)_slot = j),
+// rev_q[e] = q and rev_a[e] = A_{q,slot}; refreshed whenever A changes
+template <typename T>
+__global__ void k_rev_coef(const int* __restrict__ rev_ptr, const int* __restrict__ rev_idx, const T* __restrict__ A,
+                           int64_t n, int mv, int* __restrict__ rev_q, T* __restrict__ rev_a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rev_ptr[n]) return;
+  const int idx = rev_idx[e];
+  rev_q[e] = idx / mv;
+  rev_a[e] = A[idx];
+}
+
 // out_j = W_j p_j + s_j - sum_{(q,slot): N(q)_slot = j} A_{q,slot} s_q   (W may be null)
 template <typename T>
-__global__ __launch_bounds__(256) void k_btw(const T* __restrict__ A, const int* __restrict__ rev_ptr,
-                                             const int* __restrict__ rev_idx, const double* __restrict__ s,
+__global__ __launch_bounds__(256) void k_btw(const int* __restrict__ rev_ptr, const int* __restrict__ rev_q,
+                                             const T* __restrict__ rev_a, const double* __restrict__ s,
                                              const double* __restrict__ W, const double* __restrict__ p, int64_t n,
-                                             int mv, double* __restrict__ out) {
+                                             double* __restrict__ out) {
   const int lig = threadIdx.x & 7;
   const int64_t j = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
   if (j >= n) return;  // whole 8-lane groups leave together
@@ -278,15 +291,16 @@ __global__ __launch_bounds__(256) void k_btw(const T* __restrict__ A, const int*
   // gathers in flight together (entries past the end repeat the row's last
   // entry and are skipped)
   for (int q0 = beg + lig; q0 < end; q0 += 32) {
-    int idx[4];
+    int q[4];
     double a[4], z[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) idx[k] = rev_idx[min(q0 + 8 * k, end - 1)];
-#pragma unroll
     for (int k = 0; k < 4; ++k) {
-      a[k] = (double)A[idx[k]];
-      z[k] = s[idx[k] / mv];
+      const int e = min(q0 + 8 * k, end - 1);
+      q[k] = rev_q[e];
+      a[k] = (double)rev_a[e];
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) z[k] = s[q[k]];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       if (q0 + 8 * k < end) v += a[k] * z[k];
@@ -637,9 +651,14 @@ void launch_t_minus_uc(hipStream_t st, const T* U, const double* c, const double
   hipLaunchKernelGGL((k_t_minus_uc<T>), g1(n, 16), dim3(256), 0, st, U, c, t, D, n, mp, out);
 }
 template <typename T>
-void launch_btw(hipStream_t st, const T* A, const int* rev_ptr, const int* rev_idx, const double* s, const double* W,
-                const double* p, int64_t n, int mv, double* out) {
-  hipLaunchKernelGGL((k_btw<T>), g1(n, 32), dim3(256), 0, st, A, rev_ptr, rev_idx, s, W, p, n, mv, out);
+void launch_btw(hipStream_t st, const int* rev_ptr, const int* rev_q, const T* rev_a, const double* s, const double* W,
+                const double* p, int64_t n, double* out) {
+  hipLaunchKernelGGL((k_btw<T>), g1(n, 32), dim3(256), 0, st, rev_ptr, rev_q, rev_a, s, W, p, n, out);
+}
+template <typename T>
+void launch_rev_coef(hipStream_t st, const int* rev_ptr, const int* rev_idx, const T* A, int64_t n, int mv, int* rev_q,
+                     T* rev_a) {
+  hipLaunchKernelGGL((k_rev_coef<T>), g1(n * mv), dim3(256), 0, st, rev_ptr, rev_idx, A, n, mv, rev_q, rev_a);
 }
 int launch_dot2(hipStream_t st, const double* a, const double* b, const double* c, const double* d, int64_t n,
                 double* part, double* out) {
@@ -748,8 +767,9 @@ template void launch_fitc_out<float>(hipStream_t, const float*, const double*, c
   template void launch_utv<T>(hipStream_t, const T*, const double*, const double*, int64_t, int, int, double*);   \
   template void launch_t_minus_uc<T>(hipStream_t, const T*, const double*, const double*, const double*, int64_t, \
                                      int, double*);                                                               \
-  template void launch_btw<T>(hipStream_t, const T*, const int*, const int*, const double*, const double*,        \
-                              const double*, int64_t, int, double*);                                              \
+  template void launch_btw<T>(hipStream_t, const int*, const int*, const T*, const double*, const double*,        \
+                              const double*, int64_t, double*);                                                   \
+  template void launch_rev_coef<T>(hipStream_t, const int*, const int*, const T*, int64_t, int, int*, T*);        \
   template void launch_q_plus_euc<T>(hipStream_t, const T*, const double*, const double*, const double*,          \
                                      const double*, int64_t, int, double*);                                       \
   template void launch_wgram_partial<T>(hipStream_t, const T*, const double*, int64_t, int, int, double*, int*);
